@@ -1,0 +1,198 @@
+"""Seeded scene descriptors for the five benchmark workloads.
+
+Each builder returns a :class:`SceneSpec`: the mesh, material constants,
+collider geometry, time-step settings, initial state and the seeded loss
+direction.  Everything here is an *input*; nothing computes the method.
+
+Shapes and sizes follow the published workload list (tet meshes of boxes on a
+ground plane, Neo-Hookean material, smoothed Fischer-Burmeister contact).  The
+values that the list leaves open are fixed here (cell sizes, the push law on
+the beam, the slab's sphere path, the batched-scene recipe).
+"""
+
+from __future__ import annotations
+
+import dataclasses
+from typing import Callable, Optional
+
+import numpy as np
+
+from .mesh import VoxelMesh, box_mesh, quadruped_mesh
+
+GRAVITY = np.array([0.0, 0.0, -9.81])
+
+
+@dataclasses.dataclass
+class SceneSpec:
+    name: str
+    mesh: VoxelMesh
+    density: float
+    E: float
+    nu: float
+    mu: float
+    h: float
+    eps: float  # smoothing parameter of phi_eps: sqrt(x^2 + y^2 + 2 eps^2)
+    steps: int
+    gravity: np.ndarray
+    planes: np.ndarray  # (n_planes, 4): unit normal n and offset d, gap = n.x - d
+    contact_margin: float
+    q0: np.ndarray  # (n_verts, 3)
+    v0: np.ndarray  # (n_verts, 3)
+    loss_dir: np.ndarray  # (n_verts, 3): loss = sum(loss_dir * q_T)
+    seed: int
+    # sphere colliders: list of (radius, centre(t) callable returning (3,) array)
+    spheres: list = dataclasses.field(default_factory=list)
+    # external force on vertices at step t (without gravity), (n_verts, 3)
+    f_ext: Optional[Callable[[int], np.ndarray]] = None
+
+    @property
+    def n_verts(self) -> int:
+        return self.mesh.n_verts
+
+    @property
+    def n_tets(self) -> int:
+        return self.mesh.n_tets
+
+    def force(self, t: int) -> np.ndarray:
+        if self.f_ext is None:
+            return np.zeros((self.n_verts, 3))
+        return self.f_ext(t)
+
+    def sphere_array(self, t: int) -> np.ndarray:
+        """(n_spheres, 4) rows (cx, cy, cz, r) at time index t."""
+        if not self.spheres:
+            return np.zeros((0, 4))
+        return np.array([[*np.asarray(c(t), dtype=np.float64), r] for r, c in self.spheres])
+
+
+def loss_vector(rng: np.random.Generator, n_verts: int) -> np.ndarray:
+    return rng.standard_normal((n_verts, 3))
+
+
+GROUND = np.array([[0.0, 0.0, 1.0, 0.0]])
+
+
+def tiny_scene(variant: str = "impact", seed: int = 0) -> SceneSpec:
+    """4x4x4 cells (384 tets, 125 verts), side 0.1 m, 5 mm above the ground.
+
+    ``literal``: dropped at rest (free fall of 20 steps never reaches the
+    ground).  ``impact``: same, plus a downward initial speed of 0.5 m/s so
+    that the cube lands after about 9 ms and slides.
+    """
+    rng = np.random.default_rng(seed)
+    mesh = box_mesh(4, 4, 4, 0.025, origin=(0.0, 0.0, 0.005))
+    v0 = np.zeros((mesh.n_verts, 3))
+    v0[:, :2] = rng.uniform(-0.1, 0.1, size=(mesh.n_verts, 2))
+    if variant == "impact":
+        v0[:, 2] = -0.5
+    elif variant != "literal":
+        raise ValueError(variant)
+    loss = loss_vector(rng, mesh.n_verts)
+    return SceneSpec(
+        name=f"tiny-{variant}", mesh=mesh, density=1000.0, E=1e5, nu=0.4, mu=0.5,
+        h=1e-3, eps=1e-6, steps=20, gravity=GRAVITY.copy(), planes=GROUND.copy(),
+        contact_margin=2e-3, q0=mesh.rest.copy(), v0=v0, loss_dir=loss, seed=seed,
+    )
+
+
+def beam_push_force(mesh: VoxelMesh, rng: np.random.Generator, steps: int, total: float = 50.0):
+    """Tangential push on the top face: magnitude ramps 0 -> ``total`` newtons
+    linearly over the run, one seeded horizontal direction, spread over the
+    top-face vertices with seeded U[0,1] weights normalised to sum 1."""
+    top = np.nonzero(mesh.grid_index[:, 2] == mesh.grid_index[:, 2].max())[0]
+    w = rng.uniform(0.0, 1.0, size=top.shape[0])
+    w = w / w.sum()
+    ang = rng.uniform(0.0, 2.0 * np.pi)
+    direction = np.array([np.cos(ang), np.sin(ang), 0.0])
+
+    def f(t: int) -> np.ndarray:
+        out = np.zeros((mesh.n_verts, 3))
+        mag = total * (t + 1) / steps
+        out[top] = (mag * w)[:, None] * direction[None, :]
+        return out
+
+    return f
+
+
+def beam_scene(mu: float = 0.4, seed: int = 1, steps: int = 100,
+               nx: int = 32, ny: int = 8, nz: int = 8) -> SceneSpec:
+    """32x8x8-cell beam (12,288 tets, 2,673 verts), cell 0.0175 m, resting on
+    the ground, pushed sideways on its top face (0 -> 50 N)."""
+    rng = np.random.default_rng(seed)
+    mesh = box_mesh(nx, ny, nz, 0.0175, origin=(0.0, 0.0, 0.0))
+    push = beam_push_force(mesh, rng, steps)
+    loss = loss_vector(rng, mesh.n_verts)
+    return SceneSpec(
+        name=f"beam-mu{mu}", mesh=mesh, density=1000.0, E=1e6, nu=0.45, mu=mu,
+        h=1e-3, eps=np.sqrt(0.5e-12), steps=steps, gravity=GRAVITY.copy(),
+        planes=GROUND.copy(), contact_margin=2e-3, q0=mesh.rest.copy(),
+        v0=np.zeros((mesh.n_verts, 3)), loss_dir=loss, seed=seed, f_ext=push,
+    )
+
+
+def slab_scene(seed: int = 2, steps: int = 50) -> SceneSpec:
+    """64x32x32-cell slab (393,216 tets, 70,785 verts), cell 0.01 m, pressed
+    into the ground by a kinematic sphere of radius 0.3 x 0.64 m descending
+    at constant speed to an indentation of 0.093 m at the last step."""
+    rng = np.random.default_rng(seed)
+    mesh = box_mesh(64, 32, 32, 0.01, origin=(0.0, 0.0, 0.0))
+    R = 0.3 * 0.64
+    top = 0.32
+    depth = 0.093
+    cx, cy = 0.32, 0.16
+
+    def centre(t: int) -> np.ndarray:
+        return np.array([cx, cy, top + R - depth * t / steps])
+
+    loss = loss_vector(rng, mesh.n_verts)
+    return SceneSpec(
+        name="slab", mesh=mesh, density=1000.0, E=5e5, nu=0.45, mu=0.5, h=1e-3,
+        eps=np.sqrt(0.5e-12), steps=steps, gravity=GRAVITY.copy(), planes=GROUND.copy(),
+        contact_margin=2e-3, q0=mesh.rest.copy(), v0=np.zeros((mesh.n_verts, 3)),
+        loss_dir=loss, seed=seed, spheres=[(R, centre)],
+    )
+
+
+def quadruped_scene(seed: int = 4, steps: int = 1000) -> SceneSpec:
+    """Torso 32x16x8 cells on four 4x4x16-cell legs (30,720 tets), cell
+    0.01 m, standing on the ground, mu = 0.8."""
+    rng = np.random.default_rng(seed)
+    mesh = quadruped_mesh(0.01, origin=(0.0, 0.0, 0.0))
+    loss = np.zeros((mesh.n_verts, 3))
+    loss[:, 0] = -1.0 / mesh.n_verts  # placeholder direction; the rollout loss is the COM shift
+    return SceneSpec(
+        name="quadruped", mesh=mesh, density=1000.0, E=1e5, nu=0.4, mu=0.8, h=1e-3,
+        eps=np.sqrt(0.5e-12), steps=steps, gravity=GRAVITY.copy(), planes=GROUND.copy(),
+        contact_margin=2e-3, q0=mesh.rest.copy(), v0=np.zeros((mesh.n_verts, 3)),
+        loss_dir=loss, seed=seed,
+    )
+
+
+def batched_scenes(n_scenes: int = 256, seed: int = 3):
+    """Boxes with log-uniform tet counts in [2e3, 1e5], seeded aspect, E, nu,
+    mu and tangential initial velocity; one in eight hovers 5 mm up."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for s in range(n_scenes):
+        T = np.exp(rng.uniform(np.log(2e3), np.log(1e5)))
+        while True:
+            a = rng.uniform(0.5, 2.0, size=3)
+            cells = T / 6.0
+            base = (cells / np.prod(a)) ** (1.0 / 3.0)
+            nxyz = np.maximum(1, np.round(base * a).astype(int))
+            if (nxyz[0] + 1) * (nxyz[1] + 1) <= 2000:
+                break
+        hover = (s % 8) == 7
+        mesh = box_mesh(*map(int, nxyz), 0.01, origin=(0.0, 0.0, 0.005 if hover else 0.0))
+        v0 = np.zeros((mesh.n_verts, 3))
+        v0[:, :2] = rng.uniform(-0.1, 0.1, size=(mesh.n_verts, 2))
+        E = float(np.exp(rng.uniform(np.log(1e4), np.log(1e7))))
+        nu = float(rng.uniform(0.3, 0.48))
+        mu = float(rng.uniform(0.1, 1.0))
+        out.append(SceneSpec(
+            name=f"batch{s}", mesh=mesh, density=1000.0, E=E, nu=nu, mu=mu, h=1e-3,
+            eps=np.sqrt(0.5e-12), steps=10, gravity=GRAVITY.copy(), planes=GROUND.copy(),
+            contact_margin=2e-3, q0=mesh.rest.copy(), v0=v0,
+            loss_dir=loss_vector(rng, mesh.n_verts), seed=seed * 1000 + s,
+        ))
+    return out
