@@ -1,0 +1,190 @@
+/*
+ * adjoint.h -- C ABI of the per-time-step analytical adjoint for Neo-Hookean
+ * tet meshes with smoothed Fischer-Burmeister frictional contact
+ * ("Fast and Reliable Gradients for Deformables Across Frictional Contact
+ * Regimes", arXiv 2603.16478).  One GPU (gfx950), HIP.
+ *
+ * Problem statement (Sec. 3, eq:implicit, eq:lagrange, eq:contact,
+ * eq:internal, eq:dynamics): an implicit step maps (qbar, vbar, f_ext;
+ * E, nu, mu) to (q, v).  Its adjoint (Sec. 5.1, eq:adjoint) solves
+ *     Acal^T z = (dL/dq + dL/dv / h)^T,   Acal = A - dA + h^2 H_c^T K_c H_c
+ * and maps z to gradients (eq:compute_gradient, App. B.3).
+ *
+ * Conventions for every entry point
+ *   - Arrays marked "device" are device pointers (HIP global memory) owned
+ *     by the caller; arrays marked "host" are host memory read during the
+ *     call.  Vectors over vertices are AoS [n_verts][3] double.
+ *   - `stream` is a hipStream_t passed as void*; NULL means the default
+ *     stream.  Calls enqueue work and may return before it finishes, except
+ *     where stated.  Outputs are valid after the stream synchronises.
+ *   - Every call returns an adj_status.  On error nothing is enqueued (shape
+ *     and argument errors are detected before any launch) and
+ *     adj_last_error() returns a message (thread-local).
+ *   - A scene is used by one host thread at a time.
+ */
+#ifndef PAPER_2603_16478_ADJOINT_H
+#define PAPER_2603_16478_ADJOINT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  ADJ_OK = 0,
+  ADJ_E_ARG = -1,       /* null pointer, non-finite or out-of-range argument */
+  ADJ_E_SHAPE = -2,     /* sizes inconsistent with the scene */
+  ADJ_E_INVERTED = -3,  /* a tet with det F <= 0 (Neo-Hookean log J undefined) */
+  ADJ_E_NOCONV = -4,    /* Krylov / Newton did not reach the tolerance; outputs hold the last iterate */
+  ADJ_E_SINGULAR = -5,  /* zero or non-finite pivot (elastic factor or capacitance) */
+  ADJ_E_DEVICE = -6,    /* a HIP runtime call failed */
+  ADJ_E_OOM = -7,       /* device or host allocation failed */
+  ADJ_E_NOTIMPL = -8
+} adj_status;
+
+typedef enum { ADJ_FP64 = 0, ADJ_MIXED = 1 } adj_precision;
+
+typedef struct adj_scene adj_scene; /* opaque */
+
+/* Scene description (host memory, read during adj_scene_create only).
+ * Mesh and material (Sec. 3.1, 3.3): rest positions, tets with positive
+ * orientation, density, Young's modulus E and Poisson ratio nu (scalars, or
+ * one value per tet when per_tet_material = 1).  Contact colliders: planes
+ * (n, d) with gap n.x - d, unit n.  h = time step, eps = smoothing parameter
+ * of phi_eps(x,y) = x + y - sqrt(x^2 + y^2 + 2 eps^2) (Sec. 5.2). */
+typedef struct {
+  int32_t n_verts;
+  int32_t n_tets;
+  const double* rest_pos; /* host [n_verts*3] */
+  const int32_t* tets;    /* host [n_tets*4] */
+  double density;
+  double h;
+  double eps;
+  const double* E;        /* host [1] or [n_tets] */
+  const double* nu;       /* host [1] or [n_tets] */
+  int32_t per_tet_material;
+  double gravity[3];
+  int32_t n_planes;
+  const double* planes;   /* host [n_planes*4] */
+  double contact_margin;  /* candidate if predicted gap <= margin */
+} adj_scene_desc;
+
+/* Converged contact state of one step (the forward step record).  All
+ * arrays are device memory, n_contacts entries, sorted by vertex id.
+ * frame: rows (n, t1, t2) of the contact frame H_c (Sec. 3.2); delta and
+ * lambda: delta_c and lambda_c in frame coordinates (delta_n, delta_f1,
+ * delta_f2), (lambda_n, lambda_f1, lambda_f2).  fric = 1 for a contact with
+ * friction rows, 0 for a normal-only contact.  d_n, d_f: offsets of the
+ * constraint (delta_n = n.x - d_n, delta_f = T (x - xbar) - d_f). */
+typedef struct {
+  int32_t n_contacts;  /* host value */
+  int32_t capacity;    /* host value: allocated entries (forward output only) */
+  int32_t* vid;        /* device [capacity] */
+  int32_t* fric;       /* device [capacity] */
+  double* frame;       /* device [capacity*9] */
+  double* delta;       /* device [capacity*3] */
+  double* lambda;      /* device [capacity*3] */
+  double* d_n;         /* device [capacity] */
+  double* d_f;         /* device [capacity*2] */
+  double mu;           /* friction coefficient of the step */
+} adj_contact_state;
+
+typedef struct {
+  double rtol;          /* relative residual |b - Acal^T z| / |b| (Sec. 6.1: 1e-8) */
+  int32_t maxit;        /* total Krylov iterations over all restarts */
+  int32_t restart;      /* GMRES restart length, 1..128 */
+  int32_t max_refine;   /* outer FP64 refinement sweeps (mixed precision) */
+  adj_precision prec;
+  int32_t reuse_delassus; /* 1: keep H A^{-1} H^T while the contact vertex set is unchanged */
+} adj_solve_opts;
+
+typedef struct {
+  int32_t iters;        /* Krylov iterations taken */
+  int32_t refine_steps;
+  int32_t n_contacts;
+  int32_t m_rows;       /* rows of the contact-space capacitance */
+  double relres;        /* true relative residual at exit */
+  int32_t delassus_rebuilt;
+} adj_solve_info;
+
+/* Build the scene: rest-shape operators, lumped mass, the constant system
+ * matrix A = M + h^2 sum_i w_i G_i^T G_i (eq:dynamics) and its Cholesky
+ * factor with its sparse inverse S = L^{-1} (Sec. 3.4: A^{-1} = S^T S),
+ * the block-sparse pattern of Acal with the element-to-entry map (Sec. 5.4,
+ * matrix assembly), and device workspaces sized for `max_contacts`.
+ * Errors: ADJ_E_ARG, ADJ_E_INVERTED (rest tet with det <= 0),
+ * ADJ_E_SINGULAR, ADJ_E_OOM, ADJ_E_DEVICE.  *out is NULL on error. */
+adj_status adj_scene_create(const adj_scene_desc* desc, int32_t max_contacts, adj_scene** out);
+adj_status adj_scene_destroy(adj_scene* scene);
+
+/* Linearise the converged step (Sec. 5.2-5.4): per-tet SVD projection
+ * Jacobians J_i (Sec. 5.3, App. B.0-B.4) assembled into the block-sparse
+ * Acal^T through the element-to-entry map, contact blocks K_c, k_mu
+ * (eq:final_diff_contact, App. A.1), and the Woodbury capacitance
+ * K^{-T} + h^2 H A^{-1} H^T with its inverse (eq:woodbury_formula).
+ * q: device [n_verts*3] converged positions.  The contact state must stay
+ * alive and unchanged until adjoint_solve and vjp_params have run.
+ * Errors: ADJ_E_SHAPE (n_contacts > max_contacts), ADJ_E_ARG,
+ * ADJ_E_INVERTED (reported after the stream synchronises, see
+ * adj_check_status). */
+adj_status adjoint_setup(adj_scene* scene, const adj_contact_state* contacts, const double* q,
+                         const adj_solve_opts* opts, void* stream);
+
+/* Solve Acal^T z = dL_dq + dL_dv / h with right-preconditioned GMRES and
+ * the Woodbury preconditioner (Sec. 5.4).  dL_dq, dL_dv: device
+ * [n_verts*3]; z: device [n_verts*3] output.  Synchronises the stream at
+ * the end (the iteration count and residual are host values).  Returns
+ * ADJ_E_NOCONV if rtol was not met within maxit (z holds the last iterate). */
+adj_status adjoint_solve(adj_scene* scene, const double* dL_dq, const double* dL_dv, double* z,
+                         const adj_solve_opts* opts, adj_solve_info* info, void* stream);
+
+/* Gradients from z (eq:compute_gradient, App. B.3):
+ *   dL_dqbar = M z + h^2 sum_c H_c^T P_f K_c^T H_c z - dL_dv / h
+ *   dL_dvbar = h M z,   dL_dfext = h^2 z
+ *   grad3[0] += dL/dE, grad3[1] += dL/dnu, grad3[2] += dL/dmu (friction)
+ *   dE_tet[i] += dL/dE_i, dnu_tet[i] += dL/dnu_i (optional, may be NULL)
+ * All pointers device; vectors [n_verts*3]; grad3 [3]; per-tet [n_tets].
+ * Requires adjoint_setup on the same step. */
+adj_status vjp_params(adj_scene* scene, const double* z, const double* dL_dv, double* dL_dqbar,
+                      double* dL_dvbar, double* dL_dfext, double* grad3, double* dE_tet,
+                      double* dnu_tet, void* stream);
+
+/* One implicit step (eq:dynamics): converge (q, lambda) from (qbar, vbar,
+ * f_ext) with a damped Newton method whose linear systems are Acal dq = r,
+ * and write q, v and the contact state of the step.  qbar, vbar, f_ext, q,
+ * v: device [n_verts*3]; f_ext excludes gravity (taken from the scene).
+ * contacts->capacity bounds the number of contacts (ADJ_E_SHAPE beyond).
+ * Synchronises the stream.  Returns ADJ_E_NOCONV if the Newton residual did
+ * not reach its tolerance. */
+adj_status sim_forward_step(adj_scene* scene, const double* qbar, const double* vbar,
+                            const double* f_ext, double mu, double* q, double* v,
+                            adj_contact_state* contacts, void* stream);
+
+/* Scene sizes and host-side statistics: out[0] n_verts, out[1] n_tets,
+ * out[2] nnz blocks of Acal, out[3] nnz(L), out[4] nnz(S), out[5]
+ * max_contacts.  out: host [6]. */
+adj_status adj_scene_info(const adj_scene* scene, int64_t* out);
+
+/* Synchronise the stream and report device-side errors of the last setup
+ * (ADJ_E_INVERTED when a tet had det F <= 0). */
+adj_status adj_check_status(adj_scene* scene, void* stream);
+
+/* Diagnostics: copy an internal array of the last adjoint_setup to host
+ * memory (synchronises the device).  what = 0: Acal^T block values
+ * [nnz_blocks][3][3] row-major; 1: block row pointer [n_verts+1] int32;
+ * 2: block column indices [nnz_blocks] int32; 3: inverse of the Woodbury
+ * capacitance [m][m]; 4: Delassus matrix of the contact vertices
+ * [n_cv][n_cv]; 5: per-contact rotated bases Q = R frame [n_contacts][3][3].
+ * *size_bytes receives the array size; nothing is copied when capacity_bytes
+ * is smaller (ADJ_E_SHAPE).  For tests and debugging. */
+adj_status adj_debug_export(const adj_scene* scene, int32_t what, void* host_out, int64_t capacity_bytes,
+                            int64_t* size_bytes);
+
+const char* adj_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,56 @@
+"""Build libadjoint.so in-tree for gfx950 (hipcc for the kernels, g++ for the
+host scene builder).  Usage: python -m paper_2603_16478_amd.build"""
+
+from __future__ import annotations
+
+import os
+import shutil
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+CSRC = os.path.join(HERE, "csrc")
+INCLUDE = os.path.join(ROOT, "include")
+BUILD = os.path.join(HERE, "_build")
+LIB = os.path.join(HERE, "libadjoint.so")
+
+HIP_SOURCES = ["kernels_elastic.hip", "kernels_contact.hip", "kernels_dense.hip", "kernels_krylov.hip",
+               "api.hip"]
+CPP_SOURCES = ["host_scene.cpp"]
+
+HIPCC_FLAGS = [
+    "-O3", "-fPIC", "-std=c++17", "--offload-arch=gfx950",
+    # packed FP32 instructions are disabled for all device code
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-Wno-unused-result",
+]
+
+
+def _run(cmd):
+    print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+
+
+def build(verbose: bool = True) -> str:
+    hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    os.makedirs(BUILD, exist_ok=True)
+    objs = []
+    for src in CPP_SOURCES:
+        obj = os.path.join(BUILD, src + ".o")
+        _run(["g++", "-O3", "-fPIC", "-std=c++17", "-I", INCLUDE, "-I", CSRC, "-c",
+              os.path.join(CSRC, src), "-o", obj])
+        objs.append(obj)
+    for src in HIP_SOURCES:
+        obj = os.path.join(BUILD, src + ".o")
+        _run([hipcc, *HIPCC_FLAGS, "-I", INCLUDE, "-I", CSRC, "-c", os.path.join(CSRC, src), "-o", obj])
+        objs.append(obj)
+    tmp = LIB + ".tmp"
+    _run([hipcc, "-shared", "-fPIC", "--offload-arch=gfx950", *objs, "-o", tmp])
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    build()
+    sys.exit(0)

@@ -1,0 +1,53 @@
+// Host-side scene construction: rest-shape operators, lumped mass, the
+// constant scalar system matrix, its fill-reducing ordering, sparse Cholesky
+// factor and sparse inverse, and the block pattern of the adjoint matrix with
+// its element-to-entry map.  Plain C++, runs once per scene.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "adjoint.h"
+
+namespace adj {
+
+// The 10 blocks (k <= l) of a symmetric 4x4 block element matrix.
+extern const int kPairK[10];
+extern const int kPairL[10];
+int pair_index(int k, int l);  // k <= l
+
+struct HostScene {
+  int nv = 0, nt = 0;
+  double h = 0, eps = 0, density = 0;
+  double gravity[3] = {0, 0, 0};
+  double margin = 0;
+  std::vector<double> planes;  // [n_planes*4]
+  std::vector<double> rest;    // [nv*3]
+  std::vector<int32_t> tets;   // [nt*4]
+  std::vector<double> Bm;      // [nt*9] row-major B_m = D_m^{-1}
+  std::vector<double> Bt;      // [nt*12] row-major 4x3: [-1^T B_m; B_m]
+  std::vector<double> vol, lmu, llam, E, nu;  // per tet (Lame mu, lambda; E, nu)
+  std::vector<double> mass;    // per vertex
+  // Block pattern of Acal: rows = vertices, sorted columns, diagonal included.
+  std::vector<int32_t> rowptr, col, diag_slot, row_of_slot;
+  // Element-to-entry map: contributions to each block slot, ordered by
+  // (tet, local pair); code = tet*32 + pair*2 + transpose.
+  std::vector<int32_t> slot_ptr, slot_code;
+  std::vector<double> As;      // scalar A_s per slot (A = A_s (x) I_3)
+  // Fill-reducing ordering (internal index -> vertex) and its inverse.
+  std::vector<int32_t> perm, iperm;
+  // Cholesky factor of P A_s P^T, CSC, diagonal first in every column.
+  std::vector<int32_t> Lp, Li, parent;
+  std::vector<double> Lx;
+  // S = L^{-1} P: CSR by internal row (columns = vertices) and CSR of S^T
+  // (rows = vertices, columns = internal rows).
+  std::vector<int64_t> Sp, STp;
+  std::vector<int32_t> Sj, STj;
+  std::vector<double> Sx, STx;
+};
+
+// Returns ADJ_OK or an error code with a message in err.
+adj_status build_host_scene(const adj_scene_desc* d, HostScene& s, std::string& err);
+
+}  // namespace adj

@@ -1,0 +1,415 @@
+// Krylov solve of the adjoint system (Sec. 5.4): right-preconditioned
+// restarted GMRES, classical Gram-Schmidt applied twice, Givens rotations,
+// the Woodbury preconditioner
+//     P r = A^{-1} r - h^2 A^{-1} Hq^T X Hq A^{-1} r,   X = C^{-1}
+// with A^{-1} = S^T S applied as two sparse products (Sec. 3.4) and
+// A^{-1} Hq^T = Z (x) Q^T, and the matrix-free product with Acal^T as one
+// block-sparse product (contacts act on diagonal blocks only, so they are
+// folded into those blocks at setup).
+//
+// The basis is stored unnormalised with per-vector scale factors: V_i =
+// scale[i] * Vt_i, which spares a normalisation pass.  Iterations run from
+// device-side state (current index j and an `active` flag), so the host can
+// launch a chunk of iterations without reading anything back; kernels of an
+// inactive cycle return immediately.
+#include "device_common.h"
+
+namespace adj {
+
+struct GmresState {
+  int j;          // completed iterations of this cycle
+  int active;     // 1 while the cycle runs
+  int restart;
+  int pad;
+  double tol;     // absolute tolerance on the residual estimate
+  double res;     // current residual estimate |g_{j}|
+  double rnorm;   // true residual norm (restart checks)
+};
+
+__device__ __forceinline__ bool gm_inactive(const GmresState* s) { return s && s->active == 0; }
+
+// y = S x (3 interleaved right-hand sides); one wavefront per row.
+// `st` only gates the launch (inactive cycle -> return).  With use_j = 1
+// the input is the current basis vector, x = xbase + j*stride scaled by
+// scale[j] (st and scale must then be non-null); otherwise x = xbase.
+__global__ void __launch_bounds__(256) k_spmv_csr3(int nrows, const long long* __restrict__ rp,
+                                                   const int* __restrict__ cj,
+                                                   const double* __restrict__ cx,
+                                                   const double* __restrict__ xbase, long long stride,
+                                                   const double* __restrict__ scale,
+                                                   const GmresState* __restrict__ st, int use_j,
+                                                   double* __restrict__ y) {
+  if (gm_inactive(st)) return;
+  const int lane = threadIdx.x & 63;
+  const int row = blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
+  if (row >= nrows) return;
+  const double* x = xbase;
+  double sc = 1.0;
+  if (use_j) {
+    x = xbase + (long long)st->j * stride;
+    sc = scale[st->j];
+  }
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+  for (long long p = rp[row] + lane; p < rp[row + 1]; p += 64) {
+    const double v = cx[p];
+    const int c = cj[p];
+    a0 += v * x[3 * c];
+    a1 += v * x[3 * c + 1];
+    a2 += v * x[3 * c + 2];
+  }
+  a0 = wave_sum(a0);
+  a1 = wave_sum(a1);
+  a2 = wave_sum(a2);
+  if (lane == 0) {
+    y[3 * row] = sc * a0;
+    y[3 * row + 1] = sc * a1;
+    y[3 * row + 2] = sc * a2;
+  }
+}
+
+// t = X (Hq u): each block first forms g = Hq u (m entries) in LDS, then one
+// wavefront per row of X.
+__global__ void __launch_bounds__(256) k_wb_gather(int m, const int* __restrict__ row_c,
+                                                   const int* __restrict__ row_i,
+                                                   const int* __restrict__ vid,
+                                                   const double* __restrict__ Q,
+                                                   const double* __restrict__ X,
+                                                   const double* __restrict__ u,
+                                                   const GmresState* __restrict__ st,
+                                                   double* __restrict__ t) {
+  if (gm_inactive(st)) return;
+  extern __shared__ double g[];
+  for (int r = threadIdx.x; r < m; r += blockDim.x) {
+    const int c = row_c[r];
+    const double* q = Q + 9 * c + 3 * row_i[r];
+    const int v = vid[c];
+    g[r] = q[0] * u[3 * v] + q[1] * u[3 * v + 1] + q[2] * u[3 * v + 2];
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int row = blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
+  if (row >= m) return;
+  const double* xr = X + (size_t)row * m;
+  double acc = 0.0;
+  for (int k = lane; k < m; k += 64) acc += xr[k] * g[k];
+  acc = wave_sum(acc);
+  if (lane == 0) t[row] = acc;
+}
+
+// y = u - h^2 Z t' with t'_cv = sum over the contacts at vertex cv of Q_c^T t_c
+// (computed per block in LDS); one wavefront per vertex row.
+__global__ void __launch_bounds__(256) k_wb_correct(int nv, int ncv, const int* __restrict__ cv_ptr,
+                                                    const int* __restrict__ c_row0,
+                                                    const int* __restrict__ c_nrow,
+                                                    const double* __restrict__ Q,
+                                                    const double* __restrict__ t,
+                                                    const double* __restrict__ Z, double h2,
+                                                    const double* __restrict__ u,
+                                                    const GmresState* __restrict__ st,
+                                                    double* __restrict__ y) {
+  if (gm_inactive(st)) return;
+  extern __shared__ double tp[];  // [ncv][3]
+  for (int a = threadIdx.x; a < ncv; a += blockDim.x) {
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    for (int c = cv_ptr[a]; c < cv_ptr[a + 1]; ++c)
+      for (int i = 0; i < c_nrow[c]; ++i) {
+        const double tv = t[c_row0[c] + i];
+        const double* q = Q + 9 * c + 3 * i;
+        s0 += q[0] * tv;
+        s1 += q[1] * tv;
+        s2 += q[2] * tv;
+      }
+    tp[3 * a] = s0;
+    tp[3 * a + 1] = s1;
+    tp[3 * a + 2] = s2;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int row = blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
+  if (row >= nv) return;
+  const double* zr = Z + (size_t)row * ncv;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+  for (int k = lane; k < ncv; k += 64) {
+    const double zz = zr[k];
+    a0 += zz * tp[3 * k];
+    a1 += zz * tp[3 * k + 1];
+    a2 += zz * tp[3 * k + 2];
+  }
+  a0 = wave_sum(a0);
+  a1 = wave_sum(a1);
+  a2 = wave_sum(a2);
+  if (lane == 0) {
+    y[3 * row] = u[3 * row] - h2 * a0;
+    y[3 * row + 1] = u[3 * row + 1] - h2 * a1;
+    y[3 * row + 2] = u[3 * row + 2] - h2 * a2;
+  }
+}
+
+// w = Acal^T x, block-sparse 3x3; 16 lanes per block row.  Output to
+// outbase + (j+1)*stride when state is given.
+__global__ void __launch_bounds__(256) k_bsr_spmv(int nv, const int* __restrict__ rowptr,
+                                                  const int* __restrict__ col,
+                                                  const double* __restrict__ val,
+                                                  const double* __restrict__ x,
+                                                  double* __restrict__ outbase, long long stride,
+                                                  const GmresState* __restrict__ st) {
+  if (gm_inactive(st)) return;
+  const int sub = threadIdx.x & 15;
+  const int row = blockIdx.x * (blockDim.x / 16) + threadIdx.x / 16;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+  if (row < nv) {
+    for (int p = rowptr[row] + sub; p < rowptr[row + 1]; p += 16) {
+      const double* b = val + 9 * (size_t)p;
+      const int c = col[p];
+      const double x0 = x[3 * c], x1 = x[3 * c + 1], x2 = x[3 * c + 2];
+      a0 += b[0] * x0 + b[1] * x1 + b[2] * x2;
+      a1 += b[3] * x0 + b[4] * x1 + b[5] * x2;
+      a2 += b[6] * x0 + b[7] * x1 + b[8] * x2;
+    }
+  }
+  a0 = group_sum<16>(a0);
+  a1 = group_sum<16>(a1);
+  a2 = group_sum<16>(a2);
+  if (row < nv && sub == 0) {
+    double* out = outbase + (st ? (long long)(st->j + 1) * stride : 0);
+    out[3 * row] = a0;
+    out[3 * row + 1] = a1;
+    out[3 * row + 2] = a2;
+  }
+}
+
+constexpr int kRowsPerBlock = 1024;
+
+// CGS pass 1: h_i = scale_i * (Vt_i . w), i <= j, with w = Vt_{j+1}.
+// Per-block partials; the last block reduces into hbuf.
+__global__ void __launch_bounds__(256) k_gm_dots(long long n, const double* __restrict__ Vt,
+                                                 long long stride, const double* __restrict__ scale,
+                                                 GmresState* __restrict__ st,
+                                                 double* __restrict__ partial, unsigned* counter,
+                                                 double* __restrict__ hbuf) {
+  if (st->active == 0) return;
+  __shared__ bool is_last;
+  const int j = st->j;
+  const double* w = Vt + (long long)(j + 1) * stride;
+  const long long r0 = (long long)blockIdx.x * kRowsPerBlock;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x / 64, nw = blockDim.x / 64;
+  for (int i = wid; i <= j; i += nw) {
+    const double* vi = Vt + (long long)i * stride;
+    double acc = 0.0;
+    for (long long r = r0 + lane; r < r0 + kRowsPerBlock && r < n; r += 64) acc += vi[r] * w[r];
+    acc = wave_sum(acc);
+    if (lane == 0) partial[(size_t)blockIdx.x * 130 + i] = acc;
+  }
+  if (last_block(counter, &is_last)) {
+    for (int i = threadIdx.x; i <= j; i += blockDim.x) {
+      double s = 0.0;
+      for (int b = 0; b < (int)gridDim.x; ++b) s += partial[(size_t)b * 130 + i];
+      hbuf[i] = scale[i] * s;
+    }
+  }
+}
+
+// CGS: w -= sum_i h_i V_i on this block's rows, then partial dots of the
+// updated w (second pass) or its squared norm (final pass).
+// mode 0: second pass -> h2 into hbuf[130 + i]; column of H gets h + h2 later
+// mode 1: final update with h2, norm, Givens rotation, bookkeeping
+__global__ void __launch_bounds__(256) k_gm_update(long long n, double* __restrict__ Vt,
+                                                   long long stride, double* __restrict__ scale,
+                                                   GmresState* __restrict__ st,
+                                                   double* __restrict__ partial, unsigned* counter,
+                                                   double* __restrict__ hbuf, double* __restrict__ H,
+                                                   double* __restrict__ cs, double* __restrict__ sn,
+                                                   double* __restrict__ gvec, int mode) {
+  if (st->active == 0) return;
+  __shared__ bool is_last;
+  __shared__ double lds[32];
+  const int j = st->j;
+  double* w = Vt + (long long)(j + 1) * stride;
+  const double* h = hbuf + (mode == 0 ? 0 : 130);
+  const long long r0 = (long long)blockIdx.x * kRowsPerBlock;
+  for (long long r = r0 + threadIdx.x; r < r0 + kRowsPerBlock && r < n; r += blockDim.x) {
+    double acc = w[r];
+    for (int i = 0; i <= j; ++i) acc -= h[i] * scale[i] * Vt[(long long)i * stride + r];
+    w[r] = acc;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wid = threadIdx.x / 64, nw = blockDim.x / 64;
+  if (mode == 0) {
+    for (int i = wid; i <= j; i += nw) {
+      const double* vi = Vt + (long long)i * stride;
+      double acc = 0.0;
+      for (long long r = r0 + lane; r < r0 + kRowsPerBlock && r < n; r += 64) acc += vi[r] * w[r];
+      acc = wave_sum(acc);
+      if (lane == 0) partial[(size_t)blockIdx.x * 130 + i] = acc;
+    }
+  } else {
+    double acc = 0.0;
+    for (long long r = r0 + threadIdx.x; r < r0 + kRowsPerBlock && r < n; r += blockDim.x)
+      acc += w[r] * w[r];
+    acc = block_sum(acc, lds);
+    if (threadIdx.x == 0) partial[(size_t)blockIdx.x * 130] = acc;
+  }
+  if (!last_block(counter, &is_last)) return;
+  if (mode == 0) {
+    for (int i = threadIdx.x; i <= j; i += blockDim.x) {
+      double s = 0.0;
+      for (int b = 0; b < (int)gridDim.x; ++b) s += partial[(size_t)b * 130 + i];
+      hbuf[130 + i] = scale[i] * s;
+    }
+    return;
+  }
+  if (threadIdx.x != 0) return;
+  double s = 0.0;
+  for (int b = 0; b < (int)gridDim.x; ++b) s += partial[(size_t)b * 130];
+  const double nrm = sqrt(s);
+  const int R = st->restart;
+  double* Hc = H + (size_t)j * (R + 1);  // column j, column-major (R+1) x R
+  for (int i = 0; i <= j; ++i) Hc[i] = hbuf[i] + hbuf[130 + i];
+  Hc[j + 1] = nrm;
+  scale[j + 1] = (nrm > 0.0) ? 1.0 / nrm : 0.0;
+  for (int i = 0; i < j; ++i) {
+    const double a = Hc[i], b = Hc[i + 1];
+    Hc[i] = cs[i] * a + sn[i] * b;
+    Hc[i + 1] = -sn[i] * a + cs[i] * b;
+  }
+  const double a = Hc[j], b = Hc[j + 1];
+  const double rr = sqrt(a * a + b * b);
+  const double c = (rr > 0.0) ? a / rr : 1.0, sv = (rr > 0.0) ? b / rr : 0.0;
+  cs[j] = c;
+  sn[j] = sv;
+  Hc[j] = rr;
+  Hc[j + 1] = 0.0;
+  gvec[j + 1] = -sv * gvec[j];
+  gvec[j] = c * gvec[j];
+  st->res = fabs(gvec[j + 1]);
+  st->j = j + 1;
+  if (st->res <= st->tol || j + 1 >= R || !(nrm > 0.0) || !isfinite(st->res)) st->active = 0;
+}
+
+// y_i = scale_i * (H^{-1} g)_i for the completed iterations (upper triangular).
+__global__ void k_gm_solve_small(const GmresState* __restrict__ st, const double* __restrict__ H,
+                                 const double* __restrict__ gvec, const double* __restrict__ scale,
+                                 double* __restrict__ coef) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const int k = st->j, R = st->restart;
+  for (int i = k - 1; i >= 0; --i) {
+    double s = gvec[i];
+    for (int l = i + 1; l < k; ++l) s -= H[(size_t)l * (R + 1) + i] * coef[l];
+    coef[i] = s / H[(size_t)i * (R + 1) + i];
+  }
+  for (int i = 0; i < k; ++i) coef[i] *= scale[i];
+  coef[128] = (double)k;
+}
+
+// out = sum_{i<k} coef_i Vt_i
+__global__ void k_gm_combine(long long n, const double* __restrict__ Vt, long long stride,
+                             const double* __restrict__ coef, double* __restrict__ out) {
+  const long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  const int k = (int)coef[128];
+  double acc = 0.0;
+  for (int i = 0; i < k; ++i) acc += coef[i] * Vt[(long long)i * stride + r];
+  out[r] = acc;
+}
+
+// z += dz; r = b - Acal^T z is formed by k_bsr_spmv into r then k_residual.
+__global__ void k_axpy(long long n, double a, const double* __restrict__ x, double* __restrict__ y) {
+  const long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < n) y[r] += a * x[r];
+}
+
+// r = b - Ax (in place on Ax), |r|^2 partials, last block writes st->rnorm,
+// and (when v0 is given) v0 = r with scale 1/|r|, g = [|r|, 0, ...].
+__global__ void __launch_bounds__(256) k_residual(long long n, const double* __restrict__ b,
+                                                  double* __restrict__ r, double* __restrict__ v0,
+                                                  double* __restrict__ partial, unsigned* counter,
+                                                  GmresState* __restrict__ st,
+                                                  double* __restrict__ scale,
+                                                  double* __restrict__ gvec) {
+  __shared__ double lds[32];
+  __shared__ bool is_last;
+  double acc = 0.0;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    const double v = b[i] - r[i];
+    r[i] = v;
+    if (v0) v0[i] = v;
+    acc += v * v;
+  }
+  acc = block_sum(acc, lds);
+  if (threadIdx.x == 0) partial[blockIdx.x] = acc;
+  if (!last_block(counter, &is_last)) return;
+  if (threadIdx.x != 0) return;
+  double s = 0.0;
+  for (int i = 0; i < (int)gridDim.x; ++i) s += partial[i];
+  const double nrm = sqrt(s);
+  st->rnorm = nrm;
+  st->res = nrm;
+  st->j = 0;
+  st->active = (nrm > st->tol) ? 1 : 0;
+  scale[0] = (nrm > 0.0) ? 1.0 / nrm : 0.0;
+  gvec[0] = nrm;
+}
+
+// host-side launchers ------------------------------------------------------
+
+void launch_spmv_csr3(hipStream_t s, int nrows, const long long* rp, const int* cj, const double* cx,
+                      const double* xbase, long long stride, const double* scale,
+                      const GmresState* st, double* y) {
+  // the basis vector is addressed through the state only when both are given
+  const int use_j = (st != nullptr && scale != nullptr) ? 1 : 0;
+  k_spmv_csr3<<<(nrows + 3) / 4, 256, 0, s>>>(nrows, rp, cj, cx, xbase, stride, scale, st, use_j, y);
+}
+
+void launch_wb_gather(hipStream_t s, int m, const int* row_c, const int* row_i, const int* vid,
+                      const double* Q, const double* X, const double* u, const GmresState* st,
+                      double* t) {
+  if (m == 0) return;
+  k_wb_gather<<<(m + 3) / 4, 256, (size_t)m * sizeof(double), s>>>(m, row_c, row_i, vid, Q, X, u, st, t);
+}
+
+void launch_wb_correct(hipStream_t s, int nv, int ncv, const int* cv_ptr, const int* c_row0,
+                       const int* c_nrow, const double* Q, const double* t, const double* Z, double h2,
+                       const double* u, const GmresState* st, double* y) {
+  k_wb_correct<<<(nv + 3) / 4, 256, (size_t)3 * ncv * sizeof(double), s>>>(
+      nv, ncv, cv_ptr, c_row0, c_nrow, Q, t, Z, h2, u, st, y);
+}
+
+void launch_bsr_spmv(hipStream_t s, int nv, const int* rowptr, const int* col, const double* val,
+                     const double* x, double* outbase, long long stride, const GmresState* st) {
+  k_bsr_spmv<<<(nv + 15) / 16, 256, 0, s>>>(nv, rowptr, col, val, x, outbase, stride, st);
+}
+
+int gm_blocks(long long n) { return (int)((n + kRowsPerBlock - 1) / kRowsPerBlock); }
+
+void launch_gm_dots(hipStream_t s, long long n, const double* Vt, long long stride, const double* scale,
+                    GmresState* st, double* partial, unsigned* counter, double* hbuf) {
+  k_gm_dots<<<gm_blocks(n), 256, 0, s>>>(n, Vt, stride, scale, st, partial, counter, hbuf);
+}
+
+void launch_gm_update(hipStream_t s, long long n, double* Vt, long long stride, double* scale,
+                      GmresState* st, double* partial, unsigned* counter, double* hbuf, double* H,
+                      double* cs, double* sn, double* gvec, int mode) {
+  k_gm_update<<<gm_blocks(n), 256, 0, s>>>(n, Vt, stride, scale, st, partial, counter, hbuf, H, cs, sn,
+                                           gvec, mode);
+}
+
+void launch_gm_finish(hipStream_t s, long long n, const GmresState* st, const double* H,
+                      const double* gvec, const double* scale, const double* Vt, long long stride,
+                      double* coef, double* out) {
+  k_gm_solve_small<<<1, 64, 0, s>>>(st, H, gvec, scale, coef);
+  k_gm_combine<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, Vt, stride, coef, out);
+}
+
+void launch_axpy(hipStream_t s, long long n, double a, const double* x, double* y) {
+  k_axpy<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, a, x, y);
+}
+
+void launch_residual(hipStream_t s, long long n, const double* b, double* r, double* v0, double* partial,
+                     unsigned* counter, GmresState* st, double* scale, double* gvec) {
+  int blocks = (int)((n + 255) / 256);
+  if (blocks > 256) blocks = 256;
+  k_residual<<<blocks, 256, 0, s>>>(n, b, r, v0, partial, counter, st, scale, gvec);
+}
+
+}  // namespace adj

@@ -1,0 +1,213 @@
+"""ctypes binding of libadjoint.so (include/adjoint.h).
+
+Argument marshalling only: the functions below take torch tensors (device
+memory) or NumPy arrays (host memory), pass raw pointers and sizes to the C
+ABI and raise on a non-zero status.  Every step of the adjoint runs in the
+HIP kernels of the library.  Loading fails loudly when the library has not
+been built; there is no fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libadjoint.so")
+
+STATUS = {0: "ADJ_OK", -1: "ADJ_E_ARG", -2: "ADJ_E_SHAPE", -3: "ADJ_E_INVERTED",
+          -4: "ADJ_E_NOCONV", -5: "ADJ_E_SINGULAR", -6: "ADJ_E_DEVICE", -7: "ADJ_E_OOM",
+          -8: "ADJ_E_NOTIMPL"}
+ADJ_FP64, ADJ_MIXED = 0, 1
+
+# names declared in include/adjoint.h
+EXPORTS = ("adj_scene_create", "adj_scene_destroy", "adjoint_setup", "adjoint_solve", "vjp_params",
+           "sim_forward_step", "adj_scene_info", "adj_check_status", "adj_debug_export",
+           "adj_last_error")
+
+
+class AdjError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class SceneDesc(C.Structure):
+    _fields_ = [("n_verts", C.c_int32), ("n_tets", C.c_int32), ("rest_pos", C.c_void_p),
+                ("tets", C.c_void_p), ("density", C.c_double), ("h", C.c_double), ("eps", C.c_double),
+                ("E", C.c_void_p), ("nu", C.c_void_p), ("per_tet_material", C.c_int32),
+                ("gravity", C.c_double * 3), ("n_planes", C.c_int32), ("planes", C.c_void_p),
+                ("contact_margin", C.c_double)]
+
+
+class ContactState(C.Structure):
+    _fields_ = [("n_contacts", C.c_int32), ("capacity", C.c_int32), ("vid", C.c_void_p),
+                ("fric", C.c_void_p), ("frame", C.c_void_p), ("delta", C.c_void_p),
+                ("lam", C.c_void_p), ("d_n", C.c_void_p), ("d_f", C.c_void_p), ("mu", C.c_double)]
+
+
+class SolveOpts(C.Structure):
+    _fields_ = [("rtol", C.c_double), ("maxit", C.c_int32), ("restart", C.c_int32),
+                ("max_refine", C.c_int32), ("prec", C.c_int32), ("reuse_delassus", C.c_int32)]
+
+
+class SolveInfo(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("refine_steps", C.c_int32), ("n_contacts", C.c_int32),
+                ("m_rows", C.c_int32), ("relres", C.c_double), ("delassus_rebuilt", C.c_int32)]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH) -> C.CDLL:
+    """Load the built library (raises if it is missing)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is not built; run paper_2603_16478_amd.build.build() first")
+    lib = C.CDLL(path)
+    vp = C.c_void_p
+    lib.adj_last_error.restype = C.c_char_p
+    lib.adj_scene_create.argtypes = [C.POINTER(SceneDesc), C.c_int32, C.POINTER(vp)]
+    lib.adj_scene_destroy.argtypes = [vp]
+    lib.adjoint_setup.argtypes = [vp, C.POINTER(ContactState), vp, C.POINTER(SolveOpts), vp]
+    lib.adjoint_solve.argtypes = [vp, vp, vp, vp, C.POINTER(SolveOpts), C.POINTER(SolveInfo), vp]
+    lib.vjp_params.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.sim_forward_step.argtypes = [vp, vp, vp, vp, C.c_double, vp, vp, C.POINTER(ContactState), vp]
+    lib.adj_scene_info.argtypes = [vp, C.POINTER(C.c_int64)]
+    lib.adj_check_status.argtypes = [vp, vp]
+    lib.adj_debug_export.argtypes = [vp, C.c_int32, vp, C.c_int64, C.POINTER(C.c_int64)]
+    for name in EXPORTS:
+        if name != "adj_last_error":
+            getattr(lib, name).restype = C.c_int
+    _lib = lib
+    return lib
+
+
+def check(status: int):
+    if status != 0:
+        raise AdjError(status, load().adj_last_error().decode())
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if isinstance(t, np.ndarray):
+        return t.ctypes.data
+    return t.data_ptr()
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    return stream
+
+
+class Scene:
+    """Owns an adj_scene (adj_scene_create / adj_scene_destroy)."""
+
+    def __init__(self, rest, tets, density, h, eps, E, nu, gravity, planes, contact_margin,
+                 max_contacts):
+        lib = load()
+        self._keep = []
+        rest = np.ascontiguousarray(rest, dtype=np.float64)
+        tets = np.ascontiguousarray(tets, dtype=np.int32)
+        E = np.ascontiguousarray(np.atleast_1d(E), dtype=np.float64)
+        nu = np.ascontiguousarray(np.atleast_1d(nu), dtype=np.float64)
+        planes = np.ascontiguousarray(np.asarray(planes, dtype=np.float64).reshape(-1, 4))
+        self._keep += [rest, tets, E, nu, planes]
+        d = SceneDesc()
+        d.n_verts, d.n_tets = rest.shape[0], tets.shape[0]
+        d.rest_pos, d.tets = rest.ctypes.data, tets.ctypes.data
+        d.density, d.h, d.eps = float(density), float(h), float(eps)
+        d.E, d.nu = E.ctypes.data, nu.ctypes.data
+        d.per_tet_material = 1 if E.shape[0] == tets.shape[0] and tets.shape[0] > 1 else 0
+        d.gravity = (C.c_double * 3)(*[float(g) for g in gravity])
+        d.n_planes = planes.shape[0]
+        d.planes = planes.ctypes.data if planes.shape[0] else None
+        d.contact_margin = float(contact_margin)
+        handle = C.c_void_p()
+        check(lib.adj_scene_create(C.byref(d), int(max_contacts), C.byref(handle)))
+        self.handle = handle
+        self.n_verts, self.n_tets, self.h = d.n_verts, d.n_tets, d.h
+
+    def info(self):
+        out = (C.c_int64 * 6)()
+        check(load().adj_scene_info(self.handle, out))
+        keys = ("n_verts", "n_tets", "nnz_blocks", "nnz_L", "nnz_S", "max_contacts")
+        return dict(zip(keys, list(out)))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            check(load().adj_scene_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def make_contact_state(n, vid, fric, frame, delta, lam, mu, d_n=None, d_f=None, capacity=None):
+    """Fill an adj_contact_state from device tensors (sorted by vertex)."""
+    cs = ContactState()
+    cs.n_contacts = int(n)
+    cs.capacity = int(capacity if capacity is not None else n)
+    cs.vid, cs.fric, cs.frame = _ptr(vid), _ptr(fric), _ptr(frame)
+    cs.delta, cs.lam = _ptr(delta), _ptr(lam)
+    cs.d_n, cs.d_f = _ptr(d_n), _ptr(d_f)
+    cs.mu = float(mu)
+    return cs
+
+
+def solve_opts(rtol=1e-8, maxit=2000, restart=64, prec=ADJ_FP64, reuse_delassus=1, max_refine=4):
+    o = SolveOpts()
+    o.rtol, o.maxit, o.restart, o.max_refine = float(rtol), int(maxit), int(restart), int(max_refine)
+    o.prec, o.reuse_delassus = int(prec), int(reuse_delassus)
+    return o
+
+
+def adjoint_setup(scene: Scene, contacts: ContactState, q, opts: SolveOpts, stream=None):
+    check(load().adjoint_setup(scene.handle, C.byref(contacts), _ptr(q), C.byref(opts), _stream(stream)))
+
+
+def adjoint_solve(scene: Scene, dL_dq, dL_dv, z, opts: SolveOpts, stream=None, raise_noconv=True):
+    info = SolveInfo()
+    st = load().adjoint_solve(scene.handle, _ptr(dL_dq), _ptr(dL_dv), _ptr(z), C.byref(opts),
+                              C.byref(info), _stream(stream))
+    if st != 0 and not (st == -4 and not raise_noconv):
+        check(st)
+    return info
+
+
+def vjp_params(scene: Scene, z, dL_dv, dL_dqbar, dL_dvbar, dL_dfext, grad3, dE_tet=None, dnu_tet=None,
+               stream=None):
+    check(load().vjp_params(scene.handle, _ptr(z), _ptr(dL_dv), _ptr(dL_dqbar), _ptr(dL_dvbar),
+                            _ptr(dL_dfext), _ptr(grad3), _ptr(dE_tet), _ptr(dnu_tet), _stream(stream)))
+
+
+_DEBUG = {0: ("val", np.float64), 1: ("rowptr", np.int32), 2: ("col", np.int32),
+          3: ("capinv", np.float64), 4: ("delassus", np.float64), 5: ("Q", np.float64)}
+
+
+def debug_export(scene: Scene, what: int) -> np.ndarray:
+    lib = load()
+    size = C.c_int64()
+    lib.adj_debug_export(scene.handle, int(what), None, 0, C.byref(size))
+    out = np.empty(max(size.value, 1) // np.dtype(_DEBUG[what][1]).itemsize, dtype=_DEBUG[what][1])
+    check(lib.adj_debug_export(scene.handle, int(what), out.ctypes.data, out.nbytes, C.byref(size)))
+    return out[: size.value // out.itemsize]
+
+
+def check_status(scene: Scene, stream=None):
+    check(load().adj_check_status(scene.handle, _stream(stream)))
+
+
+def sim_forward_step(scene: Scene, qbar, vbar, f_ext, mu, q, v, contacts: ContactState, stream=None):
+    check(load().sim_forward_step(scene.handle, _ptr(qbar), _ptr(vbar), _ptr(f_ext), float(mu), _ptr(q),
+                                  _ptr(v), C.byref(contacts), _stream(stream)))
