@@ -139,6 +139,37 @@ struct adj_scene {
   GmresState* h_state = nullptr;  // pinned
   double *d_t1 = nullptr, *d_u = nullptr, *d_y = nullptr, *d_r = nullptr, *d_b = nullptr,
          *d_dz = nullptr, *d_xt = nullptr;
+  // live kernel timing (adj_profile_begin / adj_profile_end)
+  int prof_kernel = -1;
+  std::vector<hipEvent_t> prof_ev;
+  size_t prof_used = 0;
+};
+
+static const size_t kMaxProfiled = 65536;
+
+// Bracket one launch of kernel class `id` with events when it is profiled.
+struct ProfScope {
+  adj_scene* s;
+  hipStream_t st;
+  bool on;
+  ProfScope(adj_scene* s_, int id, hipStream_t st_) : s(s_), st(st_), on(false) {
+    if (s->prof_kernel != id || s->prof_used >= kMaxProfiled) return;
+    if (s->prof_ev.size() < 2 * (s->prof_used + 1)) {
+      hipEvent_t a, b;
+      if (hipEventCreate(&a) != hipSuccess) return;
+      if (hipEventCreate(&b) != hipSuccess) {
+        (void)hipEventDestroy(a);
+        return;
+      }
+      s->prof_ev.push_back(a);
+      s->prof_ev.push_back(b);
+    }
+    on = hipEventRecord(s->prof_ev[2 * s->prof_used], st) == hipSuccess;
+  }
+  ~ProfScope() {
+    if (!on) return;
+    if (hipEventRecord(s->prof_ev[2 * s->prof_used + 1], st) == hipSuccess) s->prof_used++;
+  }
 };
 
 static void free_scene(adj_scene* s) {
@@ -158,6 +189,7 @@ static void free_scene(adj_scene* s) {
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (s->h_state) (void)hipHostFree(s->h_state);
+  for (hipEvent_t e : s->prof_ev) (void)hipEventDestroy(e);
   delete s;
 }
 
@@ -351,10 +383,16 @@ extern "C" adj_status adjoint_setup(adj_scene* s, const adj_contact_state* cst, 
     HIPCHK(hipMemcpyAsync(s->d_cv_ptr, cv_ptr.data(), (ncv + 1) * sizeof(int), hipMemcpyHostToDevice, st));
   }
   // a1 + a2: per-tet Jacobians, gather assembly of Acal^T
-  launch_tet_blocks(st, s->nt, s->d_tets, s->d_Bt, s->d_vol, s->d_lmu, s->d_llam, h2, q, s->d_tetblk,
-                    s->d_err);
-  launch_assemble(st, s->nnzb, s->d_slot_ptr, s->d_slot_code, s->d_tetblk, s->d_row_of_slot, s->d_col,
-                  s->d_mass, s->d_val);
+  {
+    ProfScope p(s, 5, st);
+    launch_tet_blocks(st, s->nt, s->d_tets, s->d_Bt, s->d_vol, s->d_lmu, s->d_llam, h2, q, s->d_tetblk,
+                      s->d_err);
+  }
+  {
+    ProfScope p(s, 6, st);
+    launch_assemble(st, s->nnzb, s->d_slot_ptr, s->d_slot_code, s->d_tetblk, s->d_row_of_slot, s->d_col,
+                    s->d_mass, s->d_val);
+  }
   // a3: contact blocks folded into the diagonal blocks of Acal^T
   launch_contact_blocks(st, nc, cst->fric, cst->frame, cst->delta, cst->lambda, cst->mu, s->hs.eps, h2, 1,
                         s->d_Wt, s->d_Q, s->d_kh, s->d_Kc, s->d_kmu);
@@ -387,7 +425,10 @@ extern "C" adj_status adjoint_setup(adj_scene* s, const adj_contact_state* cst, 
     s->cap_m = std::max(s->cap_m, (size_t)m);
     launch_capacitance(st, m, s->d_row_c, s->d_row_i, s->d_cmap, ncv, s->d_D, s->d_Q, s->d_kh, cst->mu,
                        h2, s->d_C);
-    launch_gauss_jordan(st, m, s->d_C, s->d_P, s->d_colbuf, s->d_err);
+    {
+      ProfScope p(s, 7, st);
+      launch_gauss_jordan(st, m, s->d_C, s->d_P, s->d_colbuf, s->d_err);
+    }
   }
   HIPCHK(hipGetLastError());
   s->setup_done = true;
@@ -409,15 +450,26 @@ extern "C" adj_status adj_check_status(adj_scene* s, void* stream) {
 static void apply_precond(adj_scene* s, hipStream_t st, const double* x, long long stride,
                           const double* scale, const GmresState* state, double* out) {
   const double h2 = s->hs.h * s->hs.h;
-  launch_spmv_csr3(st, s->nv, s->d_Sp, s->d_Sj, s->d_Sx, x, stride, scale, state, s->d_t1);
-  if (s->nc == 0) {
-    launch_spmv_csr3(st, s->nv, s->d_STp, s->d_STj, s->d_STx, s->d_t1, 0, nullptr, state, out);
-    return;
+  {
+    ProfScope p(s, 0, st);
+    launch_spmv_csr3(st, s->nv, s->d_Sp, s->d_Sj, s->d_Sx, x, stride, scale, state, s->d_t1);
   }
-  launch_spmv_csr3(st, s->nv, s->d_STp, s->d_STj, s->d_STx, s->d_t1, 0, nullptr, state, s->d_u);
-  launch_wb_gather(st, s->m, s->d_row_c, s->d_row_i, s->cur_vid, s->d_Q, s->d_C, s->d_u, state, s->d_tvec);
-  launch_wb_correct(st, s->nv, s->ncv, s->d_cv_ptr, s->d_c_row0, s->d_c_nrow, s->d_Q, s->d_tvec, s->d_Z, h2,
-                    s->d_u, state, out);
+  double* u = (s->nc == 0) ? out : s->d_u;
+  {
+    ProfScope p(s, 1, st);
+    launch_spmv_csr3(st, s->nv, s->d_STp, s->d_STj, s->d_STx, s->d_t1, 0, nullptr, state, u);
+  }
+  if (s->nc == 0) return;
+  {
+    ProfScope p(s, 2, st);
+    launch_wb_gather(st, s->m, s->d_row_c, s->d_row_i, s->cur_vid, s->d_Q, s->d_C, s->d_u, state,
+                     s->d_tvec);
+  }
+  {
+    ProfScope p(s, 3, st);
+    launch_wb_correct(st, s->nv, s->ncv, s->d_cv_ptr, s->d_c_row0, s->d_c_nrow, s->d_Q, s->d_tvec, s->d_Z,
+                      h2, s->d_u, state, out);
+  }
 }
 
 extern "C" adj_status adjoint_solve(adj_scene* s, const double* dL_dq, const double* dL_dv, double* z,
@@ -461,11 +513,20 @@ extern "C" adj_status adjoint_solve(adj_scene* s, const double* dL_dq, const dou
     while (true) {
       for (int k = 0; k < chunk; ++k) {
         apply_precond(s, st, s->d_Vt, stride, s->d_scale, s->d_state, s->d_y);
-        launch_bsr_spmv(st, s->nv, s->d_rowptr, s->d_col, s->d_val, s->d_y, s->d_Vt, stride, s->d_state);
-        launch_gm_dots(st, n3, s->d_Vt, stride, s->d_scale, s->d_state, s->d_partial, s->d_counter,
-                       s->d_hbuf);
-        launch_gm_update(st, n3, s->d_Vt, stride, s->d_scale, s->d_state, s->d_partial, s->d_counter + 1,
-                         s->d_hbuf, s->d_H, s->d_cs, s->d_sn, s->d_g, 0);
+        {
+          ProfScope p(s, 4, st);
+          launch_bsr_spmv(st, s->nv, s->d_rowptr, s->d_col, s->d_val, s->d_y, s->d_Vt, stride, s->d_state);
+        }
+        {
+          ProfScope p(s, 8, st);
+          launch_gm_dots(st, n3, s->d_Vt, stride, s->d_scale, s->d_state, s->d_partial, s->d_counter,
+                         s->d_hbuf);
+        }
+        {
+          ProfScope p(s, 9, st);
+          launch_gm_update(st, n3, s->d_Vt, stride, s->d_scale, s->d_state, s->d_partial, s->d_counter + 1,
+                           s->d_hbuf, s->d_H, s->d_cs, s->d_sn, s->d_g, 0);
+        }
         launch_gm_update(st, n3, s->d_Vt, stride, s->d_scale, s->d_state, s->d_partial, s->d_counter + 2,
                          s->d_hbuf, s->d_H, s->d_cs, s->d_sn, s->d_g, 1);
       }
@@ -518,6 +579,29 @@ extern "C" adj_status vjp_params(adj_scene* s, const double* z, const double* dL
   launch_vjp_tets(st, s->nt, s->d_tets, s->d_Bt, s->d_vol, s->d_lmu, s->d_llam, s->d_E, s->d_nu, h2,
                   s->cur_q, z, dE_tet, dnu_tet, s->d_partial + 4096, s->d_counter + 5, grad3);
   HIPCHK(hipGetLastError());
+  return ADJ_OK;
+}
+
+extern "C" adj_status adj_profile_begin(adj_scene* s, int32_t kernel) {
+  if (!s || kernel < 0 || kernel > 9) return fail(ADJ_E_ARG, "bad profile request");
+  s->prof_kernel = kernel;
+  s->prof_used = 0;
+  return ADJ_OK;
+}
+
+extern "C" adj_status adj_profile_end(adj_scene* s, double* total_ms, int64_t* launches) {
+  if (!s || !total_ms || !launches) return fail(ADJ_E_ARG, "null argument");
+  double tot = 0.0;
+  for (size_t i = 0; i < s->prof_used; ++i) {
+    HIPCHK(hipEventSynchronize(s->prof_ev[2 * i + 1]));
+    float ms = 0.0f;
+    HIPCHK(hipEventElapsedTime(&ms, s->prof_ev[2 * i], s->prof_ev[2 * i + 1]));
+    tot += ms;
+  }
+  *total_ms = tot;
+  *launches = (int64_t)s->prof_used;
+  s->prof_kernel = -1;
+  s->prof_used = 0;
   return ADJ_OK;
 }
 

@@ -25,7 +25,9 @@ ADJ_FP64, ADJ_MIXED = 0, 1
 # names declared in include/adjoint.h
 EXPORTS = ("adj_scene_create", "adj_scene_destroy", "adjoint_setup", "adjoint_solve", "vjp_params",
            "sim_forward_step", "adj_scene_info", "adj_check_status", "adj_debug_export",
-           "adj_last_error")
+           "adj_profile_begin", "adj_profile_end", "adj_last_error")
+KERNELS = {"S": 0, "ST": 1, "capinv": 2, "Z": 3, "bsr": 4, "tet": 5, "assemble": 6, "gj": 7,
+           "gs_dots": 8, "gs_update": 9}
 
 
 class AdjError(RuntimeError):
@@ -80,6 +82,8 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.adj_scene_info.argtypes = [vp, C.POINTER(C.c_int64)]
     lib.adj_check_status.argtypes = [vp, vp]
     lib.adj_debug_export.argtypes = [vp, C.c_int32, vp, C.c_int64, C.POINTER(C.c_int64)]
+    lib.adj_profile_begin.argtypes = [vp, C.c_int32]
+    lib.adj_profile_end.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
     for name in EXPORTS:
         if name != "adj_last_error":
             getattr(lib, name).restype = C.c_int
@@ -202,6 +206,16 @@ def debug_export(scene: Scene, what: int) -> np.ndarray:
     out = np.empty(max(size.value, 1) // np.dtype(_DEBUG[what][1]).itemsize, dtype=_DEBUG[what][1])
     check(lib.adj_debug_export(scene.handle, int(what), out.ctypes.data, out.nbytes, C.byref(size)))
     return out[: size.value // out.itemsize]
+
+
+def profile_begin(scene: Scene, kernel: str):
+    check(load().adj_profile_begin(scene.handle, KERNELS[kernel]))
+
+
+def profile_end(scene: Scene):
+    ms, n = C.c_double(), C.c_int64()
+    check(load().adj_profile_end(scene.handle, C.byref(ms), C.byref(n)))
+    return ms.value, n.value
 
 
 def check_status(scene: Scene, stream=None):
