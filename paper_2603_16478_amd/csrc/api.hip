@@ -31,7 +31,7 @@ void launch_vjp_tets(hipStream_t, int, const int*, const double*, const double*,
 void launch_contact_blocks(hipStream_t, int, const int*, const double*, const double*, const double*,
                            double, double, double, int, double*, double*, double*, double*, double*);
 void launch_contact_fold(hipStream_t, int, const int*, const int*, const double*, double*);
-void launch_capacitance(hipStream_t, int, const int*, const int*, const int*, int, const double*,
+void launch_capacitance(hipStream_t, int, int, const int*, const int*, const int*, int, const double*,
                         const double*, const double*, double, double, double*);
 void launch_vjp_contacts(hipStream_t, int, const int*, const double*, const double*, const double*,
                          const double*, double, double*, double*, unsigned*, double*);
@@ -40,10 +40,12 @@ void launch_vjp_vectors(hipStream_t, int, const double*, const double*, const do
 void launch_fill_zero(hipStream_t, size_t, double*);
 void launch_delassus(hipStream_t, int, int, const int*, const long long*, const int*, const double*,
                      double*, double*, double*);
-void launch_gauss_jordan(hipStream_t, int, double*, double*, double*, int*);
+double* launch_gauss_jordan(hipStream_t, int, int, double*, double*, int*);
 void launch_spmv_csr3(hipStream_t, int, const long long*, const int*, const double*, const double*,
                       long long, const double*, const GmresState*, double*);
-void launch_wb_gather(hipStream_t, int, const int*, const int*, const int*, const double*,
+void launch_spmv_tasks(hipStream_t, int, const int4*, const long long*, const int*, const double*,
+                       const double*, long long, const double*, const GmresState*, double*);
+void launch_wb_gather(hipStream_t, int, int, const int*, const int*, const int*, const double*,
                       const double*, const double*, const GmresState*, double*);
 void launch_wb_correct(hipStream_t, int, int, const int*, const int*, const int*, const double*,
                        const double*, const double*, double, const double*, const GmresState*, double*);
@@ -111,6 +113,8 @@ struct adj_scene {
   long long *d_Sp = nullptr, *d_STp = nullptr;
   int *d_Sj = nullptr, *d_STj = nullptr;
   double *d_Sx = nullptr, *d_STx = nullptr;
+  int *d_Stasks = nullptr, *d_STtasks = nullptr;
+  int nS_tasks = 0, nST_tasks = 0;
   // per-step
   double *d_tetblk = nullptr, *d_val = nullptr;
   int* d_err = nullptr;
@@ -124,7 +128,8 @@ struct adj_scene {
   double *d_Y = nullptr, *d_D = nullptr, *d_Z = nullptr, *d_C = nullptr, *d_P = nullptr,
          *d_colbuf = nullptr, *d_tvec = nullptr;
   // current step
-  int nc = 0, ncv = 0, m = 0;
+  int nc = 0, ncv = 0, m = 0, mp = 0;
+  double* d_X = nullptr;  // the buffer (d_C or d_colbuf) holding the capacitance inverse
   double mu = 0.0;
   const int* cur_vid = nullptr;
   const double* cur_frame = nullptr;
@@ -185,7 +190,8 @@ static void free_scene(adj_scene* s) {
                   s->d_colbuf,   s->d_tvec,   s->d_Vt,    s->d_scale,       s->d_H,
                   s->d_cs,       s->d_sn,     s->d_g,     s->d_hbuf,        s->d_coef,
                   s->d_partial,  s->d_counter, s->d_state, s->d_t1,         s->d_u,
-                  s->d_y,        s->d_r,      s->d_b,     s->d_dz,          s->d_xt};
+                  s->d_y,        s->d_r,      s->d_b,     s->d_dz,          s->d_xt,
+                  s->d_Stasks,   s->d_STtasks};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (s->h_state) (void)hipHostFree(s->h_state);
@@ -246,6 +252,10 @@ extern "C" adj_status adj_scene_create(const adj_scene_desc* desc, int32_t max_c
   UP(s->d_STj, h.STj);
   UP(s->d_Sx, h.Sx);
   UP(s->d_STx, h.STx);
+  UP(s->d_Stasks, h.S_tasks);
+  UP(s->d_STtasks, h.ST_tasks);
+  s->nS_tasks = (int)(h.S_tasks.size() / 4);
+  s->nST_tasks = (int)(h.ST_tasks.size() / 4);
 #undef UP
   bool ok = true;
   const size_t mc = (size_t)std::max(1, max_contacts);
@@ -417,17 +427,19 @@ extern "C" adj_status adjoint_setup(adj_scene* s, const adj_contact_state* cst, 
       s->delassus_valid = true;
       s->delassus_rebuilt = 1;
     }
-    size_t capC = s->cap_m * s->cap_m, capB = s->cap_m * 32;
-    if ((size_t)m > s->cap_m) capC = capB = 0;
+    const int mp = ((m + 31) / 32) * 32;
+    s->mp = mp;
+    size_t capC = s->cap_m * s->cap_m, capB = capC;
+    if ((size_t)mp > s->cap_m) capC = capB = 0;
     adj_status a;
-    if ((a = grow(&s->d_C, &capC, (size_t)m * m)) != ADJ_OK) return a;
-    if ((a = grow(&s->d_colbuf, &capB, (size_t)m * 32)) != ADJ_OK) return a;
-    s->cap_m = std::max(s->cap_m, (size_t)m);
-    launch_capacitance(st, m, s->d_row_c, s->d_row_i, s->d_cmap, ncv, s->d_D, s->d_Q, s->d_kh, cst->mu,
+    if ((a = grow(&s->d_C, &capC, (size_t)mp * mp)) != ADJ_OK) return a;
+    if ((a = grow(&s->d_colbuf, &capB, (size_t)mp * mp)) != ADJ_OK) return a;
+    s->cap_m = std::max(s->cap_m, (size_t)mp);
+    launch_capacitance(st, m, mp, s->d_row_c, s->d_row_i, s->d_cmap, ncv, s->d_D, s->d_Q, s->d_kh, cst->mu,
                        h2, s->d_C);
     {
       ProfScope p(s, 7, st);
-      launch_gauss_jordan(st, m, s->d_C, s->d_P, s->d_colbuf, s->d_err);
+      s->d_X = launch_gauss_jordan(st, m, mp, s->d_C, s->d_colbuf, s->d_err);
     }
   }
   HIPCHK(hipGetLastError());
@@ -452,17 +464,19 @@ static void apply_precond(adj_scene* s, hipStream_t st, const double* x, long lo
   const double h2 = s->hs.h * s->hs.h;
   {
     ProfScope p(s, 0, st);
-    launch_spmv_csr3(st, s->nv, s->d_Sp, s->d_Sj, s->d_Sx, x, stride, scale, state, s->d_t1);
+    launch_spmv_tasks(st, s->nS_tasks, (const int4*)s->d_Stasks, s->d_Sp, s->d_Sj, s->d_Sx, x, stride, scale,
+                      state, s->d_t1);
   }
   double* u = (s->nc == 0) ? out : s->d_u;
   {
     ProfScope p(s, 1, st);
-    launch_spmv_csr3(st, s->nv, s->d_STp, s->d_STj, s->d_STx, s->d_t1, 0, nullptr, state, u);
+    launch_spmv_tasks(st, s->nST_tasks, (const int4*)s->d_STtasks, s->d_STp, s->d_STj, s->d_STx, s->d_t1, 0,
+                      nullptr, state, u);
   }
   if (s->nc == 0) return;
   {
     ProfScope p(s, 2, st);
-    launch_wb_gather(st, s->m, s->d_row_c, s->d_row_i, s->cur_vid, s->d_Q, s->d_C, s->d_u, state,
+    launch_wb_gather(st, s->m, s->mp, s->d_row_c, s->d_row_i, s->cur_vid, s->d_Q, s->d_X, s->d_u, state,
                      s->d_tvec);
   }
   {
@@ -614,7 +628,7 @@ extern "C" adj_status adj_debug_export(const adj_scene* s, int32_t what, void* h
     case 0: src = s->d_val; bytes = 9LL * s->nnzb * 8; break;
     case 1: src = s->d_rowptr; bytes = (s->nv + 1LL) * 4; break;
     case 2: src = s->d_col; bytes = (int64_t)s->nnzb * 4; break;
-    case 3: src = s->d_C; bytes = (int64_t)s->m * s->m * 8; break;
+    case 3: src = s->d_X; bytes = (int64_t)s->mp * s->mp * 8; break;
     case 4: src = s->d_D; bytes = (int64_t)s->ncv * s->ncv * 8; break;
     case 5: src = s->d_Q; bytes = 9LL * s->nc * 8; break;
     default: return fail(ADJ_E_ARG, "unknown array");

@@ -105,6 +105,28 @@ void nested_dissection(const std::vector<int32_t>& verts, const std::vector<doub
 
 }  // namespace
 
+std::vector<int32_t> make_row_tasks(const std::vector<int64_t>& rowptr, int64_t big) {
+  std::vector<int32_t> t;
+  std::vector<int32_t> small;
+  const int n = (int)rowptr.size() - 1;
+  for (int r = 0; r < n; ++r) {
+    if (rowptr[r + 1] - rowptr[r] > big) {
+      t.insert(t.end(), {r | 0x40000000, -1, -1, -1});
+    } else {
+      small.push_back(r);
+      if (small.size() == 4) {
+        t.insert(t.end(), small.begin(), small.end());
+        small.clear();
+      }
+    }
+  }
+  if (!small.empty()) {
+    while (small.size() < 4) small.push_back(-1);
+    t.insert(t.end(), small.begin(), small.end());
+  }
+  return t;
+}
+
 adj_status build_host_scene(const adj_scene_desc* d, HostScene& s, std::string& err) {
   if (!d || d->n_verts <= 0 || d->n_tets <= 0 || !d->rest_pos || !d->tets || !d->E || !d->nu) {
     err = "scene_desc: missing arrays or non-positive sizes";
@@ -356,6 +378,8 @@ adj_status build_host_scene(const adj_scene_desc* d, HostScene& s, std::string& 
       s.Sj[o] = v;
       s.Sx[o] = s.STx[p];
     }
+  s.S_tasks = make_row_tasks(s.Sp, 256);
+  s.ST_tasks = make_row_tasks(s.STp, 256);
   return ADJ_OK;
 }
 

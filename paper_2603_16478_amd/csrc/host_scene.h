@@ -45,7 +45,13 @@ struct HostScene {
   std::vector<int64_t> Sp, STp;
   std::vector<int32_t> Sj, STj;
   std::vector<double> Sx, STx;
+  // load-balanced row tasks for the S and S^T products (4 ints per block)
+  std::vector<int32_t> S_tasks, ST_tasks;
 };
+
+// Pack CSR rows into blocks: rows longer than `big` get a block each (flag
+// 0x40000000), shorter rows go four to a block; -1 marks an empty slot.
+std::vector<int32_t> make_row_tasks(const std::vector<int64_t>& rowptr, int64_t big);
 
 // Returns ADJ_OK or an error code with a message in err.
 adj_status build_host_scene(const adj_scene_desc* d, HostScene& s, std::string& err);

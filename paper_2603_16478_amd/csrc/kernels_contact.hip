@@ -121,7 +121,7 @@ __global__ void k_contact_fold(int nc, const int* __restrict__ vid, const int* _
 }
 
 // C[r][r'] (row-major m x m) for the transposed system.
-__global__ void k_capacitance(int m, const int* __restrict__ row_c, const int* __restrict__ row_i,
+__global__ void k_capacitance(int m, int mp, const int* __restrict__ row_c, const int* __restrict__ row_i,
                               const int* __restrict__ cmap, int ncv, const double* __restrict__ D,
                               const double* __restrict__ Q, const double* __restrict__ kh, double mu,
                               double h2, double* __restrict__ C) {
@@ -142,7 +142,7 @@ __global__ void k_capacitance(int m, const int* __restrict__ row_c, const int* _
     else if (a == 1 && b == 1) v += 1.0 / kb;
     else if (a == 2 && b == 2) v += (kc > 1e-200) ? 1.0 / kc : 1e200;
   }
-  C[(size_t)i * m + j] = v;
+  C[(size_t)i * mp + j] = v;
 }
 
 // Contact part of the state gradient and the friction-coefficient gradient:
@@ -218,12 +218,12 @@ void launch_contact_fold(hipStream_t st, int nc, const int* vid, const int* diag
   k_contact_fold<<<(nc + 63) / 64, 64, 0, st>>>(nc, vid, diag_slot, Wt, val);
 }
 
-void launch_capacitance(hipStream_t st, int m, const int* row_c, const int* row_i, const int* cmap,
-                        int ncv, const double* D, const double* Q, const double* kh, double mu,
-                        double h2, double* C) {
+void launch_capacitance(hipStream_t st, int m, int mp, const int* row_c, const int* row_i,
+                        const int* cmap, int ncv, const double* D, const double* Q, const double* kh,
+                        double mu, double h2, double* C) {
   if (m == 0) return;
   dim3 grid((m + 255) / 256, m);
-  k_capacitance<<<grid, 256, 0, st>>>(m, row_c, row_i, cmap, ncv, D, Q, kh, mu, h2, C);
+  k_capacitance<<<grid, 256, 0, st>>>(m, mp, row_c, row_i, cmap, ncv, D, Q, kh, mu, h2, C);
 }
 
 void launch_vjp_contacts(hipStream_t st, int nc, const int* vid, const double* frame, const double* Kc,

@@ -67,108 +67,130 @@ __global__ void __launch_bounds__(256) k_spmm_Z(int nv, int ncv, const long long
 
 constexpr int kNB = 32;
 
-// Step 1 of block k: invert the diagonal block (partial pivoting inside the
-// block) into P, and save the old column block of C into colbuf (m x nb).
-__global__ void __launch_bounds__(256) k_gj_diag(int m, int k0, int kb, double* __restrict__ C,
-                                                 double* __restrict__ P, double* __restrict__ colbuf,
-                                                 int* __restrict__ err) {
-  __shared__ double A[kNB][2 * kNB + 1];
-  __shared__ int piv;
-  const int tid = threadIdx.x;
-  for (int e = tid; e < kb * 2 * kNB; e += blockDim.x) {
-    const int i = e / (2 * kNB), j = e % (2 * kNB);
-    A[i][j] = (j < kb) ? C[(size_t)(k0 + i) * m + k0 + j] : ((j - kNB == i) ? 1.0 : 0.0);
-  }
-  for (size_t e = tid; e < (size_t)m * kb; e += blockDim.x) {
-    const int i = (int)(e / kb), j = (int)(e % kb);
-    colbuf[(size_t)i * kNB + j] = C[(size_t)i * m + k0 + j];
-  }
-  __syncthreads();
-  for (int p = 0; p < kb; ++p) {
-    if (tid == 0) {
-      int best = p;
-      double bv = fabs(A[p][p]);
-      for (int i = p + 1; i < kb; ++i)
-        if (fabs(A[i][p]) > bv) {
-          bv = fabs(A[i][p]);
-          best = i;
-        }
-      piv = best;
-      if (!(bv > 0.0) || !isfinite(bv)) err[0] = 2;
+// Gauss-Jordan exchange step for the diagonal block k (rows/cols k0..k0+32)
+// of the padded mp x mp matrix (mp a multiple of 32, padding = identity):
+//   P = A_kk^{-1};  B_kk = P;  B_kj = P A_kj;  B_ik = -A_ik P;
+//   B_ij = A_ij - A_ik P A_kj
+// from buffer A into buffer B (ping-pong, so no block reads what another
+// block writes).  After all blocks the last output buffer is the inverse.
+//
+// One block of 256 threads per 32x32 output tile (I, J).  Wavefront 0
+// inverts A_kk in registers: lane c holds column c of [A_kk | I]; pivot
+// rows are found from uniform copies of the pivot column (readlane), so
+// the 32 elimination steps need no LDS round trips.
+
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+  int lo = __double2loint(v), hi = __double2hiint(v);
+  lo = __builtin_amdgcn_readlane(lo, lane);
+  hi = __builtin_amdgcn_readlane(hi, lane);
+  return __hiloint2double(hi, lo);
+}
+
+// One Gauss-Jordan pivot step (compile-time pivot index P, so every array
+// index below is a constant and the columns stay in registers).
+template <int P>
+__device__ __forceinline__ void gj_pivot(double (&col)[kNB], bool& bad) {
+  double f[kNB];
+#pragma unroll
+  for (int i = 0; i < kNB; ++i) f[i] = readlane_d(col[i], P);
+  int idx = P;
+  double best = fabs(f[P]);
+#pragma unroll
+  for (int i = P + 1; i < kNB; ++i)
+    if (fabs(f[i]) > best) {
+      best = fabs(f[i]);
+      idx = i;
     }
-    __syncthreads();
-    const int b = piv;
-    if (b != p)
-      for (int j = tid; j < 2 * kNB; j += blockDim.x) {
-        double t = A[p][j];
-        A[p][j] = A[b][j];
-        A[b][j] = t;
-      }
-    __syncthreads();
-    const double inv = 1.0 / A[p][p];
-    __syncthreads();
-    for (int j = tid; j < 2 * kNB; j += blockDim.x) A[p][j] *= inv;
-    __syncthreads();
-    for (int e = tid; e < kb * 2 * kNB; e += blockDim.x) {
-      const int i = e / (2 * kNB), j = e % (2 * kNB);
-      if (i != p && j != p) A[i][j] -= A[i][p] * A[p][j];
+  if (!(best > 0.0) || !isfinite(best)) bad = true;
+  const double cp = col[P], fp = f[P];
+  double cs = cp, fs = fp;
+#pragma unroll
+  for (int i = P + 1; i < kNB; ++i)
+    if (i == idx) {
+      cs = col[i];
+      fs = f[i];
+      col[i] = cp;
+      f[i] = fp;
     }
-    __syncthreads();
-    // column p is read by the sweep above and only cleared afterwards
-    for (int i = tid; i < kb; i += blockDim.x)
-      if (i != p) A[i][p] = 0.0;
-    __syncthreads();
-  }
-  for (int e = tid; e < kb * kb; e += blockDim.x) {
-    const int i = e / kb, j = e % kb;
-    P[i * kNB + j] = A[i][kNB + j];
+  const double inv = 1.0 / fs;
+  col[P] = cs * inv;
+#pragma unroll
+  for (int i = 0; i < kNB; ++i)
+    if (i != P) col[i] -= f[i] * col[P];
+  if constexpr (P + 1 < kNB) gj_pivot<P + 1>(col, bad);
+}
+
+__device__ __forceinline__ void invert32_wave(const double* __restrict__ Akk, int mp,
+                                              double (*Ps)[kNB + 1], int* __restrict__ err) {
+  const int lane = threadIdx.x & 63;
+  double col[kNB];
+#pragma unroll
+  for (int i = 0; i < kNB; ++i)
+    col[i] = (lane < kNB) ? Akk[(size_t)i * mp + lane] : ((lane - kNB == i) ? 1.0 : 0.0);
+  bool bad = false;
+  gj_pivot<0>(col, bad);
+  if (lane == 0 && bad) err[0] = 2;
+  if (lane >= kNB) {
+#pragma unroll
+    for (int i = 0; i < kNB; ++i) Ps[i][lane - kNB] = col[i];
   }
 }
 
-// Step 2: row block k of C <- P * (row block k), columns outside the block.
-__global__ void __launch_bounds__(256) k_gj_row(int m, int k0, int kb, double* __restrict__ C,
-                                                const double* __restrict__ P) {
-  __shared__ double Ps[kNB][kNB + 1];
-  __shared__ double R[kNB][65];
+__global__ void __launch_bounds__(256) k_gj_step(int mp, int k0, const double* __restrict__ A,
+                                                 double* __restrict__ B, int* __restrict__ err) {
+  __shared__ double Ps[kNB][kNB + 1];   // P = A_kk^{-1}
+  __shared__ double Cs[kNB][kNB + 1];   // A_{I,k}
+  __shared__ double Rs[kNB][kNB + 1];   // A_{k,J}
+  __shared__ double Ws[kNB][kNB + 1];   // W = A_{I,k} P
   const int tid = threadIdx.x;
-  const int j0 = blockIdx.x * 64;
-  for (int e = tid; e < kb * kb; e += blockDim.x) Ps[e / kb][e % kb] = P[(e / kb) * kNB + e % kb];
-  for (int e = tid; e < kb * 64; e += blockDim.x) {
-    const int i = e / 64, j = j0 + e % 64;
-    R[i][e % 64] = (j < m) ? C[(size_t)(k0 + i) * m + j] : 0.0;
+  const int I0 = blockIdx.y * kNB, J0 = blockIdx.x * kNB;
+  const bool Ik = (I0 == k0), Jk = (J0 == k0);
+  if (tid < 64) invert32_wave(A + (size_t)k0 * mp + k0, mp, Ps, err);
+  for (int e = tid; e < kNB * kNB; e += 256) {
+    const int r = e / kNB, c = e % kNB;
+    Cs[r][c] = A[(size_t)(I0 + r) * mp + k0 + c];
+    Rs[r][c] = A[(size_t)(k0 + r) * mp + J0 + c];
   }
   __syncthreads();
-  for (int e = tid; e < kb * 64; e += blockDim.x) {
-    const int i = e / 64, jj = e % 64, j = j0 + jj;
-    if (j >= m || (j >= k0 && j < k0 + kb)) continue;
-    double acc = 0.0;
-    for (int l = 0; l < kb; ++l) acc += Ps[i][l] * R[l][jj];
-    C[(size_t)(k0 + i) * m + j] = acc;
+  if (!Ik) {
+    for (int e = tid; e < kNB * kNB; e += 256) {
+      const int r = e / kNB, c = e % kNB;
+      double acc = 0.0;
+#pragma unroll 8
+      for (int l = 0; l < kNB; ++l) acc += Cs[r][l] * Ps[l][c];
+      Ws[r][c] = acc;
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < kNB * kNB; e += 256) {
+    const int r = e / kNB, c = e % kNB;
+    double v;
+    if (Ik && Jk) {
+      v = Ps[r][c];
+    } else if (Ik) {
+      double acc = 0.0;
+#pragma unroll 8
+      for (int l = 0; l < kNB; ++l) acc += Ps[r][l] * Rs[l][c];
+      v = acc;
+    } else if (Jk) {
+      v = -Ws[r][c];
+    } else {
+      double acc = 0.0;
+#pragma unroll 8
+      for (int l = 0; l < kNB; ++l) acc += Ws[r][l] * Rs[l][c];
+      v = A[(size_t)(I0 + r) * mp + J0 + c] - acc;
+    }
+    B[(size_t)(I0 + r) * mp + J0 + c] = v;
   }
 }
 
-// Step 3: every other row: C_ij -= colbuf_i . C_kj (j outside block k);
-// C_ik = -colbuf_i P; diagonal block <- P.
-__global__ void __launch_bounds__(256) k_gj_update(int m, int k0, int kb, double* __restrict__ C,
-                                                   const double* __restrict__ P,
-                                                   const double* __restrict__ colbuf) {
+// identity padding of rows/cols m..mp-1 of a row-major mp x mp matrix
+__global__ void k_pad_identity(int m, int mp, double* __restrict__ C) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   const int i = blockIdx.y;
-  if (j >= m) return;
-  const bool jin = (j >= k0 && j < k0 + kb);
-  if (i >= k0 && i < k0 + kb) {
-    if (jin) C[(size_t)i * m + j] = P[(i - k0) * kNB + (j - k0)];
-    return;
-  }
-  const double* cb = colbuf + (size_t)i * kNB;
-  double acc = 0.0;
-  if (jin) {
-    for (int l = 0; l < kb; ++l) acc -= cb[l] * P[l * kNB + (j - k0)];
-    C[(size_t)i * m + j] = acc;
-  } else {
-    for (int l = 0; l < kb; ++l) acc += cb[l] * C[(size_t)(k0 + l) * m + j];
-    C[(size_t)i * m + j] -= acc;
-  }
+  if (j >= mp || i >= mp) return;
+  if (i < m && j < m) return;
+  C[(size_t)i * mp + j] = (i == j) ? 1.0 : 0.0;
 }
 
 void launch_fill_zero(hipStream_t st, size_t n, double* a) {
@@ -186,14 +208,25 @@ void launch_delassus(hipStream_t st, int nv, int ncv, const int* cv, const long 
   k_spmm_Z<<<nv, 256, 0, st>>>(nv, ncv, STp, STj, STx, Y, Z);
 }
 
-void launch_gauss_jordan(hipStream_t st, int m, double* C, double* P, double* colbuf, int* err) {
-  for (int k0 = 0; k0 < m; k0 += kNB) {
-    const int kb = (m - k0 < kNB) ? (m - k0) : kNB;
-    k_gj_diag<<<1, 256, 0, st>>>(m, k0, kb, C, P, colbuf, err);
-    k_gj_row<<<(m + 63) / 64, 256, 0, st>>>(m, k0, kb, C, P);
-    dim3 g((m + 255) / 256, m);
-    k_gj_update<<<g, 256, 0, st>>>(m, k0, kb, C, P, colbuf);
+// Inverse of the m x m capacitance held in the top-left of the row-major
+// mp x mp buffer C0 (mp = 32 * ceil(m/32)); returns the buffer (C0 or C1)
+// that holds the inverse.
+double* launch_gauss_jordan(hipStream_t st, int m, int mp, double* C0, double* C1, int* err) {
+  if (mp > m) {
+    dim3 gpad((mp + 255) / 256, mp);
+    k_pad_identity<<<gpad, 256, 0, st>>>(m, mp, C0);
   }
+  double* A = C0;
+  double* B = C1;
+  const int nb = mp / kNB;
+  for (int k = 0; k < nb; ++k) {
+    dim3 g(nb, nb);
+    k_gj_step<<<g, 256, 0, st>>>(mp, k * kNB, A, B, err);
+    double* t = A;
+    A = B;
+    B = t;
+  }
+  return A;
 }
 
 }  // namespace adj

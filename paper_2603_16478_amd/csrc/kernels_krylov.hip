@@ -67,9 +67,71 @@ __global__ void __launch_bounds__(256) k_spmv_csr3(int nrows, const long long* _
   }
 }
 
+// Load-balanced variant: the host packs rows into tasks of one block each:
+// a long row (flag kBigRow) is reduced by the whole block, otherwise up to
+// four short rows are handled by one wavefront each (-1 = empty slot).
+constexpr int kBigRow = 0x40000000;
+
+__global__ void __launch_bounds__(256) k_spmv_tasks(const int4* __restrict__ tasks,
+                                                    const long long* __restrict__ rp,
+                                                    const int* __restrict__ cj,
+                                                    const double* __restrict__ cx,
+                                                    const double* __restrict__ xbase, long long stride,
+                                                    const double* __restrict__ scale,
+                                                    const GmresState* __restrict__ st, int use_j,
+                                                    double* __restrict__ y) {
+  if (gm_inactive(st)) return;
+  __shared__ double lds[32];
+  const int4 t = tasks[blockIdx.x];
+  const double* x = xbase;
+  double sc = 1.0;
+  if (use_j) {
+    x = xbase + (long long)st->j * stride;
+    sc = scale[st->j];
+  }
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+  if (t.x >= 0 && (t.x & kBigRow)) {
+    const int row = t.x & ~kBigRow;
+    for (long long p = rp[row] + threadIdx.x; p < rp[row + 1]; p += blockDim.x) {
+      const double v = cx[p];
+      const int c = cj[p];
+      a0 += v * x[3 * c];
+      a1 += v * x[3 * c + 1];
+      a2 += v * x[3 * c + 2];
+    }
+    a0 = block_sum(a0, lds);
+    a1 = block_sum(a1, lds);
+    a2 = block_sum(a2, lds);
+    if (threadIdx.x == 0) {
+      y[3 * row] = sc * a0;
+      y[3 * row + 1] = sc * a1;
+      y[3 * row + 2] = sc * a2;
+    }
+    return;
+  }
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int row = (w == 0) ? t.x : (w == 1) ? t.y : (w == 2) ? t.z : t.w;
+  if (row < 0) return;
+  for (long long p = rp[row] + lane; p < rp[row + 1]; p += 64) {
+    const double v = cx[p];
+    const int c = cj[p];
+    a0 += v * x[3 * c];
+    a1 += v * x[3 * c + 1];
+    a2 += v * x[3 * c + 2];
+  }
+  a0 = wave_sum(a0);
+  a1 = wave_sum(a1);
+  a2 = wave_sum(a2);
+  if (lane == 0) {
+    y[3 * row] = sc * a0;
+    y[3 * row + 1] = sc * a1;
+    y[3 * row + 2] = sc * a2;
+  }
+}
+
 // t = X (Hq u): each block first forms g = Hq u (m entries) in LDS, then one
 // wavefront per row of X.
-__global__ void __launch_bounds__(256) k_wb_gather(int m, const int* __restrict__ row_c,
+__global__ void __launch_bounds__(256) k_wb_gather(int m, int mp, const int* __restrict__ row_c,
                                                    const int* __restrict__ row_i,
                                                    const int* __restrict__ vid,
                                                    const double* __restrict__ Q,
@@ -89,7 +151,7 @@ __global__ void __launch_bounds__(256) k_wb_gather(int m, const int* __restrict_
   const int lane = threadIdx.x & 63;
   const int row = blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
   if (row >= m) return;
-  const double* xr = X + (size_t)row * m;
+  const double* xr = X + (size_t)row * mp;
   double acc = 0.0;
   for (int k = lane; k < m; k += 64) acc += xr[k] * g[k];
   acc = wave_sum(acc);
@@ -178,7 +240,7 @@ __global__ void __launch_bounds__(256) k_bsr_spmv(int nv, const int* __restrict_
   }
 }
 
-constexpr int kRowsPerBlock = 1024;
+constexpr int kRowsPerBlock = 256;
 
 // CGS pass 1: h_i = scale_i * (Vt_i . w), i <= j, with w = Vt_{j+1}.
 // Per-block partials; the last block reduces into hbuf.
@@ -361,11 +423,19 @@ void launch_spmv_csr3(hipStream_t s, int nrows, const long long* rp, const int* 
   k_spmv_csr3<<<(nrows + 3) / 4, 256, 0, s>>>(nrows, rp, cj, cx, xbase, stride, scale, st, use_j, y);
 }
 
-void launch_wb_gather(hipStream_t s, int m, const int* row_c, const int* row_i, const int* vid,
+void launch_spmv_tasks(hipStream_t s, int ntasks, const int4* tasks, const long long* rp, const int* cj,
+                       const double* cx, const double* xbase, long long stride, const double* scale,
+                       const GmresState* st, double* y) {
+  const int use_j = (st != nullptr && scale != nullptr) ? 1 : 0;
+  k_spmv_tasks<<<ntasks, 256, 0, s>>>(tasks, rp, cj, cx, xbase, stride, scale, st, use_j, y);
+}
+
+void launch_wb_gather(hipStream_t s, int m, int mp, const int* row_c, const int* row_i, const int* vid,
                       const double* Q, const double* X, const double* u, const GmresState* st,
                       double* t) {
   if (m == 0) return;
-  k_wb_gather<<<(m + 3) / 4, 256, (size_t)m * sizeof(double), s>>>(m, row_c, row_i, vid, Q, X, u, st, t);
+  k_wb_gather<<<(m + 3) / 4, 256, (size_t)m * sizeof(double), s>>>(m, mp, row_c, row_i, vid, Q, X, u, st,
+                                                                    t);
 }
 
 void launch_wb_correct(hipStream_t s, int nv, int ncv, const int* cv_ptr, const int* c_row0,

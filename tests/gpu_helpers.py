@@ -36,7 +36,8 @@ def contact_tensors(record, device="cuda"):
     return t
 
 
-def run_adjoint(scene, record, q, gq, gv, rtol=1e-13, maxit=3000, restart=64, want_tet=False):
+def run_adjoint(scene, record, q, gq, gv, rtol=1e-13, maxit=3000, restart=64, want_tet=False,
+                raise_noconv=True):
     """setup + solve + vjp on the GPU; returns a dict of numpy results."""
     torch = torch_cuda()
     from paper_2603_16478_amd import native
@@ -51,7 +52,7 @@ def run_adjoint(scene, record, q, gq, gv, rtol=1e-13, maxit=3000, restart=64, wa
     opts = native.solve_opts(rtol=rtol, maxit=maxit, restart=restart)
     native.adjoint_setup(scene, cs, qd, opts)
     native.check_status(scene)
-    info = native.adjoint_solve(scene, gqd, gvd, z, opts)
+    info = native.adjoint_solve(scene, gqd, gvd, z, opts, raise_noconv=raise_noconv)
     dqbar, dvbar, dfext = torch.empty_like(qd), torch.empty_like(qd), torch.empty_like(qd)
     grad3 = torch.zeros(3, dtype=torch.float64, device=dev)
     nt = scene.n_tets
