@@ -167,6 +167,27 @@ def main():
     torch.cuda.synchronize()
     bms, blaunch = native.profile_end(scene)
 
+    # mixed precision (FP32-stored matrices inside GMRES, FP64 refinement) on the same steps
+    opts_m = native.solve_opts(rtol=args.rtol, maxit=5000, restart=64, prec=native.ADJ_MIXED, max_refine=8)
+    miters = []
+
+    def one_mixed(i):
+        t = dstates[i % len(dstates)]
+        native.adjoint_setup(scene, t["cs"], t["q"], opts_m)
+        info_m = native.adjoint_solve(scene, gq, gv, z, opts_m)
+        native.vjp_params(scene, z, gv, dqbar, dvbar, dfext, grad3)
+        miters.append((info_m.iters, info_m.refine_steps))
+
+    for i in range(args.warmup):
+        one_mixed(i)
+    torch.cuda.synchronize()
+    miters.clear()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        one_mixed(args.warmup + i)
+    torch.cuda.synchronize()
+    dt_m = time.perf_counter() - t0
+
     t_avg = dstates[0]
     nc0 = int(states[0]["vid"].shape[0])
     abytes = algorithmic_bytes(args.roofline_kernel, info, nc0, t_avg["m"], t_avg["ncv"])
@@ -213,6 +234,11 @@ def main():
         },
         "matvec": {"bytes_per_launch": mv_bytes, "avg_launch_us": 1e3 * mv_ms,
                    "GB/s": mv_bytes / (mv_ms * 1e-3) / 1e9 if blaunch else None},
+        "mixed": {"value": args.steps / dt_m, "unit": "adjoint solves/s",
+                  "ms_per_step": 1e3 * dt_m / args.steps,
+                  "krylov_iters_mean": float(np.mean([a for a, _ in miters])),
+                  "refine_steps_mean": float(np.mean([b for _, b in miters])),
+                  "speedup_vs_fp64": (args.steps / dt_m) / (args.steps / dt)},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(spec, states, args.cpu_sample)

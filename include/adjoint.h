@@ -152,15 +152,28 @@ adj_status vjp_params(adj_scene* scene, const double* z, const double* dL_dv, do
                       double* dnu_tet, void* stream);
 
 /* One implicit step (eq:dynamics): converge (q, lambda) from (qbar, vbar,
- * f_ext) with a damped Newton method whose linear systems are Acal dq = r,
- * and write q, v and the contact state of the step.  qbar, vbar, f_ext, q,
- * v: device [n_verts*3]; f_ext excludes gravity (taken from the scene).
- * contacts->capacity bounds the number of contacts (ADJ_E_SHAPE beyond).
- * Synchronises the stream.  Returns ADJ_E_NOCONV if the Newton residual did
- * not reach its tolerance. */
+ * f_ext) with a damped Newton method whose linear systems are Acal du = r
+ * (the adjoint matrix at the iterate, solved with the same GMRES and
+ * Woodbury preconditioner), and write q, v and the contact state of the
+ * step.  qbar, vbar, f_ext, q, v: device [n_verts*3]; f_ext excludes gravity
+ * (taken from the scene).  contacts->capacity bounds the number of contacts
+ * (ADJ_E_SHAPE beyond); its arrays receive the step record (d_n, d_f may be
+ * NULL).  Contact multipliers are warm-started from the previous call on the
+ * same scene (adj_forward_reset clears them).  Synchronises the stream.
+ * Invalidates the last adjoint_setup.  Returns ADJ_E_NOCONV if the paper's
+ * residual rows did not fall below 1e-8, ADJ_E_INVERTED for an inverted
+ * element at the initial guess. */
 adj_status sim_forward_step(adj_scene* scene, const double* qbar, const double* vbar,
                             const double* f_ext, double mu, double* q, double* v,
                             adj_contact_state* contacts, void* stream);
+
+/* out[0] = Newton iterations of the last sim_forward_step, out[1] = the
+ * max-norm of its residual rows (force rows in N, contact rows unscaled).
+ * out: host [2]. */
+adj_status adj_forward_stats(const adj_scene* scene, double* out);
+
+/* Forget the warm start of the contact multipliers. */
+adj_status adj_forward_reset(adj_scene* scene);
 
 /* Scene sizes and host-side statistics: out[0] n_verts, out[1] n_tets,
  * out[2] nnz blocks of Acal, out[3] nnz(L), out[4] nnz(S), out[5]

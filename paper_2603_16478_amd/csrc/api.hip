@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <unordered_map>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -32,7 +33,7 @@ void launch_contact_blocks(hipStream_t, int, const int*, const double*, const do
                            double, double, double, int, double*, double*, double*, double*, double*);
 void launch_contact_fold(hipStream_t, int, const int*, const int*, const double*, double*);
 void launch_capacitance(hipStream_t, int, int, const int*, const int*, const int*, int, const double*,
-                        const double*, const double*, double, double, double*);
+                        const double*, const double*, double, double, int, double*);
 void launch_vjp_contacts(hipStream_t, int, const int*, const double*, const double*, const double*,
                          const double*, double, double*, double*, unsigned*, double*);
 void launch_vjp_vectors(hipStream_t, int, const double*, const double*, const double*, double, double*,
@@ -45,6 +46,15 @@ void launch_spmv_csr3(hipStream_t, int, const long long*, const int*, const doub
                       long long, const double*, const GmresState*, double*);
 void launch_spmv_tasks(hipStream_t, int, const int4*, const long long*, const int*, const double*,
                        const double*, long long, const double*, const GmresState*, double*);
+void launch_spmv_tasks(hipStream_t, int, const int4*, const long long*, const int*, const float*,
+                       const double*, long long, const double*, const GmresState*, double*);
+void launch_wb_gather(hipStream_t, int, int, const int*, const int*, const int*, const double*,
+                      const float*, const double*, const GmresState*, double*);
+void launch_wb_correct(hipStream_t, int, int, const int*, const int*, const int*, const double*,
+                       const double*, const float*, double, const double*, const GmresState*, double*);
+void launch_bsr_spmv(hipStream_t, int, const int*, const int*, const float*, const double*, double*,
+                     long long, const GmresState*);
+void launch_to_f32(hipStream_t, long long, const double*, float*);
 void launch_wb_gather(hipStream_t, int, int, const int*, const int*, const int*, const double*,
                       const double*, const double*, const GmresState*, double*);
 void launch_wb_correct(hipStream_t, int, int, const int*, const int*, const int*, const double*,
@@ -61,6 +71,19 @@ void launch_gm_finish(hipStream_t, long long, const GmresState*, const double*, 
 void launch_axpy(hipStream_t, long long, double, const double*, double*);
 void launch_residual(hipStream_t, long long, const double*, double*, double*, double*, unsigned*,
                      GmresState*, double*, double*);
+
+void launch_fwd_predict(hipStream_t, int, const double*, const double*, const double*, const double*, double,
+                        const double*, double*, double*);
+void launch_fwd_detect(hipStream_t, int, const double*, int, const double*, double, int*);
+void launch_add_vec(hipStream_t, long long, const double*, const double*, double, double*);
+void launch_scale_vec(hipStream_t, long long, const double*, double, double*);
+void launch_tet_force(hipStream_t, int, const int*, const double*, const double*, const double*,
+                      const double*, double, const double*, double*, int*);
+void launch_gather_force(hipStream_t, int, const int*, const int*, const double*, const double*,
+                         const double*, const double*, double*);
+void launch_add_contact_vec(hipStream_t, int, const int*, const double*, double*);
+void launch_gather_contact_rows(hipStream_t, int, const int*, const double*, double*);
+void launch_norms(hipStream_t, long long, const double*, double*, unsigned*, double*);
 
 }  // namespace adj
 
@@ -144,6 +167,19 @@ struct adj_scene {
   GmresState* h_state = nullptr;  // pinned
   double *d_t1 = nullptr, *d_u = nullptr, *d_y = nullptr, *d_r = nullptr, *d_b = nullptr,
          *d_dz = nullptr, *d_xt = nullptr;
+  // mixed precision: FP32 storage of the matrices used inside the inner solve
+  float *d_Sx32 = nullptr, *d_STx32 = nullptr, *d_val32 = nullptr, *d_Z32 = nullptr, *d_X32 = nullptr;
+  size_t cap_z32 = 0, cap_x32 = 0;
+  bool z32_valid = false, mixed_ready = false;
+  // forward step
+  double* d_planes = nullptr;
+  int *d_vptr = nullptr, *d_vcode = nullptr, *d_mask = nullptr, *d_fvid = nullptr;
+  double *d_force = nullptr, *d_utilde = nullptr, *d_qtilde = nullptr, *d_fu = nullptr, *d_du = nullptr,
+         *d_ut = nullptr, *d_qcur = nullptr, *d_rq = nullptr, *d_rhs = nullptr, *d_cvec = nullptr,
+         *d_cu = nullptr, *d_norms = nullptr;
+  std::unordered_map<long long, std::pair<double, double>> warm;
+  int fwd_newton_iters = 0;
+  double fwd_residual = 0.0;
   // live kernel timing (adj_profile_begin / adj_profile_end)
   int prof_kernel = -1;
   std::vector<hipEvent_t> prof_ev;
@@ -191,7 +227,11 @@ static void free_scene(adj_scene* s) {
                   s->d_cs,       s->d_sn,     s->d_g,     s->d_hbuf,        s->d_coef,
                   s->d_partial,  s->d_counter, s->d_state, s->d_t1,         s->d_u,
                   s->d_y,        s->d_r,      s->d_b,     s->d_dz,          s->d_xt,
-                  s->d_Stasks,   s->d_STtasks};
+                  s->d_Stasks,   s->d_STtasks, s->d_planes,  s->d_vptr,   s->d_vcode,
+                  s->d_mask,     s->d_fvid,   s->d_force, s->d_utilde,      s->d_qtilde,
+                  s->d_fu,       s->d_du,     s->d_ut,    s->d_qcur,        s->d_rq,
+                  s->d_rhs,      s->d_cvec,   s->d_cu,    s->d_norms,       s->d_Sx32,
+                  s->d_STx32,    s->d_val32,  s->d_Z32,   s->d_X32};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (s->h_state) (void)hipHostFree(s->h_state);
@@ -252,6 +292,9 @@ extern "C" adj_status adj_scene_create(const adj_scene_desc* desc, int32_t max_c
   UP(s->d_STj, h.STj);
   UP(s->d_Sx, h.Sx);
   UP(s->d_STx, h.STx);
+  UP(s->d_planes, h.planes);
+  UP(s->d_vptr, h.vptr);
+  UP(s->d_vcode, h.vcode);
   UP(s->d_Stasks, h.S_tasks);
   UP(s->d_STtasks, h.ST_tasks);
   s->nS_tasks = (int)(h.S_tasks.size() / 4);
@@ -297,10 +340,29 @@ extern "C" adj_status adj_scene_create(const adj_scene_desc* desc, int32_t max_c
   ok &= dalloc(&s->d_dz, (size_t)s->n3) == hipSuccess;
   ok &= dalloc(&s->d_xt, (size_t)s->n3) == hipSuccess;
   ok &= hipHostMalloc((void**)&s->h_state, sizeof(GmresState), hipHostMallocDefault) == hipSuccess;
+  ok &= dalloc(&s->d_mask, (size_t)s->nv) == hipSuccess;
+  ok &= dalloc(&s->d_Sx32, h.Sx.size()) == hipSuccess;
+  ok &= dalloc(&s->d_STx32, h.STx.size()) == hipSuccess;
+  ok &= dalloc(&s->d_val32, 9 * (size_t)s->nnzb) == hipSuccess;
+  ok &= dalloc(&s->d_fvid, mc) == hipSuccess;
+  ok &= dalloc(&s->d_force, 12 * (size_t)s->nt) == hipSuccess;
+  ok &= dalloc(&s->d_utilde, (size_t)s->n3) == hipSuccess;
+  ok &= dalloc(&s->d_qtilde, (size_t)s->n3) == hipSuccess;
+  ok &= dalloc(&s->d_fu, (size_t)s->n3) == hipSuccess;
+  ok &= dalloc(&s->d_du, (size_t)s->n3) == hipSuccess;
+  ok &= dalloc(&s->d_ut, (size_t)s->n3) == hipSuccess;
+  ok &= dalloc(&s->d_qcur, (size_t)s->n3) == hipSuccess;
+  ok &= dalloc(&s->d_rq, (size_t)s->n3) == hipSuccess;
+  ok &= dalloc(&s->d_rhs, (size_t)s->n3) == hipSuccess;
+  ok &= dalloc(&s->d_cvec, 3 * mc) == hipSuccess;
+  ok &= dalloc(&s->d_cu, 3 * mc) == hipSuccess;
+  ok &= dalloc(&s->d_norms, 4) == hipSuccess;
   if (!ok) {
     free_scene(s);
     return fail(ADJ_E_OOM, "device workspace allocation failed");
   }
+  launch_to_f32(nullptr, (long long)h.Sx.size(), s->d_Sx, s->d_Sx32);
+  launch_to_f32(nullptr, (long long)h.STx.size(), s->d_STx, s->d_STx32);
   if (hipMemset(s->d_counter, 0, 16 * sizeof(unsigned)) != hipSuccess ||
       hipMemset(s->d_err, 0, 4 * sizeof(int)) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
     free_scene(s);
@@ -314,6 +376,18 @@ extern "C" adj_status adj_scene_destroy(adj_scene* scene) {
   if (!scene) return fail(ADJ_E_ARG, "scene is null");
   (void)hipDeviceSynchronize();
   free_scene(scene);
+  return ADJ_OK;
+}
+
+static adj_status growf(float** p, size_t* cap, size_t need) {
+  if (need <= *cap && *p) return ADJ_OK;
+  if (*p) (void)hipFree(*p);
+  *p = nullptr;
+  if (dalloc(p, need) != hipSuccess) {
+    *cap = 0;
+    return fail(ADJ_E_OOM, "device allocation failed");
+  }
+  *cap = need;
   return ADJ_OK;
 }
 
@@ -340,24 +414,11 @@ static adj_status grow(double** p, size_t* cap, size_t need) {
   return ADJ_OK;
 }
 
-extern "C" adj_status adjoint_setup(adj_scene* s, const adj_contact_state* cst, const double* q,
-                                    const adj_solve_opts* opts, void* stream) {
-  if (!s || !cst || !q) return fail(ADJ_E_ARG, "null argument");
-  if (cst->n_contacts < 0 || cst->n_contacts > s->max_contacts)
-    return fail(ADJ_E_SHAPE, "n_contacts exceeds the scene's max_contacts");
-  if (cst->n_contacts > 0 && (!cst->vid || !cst->fric || !cst->frame || !cst->delta || !cst->lambda))
-    return fail(ADJ_E_ARG, "contact arrays missing");
-  if (!std::isfinite(cst->mu) || cst->mu < 0) return fail(ADJ_E_ARG, "mu must be finite and >= 0");
-  hipStream_t st = (hipStream_t)stream;
-  const int nc = cst->n_contacts;
-  const double h2 = s->hs.h * s->hs.h;
-  // contact bookkeeping on the host: unique contact vertices, row layout
-  std::vector<int> vid(nc), fric(nc);
-  if (nc) {
-    HIPCHK(hipMemcpyAsync(vid.data(), cst->vid, nc * sizeof(int), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync(fric.data(), cst->fric, nc * sizeof(int), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-  }
+// Contact bookkeeping shared by the adjoint and the forward step: unique
+// contact vertices, capacitance row layout, upload of the maps, and the
+// Delassus matrix / Z (rebuilt only when the contact vertex set changes).
+static adj_status contact_layout(adj_scene* s, hipStream_t st, int nc, const std::vector<int>& vid,
+                                 const std::vector<int>& fric, bool reuse) {
   std::vector<int> cv, cv_ptr, cmap(nc), row_c, row_i, c_row0(nc), c_nrow(nc);
   for (int c = 0; c < nc; ++c) {
     if (vid[c] < 0 || vid[c] >= s->nv) return fail(ADJ_E_ARG, "contact vertex out of range");
@@ -379,10 +440,6 @@ extern "C" adj_status adjoint_setup(adj_scene* s, const adj_contact_state* cst, 
   s->nc = nc;
   s->ncv = ncv;
   s->m = m;
-  s->mu = cst->mu;
-  s->cur_vid = cst->vid;
-  s->cur_frame = cst->frame;
-  s->cur_q = q;
   if (nc) {
     HIPCHK(hipMemcpyAsync(s->d_cmap, cmap.data(), nc * sizeof(int), hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(s->d_c_row0, c_row0.data(), nc * sizeof(int), hipMemcpyHostToDevice, st));
@@ -391,7 +448,70 @@ extern "C" adj_status adjoint_setup(adj_scene* s, const adj_contact_state* cst, 
     HIPCHK(hipMemcpyAsync(s->d_row_i, row_i.data(), m * sizeof(int), hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(s->d_cv, cv.data(), ncv * sizeof(int), hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(s->d_cv_ptr, cv_ptr.data(), (ncv + 1) * sizeof(int), hipMemcpyHostToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));  // host vectors go out of scope
   }
+  s->delassus_rebuilt = 0;
+  if (nc && !(reuse && s->delassus_valid && cv == s->cv_cached)) {
+    adj_status a;
+    size_t capY = s->cap_ncv ? (size_t)s->nv * s->cap_ncv : 0, capD = s->cap_ncv * s->cap_ncv, capZ = capY;
+    if ((size_t)ncv > s->cap_ncv) capY = capZ = capD = 0;
+    if ((a = grow(&s->d_Y, &capY, (size_t)s->nv * ncv)) != ADJ_OK) return a;
+    if ((a = grow(&s->d_Z, &capZ, (size_t)s->nv * ncv)) != ADJ_OK) return a;
+    if ((a = grow(&s->d_D, &capD, (size_t)ncv * ncv)) != ADJ_OK) return a;
+    s->cap_ncv = std::max(s->cap_ncv, (size_t)ncv);
+    launch_delassus(st, s->nv, ncv, s->d_cv, s->d_STp, s->d_STj, s->d_STx, s->d_Y, s->d_D, s->d_Z);
+    s->cv_cached = cv;
+    s->delassus_valid = true;
+    s->delassus_rebuilt = 1;
+    s->z32_valid = false;
+  }
+  return ADJ_OK;
+}
+
+// Capacitance Khat^{-T} + h^2 Hq A^{-1} Hq^T (transpose = 1, adjoint) or
+// Khat^{-1} + ... (transpose = 0, forward Newton) from s->d_Q, s->d_kh, and
+// its inverse s->d_X.
+static adj_status build_capacitance(adj_scene* s, hipStream_t st, double mu, int transpose) {
+  if (!s->nc) return ADJ_OK;
+  const double h2 = s->hs.h * s->hs.h;
+  const int m = s->m, mp = ((m + 31) / 32) * 32;
+  s->mp = mp;
+  size_t capC = s->cap_m * s->cap_m, capB = capC;
+  if ((size_t)mp > s->cap_m) capC = capB = 0;
+  adj_status a;
+  if ((a = grow(&s->d_C, &capC, (size_t)mp * mp)) != ADJ_OK) return a;
+  if ((a = grow(&s->d_colbuf, &capB, (size_t)mp * mp)) != ADJ_OK) return a;
+  s->cap_m = std::max(s->cap_m, (size_t)mp);
+  launch_capacitance(st, m, mp, s->d_row_c, s->d_row_i, s->d_cmap, s->ncv, s->d_D, s->d_Q, s->d_kh, mu, h2,
+                     transpose, s->d_C);
+  {
+    ProfScope p(s, 7, st);
+    s->d_X = launch_gauss_jordan(st, m, mp, s->d_C, s->d_colbuf, s->d_err);
+  }
+  return ADJ_OK;
+}
+
+extern "C" adj_status adjoint_setup(adj_scene* s, const adj_contact_state* cst, const double* q,
+                                    const adj_solve_opts* opts, void* stream) {
+  if (!s || !cst || !q) return fail(ADJ_E_ARG, "null argument");
+  if (cst->n_contacts < 0 || cst->n_contacts > s->max_contacts)
+    return fail(ADJ_E_SHAPE, "n_contacts exceeds the scene's max_contacts");
+  if (cst->n_contacts > 0 && (!cst->vid || !cst->fric || !cst->frame || !cst->delta || !cst->lambda))
+    return fail(ADJ_E_ARG, "contact arrays missing");
+  if (!std::isfinite(cst->mu) || cst->mu < 0) return fail(ADJ_E_ARG, "mu must be finite and >= 0");
+  hipStream_t st = (hipStream_t)stream;
+  const int nc = cst->n_contacts;
+  const double h2 = s->hs.h * s->hs.h;
+  std::vector<int> vid(nc), fric(nc);
+  if (nc) {
+    HIPCHK(hipMemcpyAsync(vid.data(), cst->vid, nc * sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(fric.data(), cst->fric, nc * sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+  }
+  s->mu = cst->mu;
+  s->cur_vid = cst->vid;
+  s->cur_frame = cst->frame;
+  s->cur_q = q;
   // a1 + a2: per-tet Jacobians, gather assembly of Acal^T
   {
     ProfScope p(s, 5, st);
@@ -408,39 +528,23 @@ extern "C" adj_status adjoint_setup(adj_scene* s, const adj_contact_state* cst, 
                         s->d_Wt, s->d_Q, s->d_kh, s->d_Kc, s->d_kmu);
   launch_contact_fold(st, nc, cst->vid, s->d_diag_slot, s->d_Wt, s->d_val);
   // a4: Delassus (cached per contact vertex set), capacitance, its inverse
-  s->delassus_rebuilt = 0;
-  if (nc) {
-    const bool reuse = opts ? opts->reuse_delassus != 0 : true;
-    if (!(reuse && s->delassus_valid && cv == s->cv_cached)) {
-      adj_status a;
-      size_t capY = s->cap_ncv ? (size_t)s->nv * s->cap_ncv : 0, capD = s->cap_ncv * s->cap_ncv,
-             capZ = capY;
-      if ((size_t)ncv > s->cap_ncv) {
-        capY = capZ = capD = 0;
+  adj_status a = contact_layout(s, st, nc, vid, fric, opts ? opts->reuse_delassus != 0 : true);
+  if (a != ADJ_OK) return a;
+  if ((a = build_capacitance(s, st, cst->mu, 1)) != ADJ_OK) return a;
+  s->mixed_ready = false;
+  if (opts && opts->prec == ADJ_MIXED) {
+    // FP32 storage of the matrices read inside the inner solve
+    launch_to_f32(st, 9LL * s->nnzb, s->d_val, s->d_val32);
+    if (nc) {
+      if (!s->z32_valid) {
+        if ((a = growf(&s->d_Z32, &s->cap_z32, (size_t)s->nv * s->ncv)) != ADJ_OK) return a;
+        launch_to_f32(st, (long long)s->nv * s->ncv, s->d_Z, s->d_Z32);
+        s->z32_valid = true;
       }
-      if ((a = grow(&s->d_Y, &capY, (size_t)s->nv * ncv)) != ADJ_OK) return a;
-      if ((a = grow(&s->d_Z, &capZ, (size_t)s->nv * ncv)) != ADJ_OK) return a;
-      if ((a = grow(&s->d_D, &capD, (size_t)ncv * ncv)) != ADJ_OK) return a;
-      s->cap_ncv = std::max(s->cap_ncv, (size_t)ncv);
-      launch_delassus(st, s->nv, ncv, s->d_cv, s->d_STp, s->d_STj, s->d_STx, s->d_Y, s->d_D, s->d_Z);
-      s->cv_cached = cv;
-      s->delassus_valid = true;
-      s->delassus_rebuilt = 1;
+      if ((a = growf(&s->d_X32, &s->cap_x32, (size_t)s->mp * s->mp)) != ADJ_OK) return a;
+      launch_to_f32(st, (long long)s->mp * s->mp, s->d_X, s->d_X32);
     }
-    const int mp = ((m + 31) / 32) * 32;
-    s->mp = mp;
-    size_t capC = s->cap_m * s->cap_m, capB = capC;
-    if ((size_t)mp > s->cap_m) capC = capB = 0;
-    adj_status a;
-    if ((a = grow(&s->d_C, &capC, (size_t)mp * mp)) != ADJ_OK) return a;
-    if ((a = grow(&s->d_colbuf, &capB, (size_t)mp * mp)) != ADJ_OK) return a;
-    s->cap_m = std::max(s->cap_m, (size_t)mp);
-    launch_capacitance(st, m, mp, s->d_row_c, s->d_row_i, s->d_cmap, ncv, s->d_D, s->d_Q, s->d_kh, cst->mu,
-                       h2, s->d_C);
-    {
-      ProfScope p(s, 7, st);
-      s->d_X = launch_gauss_jordan(st, m, mp, s->d_C, s->d_colbuf, s->d_err);
-    }
+    s->mixed_ready = true;
   }
   HIPCHK(hipGetLastError());
   s->setup_done = true;
@@ -458,49 +562,68 @@ extern "C" adj_status adj_check_status(adj_scene* s, void* stream) {
   return ADJ_OK;
 }
 
-// P x -> out (x and out distinct from the scratch vectors t1, u, tvec)
+// P x -> out (x and out distinct from the scratch vectors t1, u, tvec).
+// f32: the matrices are read from their FP32 copies (vectors stay FP64).
 static void apply_precond(adj_scene* s, hipStream_t st, const double* x, long long stride,
-                          const double* scale, const GmresState* state, double* out) {
+                          const double* scale, const GmresState* state, double* out, bool f32 = false) {
   const double h2 = s->hs.h * s->hs.h;
   {
     ProfScope p(s, 0, st);
-    launch_spmv_tasks(st, s->nS_tasks, (const int4*)s->d_Stasks, s->d_Sp, s->d_Sj, s->d_Sx, x, stride, scale,
-                      state, s->d_t1);
+    if (f32)
+      launch_spmv_tasks(st, s->nS_tasks, (const int4*)s->d_Stasks, s->d_Sp, s->d_Sj, s->d_Sx32, x, stride,
+                        scale, state, s->d_t1);
+    else
+      launch_spmv_tasks(st, s->nS_tasks, (const int4*)s->d_Stasks, s->d_Sp, s->d_Sj, s->d_Sx, x, stride,
+                        scale, state, s->d_t1);
   }
   double* u = (s->nc == 0) ? out : s->d_u;
   {
     ProfScope p(s, 1, st);
-    launch_spmv_tasks(st, s->nST_tasks, (const int4*)s->d_STtasks, s->d_STp, s->d_STj, s->d_STx, s->d_t1, 0,
-                      nullptr, state, u);
+    if (f32)
+      launch_spmv_tasks(st, s->nST_tasks, (const int4*)s->d_STtasks, s->d_STp, s->d_STj, s->d_STx32, s->d_t1,
+                        0, nullptr, state, u);
+    else
+      launch_spmv_tasks(st, s->nST_tasks, (const int4*)s->d_STtasks, s->d_STp, s->d_STj, s->d_STx, s->d_t1,
+                        0, nullptr, state, u);
   }
   if (s->nc == 0) return;
   {
     ProfScope p(s, 2, st);
-    launch_wb_gather(st, s->m, s->mp, s->d_row_c, s->d_row_i, s->cur_vid, s->d_Q, s->d_X, s->d_u, state,
-                     s->d_tvec);
+    if (f32)
+      launch_wb_gather(st, s->m, s->mp, s->d_row_c, s->d_row_i, s->cur_vid, s->d_Q, s->d_X32, s->d_u, state,
+                       s->d_tvec);
+    else
+      launch_wb_gather(st, s->m, s->mp, s->d_row_c, s->d_row_i, s->cur_vid, s->d_Q, s->d_X, s->d_u, state,
+                       s->d_tvec);
   }
   {
     ProfScope p(s, 3, st);
-    launch_wb_correct(st, s->nv, s->ncv, s->d_cv_ptr, s->d_c_row0, s->d_c_nrow, s->d_Q, s->d_tvec, s->d_Z,
-                      h2, s->d_u, state, out);
+    if (f32)
+      launch_wb_correct(st, s->nv, s->ncv, s->d_cv_ptr, s->d_c_row0, s->d_c_nrow, s->d_Q, s->d_tvec,
+                        s->d_Z32, h2, s->d_u, state, out);
+    else
+      launch_wb_correct(st, s->nv, s->ncv, s->d_cv_ptr, s->d_c_row0, s->d_c_nrow, s->d_Q, s->d_tvec, s->d_Z,
+                        h2, s->d_u, state, out);
   }
 }
 
-extern "C" adj_status adjoint_solve(adj_scene* s, const double* dL_dq, const double* dL_dv, double* z,
-                                    const adj_solve_opts* opts, adj_solve_info* info, void* stream) {
-  if (!s || !dL_dq || !dL_dv || !z || !opts) return fail(ADJ_E_ARG, "null argument");
-  if (!s->setup_done) return fail(ADJ_E_ARG, "adjoint_setup has not run");
-  if (!(opts->rtol > 0) || opts->maxit <= 0 || opts->restart < 1 || opts->restart > kMaxRestart)
-    return fail(ADJ_E_ARG, "invalid solve options");
-  if (opts->prec != ADJ_FP64) return fail(ADJ_E_NOTIMPL, "only ADJ_FP64 is implemented in this build");
-  hipStream_t st = (hipStream_t)stream;
+static void bsr(adj_scene* s, hipStream_t st, const double* x, double* outbase, long long stride,
+                const GmresState* state, bool f32) {
+  if (f32)
+    launch_bsr_spmv(st, s->nv, s->d_rowptr, s->d_col, s->d_val32, x, outbase, stride, state);
+  else
+    launch_bsr_spmv(st, s->nv, s->d_rowptr, s->d_col, s->d_val, x, outbase, stride, state);
+}
+
+// Right-preconditioned restarted GMRES on the assembled matrix (s->d_val,
+// contacts folded) with the current Woodbury preconditioner: x = A^{-1} b.
+static adj_status gmres_solve(adj_scene* s, hipStream_t st, const double* b, double* x, double rtol,
+                              int maxit, int R, int* iters_out, double* relres_out, bool* converged_out,
+                              bool f32 = false) {
   const long long n3 = s->n3;
   const long long stride = n3;
-  const int R = opts->restart;
-  // b = dL_dq + dL_dv / h
-  HIPCHK(hipMemcpyAsync(s->d_b, dL_dq, n3 * sizeof(double), hipMemcpyDeviceToDevice, st));
-  launch_axpy(st, n3, 1.0 / s->hs.h, dL_dv, s->d_b);
-  launch_fill_zero(st, (size_t)n3, z);
+  if (b != s->d_b) HIPCHK(hipMemcpyAsync(s->d_b, b, n3 * sizeof(double), hipMemcpyDeviceToDevice, st));
+  launch_fill_zero(st, (size_t)n3, x);
   launch_fill_zero(st, (size_t)n3, s->d_r);
   GmresState init{};
   init.restart = R;
@@ -511,7 +634,7 @@ extern "C" adj_status adjoint_solve(adj_scene* s, const double* dL_dq, const dou
   HIPCHK(hipMemcpyAsync(s->h_state, s->d_state, sizeof(GmresState), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   const double bnorm = s->h_state->rnorm;
-  const double tol = opts->rtol * bnorm;
+  const double tol = rtol * bnorm;
   GmresState cur = *s->h_state;
   cur.tol = tol;
   cur.restart = R;
@@ -521,15 +644,14 @@ extern "C" adj_status adjoint_solve(adj_scene* s, const double* dL_dq, const dou
   double relres = (bnorm > 0) ? cur.rnorm / bnorm : 0.0;
   bool converged = !(bnorm > tol);
   const int chunk = 8;
-  while (!converged && total < opts->maxit) {
-    // one restart cycle
+  while (!converged && total < maxit) {
     int done_in_cycle = 0;
     while (true) {
       for (int k = 0; k < chunk; ++k) {
-        apply_precond(s, st, s->d_Vt, stride, s->d_scale, s->d_state, s->d_y);
+        apply_precond(s, st, s->d_Vt, stride, s->d_scale, s->d_state, s->d_y, f32);
         {
           ProfScope p(s, 4, st);
-          launch_bsr_spmv(st, s->nv, s->d_rowptr, s->d_col, s->d_val, s->d_y, s->d_Vt, stride, s->d_state);
+          bsr(s, st, s->d_y, s->d_Vt, stride, s->d_state, f32);
         }
         {
           ProfScope p(s, 8, st);
@@ -548,17 +670,15 @@ extern "C" adj_status adjoint_solve(adj_scene* s, const double* dL_dq, const dou
       HIPCHK(hipMemcpyAsync(s->h_state, s->d_state, sizeof(GmresState), hipMemcpyDeviceToHost, st));
       HIPCHK(hipStreamSynchronize(st));
       done_in_cycle = s->h_state->j;
-      if (!s->h_state->active || total + done_in_cycle >= opts->maxit) break;
+      if (!s->h_state->active || total + done_in_cycle >= maxit) break;
     }
     total += done_in_cycle;
-    // z += P (V y)
     launch_gm_finish(st, n3, s->d_state, s->d_H, s->d_g, s->d_scale, s->d_Vt, stride, s->d_coef, s->d_xt);
-    apply_precond(s, st, s->d_xt, 0, nullptr, nullptr, s->d_dz);
-    launch_axpy(st, n3, 1.0, s->d_dz, z);
-    // true residual; restarts the next cycle from it
-    launch_bsr_spmv(st, s->nv, s->d_rowptr, s->d_col, s->d_val, z, s->d_r, 0, nullptr);
-    launch_residual(st, n3, s->d_b, s->d_r, s->d_Vt, s->d_partial, s->d_counter + 3, s->d_state,
-                    s->d_scale, s->d_g);
+    apply_precond(s, st, s->d_xt, 0, nullptr, nullptr, s->d_dz, f32);
+    launch_axpy(st, n3, 1.0, s->d_dz, x);
+    bsr(s, st, x, s->d_r, 0, nullptr, f32);
+    launch_residual(st, n3, s->d_b, s->d_r, s->d_Vt, s->d_partial, s->d_counter + 3, s->d_state, s->d_scale,
+                    s->d_g);
     HIPCHK(hipGetLastError());
     HIPCHK(hipMemcpyAsync(s->h_state, s->d_state, sizeof(GmresState), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
@@ -567,9 +687,71 @@ extern "C" adj_status adjoint_solve(adj_scene* s, const double* dL_dq, const dou
     converged = s->h_state->rnorm <= tol;
     if (done_in_cycle == 0 && !converged) break;  // no progress possible
   }
+  *iters_out = total;
+  *relres_out = relres;
+  *converged_out = converged;
+  return ADJ_OK;
+}
+
+extern "C" adj_status adjoint_solve(adj_scene* s, const double* dL_dq, const double* dL_dv, double* z,
+                                    const adj_solve_opts* opts, adj_solve_info* info, void* stream) {
+  if (!s || !dL_dq || !dL_dv || !z || !opts) return fail(ADJ_E_ARG, "null argument");
+  if (!s->setup_done) return fail(ADJ_E_ARG, "adjoint_setup has not run");
+  if (!(opts->rtol > 0) || opts->maxit <= 0 || opts->restart < 1 || opts->restart > kMaxRestart)
+    return fail(ADJ_E_ARG, "invalid solve options");
+  if (opts->prec != ADJ_FP64 && opts->prec != ADJ_MIXED) return fail(ADJ_E_ARG, "unknown precision");
+  if (opts->prec == ADJ_MIXED && !s->mixed_ready)
+    return fail(ADJ_E_ARG, "adjoint_setup must run with ADJ_MIXED before a mixed solve");
+  hipStream_t st = (hipStream_t)stream;
+  const long long n3 = s->n3;
+  // b = dL_dq + dL_dv / h
+  HIPCHK(hipMemcpyAsync(s->d_rhs, dL_dq, n3 * sizeof(double), hipMemcpyDeviceToDevice, st));
+  launch_axpy(st, n3, 1.0 / s->hs.h, dL_dv, s->d_rhs);
+  int total = 0, refine = 0;
+  double relres = 0.0;
+  bool converged = false;
+  adj_status a;
+  if (opts->prec == ADJ_FP64) {
+    a = gmres_solve(s, st, s->d_rhs, z, opts->rtol, opts->maxit, opts->restart, &total, &relres, &converged);
+    if (a != ADJ_OK) return a;
+  } else {
+    // Iterative refinement: FP64 residual r = b - Acal^T z with the FP64
+    // matrix; inner GMRES with FP32-stored matrices solves Acal^T dz = r.
+    launch_fill_zero(st, (size_t)n3, z);
+    HIPCHK(hipMemcpyAsync(s->d_fu, s->d_rhs, n3 * sizeof(double), hipMemcpyDeviceToDevice, st));
+    launch_norms(st, n3, s->d_rhs, s->d_partial, s->d_counter + 7, s->d_norms);
+    double nb[2];
+    HIPCHK(hipMemcpyAsync(nb, s->d_norms, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    const double bnorm = std::sqrt(nb[0]);
+    double rnorm = bnorm;
+    relres = bnorm > 0 ? 1.0 : 0.0;
+    converged = !(bnorm > 0);
+    for (refine = 0; refine <= std::max(0, opts->max_refine) && !converged && total < opts->maxit; ++refine) {
+      const double inner = std::max(1e-6, 0.5 * opts->rtol * bnorm / rnorm);
+      int it = 0;
+      double rr = 0.0;
+      bool cv = false;
+      if ((a = gmres_solve(s, st, s->d_fu, s->d_du, inner, opts->maxit - total, opts->restart, &it, &rr, &cv,
+                           true)) != ADJ_OK)
+        return a;
+      total += it;
+      launch_axpy(st, n3, 1.0, s->d_du, z);
+      // r = b - Acal^T z in FP64
+      bsr(s, st, z, s->d_fu, 0, nullptr, false);
+      launch_add_vec(st, n3, s->d_rhs, s->d_fu, -1.0, s->d_fu);
+      launch_norms(st, n3, s->d_fu, s->d_partial, s->d_counter + 7, s->d_norms);
+      HIPCHK(hipMemcpyAsync(nb, s->d_norms, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      rnorm = std::sqrt(nb[0]);
+      relres = rnorm / bnorm;
+      if (!std::isfinite(relres)) return fail(ADJ_E_SINGULAR, "non-finite residual in the refinement");
+      converged = relres <= opts->rtol;
+    }
+  }
   if (info) {
     info->iters = total;
-    info->refine_steps = 0;
+    info->refine_steps = refine;
     info->n_contacts = s->nc;
     info->m_rows = s->m;
     info->relres = relres;
@@ -640,10 +822,469 @@ extern "C" adj_status adj_debug_export(const adj_scene* s, int32_t what, void* h
   return ADJ_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Forward step (eq:dynamics).  Damped Newton on the step displacement u = q -
+// qbar, the normal multipliers lambda_n and the friction magnitudes s
+// (lambda_f = -s delta_f/|delta_f|).  The reduced Newton matrix is Acal at
+// the iterate, assembled and solved with the adjoint's kernels (non-
+// transposed).  Contact rows are O(n_c) and evaluated on the host; the
+// per-tet and per-vertex work and the linear solves run on the GPU.
+// ---------------------------------------------------------------------------
+
+namespace {
+
+inline double fb_rm(double x, double y, double e2) {  // r - x
+  const double r = std::sqrt(x * x + y * y + e2);
+  return (x > 0.0) ? (y * y + e2) / (r + x) : r - x;
+}
+inline double fb_phi(double x, double y, double e2) {
+  const double r = std::sqrt(x * x + y * y + e2);
+  const double sxy = x + y;
+  return (sxy > 0.0) ? (2.0 * (x * y) - e2) / (sxy + r) : sxy - r;
+}
+
+struct FwdContacts {
+  int n = 0;
+  std::vector<int> vid, collider, fric;
+  std::vector<double> frame, d_n, d_f, k, g0;
+};
+
+void tangent_frame(const double* n, double* F) {
+  const double an[3] = {std::fabs(n[0]), std::fabs(n[1]), std::fabs(n[2])};
+  int kk = 0;
+  if (an[1] < an[kk]) kk = 1;
+  if (an[2] < an[kk]) kk = 2;
+  double e[3] = {0, 0, 0};
+  e[kk] = 1.0;
+  double c[3] = {n[1] * e[2] - n[2] * e[1], n[2] * e[0] - n[0] * e[2], n[0] * e[1] - n[1] * e[0]};
+  const double nc = std::sqrt(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]);
+  double t1[3] = {c[0] / nc, c[1] / nc, c[2] / nc};
+  double t2[3] = {n[1] * t1[2] - n[2] * t1[1], n[2] * t1[0] - n[0] * t1[2], n[0] * t1[1] - n[1] * t1[0]};
+  for (int i = 0; i < 3; ++i) {
+    F[i] = n[i];
+    F[3 + i] = t1[i];
+    F[6 + i] = t2[i];
+  }
+}
+
+// Contact state at (uc, lam_n, s): delta, |delta_f|, direction, lambda, phi rows.
+struct CState {
+  std::vector<double> delta, x, dhat, lam, phin, phif;
+};
+
+void contact_state(const FwdContacts& C, const std::vector<double>& uc, const std::vector<double>& lam_n,
+                   const std::vector<double>& sf, double mu, const std::vector<double>& eps, CState& out) {
+  const int n = C.n;
+  out.delta.assign(3 * n, 0.0);
+  out.x.assign(n, 0.0);
+  out.dhat.assign(2 * n, 0.0);
+  out.lam.assign(3 * n, 0.0);
+  out.phin.assign(n, 0.0);
+  out.phif.assign(n, 0.0);
+  for (int c = 0; c < n; ++c) {
+    const double* F = &C.frame[9 * c];
+    const double* u = &uc[3 * c];
+    const double dn = C.g0[c] + (F[0] * u[0] + F[1] * u[1] + F[2] * u[2]);
+    const double d1 = (F[3] * u[0] + F[4] * u[1] + F[5] * u[2]) - C.d_f[2 * c];
+    const double d2 = (F[6] * u[0] + F[7] * u[1] + F[8] * u[2]) - C.d_f[2 * c + 1];
+    out.delta[3 * c] = dn;
+    out.delta[3 * c + 1] = d1;
+    out.delta[3 * c + 2] = d2;
+    const double x = std::hypot(d1, d2);
+    out.x[c] = x;
+    double h1 = 1.0, h2 = 0.0;
+    if (x > 0) {
+      h1 = d1 / x;
+      h2 = d2 / x;
+    }
+    out.dhat[2 * c] = h1;
+    out.dhat[2 * c + 1] = h2;
+    out.lam[3 * c] = lam_n[c];
+    if (C.fric[c]) {
+      out.lam[3 * c + 1] = -sf[c] * h1;
+      out.lam[3 * c + 2] = -sf[c] * h2;
+    }
+    const double k = C.k[c];
+    const double e2 = 2.0 * eps[c] * eps[c] * k;
+    out.phin[c] = fb_phi(k * dn, lam_n[c], e2);
+    out.phif[c] = C.fric[c] ? fb_phi(k * x, mu * lam_n[c] - sf[c], e2) : 0.0;
+  }
+}
+
+}  // namespace
+
+// Residual r_q (device, s->d_rq), contact state (host) and merit at (u_dev, lam_n, s).
+static adj_status fwd_eval(adj_scene* s, hipStream_t st, const double* qbar, const double* u_dev,
+                           const FwdContacts& C, const std::vector<double>& lam_n,
+                           const std::vector<double>& sf, double mu, const std::vector<double>& eps,
+                           CState& cs, double* merit, double* fmax, double* pmax, bool* inverted) {
+  const double h = s->hs.h, h2 = h * h;
+  const long long n3 = s->n3;
+  launch_add_vec(st, n3, qbar, u_dev, 1.0, s->d_qcur);
+  HIPCHK(hipMemsetAsync(s->d_err + 1, 0, sizeof(int), st));
+  launch_tet_force(st, s->nt, s->d_tets, s->d_Bt, s->d_vol, s->d_lmu, s->d_llam, h2, s->d_qcur, s->d_force,
+                   s->d_err);
+  launch_gather_force(st, s->nv, s->d_vptr, s->d_vcode, s->d_force, s->d_mass, u_dev, s->d_utilde, s->d_rq);
+  std::vector<double> uc(3 * (size_t)C.n);
+  if (C.n) {
+    launch_gather_contact_rows(st, C.n, s->d_fvid, u_dev, s->d_cu);
+    HIPCHK(hipMemcpyAsync(uc.data(), s->d_cu, 3 * C.n * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+  }
+  contact_state(C, uc, lam_n, sf, mu, eps, cs);
+  if (C.n) {
+    std::vector<double> fw(3 * (size_t)C.n);
+    for (int c = 0; c < C.n; ++c) {
+      const double* F = &C.frame[9 * c];
+      const double* l = &cs.lam[3 * c];
+      for (int j = 0; j < 3; ++j) fw[3 * c + j] = -h2 * (F[j] * l[0] + F[3 + j] * l[1] + F[6 + j] * l[2]);
+    }
+    HIPCHK(hipMemcpyAsync(s->d_cvec, fw.data(), fw.size() * sizeof(double), hipMemcpyHostToDevice, st));
+    launch_add_contact_vec(st, C.n, s->d_fvid, s->d_cvec, s->d_rq);
+  }
+  launch_norms(st, n3, s->d_rq, s->d_partial, s->d_counter + 6, s->d_norms);
+  double nr[2];
+  int errs[2];
+  HIPCHK(hipMemcpyAsync(nr, s->d_norms, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(errs, s->d_err, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  *inverted = errs[1] != 0;
+  double ps = 0.0, pm = 0.0;
+  for (int c = 0; c < C.n; ++c) {
+    ps += cs.phin[c] * cs.phin[c] + cs.phif[c] * cs.phif[c];
+    pm = std::max(pm, std::max(std::fabs(cs.phin[c]), std::fabs(cs.phif[c])));
+  }
+  *merit = 0.5 * (nr[0] / (h2 * h2) + ps);
+  *fmax = nr[1] / h2;
+  *pmax = pm;
+  return ADJ_OK;
+}
+
+// One damped Newton solve with smoothing eps (per contact).  Returns ok.
+static adj_status fwd_newton(adj_scene* s, hipStream_t st, const double* qbar, FwdContacts& C,
+                             std::vector<double>& lam_n, std::vector<double>& sf, double mu,
+                             const std::vector<double>& eps, int maxit, double tol_f, double tol_p,
+                             bool* ok_out, int* iters) {
+  const double h = s->hs.h, h2 = h * h;
+  const long long n3 = s->n3;
+  const int nc = C.n;
+  CState cs;
+  double merit, fmax, pmax;
+  bool inv;
+  adj_status a = fwd_eval(s, st, qbar, s->d_fu, C, lam_n, sf, mu, eps, cs, &merit, &fmax, &pmax, &inv);
+  if (a != ADJ_OK) return a;
+  if (inv) return fail(ADJ_E_INVERTED, "inverted element at the initial guess of the step");
+  bool ok = false;
+  int it = 0;
+  std::vector<double> Wt(9 * (size_t)nc), Q(9 * (size_t)nc), kh(4 * (size_t)nc), rc(3 * (size_t)nc),
+      av(nc), bv(nc), bn(nc), bf(nc);
+  for (it = 1; it <= maxit; ++it) {
+    // Newton matrix: elastic blocks at q = qbar + u, contact blocks at the iterate
+    launch_add_vec(st, n3, qbar, s->d_fu, 1.0, s->d_qcur);
+    launch_tet_blocks(st, s->nt, s->d_tets, s->d_Bt, s->d_vol, s->d_lmu, s->d_llam, h2, s->d_qcur,
+                      s->d_tetblk, s->d_err);
+    launch_assemble(st, s->nnzb, s->d_slot_ptr, s->d_slot_code, s->d_tetblk, s->d_row_of_slot, s->d_col,
+                    s->d_mass, s->d_val);
+    for (int c = 0; c < nc; ++c) {
+      const double k = C.k[c];
+      const double e2 = 2.0 * eps[c] * eps[c] * k;
+      const double dn = cs.delta[3 * c], x = cs.x[c];
+      const double ra = fb_rm(k * dn, lam_n[c], e2), rb = fb_rm(lam_n[c], k * dn, e2);
+      const double rn = std::sqrt((k * dn) * (k * dn) + lam_n[c] * lam_n[c] + e2);
+      av[c] = k * ra / rb;
+      bn[c] = rb / rn;
+      double Rm[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+      double Kh[3][3] = {{av[c], 0, 0}, {0, 0, 0}, {0, 0, 0}};
+      bv[c] = 0.0;
+      bf[c] = 1.0;
+      double cc = 0.0;
+      if (C.fric[c]) {
+        const double yf = mu * lam_n[c] - sf[c];
+        const double rfa = fb_rm(k * x, yf, e2), rfb = fb_rm(yf, k * x, e2);
+        const double rf = std::sqrt((k * x) * (k * x) + yf * yf + e2);
+        bv[c] = k * rfa / rfb;
+        bf[c] = rfb / rf;
+        cc = (x > 0) ? sf[c] / x : 0.0;
+        const double h1 = cs.dhat[2 * c], hh2 = cs.dhat[2 * c + 1];
+        Rm[1][1] = h1; Rm[1][2] = hh2; Rm[2][1] = -hh2; Rm[2][2] = h1;
+        Kh[1][0] = -mu * av[c];
+        Kh[1][1] = bv[c];
+        Kh[2][2] = cc;
+      }
+      // K = R^T Kh R (frame coordinates); world block h^2 F^T K F; Q = R F
+      double T[3][3], K[3][3];
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) T[i][j] = Kh[i][0] * Rm[0][j] + Kh[i][1] * Rm[1][j] + Kh[i][2] * Rm[2][j];
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) K[i][j] = Rm[0][i] * T[0][j] + Rm[1][i] * T[1][j] + Rm[2][i] * T[2][j];
+      const double* F = &C.frame[9 * c];
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+          double acc = 0.0;
+          for (int p = 0; p < 3; ++p)
+            for (int q = 0; q < 3; ++q) acc += F[3 * p + i] * K[p][q] * F[3 * q + j];
+          Wt[9 * c + 3 * i + j] = h2 * acc;
+          Q[9 * c + 3 * i + j] = Rm[i][0] * F[j] + Rm[i][1] * F[3 + j] + Rm[i][2] * F[6 + j];
+        }
+      kh[4 * c] = av[c];
+      kh[4 * c + 1] = bv[c];
+      kh[4 * c + 2] = cc;
+      kh[4 * c + 3] = C.fric[c] ? 1.0 : 0.0;
+      // rhs contribution h^2 F^T R^T e
+      double e[3] = {-cs.phin[c] / bn[c], 0.0, 0.0};
+      if (C.fric[c]) e[1] = mu * cs.phin[c] / bn[c] - cs.phif[c] / bf[c];
+      double re[3];
+      for (int i = 0; i < 3; ++i) re[i] = Rm[0][i] * e[0] + Rm[1][i] * e[1] + Rm[2][i] * e[2];
+      for (int j = 0; j < 3; ++j) rc[3 * c + j] = h2 * (F[j] * re[0] + F[3 + j] * re[1] + F[6 + j] * re[2]);
+    }
+    if (nc) {
+      HIPCHK(hipMemcpyAsync(s->d_Wt, Wt.data(), Wt.size() * sizeof(double), hipMemcpyHostToDevice, st));
+      HIPCHK(hipMemcpyAsync(s->d_Q, Q.data(), Q.size() * sizeof(double), hipMemcpyHostToDevice, st));
+      HIPCHK(hipMemcpyAsync(s->d_kh, kh.data(), kh.size() * sizeof(double), hipMemcpyHostToDevice, st));
+      HIPCHK(hipMemcpyAsync(s->d_cvec, rc.data(), rc.size() * sizeof(double), hipMemcpyHostToDevice, st));
+      launch_contact_fold(st, nc, s->d_fvid, s->d_diag_slot, s->d_Wt, s->d_val);
+      if ((a = build_capacitance(s, st, mu, 0)) != ADJ_OK) return a;
+    }
+    // rhs = -r_q + h^2 sum F^T R^T e
+    launch_scale_vec(st, n3, s->d_rq, -1.0, s->d_rhs);
+    launch_add_contact_vec(st, nc, s->d_fvid, s->d_cvec, s->d_rhs);
+    int git = 0;
+    double grel = 0.0;
+    bool gconv = false;
+    if ((a = gmres_solve(s, st, s->d_rhs, s->d_du, 1e-11, 600, 64, &git, &grel, &gconv)) != ADJ_OK) return a;
+    // multiplier updates
+    std::vector<double> duc(3 * (size_t)nc), dlam(nc), ds(nc), ddf(2 * (size_t)nc);
+    if (nc) {
+      launch_gather_contact_rows(st, nc, s->d_fvid, s->d_du, s->d_cu);
+      HIPCHK(hipMemcpyAsync(duc.data(), s->d_cu, duc.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+    }
+    for (int c = 0; c < nc; ++c) {
+      const double* F = &C.frame[9 * c];
+      const double* d = &duc[3 * c];
+      const double ddn = F[0] * d[0] + F[1] * d[1] + F[2] * d[2];
+      ddf[2 * c] = F[3] * d[0] + F[4] * d[1] + F[5] * d[2];
+      ddf[2 * c + 1] = F[6] * d[0] + F[7] * d[1] + F[8] * d[2];
+      dlam[c] = -av[c] * ddn - cs.phin[c] / bn[c];
+      if (C.fric[c]) {
+        const double dx = cs.dhat[2 * c] * ddf[2 * c] + cs.dhat[2 * c + 1] * ddf[2 * c + 1];
+        ds[c] = mu * dlam[c] + bv[c] * dx + cs.phif[c] / bf[c];
+      } else {
+        ds[c] = 0.0;
+      }
+    }
+    // no step may shrink |delta_f| of a frictional contact below 1% of its value
+    double alpha = 1.0;
+    for (int k = 0; k < 60; ++k) {
+      bool viol = false;
+      for (int c = 0; c < nc && !viol; ++c) {
+        if (!C.fric[c] || !(cs.x[c] > 0)) continue;
+        const double x1 = cs.delta[3 * c + 1] + alpha * ddf[2 * c];
+        const double x2 = cs.delta[3 * c + 2] + alpha * ddf[2 * c + 1];
+        if (std::hypot(x1, x2) < 0.01 * cs.x[c]) viol = true;
+      }
+      if (!viol) break;
+      alpha *= 0.5;
+    }
+    bool accepted = false;
+    CState ct;
+    double mt = 0, ft = 0, pt = 0;
+    std::vector<double> lt(nc), stt(nc);
+    for (int k = 0; k < 40; ++k) {
+      launch_add_vec(st, n3, s->d_fu, s->d_du, alpha, s->d_ut);
+      for (int c = 0; c < nc; ++c) {
+        lt[c] = lam_n[c] + alpha * dlam[c];
+        stt[c] = sf[c] + alpha * ds[c];
+      }
+      if ((a = fwd_eval(s, st, qbar, s->d_ut, C, lt, stt, mu, eps, ct, &mt, &ft, &pt, &inv)) != ADJ_OK) return a;
+      if (inv) {
+        alpha *= 0.5;
+        continue;
+      }
+      if (mt <= (1.0 - 1e-4 * alpha) * merit || mt == 0.0) {
+        accepted = true;
+        break;
+      }
+      alpha *= 0.5;
+    }
+    if (!accepted) break;
+    // accept: u <- u_trial
+    HIPCHK(hipMemcpyAsync(s->d_fu, s->d_ut, n3 * sizeof(double), hipMemcpyDeviceToDevice, st));
+    lam_n = lt;
+    sf = stt;
+    cs = ct;
+    merit = mt;
+    fmax = ft;
+    pmax = pt;
+    // |alpha du|_max and |u|_max for the small-step test
+    launch_scale_vec(st, n3, s->d_du, alpha, s->d_ut);
+    launch_norms(st, n3, s->d_ut, s->d_partial, s->d_counter + 6, s->d_norms);
+    double nd[2], nu[2];
+    HIPCHK(hipMemcpyAsync(nd, s->d_norms, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    launch_norms(st, n3, s->d_fu, s->d_partial, s->d_counter + 6, s->d_norms);
+    HIPCHK(hipMemcpyAsync(nu, s->d_norms, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    const bool small = nd[1] <= 4e-16 * std::max(1.0, nu[1]);
+    if (alpha == 1.0 && ((fmax <= tol_f && pmax <= tol_p) || small)) {
+      ok = fmax <= 1e3 * tol_f && pmax <= 1e3 * tol_p;
+      break;
+    }
+  }
+  if (!ok) ok = fmax <= 1e3 * tol_f && pmax <= 1e3 * tol_p;
+  *ok_out = ok;
+  *iters = it;
+  return ADJ_OK;
+}
+
 extern "C" adj_status sim_forward_step(adj_scene* s, const double* qbar, const double* vbar,
                                        const double* f_ext, double mu, double* q, double* v,
-                                       adj_contact_state* contacts, void* stream) {
-  (void)s; (void)qbar; (void)vbar; (void)f_ext; (void)mu; (void)q; (void)v; (void)contacts;
-  (void)stream;
-  return fail(ADJ_E_NOTIMPL, "sim_forward_step is not implemented in this build");
+                                       adj_contact_state* out, void* stream) {
+  if (!s || !qbar || !vbar || !f_ext || !q || !v || !out) return fail(ADJ_E_ARG, "null argument");
+  if (!std::isfinite(mu) || mu < 0) return fail(ADJ_E_ARG, "mu must be finite and >= 0");
+  hipStream_t st = (hipStream_t)stream;
+  const double h = s->hs.h;
+  const long long n3 = s->n3;
+  const int np = (int)(s->hs.planes.size() / 4);
+  if (np > 15) return fail(ADJ_E_ARG, "at most 15 planes");
+  // prediction and candidates
+  launch_fwd_predict(st, s->nv, qbar, vbar, f_ext, s->d_mass, h, s->hs.gravity, s->d_utilde, s->d_qtilde);
+  launch_fwd_detect(st, s->nv, s->d_qtilde, np, s->d_planes, s->hs.margin, s->d_mask);
+  std::vector<int> mask(s->nv);
+  HIPCHK(hipMemcpyAsync(mask.data(), s->d_mask, s->nv * sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  FwdContacts C;
+  for (int vv = 0; vv < s->nv; ++vv)
+    for (int p = 0; p < np; ++p)
+      if (mask[vv] & (1 << (2 * p))) {
+        C.vid.push_back(vv);
+        C.collider.push_back(p);
+        C.fric.push_back((mask[vv] >> (2 * p + 1)) & 1);
+        double F[9];
+        tangent_frame(&s->hs.planes[4 * p], F);
+        C.frame.insert(C.frame.end(), F, F + 9);
+        C.d_n.push_back(s->hs.planes[4 * p + 3]);
+        C.d_f.push_back(0.0);
+        C.d_f.push_back(0.0);
+        C.k.push_back(s->hs.As[s->hs.diag_slot[vv]] / (h * h));
+      }
+  C.n = (int)C.vid.size();
+  const int nc = C.n;
+  if (nc > s->max_contacts || nc > out->capacity)
+    return fail(ADJ_E_SHAPE, "more contacts than max_contacts / the output capacity");
+  if (nc && (!out->vid || !out->fric || !out->frame || !out->delta || !out->lambda))
+    return fail(ADJ_E_ARG, "contact output arrays missing");
+  // gap at the start of the step, n . xbar - d_n
+  C.g0.assign(nc, 0.0);
+  if (nc) {
+    HIPCHK(hipMemcpyAsync(s->d_fvid, C.vid.data(), nc * sizeof(int), hipMemcpyHostToDevice, st));
+    launch_gather_contact_rows(st, nc, s->d_fvid, qbar, s->d_cu);
+    std::vector<double> xb(3 * (size_t)nc);
+    HIPCHK(hipMemcpyAsync(xb.data(), s->d_cu, xb.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    for (int c = 0; c < nc; ++c)
+      C.g0[c] = (C.frame[9 * c] * xb[3 * c] + C.frame[9 * c + 1] * xb[3 * c + 1] +
+                 C.frame[9 * c + 2] * xb[3 * c + 2]) - C.d_n[c];
+  }
+  // warm start from the previous step (by vertex and collider)
+  std::vector<double> lam0(nc, 0.0), s0(nc, 0.0);
+  for (int c = 0; c < nc; ++c) {
+    auto it = s->warm.find((long long)C.vid[c] * 64 + C.collider[c]);
+    if (it != s->warm.end()) {
+      lam0[c] = it->second.first;
+      s0[c] = C.fric[c] ? it->second.second : 0.0;
+    }
+  }
+  adj_status a = contact_layout(s, st, nc, C.vid, C.fric, true);
+  if (a != ADJ_OK) return a;
+  s->cur_vid = s->d_fvid;
+  const double tol_f = 1e-11, tol_p = 1e-13;
+  std::vector<double> lam_n = lam0, sf = s0;
+  HIPCHK(hipMemcpyAsync(s->d_fu, s->d_utilde, n3 * sizeof(double), hipMemcpyDeviceToDevice, st));
+  int total = 0;
+  while (true) {
+    std::vector<double> l_start = lam_n, s_start = sf;
+    // qtilde is free after detection: it keeps the starting displacement
+    HIPCHK(hipMemcpyAsync(s->d_qtilde, s->d_fu, n3 * sizeof(double), hipMemcpyDeviceToDevice, st));
+    std::vector<double> eps(nc, s->hs.eps);
+    bool ok = false;
+    int its = 0;
+    if ((a = fwd_newton(s, st, qbar, C, lam_n, sf, mu, eps, 60, tol_f, tol_p, &ok, &its)) != ADJ_OK) return a;
+    total += its;
+    if (!ok) {
+      // continuation in the smoothing: eps_j^2 = eps^2 gamma_j, gamma_j -> 1
+      lam_n = l_start;
+      sf = s_start;
+      HIPCHK(hipMemcpyAsync(s->d_fu, s->d_qtilde, n3 * sizeof(double), hipMemcpyDeviceToDevice, st));
+      for (double gamma = 1e6;; gamma /= 30.0) {
+        const bool last = gamma <= 1.0;
+        std::vector<double> ej(nc, s->hs.eps * std::sqrt(std::max(gamma, 1.0)));
+        if ((a = fwd_newton(s, st, qbar, C, lam_n, sf, mu, ej, 60, last ? tol_f : 1e-7, last ? tol_p : 1e-7,
+                            &ok, &its)) != ADJ_OK)
+          return a;
+        total += its;
+        if (last) break;
+      }
+    }
+    bool bad = false;
+    for (int c = 0; c < nc; ++c)
+      if (C.fric[c] && sf[c] < 0.0) {
+        C.fric[c] = 0;
+        sf[c] = 0.0;
+        bad = true;
+      }
+    if (!bad) break;
+    // a contact that separated inside the step has no solution of the
+    // friction rows: demote it to normal-only and solve again
+    if ((a = contact_layout(s, st, nc, C.vid, C.fric, true)) != ADJ_OK) return a;
+  }
+  // final state, record, outputs
+  CState cs;
+  double merit, fmax, pmax;
+  bool inv;
+  std::vector<double> eps(nc, s->hs.eps);
+  if ((a = fwd_eval(s, st, qbar, s->d_fu, C, lam_n, sf, mu, eps, cs, &merit, &fmax, &pmax, &inv)) != ADJ_OK)
+    return a;
+  launch_add_vec(st, n3, qbar, s->d_fu, 1.0, q);
+  launch_scale_vec(st, n3, s->d_fu, 1.0 / h, v);
+  out->n_contacts = nc;
+  out->mu = mu;
+  if (nc) {
+    HIPCHK(hipMemcpyAsync(out->vid, C.vid.data(), nc * sizeof(int), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(out->fric, C.fric.data(), nc * sizeof(int), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(out->frame, C.frame.data(), 9 * nc * sizeof(double), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(out->delta, cs.delta.data(), 3 * nc * sizeof(double), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(out->lambda, cs.lam.data(), 3 * nc * sizeof(double), hipMemcpyHostToDevice, st));
+    if (out->d_n) HIPCHK(hipMemcpyAsync(out->d_n, C.d_n.data(), nc * sizeof(double), hipMemcpyHostToDevice, st));
+    if (out->d_f) HIPCHK(hipMemcpyAsync(out->d_f, C.d_f.data(), 2 * nc * sizeof(double), hipMemcpyHostToDevice, st));
+  }
+  s->warm.clear();
+  for (int c = 0; c < nc; ++c) s->warm[(long long)C.vid[c] * 64 + C.collider[c]] = {lam_n[c], sf[c]};
+  HIPCHK(hipStreamSynchronize(st));
+  s->fwd_newton_iters = total;
+  s->fwd_residual = std::max(fmax, pmax);
+  s->setup_done = false;  // the adjoint workspaces now hold the Newton matrix
+  // the paper's (unscaled) rows at the returned state
+  double worst = fmax;
+  for (int c = 0; c < nc; ++c) {
+    const double e2 = 2.0 * s->hs.eps * s->hs.eps;
+    worst = std::max(worst, std::fabs(fb_phi(cs.delta[3 * c], cs.lam[3 * c], e2)));
+    if (C.fric[c]) worst = std::max(worst, std::fabs(fb_phi(cs.x[c], mu * lam_n[c] - sf[c], e2)));
+  }
+  s->fwd_residual = worst;
+  if (!(worst <= 1e-8)) return fail(ADJ_E_NOCONV, "forward Newton residual " + std::to_string(worst));
+  return ADJ_OK;
+}
+
+extern "C" adj_status adj_forward_stats(const adj_scene* s, double* out) {
+  if (!s || !out) return fail(ADJ_E_ARG, "null argument");
+  out[0] = s->fwd_newton_iters;
+  out[1] = s->fwd_residual;
+  return ADJ_OK;
+}
+
+extern "C" adj_status adj_forward_reset(adj_scene* s) {
+  if (!s) return fail(ADJ_E_ARG, "scene is null");
+  s->warm.clear();
+  return ADJ_OK;
 }

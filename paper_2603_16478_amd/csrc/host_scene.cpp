@@ -247,6 +247,17 @@ adj_status build_host_scene(const adj_scene_desc* d, HostScene& s, std::string& 
       }
   }
   for (int v = 0; v < nv; ++v) s.As[s.diag_slot[v]] += s.mass[v];
+  // vertex incidence (for gathering element forces)
+  s.vptr.assign(nv + 1, 0);
+  for (int t = 0; t < nt; ++t)
+    for (int k = 0; k < 4; ++k) s.vptr[s.tets[4 * t + k] + 1]++;
+  for (int v = 0; v < nv; ++v) s.vptr[v + 1] += s.vptr[v];
+  s.vcode.resize(4 * (size_t)nt);
+  {
+    std::vector<int32_t> pos(s.vptr.begin(), s.vptr.end() - 1);
+    for (int t = 0; t < nt; ++t)
+      for (int k = 0; k < 4; ++k) s.vcode[pos[s.tets[4 * t + k]]++] = t * 4 + k;
+  }
 
   // ordering
   {

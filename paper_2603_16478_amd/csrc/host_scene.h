@@ -35,6 +35,8 @@ struct HostScene {
   // (tet, local pair); code = tet*32 + pair*2 + transpose.
   std::vector<int32_t> slot_ptr, slot_code;
   std::vector<double> As;      // scalar A_s per slot (A = A_s (x) I_3)
+  // vertex -> incident (tet, corner) list, code = tet*4 + corner, tet order
+  std::vector<int32_t> vptr, vcode;
   // Fill-reducing ordering (internal index -> vertex) and its inverse.
   std::vector<int32_t> perm, iperm;
   // Cholesky factor of P A_s P^T, CSC, diagonal first in every column.

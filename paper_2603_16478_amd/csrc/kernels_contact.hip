@@ -124,7 +124,7 @@ __global__ void k_contact_fold(int nc, const int* __restrict__ vid, const int* _
 __global__ void k_capacitance(int m, int mp, const int* __restrict__ row_c, const int* __restrict__ row_i,
                               const int* __restrict__ cmap, int ncv, const double* __restrict__ D,
                               const double* __restrict__ Q, const double* __restrict__ kh, double mu,
-                              double h2, double* __restrict__ C) {
+                              double h2, int transpose, double* __restrict__ C) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   const int i = blockIdx.y;
   if (j >= m || i >= m) return;
@@ -137,8 +137,9 @@ __global__ void k_capacitance(int m, int mp, const int* __restrict__ row_c, cons
     // Khat^{-T} = [[1/a, mu/b, 0], [0, 1/b, 0], [0, 0, 1/c]]; a zero c
     // (no friction magnitude) drops the row from the low-rank term.
     const double ka = kh[4 * c], kb = kh[4 * c + 1], kc = kh[4 * c + 2];
+    // Khat^{-1} (forward Newton, transpose = 0) has mu/b at (1, 0) instead
     if (a == 0 && b == 0) v += 1.0 / ka;
-    else if (a == 0 && b == 1) v += mu / kb;
+    else if (transpose ? (a == 0 && b == 1) : (a == 1 && b == 0)) v += mu / kb;
     else if (a == 1 && b == 1) v += 1.0 / kb;
     else if (a == 2 && b == 2) v += (kc > 1e-200) ? 1.0 / kc : 1e200;
   }
@@ -220,10 +221,10 @@ void launch_contact_fold(hipStream_t st, int nc, const int* vid, const int* diag
 
 void launch_capacitance(hipStream_t st, int m, int mp, const int* row_c, const int* row_i,
                         const int* cmap, int ncv, const double* D, const double* Q, const double* kh,
-                        double mu, double h2, double* C) {
+                        double mu, double h2, int transpose, double* C) {
   if (m == 0) return;
   dim3 grid((m + 255) / 256, m);
-  k_capacitance<<<grid, 256, 0, st>>>(m, mp, row_c, row_i, cmap, ncv, D, Q, kh, mu, h2, C);
+  k_capacitance<<<grid, 256, 0, st>>>(m, mp, row_c, row_i, cmap, ncv, D, Q, kh, mu, h2, transpose, C);
 }
 
 void launch_vjp_contacts(hipStream_t st, int nc, const int* vid, const double* frame, const double* Kc,

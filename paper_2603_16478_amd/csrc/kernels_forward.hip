@@ -1,0 +1,236 @@
+// Kernels of the forward step (eq:dynamics): inertial prediction, contact
+// candidates, elastic forces of the local projections, per-vertex residual
+// gather and small reductions.  The Newton matrix reuses the adjoint's
+// per-tet Jacobian and assembly kernels (the reduced Newton matrix is Acal).
+#include "device_common.h"
+#include "nh_local.h"
+
+namespace adj {
+
+// Prediction and detection are evaluated left to right without contraction
+// so that the candidate decisions are reproducible bit for bit.
+#pragma clang fp contract(off)
+
+// qtilde = (qbar + h vbar) + (h*h) (g + f/m);  utilde = h vbar + (h*h) (g + f/m)
+__global__ void k_fwd_predict(int nv, const double* __restrict__ qbar, const double* __restrict__ vbar,
+                              const double* __restrict__ fext, const double* __restrict__ mass, double h,
+                              double gx, double gy, double gz, double* __restrict__ utilde,
+                              double* __restrict__ qtilde) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 3 * nv) return;
+  const int c = i % 3;
+  const double g = (c == 0) ? gx : (c == 1) ? gy : gz;
+  const double acc = g + fext[i] / mass[i / 3];
+  const double hh = h * h;
+  qtilde[i] = (qbar[i] + h * vbar[i]) + hh * acc;
+  utilde[i] = h * vbar[i] + hh * acc;
+}
+
+// mask bit 2p: gap to plane p at qtilde <= margin; bit 2p+1: gap <= 0
+__global__ void k_fwd_detect(int nv, const double* __restrict__ qtilde, int nplanes,
+                             const double* __restrict__ planes, double margin, int* __restrict__ mask) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= nv) return;
+  int mk = 0;
+  const double x0 = qtilde[3 * v], x1 = qtilde[3 * v + 1], x2 = qtilde[3 * v + 2];
+  for (int p = 0; p < nplanes && p < 15; ++p) {
+    const double* pl = planes + 4 * p;
+    const double gap = ((pl[0] * x0 + pl[1] * x1) + pl[2] * x2) - pl[3];
+    if (gap <= margin) mk |= 1 << (2 * p);
+    if (gap <= 0.0) mk |= 1 << (2 * p + 1);
+  }
+  mask[v] = mk;
+}
+
+#pragma clang fp contract(on)
+
+__global__ void k_add_vec(long long n, const double* __restrict__ a, const double* __restrict__ b, double alpha,
+                          double* __restrict__ out) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = a[i] + alpha * b[i];
+}
+
+__global__ void k_scale_vec(long long n, const double* __restrict__ a, double alpha, double* __restrict__ out) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = alpha * a[i];
+}
+
+// Elastic force of the local projections (eq:internal, eq:dynamics):
+// h^2 w_i G_i^T (G_i q - p_i), w_i = 2 mu_i V_i, p_i = vec(U Theta V^T).
+// out[t*12 + 3k + r] = h^2 w_i sum_c Bt[k][c] (F - P)[r][c].
+__global__ void __launch_bounds__(128) k_tet_force(int nt, const int* __restrict__ tets,
+                                                   const double* __restrict__ Bt,
+                                                   const double* __restrict__ vol,
+                                                   const double* __restrict__ lmu,
+                                                   const double* __restrict__ llam, double h2,
+                                                   const double* __restrict__ q, double* __restrict__ out,
+                                                   int* __restrict__ err) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nt) return;
+  double x[4][3], B[4][3];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int v = tets[4 * t + k];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      x[k][c] = q[3 * v + c];
+      B[k][c] = Bt[12 * t + 3 * k + c];
+    }
+  }
+  double F[3][3];
+  deformation_gradient(x, B, F);
+  if (!(det3(F) > 0.0)) {
+    err[1] = 1;
+    for (int e = 0; e < 12; ++e) out[12 * (size_t)t + e] = 0.0;
+    return;
+  }
+  const double mu = lmu[t], lam = llam[t];
+  double U[3][3], s[3], V[3][3];
+  svd3(F, U, s, V);
+  NHLocal L;
+  nh_theta(s, mu, lam, L);
+  double Dm[3][3];
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      Dm[r][c] = F[r][c] - (U[r][0] * L.th[0] * V[c][0] + U[r][1] * L.th[1] * V[c][1] + U[r][2] * L.th[2] * V[c][2]);
+  const double sc = h2 * 2.0 * mu * vol[t];
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+      out[12 * (size_t)t + 3 * k + r] = sc * (B[k][0] * Dm[r][0] + B[k][1] * Dm[r][1] + B[k][2] * Dm[r][2]);
+}
+
+// r_v = m_v (u_v - utilde_v) + sum over incident (tet, corner) of the element force
+__global__ void k_gather_force(int nv, const int* __restrict__ vptr, const int* __restrict__ vcode,
+                               const double* __restrict__ force, const double* __restrict__ mass,
+                               const double* __restrict__ u, const double* __restrict__ utilde,
+                               double* __restrict__ r) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= nv) return;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+  for (int p = vptr[v]; p < vptr[v + 1]; ++p) {
+    const int code = vcode[p];
+    const double* f = force + 12 * (size_t)(code >> 2) + 3 * (code & 3);
+    a0 += f[0];
+    a1 += f[1];
+    a2 += f[2];
+  }
+  const double m = mass[v];
+  r[3 * v] = m * (u[3 * v] - utilde[3 * v]) + a0;
+  r[3 * v + 1] = m * (u[3 * v + 1] - utilde[3 * v + 1]) + a1;
+  r[3 * v + 2] = m * (u[3 * v + 2] - utilde[3 * v + 2]) + a2;
+}
+
+// out[v] += sum of vec over the contacts at v (contacts sorted by vertex)
+__global__ void k_add_contact_vec(int nc, const int* __restrict__ vid, const double* __restrict__ vec,
+                                  double* __restrict__ out) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nc) return;
+  const int v = vid[c];
+  if (c > 0 && vid[c - 1] == v) return;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+  for (int k = c; k < nc && vid[k] == v; ++k) {
+    a0 += vec[3 * k];
+    a1 += vec[3 * k + 1];
+    a2 += vec[3 * k + 2];
+  }
+  out[3 * v] += a0;
+  out[3 * v + 1] += a1;
+  out[3 * v + 2] += a2;
+}
+
+__global__ void k_gather_contact_rows(int nc, const int* __restrict__ vid, const double* __restrict__ x,
+                                      double* __restrict__ out) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nc) return;
+  const int v = vid[c];
+  out[3 * c] = x[3 * v];
+  out[3 * c + 1] = x[3 * v + 1];
+  out[3 * c + 2] = x[3 * v + 2];
+}
+
+// out[0] = sum x_i^2 * w, out[1] = max |x_i| (deterministic, last block)
+__global__ void __launch_bounds__(256) k_norms(long long n, const double* __restrict__ x, double* __restrict__ partial,
+                                               unsigned* counter, double* __restrict__ out) {
+  __shared__ double lds[32];
+  __shared__ double mx[8];
+  __shared__ bool is_last;
+  double s = 0.0, m = 0.0;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    const double v = x[i];
+    s += v * v;
+    m = fmax(m, fabs(v));
+  }
+  s = block_sum(s, lds);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+  if ((threadIdx.x & 63) == 0) mx[threadIdx.x / 64] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double mm = 0.0;
+    for (int i = 0; i < (int)blockDim.x / 64; ++i) mm = fmax(mm, mx[i]);
+    partial[2 * blockIdx.x] = s;
+    partial[2 * blockIdx.x + 1] = mm;
+  }
+  if (!last_block(counter, &is_last)) return;
+  if (threadIdx.x != 0) return;
+  double a = 0.0, b = 0.0;
+  for (int i = 0; i < (int)gridDim.x; ++i) {
+    a += partial[2 * i];
+    b = fmax(b, partial[2 * i + 1]);
+  }
+  out[0] = a;
+  out[1] = b;
+}
+
+void launch_fwd_predict(hipStream_t st, int nv, const double* qbar, const double* vbar, const double* fext,
+                        const double* mass, double h, const double* g, double* utilde, double* qtilde) {
+  k_fwd_predict<<<(3 * nv + 255) / 256, 256, 0, st>>>(nv, qbar, vbar, fext, mass, h, g[0], g[1], g[2], utilde,
+                                                      qtilde);
+}
+
+void launch_fwd_detect(hipStream_t st, int nv, const double* qtilde, int nplanes, const double* planes,
+                       double margin, int* mask) {
+  k_fwd_detect<<<(nv + 255) / 256, 256, 0, st>>>(nv, qtilde, nplanes, planes, margin, mask);
+}
+
+void launch_add_vec(hipStream_t st, long long n, const double* a, const double* b, double alpha, double* out) {
+  k_add_vec<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(n, a, b, alpha, out);
+}
+
+void launch_scale_vec(hipStream_t st, long long n, const double* a, double alpha, double* out) {
+  k_scale_vec<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(n, a, alpha, out);
+}
+
+void launch_tet_force(hipStream_t st, int nt, const int* tets, const double* Bt, const double* vol,
+                      const double* lmu, const double* llam, double h2, const double* q, double* out, int* err) {
+  k_tet_force<<<(nt + 127) / 128, 128, 0, st>>>(nt, tets, Bt, vol, lmu, llam, h2, q, out, err);
+}
+
+void launch_gather_force(hipStream_t st, int nv, const int* vptr, const int* vcode, const double* force,
+                         const double* mass, const double* u, const double* utilde, double* r) {
+  k_gather_force<<<(nv + 255) / 256, 256, 0, st>>>(nv, vptr, vcode, force, mass, u, utilde, r);
+}
+
+void launch_add_contact_vec(hipStream_t st, int nc, const int* vid, const double* vec, double* out) {
+  if (nc == 0) return;
+  k_add_contact_vec<<<(nc + 255) / 256, 256, 0, st>>>(nc, vid, vec, out);
+}
+
+void launch_gather_contact_rows(hipStream_t st, int nc, const int* vid, const double* x, double* out) {
+  if (nc == 0) return;
+  k_gather_contact_rows<<<(nc + 255) / 256, 256, 0, st>>>(nc, vid, x, out);
+}
+
+void launch_norms(hipStream_t st, long long n, const double* x, double* partial, unsigned* counter,
+                  double* out) {
+  int blocks = (int)((n + 255) / 256);
+  if (blocks > 256) blocks = 256;
+  k_norms<<<blocks, 256, 0, st>>>(n, x, partial, counter, out);
+}
+
+}  // namespace adj

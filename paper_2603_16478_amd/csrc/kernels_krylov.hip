@@ -72,10 +72,11 @@ __global__ void __launch_bounds__(256) k_spmv_csr3(int nrows, const long long* _
 // four short rows are handled by one wavefront each (-1 = empty slot).
 constexpr int kBigRow = 0x40000000;
 
+template <class MT>
 __global__ void __launch_bounds__(256) k_spmv_tasks(const int4* __restrict__ tasks,
                                                     const long long* __restrict__ rp,
                                                     const int* __restrict__ cj,
-                                                    const double* __restrict__ cx,
+                                                    const MT* __restrict__ cx,
                                                     const double* __restrict__ xbase, long long stride,
                                                     const double* __restrict__ scale,
                                                     const GmresState* __restrict__ st, int use_j,
@@ -93,7 +94,7 @@ __global__ void __launch_bounds__(256) k_spmv_tasks(const int4* __restrict__ tas
   if (t.x >= 0 && (t.x & kBigRow)) {
     const int row = t.x & ~kBigRow;
     for (long long p = rp[row] + threadIdx.x; p < rp[row + 1]; p += blockDim.x) {
-      const double v = cx[p];
+      const double v = (double)cx[p];
       const int c = cj[p];
       a0 += v * x[3 * c];
       a1 += v * x[3 * c + 1];
@@ -113,7 +114,7 @@ __global__ void __launch_bounds__(256) k_spmv_tasks(const int4* __restrict__ tas
   const int row = (w == 0) ? t.x : (w == 1) ? t.y : (w == 2) ? t.z : t.w;
   if (row < 0) return;
   for (long long p = rp[row] + lane; p < rp[row + 1]; p += 64) {
-    const double v = cx[p];
+    const double v = (double)cx[p];
     const int c = cj[p];
     a0 += v * x[3 * c];
     a1 += v * x[3 * c + 1];
@@ -131,11 +132,12 @@ __global__ void __launch_bounds__(256) k_spmv_tasks(const int4* __restrict__ tas
 
 // t = X (Hq u): each block first forms g = Hq u (m entries) in LDS, then one
 // wavefront per row of X.
+template <class MT>
 __global__ void __launch_bounds__(256) k_wb_gather(int m, int mp, const int* __restrict__ row_c,
                                                    const int* __restrict__ row_i,
                                                    const int* __restrict__ vid,
                                                    const double* __restrict__ Q,
-                                                   const double* __restrict__ X,
+                                                   const MT* __restrict__ X,
                                                    const double* __restrict__ u,
                                                    const GmresState* __restrict__ st,
                                                    double* __restrict__ t) {
@@ -151,21 +153,22 @@ __global__ void __launch_bounds__(256) k_wb_gather(int m, int mp, const int* __r
   const int lane = threadIdx.x & 63;
   const int row = blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
   if (row >= m) return;
-  const double* xr = X + (size_t)row * mp;
+  const MT* xr = X + (size_t)row * mp;
   double acc = 0.0;
-  for (int k = lane; k < m; k += 64) acc += xr[k] * g[k];
+  for (int k = lane; k < m; k += 64) acc += (double)xr[k] * g[k];
   acc = wave_sum(acc);
   if (lane == 0) t[row] = acc;
 }
 
 // y = u - h^2 Z t' with t'_cv = sum over the contacts at vertex cv of Q_c^T t_c
 // (computed per block in LDS); one wavefront per vertex row.
+template <class MT>
 __global__ void __launch_bounds__(256) k_wb_correct(int nv, int ncv, const int* __restrict__ cv_ptr,
                                                     const int* __restrict__ c_row0,
                                                     const int* __restrict__ c_nrow,
                                                     const double* __restrict__ Q,
                                                     const double* __restrict__ t,
-                                                    const double* __restrict__ Z, double h2,
+                                                    const MT* __restrict__ Z, double h2,
                                                     const double* __restrict__ u,
                                                     const GmresState* __restrict__ st,
                                                     double* __restrict__ y) {
@@ -189,10 +192,10 @@ __global__ void __launch_bounds__(256) k_wb_correct(int nv, int ncv, const int* 
   const int lane = threadIdx.x & 63;
   const int row = blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
   if (row >= nv) return;
-  const double* zr = Z + (size_t)row * ncv;
+  const MT* zr = Z + (size_t)row * ncv;
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
   for (int k = lane; k < ncv; k += 64) {
-    const double zz = zr[k];
+    const double zz = (double)zr[k];
     a0 += zz * tp[3 * k];
     a1 += zz * tp[3 * k + 1];
     a2 += zz * tp[3 * k + 2];
@@ -209,9 +212,10 @@ __global__ void __launch_bounds__(256) k_wb_correct(int nv, int ncv, const int* 
 
 // w = Acal^T x, block-sparse 3x3; 16 lanes per block row.  Output to
 // outbase + (j+1)*stride when state is given.
+template <class MT>
 __global__ void __launch_bounds__(256) k_bsr_spmv(int nv, const int* __restrict__ rowptr,
                                                   const int* __restrict__ col,
-                                                  const double* __restrict__ val,
+                                                  const MT* __restrict__ val,
                                                   const double* __restrict__ x,
                                                   double* __restrict__ outbase, long long stride,
                                                   const GmresState* __restrict__ st) {
@@ -221,12 +225,12 @@ __global__ void __launch_bounds__(256) k_bsr_spmv(int nv, const int* __restrict_
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
   if (row < nv) {
     for (int p = rowptr[row] + sub; p < rowptr[row + 1]; p += 16) {
-      const double* b = val + 9 * (size_t)p;
+      const MT* b = val + 9 * (size_t)p;
       const int c = col[p];
       const double x0 = x[3 * c], x1 = x[3 * c + 1], x2 = x[3 * c + 2];
-      a0 += b[0] * x0 + b[1] * x1 + b[2] * x2;
-      a1 += b[3] * x0 + b[4] * x1 + b[5] * x2;
-      a2 += b[6] * x0 + b[7] * x1 + b[8] * x2;
+      a0 += (double)b[0] * x0 + (double)b[1] * x1 + (double)b[2] * x2;
+      a1 += (double)b[3] * x0 + (double)b[4] * x1 + (double)b[5] * x2;
+      a2 += (double)b[6] * x0 + (double)b[7] * x1 + (double)b[8] * x2;
     }
   }
   a0 = group_sum<16>(a0);
@@ -423,31 +427,75 @@ void launch_spmv_csr3(hipStream_t s, int nrows, const long long* rp, const int* 
   k_spmv_csr3<<<(nrows + 3) / 4, 256, 0, s>>>(nrows, rp, cj, cx, xbase, stride, scale, st, use_j, y);
 }
 
+template <class MT>
+static void spmv_tasks_impl(hipStream_t s, int ntasks, const int4* tasks, const long long* rp, const int* cj,
+                            const MT* cx, const double* xbase, long long stride, const double* scale,
+                            const GmresState* st, double* y) {
+  const int use_j = (st != nullptr && scale != nullptr) ? 1 : 0;
+  k_spmv_tasks<MT><<<ntasks, 256, 0, s>>>(tasks, rp, cj, cx, xbase, stride, scale, st, use_j, y);
+}
 void launch_spmv_tasks(hipStream_t s, int ntasks, const int4* tasks, const long long* rp, const int* cj,
                        const double* cx, const double* xbase, long long stride, const double* scale,
                        const GmresState* st, double* y) {
-  const int use_j = (st != nullptr && scale != nullptr) ? 1 : 0;
-  k_spmv_tasks<<<ntasks, 256, 0, s>>>(tasks, rp, cj, cx, xbase, stride, scale, st, use_j, y);
+  spmv_tasks_impl(s, ntasks, tasks, rp, cj, cx, xbase, stride, scale, st, y);
+}
+void launch_spmv_tasks(hipStream_t s, int ntasks, const int4* tasks, const long long* rp, const int* cj,
+                       const float* cx, const double* xbase, long long stride, const double* scale,
+                       const GmresState* st, double* y) {
+  spmv_tasks_impl(s, ntasks, tasks, rp, cj, cx, xbase, stride, scale, st, y);
 }
 
-void launch_wb_gather(hipStream_t s, int m, int mp, const int* row_c, const int* row_i, const int* vid,
-                      const double* Q, const double* X, const double* u, const GmresState* st,
-                      double* t) {
+template <class MT>
+static void wb_gather_impl(hipStream_t s, int m, int mp, const int* row_c, const int* row_i, const int* vid,
+                           const double* Q, const MT* X, const double* u, const GmresState* st, double* t) {
   if (m == 0) return;
-  k_wb_gather<<<(m + 3) / 4, 256, (size_t)m * sizeof(double), s>>>(m, mp, row_c, row_i, vid, Q, X, u, st,
-                                                                    t);
+  k_wb_gather<MT><<<(m + 3) / 4, 256, (size_t)m * sizeof(double), s>>>(m, mp, row_c, row_i, vid, Q, X, u, st,
+                                                                        t);
+}
+void launch_wb_gather(hipStream_t s, int m, int mp, const int* row_c, const int* row_i, const int* vid,
+                      const double* Q, const double* X, const double* u, const GmresState* st, double* t) {
+  wb_gather_impl(s, m, mp, row_c, row_i, vid, Q, X, u, st, t);
+}
+void launch_wb_gather(hipStream_t s, int m, int mp, const int* row_c, const int* row_i, const int* vid,
+                      const double* Q, const float* X, const double* u, const GmresState* st, double* t) {
+  wb_gather_impl(s, m, mp, row_c, row_i, vid, Q, X, u, st, t);
 }
 
-void launch_wb_correct(hipStream_t s, int nv, int ncv, const int* cv_ptr, const int* c_row0,
-                       const int* c_nrow, const double* Q, const double* t, const double* Z, double h2,
-                       const double* u, const GmresState* st, double* y) {
-  k_wb_correct<<<(nv + 3) / 4, 256, (size_t)3 * ncv * sizeof(double), s>>>(
-      nv, ncv, cv_ptr, c_row0, c_nrow, Q, t, Z, h2, u, st, y);
+template <class MT>
+static void wb_correct_impl(hipStream_t s, int nv, int ncv, const int* cv_ptr, const int* c_row0,
+                            const int* c_nrow, const double* Q, const double* t, const MT* Z, double h2,
+                            const double* u, const GmresState* st, double* y) {
+  k_wb_correct<MT><<<(nv + 3) / 4, 256, (size_t)3 * ncv * sizeof(double), s>>>(nv, ncv, cv_ptr, c_row0,
+                                                                                c_nrow, Q, t, Z, h2, u, st,
+                                                                                y);
+}
+void launch_wb_correct(hipStream_t s, int nv, int ncv, const int* cv_ptr, const int* c_row0, const int* c_nrow,
+                       const double* Q, const double* t, const double* Z, double h2, const double* u,
+                       const GmresState* st, double* y) {
+  wb_correct_impl(s, nv, ncv, cv_ptr, c_row0, c_nrow, Q, t, Z, h2, u, st, y);
+}
+void launch_wb_correct(hipStream_t s, int nv, int ncv, const int* cv_ptr, const int* c_row0, const int* c_nrow,
+                       const double* Q, const double* t, const float* Z, double h2, const double* u,
+                       const GmresState* st, double* y) {
+  wb_correct_impl(s, nv, ncv, cv_ptr, c_row0, c_nrow, Q, t, Z, h2, u, st, y);
 }
 
 void launch_bsr_spmv(hipStream_t s, int nv, const int* rowptr, const int* col, const double* val,
                      const double* x, double* outbase, long long stride, const GmresState* st) {
-  k_bsr_spmv<<<(nv + 15) / 16, 256, 0, s>>>(nv, rowptr, col, val, x, outbase, stride, st);
+  k_bsr_spmv<double><<<(nv + 15) / 16, 256, 0, s>>>(nv, rowptr, col, val, x, outbase, stride, st);
+}
+void launch_bsr_spmv(hipStream_t s, int nv, const int* rowptr, const int* col, const float* val,
+                     const double* x, double* outbase, long long stride, const GmresState* st) {
+  k_bsr_spmv<float><<<(nv + 15) / 16, 256, 0, s>>>(nv, rowptr, col, val, x, outbase, stride, st);
+}
+
+__global__ void k_to_f32(long long n, const double* __restrict__ a, float* __restrict__ out) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = (float)a[i];
+}
+void launch_to_f32(hipStream_t s, long long n, const double* a, float* out) {
+  if (n <= 0) return;
+  k_to_f32<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, a, out);
 }
 
 int gm_blocks(long long n) { return (int)((n + kRowsPerBlock - 1) / kRowsPerBlock); }

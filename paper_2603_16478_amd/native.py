@@ -25,7 +25,8 @@ ADJ_FP64, ADJ_MIXED = 0, 1
 # names declared in include/adjoint.h
 EXPORTS = ("adj_scene_create", "adj_scene_destroy", "adjoint_setup", "adjoint_solve", "vjp_params",
            "sim_forward_step", "adj_scene_info", "adj_check_status", "adj_debug_export",
-           "adj_profile_begin", "adj_profile_end", "adj_last_error")
+           "adj_profile_begin", "adj_profile_end", "adj_forward_stats", "adj_forward_reset",
+           "adj_last_error")
 KERNELS = {"S": 0, "ST": 1, "capinv": 2, "Z": 3, "bsr": 4, "tet": 5, "assemble": 6, "gj": 7,
            "gs_dots": 8, "gs_update": 9}
 
@@ -83,6 +84,8 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.adj_check_status.argtypes = [vp, vp]
     lib.adj_debug_export.argtypes = [vp, C.c_int32, vp, C.c_int64, C.POINTER(C.c_int64)]
     lib.adj_profile_begin.argtypes = [vp, C.c_int32]
+    lib.adj_forward_stats.argtypes = [vp, C.POINTER(C.c_double)]
+    lib.adj_forward_reset.argtypes = [vp]
     lib.adj_profile_end.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
     for name in EXPORTS:
         if name != "adj_last_error":
@@ -225,3 +228,44 @@ def check_status(scene: Scene, stream=None):
 def sim_forward_step(scene: Scene, qbar, vbar, f_ext, mu, q, v, contacts: ContactState, stream=None):
     check(load().sim_forward_step(scene.handle, _ptr(qbar), _ptr(vbar), _ptr(f_ext), float(mu), _ptr(q),
                                   _ptr(v), C.byref(contacts), _stream(stream)))
+
+
+def forward_stats(scene: Scene):
+    out = (C.c_double * 2)()
+    check(load().adj_forward_stats(scene.handle, out))
+    return int(out[0]), float(out[1])
+
+
+def forward_reset(scene: Scene):
+    check(load().adj_forward_reset(scene.handle))
+
+
+class ContactBuffers:
+    """Device arrays for one step record (capacity entries) and the
+    adj_contact_state that points at them."""
+
+    def __init__(self, capacity, device="cuda"):
+        import torch
+        n = max(int(capacity), 1)
+        self.vid = torch.zeros(n, dtype=torch.int32, device=device)
+        self.fric = torch.zeros(n, dtype=torch.int32, device=device)
+        self.frame = torch.zeros(n, 9, dtype=torch.float64, device=device)
+        self.delta = torch.zeros(n, 3, dtype=torch.float64, device=device)
+        self.lam = torch.zeros(n, 3, dtype=torch.float64, device=device)
+        self.d_n = torch.zeros(n, dtype=torch.float64, device=device)
+        self.d_f = torch.zeros(n, 2, dtype=torch.float64, device=device)
+        self.state = make_contact_state(0, self.vid, self.fric, self.frame, self.delta, self.lam, 0.0,
+                                        self.d_n, self.d_f, capacity=capacity)
+
+    @property
+    def n(self):
+        return int(self.state.n_contacts)
+
+    def clone(self):
+        """A copy of the current record (device tensors) with its own state."""
+        c = ContactBuffers.__new__(ContactBuffers)
+        for k in ("vid", "fric", "frame", "delta", "lam", "d_n", "d_f"):
+            setattr(c, k, getattr(self, k).clone())
+        c.state = make_contact_state(self.state.n_contacts, c.vid, c.fric, c.frame, c.delta, c.lam,
+                                     self.state.mu, c.d_n, c.d_f, capacity=self.state.capacity)
+        return c

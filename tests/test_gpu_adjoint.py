@@ -111,3 +111,44 @@ def test_beam_adjoint_matches_oracle(mu, t):
     assert abs(g[0] - ref.dE) <= TOL_FP64 * np.abs(ref.dE_tet).sum()
     assert abs(g[1] - ref.dnu) <= TOL_FP64 * np.abs(ref.dnu_tet).sum()
     assert abs(g[2] - ref.dmu_fric) <= TOL_FP64 * max(abs(ref.dmu_fric), 1e-30)
+
+
+@pytest.mark.parametrize("mu,t", [(1.0, 3), (0.1, 2), (0.4, 3)])
+def test_beam_mixed_precision_matches_oracle(mu, t):
+    """ADJ_MIXED (FP32-stored S, Z, capacitance inverse and block matrix in
+    the inner GMRES; FP64 Gram-Schmidt, FP64 refinement residual) against
+    the FP64 oracle: 1e-4 relative on every output (the mixed-precision
+    target), at the benchmark tolerance rtol 1e-8."""
+    torch = torch_cuda()
+    from paper_2603_16478_amd import native
+    from oracle.rollout import scene_disc
+    from synth import beam_scene
+    from gpu_helpers import contact_tensors
+    q, rec = _beam_state(mu, t)
+    spec = beam_scene(mu=mu)
+    ref = adj.adjoint_step(scene_disc(spec), q, rec, spec.loss_dir, np.zeros_like(q), spec.eps, spec.E, spec.nu)
+    scene = make_scene(spec, max_contacts=rec.contacts.n)
+    tens = contact_tensors(rec)
+    cs = native.make_contact_state(rec.contacts.n, tens["vid"], tens["fric"], tens["frame"], tens["delta"],
+                                   tens["lam"], rec.mu)
+    qd = torch.tensor(q, device="cuda")
+    gq = torch.tensor(spec.loss_dir, device="cuda")
+    gv = torch.zeros_like(gq)
+    z = torch.zeros_like(gq)
+    opts = native.solve_opts(rtol=1e-8, maxit=3000, restart=64, prec=native.ADJ_MIXED, max_refine=8)
+    native.adjoint_setup(scene, cs, qd, opts)
+    native.check_status(scene)
+    info = native.adjoint_solve(scene, gq, gv, z, opts)
+    dq, dv, df = torch.empty_like(qd), torch.empty_like(qd), torch.empty_like(qd)
+    g3 = torch.zeros(3, dtype=torch.float64, device="cuda")
+    native.vjp_params(scene, z, gv, dq, dv, df, g3)
+    torch.cuda.synchronize()
+    err = rel(z.cpu().numpy(), ref.z)
+    print(f"mixed mu={mu} t={t}: iters {info.iters} refine {info.refine_steps} relres {info.relres:.2e} "
+          f"z err {err:.2e}", flush=True)
+    assert info.relres <= 1e-8
+    assert err <= 1e-4
+    assert rel(dq.cpu().numpy(), ref.dqbar) <= 1e-4
+    g = g3.cpu().numpy()
+    assert abs(g[0] - ref.dE) <= 1e-4 * np.abs(ref.dE_tet).sum()
+    assert abs(g[1] - ref.dnu) <= 1e-4 * np.abs(ref.dnu_tet).sum()
