@@ -100,6 +100,7 @@ def main():
     ap.add_argument("--roofline-kernel", default="S", choices=["S", "ST", "bsr", "capinv", "Z", "tet"])
     ap.add_argument("--cpu-sample", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; --gpus above 1 is not supported",
@@ -138,6 +139,12 @@ def main():
     dqbar, dvbar, dfext = torch.empty_like(gq), torch.empty_like(gq), torch.empty_like(gq)
     grad3 = torch.zeros(3, dtype=torch.float64, device=dev)
     opts = native.solve_opts(rtol=args.rtol, maxit=5000, restart=64)
+
+    tuning = native.get_tuning(scene)
+    if not args.no_autotune:
+        t0s = dstates[0]
+        native.adjoint_setup(scene, t0s["cs"], t0s["q"], opts)
+        tuning = native.autotune(scene, gq, gv, z, opts, reps=3)
 
     iters = []
 
@@ -217,6 +224,7 @@ def main():
             "capacitance_rows": t_avg["m"],
             "krylov_iters_mean": float(np.mean(iters)) if iters else None,
             "precision": "fp64",
+            "tuning": tuning,
         },
         "roofline": {
             "kernel": {"S": "sparse-inverse product S x", "ST": "sparse-inverse product S^T x",

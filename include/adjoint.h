@@ -91,6 +91,13 @@ typedef struct {
   double mu;           /* friction coefficient of the step */
 } adj_contact_state;
 
+/* Krylov method (Sec. 5.4: GMRES for the non-symmetric frictional system,
+ * conjugate gradients when the system is symmetric positive definite).
+ * ADJ_AUTO picks PCG when no contact is frictional or mu = 0 (then every
+ * contact block, hence Acal^T and the Woodbury preconditioner, is symmetric),
+ * GMRES otherwise; ADJ_PCG on a non-symmetric system is ADJ_E_ARG. */
+typedef enum { ADJ_AUTO = 0, ADJ_GMRES = 1, ADJ_PCG = 2 } adj_krylov;
+
 typedef struct {
   double rtol;          /* relative residual |b - Acal^T z| / |b| (Sec. 6.1: 1e-8) */
   int32_t maxit;        /* total Krylov iterations over all restarts */
@@ -98,6 +105,7 @@ typedef struct {
   int32_t max_refine;   /* outer FP64 refinement sweeps (mixed precision) */
   adj_precision prec;
   int32_t reuse_delassus; /* 1: keep H A^{-1} H^T while the contact vertex set is unchanged */
+  adj_krylov method;
 } adj_solve_opts;
 
 typedef struct {
@@ -107,6 +115,7 @@ typedef struct {
   int32_t m_rows;       /* rows of the contact-space capacitance */
   double relres;        /* true relative residual at exit */
   int32_t delassus_rebuilt;
+  int32_t method;       /* ADJ_GMRES or ADJ_PCG: the method that ran */
 } adj_solve_info;
 
 /* Build the scene: rest-shape operators, lumped mass, the constant system
@@ -188,7 +197,8 @@ adj_status adj_check_status(adj_scene* scene, void* stream);
  * memory (synchronises the device).  what = 0: Acal^T block values
  * [nnz_blocks][3][3] row-major; 1: block row pointer [n_verts+1] int32;
  * 2: block column indices [nnz_blocks] int32; 3: inverse of the Woodbury
- * capacitance [m][m]; 4: Delassus matrix of the contact vertices
+ * capacitance [mp][mp] (m rows padded with identity to mp, a multiple of
+ * 64); 4: Delassus matrix of the contact vertices
  * [n_cv][n_cv]; 5: per-contact rotated bases Q = R frame [n_contacts][3][3].
  * *size_bytes receives the array size; nothing is copied when capacity_bytes
  * is smaller (ADJ_E_SHAPE).  For tests and debugging. */
@@ -206,6 +216,32 @@ adj_status adj_debug_export(const adj_scene* scene, int32_t what, void* host_out
  * are timed per region (later ones are not). */
 adj_status adj_profile_begin(adj_scene* scene, int32_t kernel);
 adj_status adj_profile_end(adj_scene* scene, double* total_ms, int64_t* launches);
+
+/* Launch shapes of the Krylov loop.  They change only how work is split
+ * over the GPU and the order of floating-point sums inside reductions (so
+ * results are bitwise reproducible for a fixed tuning, and agree across
+ * tunings to rounding).  Defaults: gs_rows 64, bsr_lanes 16, chunk 8,
+ * graph 0. */
+typedef struct {
+  int32_t gs_rows;   /* rows per 256-thread block of the Gram-Schmidt kernels: 64, 128, 256 */
+  int32_t bsr_lanes; /* lanes per block row of the Acal^T product: 4, 8, 16, 32 */
+  int32_t chunk;     /* Krylov iterations enqueued between host checks: 1..64 */
+  int32_t graph;     /* 1: each chunk is captured once per setup as a HIP graph and replayed */
+} adj_tuning;
+
+/* Set or read the scene's launch shapes.  ADJ_E_ARG on a value outside the
+ * listed sets. */
+adj_status adj_set_tuning(adj_scene* scene, const adj_tuning* t);
+adj_status adj_get_tuning(const adj_scene* scene, adj_tuning* t);
+
+/* Autotuner: after adjoint_setup, times adjoint_solve with right-hand side
+ * (dL_dq, dL_dv) under candidate launch shapes (coordinate descent over
+ * gs_rows, bsr_lanes, chunk and graph, each candidate the best of `reps`
+ * timed solves, HIP events on `stream`), keeps the fastest on the scene and
+ * writes it to *best (host).  z: device scratch [n_verts*3] that receives
+ * the last solution.  Synchronises the stream. */
+adj_status adj_autotune(adj_scene* scene, const double* dL_dq, const double* dL_dv, double* z,
+                        const adj_solve_opts* opts, int32_t reps, adj_tuning* best, void* stream);
 
 const char* adj_last_error(void);
 

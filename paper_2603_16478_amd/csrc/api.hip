@@ -40,7 +40,16 @@ void launch_vjp_vectors(hipStream_t, int, const double*, const double*, const do
                         double*, double*);
 void launch_fill_zero(hipStream_t, size_t, double*);
 void launch_delassus(hipStream_t, int, int, const int*, const long long*, const int*, const double*,
-                     double*, double*, double*);
+                     double*, double*, double*, double*);
+int delassus_slices(int, int);
+void launch_pcg_alpha(hipStream_t, long long, const double*, const double*, double*, unsigned*, GmresState*,
+                      double*);
+void launch_pcg_xr(hipStream_t, long long, double*, double*, const double*, const double*, double*, unsigned*,
+                   GmresState*, const double*);
+void launch_pcg_beta(hipStream_t, long long, const double*, const double*, double*, unsigned*, GmresState*,
+                     double*, int);
+void launch_pcg_p(hipStream_t, long long, const double*, double*, const GmresState*, const double*);
+void launch_pcg_residual(hipStream_t, long long, const double*, double*, double*, unsigned*, GmresState*);
 double* launch_gauss_jordan(hipStream_t, int, int, double*, double*, int*);
 void launch_spmv_csr3(hipStream_t, int, const long long*, const int*, const double*, const double*,
                       long long, const double*, const GmresState*, double*);
@@ -48,23 +57,19 @@ void launch_spmv_tasks(hipStream_t, int, const int4*, const long long*, const in
                        const double*, long long, const double*, const GmresState*, double*);
 void launch_spmv_tasks(hipStream_t, int, const int4*, const long long*, const int*, const float*,
                        const double*, long long, const double*, const GmresState*, double*);
-void launch_wb_gather(hipStream_t, int, int, const int*, const int*, const int*, const double*,
-                      const float*, const double*, const GmresState*, double*);
-void launch_wb_correct(hipStream_t, int, int, const int*, const int*, const int*, const double*,
-                       const double*, const float*, double, const double*, const GmresState*, double*);
-void launch_bsr_spmv(hipStream_t, int, const int*, const int*, const float*, const double*, double*,
+void launch_bsr_spmv(hipStream_t, int, int, const int*, const int*, const float*, const double*, double*,
                      long long, const GmresState*);
 void launch_to_f32(hipStream_t, long long, const double*, float*);
 void launch_wb_gather(hipStream_t, int, int, const int*, const int*, const int*, const double*,
                       const double*, const double*, const GmresState*, double*);
 void launch_wb_correct(hipStream_t, int, int, const int*, const int*, const int*, const double*,
                        const double*, const double*, double, const double*, const GmresState*, double*);
-void launch_bsr_spmv(hipStream_t, int, const int*, const int*, const double*, const double*, double*,
+void launch_bsr_spmv(hipStream_t, int, int, const int*, const int*, const double*, const double*, double*,
                      long long, const GmresState*);
-int gm_blocks(long long);
-void launch_gm_dots(hipStream_t, long long, const double*, long long, const double*, GmresState*,
+int gm_blocks(long long, int);
+void launch_gm_dots(hipStream_t, long long, int, const double*, long long, const double*, GmresState*,
                     double*, unsigned*, double*);
-void launch_gm_update(hipStream_t, long long, double*, long long, double*, GmresState*, double*,
+void launch_gm_update(hipStream_t, long long, int, double*, long long, double*, GmresState*, double*,
                       unsigned*, double*, double*, double*, double*, double*, int);
 void launch_gm_finish(hipStream_t, long long, const GmresState*, const double*, const double*,
                       const double*, const double*, long long, double*, double*);
@@ -125,6 +130,7 @@ hipError_t upload(T** p, const std::vector<T>& v) {
 
 struct adj_scene {
   HostScene hs;
+  adj_tuning tune{64, 16, 8, 0};
   int nv = 0, nt = 0, nnzb = 0, max_contacts = 0;
   long long n3 = 0;
   int restart = 0;
@@ -147,6 +153,10 @@ struct adj_scene {
   // Delassus cache
   std::vector<int> cv_cached;
   bool delassus_valid = false;
+  bool delassus_f32 = false;
+  bool symmetric = true;      // Acal^T symmetric: no frictional contact, or mu = 0  // D computed on FP32 matrix cores (mixed precision)
+  double* d_Pws = nullptr;    // K-slice partials of the Delassus product
+  size_t cap_pws = 0;
   size_t cap_ncv = 0, cap_m = 0;
   double *d_Y = nullptr, *d_D = nullptr, *d_Z = nullptr, *d_C = nullptr, *d_P = nullptr,
          *d_colbuf = nullptr, *d_tvec = nullptr;
@@ -168,18 +178,20 @@ struct adj_scene {
   double *d_t1 = nullptr, *d_u = nullptr, *d_y = nullptr, *d_r = nullptr, *d_b = nullptr,
          *d_dz = nullptr, *d_xt = nullptr;
   // mixed precision: FP32 storage of the matrices used inside the inner solve
-  float *d_Sx32 = nullptr, *d_STx32 = nullptr, *d_val32 = nullptr, *d_Z32 = nullptr, *d_X32 = nullptr;
-  size_t cap_z32 = 0, cap_x32 = 0;
-  bool z32_valid = false, mixed_ready = false;
+  float *d_Sx32 = nullptr, *d_STx32 = nullptr, *d_val32 = nullptr;
+  bool mixed_ready = false;
   // forward step
   double* d_planes = nullptr;
   int *d_vptr = nullptr, *d_vcode = nullptr, *d_mask = nullptr, *d_fvid = nullptr;
   double *d_force = nullptr, *d_utilde = nullptr, *d_qtilde = nullptr, *d_fu = nullptr, *d_du = nullptr,
          *d_ut = nullptr, *d_qcur = nullptr, *d_rq = nullptr, *d_rhs = nullptr, *d_cvec = nullptr,
-         *d_cu = nullptr, *d_norms = nullptr;
+         *d_cu = nullptr, *d_norms = nullptr, *d_x_pcg = nullptr;
   std::unordered_map<long long, std::pair<double, double>> warm;
   int fwd_newton_iters = 0;
   double fwd_residual = 0.0;
+  // captured Krylov chunks (tuning.graph = 1), rebuilt after every setup
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t chunk_exec[4] = {nullptr, nullptr, nullptr, nullptr};  // [pcg][f32]
   // live kernel timing (adj_profile_begin / adj_profile_end)
   int prof_kernel = -1;
   std::vector<hipEvent_t> prof_ev;
@@ -231,11 +243,14 @@ static void free_scene(adj_scene* s) {
                   s->d_mask,     s->d_fvid,   s->d_force, s->d_utilde,      s->d_qtilde,
                   s->d_fu,       s->d_du,     s->d_ut,    s->d_qcur,        s->d_rq,
                   s->d_rhs,      s->d_cvec,   s->d_cu,    s->d_norms,       s->d_Sx32,
-                  s->d_STx32,    s->d_val32,  s->d_Z32,   s->d_X32};
+                  s->d_STx32,    s->d_val32,  s->d_Pws,   s->d_x_pcg};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (s->h_state) (void)hipHostFree(s->h_state);
   for (hipEvent_t e : s->prof_ev) (void)hipEventDestroy(e);
+  for (hipGraphExec_t& g : s->chunk_exec)
+    if (g) (void)hipGraphExecDestroy(g);
+  if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
   delete s;
 }
 
@@ -303,7 +318,7 @@ extern "C" adj_status adj_scene_create(const adj_scene_desc* desc, int32_t max_c
   bool ok = true;
   const size_t mc = (size_t)std::max(1, max_contacts);
   const size_t R = kMaxRestart;
-  const size_t nblk = (size_t)gm_blocks(s->n3) + 300;
+  const size_t nblk = (size_t)gm_blocks(s->n3, 64) + 300;  // smallest rows-per-block is 64
   ok &= dalloc(&s->d_tetblk, 90 * (size_t)s->nt) == hipSuccess;
   ok &= dalloc(&s->d_val, 9 * (size_t)s->nnzb) == hipSuccess;
   ok &= dalloc(&s->d_err, 4) == hipSuccess;
@@ -339,6 +354,7 @@ extern "C" adj_status adj_scene_create(const adj_scene_desc* desc, int32_t max_c
   ok &= dalloc(&s->d_b, (size_t)s->n3) == hipSuccess;
   ok &= dalloc(&s->d_dz, (size_t)s->n3) == hipSuccess;
   ok &= dalloc(&s->d_xt, (size_t)s->n3) == hipSuccess;
+  ok &= dalloc(&s->d_x_pcg, (size_t)s->n3) == hipSuccess;
   ok &= hipHostMalloc((void**)&s->h_state, sizeof(GmresState), hipHostMallocDefault) == hipSuccess;
   ok &= dalloc(&s->d_mask, (size_t)s->nv) == hipSuccess;
   ok &= dalloc(&s->d_Sx32, h.Sx.size()) == hipSuccess;
@@ -379,18 +395,6 @@ extern "C" adj_status adj_scene_destroy(adj_scene* scene) {
   return ADJ_OK;
 }
 
-static adj_status growf(float** p, size_t* cap, size_t need) {
-  if (need <= *cap && *p) return ADJ_OK;
-  if (*p) (void)hipFree(*p);
-  *p = nullptr;
-  if (dalloc(p, need) != hipSuccess) {
-    *cap = 0;
-    return fail(ADJ_E_OOM, "device allocation failed");
-  }
-  *cap = need;
-  return ADJ_OK;
-}
-
 extern "C" adj_status adj_scene_info(const adj_scene* s, int64_t* out) {
   if (!s || !out) return fail(ADJ_E_ARG, "null argument");
   out[0] = s->nv;
@@ -416,9 +420,18 @@ static adj_status grow(double** p, size_t* cap, size_t need) {
 
 // Contact bookkeeping shared by the adjoint and the forward step: unique
 // contact vertices, capacitance row layout, upload of the maps, and the
+static void drop_chunk_graphs(adj_scene* s) {
+  for (hipGraphExec_t& g : s->chunk_exec)
+    if (g) {
+      (void)hipGraphExecDestroy(g);
+      g = nullptr;
+    }
+}
+
 // Delassus matrix / Z (rebuilt only when the contact vertex set changes).
 static adj_status contact_layout(adj_scene* s, hipStream_t st, int nc, const std::vector<int>& vid,
                                  const std::vector<int>& fric, bool reuse) {
+  drop_chunk_graphs(s);  // captured chunks hold the contact layout
   std::vector<int> cv, cv_ptr, cmap(nc), row_c, row_i, c_row0(nc), c_nrow(nc);
   for (int c = 0; c < nc; ++c) {
     if (vid[c] < 0 || vid[c] >= s->nv) return fail(ADJ_E_ARG, "contact vertex out of range");
@@ -459,11 +472,12 @@ static adj_status contact_layout(adj_scene* s, hipStream_t st, int nc, const std
     if ((a = grow(&s->d_Z, &capZ, (size_t)s->nv * ncv)) != ADJ_OK) return a;
     if ((a = grow(&s->d_D, &capD, (size_t)ncv * ncv)) != ADJ_OK) return a;
     s->cap_ncv = std::max(s->cap_ncv, (size_t)ncv);
-    launch_delassus(st, s->nv, ncv, s->d_cv, s->d_STp, s->d_STj, s->d_STx, s->d_Y, s->d_D, s->d_Z);
+    const int ks = delassus_slices(s->nv, ncv);
+    if (ks > 1 && (a = grow(&s->d_Pws, &s->cap_pws, (size_t)ks * ncv * ncv)) != ADJ_OK) return a;
+    launch_delassus(st, s->nv, ncv, s->d_cv, s->d_STp, s->d_STj, s->d_STx, s->d_Y, s->d_D, s->d_Z, s->d_Pws);
     s->cv_cached = cv;
     s->delassus_valid = true;
     s->delassus_rebuilt = 1;
-    s->z32_valid = false;
   }
   return ADJ_OK;
 }
@@ -472,9 +486,10 @@ static adj_status contact_layout(adj_scene* s, hipStream_t st, int nc, const std
 // Khat^{-1} + ... (transpose = 0, forward Newton) from s->d_Q, s->d_kh, and
 // its inverse s->d_X.
 static adj_status build_capacitance(adj_scene* s, hipStream_t st, double mu, int transpose) {
+  drop_chunk_graphs(s);  // captured chunks hold the contact layout and the address of X
   if (!s->nc) return ADJ_OK;
   const double h2 = s->hs.h * s->hs.h;
-  const int m = s->m, mp = ((m + 31) / 32) * 32;
+  const int m = s->m, mp = ((m + 63) / 64) * 64;  // Gauss-Jordan tiles are 64 x 64
   s->mp = mp;
   size_t capC = s->cap_m * s->cap_m, capB = capC;
   if ((size_t)mp > s->cap_m) capC = capB = 0;
@@ -508,7 +523,12 @@ extern "C" adj_status adjoint_setup(adj_scene* s, const adj_contact_state* cst, 
     HIPCHK(hipMemcpyAsync(fric.data(), cst->fric, nc * sizeof(int), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
   }
+  drop_chunk_graphs(s);
   s->mu = cst->mu;
+  s->symmetric = true;
+  if (cst->mu != 0.0)
+    for (int c = 0; c < nc; ++c)
+      if (fric[c]) s->symmetric = false;
   s->cur_vid = cst->vid;
   s->cur_frame = cst->frame;
   s->cur_q = q;
@@ -533,17 +553,12 @@ extern "C" adj_status adjoint_setup(adj_scene* s, const adj_contact_state* cst, 
   if ((a = build_capacitance(s, st, cst->mu, 1)) != ADJ_OK) return a;
   s->mixed_ready = false;
   if (opts && opts->prec == ADJ_MIXED) {
-    // FP32 storage of the matrices read inside the inner solve
+    // FP32 storage of the block matrix read by the inner solve (S and S^T
+    // have FP32 copies from scene creation).  The Woodbury factors D, X and
+    // Z stay FP64: in the directions of stiff contacts the correction
+    // cancels A^{-1} r almost exactly, so their rounding would be amplified
+    // by the contact-to-elastic stiffness ratio.
     launch_to_f32(st, 9LL * s->nnzb, s->d_val, s->d_val32);
-    if (nc) {
-      if (!s->z32_valid) {
-        if ((a = growf(&s->d_Z32, &s->cap_z32, (size_t)s->nv * s->ncv)) != ADJ_OK) return a;
-        launch_to_f32(st, (long long)s->nv * s->ncv, s->d_Z, s->d_Z32);
-        s->z32_valid = true;
-      }
-      if ((a = growf(&s->d_X32, &s->cap_x32, (size_t)s->mp * s->mp)) != ADJ_OK) return a;
-      launch_to_f32(st, (long long)s->mp * s->mp, s->d_X, s->d_X32);
-    }
     s->mixed_ready = true;
   }
   HIPCHK(hipGetLastError());
@@ -563,7 +578,7 @@ extern "C" adj_status adj_check_status(adj_scene* s, void* stream) {
 }
 
 // P x -> out (x and out distinct from the scratch vectors t1, u, tvec).
-// f32: the matrices are read from their FP32 copies (vectors stay FP64).
+// f32: S and S^T are read from their FP32 copies (vectors, X and Z stay FP64).
 static void apply_precond(adj_scene* s, hipStream_t st, const double* x, long long stride,
                           const double* scale, const GmresState* state, double* out, bool f32 = false) {
   const double h2 = s->hs.h * s->hs.h;
@@ -589,30 +604,98 @@ static void apply_precond(adj_scene* s, hipStream_t st, const double* x, long lo
   if (s->nc == 0) return;
   {
     ProfScope p(s, 2, st);
-    if (f32)
-      launch_wb_gather(st, s->m, s->mp, s->d_row_c, s->d_row_i, s->cur_vid, s->d_Q, s->d_X32, s->d_u, state,
-                       s->d_tvec);
-    else
-      launch_wb_gather(st, s->m, s->mp, s->d_row_c, s->d_row_i, s->cur_vid, s->d_Q, s->d_X, s->d_u, state,
-                       s->d_tvec);
+    launch_wb_gather(st, s->m, s->mp, s->d_row_c, s->d_row_i, s->cur_vid, s->d_Q, s->d_X, s->d_u, state,
+                     s->d_tvec);
   }
   {
     ProfScope p(s, 3, st);
-    if (f32)
-      launch_wb_correct(st, s->nv, s->ncv, s->d_cv_ptr, s->d_c_row0, s->d_c_nrow, s->d_Q, s->d_tvec,
-                        s->d_Z32, h2, s->d_u, state, out);
-    else
-      launch_wb_correct(st, s->nv, s->ncv, s->d_cv_ptr, s->d_c_row0, s->d_c_nrow, s->d_Q, s->d_tvec, s->d_Z,
-                        h2, s->d_u, state, out);
+    launch_wb_correct(st, s->nv, s->ncv, s->d_cv_ptr, s->d_c_row0, s->d_c_nrow, s->d_Q, s->d_tvec, s->d_Z, h2,
+                      s->d_u, state, out);
   }
 }
 
 static void bsr(adj_scene* s, hipStream_t st, const double* x, double* outbase, long long stride,
                 const GmresState* state, bool f32) {
   if (f32)
-    launch_bsr_spmv(st, s->nv, s->d_rowptr, s->d_col, s->d_val32, x, outbase, stride, state);
+    launch_bsr_spmv(st, s->tune.bsr_lanes, s->nv, s->d_rowptr, s->d_col, s->d_val32, x, outbase, stride, state);
   else
-    launch_bsr_spmv(st, s->nv, s->d_rowptr, s->d_col, s->d_val, x, outbase, stride, state);
+    launch_bsr_spmv(st, s->tune.bsr_lanes, s->nv, s->d_rowptr, s->d_col, s->d_val, x, outbase, stride, state);
+}
+
+static void gmres_chunk(adj_scene* s, hipStream_t st, bool f32) {
+  const long long n3 = s->n3, stride = n3;
+  for (int k = 0; k < s->tune.chunk; ++k) {
+    apply_precond(s, st, s->d_Vt, stride, s->d_scale, s->d_state, s->d_y, f32);
+    {
+      ProfScope p(s, 4, st);
+      bsr(s, st, s->d_y, s->d_Vt, stride, s->d_state, f32);
+    }
+    {
+      ProfScope p(s, 8, st);
+      launch_gm_dots(st, n3, s->tune.gs_rows, s->d_Vt, stride, s->d_scale, s->d_state, s->d_partial,
+                     s->d_counter, s->d_hbuf);
+    }
+    {
+      ProfScope p(s, 9, st);
+      launch_gm_update(st, n3, s->tune.gs_rows, s->d_Vt, stride, s->d_scale, s->d_state, s->d_partial,
+                       s->d_counter + 1, s->d_hbuf, s->d_H, s->d_cs, s->d_sn, s->d_g, 0);
+    }
+    launch_gm_update(st, n3, s->tune.gs_rows, s->d_Vt, stride, s->d_scale, s->d_state, s->d_partial,
+                     s->d_counter + 2, s->d_hbuf, s->d_H, s->d_cs, s->d_sn, s->d_g, 1);
+  }
+}
+
+static void pcg_chunk(adj_scene* s, hipStream_t st, bool f32) {
+  const long long n3 = s->n3;
+  double* p = s->d_Vt;
+  double* w = s->d_Vt + n3;
+  double* z = s->d_y;
+  double* sc = s->d_coef;
+  unsigned* ctr = s->d_counter + 8;
+  for (int k = 0; k < s->tune.chunk; ++k) {
+    {
+      ProfScope pr(s, 4, st);
+      bsr(s, st, p, w, 0, s->d_state, f32);
+    }
+    launch_pcg_alpha(st, n3, p, w, s->d_partial, ctr, s->d_state, sc);
+    launch_pcg_xr(st, n3, s->d_x_pcg, s->d_r, p, w, s->d_partial, ctr, s->d_state, sc);
+    apply_precond(s, st, s->d_r, 0, nullptr, s->d_state, z, f32);
+    launch_pcg_beta(st, n3, s->d_r, z, s->d_partial, ctr, s->d_state, sc, 0);
+    launch_pcg_p(st, n3, z, p, s->d_state, sc);
+  }
+}
+
+// One chunk of Krylov iterations (kind 0 GMRES, 1 PCG) on `st`: launched
+// directly, or (tuning.graph = 1, no live profiling) replayed from a graph
+// captured on the scene's private stream after the last setup.
+static hipError_t run_chunk(adj_scene* s, hipStream_t st, int kind, bool f32) {
+  if (!s->tune.graph || s->prof_kernel >= 0) {
+    if (kind == 0)
+      gmres_chunk(s, st, f32);
+    else
+      pcg_chunk(s, st, f32);
+    return hipGetLastError();
+  }
+  hipGraphExec_t& ex = s->chunk_exec[2 * kind + (f32 ? 1 : 0)];
+  if (!ex) {
+    hipError_t e;
+    if (!s->cap_stream && (e = hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking)) != hipSuccess)
+      return e;
+    if ((e = hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal)) != hipSuccess) return e;
+    if (kind == 0)
+      gmres_chunk(s, s->cap_stream, f32);
+    else
+      pcg_chunk(s, s->cap_stream, f32);
+    hipGraph_t g = nullptr;
+    if ((e = hipStreamEndCapture(s->cap_stream, &g)) != hipSuccess) return e;
+    e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+      ex = nullptr;
+      return e;
+    }
+  }
+  return hipGraphLaunch(ex, st);
 }
 
 // Right-preconditioned restarted GMRES on the assembled matrix (s->d_val,
@@ -643,29 +726,10 @@ static adj_status gmres_solve(adj_scene* s, hipStream_t st, const double* b, dou
   int total = 0;
   double relres = (bnorm > 0) ? cur.rnorm / bnorm : 0.0;
   bool converged = !(bnorm > tol);
-  const int chunk = 8;
   while (!converged && total < maxit) {
     int done_in_cycle = 0;
     while (true) {
-      for (int k = 0; k < chunk; ++k) {
-        apply_precond(s, st, s->d_Vt, stride, s->d_scale, s->d_state, s->d_y, f32);
-        {
-          ProfScope p(s, 4, st);
-          bsr(s, st, s->d_y, s->d_Vt, stride, s->d_state, f32);
-        }
-        {
-          ProfScope p(s, 8, st);
-          launch_gm_dots(st, n3, s->d_Vt, stride, s->d_scale, s->d_state, s->d_partial, s->d_counter,
-                         s->d_hbuf);
-        }
-        {
-          ProfScope p(s, 9, st);
-          launch_gm_update(st, n3, s->d_Vt, stride, s->d_scale, s->d_state, s->d_partial, s->d_counter + 1,
-                           s->d_hbuf, s->d_H, s->d_cs, s->d_sn, s->d_g, 0);
-        }
-        launch_gm_update(st, n3, s->d_Vt, stride, s->d_scale, s->d_state, s->d_partial, s->d_counter + 2,
-                         s->d_hbuf, s->d_H, s->d_cs, s->d_sn, s->d_g, 1);
-      }
+      HIPCHK(run_chunk(s, st, 0, f32));
       HIPCHK(hipGetLastError());
       HIPCHK(hipMemcpyAsync(s->h_state, s->d_state, sizeof(GmresState), hipMemcpyDeviceToHost, st));
       HIPCHK(hipStreamSynchronize(st));
@@ -693,6 +757,76 @@ static adj_status gmres_solve(adj_scene* s, hipStream_t st, const double* b, dou
   return ADJ_OK;
 }
 
+// Preconditioned conjugate gradients (symmetric case), same preconditioner
+// and stopping rule as GMRES; the recurrence residual is confirmed by the
+// true residual, and the iteration restarts from the current x if they
+// disagree.  p = Vt_0, w = Vt_1, z = y; device scalars in coef[0..3].
+static adj_status pcg_solve(adj_scene* s, hipStream_t st, const double* b, double* x, double rtol, int maxit,
+                            int* iters_out, double* relres_out, bool* converged_out, bool f32 = false) {
+  const long long n3 = s->n3;
+  double* p = s->d_Vt;
+  double* z = s->d_y;
+  double* xi = s->d_x_pcg;  // fixed address, so a captured chunk stays valid
+  double* sc = s->d_coef;
+  unsigned* ctr = s->d_counter + 8;
+  if (b != s->d_b) HIPCHK(hipMemcpyAsync(s->d_b, b, n3 * sizeof(double), hipMemcpyDeviceToDevice, st));
+  launch_fill_zero(st, (size_t)n3, xi);
+  launch_fill_zero(st, (size_t)n3, s->d_r);
+  GmresState init{};
+  HIPCHK(hipMemcpyAsync(s->d_state, &init, sizeof(GmresState), hipMemcpyHostToDevice, st));
+  launch_pcg_residual(st, n3, s->d_b, s->d_r, s->d_partial, ctr, s->d_state);
+  HIPCHK(hipMemcpyAsync(s->h_state, s->d_state, sizeof(GmresState), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  const double bnorm = s->h_state->rnorm;
+  const double tol = rtol * bnorm;
+  double rnorm = bnorm;
+  int total = 0;
+  bool converged = !(bnorm > tol);
+  for (int pass = 0; pass < 8 && !converged && total < maxit; ++pass) {
+    GmresState cur{};
+    cur.tol = tol;
+    cur.restart = maxit - total;
+    cur.res = rnorm;
+    cur.rnorm = rnorm;
+    cur.active = 1;
+    HIPCHK(hipMemcpyAsync(s->d_state, &cur, sizeof(GmresState), hipMemcpyHostToDevice, st));
+    apply_precond(s, st, s->d_r, 0, nullptr, s->d_state, z, f32);
+    launch_pcg_beta(st, n3, s->d_r, z, s->d_partial, ctr, s->d_state, sc, 1);
+    launch_fill_zero(st, (size_t)n3, p);
+    launch_pcg_p(st, n3, z, p, s->d_state, sc);
+    int done = 0;
+    while (true) {
+      HIPCHK(run_chunk(s, st, 1, f32));
+      HIPCHK(hipGetLastError());
+      HIPCHK(hipMemcpyAsync(s->h_state, s->d_state, sizeof(GmresState), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      done = s->h_state->j;
+      if (!s->h_state->active) break;
+    }
+    total += done;
+    // true residual
+    bsr(s, st, xi, s->d_r, 0, nullptr, f32);
+    launch_pcg_residual(st, n3, s->d_b, s->d_r, s->d_partial, ctr, s->d_state);
+    HIPCHK(hipMemcpyAsync(s->h_state, s->d_state, sizeof(GmresState), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    rnorm = s->h_state->rnorm;
+    if (!std::isfinite(rnorm)) return fail(ADJ_E_SINGULAR, "non-finite residual in the Krylov solve");
+    converged = rnorm <= tol;
+    if (done == 0) break;  // breakdown without progress
+  }
+  HIPCHK(hipMemcpyAsync(x, xi, n3 * sizeof(double), hipMemcpyDeviceToDevice, st));
+  *iters_out = total;
+  *relres_out = (bnorm > 0) ? rnorm / bnorm : 0.0;
+  *converged_out = converged;
+  return ADJ_OK;
+}
+
+static adj_status krylov_solve(adj_scene* s, hipStream_t st, bool use_pcg, const double* b, double* x,
+                               double rtol, int maxit, int R, int* iters, double* relres, bool* conv, bool f32) {
+  if (use_pcg) return pcg_solve(s, st, b, x, rtol, maxit, iters, relres, conv, f32);
+  return gmres_solve(s, st, b, x, rtol, maxit, R, iters, relres, conv, f32);
+}
+
 extern "C" adj_status adjoint_solve(adj_scene* s, const double* dL_dq, const double* dL_dv, double* z,
                                     const adj_solve_opts* opts, adj_solve_info* info, void* stream) {
   if (!s || !dL_dq || !dL_dv || !z || !opts) return fail(ADJ_E_ARG, "null argument");
@@ -700,6 +834,11 @@ extern "C" adj_status adjoint_solve(adj_scene* s, const double* dL_dq, const dou
   if (!(opts->rtol > 0) || opts->maxit <= 0 || opts->restart < 1 || opts->restart > kMaxRestart)
     return fail(ADJ_E_ARG, "invalid solve options");
   if (opts->prec != ADJ_FP64 && opts->prec != ADJ_MIXED) return fail(ADJ_E_ARG, "unknown precision");
+  if (opts->method != ADJ_AUTO && opts->method != ADJ_GMRES && opts->method != ADJ_PCG)
+    return fail(ADJ_E_ARG, "unknown Krylov method");
+  if (opts->method == ADJ_PCG && !s->symmetric)
+    return fail(ADJ_E_ARG, "PCG needs a symmetric system (no frictional contact, or mu = 0)");
+  const bool use_pcg = opts->method == ADJ_PCG || (opts->method == ADJ_AUTO && s->symmetric);
   if (opts->prec == ADJ_MIXED && !s->mixed_ready)
     return fail(ADJ_E_ARG, "adjoint_setup must run with ADJ_MIXED before a mixed solve");
   hipStream_t st = (hipStream_t)stream;
@@ -712,7 +851,8 @@ extern "C" adj_status adjoint_solve(adj_scene* s, const double* dL_dq, const dou
   bool converged = false;
   adj_status a;
   if (opts->prec == ADJ_FP64) {
-    a = gmres_solve(s, st, s->d_rhs, z, opts->rtol, opts->maxit, opts->restart, &total, &relres, &converged);
+    a = krylov_solve(s, st, use_pcg, s->d_rhs, z, opts->rtol, opts->maxit, opts->restart, &total, &relres,
+                     &converged, false);
     if (a != ADJ_OK) return a;
   } else {
     // Iterative refinement: FP64 residual r = b - Acal^T z with the FP64
@@ -732,8 +872,8 @@ extern "C" adj_status adjoint_solve(adj_scene* s, const double* dL_dq, const dou
       int it = 0;
       double rr = 0.0;
       bool cv = false;
-      if ((a = gmres_solve(s, st, s->d_fu, s->d_du, inner, opts->maxit - total, opts->restart, &it, &rr, &cv,
-                           true)) != ADJ_OK)
+      if ((a = krylov_solve(s, st, use_pcg, s->d_fu, s->d_du, inner, opts->maxit - total, opts->restart, &it,
+                            &rr, &cv, true)) != ADJ_OK)
         return a;
       total += it;
       launch_axpy(st, n3, 1.0, s->d_du, z);
@@ -756,6 +896,7 @@ extern "C" adj_status adjoint_solve(adj_scene* s, const double* dL_dq, const dou
     info->m_rows = s->m;
     info->relres = relres;
     info->delassus_rebuilt = s->delassus_rebuilt;
+    info->method = use_pcg ? ADJ_PCG : ADJ_GMRES;
   }
   if (!converged) return fail(ADJ_E_NOCONV, "Krylov solve did not reach rtol");
   return ADJ_OK;
@@ -776,6 +917,92 @@ extern "C" adj_status vjp_params(adj_scene* s, const double* z, const double* dL
                   s->cur_q, z, dE_tet, dnu_tet, s->d_partial + 4096, s->d_counter + 5, grad3);
   HIPCHK(hipGetLastError());
   return ADJ_OK;
+}
+
+static bool valid_tuning(const adj_tuning& t) {
+  const bool gs = t.gs_rows == 64 || t.gs_rows == 128 || t.gs_rows == 256;
+  const bool ln = t.bsr_lanes == 4 || t.bsr_lanes == 8 || t.bsr_lanes == 16 || t.bsr_lanes == 32;
+  return gs && ln && t.chunk >= 1 && t.chunk <= 64 && (t.graph == 0 || t.graph == 1);
+}
+
+extern "C" adj_status adj_set_tuning(adj_scene* s, const adj_tuning* t) {
+  if (!s || !t) return fail(ADJ_E_ARG, "null argument");
+  if (!valid_tuning(*t)) return fail(ADJ_E_ARG, "tuning value outside the supported set");
+  s->tune = *t;
+  drop_chunk_graphs(s);
+  return ADJ_OK;
+}
+
+extern "C" adj_status adj_get_tuning(const adj_scene* s, adj_tuning* t) {
+  if (!s || !t) return fail(ADJ_E_ARG, "null argument");
+  *t = s->tune;
+  return ADJ_OK;
+}
+
+// Coordinate descent over the launch shapes; each candidate is timed as the
+// best of `reps` full solves (HIP events), with captured chunks dropped
+// before every solve so that graph replay pays its capture as it would
+// after a fresh setup.
+extern "C" adj_status adj_autotune(adj_scene* s, const double* dL_dq, const double* dL_dv, double* z,
+                                   const adj_solve_opts* opts, int32_t reps, adj_tuning* best, void* stream) {
+  if (!s || !dL_dq || !dL_dv || !z || !opts || !best) return fail(ADJ_E_ARG, "null argument");
+  if (!s->setup_done) return fail(ADJ_E_ARG, "adjoint_setup has not run");
+  if (s->prof_kernel >= 0) return fail(ADJ_E_ARG, "autotune while live profiling is armed");
+  hipStream_t st = (hipStream_t)stream;
+  reps = std::max(1, reps);
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(ADJ_E_DEVICE, "hipEventCreate failed");
+  }
+  adj_status status = ADJ_OK;
+  auto time_of = [&](const adj_tuning& t, float* out_ms) -> adj_status {
+    s->tune = t;
+    float bms = 1e30f;
+    for (int r = 0; r < reps; ++r) {
+      drop_chunk_graphs(s);
+      if (hipEventRecord(e0, st) != hipSuccess) return fail(ADJ_E_DEVICE, "hipEventRecord failed");
+      adj_solve_info info{};
+      adj_status a = adjoint_solve(s, dL_dq, dL_dv, z, opts, &info, stream);
+      if (a != ADJ_OK) return a;
+      if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
+        return fail(ADJ_E_DEVICE, "event synchronisation failed");
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return fail(ADJ_E_DEVICE, "event timing failed");
+      bms = std::min(bms, ms);
+    }
+    *out_ms = bms;
+    return ADJ_OK;
+  };
+  adj_tuning cur = s->tune;
+  float cur_ms = 0.f;
+  status = time_of(cur, &cur_ms);
+  const int gs[] = {64, 128, 256}, ln[] = {4, 8, 16, 32}, ch[] = {4, 8, 16, 32}, gr[] = {0, 1};
+  for (int sweep = 0; sweep < 2 && status == ADJ_OK; ++sweep) {
+    for (int dim = 0; dim < 4 && status == ADJ_OK; ++dim) {
+      const int* vals = dim == 0 ? gs : dim == 1 ? ln : dim == 2 ? ch : gr;
+      const int nvals = dim == 0 ? 3 : dim == 3 ? 2 : 4;
+      for (int k = 0; k < nvals && status == ADJ_OK; ++k) {
+        adj_tuning t = cur;
+        int* field = dim == 0 ? &t.gs_rows : dim == 1 ? &t.bsr_lanes : dim == 2 ? &t.chunk : &t.graph;
+        if (*field == vals[k]) continue;
+        *field = vals[k];
+        float ms = 0.f;
+        status = time_of(t, &ms);
+        if (status == ADJ_OK && ms < cur_ms) {
+          cur = t;
+          cur_ms = ms;
+        }
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  s->tune = cur;
+  drop_chunk_graphs(s);
+  *best = cur;
+  return status;
 }
 
 extern "C" adj_status adj_profile_begin(adj_scene* s, int32_t kernel) {

@@ -14,6 +14,8 @@
 // preconditioner apply needs one dense matrix-vector product.
 #include "device_common.h"
 
+#include <algorithm>
+
 namespace adj {
 
 __global__ void k_fill_zero(size_t n, double* __restrict__ a) {
@@ -32,23 +34,109 @@ __global__ void k_fill_Y(int ncv, const int* __restrict__ cv, const long long* _
     Y[(size_t)STj[p] * ncv + c] = STx[p];
 }
 
-// D = Y^T Y, 16x16 output tile per 256-thread block, K split over 16 rows.
-__global__ void __launch_bounds__(256) k_syrk(int nv, int ncv, const double* __restrict__ Y,
-                                              double* __restrict__ D) {
-  __shared__ double ta[16][17], tb[16][17];
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-  const int a0 = blockIdx.y * 16, b0 = blockIdx.x * 16;
-  double acc = 0.0;
-  for (int r0 = 0; r0 < nv; r0 += 16) {
-    const int r = r0 + ty;
-    ta[ty][tx] = (r < nv && a0 + tx < ncv) ? Y[(size_t)r * ncv + a0 + tx] : 0.0;
-    tb[ty][tx] = (r < nv && b0 + tx < ncv) ? Y[(size_t)r * ncv + b0 + tx] : 0.0;
+// D = Y^T Y on the matrix cores.  One 256-thread block per 64x64 tile of
+// the lower triangle of D (tile row >= tile column) and per K-slice of the
+// n_v rows of Y; each wavefront owns a 32x32 quarter of the tile as 2x2
+// MFMA 16x16 accumulators.  16-row panels of Y are staged through LDS.
+// FP64 products and sums (v_mfma_f64_16x16x4f64).  D is kept in FP64 in
+// both precision modes: for stiff contacts the Woodbury correction cancels
+// A^{-1} r almost exactly, and FP32 rounding of D would be amplified by the
+// contact-to-elastic stiffness ratio.
+// 16x16x4 operand layout (lane l = 16 kq + i, i < 16, kq < 4): the A operand
+// of lane l is A[i][kq], the B operand B[kq][i]; accumulator value e (0..3)
+// of lane l is C[r][i] with r = kq + 4 e (checked on the device; the f32
+// variant of the instruction uses r = 4 kq + e instead).
+// With ks > 1 K-slices the block writes its partial tile to P[slice], and
+// k_syrk_reduce sums the slices in fixed order; with one slice it writes D.
+// Both triangles of D are written (D is symmetric).
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+template <typename T> struct MfmaAcc;
+template <> struct MfmaAcc<double> {
+  using V = d4;
+  static __device__ __forceinline__ V step(double a, double b, V c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int kq, int e) { return kq + 4 * e; }
+};
+
+constexpr int kSyT = 64;  // output tile edge
+constexpr int kSyK = 16;  // rows of Y per LDS panel
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_syrk_mfma(int nv, int ncv, int rows_per_slice,
+                                                   const double* __restrict__ Y, double* __restrict__ out) {
+  __shared__ T As[kSyK][kSyT + 1];
+  __shared__ T Bs[kSyK][kSyT + 1];
+  // blockIdx.x enumerates lower-triangle tiles: x = ti (ti + 1) / 2 + tj, tj <= ti
+  const int x = blockIdx.x;
+  int ti = (int)((sqrt(8.0 * x + 1.0) - 1.0) * 0.5);
+  while ((ti + 1) * (ti + 2) / 2 <= x) ++ti;
+  while (ti * (ti + 1) / 2 > x) --ti;
+  const int tj = x - ti * (ti + 1) / 2;
+  const int a0 = ti * kSyT, b0 = tj * kSyT;
+  const int r_begin = blockIdx.y * rows_per_slice;
+  const int r_end = min(nv, r_begin + rows_per_slice);
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wa = 32 * (w >> 1), wb = 32 * (w & 1);
+  const int li = lane & 15, lk = lane >> 4;
+  using V = typename MfmaAcc<T>::V;
+  V acc[2][2];
+#pragma unroll
+  for (int p = 0; p < 2; ++p)
+#pragma unroll
+    for (int q = 0; q < 2; ++q) acc[p][q] = V{0, 0, 0, 0};
+  for (int r0 = r_begin; r0 < r_end; r0 += kSyK) {
+#pragma unroll
+    for (int e = 0; e < (kSyK * kSyT) / 256; ++e) {
+      const int idx = tid + 256 * e;
+      const int kr = idx / kSyT, c = idx % kSyT;
+      const int r = r0 + kr;
+      const bool rin = r < r_end;
+      As[kr][c] = (rin && a0 + c < ncv) ? (T)Y[(size_t)r * ncv + a0 + c] : (T)0;
+      Bs[kr][c] = (rin && b0 + c < ncv) ? (T)Y[(size_t)r * ncv + b0 + c] : (T)0;
+    }
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < 16; ++k) acc += ta[k][ty] * tb[k][tx];
+    for (int k4 = 0; k4 < kSyK; k4 += 4) {
+      T av[2], bv[2];
+#pragma unroll
+      for (int p = 0; p < 2; ++p) {
+        av[p] = As[k4 + lk][wa + 16 * p + li];
+        bv[p] = Bs[k4 + lk][wb + 16 * p + li];
+      }
+#pragma unroll
+      for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int q = 0; q < 2; ++q) acc[p][q] = MfmaAcc<T>::step(av[p], bv[q], acc[p][q]);
+    }
     __syncthreads();
   }
-  if (a0 + ty < ncv && b0 + tx < ncv) D[(size_t)(a0 + ty) * ncv + b0 + tx] = acc;
+  double* dst = out + (size_t)blockIdx.y * ncv * ncv;
+#pragma unroll
+  for (int p = 0; p < 2; ++p)
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int i = a0 + wa + 16 * p + MfmaAcc<T>::row(lk, e);
+        const int j = b0 + wb + 16 * q + li;
+        if (i < ncv && j < ncv) {
+          const double v = (double)acc[p][q][e];
+          dst[(size_t)i * ncv + j] = v;
+          if (ti != tj) dst[(size_t)j * ncv + i] = v;
+        }
+      }
+}
+
+// D[i][j] = sum over slices of P[s][i][j] (fixed order), all i, j
+__global__ void k_syrk_reduce(int ncv, int ks, const double* __restrict__ P, double* __restrict__ D) {
+  const size_t n = (size_t)ncv * ncv;
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double a = 0.0;
+  for (int s = 0; s < ks; ++s) a += P[(size_t)s * n + i];
+  D[i] = a;
 }
 
 // Z[v][c] = sum_p S^T[v][p] Y[p][c]  (one block per vertex row)
@@ -67,121 +155,181 @@ __global__ void __launch_bounds__(256) k_spmm_Z(int nv, int ncv, const long long
 
 constexpr int kNB = 32;
 
-// Gauss-Jordan exchange step for the diagonal block k (rows/cols k0..k0+32)
-// of the padded mp x mp matrix (mp a multiple of 32, padding = identity):
-//   P = A_kk^{-1};  B_kk = P;  B_kj = P A_kj;  B_ik = -A_ik P;
-//   B_ij = A_ij - A_ik P A_kj
-// from buffer A into buffer B (ping-pong, so no block reads what another
-// block writes).  After all blocks the last output buffer is the inverse.
-//
-// One block of 256 threads per 32x32 output tile (I, J).  Wavefront 0
-// inverts A_kk in registers: lane c holds column c of [A_kk | I]; pivot
-// rows are found from uniform copies of the pivot column (readlane), so
-// the 32 elimination steps need no LDS round trips.
+// Capacitance inverse by block Gauss-Jordan elimination with 32x32 pivot
+// blocks (partial pivoting inside each block), from buffer A into buffer B
+// per block step (ping-pong, so no block reads what another block writes).
+// After the last step the last output buffer holds the inverse.
 
-__device__ __forceinline__ double readlane_d(double v, int lane) {
-  int lo = __double2loint(v), hi = __double2hiint(v);
-  lo = __builtin_amdgcn_readlane(lo, lane);
-  hi = __builtin_amdgcn_readlane(hi, lane);
-  return __hiloint2double(hi, lo);
-}
-
-// One Gauss-Jordan pivot step (compile-time pivot index P, so every array
-// index below is a constant and the columns stay in registers).
-template <int P>
-__device__ __forceinline__ void gj_pivot(double (&col)[kNB], bool& bad) {
-  double f[kNB];
+// Inverse of the 32x32 pivot block by one wavefront, row per lane: lane r
+// (r < 32) holds row r of A_kk, lane 32 + r row r of the identity.  Step k
+// picks the unused row with the largest |A[r][k]| (argmax by shuffles, lower
+// row on ties), broadcasts that row through LDS and eliminates column k from
+// every other row.  Rows are never swapped: with p_k the row chosen at step
+// k, the eliminated A part is a permutation and row k of the inverse is row
+// p_k of the transformed identity.  The column index is a template
+// parameter, so every register index is static.
+template <int K>
+__device__ __forceinline__ void gj_rows_step(double (&x)[kNB], bool& used, int& step_of_row, bool& bad,
+                                             double* __restrict__ prow) {
+  const int lane = threadIdx.x & 63, r = lane & 31;
+  // pivot column value of this lane's row (the A part lives in lanes < 32)
+  const double ak = __shfl(x[K], r, 64);
+  double key = used ? -1.0 : fabs(ak);
+  int idx = r;
 #pragma unroll
-  for (int i = 0; i < kNB; ++i) f[i] = readlane_d(col[i], P);
-  int idx = P;
-  double best = fabs(f[P]);
-#pragma unroll
-  for (int i = P + 1; i < kNB; ++i)
-    if (fabs(f[i]) > best) {
-      best = fabs(f[i]);
-      idx = i;
-    }
+  for (int o = 16; o > 0; o >>= 1) {
+    const double k2 = __shfl_xor(key, o, 64);
+    const int i2 = __shfl_xor(idx, o, 64);
+    const bool take = (k2 > key) | ((k2 == key) & (i2 < idx));
+    key = take ? k2 : key;
+    idx = take ? i2 : idx;
+  }
+  const int p = __builtin_amdgcn_readfirstlane(idx);
+  const double best = __shfl(key, 0, 64);
   if (!(best > 0.0) || !isfinite(best)) bad = true;
-  const double cp = col[P], fp = f[P];
-  double cs = cp, fs = fp;
+  // broadcast the pivot row: A part to prow[0..31], identity part to prow[32..63]
+  if (r == p) {
 #pragma unroll
-  for (int i = P + 1; i < kNB; ++i)
-    if (i == idx) {
-      cs = col[i];
-      fs = f[i];
-      col[i] = cp;
-      f[i] = fp;
-    }
-  const double inv = 1.0 / fs;
-  col[P] = cs * inv;
+    for (int c = 0; c < kNB; ++c) prow[(lane & 32) + c] = x[c];
+  }
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  const double inv = 1.0 / prow[K];
+  const double* pr = prow + (lane & 32);
+  // pivot row: x <- x / a_pk (= x + (1/a_pk - 1) x, its own row); others:
+  // x <- x - (a_rk / a_pk) pivot row.  One FMA per entry, no divergence.
+  const bool piv = (r == p);
+  const double g = piv ? inv - 1.0 : -ak * inv;
 #pragma unroll
-  for (int i = 0; i < kNB; ++i)
-    if (i != P) col[i] -= f[i] * col[P];
-  if constexpr (P + 1 < kNB) gj_pivot<P + 1>(col, bad);
+  for (int c = 0; c < kNB; ++c) x[c] = fma(g, pr[c], x[c]);
+  if (piv) {
+    used = true;
+    step_of_row = K;
+  }
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  if constexpr (K + 1 < kNB) gj_rows_step<K + 1>(x, used, step_of_row, bad, prow);
 }
 
-__device__ __forceinline__ void invert32_wave(const double* __restrict__ Akk, int mp,
-                                              double (*Ps)[kNB + 1], int* __restrict__ err) {
-  const int lane = threadIdx.x & 63;
-  double col[kNB];
+// P = A_kk^{-1} into Ps (wavefront 0 of the block; prow: 64 doubles of LDS)
+__device__ __forceinline__ void invert32_rows(const double* __restrict__ Akk, int mp, double (*Ps)[kNB + 1],
+                                              double* __restrict__ prow, int* __restrict__ err) {
+  const int lane = threadIdx.x & 63, r = lane & 31;
+  double x[kNB];
+  if (lane < kNB) {
 #pragma unroll
-  for (int i = 0; i < kNB; ++i)
-    col[i] = (lane < kNB) ? Akk[(size_t)i * mp + lane] : ((lane - kNB == i) ? 1.0 : 0.0);
-  bool bad = false;
-  gj_pivot<0>(col, bad);
+    for (int c = 0; c < kNB; ++c) x[c] = Akk[(size_t)r * mp + c];
+  } else {
+#pragma unroll
+    for (int c = 0; c < kNB; ++c) x[c] = (c == r) ? 1.0 : 0.0;
+  }
+  bool used = false, bad = false;
+  int step_of_row = 0;
+  gj_rows_step<0>(x, used, step_of_row, bad, prow);
   if (lane == 0 && bad) err[0] = 2;
   if (lane >= kNB) {
 #pragma unroll
-    for (int i = 0; i < kNB; ++i) Ps[i][lane - kNB] = col[i];
+    for (int c = 0; c < kNB; ++c) Ps[step_of_row][c] = x[c];
   }
 }
 
-__global__ void __launch_bounds__(256) k_gj_step(int mp, int k0, const double* __restrict__ A,
-                                                 double* __restrict__ B, int* __restrict__ err) {
+// Gauss-Jordan block step on the matrix cores.  With the 32 pivot rows and
+// columns at k0 and P = A_kk^{-1}, every output entry is one formula:
+//   B = Ahat - What Rhat,
+//   Ahat = A with the pivot rows and pivot columns set to 0,
+//   What_i = A_ik P (row i outside the pivot rows),   -P_i (pivot row i),
+//   Rhat_j = A_kj (column j outside the pivot columns), e_j (pivot column j),
+// which gives P A_kj in the pivot rows, -A_ik P in the pivot columns, P in
+// the pivot block and A_ij - A_ik P A_kj elsewhere.
+// One 256-thread block per 64x64 output tile (mp a multiple of 64); wave 0
+// inverts A_kk in registers while the other waves stage the panels; the two
+// products (What for the tile rows, then the update) are 16x16x4 FP64 MFMAs
+// with 2x2 (What) and 2x2 (update) accumulator tiles per wave.
+constexpr int kGT = 64;
+
+__global__ void __launch_bounds__(256) k_gj_step_mfma(int mp, int k0, const double* __restrict__ A,
+                                                      double* __restrict__ B, int* __restrict__ err) {
   __shared__ double Ps[kNB][kNB + 1];   // P = A_kk^{-1}
-  __shared__ double Cs[kNB][kNB + 1];   // A_{I,k}
-  __shared__ double Rs[kNB][kNB + 1];   // A_{k,J}
-  __shared__ double Ws[kNB][kNB + 1];   // W = A_{I,k} P
-  const int tid = threadIdx.x;
-  const int I0 = blockIdx.y * kNB, J0 = blockIdx.x * kNB;
-  const bool Ik = (I0 == k0), Jk = (J0 == k0);
-  if (tid < 64) invert32_wave(A + (size_t)k0 * mp + k0, mp, Ps, err);
-  for (int e = tid; e < kNB * kNB; e += 256) {
+  __shared__ double Cs[kGT][kNB + 1];   // A_{I,k} (tile rows, pivot columns)
+  __shared__ double Rs[kNB][kGT + 1];   // Rhat (pivot rows, tile columns)
+  __shared__ double Ws[kGT][kNB + 1];   // -What
+  __shared__ double prow[2 * kNB];      // pivot row broadcast of the block inversion
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int I0 = blockIdx.y * kGT, J0 = blockIdx.x * kGT;
+  const int li = lane & 15, lk = lane >> 4;
+  // output sub-tiles of this wave: rows wr + 16 p, cols wc + 16 q (p, q < 2)
+  const int wr = 32 * (w >> 1), wc = 32 * (w & 1);
+  // accumulators start at Ahat (f64 MFMA result layout: row lk + 4 e, col li)
+  d4 acc[2][2];
+#pragma unroll
+  for (int p = 0; p < 2; ++p)
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int i = I0 + wr + 16 * p + lk + 4 * e;
+        const int j = J0 + wc + 16 * q + li;
+        const bool zero = (i >= k0 && i < k0 + kNB) || (j >= k0 && j < k0 + kNB);
+        acc[p][q][e] = zero ? 0.0 : A[(size_t)i * mp + j];
+      }
+  if (w == 0) invert32_rows(A + (size_t)k0 * mp + k0, mp, Ps, prow, err);
+  for (int e = tid; e < kGT * kNB; e += 256) {
     const int r = e / kNB, c = e % kNB;
     Cs[r][c] = A[(size_t)(I0 + r) * mp + k0 + c];
-    Rs[r][c] = A[(size_t)(k0 + r) * mp + J0 + c];
+  }
+  for (int e = tid; e < kNB * kGT; e += 256) {
+    const int r = e / kGT, c = e % kGT;
+    const int j = J0 + c;
+    Rs[r][c] = (j >= k0 && j < k0 + kNB) ? ((j - k0 == r) ? 1.0 : 0.0) : A[(size_t)(k0 + r) * mp + j];
   }
   __syncthreads();
-  if (!Ik) {
-    for (int e = tid; e < kNB * kNB; e += 256) {
-      const int r = e / kNB, c = e % kNB;
-      double acc = 0.0;
-#pragma unroll 8
-      for (int l = 0; l < kNB; ++l) acc += Cs[r][l] * Ps[l][c];
-      Ws[r][c] = acc;
+  // -What for the 64 tile rows: wave w computes rows 16 w .. 16 w + 15, both
+  // 16-column halves of the 32 pivot columns.
+  {
+    d4 wacc[2];
+    wacc[0] = d4{0, 0, 0, 0};
+    wacc[1] = d4{0, 0, 0, 0};
+#pragma unroll
+    for (int k4 = 0; k4 < kNB; k4 += 4) {
+      const double a = Cs[16 * w + li][k4 + lk];
+#pragma unroll
+      for (int q = 0; q < 2; ++q)
+        wacc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Ps[k4 + lk][16 * q + li], wacc[q], 0, 0, 0);
     }
-    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int r = 16 * w + lk + 4 * e;
+        const int c = 16 * q + li;
+        const int i = I0 + r;
+        Ws[r][c] = (i >= k0 && i < k0 + kNB) ? Ps[i - k0][c] : -wacc[q][e];
+      }
   }
-  for (int e = tid; e < kNB * kNB; e += 256) {
-    const int r = e / kNB, c = e % kNB;
-    double v;
-    if (Ik && Jk) {
-      v = Ps[r][c];
-    } else if (Ik) {
-      double acc = 0.0;
-#pragma unroll 8
-      for (int l = 0; l < kNB; ++l) acc += Ps[r][l] * Rs[l][c];
-      v = acc;
-    } else if (Jk) {
-      v = -Ws[r][c];
-    } else {
-      double acc = 0.0;
-#pragma unroll 8
-      for (int l = 0; l < kNB; ++l) acc += Ws[r][l] * Rs[l][c];
-      v = A[(size_t)(I0 + r) * mp + J0 + c] - acc;
-    }
-    B[(size_t)(I0 + r) * mp + J0 + c] = v;
+  __syncthreads();
+  // update: acc += (-What) Rhat over the 32 pivot indices
+#pragma unroll
+  for (int k4 = 0; k4 < kNB; k4 += 4) {
+    double av[2], bv[2];
+#pragma unroll
+    for (int p = 0; p < 2; ++p) av[p] = Ws[wr + 16 * p + li][k4 + lk];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) bv[q] = Rs[k4 + lk][wc + 16 * q + li];
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+      for (int q = 0; q < 2; ++q) acc[p][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[p], bv[q], acc[p][q], 0, 0, 0);
   }
+#pragma unroll
+  for (int p = 0; p < 2; ++p)
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int i = I0 + wr + 16 * p + lk + 4 * e;
+        const int j = J0 + wc + 16 * q + li;
+        B[(size_t)i * mp + j] = acc[p][q][e];
+      }
 }
 
 // identity padding of rows/cols m..mp-1 of a row-major mp x mp matrix
@@ -198,19 +346,37 @@ void launch_fill_zero(hipStream_t st, size_t n, double* a) {
   k_fill_zero<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(n, a);
 }
 
+// K-slices for the Delassus product: enough blocks to cover the chip
+// (~512) when the tile count is small, each slice at least 256 rows.
+int delassus_slices(int nv, int ncv) {
+  const int nt = (ncv + kSyT - 1) / kSyT;
+  const int tiles = nt * (nt + 1) / 2;
+  int ks = (512 + tiles - 1) / tiles;
+  ks = std::min(ks, std::max(1, nv / 256));
+  return std::max(ks, 1);
+}
+
 void launch_delassus(hipStream_t st, int nv, int ncv, const int* cv, const long long* STp,
-                     const int* STj, const double* STx, double* Y, double* D, double* Z) {
+                     const int* STj, const double* STx, double* Y, double* D, double* Z, double* Pws) {
   if (ncv == 0) return;
   launch_fill_zero(st, (size_t)nv * ncv, Y);
   k_fill_Y<<<ncv, 256, 0, st>>>(ncv, cv, STp, STj, STx, Y);
-  dim3 g((ncv + 15) / 16, (ncv + 15) / 16);
-  k_syrk<<<g, 256, 0, st>>>(nv, ncv, Y, D);
+  const int nt = (ncv + kSyT - 1) / kSyT;
+  const int ks = delassus_slices(nv, ncv);
+  const int rows = (((nv + ks - 1) / ks) + kSyK - 1) / kSyK * kSyK;
+  dim3 g(nt * (nt + 1) / 2, ks);
+  double* out = (ks > 1) ? Pws : D;
+  k_syrk_mfma<double><<<g, 256, 0, st>>>(nv, ncv, rows, Y, out);
+  if (ks > 1) {
+    const size_t n = (size_t)ncv * ncv;
+    k_syrk_reduce<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(ncv, ks, Pws, D);
+  }
   k_spmm_Z<<<nv, 256, 0, st>>>(nv, ncv, STp, STj, STx, Y, Z);
 }
 
 // Inverse of the m x m capacitance held in the top-left of the row-major
-// mp x mp buffer C0 (mp = 32 * ceil(m/32)); returns the buffer (C0 or C1)
-// that holds the inverse.
+// mp x mp buffer C0 (mp a multiple of 64, padding rows and columns set to
+// the identity here); returns the buffer (C0 or C1) holding the inverse.
 double* launch_gauss_jordan(hipStream_t st, int m, int mp, double* C0, double* C1, int* err) {
   if (mp > m) {
     dim3 gpad((mp + 255) / 256, mp);
@@ -220,8 +386,8 @@ double* launch_gauss_jordan(hipStream_t st, int m, int mp, double* C0, double* C
   double* B = C1;
   const int nb = mp / kNB;
   for (int k = 0; k < nb; ++k) {
-    dim3 g(nb, nb);
-    k_gj_step<<<g, 256, 0, st>>>(mp, k * kNB, A, B, err);
+    dim3 g(mp / kGT, mp / kGT);
+    k_gj_step_mfma<<<g, 256, 0, st>>>(mp, k * kNB, A, B, err);
     double* t = A;
     A = B;
     B = t;

@@ -210,9 +210,9 @@ __global__ void __launch_bounds__(256) k_wb_correct(int nv, int ncv, const int* 
   }
 }
 
-// w = Acal^T x, block-sparse 3x3; 16 lanes per block row.  Output to
-// outbase + (j+1)*stride when state is given.
-template <class MT>
+// w = Acal^T x, block-sparse 3x3; LANES lanes per block row (256 / LANES
+// rows per block).  Output to outbase + (j+1)*stride when state is given.
+template <class MT, int LANES>
 __global__ void __launch_bounds__(256) k_bsr_spmv(int nv, const int* __restrict__ rowptr,
                                                   const int* __restrict__ col,
                                                   const MT* __restrict__ val,
@@ -220,11 +220,11 @@ __global__ void __launch_bounds__(256) k_bsr_spmv(int nv, const int* __restrict_
                                                   double* __restrict__ outbase, long long stride,
                                                   const GmresState* __restrict__ st) {
   if (gm_inactive(st)) return;
-  const int sub = threadIdx.x & 15;
-  const int row = blockIdx.x * (blockDim.x / 16) + threadIdx.x / 16;
+  const int sub = threadIdx.x & (LANES - 1);
+  const int row = blockIdx.x * (blockDim.x / LANES) + threadIdx.x / LANES;
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
   if (row < nv) {
-    for (int p = rowptr[row] + sub; p < rowptr[row + 1]; p += 16) {
+    for (int p = rowptr[row] + sub; p < rowptr[row + 1]; p += LANES) {
       const MT* b = val + 9 * (size_t)p;
       const int c = col[p];
       const double x0 = x[3 * c], x1 = x[3 * c + 1], x2 = x[3 * c + 2];
@@ -233,9 +233,9 @@ __global__ void __launch_bounds__(256) k_bsr_spmv(int nv, const int* __restrict_
       a2 += (double)b[6] * x0 + (double)b[7] * x1 + (double)b[8] * x2;
     }
   }
-  a0 = group_sum<16>(a0);
-  a1 = group_sum<16>(a1);
-  a2 = group_sum<16>(a2);
+  a0 = group_sum<LANES>(a0);
+  a1 = group_sum<LANES>(a1);
+  a2 = group_sum<LANES>(a2);
   if (row < nv && sub == 0) {
     double* out = outbase + (st ? (long long)(st->j + 1) * stride : 0);
     out[3 * row] = a0;
@@ -244,11 +244,13 @@ __global__ void __launch_bounds__(256) k_bsr_spmv(int nv, const int* __restrict_
   }
 }
 
-constexpr int kRowsPerBlock = 256;
+// Gram-Schmidt kernels work on `rpb` consecutive rows per 256-thread block
+// (rpb = 64, 128 or 256, a launch parameter): each row is shared by
+// T = 256 / rpb threads that split the basis index range.
 
 // CGS pass 1: h_i = scale_i * (Vt_i . w), i <= j, with w = Vt_{j+1}.
 // Per-block partials; the last block reduces into hbuf.
-__global__ void __launch_bounds__(256) k_gm_dots(long long n, const double* __restrict__ Vt,
+__global__ void __launch_bounds__(256) k_gm_dots(long long n, int rpb, const double* __restrict__ Vt,
                                                  long long stride, const double* __restrict__ scale,
                                                  GmresState* __restrict__ st,
                                                  double* __restrict__ partial, unsigned* counter,
@@ -257,12 +259,12 @@ __global__ void __launch_bounds__(256) k_gm_dots(long long n, const double* __re
   __shared__ bool is_last;
   const int j = st->j;
   const double* w = Vt + (long long)(j + 1) * stride;
-  const long long r0 = (long long)blockIdx.x * kRowsPerBlock;
+  const long long r0 = (long long)blockIdx.x * rpb;
   const int lane = threadIdx.x & 63, wid = threadIdx.x / 64, nw = blockDim.x / 64;
   for (int i = wid; i <= j; i += nw) {
     const double* vi = Vt + (long long)i * stride;
     double acc = 0.0;
-    for (long long r = r0 + lane; r < r0 + kRowsPerBlock && r < n; r += 64) acc += vi[r] * w[r];
+    for (long long r = r0 + lane; r < r0 + rpb && r < n; r += 64) acc += vi[r] * w[r];
     acc = wave_sum(acc);
     if (lane == 0) partial[(size_t)blockIdx.x * 130 + i] = acc;
   }
@@ -279,7 +281,7 @@ __global__ void __launch_bounds__(256) k_gm_dots(long long n, const double* __re
 // updated w (second pass) or its squared norm (final pass).
 // mode 0: second pass -> h2 into hbuf[130 + i]; column of H gets h + h2 later
 // mode 1: final update with h2, norm, Givens rotation, bookkeeping
-__global__ void __launch_bounds__(256) k_gm_update(long long n, double* __restrict__ Vt,
+__global__ void __launch_bounds__(256) k_gm_update(long long n, int rpb, double* __restrict__ Vt,
                                                    long long stride, double* __restrict__ scale,
                                                    GmresState* __restrict__ st,
                                                    double* __restrict__ partial, unsigned* counter,
@@ -289,45 +291,56 @@ __global__ void __launch_bounds__(256) k_gm_update(long long n, double* __restri
   if (st->active == 0) return;
   __shared__ bool is_last;
   __shared__ double lds[32];
+  __shared__ double red[256];
+  __shared__ double hs[130];
   const int j = st->j;
   double* w = Vt + (long long)(j + 1) * stride;
   const double* h = hbuf + (mode == 0 ? 0 : 130);
-  const long long r0 = (long long)blockIdx.x * kRowsPerBlock;
-  for (long long r = r0 + threadIdx.x; r < r0 + kRowsPerBlock && r < n; r += blockDim.x) {
-    double acc = w[r];
-    for (int i = 0; i <= j; ++i) acc -= h[i] * scale[i] * Vt[(long long)i * stride + r];
-    w[r] = acc;
+  for (int i = threadIdx.x; i <= j; i += blockDim.x) hs[i] = h[i] * scale[i];
+  __syncthreads();
+  const long long r0 = (long long)blockIdx.x * rpb;
+  const int T = blockDim.x / rpb;              // threads per row
+  const int rl = threadIdx.x % rpb, part = threadIdx.x / rpb;
+  const long long r = r0 + rl;
+  double acc = 0.0;
+  if (r < n)
+    for (int i = part; i <= j; i += T) acc += hs[i] * Vt[(long long)i * stride + r];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  if (part == 0 && r < n) {
+    double a = red[rl];
+    for (int t = 1; t < T; ++t) a += red[rl + t * rpb];
+    w[r] -= a;
   }
   __syncthreads();
   const int lane = threadIdx.x & 63, wid = threadIdx.x / 64, nw = blockDim.x / 64;
   if (mode == 0) {
     for (int i = wid; i <= j; i += nw) {
       const double* vi = Vt + (long long)i * stride;
-      double acc = 0.0;
-      for (long long r = r0 + lane; r < r0 + kRowsPerBlock && r < n; r += 64) acc += vi[r] * w[r];
-      acc = wave_sum(acc);
-      if (lane == 0) partial[(size_t)blockIdx.x * 130 + i] = acc;
+      double d = 0.0;
+      for (long long rr = r0 + lane; rr < r0 + rpb && rr < n; rr += 64) d += vi[rr] * w[rr];
+      d = wave_sum(d);
+      if (lane == 0) partial[(size_t)blockIdx.x * 130 + i] = d;
     }
   } else {
-    double acc = 0.0;
-    for (long long r = r0 + threadIdx.x; r < r0 + kRowsPerBlock && r < n; r += blockDim.x)
-      acc += w[r] * w[r];
-    acc = block_sum(acc, lds);
-    if (threadIdx.x == 0) partial[(size_t)blockIdx.x * 130] = acc;
+    double d = 0.0;
+    for (long long rr = r0 + threadIdx.x; rr < r0 + rpb && rr < n; rr += blockDim.x) d += w[rr] * w[rr];
+    d = block_sum(d, lds);
+    if (threadIdx.x == 0) partial[(size_t)blockIdx.x * 130] = d;
   }
   if (!last_block(counter, &is_last)) return;
   if (mode == 0) {
     for (int i = threadIdx.x; i <= j; i += blockDim.x) {
-      double s = 0.0;
-      for (int b = 0; b < (int)gridDim.x; ++b) s += partial[(size_t)b * 130 + i];
-      hbuf[130 + i] = scale[i] * s;
+      double sum = 0.0;
+      for (int b = 0; b < (int)gridDim.x; ++b) sum += partial[(size_t)b * 130 + i];
+      hbuf[130 + i] = scale[i] * sum;
     }
     return;
   }
   if (threadIdx.x != 0) return;
-  double s = 0.0;
-  for (int b = 0; b < (int)gridDim.x; ++b) s += partial[(size_t)b * 130];
-  const double nrm = sqrt(s);
+  double sum = 0.0;
+  for (int b = 0; b < (int)gridDim.x; ++b) sum += partial[(size_t)b * 130];
+  const double nrm = sqrt(sum);
   const int R = st->restart;
   double* Hc = H + (size_t)j * (R + 1);  // column j, column-major (R+1) x R
   for (int i = 0; i <= j; ++i) Hc[i] = hbuf[i] + hbuf[130 + i];
@@ -352,19 +365,30 @@ __global__ void __launch_bounds__(256) k_gm_update(long long n, double* __restri
   if (st->res <= st->tol || j + 1 >= R || !(nrm > 0.0) || !isfinite(st->res)) st->active = 0;
 }
 
-// y_i = scale_i * (H^{-1} g)_i for the completed iterations (upper triangular).
-__global__ void k_gm_solve_small(const GmresState* __restrict__ st, const double* __restrict__ H,
-                                 const double* __restrict__ gvec, const double* __restrict__ scale,
-                                 double* __restrict__ coef) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// y_i = scale_i * (H^{-1} g)_i for the completed iterations (upper
+// triangular), by column-oriented back substitution in one wavefront:
+// step l divides y_l, then every lane i < l subtracts H[i][l] y_l (column l
+// of the column-major H is contiguous, so the reads coalesce).
+__global__ void __launch_bounds__(64) k_gm_solve_small(const GmresState* __restrict__ st,
+                                                       const double* __restrict__ H,
+                                                       const double* __restrict__ gvec,
+                                                       const double* __restrict__ scale,
+                                                       double* __restrict__ coef) {
+  __shared__ double y[130];
   const int k = st->j, R = st->restart;
-  for (int i = k - 1; i >= 0; --i) {
-    double s = gvec[i];
-    for (int l = i + 1; l < k; ++l) s -= H[(size_t)l * (R + 1) + i] * coef[l];
-    coef[i] = s / H[(size_t)i * (R + 1) + i];
+  const int t = threadIdx.x;
+  for (int i = t; i < k; i += 64) y[i] = gvec[i];
+  __syncthreads();
+  for (int l = k - 1; l >= 0; --l) {
+    const double* Hl = H + (size_t)l * (R + 1);
+    const double yl = y[l] / Hl[l];
+    __syncthreads();
+    for (int i = t; i < l; i += 64) y[i] -= Hl[i] * yl;
+    if (t == 0) y[l] = yl;
+    __syncthreads();
   }
-  for (int i = 0; i < k; ++i) coef[i] *= scale[i];
-  coef[128] = (double)k;
+  for (int i = t; i < k; i += 64) coef[i] = y[i] * scale[i];
+  if (t == 0) coef[128] = (double)k;
 }
 
 // out = sum_{i<k} coef_i Vt_i
@@ -417,6 +441,131 @@ __global__ void __launch_bounds__(256) k_residual(long long n, const double* __r
   gvec[0] = nrm;
 }
 
+// Preconditioned conjugate gradients for the symmetric case (no frictional
+// contact, or mu = 0: Acal^T is symmetric positive definite and so is the
+// Woodbury preconditioner).  Device-side scalars sc = {rz, alpha, beta, pAp};
+// the GmresState carries the iteration count (j), the active flag, the
+// absolute tolerance and the recurrence residual norm (res).
+
+// alpha = rz / (p . w): per-block partials, the last block divides.
+__global__ void __launch_bounds__(256) k_pcg_alpha(long long n, const double* __restrict__ p,
+                                                   const double* __restrict__ w,
+                                                   double* __restrict__ partial, unsigned* counter,
+                                                   GmresState* __restrict__ st, double* __restrict__ sc) {
+  if (st->active == 0) return;
+  __shared__ double lds[32];
+  __shared__ bool is_last;
+  double acc = 0.0;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    acc += p[i] * w[i];
+  acc = block_sum(acc, lds);
+  if (threadIdx.x == 0) partial[blockIdx.x] = acc;
+  if (!last_block(counter, &is_last)) return;
+  if (threadIdx.x != 0) return;
+  double s = 0.0;
+  for (int b = 0; b < (int)gridDim.x; ++b) s += partial[b];
+  sc[3] = s;
+  if (!(s > 0.0) || !isfinite(s)) {  // breakdown: not positive definite
+    st->active = 0;
+    sc[1] = 0.0;
+    return;
+  }
+  sc[1] = sc[0] / s;
+}
+
+// x += alpha p; r -= alpha w; |r|^2 -> res; stop at res <= tol or after
+// `limit` iterations.
+__global__ void __launch_bounds__(256) k_pcg_xr(long long n, double* __restrict__ x, double* __restrict__ r,
+                                                const double* __restrict__ p, const double* __restrict__ w,
+                                                double* __restrict__ partial, unsigned* counter,
+                                                GmresState* __restrict__ st, const double* __restrict__ sc) {
+  if (st->active == 0) return;
+  __shared__ double lds[32];
+  __shared__ bool is_last;
+  const double alpha = sc[1];
+  double acc = 0.0;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    x[i] += alpha * p[i];
+    const double v = r[i] - alpha * w[i];
+    r[i] = v;
+    acc += v * v;
+  }
+  acc = block_sum(acc, lds);
+  if (threadIdx.x == 0) partial[blockIdx.x] = acc;
+  if (!last_block(counter, &is_last)) return;
+  if (threadIdx.x != 0) return;
+  double s = 0.0;
+  for (int b = 0; b < (int)gridDim.x; ++b) s += partial[b];
+  st->res = sqrt(s);
+  st->j += 1;
+  if (st->res <= st->tol || st->j >= st->restart || !isfinite(st->res)) st->active = 0;
+}
+
+// beta = (r . z) / rz_old (first = 1: beta = 0); then p = z + beta p is
+// done by k_pcg_p.
+__global__ void __launch_bounds__(256) k_pcg_beta(long long n, const double* __restrict__ r,
+                                                  const double* __restrict__ z,
+                                                  double* __restrict__ partial, unsigned* counter,
+                                                  GmresState* __restrict__ st, double* __restrict__ sc,
+                                                  int first) {
+  if (st->active == 0) return;
+  __shared__ double lds[32];
+  __shared__ bool is_last;
+  double acc = 0.0;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    acc += r[i] * z[i];
+  acc = block_sum(acc, lds);
+  if (threadIdx.x == 0) partial[blockIdx.x] = acc;
+  if (!last_block(counter, &is_last)) return;
+  if (threadIdx.x != 0) return;
+  double s = 0.0;
+  for (int b = 0; b < (int)gridDim.x; ++b) s += partial[b];
+  if (!isfinite(s)) {
+    st->active = 0;
+    return;
+  }
+  sc[2] = first ? 0.0 : s / sc[0];
+  sc[0] = s;
+}
+
+__global__ void k_pcg_p(long long n, const double* __restrict__ z, double* __restrict__ p,
+                        const GmresState* __restrict__ st, const double* __restrict__ sc) {
+  if (st->active == 0) return;
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  p[i] = z[i] + sc[2] * p[i];
+}
+
+// r = b - r (r holds Acal^T x on entry); |r| -> st->rnorm and st->res;
+// j = 0; active = (|r| > tol).
+__global__ void __launch_bounds__(256) k_pcg_residual(long long n, const double* __restrict__ b,
+                                                      double* __restrict__ r, double* __restrict__ partial,
+                                                      unsigned* counter, GmresState* __restrict__ st) {
+  __shared__ double lds[32];
+  __shared__ bool is_last;
+  double acc = 0.0;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    const double v = b[i] - r[i];
+    r[i] = v;
+    acc += v * v;
+  }
+  acc = block_sum(acc, lds);
+  if (threadIdx.x == 0) partial[blockIdx.x] = acc;
+  if (!last_block(counter, &is_last)) return;
+  if (threadIdx.x != 0) return;
+  double s = 0.0;
+  for (int b2 = 0; b2 < (int)gridDim.x; ++b2) s += partial[b2];
+  const double nrm = sqrt(s);
+  st->rnorm = nrm;
+  st->res = nrm;
+  st->j = 0;
+  st->active = (nrm > st->tol) ? 1 : 0;
+}
+
 // host-side launchers ------------------------------------------------------
 
 void launch_spmv_csr3(hipStream_t s, int nrows, const long long* rp, const int* cj, const double* cx,
@@ -456,11 +605,6 @@ void launch_wb_gather(hipStream_t s, int m, int mp, const int* row_c, const int*
                       const double* Q, const double* X, const double* u, const GmresState* st, double* t) {
   wb_gather_impl(s, m, mp, row_c, row_i, vid, Q, X, u, st, t);
 }
-void launch_wb_gather(hipStream_t s, int m, int mp, const int* row_c, const int* row_i, const int* vid,
-                      const double* Q, const float* X, const double* u, const GmresState* st, double* t) {
-  wb_gather_impl(s, m, mp, row_c, row_i, vid, Q, X, u, st, t);
-}
-
 template <class MT>
 static void wb_correct_impl(hipStream_t s, int nv, int ncv, const int* cv_ptr, const int* c_row0,
                             const int* c_nrow, const double* Q, const double* t, const MT* Z, double h2,
@@ -474,19 +618,25 @@ void launch_wb_correct(hipStream_t s, int nv, int ncv, const int* cv_ptr, const 
                        const GmresState* st, double* y) {
   wb_correct_impl(s, nv, ncv, cv_ptr, c_row0, c_nrow, Q, t, Z, h2, u, st, y);
 }
-void launch_wb_correct(hipStream_t s, int nv, int ncv, const int* cv_ptr, const int* c_row0, const int* c_nrow,
-                       const double* Q, const double* t, const float* Z, double h2, const double* u,
-                       const GmresState* st, double* y) {
-  wb_correct_impl(s, nv, ncv, cv_ptr, c_row0, c_nrow, Q, t, Z, h2, u, st, y);
-}
-
-void launch_bsr_spmv(hipStream_t s, int nv, const int* rowptr, const int* col, const double* val,
+template <class MT>
+static void bsr_impl(hipStream_t s, int lanes, int nv, const int* rowptr, const int* col, const MT* val,
                      const double* x, double* outbase, long long stride, const GmresState* st) {
-  k_bsr_spmv<double><<<(nv + 15) / 16, 256, 0, s>>>(nv, rowptr, col, val, x, outbase, stride, st);
+  const int rows = 256 / lanes;
+  const unsigned g = (unsigned)((nv + rows - 1) / rows);
+  switch (lanes) {
+    case 4: k_bsr_spmv<MT, 4><<<g, 256, 0, s>>>(nv, rowptr, col, val, x, outbase, stride, st); break;
+    case 8: k_bsr_spmv<MT, 8><<<g, 256, 0, s>>>(nv, rowptr, col, val, x, outbase, stride, st); break;
+    case 32: k_bsr_spmv<MT, 32><<<g, 256, 0, s>>>(nv, rowptr, col, val, x, outbase, stride, st); break;
+    default: k_bsr_spmv<MT, 16><<<g, 256, 0, s>>>(nv, rowptr, col, val, x, outbase, stride, st); break;
+  }
 }
-void launch_bsr_spmv(hipStream_t s, int nv, const int* rowptr, const int* col, const float* val,
+void launch_bsr_spmv(hipStream_t s, int lanes, int nv, const int* rowptr, const int* col, const double* val,
                      const double* x, double* outbase, long long stride, const GmresState* st) {
-  k_bsr_spmv<float><<<(nv + 15) / 16, 256, 0, s>>>(nv, rowptr, col, val, x, outbase, stride, st);
+  bsr_impl(s, lanes, nv, rowptr, col, val, x, outbase, stride, st);
+}
+void launch_bsr_spmv(hipStream_t s, int lanes, int nv, const int* rowptr, const int* col, const float* val,
+                     const double* x, double* outbase, long long stride, const GmresState* st) {
+  bsr_impl(s, lanes, nv, rowptr, col, val, x, outbase, stride, st);
 }
 
 __global__ void k_to_f32(long long n, const double* __restrict__ a, float* __restrict__ out) {
@@ -498,18 +648,18 @@ void launch_to_f32(hipStream_t s, long long n, const double* a, float* out) {
   k_to_f32<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, a, out);
 }
 
-int gm_blocks(long long n) { return (int)((n + kRowsPerBlock - 1) / kRowsPerBlock); }
+int gm_blocks(long long n, int rpb) { return (int)((n + rpb - 1) / rpb); }
 
-void launch_gm_dots(hipStream_t s, long long n, const double* Vt, long long stride, const double* scale,
+void launch_gm_dots(hipStream_t s, long long n, int rpb, const double* Vt, long long stride, const double* scale,
                     GmresState* st, double* partial, unsigned* counter, double* hbuf) {
-  k_gm_dots<<<gm_blocks(n), 256, 0, s>>>(n, Vt, stride, scale, st, partial, counter, hbuf);
+  k_gm_dots<<<gm_blocks(n, rpb), 256, 0, s>>>(n, rpb, Vt, stride, scale, st, partial, counter, hbuf);
 }
 
-void launch_gm_update(hipStream_t s, long long n, double* Vt, long long stride, double* scale,
+void launch_gm_update(hipStream_t s, long long n, int rpb, double* Vt, long long stride, double* scale,
                       GmresState* st, double* partial, unsigned* counter, double* hbuf, double* H,
                       double* cs, double* sn, double* gvec, int mode) {
-  k_gm_update<<<gm_blocks(n), 256, 0, s>>>(n, Vt, stride, scale, st, partial, counter, hbuf, H, cs, sn,
-                                           gvec, mode);
+  k_gm_update<<<gm_blocks(n, rpb), 256, 0, s>>>(n, rpb, Vt, stride, scale, st, partial, counter, hbuf, H, cs,
+                                                sn, gvec, mode);
 }
 
 void launch_gm_finish(hipStream_t s, long long n, const GmresState* st, const double* H,
@@ -528,6 +678,32 @@ void launch_residual(hipStream_t s, long long n, const double* b, double* r, dou
   int blocks = (int)((n + 255) / 256);
   if (blocks > 256) blocks = 256;
   k_residual<<<blocks, 256, 0, s>>>(n, b, r, v0, partial, counter, st, scale, gvec);
+}
+
+static int pcg_blocks(long long n) {
+  long long b = (n + 255) / 256;
+  return (int)(b < 512 ? b : 512);
+}
+
+void launch_pcg_alpha(hipStream_t s, long long n, const double* p, const double* w, double* partial,
+                      unsigned* counter, GmresState* st, double* sc) {
+  k_pcg_alpha<<<pcg_blocks(n), 256, 0, s>>>(n, p, w, partial, counter, st, sc);
+}
+void launch_pcg_xr(hipStream_t s, long long n, double* x, double* r, const double* p, const double* w,
+                   double* partial, unsigned* counter, GmresState* st, const double* sc) {
+  k_pcg_xr<<<pcg_blocks(n), 256, 0, s>>>(n, x, r, p, w, partial, counter, st, sc);
+}
+void launch_pcg_beta(hipStream_t s, long long n, const double* r, const double* z, double* partial,
+                     unsigned* counter, GmresState* st, double* sc, int first) {
+  k_pcg_beta<<<pcg_blocks(n), 256, 0, s>>>(n, r, z, partial, counter, st, sc, first);
+}
+void launch_pcg_p(hipStream_t s, long long n, const double* z, double* p, const GmresState* st,
+                  const double* sc) {
+  k_pcg_p<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, z, p, st, sc);
+}
+void launch_pcg_residual(hipStream_t s, long long n, const double* b, double* r, double* partial,
+                         unsigned* counter, GmresState* st) {
+  k_pcg_residual<<<pcg_blocks(n), 256, 0, s>>>(n, b, r, partial, counter, st);
 }
 
 }  // namespace adj

@@ -21,12 +21,13 @@ STATUS = {0: "ADJ_OK", -1: "ADJ_E_ARG", -2: "ADJ_E_SHAPE", -3: "ADJ_E_INVERTED",
           -4: "ADJ_E_NOCONV", -5: "ADJ_E_SINGULAR", -6: "ADJ_E_DEVICE", -7: "ADJ_E_OOM",
           -8: "ADJ_E_NOTIMPL"}
 ADJ_FP64, ADJ_MIXED = 0, 1
+ADJ_AUTO, ADJ_GMRES, ADJ_PCG = 0, 1, 2
 
 # names declared in include/adjoint.h
 EXPORTS = ("adj_scene_create", "adj_scene_destroy", "adjoint_setup", "adjoint_solve", "vjp_params",
            "sim_forward_step", "adj_scene_info", "adj_check_status", "adj_debug_export",
            "adj_profile_begin", "adj_profile_end", "adj_forward_stats", "adj_forward_reset",
-           "adj_last_error")
+           "adj_set_tuning", "adj_get_tuning", "adj_autotune", "adj_last_error")
 KERNELS = {"S": 0, "ST": 1, "capinv": 2, "Z": 3, "bsr": 4, "tet": 5, "assemble": 6, "gj": 7,
            "gs_dots": 8, "gs_update": 9}
 
@@ -53,12 +54,21 @@ class ContactState(C.Structure):
 
 class SolveOpts(C.Structure):
     _fields_ = [("rtol", C.c_double), ("maxit", C.c_int32), ("restart", C.c_int32),
-                ("max_refine", C.c_int32), ("prec", C.c_int32), ("reuse_delassus", C.c_int32)]
+                ("max_refine", C.c_int32), ("prec", C.c_int32), ("reuse_delassus", C.c_int32),
+                ("method", C.c_int32)]
 
 
 class SolveInfo(C.Structure):
     _fields_ = [("iters", C.c_int32), ("refine_steps", C.c_int32), ("n_contacts", C.c_int32),
-                ("m_rows", C.c_int32), ("relres", C.c_double), ("delassus_rebuilt", C.c_int32)]
+                ("m_rows", C.c_int32), ("relres", C.c_double), ("delassus_rebuilt", C.c_int32),
+                ("method", C.c_int32)]
+
+
+class Tuning(C.Structure):
+    _fields_ = [("gs_rows", C.c_int32), ("bsr_lanes", C.c_int32), ("chunk", C.c_int32), ("graph", C.c_int32)]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
 
 
 _lib = None
@@ -87,6 +97,9 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.adj_forward_stats.argtypes = [vp, C.POINTER(C.c_double)]
     lib.adj_forward_reset.argtypes = [vp]
     lib.adj_profile_end.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+    lib.adj_set_tuning.argtypes = [vp, C.POINTER(Tuning)]
+    lib.adj_get_tuning.argtypes = [vp, C.POINTER(Tuning)]
+    lib.adj_autotune.argtypes = [vp, vp, vp, vp, C.POINTER(SolveOpts), C.c_int32, C.POINTER(Tuning), vp]
     for name in EXPORTS:
         if name != "adj_last_error":
             getattr(lib, name).restype = C.c_int
@@ -172,10 +185,11 @@ def make_contact_state(n, vid, fric, frame, delta, lam, mu, d_n=None, d_f=None, 
     return cs
 
 
-def solve_opts(rtol=1e-8, maxit=2000, restart=64, prec=ADJ_FP64, reuse_delassus=1, max_refine=4):
+def solve_opts(rtol=1e-8, maxit=2000, restart=64, prec=ADJ_FP64, reuse_delassus=1, max_refine=4,
+               method=ADJ_AUTO):
     o = SolveOpts()
     o.rtol, o.maxit, o.restart, o.max_refine = float(rtol), int(maxit), int(restart), int(max_refine)
-    o.prec, o.reuse_delassus = int(prec), int(reuse_delassus)
+    o.prec, o.reuse_delassus, o.method = int(prec), int(reuse_delassus), int(method)
     return o
 
 
@@ -269,3 +283,22 @@ class ContactBuffers:
         c.state = make_contact_state(self.state.n_contacts, c.vid, c.fric, c.frame, c.delta, c.lam,
                                      self.state.mu, c.d_n, c.d_f, capacity=self.state.capacity)
         return c
+
+
+def set_tuning(scene: Scene, gs_rows=64, bsr_lanes=16, chunk=8, graph=0):
+    t = Tuning(int(gs_rows), int(bsr_lanes), int(chunk), int(graph))
+    check(load().adj_set_tuning(scene.handle, C.byref(t)))
+
+
+def get_tuning(scene: Scene) -> dict:
+    t = Tuning()
+    check(load().adj_get_tuning(scene.handle, C.byref(t)))
+    return t.as_dict()
+
+
+def autotune(scene: Scene, dL_dq, dL_dv, z, opts: SolveOpts, reps=3, stream=None) -> dict:
+    """Time candidate launch shapes on the set-up scene and keep the fastest."""
+    t = Tuning()
+    check(load().adj_autotune(scene.handle, _ptr(dL_dq), _ptr(dL_dv), _ptr(z), C.byref(opts), int(reps),
+                              C.byref(t), _stream(stream)))
+    return t.as_dict()

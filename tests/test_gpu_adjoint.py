@@ -115,8 +115,8 @@ def test_beam_adjoint_matches_oracle(mu, t):
 
 @pytest.mark.parametrize("mu,t", [(1.0, 3), (0.1, 2), (0.4, 3)])
 def test_beam_mixed_precision_matches_oracle(mu, t):
-    """ADJ_MIXED (FP32-stored S, Z, capacitance inverse and block matrix in
-    the inner GMRES; FP64 Gram-Schmidt, FP64 refinement residual) against
+    """ADJ_MIXED (FP32-stored S, S^T and block matrix in the inner GMRES;
+    FP64 Woodbury factors, Gram-Schmidt and refinement residual) against
     the FP64 oracle: 1e-4 relative on every output (the mixed-precision
     target), at the benchmark tolerance rtol 1e-8."""
     torch = torch_cuda()
@@ -152,3 +152,91 @@ def test_beam_mixed_precision_matches_oracle(mu, t):
     g = g3.cpu().numpy()
     assert abs(g[0] - ref.dE) <= 1e-4 * np.abs(ref.dE_tet).sum()
     assert abs(g[1] - ref.dnu) <= 1e-4 * np.abs(ref.dnu_tet).sum()
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("mixed", 1e-12)])
+def test_beam_delassus_matches_oracle_inverse(prec, tol):
+    """a4: the Delassus matrix of the contact vertices from the FP64 matrix
+    cores equals the rows and columns of A^{-1} at those vertices (x
+    components of the oracle's 3n x 3n A, which is I3-structured), solved
+    directly by sparse LU.  Mixed precision keeps D in FP64 as well."""
+    torch = torch_cuda()
+    import scipy.sparse.linalg as spla
+    from paper_2603_16478_amd import native
+    from oracle.rollout import scene_disc
+    from synth import beam_scene
+    from gpu_helpers import contact_tensors
+    q, rec = _beam_state(1.0, 3)
+    spec = beam_scene(mu=1.0)
+    disc = scene_disc(spec)
+    cv = np.unique(rec.contacts.vid)
+    lu = spla.splu(disc.A.tocsc())
+    rhs = np.zeros((disc.A.shape[0], cv.size))
+    rhs[3 * cv, np.arange(cv.size)] = 1.0
+    ref = lu.solve(rhs)[3 * cv, :]
+    scene = make_scene(spec, max_contacts=rec.contacts.n)
+    tens = contact_tensors(rec)
+    cs = native.make_contact_state(rec.contacts.n, tens["vid"], tens["fric"], tens["frame"], tens["delta"],
+                                   tens["lam"], rec.mu)
+    opts = native.solve_opts(rtol=1e-8, maxit=100, restart=64,
+                             prec=native.ADJ_MIXED if prec == "mixed" else native.ADJ_FP64)
+    native.adjoint_setup(scene, cs, torch.tensor(q, device="cuda"), opts)
+    native.check_status(scene)
+    D = native.debug_export(scene, 4).reshape(cv.size, cv.size)
+    err = np.abs(D - ref).max() / np.abs(ref).max()
+    print(f"Delassus {prec}: n_cv {cv.size}, rel err {err:.2e}, symmetric {np.array_equal(D, D.T)}", flush=True)
+    assert np.array_equal(D, D.T)
+    assert err <= tol
+
+
+@pytest.mark.parametrize("which", ["tiny", "beam"])
+def test_capacitance_inverse_matches_oracle(which):
+    """a4: the Gauss-Jordan inverse X of the transposed-system capacitance
+    K^{-T} + h^2 H A^{-1} H^T (Sec. 5.4) against the oracle's capacitance:
+    X C = I on the rows the oracle keeps (rows with a zero K entry are
+    decoupled on the GPU and dropped by the oracle).  The beam's 891 rows pad
+    to 896 (matrix-core step), the tiny cube's to 128."""
+    torch = torch_cuda()
+    import scipy.sparse.linalg as spla
+    from paper_2603_16478_amd import native
+    from oracle import contact as ct
+    from oracle.woodbury import contact_rows
+    from gpu_helpers import contact_tensors
+    if which == "tiny":
+        spec, ro = _tiny(20)
+        rec, q, disc = ro.records[12], ro.qs[13], ro.disc
+    else:
+        from oracle.rollout import scene_disc
+        from synth import beam_scene
+        q, rec = _beam_state(1.0, 3)
+        spec = beam_scene(mu=1.0)
+        disc = scene_disc(spec)
+    blocks = ct.contact_blocks(rec.contacts, rec.delta, rec.lam, rec.mu, spec.eps)
+    H, K = contact_rows(disc.n_verts, rec.contacts, blocks)
+    AinvHt = spla.splu(disc.A.tocsc()).solve(H.T)
+    Cref = np.linalg.inv(K).T + spec.h ** 2 * (H @ AinvHt)
+    keep = []
+    row = 0
+    for c in range(rec.contacts.n):
+        if not rec.contacts.fric[c]:
+            keep.append(row)
+            row += 1
+            continue
+        keep += [row, row + 1] + ([row + 2] if blocks.Khat[c][2, 2] != 0.0 else [])
+        row += 3
+    m = row
+    scene = make_scene(spec, max_contacts=rec.contacts.n)
+    tens = contact_tensors(rec)
+    cs = native.make_contact_state(rec.contacts.n, tens["vid"], tens["fric"], tens["frame"], tens["delta"],
+                                   tens["lam"], rec.mu)
+    opts = native.solve_opts(rtol=1e-8, maxit=100, restart=64)
+    native.adjoint_setup(scene, cs, torch.tensor(q, device="cuda"), opts)
+    native.check_status(scene)
+    X = native.debug_export(scene, 3)
+    mp = int(round(np.sqrt(X.size)))
+    assert mp % 64 == 0 and mp >= m
+    X = X.reshape(mp, mp)[np.ix_(keep, keep)]
+    res = np.abs(X @ Cref - np.eye(len(keep))).max()
+    print(f"capacitance {which}: m {m} (kept {len(keep)}), mp {mp}, |X C - I| {res:.2e}, "
+          f"cond {np.linalg.cond(Cref):.2e}", flush=True)
+    assert res <= 1e-8
