@@ -28,28 +28,20 @@ void launch_assemble(hipStream_t, int, const int*, const int*, const double*, co
                      const double*, double*);
 void launch_vjp_tets(hipStream_t, int, const int*, const double*, const double*, const double*,
                      const double*, const double*, const double*, double, const double*, const double*,
-                     double*, double*, double*, unsigned*, double*);
+                     double*, double*, double*, double*);
 void launch_contact_blocks(hipStream_t, int, const int*, const double*, const double*, const double*,
                            double, double, double, int, double*, double*, double*, double*, double*);
 void launch_contact_fold(hipStream_t, int, const int*, const int*, const double*, double*);
 void launch_capacitance(hipStream_t, int, int, const int*, const int*, const int*, int, const double*,
                         const double*, const double*, double, double, int, double*);
 void launch_vjp_contacts(hipStream_t, int, const int*, const double*, const double*, const double*,
-                         const double*, double, double*, double*, unsigned*, double*);
+                         const double*, double, double*, double*, double*);
 void launch_vjp_vectors(hipStream_t, int, const double*, const double*, const double*, double, double*,
                         double*, double*);
 void launch_fill_zero(hipStream_t, size_t, double*);
 void launch_delassus(hipStream_t, int, int, const int*, const long long*, const int*, const double*,
                      double*, double*, double*, double*);
 int delassus_slices(int, int);
-void launch_pcg_alpha(hipStream_t, long long, const double*, const double*, double*, unsigned*, GmresState*,
-                      double*);
-void launch_pcg_xr(hipStream_t, long long, double*, double*, const double*, const double*, double*, unsigned*,
-                   GmresState*, const double*);
-void launch_pcg_beta(hipStream_t, long long, const double*, const double*, double*, unsigned*, GmresState*,
-                     double*, int);
-void launch_pcg_p(hipStream_t, long long, const double*, double*, const GmresState*, const double*);
-void launch_pcg_residual(hipStream_t, long long, const double*, double*, double*, unsigned*, GmresState*);
 double* launch_gauss_jordan(hipStream_t, int, int, double*, double*, int*);
 void launch_spmv_csr3(hipStream_t, int, const long long*, const int*, const double*, const double*,
                       long long, const double*, const GmresState*, double*);
@@ -67,16 +59,27 @@ void launch_wb_correct(hipStream_t, int, int, const int*, const int*, const int*
 void launch_bsr_spmv(hipStream_t, int, int, const int*, const int*, const double*, const double*, double*,
                      long long, const GmresState*);
 int gm_blocks(long long, int);
-void launch_gm_dots(hipStream_t, long long, int, const double*, long long, const double*, GmresState*,
-                    double*, unsigned*, double*);
-void launch_gm_update(hipStream_t, long long, int, double*, long long, double*, GmresState*, double*,
-                      unsigned*, double*, double*, double*, double*, double*, int);
+int bsr_blocks(int, int);
+int vec_blocks(long long);
+void launch_bsr_dots(hipStream_t, int, int, const int*, const int*, const double*, const double*, double*,
+                     long long, const GmresState*, int, double*);
+void launch_bsr_dots(hipStream_t, int, int, const int*, const int*, const float*, const double*, double*,
+                     long long, const GmresState*, int, double*);
+void launch_gm_update(hipStream_t, long long, int, double*, long long, const double*, const GmresState*,
+                      const double*, int, double*, double*, int);
+void launch_gm_givens(hipStream_t, GmresState*, const double*, int, double*, const double*, double*, double*,
+                      double*, double*);
+void launch_residual(hipStream_t, long long, const double*, double*, double*, double*, GmresState*, double*,
+                     double*);
+void launch_pcg_xr(hipStream_t, long long, double*, double*, const double*, const double*, const double*, int,
+                   const GmresState*, const double*, double*);
+void launch_dot_partials(hipStream_t, long long, const double*, const double*, const GmresState*, double*);
+void launch_pcg_scalar(hipStream_t, GmresState*, const double*, int, const double*, int, const double*, int,
+                       double*, int);
+void launch_pcg_p(hipStream_t, long long, const double*, double*, const GmresState*, const double*);
 void launch_gm_finish(hipStream_t, long long, const GmresState*, const double*, const double*,
                       const double*, const double*, long long, double*, double*);
 void launch_axpy(hipStream_t, long long, double, const double*, double*);
-void launch_residual(hipStream_t, long long, const double*, double*, double*, double*, unsigned*,
-                     GmresState*, double*, double*);
-
 void launch_fwd_predict(hipStream_t, int, const double*, const double*, const double*, const double*, double,
                         const double*, double*, double*);
 void launch_fwd_detect(hipStream_t, int, const double*, int, const double*, double, int*);
@@ -88,7 +91,7 @@ void launch_gather_force(hipStream_t, int, const int*, const int*, const double*
                          const double*, const double*, double*);
 void launch_add_contact_vec(hipStream_t, int, const int*, const double*, double*);
 void launch_gather_contact_rows(hipStream_t, int, const int*, const double*, double*);
-void launch_norms(hipStream_t, long long, const double*, double*, unsigned*, double*);
+void launch_norms(hipStream_t, long long, const double*, double*, double*);
 
 }  // namespace adj
 
@@ -172,6 +175,10 @@ struct adj_scene {
   // Krylov workspace
   double *d_Vt = nullptr, *d_scale = nullptr, *d_H = nullptr, *d_cs = nullptr, *d_sn = nullptr,
          *d_g = nullptr, *d_hbuf = nullptr, *d_coef = nullptr, *d_partial = nullptr;
+  size_t preg = 0;  // doubles per partial-sum region (three regions in d_partial)
+  double* P1() const { return d_partial; }
+  double* P2() const { return d_partial + preg; }
+  double* P3() const { return d_partial + 2 * preg; }
   unsigned* d_counter = nullptr;
   GmresState* d_state = nullptr;
   GmresState* h_state = nullptr;  // pinned
@@ -318,7 +325,11 @@ extern "C" adj_status adj_scene_create(const adj_scene_desc* desc, int32_t max_c
   bool ok = true;
   const size_t mc = (size_t)std::max(1, max_contacts);
   const size_t R = kMaxRestart;
-  const size_t nblk = (size_t)gm_blocks(s->n3, 64) + 300;  // smallest rows-per-block is 64
+  // per-block partial sums: enough blocks for any tuning (block-sparse
+  // product with 32 lanes per row, Gram-Schmidt with 64 rows per block,
+  // vector kernels with at most 512 blocks)
+  const size_t nblk = std::max<size_t>({(size_t)bsr_blocks(s->nv, 32), (size_t)gm_blocks(s->n3, 64), 512}) + 8;
+  s->preg = nblk * 130;
   ok &= dalloc(&s->d_tetblk, 90 * (size_t)s->nt) == hipSuccess;
   ok &= dalloc(&s->d_val, 9 * (size_t)s->nnzb) == hipSuccess;
   ok &= dalloc(&s->d_err, 4) == hipSuccess;
@@ -344,7 +355,7 @@ extern "C" adj_status adj_scene_create(const adj_scene_desc* desc, int32_t max_c
   ok &= dalloc(&s->d_g, R + 2) == hipSuccess;
   ok &= dalloc(&s->d_hbuf, 260) == hipSuccess;
   ok &= dalloc(&s->d_coef, 130) == hipSuccess;
-  ok &= dalloc(&s->d_partial, nblk * 130) == hipSuccess;
+  ok &= dalloc(&s->d_partial, 3 * s->preg) == hipSuccess;
   ok &= dalloc(&s->d_counter, 16) == hipSuccess;
   ok &= dalloc(&s->d_state, 1) == hipSuccess;
   ok &= dalloc(&s->d_t1, (size_t)s->n3) == hipSuccess;
@@ -622,46 +633,61 @@ static void bsr(adj_scene* s, hipStream_t st, const double* x, double* outbase, 
     launch_bsr_spmv(st, s->tune.bsr_lanes, s->nv, s->d_rowptr, s->d_col, s->d_val, x, outbase, stride, state);
 }
 
+// One GMRES iteration per pass of the loop: preconditioner (4 launches),
+// block-sparse product fused with the first Gram-Schmidt dots, the two
+// Gram-Schmidt updates (classical Gram-Schmidt applied twice) and the
+// one-block Givens step.
 static void gmres_chunk(adj_scene* s, hipStream_t st, bool f32) {
   const long long n3 = s->n3, stride = n3;
+  const int nb1 = bsr_blocks(s->nv, s->tune.bsr_lanes), nb2 = gm_blocks(n3, s->tune.gs_rows);
   for (int k = 0; k < s->tune.chunk; ++k) {
     apply_precond(s, st, s->d_Vt, stride, s->d_scale, s->d_state, s->d_y, f32);
     {
       ProfScope p(s, 4, st);
-      bsr(s, st, s->d_y, s->d_Vt, stride, s->d_state, f32);
-    }
-    {
-      ProfScope p(s, 8, st);
-      launch_gm_dots(st, n3, s->tune.gs_rows, s->d_Vt, stride, s->d_scale, s->d_state, s->d_partial,
-                     s->d_counter, s->d_hbuf);
+      if (f32)
+        launch_bsr_dots(st, s->tune.bsr_lanes, s->nv, s->d_rowptr, s->d_col, s->d_val32, s->d_y, s->d_Vt, stride,
+                        s->d_state, -1, s->P1());
+      else
+        launch_bsr_dots(st, s->tune.bsr_lanes, s->nv, s->d_rowptr, s->d_col, s->d_val, s->d_y, s->d_Vt, stride,
+                        s->d_state, -1, s->P1());
     }
     {
       ProfScope p(s, 9, st);
-      launch_gm_update(st, n3, s->tune.gs_rows, s->d_Vt, stride, s->d_scale, s->d_state, s->d_partial,
-                       s->d_counter + 1, s->d_hbuf, s->d_H, s->d_cs, s->d_sn, s->d_g, 0);
+      launch_gm_update(st, n3, s->tune.gs_rows, s->d_Vt, stride, s->d_scale, s->d_state, s->P1(), nb1, s->P2(),
+                       s->d_hbuf, 0);
     }
-    launch_gm_update(st, n3, s->tune.gs_rows, s->d_Vt, stride, s->d_scale, s->d_state, s->d_partial,
-                     s->d_counter + 2, s->d_hbuf, s->d_H, s->d_cs, s->d_sn, s->d_g, 1);
+    {
+      ProfScope p(s, 8, st);
+      launch_gm_update(st, n3, s->tune.gs_rows, s->d_Vt, stride, s->d_scale, s->d_state, s->P2(), nb2, s->P3(),
+                       s->d_hbuf, 1);
+      launch_gm_givens(st, s->d_state, s->P3(), nb2, s->d_scale, s->d_hbuf, s->d_H, s->d_cs, s->d_sn, s->d_g);
+    }
   }
 }
 
+// One PCG iteration per pass (see the kernel file for the sequence); p and w
+// are basis slots 0 and 1, so the fused product-and-dot kernel gives p . w.
 static void pcg_chunk(adj_scene* s, hipStream_t st, bool f32) {
   const long long n3 = s->n3;
   double* p = s->d_Vt;
   double* w = s->d_Vt + n3;
   double* z = s->d_y;
-  double* sc = s->d_coef;
-  unsigned* ctr = s->d_counter + 8;
+  const int nb1 = bsr_blocks(s->nv, s->tune.bsr_lanes), nbv = vec_blocks(n3);
   for (int k = 0; k < s->tune.chunk; ++k) {
     {
       ProfScope pr(s, 4, st);
-      bsr(s, st, p, w, 0, s->d_state, f32);
+      if (f32)
+        launch_bsr_dots(st, s->tune.bsr_lanes, s->nv, s->d_rowptr, s->d_col, s->d_val32, p, s->d_Vt, n3,
+                        s->d_state, 0, s->P1());
+      else
+        launch_bsr_dots(st, s->tune.bsr_lanes, s->nv, s->d_rowptr, s->d_col, s->d_val, p, s->d_Vt, n3,
+                        s->d_state, 0, s->P1());
     }
-    launch_pcg_alpha(st, n3, p, w, s->d_partial, ctr, s->d_state, sc);
-    launch_pcg_xr(st, n3, s->d_x_pcg, s->d_r, p, w, s->d_partial, ctr, s->d_state, sc);
+    launch_pcg_xr(st, n3, s->d_x_pcg, s->d_r, p, w, s->P1(), nb1, s->d_state, s->d_coef, s->P3());
     apply_precond(s, st, s->d_r, 0, nullptr, s->d_state, z, f32);
-    launch_pcg_beta(st, n3, s->d_r, z, s->d_partial, ctr, s->d_state, sc, 0);
-    launch_pcg_p(st, n3, z, p, s->d_state, sc);
+    launch_dot_partials(st, n3, s->d_r, z, s->d_state, s->P2());
+    launch_pcg_scalar(st, s->d_state, s->P2(), nbv, s->P3(), nbv, s->P1(), nb1, s->d_coef, 0);
+    launch_pcg_p(st, n3, z, p, s->d_state, s->d_coef);
   }
 }
 
@@ -712,7 +738,7 @@ static adj_status gmres_solve(adj_scene* s, hipStream_t st, const double* b, dou
   init.restart = R;
   init.tol = 0.0;
   HIPCHK(hipMemcpyAsync(s->d_state, &init, sizeof(GmresState), hipMemcpyHostToDevice, st));
-  launch_residual(st, n3, s->d_b, s->d_r, s->d_Vt, s->d_partial, s->d_counter, s->d_state, s->d_scale,
+  launch_residual(st, n3, s->d_b, s->d_r, s->d_Vt, s->P3(), s->d_state, s->d_scale,
                   s->d_g);
   HIPCHK(hipMemcpyAsync(s->h_state, s->d_state, sizeof(GmresState), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
@@ -741,7 +767,7 @@ static adj_status gmres_solve(adj_scene* s, hipStream_t st, const double* b, dou
     apply_precond(s, st, s->d_xt, 0, nullptr, nullptr, s->d_dz, f32);
     launch_axpy(st, n3, 1.0, s->d_dz, x);
     bsr(s, st, x, s->d_r, 0, nullptr, f32);
-    launch_residual(st, n3, s->d_b, s->d_r, s->d_Vt, s->d_partial, s->d_counter + 3, s->d_state, s->d_scale,
+    launch_residual(st, n3, s->d_b, s->d_r, s->d_Vt, s->P3(), s->d_state, s->d_scale,
                     s->d_g);
     HIPCHK(hipGetLastError());
     HIPCHK(hipMemcpyAsync(s->h_state, s->d_state, sizeof(GmresState), hipMemcpyDeviceToHost, st));
@@ -768,13 +794,12 @@ static adj_status pcg_solve(adj_scene* s, hipStream_t st, const double* b, doubl
   double* z = s->d_y;
   double* xi = s->d_x_pcg;  // fixed address, so a captured chunk stays valid
   double* sc = s->d_coef;
-  unsigned* ctr = s->d_counter + 8;
   if (b != s->d_b) HIPCHK(hipMemcpyAsync(s->d_b, b, n3 * sizeof(double), hipMemcpyDeviceToDevice, st));
   launch_fill_zero(st, (size_t)n3, xi);
   launch_fill_zero(st, (size_t)n3, s->d_r);
   GmresState init{};
   HIPCHK(hipMemcpyAsync(s->d_state, &init, sizeof(GmresState), hipMemcpyHostToDevice, st));
-  launch_pcg_residual(st, n3, s->d_b, s->d_r, s->d_partial, ctr, s->d_state);
+  launch_residual(st, n3, s->d_b, s->d_r, nullptr, s->P3(), s->d_state, nullptr, nullptr);
   HIPCHK(hipMemcpyAsync(s->h_state, s->d_state, sizeof(GmresState), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   const double bnorm = s->h_state->rnorm;
@@ -791,7 +816,8 @@ static adj_status pcg_solve(adj_scene* s, hipStream_t st, const double* b, doubl
     cur.active = 1;
     HIPCHK(hipMemcpyAsync(s->d_state, &cur, sizeof(GmresState), hipMemcpyHostToDevice, st));
     apply_precond(s, st, s->d_r, 0, nullptr, s->d_state, z, f32);
-    launch_pcg_beta(st, n3, s->d_r, z, s->d_partial, ctr, s->d_state, sc, 1);
+    launch_dot_partials(st, n3, s->d_r, z, s->d_state, s->P2());
+    launch_pcg_scalar(st, s->d_state, s->P2(), vec_blocks(n3), nullptr, 0, nullptr, 0, sc, 1);
     launch_fill_zero(st, (size_t)n3, p);
     launch_pcg_p(st, n3, z, p, s->d_state, sc);
     int done = 0;
@@ -806,7 +832,7 @@ static adj_status pcg_solve(adj_scene* s, hipStream_t st, const double* b, doubl
     total += done;
     // true residual
     bsr(s, st, xi, s->d_r, 0, nullptr, f32);
-    launch_pcg_residual(st, n3, s->d_b, s->d_r, s->d_partial, ctr, s->d_state);
+    launch_residual(st, n3, s->d_b, s->d_r, nullptr, s->P3(), s->d_state, nullptr, nullptr);
     HIPCHK(hipMemcpyAsync(s->h_state, s->d_state, sizeof(GmresState), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     rnorm = s->h_state->rnorm;
@@ -859,7 +885,7 @@ extern "C" adj_status adjoint_solve(adj_scene* s, const double* dL_dq, const dou
     // matrix; inner GMRES with FP32-stored matrices solves Acal^T dz = r.
     launch_fill_zero(st, (size_t)n3, z);
     HIPCHK(hipMemcpyAsync(s->d_fu, s->d_rhs, n3 * sizeof(double), hipMemcpyDeviceToDevice, st));
-    launch_norms(st, n3, s->d_rhs, s->d_partial, s->d_counter + 7, s->d_norms);
+    launch_norms(st, n3, s->d_rhs, s->P3(), s->d_norms);
     double nb[2];
     HIPCHK(hipMemcpyAsync(nb, s->d_norms, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
@@ -880,7 +906,7 @@ extern "C" adj_status adjoint_solve(adj_scene* s, const double* dL_dq, const dou
       // r = b - Acal^T z in FP64
       bsr(s, st, z, s->d_fu, 0, nullptr, false);
       launch_add_vec(st, n3, s->d_rhs, s->d_fu, -1.0, s->d_fu);
-      launch_norms(st, n3, s->d_fu, s->d_partial, s->d_counter + 7, s->d_norms);
+      launch_norms(st, n3, s->d_fu, s->P3(), s->d_norms);
       HIPCHK(hipMemcpyAsync(nb, s->d_norms, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
       HIPCHK(hipStreamSynchronize(st));
       rnorm = std::sqrt(nb[0]);
@@ -912,9 +938,9 @@ extern "C" adj_status vjp_params(adj_scene* s, const double* z, const double* dL
   const double h = s->hs.h, h2 = h * h;
   launch_vjp_vectors(st, s->nv, z, dL_dv, s->d_mass, h, dL_dqbar, dL_dvbar, dL_dfext);
   launch_vjp_contacts(st, s->nc, s->cur_vid, s->cur_frame, s->d_Kc, s->d_kmu, z, h2, dL_dqbar,
-                      s->d_partial, s->d_counter + 4, grad3);
+                      s->P1(), grad3);
   launch_vjp_tets(st, s->nt, s->d_tets, s->d_Bt, s->d_vol, s->d_lmu, s->d_llam, s->d_E, s->d_nu, h2,
-                  s->cur_q, z, dE_tet, dnu_tet, s->d_partial + 4096, s->d_counter + 5, grad3);
+                  s->cur_q, z, dE_tet, dnu_tet, s->P2(), grad3);
   HIPCHK(hipGetLastError());
   return ADJ_OK;
 }
@@ -1169,7 +1195,7 @@ static adj_status fwd_eval(adj_scene* s, hipStream_t st, const double* qbar, con
     HIPCHK(hipMemcpyAsync(s->d_cvec, fw.data(), fw.size() * sizeof(double), hipMemcpyHostToDevice, st));
     launch_add_contact_vec(st, C.n, s->d_fvid, s->d_cvec, s->d_rq);
   }
-  launch_norms(st, n3, s->d_rq, s->d_partial, s->d_counter + 6, s->d_norms);
+  launch_norms(st, n3, s->d_rq, s->P3(), s->d_norms);
   double nr[2];
   int errs[2];
   HIPCHK(hipMemcpyAsync(nr, s->d_norms, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -1345,11 +1371,11 @@ static adj_status fwd_newton(adj_scene* s, hipStream_t st, const double* qbar, F
     pmax = pt;
     // |alpha du|_max and |u|_max for the small-step test
     launch_scale_vec(st, n3, s->d_du, alpha, s->d_ut);
-    launch_norms(st, n3, s->d_ut, s->d_partial, s->d_counter + 6, s->d_norms);
+    launch_norms(st, n3, s->d_ut, s->P3(), s->d_norms);
     double nd[2], nu[2];
     HIPCHK(hipMemcpyAsync(nd, s->d_norms, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
-    launch_norms(st, n3, s->d_fu, s->d_partial, s->d_counter + 6, s->d_norms);
+    launch_norms(st, n3, s->d_fu, s->P3(), s->d_norms);
     HIPCHK(hipMemcpyAsync(nu, s->d_norms, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     const bool small = nd[1] <= 4e-16 * std::max(1.0, nu[1]);

@@ -155,10 +155,8 @@ __global__ void __launch_bounds__(256) k_vjp_contacts(int nc, const int* __restr
                                                       const double* __restrict__ kmu,
                                                       const double* __restrict__ z, double h2,
                                                       double* __restrict__ dqbar,
-                                                      double* __restrict__ partial,
-                                                      unsigned* counter, double* __restrict__ grad) {
+                                                      double* __restrict__ partial) {
   __shared__ double lds[32];
-  __shared__ bool is_last;
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   double gmu = 0.0;
   if (c < nc) {
@@ -185,13 +183,9 @@ __global__ void __launch_bounds__(256) k_vjp_contacts(int nc, const int* __restr
   }
   double s = block_sum(gmu, lds);
   if (threadIdx.x == 0) partial[blockIdx.x] = s;
-  if (last_block(counter, &is_last)) {
-    double a = 0.0;
-    for (int i = threadIdx.x; i < (int)gridDim.x; i += blockDim.x) a += partial[i];
-    a = block_sum(a, lds);
-    if (threadIdx.x == 0) grad[2] += a;
-  }
 }
+
+void launch_add_partials(hipStream_t st, const double* partial, int nb, int k, double* grad);
 
 // dL/dqbar = M z - dL_dv/h, dL/dvbar = h M z, dL/dfext = h^2 z.
 __global__ void k_vjp_vectors(int nv, const double* __restrict__ z, const double* __restrict__ gv,
@@ -229,10 +223,11 @@ void launch_capacitance(hipStream_t st, int m, int mp, const int* row_c, const i
 
 void launch_vjp_contacts(hipStream_t st, int nc, const int* vid, const double* frame, const double* Kc,
                          const double* kmu, const double* z, double h2, double* dqbar, double* partial,
-                         unsigned* counter, double* grad) {
+                         double* grad) {
   if (nc == 0) return;
-  k_vjp_contacts<<<(nc + 255) / 256, 256, 0, st>>>(nc, vid, frame, Kc, kmu, z, h2, dqbar, partial,
-                                                    counter, grad);
+  const int nb = (nc + 255) / 256;
+  k_vjp_contacts<<<nb, 256, 0, st>>>(nc, vid, frame, Kc, kmu, z, h2, dqbar, partial);
+  launch_add_partials(st, partial, nb, 1, grad + 2);
 }
 
 void launch_vjp_vectors(hipStream_t st, int nv, const double* z, const double* gv, const double* mass,

@@ -148,7 +148,8 @@ __global__ void __launch_bounds__(256) k_assemble(int nnzb, const int* __restric
 // dp/dmu = vec(U Diag(dtheta/dmu) V^T), dtheta/dmu = -(dg/dtheta)^{-1}(3 theta - 2 sigma - 1/theta),
 // dtheta/dlam = -(dg/dtheta)^{-1}(log J / theta); then the chain rule to E, nu.
 // Writes per-tet dE, dnu (accumulate) when requested and per-block partial
-// sums; the last block adds the totals to grad[0], grad[1].
+// sums (partial[2b], partial[2b+1]); k_add_partials adds the totals to
+// grad[0], grad[1].
 __global__ void __launch_bounds__(256) k_vjp_tets(int nt, const int* __restrict__ tets,
                                                   const double* __restrict__ Bt,
                                                   const double* __restrict__ vol,
@@ -160,10 +161,8 @@ __global__ void __launch_bounds__(256) k_vjp_tets(int nt, const int* __restrict_
                                                   const double* __restrict__ z,
                                                   double* __restrict__ dE_tet,
                                                   double* __restrict__ dnu_tet,
-                                                  double* __restrict__ partial, unsigned* counter,
-                                                  double* __restrict__ grad) {
+                                                  double* __restrict__ partial) {
   __shared__ double lds[32];
-  __shared__ bool is_last;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   double gE = 0.0, gnu = 0.0;
   if (t < nt) {
@@ -224,19 +223,23 @@ __global__ void __launch_bounds__(256) k_vjp_tets(int nt, const int* __restrict_
     partial[2 * blockIdx.x] = sE;
     partial[2 * blockIdx.x + 1] = sN;
   }
-  if (last_block(counter, &is_last)) {
-    double a = 0.0, b = 0.0;
-    for (int i = threadIdx.x; i < (int)gridDim.x; i += blockDim.x) {
-      a += partial[2 * i];
-      b += partial[2 * i + 1];
-    }
+}
+
+// One block: grad[c] += sum_b partial[b * k + c], c < k (fixed order).
+__global__ void __launch_bounds__(256) k_add_partials(const double* __restrict__ partial, int nb, int k,
+                                                      double* __restrict__ grad) {
+  __shared__ double lds[32];
+  for (int c = 0; c < k; ++c) {
+    double a = 0.0;
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) a += partial[(size_t)b * k + c];
     a = block_sum(a, lds);
-    b = block_sum(b, lds);
-    if (threadIdx.x == 0) {
-      grad[0] += a;
-      grad[1] += b;
-    }
+    if (threadIdx.x == 0) grad[c] += a;
   }
+}
+
+void launch_add_partials(hipStream_t st, const double* partial, int nb, int k, double* grad) {
+  if (nb <= 0) return;
+  k_add_partials<<<1, 256, 0, st>>>(partial, nb, k, grad);
 }
 
 void launch_tet_blocks(hipStream_t st, int nt, const int* tets, const double* Bt, const double* vol,
@@ -255,9 +258,10 @@ void launch_assemble(hipStream_t st, int nnzb, const int* slot_ptr, const int* s
 void launch_vjp_tets(hipStream_t st, int nt, const int* tets, const double* Bt, const double* vol,
                      const double* lmu, const double* llam, const double* Ev, const double* nuv,
                      double h2, const double* q, const double* z, double* dE_tet, double* dnu_tet,
-                     double* partial, unsigned* counter, double* grad) {
-  k_vjp_tets<<<(nt + 255) / 256, 256, 0, st>>>(nt, tets, Bt, vol, lmu, llam, Ev, nuv, h2, q, z, dE_tet,
-                                                dnu_tet, partial, counter, grad);
+                     double* partial, double* grad) {
+  const int nb = (nt + 255) / 256;
+  k_vjp_tets<<<nb, 256, 0, st>>>(nt, tets, Bt, vol, lmu, llam, Ev, nuv, h2, q, z, dE_tet, dnu_tet, partial);
+  launch_add_partials(st, partial, nb, 2, grad);
 }
 
 }  // namespace adj

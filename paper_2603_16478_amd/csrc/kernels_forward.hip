@@ -152,12 +152,12 @@ __global__ void k_gather_contact_rows(int nc, const int* __restrict__ vid, const
   out[3 * c + 2] = x[3 * v + 2];
 }
 
-// out[0] = sum x_i^2 * w, out[1] = max |x_i| (deterministic, last block)
-__global__ void __launch_bounds__(256) k_norms(long long n, const double* __restrict__ x, double* __restrict__ partial,
-                                               unsigned* counter, double* __restrict__ out) {
+// out[0] = sum x_i^2, out[1] = max |x_i|: per-block partials, then one
+// block sums them in fixed order.
+__global__ void __launch_bounds__(256) k_norms(long long n, const double* __restrict__ x,
+                                               double* __restrict__ partial) {
   __shared__ double lds[32];
   __shared__ double mx[8];
-  __shared__ bool is_last;
   double s = 0.0, m = 0.0;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x) {
@@ -176,10 +176,13 @@ __global__ void __launch_bounds__(256) k_norms(long long n, const double* __rest
     partial[2 * blockIdx.x] = s;
     partial[2 * blockIdx.x + 1] = mm;
   }
-  if (!last_block(counter, &is_last)) return;
+}
+
+__global__ void __launch_bounds__(64) k_norms_finish(const double* __restrict__ partial, int nb,
+                                                     double* __restrict__ out) {
   if (threadIdx.x != 0) return;
   double a = 0.0, b = 0.0;
-  for (int i = 0; i < (int)gridDim.x; ++i) {
+  for (int i = 0; i < nb; ++i) {
     a += partial[2 * i];
     b = fmax(b, partial[2 * i + 1]);
   }
@@ -226,11 +229,11 @@ void launch_gather_contact_rows(hipStream_t st, int nc, const int* vid, const do
   k_gather_contact_rows<<<(nc + 255) / 256, 256, 0, st>>>(nc, vid, x, out);
 }
 
-void launch_norms(hipStream_t st, long long n, const double* x, double* partial, unsigned* counter,
-                  double* out) {
+void launch_norms(hipStream_t st, long long n, const double* x, double* partial, double* out) {
   int blocks = (int)((n + 255) / 256);
   if (blocks > 256) blocks = 256;
-  k_norms<<<blocks, 256, 0, st>>>(n, x, partial, counter, out);
+  k_norms<<<blocks, 256, 0, st>>>(n, x, partial);
+  k_norms_finish<<<1, 64, 0, st>>>(partial, blocks, out);
 }
 
 }  // namespace adj

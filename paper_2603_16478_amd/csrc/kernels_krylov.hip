@@ -244,72 +244,125 @@ __global__ void __launch_bounds__(256) k_bsr_spmv(int nv, const int* __restrict_
   }
 }
 
-// Gram-Schmidt kernels work on `rpb` consecutive rows per 256-thread block
-// (rpb = 64, 128 or 256, a launch parameter): each row is shared by
-// T = 256 / rpb threads that split the basis index range.
+// Reductions without inter-block handshakes.  A kernel that needs a global
+// sum writes one partial per block; the kernels that consume the sum re-add
+// the partials themselves (every block, in the same fixed order, so all of
+// them get the same bits), and state that must have a single writer is
+// updated by a one-block kernel.  A "last block reduces" handshake (fence +
+// atomic counter) serialises the blocks on this multi-die GPU and costs
+// more than one extra launch.
+constexpr int kLd = 130;  // partials of one block: [0 .. 129], basis index i
 
-// CGS pass 1: h_i = scale_i * (Vt_i . w), i <= j, with w = Vt_{j+1}.
-// Per-block partials; the last block reduces into hbuf.
-__global__ void __launch_bounds__(256) k_gm_dots(long long n, int rpb, const double* __restrict__ Vt,
-                                                 long long stride, const double* __restrict__ scale,
-                                                 GmresState* __restrict__ st,
-                                                 double* __restrict__ partial, unsigned* counter,
-                                                 double* __restrict__ hbuf) {
-  if (st->active == 0) return;
-  __shared__ bool is_last;
-  const int j = st->j;
-  const double* w = Vt + (long long)(j + 1) * stride;
-  const long long r0 = (long long)blockIdx.x * rpb;
-  const int lane = threadIdx.x & 63, wid = threadIdx.x / 64, nw = blockDim.x / 64;
-  for (int i = wid; i <= j; i += nw) {
-    const double* vi = Vt + (long long)i * stride;
-    double acc = 0.0;
-    for (long long r = r0 + lane; r < r0 + rpb && r < n; r += 64) acc += vi[r] * w[r];
-    acc = wave_sum(acc);
-    if (lane == 0) partial[(size_t)blockIdx.x * 130 + i] = acc;
+// res[i] = sum_b P[b * ld + i] for i < cnt (cnt <= 130), fixed order; all
+// 256 threads of the block take part; tmp: 256 doubles of LDS.
+__device__ __forceinline__ void sum_partials(const double* __restrict__ P, int nb, int ld, int cnt,
+                                             double* __restrict__ res, double* __restrict__ tmp) {
+  int G = 1;
+  while (2 * G * cnt <= 256) G *= 2;  // threads per entry (power of two)
+  const int t = threadIdx.x, i = t / G, g = t % G;
+  double a = 0.0;
+  if (i < cnt)
+    for (int b = g; b < nb; b += G) a += P[(size_t)b * ld + i];
+  tmp[t] = a;
+  __syncthreads();
+  for (int h = G / 2; h > 0; h >>= 1) {
+    if (g < h && i < cnt) tmp[t] += tmp[t + h];
+    __syncthreads();
   }
-  if (last_block(counter, &is_last)) {
-    for (int i = threadIdx.x; i <= j; i += blockDim.x) {
-      double s = 0.0;
-      for (int b = 0; b < (int)gridDim.x; ++b) s += partial[(size_t)b * 130 + i];
-      hbuf[i] = scale[i] * s;
+  if (g == 0 && i < cnt) res[i] = tmp[t];
+  __syncthreads();
+}
+
+// w = Acal^T y fused with the first Gram-Schmidt pass: the block writes its
+// rows of w = Vt_{j+1} and the partial dots Vt_i . w over those rows
+// (i <= j) to P[blockIdx.x * kLd + i].  jfix >= 0 overrides j (PCG: w =
+// Acal^T p with p = Vt_0, w = Vt_1, partial p . w).
+template <class MT, int LANES>
+__global__ void __launch_bounds__(256) k_bsr_dots(int nv, const int* __restrict__ rowptr,
+                                                  const int* __restrict__ col, const MT* __restrict__ val,
+                                                  const double* __restrict__ y, double* __restrict__ Vt,
+                                                  long long stride, const GmresState* __restrict__ st, int jfix,
+                                                  double* __restrict__ P) {
+  if (st->active == 0) return;
+  constexpr int R = 256 / LANES;  // rows per block
+  __shared__ double wl[3 * R];
+  const int j = jfix >= 0 ? jfix : st->j;
+  double* w = Vt + (long long)(j + 1) * stride;
+  const int sub = threadIdx.x & (LANES - 1), rl = threadIdx.x / LANES;
+  const int row0 = blockIdx.x * R, row = row0 + rl;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+  if (row < nv) {
+    for (int p = rowptr[row] + sub; p < rowptr[row + 1]; p += LANES) {
+      const MT* b = val + 9 * (size_t)p;
+      const int c = col[p];
+      const double x0 = y[3 * c], x1 = y[3 * c + 1], x2 = y[3 * c + 2];
+      a0 += (double)b[0] * x0 + (double)b[1] * x1 + (double)b[2] * x2;
+      a1 += (double)b[3] * x0 + (double)b[4] * x1 + (double)b[5] * x2;
+      a2 += (double)b[6] * x0 + (double)b[7] * x1 + (double)b[8] * x2;
     }
+  }
+  a0 = group_sum<LANES>(a0);
+  a1 = group_sum<LANES>(a1);
+  a2 = group_sum<LANES>(a2);
+  if (sub == 0) {
+    const bool ok = row < nv;
+    wl[3 * rl] = ok ? a0 : 0.0;
+    wl[3 * rl + 1] = ok ? a1 : 0.0;
+    wl[3 * rl + 2] = ok ? a2 : 0.0;
+    if (ok) {
+      w[3 * row] = a0;
+      w[3 * row + 1] = a1;
+      w[3 * row + 2] = a2;
+    }
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wid = threadIdx.x / 64;
+  const long long e0 = 3LL * row0;
+  const int ne = 3 * min(R, nv - row0);
+  for (int i = wid; i <= j; i += 4) {
+    const double* vi = Vt + (long long)i * stride + e0;
+    double d = 0.0;
+    for (int e = lane; e < ne; e += 64) d += vi[e] * wl[e];
+    d = wave_sum(d);
+    if (lane == 0) P[(size_t)blockIdx.x * kLd + i] = d;
   }
 }
 
-// CGS: w -= sum_i h_i V_i on this block's rows, then partial dots of the
-// updated w (second pass) or its squared norm (final pass).
-// mode 0: second pass -> h2 into hbuf[130 + i]; column of H gets h + h2 later
-// mode 1: final update with h2, norm, Givens rotation, bookkeeping
+// Gram-Schmidt update on `rpb` rows per block (64, 128 or 256; T = 256/rpb
+// threads per row split the basis range): with c_i = scale_i^2 * sum_b
+// Pin[b][i], w -= sum_i c_i Vt_i, where w = Vt_{j+1}.  Block 0 records the
+// projection coefficients h_i = scale_i * sum_b Pin[b][i] in hbuf[hoff + i].
+// mode 0 (after the first pass): partial dots Vt_i . w -> Pout[b][i];
+// mode 1 (after the second pass): partial |w|^2 -> Pout[b][0].
 __global__ void __launch_bounds__(256) k_gm_update(long long n, int rpb, double* __restrict__ Vt,
-                                                   long long stride, double* __restrict__ scale,
-                                                   GmresState* __restrict__ st,
-                                                   double* __restrict__ partial, unsigned* counter,
-                                                   double* __restrict__ hbuf, double* __restrict__ H,
-                                                   double* __restrict__ cs, double* __restrict__ sn,
-                                                   double* __restrict__ gvec, int mode) {
+                                                   long long stride, const double* __restrict__ scale,
+                                                   const GmresState* __restrict__ st,
+                                                   const double* __restrict__ Pin, int nbin,
+                                                   double* __restrict__ Pout, double* __restrict__ hbuf,
+                                                   int mode) {
   if (st->active == 0) return;
-  __shared__ bool is_last;
-  __shared__ double lds[32];
-  __shared__ double red[256];
-  __shared__ double hs[130];
+  __shared__ double hs[kLd];
+  __shared__ double tmp[256];
   const int j = st->j;
   double* w = Vt + (long long)(j + 1) * stride;
-  const double* h = hbuf + (mode == 0 ? 0 : 130);
-  for (int i = threadIdx.x; i <= j; i += blockDim.x) hs[i] = h[i] * scale[i];
+  sum_partials(Pin, nbin, kLd, j + 1, hs, tmp);
+  if (blockIdx.x == 0)
+    for (int i = threadIdx.x; i <= j; i += blockDim.x) hbuf[(mode == 0 ? 0 : kLd) + i] = scale[i] * hs[i];
+  __syncthreads();
+  for (int i = threadIdx.x; i <= j; i += blockDim.x) hs[i] *= scale[i] * scale[i];
   __syncthreads();
   const long long r0 = (long long)blockIdx.x * rpb;
-  const int T = blockDim.x / rpb;              // threads per row
+  const int T = blockDim.x / rpb;
   const int rl = threadIdx.x % rpb, part = threadIdx.x / rpb;
   const long long r = r0 + rl;
   double acc = 0.0;
   if (r < n)
     for (int i = part; i <= j; i += T) acc += hs[i] * Vt[(long long)i * stride + r];
-  red[threadIdx.x] = acc;
+  tmp[threadIdx.x] = acc;
   __syncthreads();
   if (part == 0 && r < n) {
-    double a = red[rl];
-    for (int t = 1; t < T; ++t) a += red[rl + t * rpb];
+    double a = tmp[rl];
+    for (int t = 1; t < T; ++t) a += tmp[rl + t * rpb];
     w[r] -= a;
   }
   __syncthreads();
@@ -320,30 +373,33 @@ __global__ void __launch_bounds__(256) k_gm_update(long long n, int rpb, double*
       double d = 0.0;
       for (long long rr = r0 + lane; rr < r0 + rpb && rr < n; rr += 64) d += vi[rr] * w[rr];
       d = wave_sum(d);
-      if (lane == 0) partial[(size_t)blockIdx.x * 130 + i] = d;
+      if (lane == 0) Pout[(size_t)blockIdx.x * kLd + i] = d;
     }
   } else {
     double d = 0.0;
     for (long long rr = r0 + threadIdx.x; rr < r0 + rpb && rr < n; rr += blockDim.x) d += w[rr] * w[rr];
-    d = block_sum(d, lds);
-    if (threadIdx.x == 0) partial[(size_t)blockIdx.x * 130] = d;
+    d = block_sum(d, tmp);
+    if (threadIdx.x == 0) Pout[(size_t)blockIdx.x * kLd] = d;
   }
-  if (!last_block(counter, &is_last)) return;
-  if (mode == 0) {
-    for (int i = threadIdx.x; i <= j; i += blockDim.x) {
-      double sum = 0.0;
-      for (int b = 0; b < (int)gridDim.x; ++b) sum += partial[(size_t)b * 130 + i];
-      hbuf[130 + i] = scale[i] * sum;
-    }
-    return;
-  }
+}
+
+// One block: |w| from the partial norms, the new Hessenberg column
+// (h + h2, |w|), its Givens rotations, the residual estimate and the state.
+__global__ void __launch_bounds__(256) k_gm_givens(GmresState* __restrict__ st, const double* __restrict__ P,
+                                                   int nb, double* __restrict__ scale,
+                                                   const double* __restrict__ hbuf, double* __restrict__ H,
+                                                   double* __restrict__ cs, double* __restrict__ sn,
+                                                   double* __restrict__ gvec) {
+  if (st->active == 0) return;
+  __shared__ double nn[1];
+  __shared__ double tmp[256];
+  sum_partials(P, nb, kLd, 1, nn, tmp);
   if (threadIdx.x != 0) return;
-  double sum = 0.0;
-  for (int b = 0; b < (int)gridDim.x; ++b) sum += partial[(size_t)b * 130];
-  const double nrm = sqrt(sum);
+  const int j = st->j;
+  const double nrm = sqrt(nn[0]);
   const int R = st->restart;
   double* Hc = H + (size_t)j * (R + 1);  // column j, column-major (R+1) x R
-  for (int i = 0; i <= j; ++i) Hc[i] = hbuf[i] + hbuf[130 + i];
+  for (int i = 0; i <= j; ++i) Hc[i] = hbuf[i] + hbuf[kLd + i];
   Hc[j + 1] = nrm;
   scale[j + 1] = (nrm > 0.0) ? 1.0 / nrm : 0.0;
   for (int i = 0; i < j; ++i) {
@@ -408,16 +464,12 @@ __global__ void k_axpy(long long n, double a, const double* __restrict__ x, doub
   if (r < n) y[r] += a * x[r];
 }
 
-// r = b - Ax (in place on Ax), |r|^2 partials, last block writes st->rnorm,
-// and (when v0 is given) v0 = r with scale 1/|r|, g = [|r|, 0, ...].
+// r = b - r (r holds Acal^T x on entry), v0 = r when given; partial |r|^2
+// per block to P[b] (contiguous).
 __global__ void __launch_bounds__(256) k_residual(long long n, const double* __restrict__ b,
                                                   double* __restrict__ r, double* __restrict__ v0,
-                                                  double* __restrict__ partial, unsigned* counter,
-                                                  GmresState* __restrict__ st,
-                                                  double* __restrict__ scale,
-                                                  double* __restrict__ gvec) {
+                                                  double* __restrict__ P) {
   __shared__ double lds[32];
-  __shared__ bool is_last;
   double acc = 0.0;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x) {
@@ -427,63 +479,51 @@ __global__ void __launch_bounds__(256) k_residual(long long n, const double* __r
     acc += v * v;
   }
   acc = block_sum(acc, lds);
-  if (threadIdx.x == 0) partial[blockIdx.x] = acc;
-  if (!last_block(counter, &is_last)) return;
+  if (threadIdx.x == 0) P[blockIdx.x] = acc;
+}
+
+// One block: |r| -> rnorm, res; j = 0; active = (|r| > tol); when scale is
+// given (GMRES restart) also scale[0] = 1/|r| and g = (|r|, 0, ...).
+__global__ void __launch_bounds__(256) k_residual_finish(const double* __restrict__ P, int nb,
+                                                         GmresState* __restrict__ st,
+                                                         double* __restrict__ scale,
+                                                         double* __restrict__ gvec) {
+  __shared__ double nn[1];
+  __shared__ double tmp[256];
+  sum_partials(P, nb, 1, 1, nn, tmp);
   if (threadIdx.x != 0) return;
-  double s = 0.0;
-  for (int i = 0; i < (int)gridDim.x; ++i) s += partial[i];
-  const double nrm = sqrt(s);
+  const double nrm = sqrt(nn[0]);
   st->rnorm = nrm;
   st->res = nrm;
   st->j = 0;
   st->active = (nrm > st->tol) ? 1 : 0;
-  scale[0] = (nrm > 0.0) ? 1.0 / nrm : 0.0;
-  gvec[0] = nrm;
+  if (scale) {
+    scale[0] = (nrm > 0.0) ? 1.0 / nrm : 0.0;
+    gvec[0] = nrm;
+  }
 }
 
 // Preconditioned conjugate gradients for the symmetric case (no frictional
 // contact, or mu = 0: Acal^T is symmetric positive definite and so is the
-// Woodbury preconditioner).  Device-side scalars sc = {rz, alpha, beta, pAp};
-// the GmresState carries the iteration count (j), the active flag, the
-// absolute tolerance and the recurrence residual norm (res).
+// Woodbury preconditioner).  Device scalars sc = {rz, -, beta, -}; the
+// GmresState carries the iteration count (j), the active flag, the
+// absolute tolerance, the iteration limit (restart) and the residual norm
+// of the recurrence (res).  Per iteration:
+//   k_bsr_dots (w = Acal^T p, partials p.w) -> k_pcg_xr (alpha from the
+//   partials, x += alpha p, r -= alpha w, partials |r|^2) -> preconditioner
+//   (z = P r) -> k_dot_partials (r.z) -> k_pcg_scalar (one block: beta,
+//   rz, res, j, active) -> k_pcg_p (p = z + beta p).
 
-// alpha = rz / (p . w): per-block partials, the last block divides.
-__global__ void __launch_bounds__(256) k_pcg_alpha(long long n, const double* __restrict__ p,
-                                                   const double* __restrict__ w,
-                                                   double* __restrict__ partial, unsigned* counter,
-                                                   GmresState* __restrict__ st, double* __restrict__ sc) {
-  if (st->active == 0) return;
-  __shared__ double lds[32];
-  __shared__ bool is_last;
-  double acc = 0.0;
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (long long)gridDim.x * blockDim.x)
-    acc += p[i] * w[i];
-  acc = block_sum(acc, lds);
-  if (threadIdx.x == 0) partial[blockIdx.x] = acc;
-  if (!last_block(counter, &is_last)) return;
-  if (threadIdx.x != 0) return;
-  double s = 0.0;
-  for (int b = 0; b < (int)gridDim.x; ++b) s += partial[b];
-  sc[3] = s;
-  if (!(s > 0.0) || !isfinite(s)) {  // breakdown: not positive definite
-    st->active = 0;
-    sc[1] = 0.0;
-    return;
-  }
-  sc[1] = sc[0] / s;
-}
-
-// x += alpha p; r -= alpha w; |r|^2 -> res; stop at res <= tol or after
-// `limit` iterations.
 __global__ void __launch_bounds__(256) k_pcg_xr(long long n, double* __restrict__ x, double* __restrict__ r,
                                                 const double* __restrict__ p, const double* __restrict__ w,
-                                                double* __restrict__ partial, unsigned* counter,
-                                                GmresState* __restrict__ st, const double* __restrict__ sc) {
+                                                const double* __restrict__ Ppw, int nbpw,
+                                                const GmresState* __restrict__ st,
+                                                const double* __restrict__ sc, double* __restrict__ Prr) {
   if (st->active == 0) return;
-  __shared__ double lds[32];
-  __shared__ bool is_last;
-  const double alpha = sc[1];
+  __shared__ double pw[1];
+  __shared__ double tmp[256];
+  sum_partials(Ppw, nbpw, kLd, 1, pw, tmp);
+  const double alpha = (pw[0] > 0.0 && isfinite(pw[0])) ? sc[0] / pw[0] : 0.0;
   double acc = 0.0;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x) {
@@ -492,43 +532,55 @@ __global__ void __launch_bounds__(256) k_pcg_xr(long long n, double* __restrict_
     r[i] = v;
     acc += v * v;
   }
-  acc = block_sum(acc, lds);
-  if (threadIdx.x == 0) partial[blockIdx.x] = acc;
-  if (!last_block(counter, &is_last)) return;
-  if (threadIdx.x != 0) return;
-  double s = 0.0;
-  for (int b = 0; b < (int)gridDim.x; ++b) s += partial[b];
-  st->res = sqrt(s);
-  st->j += 1;
-  if (st->res <= st->tol || st->j >= st->restart || !isfinite(st->res)) st->active = 0;
+  acc = block_sum(acc, tmp);
+  if (threadIdx.x == 0) Prr[blockIdx.x] = acc;
 }
 
-// beta = (r . z) / rz_old (first = 1: beta = 0); then p = z + beta p is
-// done by k_pcg_p.
-__global__ void __launch_bounds__(256) k_pcg_beta(long long n, const double* __restrict__ r,
-                                                  const double* __restrict__ z,
-                                                  double* __restrict__ partial, unsigned* counter,
-                                                  GmresState* __restrict__ st, double* __restrict__ sc,
-                                                  int first) {
+// partial a . b per block to P[b] (gated by the state)
+__global__ void __launch_bounds__(256) k_dot_partials(long long n, const double* __restrict__ a,
+                                                      const double* __restrict__ b,
+                                                      const GmresState* __restrict__ st, double* __restrict__ P) {
   if (st->active == 0) return;
   __shared__ double lds[32];
-  __shared__ bool is_last;
   double acc = 0.0;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x)
-    acc += r[i] * z[i];
+    acc += a[i] * b[i];
   acc = block_sum(acc, lds);
-  if (threadIdx.x == 0) partial[blockIdx.x] = acc;
-  if (!last_block(counter, &is_last)) return;
+  if (threadIdx.x == 0) P[blockIdx.x] = acc;
+}
+
+// One block.  first = 1: rz = r.z, beta = 0 (start of a pass).  Otherwise:
+// beta = (r.z) / rz, rz = r.z, res = |r|, j += 1, and the pass stops when
+// res <= tol, j reaches the limit, p.w <= 0 (breakdown) or a value is not
+// finite.
+__global__ void __launch_bounds__(256) k_pcg_scalar(GmresState* __restrict__ st, const double* __restrict__ Prz,
+                                                    int nbrz, const double* __restrict__ Prr, int nbrr,
+                                                    const double* __restrict__ Ppw, int nbpw,
+                                                    double* __restrict__ sc, int first) {
+  if (st->active == 0) return;
+  __shared__ double v[3];
+  __shared__ double tmp[256];
+  sum_partials(Prz, nbrz, 1, 1, v, tmp);
+  if (!first) {
+    sum_partials(Prr, nbrr, 1, 1, v + 1, tmp);
+    sum_partials(Ppw, nbpw, kLd, 1, v + 2, tmp);
+  }
   if (threadIdx.x != 0) return;
-  double s = 0.0;
-  for (int b = 0; b < (int)gridDim.x; ++b) s += partial[b];
-  if (!isfinite(s)) {
-    st->active = 0;
+  const double rz = v[0];
+  if (first) {
+    sc[2] = 0.0;
+    sc[0] = rz;
+    if (!isfinite(rz)) st->active = 0;
     return;
   }
-  sc[2] = first ? 0.0 : s / sc[0];
-  sc[0] = s;
+  const double res = sqrt(v[1]);
+  sc[2] = rz / sc[0];
+  sc[0] = rz;
+  st->res = res;
+  st->j += 1;
+  if (res <= st->tol || st->j >= st->restart || !(v[2] > 0.0) || !isfinite(res) || !isfinite(rz))
+    st->active = 0;
 }
 
 __global__ void k_pcg_p(long long n, const double* __restrict__ z, double* __restrict__ p,
@@ -537,33 +589,6 @@ __global__ void k_pcg_p(long long n, const double* __restrict__ z, double* __res
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   p[i] = z[i] + sc[2] * p[i];
-}
-
-// r = b - r (r holds Acal^T x on entry); |r| -> st->rnorm and st->res;
-// j = 0; active = (|r| > tol).
-__global__ void __launch_bounds__(256) k_pcg_residual(long long n, const double* __restrict__ b,
-                                                      double* __restrict__ r, double* __restrict__ partial,
-                                                      unsigned* counter, GmresState* __restrict__ st) {
-  __shared__ double lds[32];
-  __shared__ bool is_last;
-  double acc = 0.0;
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (long long)gridDim.x * blockDim.x) {
-    const double v = b[i] - r[i];
-    r[i] = v;
-    acc += v * v;
-  }
-  acc = block_sum(acc, lds);
-  if (threadIdx.x == 0) partial[blockIdx.x] = acc;
-  if (!last_block(counter, &is_last)) return;
-  if (threadIdx.x != 0) return;
-  double s = 0.0;
-  for (int b2 = 0; b2 < (int)gridDim.x; ++b2) s += partial[b2];
-  const double nrm = sqrt(s);
-  st->rnorm = nrm;
-  st->res = nrm;
-  st->j = 0;
-  st->active = (nrm > st->tol) ? 1 : 0;
 }
 
 // host-side launchers ------------------------------------------------------
@@ -649,17 +674,37 @@ void launch_to_f32(hipStream_t s, long long n, const double* a, float* out) {
 }
 
 int gm_blocks(long long n, int rpb) { return (int)((n + rpb - 1) / rpb); }
+int bsr_blocks(int nv, int lanes) { return (nv + 256 / lanes - 1) / (256 / lanes); }
 
-void launch_gm_dots(hipStream_t s, long long n, int rpb, const double* Vt, long long stride, const double* scale,
-                    GmresState* st, double* partial, unsigned* counter, double* hbuf) {
-  k_gm_dots<<<gm_blocks(n, rpb), 256, 0, s>>>(n, rpb, Vt, stride, scale, st, partial, counter, hbuf);
+template <class MT>
+static void bsr_dots_impl(hipStream_t s, int lanes, int nv, const int* rowptr, const int* col, const MT* val,
+                          const double* y, double* Vt, long long stride, const GmresState* st, int jfix,
+                          double* P) {
+  const unsigned g = (unsigned)bsr_blocks(nv, lanes);
+  switch (lanes) {
+    case 4: k_bsr_dots<MT, 4><<<g, 256, 0, s>>>(nv, rowptr, col, val, y, Vt, stride, st, jfix, P); break;
+    case 8: k_bsr_dots<MT, 8><<<g, 256, 0, s>>>(nv, rowptr, col, val, y, Vt, stride, st, jfix, P); break;
+    case 32: k_bsr_dots<MT, 32><<<g, 256, 0, s>>>(nv, rowptr, col, val, y, Vt, stride, st, jfix, P); break;
+    default: k_bsr_dots<MT, 16><<<g, 256, 0, s>>>(nv, rowptr, col, val, y, Vt, stride, st, jfix, P); break;
+  }
+}
+void launch_bsr_dots(hipStream_t s, int lanes, int nv, const int* rowptr, const int* col, const double* val,
+                     const double* y, double* Vt, long long stride, const GmresState* st, int jfix, double* P) {
+  bsr_dots_impl(s, lanes, nv, rowptr, col, val, y, Vt, stride, st, jfix, P);
+}
+void launch_bsr_dots(hipStream_t s, int lanes, int nv, const int* rowptr, const int* col, const float* val,
+                     const double* y, double* Vt, long long stride, const GmresState* st, int jfix, double* P) {
+  bsr_dots_impl(s, lanes, nv, rowptr, col, val, y, Vt, stride, st, jfix, P);
 }
 
-void launch_gm_update(hipStream_t s, long long n, int rpb, double* Vt, long long stride, double* scale,
-                      GmresState* st, double* partial, unsigned* counter, double* hbuf, double* H,
-                      double* cs, double* sn, double* gvec, int mode) {
-  k_gm_update<<<gm_blocks(n, rpb), 256, 0, s>>>(n, rpb, Vt, stride, scale, st, partial, counter, hbuf, H, cs,
-                                                sn, gvec, mode);
+void launch_gm_update(hipStream_t s, long long n, int rpb, double* Vt, long long stride, const double* scale,
+                      const GmresState* st, const double* Pin, int nbin, double* Pout, double* hbuf, int mode) {
+  k_gm_update<<<gm_blocks(n, rpb), 256, 0, s>>>(n, rpb, Vt, stride, scale, st, Pin, nbin, Pout, hbuf, mode);
+}
+
+void launch_gm_givens(hipStream_t s, GmresState* st, const double* P, int nb, double* scale, const double* hbuf,
+                      double* H, double* cs, double* sn, double* gvec) {
+  k_gm_givens<<<1, 256, 0, s>>>(st, P, nb, scale, hbuf, H, cs, sn, gvec);
 }
 
 void launch_gm_finish(hipStream_t s, long long n, const GmresState* st, const double* H,
@@ -673,37 +718,35 @@ void launch_axpy(hipStream_t s, long long n, double a, const double* x, double* 
   k_axpy<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, a, x, y);
 }
 
-void launch_residual(hipStream_t s, long long n, const double* b, double* r, double* v0, double* partial,
-                     unsigned* counter, GmresState* st, double* scale, double* gvec) {
-  int blocks = (int)((n + 255) / 256);
-  if (blocks > 256) blocks = 256;
-  k_residual<<<blocks, 256, 0, s>>>(n, b, r, v0, partial, counter, st, scale, gvec);
-}
-
-static int pcg_blocks(long long n) {
-  long long b = (n + 255) / 256;
+int vec_blocks(long long n) {
+  const long long b = (n + 255) / 256;
   return (int)(b < 512 ? b : 512);
 }
 
-void launch_pcg_alpha(hipStream_t s, long long n, const double* p, const double* w, double* partial,
-                      unsigned* counter, GmresState* st, double* sc) {
-  k_pcg_alpha<<<pcg_blocks(n), 256, 0, s>>>(n, p, w, partial, counter, st, sc);
+// r = b - r, v0 = r (when given), |r| into the state (and the GMRES start
+// vector scale and g when scale is given)
+void launch_residual(hipStream_t s, long long n, const double* b, double* r, double* v0, double* P,
+                     GmresState* st, double* scale, double* gvec) {
+  const int nb = vec_blocks(n);
+  k_residual<<<nb, 256, 0, s>>>(n, b, r, v0, P);
+  k_residual_finish<<<1, 256, 0, s>>>(P, nb, st, scale, gvec);
 }
+
 void launch_pcg_xr(hipStream_t s, long long n, double* x, double* r, const double* p, const double* w,
-                   double* partial, unsigned* counter, GmresState* st, const double* sc) {
-  k_pcg_xr<<<pcg_blocks(n), 256, 0, s>>>(n, x, r, p, w, partial, counter, st, sc);
+                   const double* Ppw, int nbpw, const GmresState* st, const double* sc, double* Prr) {
+  k_pcg_xr<<<vec_blocks(n), 256, 0, s>>>(n, x, r, p, w, Ppw, nbpw, st, sc, Prr);
 }
-void launch_pcg_beta(hipStream_t s, long long n, const double* r, const double* z, double* partial,
-                     unsigned* counter, GmresState* st, double* sc, int first) {
-  k_pcg_beta<<<pcg_blocks(n), 256, 0, s>>>(n, r, z, partial, counter, st, sc, first);
+void launch_dot_partials(hipStream_t s, long long n, const double* a, const double* b, const GmresState* st,
+                         double* P) {
+  k_dot_partials<<<vec_blocks(n), 256, 0, s>>>(n, a, b, st, P);
+}
+void launch_pcg_scalar(hipStream_t s, GmresState* st, const double* Prz, int nbrz, const double* Prr, int nbrr,
+                       const double* Ppw, int nbpw, double* sc, int first) {
+  k_pcg_scalar<<<1, 256, 0, s>>>(st, Prz, nbrz, Prr, nbrr, Ppw, nbpw, sc, first);
 }
 void launch_pcg_p(hipStream_t s, long long n, const double* z, double* p, const GmresState* st,
                   const double* sc) {
   k_pcg_p<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, z, p, st, sc);
-}
-void launch_pcg_residual(hipStream_t s, long long n, const double* b, double* r, double* partial,
-                         unsigned* counter, GmresState* st) {
-  k_pcg_residual<<<pcg_blocks(n), 256, 0, s>>>(n, b, r, partial, counter, st);
 }
 
 }  // namespace adj

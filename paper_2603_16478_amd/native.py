@@ -29,7 +29,7 @@ EXPORTS = ("adj_scene_create", "adj_scene_destroy", "adjoint_setup", "adjoint_so
            "adj_profile_begin", "adj_profile_end", "adj_forward_stats", "adj_forward_reset",
            "adj_set_tuning", "adj_get_tuning", "adj_autotune", "adj_last_error")
 KERNELS = {"S": 0, "ST": 1, "capinv": 2, "Z": 3, "bsr": 4, "tet": 5, "assemble": 6, "gj": 7,
-           "gs_dots": 8, "gs_update": 9}
+           "gs_pass2": 8, "gs_pass1": 9}
 
 
 class AdjError(RuntimeError):
