@@ -162,12 +162,41 @@ constexpr int kNB = 32;
 
 // Inverse of the 32x32 pivot block by one wavefront, row per lane: lane r
 // (r < 32) holds row r of A_kk, lane 32 + r row r of the identity.  Step k
-// picks the unused row with the largest |A[r][k]| (argmax by shuffles, lower
-// row on ties), broadcasts that row through LDS and eliminates column k from
-// every other row.  Rows are never swapped: with p_k the row chosen at step
-// k, the eliminated A part is a permutation and row k of the inverse is row
-// p_k of the transformed identity.  The column index is a template
-// parameter, so every register index is static.
+// picks the unused row with the largest |A[r][k]| (lower row on ties),
+// broadcasts that row through LDS and eliminates column k from every other
+// row.  Rows are never swapped: with p_k the row chosen at step k, the
+// eliminated A part is a permutation and row k of the inverse is row p_k of
+// the transformed identity.  The argmax runs on DPP lane moves inside each
+// 16-lane row (quad xor 1, quad xor 2, half-row mirror, row mirror) and one
+// readlane per row, so the step's critical path stays in the vector ALU.
+// The column index is a template parameter, so register indices are static.
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+template <int CTRL>
+__device__ __forceinline__ void argmax_dpp(double& key, int& idx) {
+  const double k2 = dpp_d<CTRL>(key);
+  const int i2 = __builtin_amdgcn_update_dpp(0, idx, CTRL, 0xF, 0xF, false);
+  const bool take = (k2 > key) | ((k2 == key) & (i2 < idx));
+  key = take ? k2 : key;
+  idx = take ? i2 : idx;
+}
+
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  return __hiloint2double(hi, lo);
+}
+
+constexpr int kDppXor1 = 0xB1;        // quad_perm [1,0,3,2]
+constexpr int kDppXor2 = 0x4E;        // quad_perm [2,3,0,1]
+constexpr int kDppHalfMirror = 0x141; // lane i <-> 7 - i within each 8 lanes
+constexpr int kDppMirror = 0x140;     // lane i <-> 15 - i within each 16 lanes
+
 template <int K>
 __device__ __forceinline__ void gj_rows_step(double (&x)[kNB], bool& used, int& step_of_row, bool& bad,
                                              double* __restrict__ prow) {
@@ -176,29 +205,28 @@ __device__ __forceinline__ void gj_rows_step(double (&x)[kNB], bool& used, int& 
   const double ak = __shfl(x[K], r, 64);
   double key = used ? -1.0 : fabs(ak);
   int idx = r;
-#pragma unroll
-  for (int o = 16; o > 0; o >>= 1) {
-    const double k2 = __shfl_xor(key, o, 64);
-    const int i2 = __shfl_xor(idx, o, 64);
-    const bool take = (k2 > key) | ((k2 == key) & (i2 < idx));
-    key = take ? k2 : key;
-    idx = take ? i2 : idx;
-  }
-  const int p = __builtin_amdgcn_readfirstlane(idx);
-  const double best = __shfl(key, 0, 64);
+  argmax_dpp<kDppXor1>(key, idx);
+  argmax_dpp<kDppXor2>(key, idx);
+  argmax_dpp<kDppHalfMirror>(key, idx);
+  argmax_dpp<kDppMirror>(key, idx);
+  const double k0 = readlane_d(key, 0), k1 = readlane_d(key, 16);
+  const int i0 = __builtin_amdgcn_readlane(idx, 0), i1 = __builtin_amdgcn_readlane(idx, 16);
+  const bool second = (k1 > k0) | ((k1 == k0) & (i1 < i0));
+  const int p = second ? i1 : i0;
+  const double best = second ? k1 : k0;
   if (!(best > 0.0) || !isfinite(best)) bad = true;
+  const double inv = 1.0 / readlane_d(ak, p);
   // broadcast the pivot row: A part to prow[0..31], identity part to prow[32..63]
-  if (r == p) {
+  const bool piv = (r == p);
+  if (piv) {
 #pragma unroll
     for (int c = 0; c < kNB; ++c) prow[(lane & 32) + c] = x[c];
   }
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  const double inv = 1.0 / prow[K];
   const double* pr = prow + (lane & 32);
   // pivot row: x <- x / a_pk (= x + (1/a_pk - 1) x, its own row); others:
   // x <- x - (a_rk / a_pk) pivot row.  One FMA per entry, no divergence.
-  const bool piv = (r == p);
   const double g = piv ? inv - 1.0 : -ak * inv;
 #pragma unroll
   for (int c = 0; c < kNB; ++c) x[c] = fma(g, pr[c], x[c]);
