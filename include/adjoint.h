@@ -244,6 +244,59 @@ adj_status adj_get_tuning(const adj_scene* scene, adj_tuning* t);
 adj_status adj_autotune(adj_scene* scene, const double* dL_dq, const double* dL_dv, double* z,
                         const adj_solve_opts* opts, int32_t reps, adj_tuning* best, void* stream);
 
+/* ---- Batched solves: many independent scenes, one launch per phase ----
+ * The scenes are packed into one disjoint union, so per-tet, per-contact and
+ * sparse-matrix work of all scenes runs in single launches; each scene keeps
+ * its own Woodbury capacitance and its own GMRES (Sec. 5.4), and the Krylov
+ * cycles of all scenes run in lockstep with a per-scene convergence mask.
+ * Packed arrays: the vertices (and DOFs) of scene s occupy [voff[s],
+ * voff[s+1]) in scene order (adj_batch_info). */
+typedef struct adj_batch adj_batch; /* opaque */
+
+/* descs: host [n_scenes], each as for adj_scene_create (the scenes must share
+ * density, h and eps); max_contacts: host [n_scenes].  Errors as for
+ * adj_scene_create. */
+adj_status adj_batch_create(int32_t n_scenes, const adj_scene_desc* descs, const int32_t* max_contacts,
+                            adj_batch** out);
+adj_status adj_batch_destroy(adj_batch* batch);
+
+/* out: host int64 [2 * (n_scenes + 1)]: vertex offsets, then tet offsets. */
+adj_status adj_batch_info(const adj_batch* batch, int64_t* out);
+
+/* Per-scene setup (a1-a4 for every scene): contacts: host [n_scenes] of
+ * contact states (device arrays, vertex ids local to the scene, sorted; mu
+ * per scene); q: device packed [n_verts_total * 3].  A scene may have at
+ * most 8192 capacitance rows and 2730 contact vertices (ADJ_E_SHAPE). */
+adj_status adj_batch_setup(adj_batch* batch, const adj_contact_state* contacts, const double* q,
+                           const adj_solve_opts* opts, void* stream);
+
+/* One GMRES per scene on Acal_s^T z_s = dL_dq_s + dL_dv_s / h to opts->rtol
+ * (each scene's own right-hand side norm); ADJ_MIXED as for adjoint_solve.
+ * dL_dq, dL_dv, z: device packed; info: host [n_scenes] or NULL.
+ * ADJ_E_NOCONV if any scene did not converge (z holds the best iterate). */
+adj_status adj_batch_solve(adj_batch* batch, const double* dL_dq, const double* dL_dv, double* z,
+                           const adj_solve_opts* opts, adj_solve_info* info, void* stream);
+
+/* Gradient contractions of every scene (as vjp_params): packed vectors;
+ * grad: device [n_scenes * 3] (dL/dE, dL/dnu, dL/dmu), accumulated (+=). */
+adj_status adj_batch_vjp(adj_batch* batch, const double* z, const double* dL_dv, double* dL_dqbar,
+                         double* dL_dvbar, double* dL_dfext, double* grad, void* stream);
+
+/* As adj_check_status, for the batch's last setup. */
+adj_status adj_batch_check_status(adj_batch* batch, void* stream);
+
+/* Diagnostics (synchronises the device): copy an array of one scene of the
+ * last setup to host memory.  what = 0: Delassus matrix [n_cv][n_cv];
+ * 1: capacitance inverse [mp][mp]; 2: Z = A^{-1} E [n_verts][n_cv]; 3: Y = S E
+ * [n_verts][n_cv].  *size_bytes receives the size; ADJ_E_SHAPE when
+ * capacity_bytes is smaller.  For tests and debugging. */
+adj_status adj_batch_debug_export(const adj_batch* batch, int32_t what, int32_t scene, void* host_out,
+                                  int64_t capacity_bytes, int64_t* size_bytes);
+
+/* The union scene of the batch (owned by the batch; valid until
+ * adj_batch_destroy), for adj_debug_export and adj_scene_info. */
+adj_status adj_batch_scene(adj_batch* batch, adj_scene** out);
+
 const char* adj_last_error(void);
 
 #ifdef __cplusplus

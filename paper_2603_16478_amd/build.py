@@ -16,7 +16,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libadjoint.so")
 
 HIP_SOURCES = ["kernels_elastic.hip", "kernels_contact.hip", "kernels_dense.hip", "kernels_krylov.hip",
-               "kernels_forward.hip", "api.hip"]
+               "kernels_forward.hip", "kernels_batch.hip", "api.hip"]
 CPP_SOURCES = ["host_scene.cpp"]
 
 HIPCC_FLAGS = [

@@ -13,13 +13,10 @@
 
 #include "adjoint.h"
 #include "host_scene.h"
+#include "krylov_state.h"
 
 namespace adj {
 
-struct GmresState {
-  int j, active, restart, pad;
-  double tol, res, rnorm;
-};
 
 // kernels (defined in the .hip kernel files)
 void launch_tet_blocks(hipStream_t, int, const int*, const double*, const double*, const double*,
@@ -30,12 +27,13 @@ void launch_vjp_tets(hipStream_t, int, const int*, const double*, const double*,
                      const double*, const double*, const double*, double, const double*, const double*,
                      double*, double*, double*, double*);
 void launch_contact_blocks(hipStream_t, int, const int*, const double*, const double*, const double*,
-                           double, double, double, int, double*, double*, double*, double*, double*);
+                           double, const double*, double, double, int, double*, double*, double*, double*,
+                           double*);
 void launch_contact_fold(hipStream_t, int, const int*, const int*, const double*, double*);
 void launch_capacitance(hipStream_t, int, int, const int*, const int*, const int*, int, const double*,
                         const double*, const double*, double, double, int, double*);
 void launch_vjp_contacts(hipStream_t, int, const int*, const double*, const double*, const double*,
-                         const double*, double, double*, double*, double*);
+                         const double*, double, double*, double*, double*, double*);
 void launch_vjp_vectors(hipStream_t, int, const double*, const double*, const double*, double, double*,
                         double*, double*);
 void launch_fill_zero(hipStream_t, size_t, double*);
@@ -555,7 +553,7 @@ extern "C" adj_status adjoint_setup(adj_scene* s, const adj_contact_state* cst, 
                     s->d_mass, s->d_val);
   }
   // a3: contact blocks folded into the diagonal blocks of Acal^T
-  launch_contact_blocks(st, nc, cst->fric, cst->frame, cst->delta, cst->lambda, cst->mu, s->hs.eps, h2, 1,
+  launch_contact_blocks(st, nc, cst->fric, cst->frame, cst->delta, cst->lambda, cst->mu, nullptr, s->hs.eps, h2, 1,
                         s->d_Wt, s->d_Q, s->d_kh, s->d_Kc, s->d_kmu);
   launch_contact_fold(st, nc, cst->vid, s->d_diag_slot, s->d_Wt, s->d_val);
   // a4: Delassus (cached per contact vertex set), capacitance, its inverse
@@ -938,7 +936,7 @@ extern "C" adj_status vjp_params(adj_scene* s, const double* z, const double* dL
   const double h = s->hs.h, h2 = h * h;
   launch_vjp_vectors(st, s->nv, z, dL_dv, s->d_mass, h, dL_dqbar, dL_dvbar, dL_dfext);
   launch_vjp_contacts(st, s->nc, s->cur_vid, s->cur_frame, s->d_Kc, s->d_kmu, z, h2, dL_dqbar,
-                      s->P1(), grad3);
+                      s->P1(), grad3, nullptr);
   launch_vjp_tets(st, s->nt, s->d_tets, s->d_Bt, s->d_vol, s->d_lmu, s->d_llam, s->d_E, s->d_nu, h2,
                   s->cur_q, z, dE_tet, dnu_tet, s->P2(), grad3);
   HIPCHK(hipGetLastError());
@@ -1541,3 +1539,5 @@ extern "C" adj_status adj_forward_reset(adj_scene* s) {
   s->warm.clear();
   return ADJ_OK;
 }
+
+#include "api_batch.inc"

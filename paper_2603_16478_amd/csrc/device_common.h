@@ -57,4 +57,24 @@ __device__ __forceinline__ bool last_block(unsigned* counter, bool* flag_lds) {
   return last;
 }
 
+// res[i] = sum_b P[b * ld + i] for i < cnt (cnt <= 256), fixed order; all
+// 256 threads of the block take part; tmp: 256 doubles of LDS.
+__device__ __forceinline__ void sum_partials(const double* __restrict__ P, int nb, int ld, int cnt,
+                                             double* __restrict__ res, double* __restrict__ tmp) {
+  int G = 1;
+  while (2 * G * cnt <= 256) G *= 2;  // threads per entry (power of two)
+  const int t = threadIdx.x, i = t / G, g = t % G;
+  double a = 0.0;
+  if (i < cnt)
+    for (int b = g; b < nb; b += G) a += P[(size_t)b * ld + i];
+  tmp[t] = a;
+  __syncthreads();
+  for (int h = G / 2; h > 0; h >>= 1) {
+    if (g < h && i < cnt) tmp[t] += tmp[t + h];
+    __syncthreads();
+  }
+  if (g == 0 && i < cnt) res[i] = tmp[t];
+  __syncthreads();
+}
+
 }  // namespace adj

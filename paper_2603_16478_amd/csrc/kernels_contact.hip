@@ -40,12 +40,14 @@ __device__ __forceinline__ double fb_ratio(double x, double y, double e2) {
 //   kmu[3] k_mu = R^T [0, lambda_n, 0] in frame coordinates
 __global__ void k_contact_blocks(int nc, const int* __restrict__ fric, const double* __restrict__ frame,
                                  const double* __restrict__ delta, const double* __restrict__ lam,
-                                 double mu, double eps, double h2, int transpose,
+                                 double mu_all, const double* __restrict__ mu_c, double eps, double h2,
+                                 int transpose,
                                  double* __restrict__ Wt, double* __restrict__ Q,
                                  double* __restrict__ kh, double* __restrict__ Kc,
                                  double* __restrict__ kmu) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= nc) return;
+  const double mu = mu_c ? mu_c[c] : mu_all;  // per-contact coefficient (batched scenes)
   const double e2 = 2.0 * eps * eps;
   const double dn = delta[3 * c], ln = lam[3 * c];
   const double a = fb_ratio(dn, ln, e2);
@@ -155,7 +157,8 @@ __global__ void __launch_bounds__(256) k_vjp_contacts(int nc, const int* __restr
                                                       const double* __restrict__ kmu,
                                                       const double* __restrict__ z, double h2,
                                                       double* __restrict__ dqbar,
-                                                      double* __restrict__ partial) {
+                                                      double* __restrict__ partial,
+                                                      double* __restrict__ gmu_c) {
   __shared__ double lds[32];
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   double gmu = 0.0;
@@ -166,6 +169,7 @@ __global__ void __launch_bounds__(256) k_vjp_contacts(int nc, const int* __restr
     for (int i = 0; i < 3; ++i)
       Hz[i] = frame[9 * c + 3 * i] * zv[0] + frame[9 * c + 3 * i + 1] * zv[1] + frame[9 * c + 3 * i + 2] * zv[2];
     gmu = -h2 * (Hz[0] * kmu[3 * c] + Hz[1] * kmu[3 * c + 1] + Hz[2] * kmu[3 * c + 2]);
+    if (gmu_c) gmu_c[c] = gmu;
     if (!(c > 0 && vid[c - 1] == v)) {  // first contact of the vertex adds the group
       double add[3] = {0, 0, 0};
       for (int k = c; k < nc && vid[k] == v; ++k) {
@@ -200,10 +204,11 @@ __global__ void k_vjp_vectors(int nv, const double* __restrict__ z, const double
 }
 
 void launch_contact_blocks(hipStream_t st, int nc, const int* fric, const double* frame,
-                           const double* delta, const double* lam, double mu, double eps, double h2,
-                           int transpose, double* Wt, double* Q, double* kh, double* Kc, double* kmu) {
+                           const double* delta, const double* lam, double mu, const double* mu_c, double eps,
+                           double h2, int transpose, double* Wt, double* Q, double* kh, double* Kc,
+                           double* kmu) {
   if (nc == 0) return;
-  k_contact_blocks<<<(nc + 63) / 64, 64, 0, st>>>(nc, fric, frame, delta, lam, mu, eps, h2, transpose,
+  k_contact_blocks<<<(nc + 63) / 64, 64, 0, st>>>(nc, fric, frame, delta, lam, mu, mu_c, eps, h2, transpose,
                                                    Wt, Q, kh, Kc, kmu);
 }
 
@@ -223,11 +228,11 @@ void launch_capacitance(hipStream_t st, int m, int mp, const int* row_c, const i
 
 void launch_vjp_contacts(hipStream_t st, int nc, const int* vid, const double* frame, const double* Kc,
                          const double* kmu, const double* z, double h2, double* dqbar, double* partial,
-                         double* grad) {
+                         double* grad, double* gmu_c) {
   if (nc == 0) return;
   const int nb = (nc + 255) / 256;
-  k_vjp_contacts<<<nb, 256, 0, st>>>(nc, vid, frame, Kc, kmu, z, h2, dqbar, partial);
-  launch_add_partials(st, partial, nb, 1, grad + 2);
+  k_vjp_contacts<<<nb, 256, 0, st>>>(nc, vid, frame, Kc, kmu, z, h2, dqbar, partial, gmu_c);
+  if (grad) launch_add_partials(st, partial, nb, 1, grad + 2);
 }
 
 void launch_vjp_vectors(hipStream_t st, int nv, const double* z, const double* gv, const double* mass,

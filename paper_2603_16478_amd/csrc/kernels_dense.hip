@@ -275,15 +275,22 @@ __device__ __forceinline__ void invert32_rows(const double* __restrict__ Akk, in
 // with 2x2 (What) and 2x2 (update) accumulator tiles per wave.
 constexpr int kGT = 64;
 
-__global__ void __launch_bounds__(256) k_gj_step_mfma(int mp, int k0, const double* __restrict__ A,
-                                                      double* __restrict__ B, int* __restrict__ err) {
-  __shared__ double Ps[kNB][kNB + 1];   // P = A_kk^{-1}
-  __shared__ double Cs[kGT][kNB + 1];   // A_{I,k} (tile rows, pivot columns)
-  __shared__ double Rs[kNB][kGT + 1];   // Rhat (pivot rows, tile columns)
-  __shared__ double Ws[kGT][kNB + 1];   // -What
-  __shared__ double prow[2 * kNB];      // pivot row broadcast of the block inversion
+struct GjShared {
+  double Ps[kNB][kNB + 1];   // P = A_kk^{-1}
+  double Cs[kGT][kNB + 1];   // A_{I,k} (tile rows, pivot columns)
+  double Rs[kNB][kGT + 1];   // Rhat (pivot rows, tile columns)
+  double Ws[kGT][kNB + 1];   // -What
+  double prow[2 * kNB];      // pivot row broadcast of the block inversion
+};
+
+// One 64x64 output tile (I0, J0) of the block step at pivot k0.
+__device__ __forceinline__ void gj_tile(int mp, int k0, int I0, int J0, const double* __restrict__ A,
+                                        double* __restrict__ B, int* __restrict__ err, GjShared& sh) {
+  auto& Ps = sh.Ps;
+  auto& Cs = sh.Cs;
+  auto& Rs = sh.Rs;
+  auto& Ws = sh.Ws;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int I0 = blockIdx.y * kGT, J0 = blockIdx.x * kGT;
   const int li = lane & 15, lk = lane >> 4;
   // output sub-tiles of this wave: rows wr + 16 p, cols wc + 16 q (p, q < 2)
   const int wr = 32 * (w >> 1), wc = 32 * (w & 1);
@@ -300,7 +307,7 @@ __global__ void __launch_bounds__(256) k_gj_step_mfma(int mp, int k0, const doub
         const bool zero = (i >= k0 && i < k0 + kNB) || (j >= k0 && j < k0 + kNB);
         acc[p][q][e] = zero ? 0.0 : A[(size_t)i * mp + j];
       }
-  if (w == 0) invert32_rows(A + (size_t)k0 * mp + k0, mp, Ps, prow, err);
+  if (w == 0) invert32_rows(A + (size_t)k0 * mp + k0, mp, Ps, sh.prow, err);
   for (int e = tid; e < kGT * kNB; e += 256) {
     const int r = e / kNB, c = e % kNB;
     Cs[r][c] = A[(size_t)(I0 + r) * mp + k0 + c];
@@ -358,6 +365,25 @@ __global__ void __launch_bounds__(256) k_gj_step_mfma(int mp, int k0, const doub
         const int j = J0 + wc + 16 * q + li;
         B[(size_t)i * mp + j] = acc[p][q][e];
       }
+}
+
+__global__ void __launch_bounds__(256) k_gj_step_mfma(int mp, int k0, const double* __restrict__ A,
+                                                      double* __restrict__ B, int* __restrict__ err) {
+  __shared__ GjShared sh;
+  gj_tile(mp, k0, blockIdx.y * kGT, blockIdx.x * kGT, A, B, err, sh);
+}
+
+// Batched block step: tile list entries {scene, I tile, J tile, -} of the
+// scenes whose padded size exceeds k0; the scene's matrix starts at
+// A + xoff[s] (and B + xoff[s]) with row length mps[s].
+__global__ void __launch_bounds__(256) kb_gj_step_mfma(const int4* __restrict__ tiles, int k0,
+                                                       const long long* __restrict__ xoff,
+                                                       const int* __restrict__ mps, const double* __restrict__ A,
+                                                       double* __restrict__ B, int* __restrict__ err) {
+  __shared__ GjShared sh;
+  const int4 e = tiles[blockIdx.x];
+  const long long o = xoff[e.x];
+  gj_tile(mps[e.x], k0, e.y * kGT, e.z * kGT, A + o, B + o, err, sh);
 }
 
 // identity padding of rows/cols m..mp-1 of a row-major mp x mp matrix
@@ -421,6 +447,11 @@ double* launch_gauss_jordan(hipStream_t st, int m, int mp, double* C0, double* C
     B = t;
   }
   return A;
+}
+
+void launchb_gj_step(hipStream_t st, int ntiles, const int4* tiles, int k0, const long long* xoff, const int* mps,
+                     const double* A, double* B, int* err) {
+  if (ntiles) kb_gj_step_mfma<<<ntiles, 256, 0, st>>>(tiles, k0, xoff, mps, A, B, err);
 }
 
 }  // namespace adj

@@ -261,7 +261,7 @@ void launch_vjp_tets(hipStream_t st, int nt, const int* tets, const double* Bt, 
                      double* partial, double* grad) {
   const int nb = (nt + 255) / 256;
   k_vjp_tets<<<nb, 256, 0, st>>>(nt, tets, Bt, vol, lmu, llam, Ev, nuv, h2, q, z, dE_tet, dnu_tet, partial);
-  launch_add_partials(st, partial, nb, 2, grad);
+  if (grad) launch_add_partials(st, partial, nb, 2, grad);
 }
 
 }  // namespace adj

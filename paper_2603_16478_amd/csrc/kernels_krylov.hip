@@ -13,18 +13,10 @@
 // launch a chunk of iterations without reading anything back; kernels of an
 // inactive cycle return immediately.
 #include "device_common.h"
+#include "krylov_state.h"
 
 namespace adj {
 
-struct GmresState {
-  int j;          // completed iterations of this cycle
-  int active;     // 1 while the cycle runs
-  int restart;
-  int pad;
-  double tol;     // absolute tolerance on the residual estimate
-  double res;     // current residual estimate |g_{j}|
-  double rnorm;   // true residual norm (restart checks)
-};
 
 __device__ __forceinline__ bool gm_inactive(const GmresState* s) { return s && s->active == 0; }
 
@@ -252,26 +244,6 @@ __global__ void __launch_bounds__(256) k_bsr_spmv(int nv, const int* __restrict_
 // atomic counter) serialises the blocks on this multi-die GPU and costs
 // more than one extra launch.
 constexpr int kLd = 130;  // partials of one block: [0 .. 129], basis index i
-
-// res[i] = sum_b P[b * ld + i] for i < cnt (cnt <= 130), fixed order; all
-// 256 threads of the block take part; tmp: 256 doubles of LDS.
-__device__ __forceinline__ void sum_partials(const double* __restrict__ P, int nb, int ld, int cnt,
-                                             double* __restrict__ res, double* __restrict__ tmp) {
-  int G = 1;
-  while (2 * G * cnt <= 256) G *= 2;  // threads per entry (power of two)
-  const int t = threadIdx.x, i = t / G, g = t % G;
-  double a = 0.0;
-  if (i < cnt)
-    for (int b = g; b < nb; b += G) a += P[(size_t)b * ld + i];
-  tmp[t] = a;
-  __syncthreads();
-  for (int h = G / 2; h > 0; h >>= 1) {
-    if (g < h && i < cnt) tmp[t] += tmp[t + h];
-    __syncthreads();
-  }
-  if (g == 0 && i < cnt) res[i] = tmp[t];
-  __syncthreads();
-}
 
 // w = Acal^T y fused with the first Gram-Schmidt pass: the block writes its
 // rows of w = Vt_{j+1} and the partial dots Vt_i . w over those rows

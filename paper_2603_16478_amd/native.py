@@ -27,7 +27,9 @@ ADJ_AUTO, ADJ_GMRES, ADJ_PCG = 0, 1, 2
 EXPORTS = ("adj_scene_create", "adj_scene_destroy", "adjoint_setup", "adjoint_solve", "vjp_params",
            "sim_forward_step", "adj_scene_info", "adj_check_status", "adj_debug_export",
            "adj_profile_begin", "adj_profile_end", "adj_forward_stats", "adj_forward_reset",
-           "adj_set_tuning", "adj_get_tuning", "adj_autotune", "adj_last_error")
+           "adj_set_tuning", "adj_get_tuning", "adj_autotune", "adj_batch_create", "adj_batch_destroy",
+           "adj_batch_info", "adj_batch_setup", "adj_batch_solve", "adj_batch_vjp", "adj_batch_check_status",
+           "adj_batch_debug_export", "adj_batch_scene", "adj_last_error")
 KERNELS = {"S": 0, "ST": 1, "capinv": 2, "Z": 3, "bsr": 4, "tet": 5, "assemble": 6, "gj": 7,
            "gs_pass2": 8, "gs_pass1": 9}
 
@@ -100,6 +102,15 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.adj_set_tuning.argtypes = [vp, C.POINTER(Tuning)]
     lib.adj_get_tuning.argtypes = [vp, C.POINTER(Tuning)]
     lib.adj_autotune.argtypes = [vp, vp, vp, vp, C.POINTER(SolveOpts), C.c_int32, C.POINTER(Tuning), vp]
+    lib.adj_batch_create.argtypes = [C.c_int32, C.POINTER(SceneDesc), C.POINTER(C.c_int32), C.POINTER(vp)]
+    lib.adj_batch_destroy.argtypes = [vp]
+    lib.adj_batch_info.argtypes = [vp, C.POINTER(C.c_int64)]
+    lib.adj_batch_setup.argtypes = [vp, C.POINTER(ContactState), vp, C.POINTER(SolveOpts), vp]
+    lib.adj_batch_solve.argtypes = [vp, vp, vp, vp, C.POINTER(SolveOpts), C.POINTER(SolveInfo), vp]
+    lib.adj_batch_vjp.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.adj_batch_check_status.argtypes = [vp, vp]
+    lib.adj_batch_debug_export.argtypes = [vp, C.c_int32, C.c_int32, vp, C.c_int64, C.POINTER(C.c_int64)]
+    lib.adj_batch_scene.argtypes = [vp, C.POINTER(vp)]
     for name in EXPORTS:
         if name != "adj_last_error":
             getattr(lib, name).restype = C.c_int
@@ -302,3 +313,85 @@ def autotune(scene: Scene, dL_dq, dL_dv, z, opts: SolveOpts, reps=3, stream=None
     check(load().adj_autotune(scene.handle, _ptr(dL_dq), _ptr(dL_dv), _ptr(z), C.byref(opts), int(reps),
                               C.byref(t), _stream(stream)))
     return t.as_dict()
+
+
+class Batch:
+    """Owns an adj_batch: several scenes solved together (adj_batch_create).
+    specs: sequence of (rest, tets, E, nu); density, h, eps are shared."""
+
+    def __init__(self, specs, density, h, eps, gravity, planes, contact_margin, max_contacts):
+        lib = load()
+        self._keep = []
+        n = len(specs)
+        descs = (SceneDesc * n)()
+        planes = np.ascontiguousarray(np.asarray(planes, dtype=np.float64).reshape(-1, 4))
+        self._keep.append(planes)
+        for k, (rest, tets, E, nu) in enumerate(specs):
+            rest = np.ascontiguousarray(rest, dtype=np.float64)
+            tets = np.ascontiguousarray(tets, dtype=np.int32)
+            E = np.ascontiguousarray(np.atleast_1d(E), dtype=np.float64)
+            nu = np.ascontiguousarray(np.atleast_1d(nu), dtype=np.float64)
+            self._keep += [rest, tets, E, nu]
+            d = descs[k]
+            d.n_verts, d.n_tets = rest.shape[0], tets.shape[0]
+            d.rest_pos, d.tets = rest.ctypes.data, tets.ctypes.data
+            d.density, d.h, d.eps = float(density), float(h), float(eps)
+            d.E, d.nu = E.ctypes.data, nu.ctypes.data
+            d.per_tet_material = 1 if E.shape[0] == tets.shape[0] and tets.shape[0] > 1 else 0
+            d.gravity = (C.c_double * 3)(*[float(g) for g in gravity])
+            d.n_planes = planes.shape[0]
+            d.planes = planes.ctypes.data if planes.shape[0] else None
+            d.contact_margin = float(contact_margin)
+        mc = (C.c_int32 * n)(*[int(m) for m in max_contacts])
+        handle = C.c_void_p()
+        check(lib.adj_batch_create(n, descs, mc, C.byref(handle)))
+        self.handle, self.n_scenes = handle, n
+        out = (C.c_int64 * (2 * (n + 1)))()
+        check(lib.adj_batch_info(handle, out))
+        self.voff = np.array(list(out)[: n + 1], dtype=np.int64)
+        self.toff = np.array(list(out)[n + 1:], dtype=np.int64)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            check(load().adj_batch_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def batch_setup(batch: Batch, contacts, q, opts: SolveOpts, stream=None):
+    """contacts: list of ContactState (one per scene); q: packed device tensor."""
+    arr = (ContactState * batch.n_scenes)(*contacts)
+    check(load().adj_batch_setup(batch.handle, arr, _ptr(q), C.byref(opts), _stream(stream)))
+
+
+def batch_solve(batch: Batch, dL_dq, dL_dv, z, opts: SolveOpts, stream=None, raise_noconv=True):
+    infos = (SolveInfo * batch.n_scenes)()
+    st = load().adj_batch_solve(batch.handle, _ptr(dL_dq), _ptr(dL_dv), _ptr(z), C.byref(opts), infos,
+                                _stream(stream))
+    if st != 0 and (raise_noconv or STATUS.get(st) != "ADJ_E_NOCONV"):
+        check(st)
+    return list(infos)
+
+
+def batch_vjp(batch: Batch, z, dL_dv, dL_dqbar, dL_dvbar, dL_dfext, grad, stream=None):
+    check(load().adj_batch_vjp(batch.handle, _ptr(z), _ptr(dL_dv), _ptr(dL_dqbar), _ptr(dL_dvbar),
+                               _ptr(dL_dfext), _ptr(grad), _stream(stream)))
+
+
+def batch_check_status(batch: Batch, stream=None):
+    check(load().adj_batch_check_status(batch.handle, _stream(stream)))
+
+
+def batch_debug_export(batch: Batch, what: int, scene: int) -> np.ndarray:
+    lib = load()
+    size = C.c_int64()
+    lib.adj_batch_debug_export(batch.handle, int(what), int(scene), None, 0, C.byref(size))
+    out = np.empty(max(size.value, 8) // 8, dtype=np.float64)
+    check(lib.adj_batch_debug_export(batch.handle, int(what), int(scene), out.ctypes.data, out.nbytes,
+                                     C.byref(size)))
+    return out[: size.value // 8]
