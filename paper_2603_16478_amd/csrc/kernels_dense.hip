@@ -283,9 +283,12 @@ struct GjShared {
   double prow[2 * kNB];      // pivot row broadcast of the block inversion
 };
 
-// One 64x64 output tile (I0, J0) of the block step at pivot k0.
+// One 64x64 output tile (I0, J0) of the block step at pivot k0.  With
+// Pg == nullptr wavefront 0 inverts the pivot block itself; otherwise P is
+// read from Pg (32 x 32, row-major), inverted once per step beforehand.
 __device__ __forceinline__ void gj_tile(int mp, int k0, int I0, int J0, const double* __restrict__ A,
-                                        double* __restrict__ B, int* __restrict__ err, GjShared& sh) {
+                                        double* __restrict__ B, int* __restrict__ err, GjShared& sh,
+                                        const double* __restrict__ Pg = nullptr) {
   auto& Ps = sh.Ps;
   auto& Cs = sh.Cs;
   auto& Rs = sh.Rs;
@@ -307,7 +310,11 @@ __device__ __forceinline__ void gj_tile(int mp, int k0, int I0, int J0, const do
         const bool zero = (i >= k0 && i < k0 + kNB) || (j >= k0 && j < k0 + kNB);
         acc[p][q][e] = zero ? 0.0 : A[(size_t)i * mp + j];
       }
-  if (w == 0) invert32_rows(A + (size_t)k0 * mp + k0, mp, Ps, sh.prow, err);
+  if (Pg) {
+    for (int e = tid; e < kNB * kNB; e += 256) Ps[e / kNB][e % kNB] = Pg[e];
+  } else if (w == 0) {
+    invert32_rows(A + (size_t)k0 * mp + k0, mp, Ps, sh.prow, err);
+  }
   for (int e = tid; e < kGT * kNB; e += 256) {
     const int r = e / kNB, c = e % kNB;
     Cs[r][c] = A[(size_t)(I0 + r) * mp + k0 + c];
@@ -373,17 +380,35 @@ __global__ void __launch_bounds__(256) k_gj_step_mfma(int mp, int k0, const doub
   gj_tile(mp, k0, blockIdx.y * kGT, blockIdx.x * kGT, A, B, err, sh);
 }
 
-// Batched block step: tile list entries {scene, I tile, J tile, -} of the
-// scenes whose padded size exceeds k0; the scene's matrix starts at
-// A + xoff[s] (and B + xoff[s]) with row length mps[s].
+// Batched block step.  kb_gj_pivot: one wavefront per scene (list of the
+// scenes whose padded size exceeds k0) inverts the scene's pivot block into
+// Pb + 1024 s; kb_gj_step_mfma: tile list entries {scene, I tile, J tile, -},
+// the scene's matrix at A + xoff[s] (and B + xoff[s]) with row length
+// mps[s], P read from Pb.  Inverting once per scene keeps the serial pivot
+// chain out of every tile block.
+__global__ void __launch_bounds__(64) kb_gj_pivot(const int* __restrict__ scenes, int k0,
+                                                  const long long* __restrict__ xoff, const int* __restrict__ mps,
+                                                  const double* __restrict__ A, double* __restrict__ Pb,
+                                                  int* __restrict__ err) {
+  __shared__ double Ps[kNB][kNB + 1];
+  __shared__ double prow[2 * kNB];
+  const int s = scenes[blockIdx.x];
+  const int mp = mps[s];
+  invert32_rows(A + xoff[s] + (size_t)k0 * mp + k0, mp, Ps, prow, err);
+  __syncthreads();
+  double* P = Pb + (size_t)s * kNB * kNB;
+  for (int e = threadIdx.x; e < kNB * kNB; e += blockDim.x) P[e] = Ps[e / kNB][e % kNB];
+}
+
 __global__ void __launch_bounds__(256) kb_gj_step_mfma(const int4* __restrict__ tiles, int k0,
                                                        const long long* __restrict__ xoff,
                                                        const int* __restrict__ mps, const double* __restrict__ A,
-                                                       double* __restrict__ B, int* __restrict__ err) {
+                                                       double* __restrict__ B, const double* __restrict__ Pb,
+                                                       int* __restrict__ err) {
   __shared__ GjShared sh;
   const int4 e = tiles[blockIdx.x];
   const long long o = xoff[e.x];
-  gj_tile(mps[e.x], k0, e.y * kGT, e.z * kGT, A + o, B + o, err, sh);
+  gj_tile(mps[e.x], k0, e.y * kGT, e.z * kGT, A + o, B + o, err, sh, Pb + (size_t)e.x * kNB * kNB);
 }
 
 // identity padding of rows/cols m..mp-1 of a row-major mp x mp matrix
@@ -449,9 +474,11 @@ double* launch_gauss_jordan(hipStream_t st, int m, int mp, double* C0, double* C
   return A;
 }
 
-void launchb_gj_step(hipStream_t st, int ntiles, const int4* tiles, int k0, const long long* xoff, const int* mps,
-                     const double* A, double* B, int* err) {
-  if (ntiles) kb_gj_step_mfma<<<ntiles, 256, 0, st>>>(tiles, k0, xoff, mps, A, B, err);
+void launchb_gj_step(hipStream_t st, int nscenes, const int* scenes, int ntiles, const int4* tiles, int k0,
+                     const long long* xoff, const int* mps, const double* A, double* B, double* Pb, int* err) {
+  if (!ntiles) return;
+  kb_gj_pivot<<<nscenes, 64, 0, st>>>(scenes, k0, xoff, mps, A, Pb, err);
+  kb_gj_step_mfma<<<ntiles, 256, 0, st>>>(tiles, k0, xoff, mps, A, B, Pb, err);
 }
 
 }  // namespace adj
