@@ -2,16 +2,21 @@
 """Adjoint solves per second on one MI355X.
 
 Workload: the 32x8x8-cell Neo-Hookean beam (12,288 tets, 2,673 vertices,
-E = 1e6 Pa, nu = 0.45) lying on the ground and pushed sideways, at friction
-coefficients 1.0 (stick), 0.1 (slip) and 0.4 (mixed), plain FP64.  One step
-of this benchmark is one adjoint solve of one recorded scene-step: setup
-(per-tet SVD Jacobians, assembly, contact blocks, capacitance), the Krylov
-solve to a relative residual of 1e-8, and the gradient contractions.  The
-steps cycle over the recorded converged states of the three runs.
+E = 1e6 Pa, nu = 0.45) lying on the ground and pushed sideways, three runs at
+friction coefficients 1.0 (stick), 0.1 (slip) and 0.4 (mixed).  One adjoint
+solve = setup (per-tet SVD Jacobians, assembly, contact blocks, capacitance
+and its inverse), the Krylov solve to a relative residual of 1e-8 and the
+gradient contractions, on a recorded converged scene-step.
 
-Also reported: the roofline of the dominant kernel (algorithmic bytes per
-launch / average launch time, from HIP events on the launch stream over the
-timed region) and the oracle's rate on the host cores (a bounded sample).
+`value` is the whole-job rate: the three runs are independent, so one step of
+this benchmark solves the three runs' adjoints at the same time step as one
+batch (one launch per phase over all three scenes, one GMRES per scene), in
+plain FP64; it counts three solves.  Also reported: the same in mixed
+precision, each scene solved alone (FP64 and mixed), the roofline of the
+batched sparse-inverse product (algorithmic bytes per launch / average
+launch time from HIP events on the launch stream over the timed region,
+and the HBM traffic of the counter runs when the kernel source still matches
+them), and the oracle's rate on one host core (a bounded sample).
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
@@ -19,9 +24,10 @@ timed region) and the oracle's rate on the host cores (a bounded sample).
 from __future__ import annotations
 
 import argparse
-import glob
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -33,6 +39,8 @@ sys.path.insert(0, ROOT)
 METRIC = "adjoint solves/sec at rel. residual 1e-8, mixed vs plain FP64; matvec HBM GB/s"
 HBM_PEAK_GBPS = 8000.0
 MUS = (1.0, 0.1, 0.4)
+COUNTERS = os.path.join(ROOT, "profiles", "s_product_batched_beam_counters.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_2603_16478_amd", "csrc", "kernels_batch.hip")
 
 
 def load_states():
@@ -51,20 +59,34 @@ def load_states():
     return states
 
 
-def algorithmic_bytes(kernel, info, nc, m, ncv):
-    nv, nnzb, nnzS = info["n_verts"], info["nnz_blocks"], info["nnz_S"]
-    n3 = 3 * nv
-    if kernel in ("S", "ST"):
-        return nnzS * (8 + 4) + (nv + 1) * 8 + 2 * n3 * 8
-    if kernel == "bsr":
-        return nnzb * (72 + 4) + (nv + 1) * 4 + 2 * n3 * 8
-    if kernel == "capinv":
-        return m * m * 8 + m * 8 + n3 * 8
-    if kernel == "Z":
-        return nv * ncv * 8 + 2 * n3 * 8 + m * 8
-    if kernel == "tet":
-        return info["n_tets"] * (16 + 96 + 24 + 96 + 720)
-    raise ValueError(kernel)
+def s_product_bytes(info):
+    """Algorithmic bytes of one sparse-inverse product y = S x (3 right-hand
+    sides): values and column indices of S, row pointers, x and y."""
+    nv, nnzS = info["n_verts"], info["nnz_S"]
+    return nnzS * (8 + 4) + (nv + 1) * 8 + 2 * 3 * nv * 8
+
+
+def bsr_bytes(info):
+    nv, nnzb = info["n_verts"], info["nnz_blocks"]
+    return nnzb * (72 + 4) + (nv + 1) * 4 + 2 * 3 * nv * 8
+
+
+def kernel_source_hash():
+    """Hash of the batched sparse-inverse product kernel's source text."""
+    src = open(KERNEL_SRC).read()
+    m = re.search(r"__global__ void __launch_bounds__\(256\) kb_spmv_tasks.*?\n}\n", src, re.S)
+    return hashlib.sha1((m.group(0) if m else src).encode()).hexdigest()
+
+
+def measured_traffic():
+    """Calibrated HBM bytes per launch from the committed counter runs, or
+    None when the kernel changed since they were taken."""
+    if not os.path.exists(COUNTERS):
+        return None
+    d = json.load(open(COUNTERS))
+    if d.get("source_sha1") != kernel_source_hash():
+        return None
+    return d["bytes_per_launch"]
 
 
 def cpu_baseline(spec, states, sample):
@@ -94,10 +116,9 @@ def cpu_baseline(spec, states, sample):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=60)
-    ap.add_argument("--warmup", type=int, default=6)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=4)
     ap.add_argument("--rtol", type=float, default=1e-8)
-    ap.add_argument("--roofline-kernel", default="S", choices=["S", "ST", "bsr", "capinv", "Z", "tet"])
     ap.add_argument("--cpu-sample", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
@@ -116,10 +137,6 @@ def main():
     spec = beam_scene(mu=0.4)
     states = load_states()
     max_c = max(int(s["vid"].shape[0]) for s in states)
-    scene = native.Scene(spec.mesh.rest, spec.mesh.tets, spec.density, spec.h, spec.eps, spec.E, spec.nu,
-                         spec.gravity, spec.planes, spec.contact_margin, max_c)
-    info = scene.info()
-    # device copies of every recorded state
     dstates = []
     for st in states:
         n = int(st["vid"].shape[0])
@@ -130,170 +147,143 @@ def main():
              "lam": torch.tensor(st["lam"], dtype=torch.float64, device=dev),
              "q": torch.tensor(st["q"], dtype=torch.float64, device=dev)}
         t["cs"] = native.make_contact_state(n, t["vid"], t["fric"], t["frame"], t["delta"], t["lam"], st["mu"])
-        t["m"] = int(3 * st["fric"].sum() + (n - st["fric"].sum()))
-        t["ncv"] = int(np.unique(st["vid"]).shape[0])
         dstates.append(t)
     gq = torch.tensor(spec.loss_dir, dtype=torch.float64, device=dev)
     gv = torch.zeros_like(gq)
-    z = torch.zeros_like(gq)
-    dqbar, dvbar, dfext = torch.empty_like(gq), torch.empty_like(gq), torch.empty_like(gq)
-    grad3 = torch.zeros(3, dtype=torch.float64, device=dev)
-    opts = native.solve_opts(rtol=args.rtol, maxit=5000, restart=64)
 
-    tuning = native.get_tuning(scene)
-    if not args.no_autotune:
-        t0s = dstates[0]
-        native.adjoint_setup(scene, t0s["cs"], t0s["q"], opts)
-        tuning = native.autotune(scene, gq, gv, z, opts, reps=3)
-
-    iters = []
-
-    def one(i):
-        t = dstates[i % len(dstates)]
-        native.adjoint_setup(scene, t["cs"], t["q"], opts)
-        info_s = native.adjoint_solve(scene, gq, gv, z, opts)
-        native.vjp_params(scene, z, gv, dqbar, dvbar, dfext, grad3)
-        iters.append(info_s.iters)
-
-    for i in range(args.warmup):
-        one(i)
-    torch.cuda.synchronize()
-    iters.clear()
-    native.profile_begin(scene, args.roofline_kernel)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        one(args.warmup + i)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    kms, launches = native.profile_end(scene, )
-    # matvec (block-sparse Acal^T product) rate over a short separate region
-    native.profile_begin(scene, "bsr")
-    for i in range(min(args.steps, 6)):
-        one(i)
-    torch.cuda.synchronize()
-    bms, blaunch = native.profile_end(scene)
-
-    # mixed precision (FP32-stored matrices inside GMRES, FP64 refinement) on the same steps
-    opts_m = native.solve_opts(rtol=args.rtol, maxit=5000, restart=64, prec=native.ADJ_MIXED, max_refine=8)
-    miters = []
-
-    def one_mixed(i):
-        t = dstates[i % len(dstates)]
-        native.adjoint_setup(scene, t["cs"], t["q"], opts_m)
-        info_m = native.adjoint_solve(scene, gq, gv, z, opts_m)
-        native.vjp_params(scene, z, gv, dqbar, dvbar, dfext, grad3)
-        miters.append((info_m.iters, info_m.refine_steps))
-
-    for i in range(args.warmup):
-        one_mixed(i)
-    torch.cuda.synchronize()
-    miters.clear()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        one_mixed(args.warmup + i)
-    torch.cuda.synchronize()
-    dt_m = time.perf_counter() - t0
-
-    # batched: the three independent runs (mu 1.0 / 0.1 / 0.4) at the same
-    # step solved as one batch (one launch per phase, one GMRES per scene)
+    # ---- batched: the three runs at the same time step as one batch ----
     by_t = {}
     for k, st in enumerate(states):
         by_t.setdefault(st["t"], []).append(k)
     groups = [v for _, v in sorted(by_t.items()) if len(v) == len(MUS)]
-    batched = None
-    if groups:
-        specs = [beam_scene(mu=mu) for mu in MUS]
-        batch = native.Batch([(sp.mesh.rest, sp.mesh.tets, sp.E, sp.nu) for sp in specs], spec.density, spec.h,
-                             spec.eps, spec.gravity, spec.planes, spec.contact_margin, [max_c] * len(MUS))
-        bgq = torch.cat([gq] * len(MUS))
-        bgv = torch.zeros_like(bgq)
-        bz = torch.zeros_like(bgq)
-        bq = [torch.cat([dstates[k]["q"] for k in g]) for g in groups]
-        bd = [torch.empty_like(bgq) for _ in range(3)]
-        bgrad = torch.zeros(3 * len(MUS), dtype=torch.float64, device=dev)
+    if not groups:
+        raise SystemExit("the beam fixtures of all three runs are needed")
+    specs = [beam_scene(mu=mu) for mu in MUS]
+    batch = native.Batch([(sp.mesh.rest, sp.mesh.tets, sp.E, sp.nu) for sp in specs], spec.density, spec.h,
+                         spec.eps, spec.gravity, spec.planes, spec.contact_margin, [max_c] * len(MUS))
+    uscene = batch.union_scene()
+    uinfo = uscene.info()
+    bgq = torch.cat([gq] * len(MUS))
+    bgv = torch.zeros_like(bgq)
+    bz = torch.zeros_like(bgq)
+    bq = [torch.cat([dstates[k]["q"] for k in g]) for g in groups]
+    bd = [torch.empty_like(bgq) for _ in range(3)]
+    bgrad = torch.zeros(3 * len(MUS), dtype=torch.float64, device=dev)
 
-        def run_batched(prec, nsteps, warm):
-            o = native.solve_opts(rtol=args.rtol, maxit=5000, restart=64, prec=prec, max_refine=8)
-            its = []
-            for i in range(warm + nsteps):
-                if i == warm:
-                    torch.cuda.synchronize()
-                    its.clear()
-                    t0b = time.perf_counter()
-                g = groups[i % len(groups)]
-                native.batch_setup(batch, [dstates[k]["cs"] for k in g], bq[i % len(groups)], o)
-                infos = native.batch_solve(batch, bgq, bgv, bz, o)
-                native.batch_vjp(batch, bz, bgv, bd[0], bd[1], bd[2], bgrad)
-                its.append(np.mean([f.iters for f in infos]))
-            torch.cuda.synchronize()
-            dtb = time.perf_counter() - t0b
-            return {"value": len(MUS) * nsteps / dtb, "unit": "adjoint solves/s", "n_scenes": len(MUS),
-                    "ms_per_batch": 1e3 * dtb / nsteps, "krylov_iters_mean": float(np.mean(its))}
+    def run_batched(prec, nsteps, warm, profile=None):
+        o = native.solve_opts(rtol=args.rtol, maxit=5000, restart=64, prec=prec, max_refine=8)
+        its = []
+        prof = None
+        t0b = time.perf_counter()
+        for i in range(warm + nsteps):
+            if i == warm:
+                torch.cuda.synchronize()
+                its.clear()
+                if profile:
+                    native.profile_begin(uscene, profile)
+                t0b = time.perf_counter()
+            g = groups[i % len(groups)]
+            native.batch_setup(batch, [dstates[k]["cs"] for k in g], bq[i % len(groups)], o)
+            infos = native.batch_solve(batch, bgq, bgv, bz, o)
+            native.batch_vjp(batch, bz, bgv, bd[0], bd[1], bd[2], bgrad)
+            its.append(np.mean([f.iters for f in infos]))
+        torch.cuda.synchronize()
+        dtb = time.perf_counter() - t0b
+        if profile:
+            prof = native.profile_end(uscene)
+        return {"value": len(MUS) * nsteps / dtb, "unit": "adjoint solves/s", "n_scenes": len(MUS),
+                "ms_per_batch": 1e3 * dtb / nsteps, "krylov_iters_mean": float(np.mean(its))}, prof
 
-        nb_steps = max(4, args.steps // len(MUS))
-        batched = {"fp64": run_batched(native.ADJ_FP64, nb_steps, 2),
-                   "mixed": run_batched(native.ADJ_MIXED, nb_steps, 2)}
-        batched["fp64"]["speedup_vs_single_fp64"] = batched["fp64"]["value"] / (args.steps / dt)
-        batched["mixed"]["speedup_vs_single_fp64"] = batched["mixed"]["value"] / (args.steps / dt)
-        batch.close()
+    bfp64, (kms, launches) = run_batched(native.ADJ_FP64, args.steps, args.warmup, profile="S")
+    _, (mv_ms, mv_launch) = run_batched(native.ADJ_FP64, 4, 0, profile="bsr")
+    bmixed, _ = run_batched(native.ADJ_MIXED, args.steps, args.warmup)
 
-    t_avg = dstates[0]
-    nc0 = int(states[0]["vid"].shape[0])
-    abytes = algorithmic_bytes(args.roofline_kernel, info, nc0, t_avg["m"], t_avg["ncv"])
+    # ---- each scene alone (single-scene path) ----
+    scene = native.Scene(spec.mesh.rest, spec.mesh.tets, spec.density, spec.h, spec.eps, spec.E, spec.nu,
+                         spec.gravity, spec.planes, spec.contact_margin, max_c)
+    z = torch.zeros_like(gq)
+    dqbar, dvbar, dfext = torch.empty_like(gq), torch.empty_like(gq), torch.empty_like(gq)
+    grad3 = torch.zeros(3, dtype=torch.float64, device=dev)
+    opts = native.solve_opts(rtol=args.rtol, maxit=5000, restart=64)
+    tuning = native.get_tuning(scene)
+    if not args.no_autotune:
+        native.adjoint_setup(scene, dstates[0]["cs"], dstates[0]["q"], opts)
+        tuning = native.autotune(scene, gq, gv, z, opts, reps=3)
+
+    def run_single(prec):
+        o = native.solve_opts(rtol=args.rtol, maxit=5000, restart=64, prec=prec, max_refine=8)
+        its = []
+        t0s = time.perf_counter()
+        for i in range(args.warmup + args.steps):
+            if i == args.warmup:
+                torch.cuda.synchronize()
+                its.clear()
+                t0s = time.perf_counter()
+            t = dstates[i % len(dstates)]
+            native.adjoint_setup(scene, t["cs"], t["q"], o)
+            info_s = native.adjoint_solve(scene, gq, gv, z, o)
+            native.vjp_params(scene, z, gv, dqbar, dvbar, dfext, grad3)
+            its.append(info_s.iters)
+        torch.cuda.synchronize()
+        dts = time.perf_counter() - t0s
+        return {"value": args.steps / dts, "unit": "adjoint solves/s", "ms_per_step": 1e3 * dts / args.steps,
+                "krylov_iters_mean": float(np.mean(its))}
+
+    single = run_single(native.ADJ_FP64)
+    single_mixed = run_single(native.ADJ_MIXED)
+
+    abytes = s_product_bytes(uinfo)
     avg_ms = kms / max(launches, 1)
     achieved = abytes / (avg_ms * 1e-3) / 1e9 if launches else 0.0
-    mv_bytes = algorithmic_bytes("bsr", info, nc0, t_avg["m"], t_avg["ncv"])
-    mv_ms = bms / max(blaunch, 1)
+    traffic = measured_traffic()
+    mv_bytes = bsr_bytes(uinfo)
+    mv_avg = mv_ms / max(mv_launch, 1)
     out = {
         "metric": METRIC,
-        "value": args.steps / dt,
+        "value": bfp64["value"],
         "unit": "adjoint solves/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": 1e3 * dt / args.steps,
+        "ms_per_step": bfp64["ms_per_batch"] / len(MUS),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
         "config": {
-            "workload": "beam 32x8x8 cells (12,288 tets, 2,673 vertices), E=1e6 Pa, nu=0.45, on the "
-                        "ground under a sideways push; mu 1.0 / 0.1 / 0.4, recorded steps 0-3 of each; "
-                        "plain FP64, GMRES(64) + Woodbury to rel. residual 1e-8",
+            "workload": "beam 32x8x8 cells (12,288 tets, 2,673 vertices), E=1e6 Pa, nu=0.45, on the ground under "
+                        "a sideways push; three runs at mu 1.0 / 0.1 / 0.4, recorded steps 0-3 of each; the three "
+                        "runs' adjoint steps solved as one batch, plain FP64, GMRES(64) + Woodbury to rel. "
+                        "residual 1e-8",
             "n_scene_steps": len(states),
-            "contacts": nc0,
-            "capacitance_rows": t_avg["m"],
-            "krylov_iters_mean": float(np.mean(iters)) if iters else None,
-            "precision": "fp64",
-            "tuning": tuning,
+            "scenes_per_batch": len(MUS),
+            "contacts_per_scene": int(states[0]["vid"].shape[0]),
+            "krylov_iters_mean": bfp64["krylov_iters_mean"],
+            "single_scene_tuning": tuning,
         },
         "roofline": {
-            "kernel": {"S": "sparse-inverse product S x", "ST": "sparse-inverse product S^T x",
-                       "bsr": "block-sparse Acal^T x", "capinv": "capacitance-inverse product",
-                       "Z": "Woodbury correction Z t", "tet": "per-tet SVD Jacobian blocks"}[args.roofline_kernel],
+            "kernel": "sparse-inverse product S x (batched, three beams)",
             "bound": "hbm",
             "achieved": achieved,
             "peak": HBM_PEAK_GBPS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBPS,
-            "traffic": None,
+            "traffic": traffic,
             "algorithmic_bytes_per_launch": abytes,
             "avg_launch_us": 1e3 * avg_ms,
             "launches_timed": launches,
         },
-        "matvec": {"bytes_per_launch": mv_bytes, "avg_launch_us": 1e3 * mv_ms,
-                   "GB/s": mv_bytes / (mv_ms * 1e-3) / 1e9 if blaunch else None},
-        "mixed": {"value": args.steps / dt_m, "unit": "adjoint solves/s",
-                  "ms_per_step": 1e3 * dt_m / args.steps,
-                  "krylov_iters_mean": float(np.mean([a for a, _ in miters])),
-                  "refine_steps_mean": float(np.mean([b for _, b in miters])),
-                  "speedup_vs_fp64": (args.steps / dt_m) / (args.steps / dt)},
-        "batched": batched,
+        "matvec": {"kernel": "Acal^T product fused with the first Gram-Schmidt dots (batched)",
+                   "bytes_per_launch": mv_bytes, "avg_launch_us": 1e3 * mv_avg,
+                   "GB/s": mv_bytes / (mv_avg * 1e-3) / 1e9 if mv_launch else None},
+        "mixed_batched": bmixed | {"speedup_vs_fp64_batched": bmixed["value"] / bfp64["value"]},
+        "single_scene": {"fp64": single, "mixed": single_mixed,
+                         "batched_speedup_fp64": bfp64["value"] / single["value"]},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(spec, states, args.cpu_sample)
+    batch.close()
     print(json.dumps(out))
 
 

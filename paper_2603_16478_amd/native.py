@@ -315,6 +315,19 @@ def autotune(scene: Scene, dL_dq, dL_dv, z, opts: SolveOpts, reps=3, stream=None
     return t.as_dict()
 
 
+class _SceneRef:
+    """Non-owning reference to a scene handle."""
+
+    def __init__(self, handle):
+        self.handle = handle
+
+    def info(self):
+        out = (C.c_int64 * 6)()
+        check(load().adj_scene_info(self.handle, out))
+        keys = ("n_verts", "n_tets", "nnz_blocks", "nnz_L", "nnz_S", "max_contacts")
+        return dict(zip(keys, list(out)))
+
+
 class Batch:
     """Owns an adj_batch: several scenes solved together (adj_batch_create).
     specs: sequence of (rest, tets, E, nu); density, h, eps are shared."""
@@ -350,6 +363,12 @@ class Batch:
         check(lib.adj_batch_info(handle, out))
         self.voff = np.array(list(out)[: n + 1], dtype=np.int64)
         self.toff = np.array(list(out)[n + 1:], dtype=np.int64)
+
+    def union_scene(self):
+        """The batch's union scene (for profile_begin/end and info); owned by the batch."""
+        h = C.c_void_p()
+        check(load().adj_batch_scene(self.handle, C.byref(h)))
+        return _SceneRef(h)
 
     def close(self):
         if getattr(self, "handle", None):
