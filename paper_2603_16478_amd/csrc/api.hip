@@ -213,9 +213,11 @@ struct ProfScope {
   ProfScope(adj_scene* s_, int id, hipStream_t st_) : s(s_), st(st_), on(false) {
     if (s->prof_kernel != id || s->prof_used >= kMaxProfiled) return;
     if (s->prof_ev.size() < 2 * (s->prof_used + 1)) {
+      // device-scope events: no system-scope cache fence around the timed
+      // launch (the timing brackets only work on this device)
       hipEvent_t a, b;
-      if (hipEventCreate(&a) != hipSuccess) return;
-      if (hipEventCreate(&b) != hipSuccess) {
+      if (hipEventCreateWithFlags(&a, hipEventDisableSystemFence) != hipSuccess) return;
+      if (hipEventCreateWithFlags(&b, hipEventDisableSystemFence) != hipSuccess) {
         (void)hipEventDestroy(a);
         return;
       }

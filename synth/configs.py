@@ -168,13 +168,14 @@ def quadruped_scene(seed: int = 4, steps: int = 1000) -> SceneSpec:
     )
 
 
-def batched_scenes(n_scenes: int = 256, seed: int = 3):
-    """Boxes with log-uniform tet counts in [2e3, 1e5], seeded aspect, E, nu,
-    mu and tangential initial velocity; one in eight hovers 5 mm up."""
+def batched_scenes(n_scenes: int = 256, seed: int = 3, tmax: float = 1e5):
+    """Boxes with log-uniform tet counts in [2e3, tmax] (1e5 for the full
+    workload), seeded aspect, E, nu, mu and tangential initial velocity; one
+    in eight hovers 5 mm up."""
     rng = np.random.default_rng(seed)
     out = []
     for s in range(n_scenes):
-        T = np.exp(rng.uniform(np.log(2e3), np.log(1e5)))
+        T = np.exp(rng.uniform(np.log(2e3), np.log(tmax)))
         while True:
             a = rng.uniform(0.5, 2.0, size=3)
             cells = T / 6.0
