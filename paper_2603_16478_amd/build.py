@@ -38,7 +38,7 @@ def build(verbose: bool = True) -> str:
     objs = []
     for src in CPP_SOURCES:
         obj = os.path.join(BUILD, src + ".o")
-        _run(["g++", "-O3", "-fPIC", "-std=c++17", "-I", INCLUDE, "-I", CSRC, "-c",
+        _run(["g++", "-O3", "-fPIC", "-std=c++17", "-pthread", "-I", INCLUDE, "-I", CSRC, "-c",
               os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
     for src in HIP_SOURCES:
@@ -46,7 +46,7 @@ def build(verbose: bool = True) -> str:
         _run([hipcc, *HIPCC_FLAGS, "-I", INCLUDE, "-I", CSRC, "-c", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
     tmp = LIB + ".tmp"
-    _run([hipcc, "-shared", "-fPIC", "--offload-arch=gfx950", *objs, "-o", tmp])
+    _run([hipcc, "-shared", "-fPIC", "-pthread", "--offload-arch=gfx950", *objs, "-o", tmp])
     os.replace(tmp, LIB)
     return LIB
 

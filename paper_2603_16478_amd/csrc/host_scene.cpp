@@ -8,6 +8,8 @@
 // its inverse S = L^{-1} P gives A^{-1} = S^T S (Sec. 3.4).
 #include "host_scene.h"
 
+#include <thread>
+
 #include <algorithm>
 #include <cmath>
 #include <numeric>
@@ -351,7 +353,6 @@ adj_status build_host_scene(const adj_scene_desc* d, HostScene& s, std::string& 
   // S = L^{-1} P column by column: column v of S is L^{-1} e_{iperm[v]},
   // nonzero exactly on the elimination-tree path from iperm[v] to the root.
   s.STp.assign(nv + 1, 0);
-  std::vector<int32_t> path;
   for (int v = 0; v < nv; ++v) {
     int len = 0;
     for (int j = s.iperm[v]; j != -1; j = s.parent[j]) ++len;
@@ -359,22 +360,36 @@ adj_status build_host_scene(const adj_scene_desc* d, HostScene& s, std::string& 
   }
   s.STj.resize(s.STp[nv]);
   s.STx.resize(s.STp[nv]);
-  std::fill(x.begin(), x.end(), 0.0);
-  for (int v = 0; v < nv; ++v) {
-    path.clear();
-    for (int j = s.iperm[v]; j != -1; j = s.parent[j]) path.push_back(j);
-    x[path[0]] = 1.0;
-    for (int j : path) {
-      x[j] /= s.Lx[s.Lp[j]];
-      double xj = x[j];
-      for (int32_t p = s.Lp[j] + 1; p < s.Lp[j + 1]; ++p) x[s.Li[p]] -= s.Lx[p] * xj;
+  // the columns are independent: spread them over host threads, each with
+  // its own work vector, writing disjoint slices of STj/STx
+  const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+  const int nthreads = (int)std::min<unsigned>(16u, hw);
+  auto columns = [&](int t0) {
+    std::vector<double> xw(nv, 0.0);
+    std::vector<int32_t> pth;
+    for (int v = t0; v < nv; v += nthreads) {
+      pth.clear();
+      for (int j = s.iperm[v]; j != -1; j = s.parent[j]) pth.push_back(j);
+      xw[pth[0]] = 1.0;
+      for (int j : pth) {
+        xw[j] /= s.Lx[s.Lp[j]];
+        const double xj = xw[j];
+        for (int32_t p = s.Lp[j] + 1; p < s.Lp[j + 1]; ++p) xw[s.Li[p]] -= s.Lx[p] * xj;
+      }
+      int64_t o = s.STp[v];
+      for (int j : pth) {
+        s.STj[o] = j;
+        s.STx[o++] = xw[j];
+        xw[j] = 0.0;
+      }
     }
-    int64_t o = s.STp[v];
-    for (int j : path) {
-      s.STj[o] = j;
-      s.STx[o++] = x[j];
-      x[j] = 0.0;
-    }
+  };
+  if (nthreads == 1 || nv < 4096) {
+    for (int t = 0; t < nthreads; ++t) columns(t);
+  } else {
+    std::vector<std::thread> pool;
+    for (int t = 0; t < nthreads; ++t) pool.emplace_back(columns, t);
+    for (auto& th : pool) th.join();
   }
   // transpose: CSR of S (rows = internal index)
   s.Sp.assign(nv + 1, 0);
