@@ -12,7 +12,9 @@ gradient contractions, on a recorded converged scene-step.
 this benchmark solves the three runs' adjoints at the same time step as one
 batch (one launch per phase over all three scenes, one GMRES per scene), in
 plain FP64; it counts three solves.  Also reported: the same in mixed
-precision, each scene solved alone (FP64 and mixed), the roofline of the
+precision, each scene solved alone (FP64 and mixed), a large batch (the
+twelve recorded scene-steps four times: 48 scenes per launch, FP64 and
+mixed, with the sparse-inverse product's bandwidth), the roofline of the
 batched sparse-inverse product (algorithmic bytes per launch / average
 launch time from HIP events on the launch stream over the timed region,
 and the HBM traffic of the counter runs when the kernel source still matches
@@ -122,6 +124,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--big-batch", type=int, default=4,
+                    help="copies of the twelve recorded scene-steps in the large-batch leg (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; --gpus above 1 is not supported",
@@ -197,6 +201,54 @@ def main():
     bfp64, (kms, launches) = run_batched(native.ADJ_FP64, args.steps, args.warmup, profile="S")
     _, (mv_ms, mv_launch) = run_batched(native.ADJ_FP64, 4, 0, profile="bsr")
     bmixed, _ = run_batched(native.ADJ_MIXED, args.steps, args.warmup)
+    batch.close()
+
+    # ---- a large batch: every recorded scene-step, four times (48 scenes) ----
+    big = None
+    if args.big_batch > 0:
+        reps = args.big_batch
+        ks = list(range(len(states))) * reps
+        bspecs = [beam_scene(mu=states[k]["mu"]) for k in ks]
+        bb = native.Batch([(sp.mesh.rest, sp.mesh.tets, sp.E, sp.nu) for sp in bspecs], spec.density, spec.h,
+                          spec.eps, spec.gravity, spec.planes, spec.contact_margin, [max_c] * len(ks))
+        bu = bb.union_scene()
+        binfo = bu.info()
+        qq = torch.cat([dstates[k]["q"] for k in ks])
+        gg = torch.cat([gq] * len(ks))
+        vv = torch.zeros_like(gg)
+        zz = torch.zeros_like(gg)
+        oo = [torch.empty_like(gg) for _ in range(3)]
+        gr = torch.zeros(3 * len(ks), dtype=torch.float64, device=dev)
+        css = [dstates[k]["cs"] for k in ks]
+
+        def run_big(prec, nsteps, warm, profile=None):
+            o = native.solve_opts(rtol=args.rtol, maxit=5000, restart=64, prec=prec, max_refine=8)
+            t0g = time.perf_counter()
+            for i in range(warm + nsteps):
+                if i == warm:
+                    torch.cuda.synchronize()
+                    if profile:
+                        native.profile_begin(bu, profile)
+                    t0g = time.perf_counter()
+                native.batch_setup(bb, css, qq, o)
+                native.batch_solve(bb, gg, vv, zz, o)
+                native.batch_vjp(bb, zz, vv, oo[0], oo[1], oo[2], gr)
+            torch.cuda.synchronize()
+            dtg = time.perf_counter() - t0g
+            prof = native.profile_end(bu) if profile else None
+            return {"value": len(ks) * nsteps / dtg, "unit": "adjoint solves/s", "ms_per_batch": 1e3 * dtg / nsteps}, prof
+
+        gf, (gms, gl) = run_big(native.ADJ_FP64, 3, 1, profile="S")
+        gm, (gmms, gml) = run_big(native.ADJ_MIXED, 3, 1, profile="S")
+        gbytes = s_product_bytes(binfo)
+        gbytes32 = binfo["nnz_S"] * (4 + 4) + (binfo["n_verts"] + 1) * 8 + 2 * 3 * binfo["n_verts"] * 8
+        big = {"n_scenes": len(ks), "n_verts": binfo["n_verts"], "n_tets": binfo["n_tets"],
+               "fp64": gf | {"s_product_GB/s": gbytes / (gms / max(gl, 1) * 1e-3) / 1e9,
+                             "s_product_frac": gbytes / (gms / max(gl, 1) * 1e-3) / 1e9 / HBM_PEAK_GBPS},
+               "mixed": gm | {"s_product_GB/s": gbytes32 / (gmms / max(gml, 1) * 1e-3) / 1e9,
+                              "s_product_frac": gbytes32 / (gmms / max(gml, 1) * 1e-3) / 1e9 / HBM_PEAK_GBPS,
+                              "speedup_vs_fp64": gm["value"] / gf["value"]}}
+        bb.close()
 
     # ---- each scene alone (single-scene path) ----
     scene = native.Scene(spec.mesh.rest, spec.mesh.tets, spec.density, spec.h, spec.eps, spec.E, spec.nu,
@@ -280,10 +332,10 @@ def main():
         "mixed_batched": bmixed | {"speedup_vs_fp64_batched": bmixed["value"] / bfp64["value"]},
         "single_scene": {"fp64": single, "mixed": single_mixed,
                          "batched_speedup_fp64": bfp64["value"] / single["value"]},
+        "large_batch": big,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(spec, states, args.cpu_sample)
-    batch.close()
     print(json.dumps(out))
 
 

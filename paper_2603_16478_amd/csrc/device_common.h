@@ -38,23 +38,38 @@ __device__ __forceinline__ double block_sum(double v, double* lds /* >= 16 */) {
   return r;
 }
 
-// "Last block done" handshake: every block has written its partial results;
-// returns true in exactly one block (the last to arrive), after an acquire
-// fence, so it may read all partials.  Resets the counter for the next use.
-__device__ __forceinline__ bool last_block(unsigned* counter, bool* flag_lds) {
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    unsigned prev = atomicAdd(counter, 1u);
-    *flag_lds = (prev == gridDim.x - 1);
+// Partial dot products of one CSR row with a vector of 3-vectors:
+// a_k += sum_p val[p] * x[3 col[p] + k] over the entries p = b + t,
+// b + t + STEP, ... below e (t: this thread's index among the STEP threads
+// sharing the row).  U entries per thread are loaded before any is used, so
+// U index loads and then 3U dependent gathers are in flight per pass instead
+// of one; masked slots read x[0..2] (in bounds for any non-empty x) with a
+// zero weight.
+template <int STEP, int U, class MT>
+__device__ __forceinline__ void row_dot3(long long b, long long e, int t, const int* __restrict__ col,
+                                         const MT* __restrict__ val, const double* __restrict__ x, double& a0,
+                                         double& a1, double& a2) {
+  for (long long p = b + t; p < e; p += (long long)STEP * U) {
+    double v[U];
+    int c[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const long long q = p + (long long)u * STEP;
+      v[u] = 0.0;
+      c[u] = 0;
+      if (q < e) {
+        v[u] = (double)val[q];
+        c[u] = col[q];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const double* xp = x + 3LL * c[u];
+      a0 = fma(v[u], xp[0], a0);
+      a1 = fma(v[u], xp[1], a1);
+      a2 = fma(v[u], xp[2], a2);
+    }
   }
-  __syncthreads();
-  bool last = *flag_lds;
-  if (last) {
-    __threadfence();
-    if (threadIdx.x == 0) *counter = 0u;
-  }
-  return last;
 }
 
 // res[i] = sum_b P[b * ld + i] for i < cnt (cnt <= 256), fixed order; all

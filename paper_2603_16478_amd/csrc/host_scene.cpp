@@ -404,8 +404,8 @@ adj_status build_host_scene(const adj_scene_desc* d, HostScene& s, std::string& 
       s.Sj[o] = v;
       s.Sx[o] = s.STx[p];
     }
-  s.S_tasks = make_row_tasks(s.Sp, 256);
-  s.ST_tasks = make_row_tasks(s.STp, 256);
+  s.S_tasks = make_row_tasks(s.Sp, 1024);
+  s.ST_tasks = make_row_tasks(s.STp, 1024);
   return ADJ_OK;
 }
 

@@ -47,13 +47,7 @@ __global__ void __launch_bounds__(256) kb_spmv_tasks(const int4* __restrict__ ta
     const double* x = xbase + (use_j ? (long long)st[s].j * stride : 0);
     const double sc = use_j ? scale[(size_t)s * lds_scale + st[s].j] : 1.0;
     double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-    for (long long p = rp[row] + threadIdx.x; p < rp[row + 1]; p += blockDim.x) {
-      const double v = (double)cx[p];
-      const int c = cj[p];
-      a0 += v * x[3 * c];
-      a1 += v * x[3 * c + 1];
-      a2 += v * x[3 * c + 2];
-    }
+    row_dot3<256, 4>(rp[row], rp[row + 1], threadIdx.x, cj, cx, x, a0, a1, a2);
     a0 = block_sum(a0, lds);
     a1 = block_sum(a1, lds);
     a2 = block_sum(a2, lds);
@@ -72,13 +66,7 @@ __global__ void __launch_bounds__(256) kb_spmv_tasks(const int4* __restrict__ ta
   const double* x = xbase + (use_j ? (long long)st[s].j * stride : 0);
   const double sc = use_j ? scale[(size_t)s * lds_scale + st[s].j] : 1.0;
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-  for (long long p = rp[row] + lane; p < rp[row + 1]; p += 64) {
-    const double v = (double)cx[p];
-    const int c = cj[p];
-    a0 += v * x[3 * c];
-    a1 += v * x[3 * c + 1];
-    a2 += v * x[3 * c + 2];
-  }
+  row_dot3<64, 4>(rp[row], rp[row + 1], lane, cj, cx, x, a0, a1, a2);
   a0 = wave_sum(a0);
   a1 = wave_sum(a1);
   a2 = wave_sum(a2);

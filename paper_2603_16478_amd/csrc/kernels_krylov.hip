@@ -85,13 +85,7 @@ __global__ void __launch_bounds__(256) k_spmv_tasks(const int4* __restrict__ tas
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
   if (t.x >= 0 && (t.x & kBigRow)) {
     const int row = t.x & ~kBigRow;
-    for (long long p = rp[row] + threadIdx.x; p < rp[row + 1]; p += blockDim.x) {
-      const double v = (double)cx[p];
-      const int c = cj[p];
-      a0 += v * x[3 * c];
-      a1 += v * x[3 * c + 1];
-      a2 += v * x[3 * c + 2];
-    }
+    row_dot3<256, 4>(rp[row], rp[row + 1], threadIdx.x, cj, cx, x, a0, a1, a2);
     a0 = block_sum(a0, lds);
     a1 = block_sum(a1, lds);
     a2 = block_sum(a2, lds);
@@ -105,13 +99,7 @@ __global__ void __launch_bounds__(256) k_spmv_tasks(const int4* __restrict__ tas
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int row = (w == 0) ? t.x : (w == 1) ? t.y : (w == 2) ? t.z : t.w;
   if (row < 0) return;
-  for (long long p = rp[row] + lane; p < rp[row + 1]; p += 64) {
-    const double v = (double)cx[p];
-    const int c = cj[p];
-    a0 += v * x[3 * c];
-    a1 += v * x[3 * c + 1];
-    a2 += v * x[3 * c + 2];
-  }
+  row_dot3<64, 4>(rp[row], rp[row + 1], lane, cj, cx, x, a0, a1, a2);
   a0 = wave_sum(a0);
   a1 = wave_sum(a1);
   a2 = wave_sum(a2);
