@@ -380,35 +380,82 @@ __global__ void __launch_bounds__(256) k_gj_step_mfma(int mp, int k0, const doub
   gj_tile(mp, k0, blockIdx.y * kGT, blockIdx.x * kGT, A, B, err, sh);
 }
 
-// Batched block step.  kb_gj_pivot: one wavefront per scene (list of the
-// scenes whose padded size exceeds k0) inverts the scene's pivot block into
-// Pb + 1024 s; kb_gj_step_mfma: tile list entries {scene, I tile, J tile, -},
-// the scene's matrix at A + xoff[s] (and B + xoff[s]) with row length
-// mps[s], P read from Pb.  Inverting once per scene keeps the serial pivot
-// chain out of every tile block.
-__global__ void __launch_bounds__(64) kb_gj_pivot(const int* __restrict__ scenes, int k0,
-                                                  const long long* __restrict__ xoff, const int* __restrict__ mps,
-                                                  const double* __restrict__ A, double* __restrict__ Pb,
-                                                  int* __restrict__ err) {
+// Batched block steps with a one-step lookahead on the pivot chain.
+// kb_gj_pivot: one wavefront per listed scene inverts the first pivot block
+// (k0 = 0) into P slot s.  kb_gj_step_mfma, at pivot k0 = 32 k: blocks
+// [0, npiv) are next-pivot tasks, one per scene that has a step k + 1; from
+// the step's input A they form that step's pivot block,
+//   A_k1k1 - (A_k1k0 P_k) A_k0k1   (k1 = k0 + 32),
+// which is exactly the block the tiles of step k write there, invert it and
+// store it in the other P slot.  The remaining blocks are the output tiles
+// {scene, I tile, J tile, -} of step k, reading P_k.  So the serial pivot
+// inversion of step k + 1 runs beside the tiles of step k instead of after
+// them; the scene's matrix is at A + xoff[s] (B + xoff[s]) with row length
+// mps[s], its P at P + 1024 s.
+__device__ __forceinline__ void gj_next_pivot(int mp, int k0, const double* __restrict__ A,
+                                              const double* __restrict__ Pc, double* __restrict__ Pn,
+                                              int* __restrict__ err, GjShared& sh) {
+  const int k1 = k0 + kNB, tid = threadIdx.x;
+  // Cs[0..31] = A_k1k0, Ps = P_k, Rs[.][0..31] = A_k0k1, Ws[32..63] = A_k1k1
+  for (int e = tid; e < kNB * kNB; e += 256) {
+    const int r = e / kNB, c = e % kNB;
+    sh.Cs[r][c] = A[(size_t)(k1 + r) * mp + k0 + c];
+    sh.Ps[r][c] = Pc[e];
+    sh.Rs[r][c] = A[(size_t)(k0 + r) * mp + k1 + c];
+    sh.Ws[kNB + r][c] = A[(size_t)(k1 + r) * mp + k1 + c];
+  }
+  __syncthreads();
+  // Ws[0..31] = A_k1k0 P_k
+  for (int e = tid; e < kNB * kNB; e += 256) {
+    const int r = e / kNB, c = e % kNB;
+    double a = 0.0;
+#pragma unroll 8
+    for (int t = 0; t < kNB; ++t) a = fma(sh.Cs[r][t], sh.Ps[t][c], a);
+    sh.Ws[r][c] = a;
+  }
+  __syncthreads();
+  // Ws[32..63] -= Ws[0..31] A_k0k1
+  for (int e = tid; e < kNB * kNB; e += 256) {
+    const int r = e / kNB, c = e % kNB;
+    double a = sh.Ws[kNB + r][c];
+#pragma unroll 8
+    for (int t = 0; t < kNB; ++t) a = fma(-sh.Ws[r][t], sh.Rs[t][c], a);
+    sh.Ws[kNB + r][c] = a;
+  }
+  __syncthreads();
+  if (tid < 64) invert32_rows(&sh.Ws[kNB][0], kNB + 1, sh.Ps, sh.prow, err);
+  __syncthreads();
+  for (int e = tid; e < kNB * kNB; e += 256) Pn[e] = sh.Ps[e / kNB][e % kNB];
+}
+
+__global__ void __launch_bounds__(64) kb_gj_pivot(const int* __restrict__ scenes, const long long* __restrict__ xoff,
+                                                  const int* __restrict__ mps, const double* __restrict__ A,
+                                                  double* __restrict__ Pb, int* __restrict__ err) {
   __shared__ double Ps[kNB][kNB + 1];
   __shared__ double prow[2 * kNB];
   const int s = scenes[blockIdx.x];
-  const int mp = mps[s];
-  invert32_rows(A + xoff[s] + (size_t)k0 * mp + k0, mp, Ps, prow, err);
+  invert32_rows(A + xoff[s], mps[s], Ps, prow, err);
   __syncthreads();
   double* P = Pb + (size_t)s * kNB * kNB;
   for (int e = threadIdx.x; e < kNB * kNB; e += blockDim.x) P[e] = Ps[e / kNB][e % kNB];
 }
 
-__global__ void __launch_bounds__(256) kb_gj_step_mfma(const int4* __restrict__ tiles, int k0,
+__global__ void __launch_bounds__(256) kb_gj_step_mfma(const int* __restrict__ next_scenes, int npiv,
+                                                       const int4* __restrict__ tiles, int k0,
                                                        const long long* __restrict__ xoff,
                                                        const int* __restrict__ mps, const double* __restrict__ A,
-                                                       double* __restrict__ B, const double* __restrict__ Pb,
-                                                       int* __restrict__ err) {
+                                                       double* __restrict__ B, const double* __restrict__ Pcur,
+                                                       double* __restrict__ Pnext, int* __restrict__ err) {
   __shared__ GjShared sh;
-  const int4 e = tiles[blockIdx.x];
+  if ((int)blockIdx.x < npiv) {
+    const int s = next_scenes[blockIdx.x];
+    const size_t po = (size_t)s * kNB * kNB;
+    gj_next_pivot(mps[s], k0, A + xoff[s], Pcur + po, Pnext + po, err, sh);
+    return;
+  }
+  const int4 e = tiles[blockIdx.x - npiv];
   const long long o = xoff[e.x];
-  gj_tile(mps[e.x], k0, e.y * kGT, e.z * kGT, A + o, B + o, err, sh, Pb + (size_t)e.x * kNB * kNB);
+  gj_tile(mps[e.x], k0, e.y * kGT, e.z * kGT, A + o, B + o, err, sh, Pcur + (size_t)e.x * kNB * kNB);
 }
 
 // identity padding of rows/cols m..mp-1 of a row-major mp x mp matrix
@@ -474,11 +521,17 @@ double* launch_gauss_jordan(hipStream_t st, int m, int mp, double* C0, double* C
   return A;
 }
 
-void launchb_gj_step(hipStream_t st, int nscenes, const int* scenes, int ntiles, const int4* tiles, int k0,
-                     const long long* xoff, const int* mps, const double* A, double* B, double* Pb, int* err) {
+void launchb_gj_pivot(hipStream_t st, int nscenes, const int* scenes, const long long* xoff, const int* mps,
+                      const double* A, double* Pb, int* err) {
+  if (!nscenes) return;
+  kb_gj_pivot<<<nscenes, 64, 0, st>>>(scenes, xoff, mps, A, Pb, err);
+}
+
+void launchb_gj_step(hipStream_t st, int npiv, const int* next_scenes, int ntiles, const int4* tiles, int k0,
+                     const long long* xoff, const int* mps, const double* A, double* B, const double* Pcur,
+                     double* Pnext, int* err) {
   if (!ntiles) return;
-  kb_gj_pivot<<<nscenes, 64, 0, st>>>(scenes, k0, xoff, mps, A, Pb, err);
-  kb_gj_step_mfma<<<ntiles, 256, 0, st>>>(tiles, k0, xoff, mps, A, B, Pb, err);
+  kb_gj_step_mfma<<<npiv + ntiles, 256, 0, st>>>(next_scenes, npiv, tiles, k0, xoff, mps, A, B, Pcur, Pnext, err);
 }
 
 }  // namespace adj
