@@ -162,7 +162,7 @@ constexpr int kNB = 32;
 
 // Inverse of the 32x32 pivot block by one wavefront, row per lane: lane r
 // (r < 32) holds row r of A_kk, lane 32 + r row r of the identity.  Step k
-// picks the unused row with the largest |A[r][k]| (lower row on ties),
+// picks the unused row with the largest |A[r][k]| (partial pivoting),
 // broadcasts that row through LDS and eliminates column k from every other
 // row.  Rows are never swapped: with p_k the row chosen at step k, the
 // eliminated A part is a permutation and row k of the inverse is row p_k of
@@ -177,15 +177,6 @@ __device__ __forceinline__ double dpp_d(double v) {
   return __hiloint2double(hi, lo);
 }
 
-template <int CTRL>
-__device__ __forceinline__ void argmax_dpp(double& key, int& idx) {
-  const double k2 = dpp_d<CTRL>(key);
-  const int i2 = __builtin_amdgcn_update_dpp(0, idx, CTRL, 0xF, 0xF, false);
-  const bool take = (k2 > key) | ((k2 == key) & (i2 < idx));
-  key = take ? k2 : key;
-  idx = take ? i2 : idx;
-}
-
 __device__ __forceinline__ double readlane_d(double v, int lane) {
   const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
   const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
@@ -197,25 +188,43 @@ constexpr int kDppXor2 = 0x4E;        // quad_perm [2,3,0,1]
 constexpr int kDppHalfMirror = 0x141; // lane i <-> 7 - i within each 8 lanes
 constexpr int kDppMirror = 0x140;     // lane i <-> 15 - i within each 16 lanes
 
+// 1 / a to full double precision: hardware reciprocal estimate refined by
+// two Newton steps (each doubles the correct bits).
+__device__ __forceinline__ double rcp_newton(double a) {
+  double r = __builtin_amdgcn_rcp(a);
+  double e = fma(-a, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-a, r, 1.0);
+  return fma(r, e, r);
+}
+
+// 32-bit max over the 16 lanes of each DPP row
+template <int CTRL>
+__device__ __forceinline__ unsigned max_dpp(unsigned v) {
+  return max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xF, 0xF, false));
+}
+
 template <int K>
 __device__ __forceinline__ void gj_rows_step(double (&x)[kNB], bool& used, int& step_of_row, bool& bad,
                                              double* __restrict__ prow) {
   const int lane = threadIdx.x & 63, r = lane & 31;
   // pivot column value of this lane's row (the A part lives in lanes < 32)
   const double ak = __shfl(x[K], r, 64);
-  double key = used ? -1.0 : fabs(ak);
-  int idx = r;
-  argmax_dpp<kDppXor1>(key, idx);
-  argmax_dpp<kDppXor2>(key, idx);
-  argmax_dpp<kDppHalfMirror>(key, idx);
-  argmax_dpp<kDppMirror>(key, idx);
-  const double k0 = readlane_d(key, 0), k1 = readlane_d(key, 16);
-  const int i0 = __builtin_amdgcn_readlane(idx, 0), i1 = __builtin_amdgcn_readlane(idx, 16);
-  const bool second = (k1 > k0) | ((k1 == k0) & (i1 < i0));
-  const int p = second ? i1 : i0;
-  const double best = second ? k1 : k0;
-  if (!(best > 0.0) || !isfinite(best)) bad = true;
-  const double inv = 1.0 / readlane_d(ak, p);
+  // pivot choice on a 32-bit key: |a_rk| rounded to float with its low 5
+  // bits replaced by 31 - r (ties within ~2^-18 relative go to the lower
+  // row), used rows 0, unused rows at least 32; one DPP max per level.
+  const unsigned mag = __float_as_uint((float)fabs(ak)) & ~31u;
+  unsigned key = used ? 0u : (max(mag, 32u) | (unsigned)(31 - r));
+  key = max_dpp<kDppXor1>(key);
+  key = max_dpp<kDppXor2>(key);
+  key = max_dpp<kDppHalfMirror>(key);
+  key = max_dpp<kDppMirror>(key);
+  const unsigned kb = max((unsigned)__builtin_amdgcn_readlane((int)key, 0),
+                          (unsigned)__builtin_amdgcn_readlane((int)key, 16));
+  const int p = 31 - (int)(kb & 31u);
+  const double apk = readlane_d(ak, p);
+  if (!(fabs(apk) > 0.0) || !isfinite(apk)) bad = true;
+  const double inv = rcp_newton(apk);
   // broadcast the pivot row: A part to prow[0..31], identity part to prow[32..63]
   const bool piv = (r == p);
   if (piv) {
@@ -405,22 +414,31 @@ __device__ __forceinline__ void gj_next_pivot(int mp, int k0, const double* __re
     sh.Ws[kNB + r][c] = A[(size_t)(k1 + r) * mp + k1 + c];
   }
   __syncthreads();
+  // one 16 x 16 output tile per wavefront, FP64 MFMA (A operand row li,
+  // k lk; B operand k lk, column li; result row lk + 4 e, column li)
+  const int lane = tid & 63, w = tid >> 6, li = lane & 15, lk = lane >> 4;
+  const int R0 = 16 * (w >> 1), C0 = 16 * (w & 1);
   // Ws[0..31] = A_k1k0 P_k
-  for (int e = tid; e < kNB * kNB; e += 256) {
-    const int r = e / kNB, c = e % kNB;
-    double a = 0.0;
-#pragma unroll 8
-    for (int t = 0; t < kNB; ++t) a = fma(sh.Cs[r][t], sh.Ps[t][c], a);
-    sh.Ws[r][c] = a;
+  {
+    d4 acc = d4{0, 0, 0, 0};
+#pragma unroll
+    for (int k4 = 0; k4 < kNB; k4 += 4)
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(sh.Cs[R0 + li][k4 + lk], sh.Ps[k4 + lk][C0 + li], acc, 0, 0, 0);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) sh.Ws[R0 + lk + 4 * e][C0 + li] = acc[e];
   }
   __syncthreads();
   // Ws[32..63] -= Ws[0..31] A_k0k1
-  for (int e = tid; e < kNB * kNB; e += 256) {
-    const int r = e / kNB, c = e % kNB;
-    double a = sh.Ws[kNB + r][c];
-#pragma unroll 8
-    for (int t = 0; t < kNB; ++t) a = fma(-sh.Ws[r][t], sh.Rs[t][c], a);
-    sh.Ws[kNB + r][c] = a;
+  {
+    d4 acc;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) acc[e] = sh.Ws[kNB + R0 + lk + 4 * e][C0 + li];
+#pragma unroll
+    for (int k4 = 0; k4 < kNB; k4 += 4)
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(-sh.Ws[R0 + li][k4 + lk], sh.Rs[k4 + lk][C0 + li], acc, 0, 0, 0);
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < 4; ++e) sh.Ws[kNB + R0 + lk + 4 * e][C0 + li] = acc[e];
   }
   __syncthreads();
   if (tid < 64) invert32_rows(&sh.Ws[kNB][0], kNB + 1, sh.Ps, sh.prow, err);
