@@ -122,7 +122,8 @@ typedef struct {
  * matrix A = M + h^2 sum_i w_i G_i^T G_i (eq:dynamics) and its Cholesky
  * factor with its sparse inverse S = L^{-1} (Sec. 3.4: A^{-1} = S^T S),
  * the block-sparse pattern of Acal with the element-to-entry map (Sec. 5.4,
- * matrix assembly), and device workspaces sized for `max_contacts`.
+ * matrix assembly), and device workspaces sized for `max_contacts`
+ * (0 .. 10000; the capacitance inverse is dense, (3 max_contacts)^2 doubles).
  * Errors: ADJ_E_ARG, ADJ_E_INVERTED (rest tet with det <= 0),
  * ADJ_E_SINGULAR, ADJ_E_OOM, ADJ_E_DEVICE.  *out is NULL on error. */
 adj_status adj_scene_create(const adj_scene_desc* desc, int32_t max_contacts, adj_scene** out);

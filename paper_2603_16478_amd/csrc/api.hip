@@ -265,8 +265,24 @@ static const int kMaxRestart = 128;
 
 extern "C" const char* adj_last_error(void) { return g_err.c_str(); }
 
+// Largest contact count of one scene: m = 3 n_c <= 30000 keeps the padded
+// capacitance (mp^2 entries) addressable with 32-bit offsets.
+constexpr int kMaxContacts = 10000;
+
+// Scene construction without the per-scene contact cap (a batch's union
+// scene holds the sum of its scenes' contacts; its capacitance stays per
+// scene).
+static adj_status scene_create(const adj_scene_desc* desc, int32_t max_contacts, adj_scene** out);
+
 extern "C" adj_status adj_scene_create(const adj_scene_desc* desc, int32_t max_contacts,
                                        adj_scene** out) {
+  if (!out) return fail(ADJ_E_ARG, "out is null");
+  *out = nullptr;
+  if (max_contacts > kMaxContacts) return fail(ADJ_E_ARG, "max_contacts above 10000");
+  return scene_create(desc, max_contacts, out);
+}
+
+static adj_status scene_create(const adj_scene_desc* desc, int32_t max_contacts, adj_scene** out) {
   if (!out) return fail(ADJ_E_ARG, "out is null");
   *out = nullptr;
   if (max_contacts < 0) return fail(ADJ_E_ARG, "max_contacts < 0");
@@ -501,6 +517,7 @@ static adj_status build_capacitance(adj_scene* s, hipStream_t st, double mu, int
   if (!s->nc) return ADJ_OK;
   const double h2 = s->hs.h * s->hs.h;
   const int m = s->m, mp = ((m + 63) / 64) * 64;  // Gauss-Jordan tiles are 64 x 64
+  if (m > 3 * kMaxContacts) return fail(ADJ_E_SHAPE, "more than 10000 contacts in one capacitance");
   s->mp = mp;
   size_t capC = s->cap_m * s->cap_m, capB = capC;
   if ((size_t)mp > s->cap_m) capC = capB = 0;

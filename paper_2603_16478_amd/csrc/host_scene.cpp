@@ -111,7 +111,14 @@ std::vector<int32_t> make_row_tasks(const std::vector<int64_t>& rowptr, int64_t 
   std::vector<int32_t> t;
   std::vector<int32_t> small;
   const int n = (int)rowptr.size() - 1;
-  for (int r = 0; r < n; ++r) {
+  // longest rows first: blocks are dispatched in grid order, so the rows that
+  // bound the launch start earliest, and the rows sharing a block have
+  // similar lengths
+  std::vector<int32_t> order(n);
+  for (int r = 0; r < n; ++r) order[r] = r;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int32_t a, int32_t b) { return rowptr[a + 1] - rowptr[a] > rowptr[b + 1] - rowptr[b]; });
+  for (int r : order) {
     if (rowptr[r + 1] - rowptr[r] > big) {
       t.insert(t.end(), {r | 0x40000000, -1, -1, -1});
     } else {

@@ -53,6 +53,7 @@ struct HostScene {
 
 // Pack CSR rows into blocks: rows longer than `big` get a block each (flag
 // 0x40000000), shorter rows go four to a block; -1 marks an empty slot.
+// Tasks are ordered by decreasing row length.
 std::vector<int32_t> make_row_tasks(const std::vector<int64_t>& rowptr, int64_t big);
 
 // Returns ADJ_OK or an error code with a message in err.

@@ -284,15 +284,19 @@ __device__ __forceinline__ void invert32_rows(const double* __restrict__ Akk, in
 // with 2x2 (What) and 2x2 (update) accumulator tiles per wave.
 constexpr int kGT = 64;
 
+// 42 KB, so three blocks fit in one CU's LDS; the step kernels are held to
+// 168 registers (three waves per SIMD) with the A tile loaded after the
+// panels are staged.
 struct GjShared {
   double Ps[kNB][kNB + 1];   // P = A_kk^{-1}
-  double Cs[kGT][kNB + 1];   // A_{I,k} (tile rows, pivot columns)
+  double Cs[kGT][kNB + 1];   // A_{I,k} (tile rows, pivot columns), then -What
   double Rs[kNB][kGT + 1];   // Rhat (pivot rows, tile columns)
-  double Ws[kGT][kNB + 1];   // -What
   double prow[2 * kNB];      // pivot row broadcast of the block inversion
 };
 
-// One 64x64 output tile (I0, J0) of the block step at pivot k0.  With
+// One 64x64 output tile (I0, J0) of the block step at pivot k0.  Offsets
+// into the matrix are 32-bit (mp^2 < 2^32 for any capacitance size the
+// library accepts), which halves the address registers of the hoisted loads.  With
 // Pg == nullptr wavefront 0 inverts the pivot block itself; otherwise P is
 // read from Pg (32 x 32, row-major), inverted once per step beforehand.
 __device__ __forceinline__ void gj_tile(int mp, int k0, int I0, int J0, const double* __restrict__ A,
@@ -301,12 +305,29 @@ __device__ __forceinline__ void gj_tile(int mp, int k0, int I0, int J0, const do
   auto& Ps = sh.Ps;
   auto& Cs = sh.Cs;
   auto& Rs = sh.Rs;
-  auto& Ws = sh.Ws;
+  auto& Ws = sh.Cs;  // wave w reads and then overwrites only rows 16 w .. 16 w + 15
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
   // output sub-tiles of this wave: rows wr + 16 p, cols wc + 16 q (p, q < 2)
   const int wr = 32 * (w >> 1), wc = 32 * (w & 1);
-  // accumulators start at Ahat (f64 MFMA result layout: row lk + 4 e, col li)
+  if (Pg) {
+    for (int e = tid; e < kNB * kNB; e += 256) Ps[e / kNB][e % kNB] = Pg[e];
+  } else if (w == 0) {
+    invert32_rows(A + (size_t)k0 * mp + k0, mp, Ps, sh.prow, err);
+  }
+  for (int e = tid; e < kGT * kNB; e += 256) {
+    const int r = e / kNB, c = e % kNB;
+    Cs[r][c] = A[(unsigned)((I0 + r) * mp + k0 + c)];
+  }
+  for (int e = tid; e < kNB * kGT; e += 256) {
+    const int r = e / kGT, c = e % kGT;
+    const int j = J0 + c;
+    Rs[r][c] = (j >= k0 && j < k0 + kNB) ? ((j - k0 == r) ? 1.0 : 0.0) : A[(unsigned)((k0 + r) * mp + j)];
+  }
+  __syncthreads();
+  // accumulators start at Ahat (f64 MFMA result layout: row lk + 4 e, col
+  // li); loaded after the panels are staged, so these loads overlap the
+  // -What products and do not add to the staging's live registers
   d4 acc[2][2];
 #pragma unroll
   for (int p = 0; p < 2; ++p)
@@ -317,23 +338,8 @@ __device__ __forceinline__ void gj_tile(int mp, int k0, int I0, int J0, const do
         const int i = I0 + wr + 16 * p + lk + 4 * e;
         const int j = J0 + wc + 16 * q + li;
         const bool zero = (i >= k0 && i < k0 + kNB) || (j >= k0 && j < k0 + kNB);
-        acc[p][q][e] = zero ? 0.0 : A[(size_t)i * mp + j];
+        acc[p][q][e] = zero ? 0.0 : A[(unsigned)(i * mp + j)];
       }
-  if (Pg) {
-    for (int e = tid; e < kNB * kNB; e += 256) Ps[e / kNB][e % kNB] = Pg[e];
-  } else if (w == 0) {
-    invert32_rows(A + (size_t)k0 * mp + k0, mp, Ps, sh.prow, err);
-  }
-  for (int e = tid; e < kGT * kNB; e += 256) {
-    const int r = e / kNB, c = e % kNB;
-    Cs[r][c] = A[(size_t)(I0 + r) * mp + k0 + c];
-  }
-  for (int e = tid; e < kNB * kGT; e += 256) {
-    const int r = e / kGT, c = e % kGT;
-    const int j = J0 + c;
-    Rs[r][c] = (j >= k0 && j < k0 + kNB) ? ((j - k0 == r) ? 1.0 : 0.0) : A[(size_t)(k0 + r) * mp + j];
-  }
-  __syncthreads();
   // -What for the 64 tile rows: wave w computes rows 16 w .. 16 w + 15, both
   // 16-column halves of the 32 pivot columns.
   {
@@ -379,11 +385,12 @@ __device__ __forceinline__ void gj_tile(int mp, int k0, int I0, int J0, const do
       for (int e = 0; e < 4; ++e) {
         const int i = I0 + wr + 16 * p + lk + 4 * e;
         const int j = J0 + wc + 16 * q + li;
-        B[(size_t)i * mp + j] = acc[p][q][e];
+        B[(unsigned)(i * mp + j)] = acc[p][q][e];
       }
 }
 
-__global__ void __launch_bounds__(256) k_gj_step_mfma(int mp, int k0, const double* __restrict__ A,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
+k_gj_step_mfma(int mp, int k0, const double* __restrict__ A,
                                                       double* __restrict__ B, int* __restrict__ err) {
   __shared__ GjShared sh;
   gj_tile(mp, k0, blockIdx.y * kGT, blockIdx.x * kGT, A, B, err, sh);
@@ -405,43 +412,43 @@ __device__ __forceinline__ void gj_next_pivot(int mp, int k0, const double* __re
                                               const double* __restrict__ Pc, double* __restrict__ Pn,
                                               int* __restrict__ err, GjShared& sh) {
   const int k1 = k0 + kNB, tid = threadIdx.x;
-  // Cs[0..31] = A_k1k0, Ps = P_k, Rs[.][0..31] = A_k0k1, Ws[32..63] = A_k1k1
+  // Cs[0..31] = A_k1k0, Cs[32..63] = A_k1k1, Ps = P_k, Rs[.][0..31] = A_k0k1
+  // and Rs[.][32..63] = A_k1k0 P_k
   for (int e = tid; e < kNB * kNB; e += 256) {
     const int r = e / kNB, c = e % kNB;
     sh.Cs[r][c] = A[(size_t)(k1 + r) * mp + k0 + c];
+    sh.Cs[kNB + r][c] = A[(size_t)(k1 + r) * mp + k1 + c];
     sh.Ps[r][c] = Pc[e];
     sh.Rs[r][c] = A[(size_t)(k0 + r) * mp + k1 + c];
-    sh.Ws[kNB + r][c] = A[(size_t)(k1 + r) * mp + k1 + c];
   }
   __syncthreads();
   // one 16 x 16 output tile per wavefront, FP64 MFMA (A operand row li,
   // k lk; B operand k lk, column li; result row lk + 4 e, column li)
   const int lane = tid & 63, w = tid >> 6, li = lane & 15, lk = lane >> 4;
   const int R0 = 16 * (w >> 1), C0 = 16 * (w & 1);
-  // Ws[0..31] = A_k1k0 P_k
   {
     d4 acc = d4{0, 0, 0, 0};
 #pragma unroll
     for (int k4 = 0; k4 < kNB; k4 += 4)
       acc = __builtin_amdgcn_mfma_f64_16x16x4f64(sh.Cs[R0 + li][k4 + lk], sh.Ps[k4 + lk][C0 + li], acc, 0, 0, 0);
 #pragma unroll
-    for (int e = 0; e < 4; ++e) sh.Ws[R0 + lk + 4 * e][C0 + li] = acc[e];
+    for (int e = 0; e < 4; ++e) sh.Rs[R0 + lk + 4 * e][kNB + C0 + li] = acc[e];
   }
   __syncthreads();
-  // Ws[32..63] -= Ws[0..31] A_k0k1
+  // A_k1k1 -= (A_k1k0 P_k) A_k0k1
   {
     d4 acc;
 #pragma unroll
-    for (int e = 0; e < 4; ++e) acc[e] = sh.Ws[kNB + R0 + lk + 4 * e][C0 + li];
+    for (int e = 0; e < 4; ++e) acc[e] = sh.Cs[kNB + R0 + lk + 4 * e][C0 + li];
 #pragma unroll
     for (int k4 = 0; k4 < kNB; k4 += 4)
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(-sh.Ws[R0 + li][k4 + lk], sh.Rs[k4 + lk][C0 + li], acc, 0, 0, 0);
-    __syncthreads();
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(-sh.Rs[R0 + li][kNB + k4 + lk], sh.Rs[k4 + lk][C0 + li], acc, 0, 0,
+                                                 0);
 #pragma unroll
-    for (int e = 0; e < 4; ++e) sh.Ws[kNB + R0 + lk + 4 * e][C0 + li] = acc[e];
+    for (int e = 0; e < 4; ++e) sh.Cs[kNB + R0 + lk + 4 * e][C0 + li] = acc[e];
   }
   __syncthreads();
-  if (tid < 64) invert32_rows(&sh.Ws[kNB][0], kNB + 1, sh.Ps, sh.prow, err);
+  if (tid < 64) invert32_rows(&sh.Cs[kNB][0], kNB + 1, sh.Ps, sh.prow, err);
   __syncthreads();
   for (int e = tid; e < kNB * kNB; e += 256) Pn[e] = sh.Ps[e / kNB][e % kNB];
 }
@@ -458,7 +465,8 @@ __global__ void __launch_bounds__(64) kb_gj_pivot(const int* __restrict__ scenes
   for (int e = threadIdx.x; e < kNB * kNB; e += blockDim.x) P[e] = Ps[e / kNB][e % kNB];
 }
 
-__global__ void __launch_bounds__(256) kb_gj_step_mfma(const int* __restrict__ next_scenes, int npiv,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
+kb_gj_step_mfma(const int* __restrict__ next_scenes, int npiv,
                                                        const int4* __restrict__ tiles, int k0,
                                                        const long long* __restrict__ xoff,
                                                        const int* __restrict__ mps, const double* __restrict__ A,

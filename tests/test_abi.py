@@ -34,3 +34,15 @@ def test_library_exports_every_declared_symbol():
     assert not missing, missing
     from paper_2603_16478_amd import native
     assert sorted(native.EXPORTS) == _declared()
+
+
+def test_scene_create_rejects_too_many_contacts_before_any_device_work():
+    # the dense capacitance inverse of one scene is capped at 10000 contacts;
+    # the argument check runs before the scene is built or the device touched
+    lib = ctypes.CDLL(_lib_path())
+    from paper_2603_16478_amd import native
+    handle = ctypes.c_void_p()
+    st = lib.adj_scene_create(ctypes.byref(native.SceneDesc()), ctypes.c_int32(10001), ctypes.byref(handle))
+    assert native.STATUS[st] == "ADJ_E_ARG" and not handle.value
+    lib.adj_last_error.restype = ctypes.c_char_p
+    assert b"10000" in lib.adj_last_error()
