@@ -72,6 +72,72 @@ __device__ __forceinline__ void row_dot3(long long b, long long e, int t, const 
   }
 }
 
+// Woodbury gather rows: t_r = sum_k X[r][k] g[k], k < m (g in LDS), for
+// rows r = r0 + w, r0 + w + 4, ... below r1, row r at Xr + (r - r0) ld; four
+// X loads per lane in flight per pass.
+template <class MT>
+__device__ __forceinline__ void wb_gather_rows(int r0, int r1, int m, const MT* __restrict__ Xr, long long ld,
+                                               const double* __restrict__ g, double* __restrict__ t) {
+  const int lane = threadIdx.x & 63;
+  for (int r = r0 + (threadIdx.x >> 6); r < r1; r += 4) {
+    const MT* xr = Xr + (size_t)(r - r0) * ld;
+    double acc = 0.0;
+    for (int k0 = lane; k0 < m; k0 += 4 * 64) {
+      double x[4];
+      int kk[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int k = k0 + 64 * q;
+        kk[q] = k < m ? k : 0;
+        x[q] = k < m ? (double)xr[k] : 0.0;
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc = fma(x[q], g[kk[q]], acc);
+    }
+    acc = wave_sum(acc);
+    if (lane == 0) t[r] = acc;
+  }
+}
+
+// Woodbury correction rows: y_v = u_v - h2 sum_k Z[v][k] tp[k] (tp: [ncv][3]
+// in LDS) for rows v = v0 + w, v0 + w + 4, ... below v1 (w: wavefront of a
+// 256-thread block), Z row v at Zr + (v - v0) ncv; four Z loads per lane in
+// flight per pass.
+template <class MT>
+__device__ __forceinline__ void wb_rows(int v0, int v1, int ncv, const MT* __restrict__ Zr,
+                                        const double* __restrict__ tp, double h2, const double* __restrict__ u,
+                                        double* __restrict__ y) {
+  const int lane = threadIdx.x & 63;
+  for (int v = v0 + (threadIdx.x >> 6); v < v1; v += 4) {
+    const MT* zr = Zr + (size_t)(v - v0) * ncv;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+    for (int k0 = lane; k0 < ncv; k0 += 4 * 64) {
+      double z[4];
+      int kk[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int k = k0 + 64 * q;
+        kk[q] = k < ncv ? k : 0;
+        z[q] = k < ncv ? (double)zr[k] : 0.0;
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        a0 = fma(z[q], tp[3 * kk[q]], a0);
+        a1 = fma(z[q], tp[3 * kk[q] + 1], a1);
+        a2 = fma(z[q], tp[3 * kk[q] + 2], a2);
+      }
+    }
+    a0 = wave_sum(a0);
+    a1 = wave_sum(a1);
+    a2 = wave_sum(a2);
+    if (lane == 0) {
+      y[3 * v] = u[3 * v] - h2 * a0;
+      y[3 * v + 1] = u[3 * v + 1] - h2 * a1;
+      y[3 * v + 2] = u[3 * v + 2] - h2 * a2;
+    }
+  }
+}
+
 // res[i] = sum_b P[b * ld + i] for i < cnt (cnt <= 256), fixed order; all
 // 256 threads of the block take part; tmp: 256 doubles of LDS.
 __device__ __forceinline__ void sum_partials(const double* __restrict__ P, int nb, int ld, int cnt,

@@ -101,14 +101,8 @@ __global__ void __launch_bounds__(256) kb_wb_gather(const int4* __restrict__ tab
     g[r] = q[0] * u[3 * v] + q[1] * u[3 * v + 1] + q[2] * u[3 * v + 2];
   }
   __syncthreads();
-  const int lane = threadIdx.x & 63;
-  const int row = e.y + (threadIdx.x >> 6);  // union capacitance row
-  if (row >= e.z) return;
-  const double* xr = Xb + xpos[s] + (size_t)(row - r0) * mps[s];
-  double acc = 0.0;
-  for (int k = lane; k < m; k += 64) acc += xr[k] * g[k];
-  acc = wave_sum(acc);
-  if (lane == 0) t[row] = acc;
+  // union capacitance rows e.y .. e.z - 1
+  wb_gather_rows(e.y, e.z, m, Xb + xpos[s] + (size_t)(e.y - r0) * mps[s], mps[s], g, t);
 }
 
 // y = u - h^2 Z_s t' on the vertex rows of one scene (4 per block, one
@@ -142,27 +136,8 @@ __global__ void __launch_bounds__(256) kb_wb_correct(const int4* __restrict__ ta
     tp[3 * a + 2] = s2;
   }
   __syncthreads();
-  const int lane = threadIdx.x & 63;
-  const int v = e.y + (threadIdx.x >> 6);
-  if (v >= e.z) return;
-  double b0 = 0.0, b1 = 0.0, b2 = 0.0;
-  if (ncv > 0) {
-    const double* zr = Zb + yoff[s] + (size_t)(v - voff[s]) * ncv;
-    for (int k = lane; k < ncv; k += 64) {
-      const double zz = zr[k];
-      b0 += zz * tp[3 * k];
-      b1 += zz * tp[3 * k + 1];
-      b2 += zz * tp[3 * k + 2];
-    }
-    b0 = wave_sum(b0);
-    b1 = wave_sum(b1);
-    b2 = wave_sum(b2);
-  }
-  if (lane == 0) {
-    y[3 * v] = u[3 * v] - h2 * b0;
-    y[3 * v + 1] = u[3 * v + 1] - h2 * b1;
-    y[3 * v + 2] = u[3 * v + 2] - h2 * b2;
-  }
+  const double* Zr = Zb + yoff[s] + (size_t)(e.y - voff[s]) * ncv;
+  wb_rows(e.y, e.z, ncv, Zr, tp, h2, u, y);
 }
 
 // ---------------------------------------------------------------------------

@@ -113,7 +113,7 @@ __global__ void __launch_bounds__(256) k_spmv_tasks(const int4* __restrict__ tas
 // t = X (Hq u): each block first forms g = Hq u (m entries) in LDS, then one
 // wavefront per row of X.
 template <class MT>
-__global__ void __launch_bounds__(256) k_wb_gather(int m, int mp, const int* __restrict__ row_c,
+__global__ void __launch_bounds__(256) k_wb_gather(int m, int mp, int rows, const int* __restrict__ row_c,
                                                    const int* __restrict__ row_i,
                                                    const int* __restrict__ vid,
                                                    const double* __restrict__ Q,
@@ -130,20 +130,14 @@ __global__ void __launch_bounds__(256) k_wb_gather(int m, int mp, const int* __r
     g[r] = q[0] * u[3 * v] + q[1] * u[3 * v + 1] + q[2] * u[3 * v + 2];
   }
   __syncthreads();
-  const int lane = threadIdx.x & 63;
-  const int row = blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
-  if (row >= m) return;
-  const MT* xr = X + (size_t)row * mp;
-  double acc = 0.0;
-  for (int k = lane; k < m; k += 64) acc += (double)xr[k] * g[k];
-  acc = wave_sum(acc);
-  if (lane == 0) t[row] = acc;
+  const int r0 = blockIdx.x * rows;
+  wb_gather_rows(r0, min(m, r0 + rows), m, X + (size_t)r0 * mp, mp, g, t);
 }
 
 // y = u - h^2 Z t' with t'_cv = sum over the contacts at vertex cv of Q_c^T t_c
 // (computed per block in LDS); one wavefront per vertex row.
 template <class MT>
-__global__ void __launch_bounds__(256) k_wb_correct(int nv, int ncv, const int* __restrict__ cv_ptr,
+__global__ void __launch_bounds__(256) k_wb_correct(int nv, int ncv, int rows, const int* __restrict__ cv_ptr,
                                                     const int* __restrict__ c_row0,
                                                     const int* __restrict__ c_nrow,
                                                     const double* __restrict__ Q,
@@ -169,25 +163,8 @@ __global__ void __launch_bounds__(256) k_wb_correct(int nv, int ncv, const int* 
     tp[3 * a + 2] = s2;
   }
   __syncthreads();
-  const int lane = threadIdx.x & 63;
-  const int row = blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
-  if (row >= nv) return;
-  const MT* zr = Z + (size_t)row * ncv;
-  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-  for (int k = lane; k < ncv; k += 64) {
-    const double zz = (double)zr[k];
-    a0 += zz * tp[3 * k];
-    a1 += zz * tp[3 * k + 1];
-    a2 += zz * tp[3 * k + 2];
-  }
-  a0 = wave_sum(a0);
-  a1 = wave_sum(a1);
-  a2 = wave_sum(a2);
-  if (lane == 0) {
-    y[3 * row] = u[3 * row] - h2 * a0;
-    y[3 * row + 1] = u[3 * row + 1] - h2 * a1;
-    y[3 * row + 2] = u[3 * row + 2] - h2 * a2;
-  }
+  const int v0 = blockIdx.x * rows;
+  wb_rows(v0, min(nv, v0 + rows), ncv, Z + (size_t)v0 * ncv, tp, h2, u, y);
 }
 
 // w = Acal^T x, block-sparse 3x3; LANES lanes per block row (256 / LANES
@@ -583,8 +560,9 @@ template <class MT>
 static void wb_gather_impl(hipStream_t s, int m, int mp, const int* row_c, const int* row_i, const int* vid,
                            const double* Q, const MT* X, const double* u, const GmresState* st, double* t) {
   if (m == 0) return;
-  k_wb_gather<MT><<<(m + 3) / 4, 256, (size_t)m * sizeof(double), s>>>(m, mp, row_c, row_i, vid, Q, X, u, st,
-                                                                        t);
+  const int rows = wb_rows_per_block(m);
+  k_wb_gather<MT><<<(m + rows - 1) / rows, 256, (size_t)m * sizeof(double), s>>>(m, mp, rows, row_c, row_i, vid, Q, X,
+                                                                               u, st, t);
 }
 void launch_wb_gather(hipStream_t s, int m, int mp, const int* row_c, const int* row_i, const int* vid,
                       const double* Q, const double* X, const double* u, const GmresState* st, double* t) {
@@ -594,9 +572,10 @@ template <class MT>
 static void wb_correct_impl(hipStream_t s, int nv, int ncv, const int* cv_ptr, const int* c_row0,
                             const int* c_nrow, const double* Q, const double* t, const MT* Z, double h2,
                             const double* u, const GmresState* st, double* y) {
-  k_wb_correct<MT><<<(nv + 3) / 4, 256, (size_t)3 * ncv * sizeof(double), s>>>(nv, ncv, cv_ptr, c_row0,
-                                                                                c_nrow, Q, t, Z, h2, u, st,
-                                                                                y);
+  const int rows = wb_rows_per_block(nv);
+  k_wb_correct<MT><<<(nv + rows - 1) / rows, 256, (size_t)3 * ncv * sizeof(double), s>>>(nv, ncv, rows, cv_ptr,
+                                                                                        c_row0, c_nrow, Q, t, Z, h2,
+                                                                                        u, st, y);
 }
 void launch_wb_correct(hipStream_t s, int nv, int ncv, const int* cv_ptr, const int* c_row0, const int* c_nrow,
                        const double* Q, const double* t, const double* Z, double h2, const double* u,

@@ -4,6 +4,15 @@
 
 namespace adj {
 
+// Rows per 256-thread block of the Woodbury gather (capacitance rows) and
+// correction (vertex rows), four per wavefront: 4 while that gives at least
+// ~2048 blocks, up to 16 for large batches (each block first stages a
+// per-scene vector in LDS, which the extra rows amortise).
+inline int wb_rows_per_block(long long total_rows) {
+  const long long q = (total_rows + 4 * 2048 - 1) / (4 * 2048);
+  return 4 * (int)(q < 1 ? 1 : (q > 4 ? 4 : q));
+}
+
 struct GmresState {
   int j;          // completed iterations of this cycle (PCG: of this pass)
   int active;     // 1 while the cycle runs
