@@ -214,7 +214,8 @@ adj_status adj_debug_export(const adj_scene* scene, int32_t what, void* host_out
  * 3 = Z product, 4 = block-sparse Acal^T product (in the Krylov loop fused
  * with the first Gram-Schmidt dots), 5 = per-tet Jacobian blocks, 6 = gather
  * assembly, 7 = the whole capacitance inversion, 8 = second Gram-Schmidt
- * update with the Givens step, 9 = first Gram-Schmidt update.  At most 65536 launches
+ * update with the Givens step, 9 = first Gram-Schmidt update, 10 = one
+ * Gauss-Jordan block step of the capacitance inversion.  At most 65536 launches
  * are timed per region (later ones are not). */
 adj_status adj_profile_begin(adj_scene* scene, int32_t kernel);
 adj_status adj_profile_end(adj_scene* scene, double* total_ms, int64_t* launches);

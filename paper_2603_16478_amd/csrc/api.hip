@@ -40,7 +40,8 @@ void launch_fill_zero(hipStream_t, size_t, double*);
 void launch_delassus(hipStream_t, int, int, const int*, const long long*, const int*, const double*,
                      double*, double*, double*, double*);
 int delassus_slices(int, int);
-double* launch_gauss_jordan(hipStream_t, int, int, double*, double*, int*);
+void launch_gj_pad(hipStream_t, int, int, double*);
+void launch_gj_step(hipStream_t, int, int, const double*, double*, int*);
 void launch_spmv_csr3(hipStream_t, int, const long long*, const int*, const double*, const double*,
                       long long, const double*, const GmresState*, double*);
 void launch_spmv_tasks(hipStream_t, int, const int4*, const long long*, const int*, const double*,
@@ -529,7 +530,15 @@ static adj_status build_capacitance(adj_scene* s, hipStream_t st, double mu, int
                      transpose, s->d_C);
   {
     ProfScope p(s, 7, st);
-    s->d_X = launch_gauss_jordan(st, m, mp, s->d_C, s->d_colbuf, s->d_err);
+    launch_gj_pad(st, m, mp, s->d_C);
+    double* A = s->d_C;
+    double* B = s->d_colbuf;
+    for (int k = 0; k < mp / 32; ++k) {
+      ProfScope pk(s, 10, st);
+      launch_gj_step(st, mp, k, A, B, s->d_err);
+      std::swap(A, B);
+    }
+    s->d_X = A;
   }
   return ADJ_OK;
 }
@@ -1049,7 +1058,7 @@ extern "C" adj_status adj_autotune(adj_scene* s, const double* dL_dq, const doub
 }
 
 extern "C" adj_status adj_profile_begin(adj_scene* s, int32_t kernel) {
-  if (!s || kernel < 0 || kernel > 9) return fail(ADJ_E_ARG, "bad profile request");
+  if (!s || kernel < 0 || kernel > 10) return fail(ADJ_E_ARG, "bad profile request");
   s->prof_kernel = kernel;
   s->prof_used = 0;
   return ADJ_OK;

@@ -527,24 +527,20 @@ void launch_delassus(hipStream_t st, int nv, int ncv, const int* cv, const long 
 }
 
 // Inverse of the m x m capacitance held in the top-left of the row-major
-// mp x mp buffer C0 (mp a multiple of 64, padding rows and columns set to
-// the identity here); returns the buffer (C0 or C1) holding the inverse.
-double* launch_gauss_jordan(hipStream_t st, int m, int mp, double* C0, double* C1, int* err) {
-  if (mp > m) {
-    dim3 gpad((mp + 255) / 256, mp);
-    k_pad_identity<<<gpad, 256, 0, st>>>(m, mp, C0);
-  }
-  double* A = C0;
-  double* B = C1;
-  const int nb = mp / kNB;
-  for (int k = 0; k < nb; ++k) {
-    dim3 g(mp / kGT, mp / kGT);
-    k_gj_step_mfma<<<g, 256, 0, st>>>(mp, k * kNB, A, B, err);
-    double* t = A;
-    A = B;
-    B = t;
-  }
-  return A;
+// mp x mp buffer C0 (mp a multiple of 64): launch_gj_pad sets the padding
+// rows and columns to the identity, then launch_gj_step runs block step k
+// (k = 0 .. mp/32 - 1) from A into B, the two buffers swapping roles each
+// step; after the last step the inverse is in C0 when mp/32 is even, else
+// in C1.
+void launch_gj_pad(hipStream_t st, int m, int mp, double* C0) {
+  if (mp <= m) return;
+  dim3 gpad((mp + 255) / 256, mp);
+  k_pad_identity<<<gpad, 256, 0, st>>>(m, mp, C0);
+}
+
+void launch_gj_step(hipStream_t st, int mp, int k, const double* A, double* B, int* err) {
+  dim3 g(mp / kGT, mp / kGT);
+  k_gj_step_mfma<<<g, 256, 0, st>>>(mp, k * kNB, A, B, err);
 }
 
 void launchb_gj_pivot(hipStream_t st, int nscenes, const int* scenes, const long long* xoff, const int* mps,

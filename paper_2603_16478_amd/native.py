@@ -31,7 +31,7 @@ EXPORTS = ("adj_scene_create", "adj_scene_destroy", "adjoint_setup", "adjoint_so
            "adj_batch_info", "adj_batch_setup", "adj_batch_solve", "adj_batch_vjp", "adj_batch_check_status",
            "adj_batch_debug_export", "adj_batch_scene", "adj_last_error")
 KERNELS = {"S": 0, "ST": 1, "capinv": 2, "Z": 3, "bsr": 4, "tet": 5, "assemble": 6, "gj": 7,
-           "gs_pass2": 8, "gs_pass1": 9}
+           "gs_pass2": 8, "gs_pass1": 9, "gj_step": 10}
 
 
 class AdjError(RuntimeError):
