@@ -284,6 +284,27 @@ adj_status adj_batch_solve(adj_batch* batch, const double* dL_dq, const double* 
 adj_status adj_batch_vjp(adj_batch* batch, const double* z, const double* dL_dv, double* dL_dqbar,
                          double* dL_dvbar, double* dL_dfext, double* grad, void* stream);
 
+/* Reverse pass over n_steps recorded steps of a batch (the time recursion of
+ * Sec. 5.1): for t = n_steps-1 down to 0, setup at (q[t], contacts[t]),
+ * one GMRES per scene on Acal_t^T z = gq + gv / h, the gradient contractions,
+ * then gq <- dL/dqbar, gv <- dL/dvbar.  The setup of step t-1 needs no
+ * gradient, so it runs on a second stream of the library's while step t is
+ * solved: b0 and b1 are two batches created from the same scene
+ * descriptions and take the steps in turn (step t on b0 when t is even).
+ * contacts: host [n_steps][n_scenes] (device arrays as for adj_batch_setup);
+ * q: host [n_steps] of device packed states; gq, gv: device packed, in: the
+ * loss gradients w.r.t. the last state, out: w.r.t. the state before step
+ * 0; dfext: host [n_steps] of device packed outputs (dL/df_ext of step t)
+ * or NULL; grad: device [n_scenes * 3], accumulated over the steps; info:
+ * host [n_steps][n_scenes] or NULL.  The call returns when the last solve
+ * has been read back (the last contractions may still run on `stream`).
+ * Errors as for the batch calls; ADJ_E_NOCONV (after finishing the pass)
+ * if a scene did not converge in some step.  Device-side setup errors are
+ * reported by adj_batch_check_status on either batch. */
+adj_status adj_batch_reverse(adj_batch* b0, adj_batch* b1, int32_t n_steps, const adj_contact_state* contacts,
+                             const double* const* q, double* gq, double* gv, double* const* dfext, double* grad,
+                             const adj_solve_opts* opts, adj_solve_info* info, void* stream);
+
 /* As adj_check_status, for the batch's last setup. */
 adj_status adj_batch_check_status(adj_batch* batch, void* stream);
 

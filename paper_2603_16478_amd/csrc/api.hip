@@ -5,6 +5,9 @@
 
 #include <algorithm>
 #include <cmath>
+#include <condition_variable>
+#include <mutex>
+#include <thread>
 #include <unordered_map>
 #include <cstdio>
 #include <cstring>
@@ -436,7 +439,10 @@ extern "C" adj_status adj_scene_info(const adj_scene* s, int64_t* out) {
 
 static adj_status grow(double** p, size_t* cap, size_t need) {
   if (need <= *cap && *p) return ADJ_OK;
-  if (*p) (void)hipFree(*p);
+  if (*p) {
+    (void)hipDeviceSynchronize();  // the old buffer may still be read on another stream
+    (void)hipFree(*p);
+  }
   *p = nullptr;
   if (dalloc(p, need) != hipSuccess) {
     *cap = 0;

@@ -29,7 +29,7 @@ EXPORTS = ("adj_scene_create", "adj_scene_destroy", "adjoint_setup", "adjoint_so
            "adj_profile_begin", "adj_profile_end", "adj_forward_stats", "adj_forward_reset",
            "adj_set_tuning", "adj_get_tuning", "adj_autotune", "adj_batch_create", "adj_batch_destroy",
            "adj_batch_info", "adj_batch_setup", "adj_batch_solve", "adj_batch_vjp", "adj_batch_check_status",
-           "adj_batch_debug_export", "adj_batch_scene", "adj_last_error")
+           "adj_batch_debug_export", "adj_batch_scene", "adj_batch_reverse", "adj_last_error")
 KERNELS = {"S": 0, "ST": 1, "capinv": 2, "Z": 3, "bsr": 4, "tet": 5, "assemble": 6, "gj": 7,
            "gs_pass2": 8, "gs_pass1": 9, "gj_step": 10}
 
@@ -111,6 +111,8 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.adj_batch_check_status.argtypes = [vp, vp]
     lib.adj_batch_debug_export.argtypes = [vp, C.c_int32, C.c_int32, vp, C.c_int64, C.POINTER(C.c_int64)]
     lib.adj_batch_scene.argtypes = [vp, C.POINTER(vp)]
+    lib.adj_batch_reverse.argtypes = [vp, vp, C.c_int32, C.POINTER(ContactState), C.POINTER(vp), vp, vp,
+                                      C.POINTER(vp), vp, C.POINTER(SolveOpts), C.POINTER(SolveInfo), vp]
     for name in EXPORTS:
         if name != "adj_last_error":
             getattr(lib, name).restype = C.c_int
@@ -400,6 +402,27 @@ def batch_solve(batch: Batch, dL_dq, dL_dv, z, opts: SolveOpts, stream=None, rai
 def batch_vjp(batch: Batch, z, dL_dv, dL_dqbar, dL_dvbar, dL_dfext, grad, stream=None):
     check(load().adj_batch_vjp(batch.handle, _ptr(z), _ptr(dL_dv), _ptr(dL_dqbar), _ptr(dL_dvbar),
                                _ptr(dL_dfext), _ptr(grad), _stream(stream)))
+
+
+def batch_reverse(b0: Batch, b1: Batch, contacts, q, gq, gv, dfext, grad, opts: SolveOpts, stream=None,
+                  raise_noconv=True):
+    """Reverse pass over len(q) recorded steps (adj_batch_reverse): contacts[t]
+    is the list of per-scene ContactState of step t, q[t] its packed state;
+    gq, gv are updated in place; dfext: list of packed outputs or None.
+    Returns the per-step lists of SolveInfo."""
+    T, ns = len(q), b0.n_scenes
+    flat = [c for step in contacts for c in step]
+    if len(contacts) != T or len(flat) != T * ns:
+        raise ValueError("contacts must hold n_scenes states for every step")
+    carr = (ContactState * (T * ns))(*flat)
+    qarr = (C.c_void_p * T)(*[_ptr(x) for x in q])
+    darr = None if dfext is None else (C.c_void_p * T)(*[_ptr(x) for x in dfext])
+    infos = (SolveInfo * (T * ns))()
+    st = load().adj_batch_reverse(b0.handle, b1.handle, int(T), carr, qarr, _ptr(gq), _ptr(gv), darr, _ptr(grad),
+                                  C.byref(opts), infos, _stream(stream))
+    if st != 0 and (raise_noconv or STATUS.get(st) != "ADJ_E_NOCONV"):
+        check(st)
+    return [list(infos[t * ns:(t + 1) * ns]) for t in range(T)]
 
 
 def batch_check_status(batch: Batch, stream=None):

@@ -46,3 +46,12 @@ def test_scene_create_rejects_too_many_contacts_before_any_device_work():
     assert native.STATUS[st] == "ADJ_E_ARG" and not handle.value
     lib.adj_last_error.restype = ctypes.c_char_p
     assert b"10000" in lib.adj_last_error()
+
+
+def test_binding_declares_argument_types_of_every_entry_point():
+    # an undeclared ctypes signature passes Python ints as 32-bit C ints,
+    # which truncates device pointers
+    from paper_2603_16478_amd import native
+    lib = native.load()
+    missing = [n for n in native.EXPORTS if n != "adj_last_error" and getattr(lib, n).argtypes is None]
+    assert not missing, missing
