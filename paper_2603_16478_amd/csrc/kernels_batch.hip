@@ -326,7 +326,8 @@ __global__ void __launch_bounds__(256) kb_residual(const int4* __restrict__ tab,
 // set_tol = 1 (first call) the tolerance becomes rtol * |r|.
 __global__ void __launch_bounds__(256) kb_residual_finish(GmresState* __restrict__ st, const int2* __restrict__ rng,
                                                           const double* __restrict__ P, double* __restrict__ scale,
-                                                          int lds_scale, double* __restrict__ gvec, double rtol,
+                                                          int lds_scale, double* __restrict__ gvec,
+                                                          const double* __restrict__ rtol, double* __restrict__ bnorm,
                                                           int set_tol) {
   const int s = blockIdx.x;
   GmresState& S = st[s];
@@ -337,7 +338,10 @@ __global__ void __launch_bounds__(256) kb_residual_finish(GmresState* __restrict
   sum_partials(P + (size_t)rg.x * kBLd, rg.y - rg.x, kBLd, 1, nn, tmp);
   if (threadIdx.x != 0) return;
   const double nrm = sqrt(nn[0]);
-  if (set_tol) S.tol = rtol * nrm;
+  if (set_tol) {  // first residual of a solve: r = b, tolerance relative to |b_s|
+    S.tol = rtol[s] * nrm;
+    bnorm[s] = nrm;
+  }
   S.rnorm = nrm;
   S.res = nrm;
   S.j = 0;
@@ -683,10 +687,10 @@ void launchb_gm_givens(hipStream_t s, int ns, GmresState* st, const int2* rng, c
   kb_gm_givens<<<ns, 256, 0, s>>>(st, rng, P, scale, lds, hbuf, H, cs, sn, g);
 }
 void launchb_residual(hipStream_t s, int nblk, int ns, const int4* tab, const int2* rng, const double* b, double* r,
-                      double* v0, GmresState* st, double* P, double* scale, int lds, double* g, double rtol,
-                      int set_tol) {
+                      double* v0, GmresState* st, double* P, double* scale, int lds, double* g, const double* rtol,
+                      double* bnorm, int set_tol) {
   kb_residual<<<nblk, 256, 0, s>>>(tab, b, r, v0, st, P);
-  kb_residual_finish<<<ns, 256, 0, s>>>(st, rng, P, scale, lds, g, rtol, set_tol);
+  kb_residual_finish<<<ns, 256, 0, s>>>(st, rng, P, scale, lds, g, rtol, bnorm, set_tol);
 }
 void launchb_finish(hipStream_t s, int ns, long long n, const int* vscene, const GmresState* st, const double* H,
                     const double* g, const double* scale, int lds, const double* Vt, long long stride, double* coef,
