@@ -570,10 +570,28 @@ __global__ void __launch_bounds__(256) kb_param_sums(const int* __restrict__ tof
   }
 }
 
-// dst[i] = src[i] + off (contact vertex ids of one scene into union ids)
-__global__ void kb_offset_ints(int n, const int* __restrict__ src, int off, int* __restrict__ dst) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) dst[i] = src[i] + off;
+// Union contact arrays from every scene's arrays in one launch: thread c
+// finds its scene (ns is small: linear scan of the ranges), shifts the
+// vertex id by the scene's first union vertex and copies the frame, gap,
+// and multiplier rows.
+__global__ void kb_gather_contacts(int nc, int ns, const ContactSrc* __restrict__ src, int* __restrict__ vid,
+                                   int* __restrict__ fric, double* __restrict__ frame, double* __restrict__ delta,
+                                   double* __restrict__ lam) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nc) return;
+  int s = 0;
+  while (s + 1 < ns && src[s + 1].off <= c) ++s;
+  const ContactSrc& S = src[s];
+  const int k = c - S.off;
+  vid[c] = S.vid[k] + S.voff;
+  fric[c] = S.fric[k];
+#pragma unroll
+  for (int e = 0; e < 9; ++e) frame[9 * c + e] = S.frame[9 * k + e];
+#pragma unroll
+  for (int e = 0; e < 3; ++e) {
+    delta[3 * c + e] = S.delta[3 * k + e];
+    lam[3 * c + e] = S.lam[3 * k + e];
+  }
 }
 
 // active = 1 for every scene not yet converged (before the end-of-cycle
@@ -740,8 +758,9 @@ void launchb_param_sums(hipStream_t s, int ns, const int* toff, const int* coff,
                         const double* tN, const double* gmu, double* grad) {
   kb_param_sums<<<ns, 256, 0, s>>>(toff, coff, tE, tN, gmu, grad);
 }
-void launchb_offset_ints(hipStream_t s, int n, const int* src, int off, int* dst) {
-  if (n > 0) kb_offset_ints<<<(n + 255) / 256, 256, 0, s>>>(n, src, off, dst);
+void launchb_gather_contacts(hipStream_t s, int nc, int ns, const ContactSrc* src, int* vid, int* fric, double* frame,
+                             double* delta, double* lam) {
+  if (nc > 0) kb_gather_contacts<<<(nc + 255) / 256, 256, 0, s>>>(nc, ns, src, vid, fric, frame, delta, lam);
 }
 
 }  // namespace adj

@@ -13,6 +13,20 @@ inline int wb_rows_per_block(long long total_rows) {
   return 4 * (int)(q < 1 ? 1 : (q > 4 ? 4 : q));
 }
 
+// Where one scene's contact arrays live (caller's device memory) and where
+// they go in the union arrays; shared by the gather kernel and the host.
+struct ContactSrc {
+  const int* vid;
+  const int* fric;
+  const double* frame;
+  const double* delta;
+  const double* lam;
+  int n;     // contacts of the scene
+  int off;   // first union contact
+  int voff;  // first union vertex
+  int pad;
+};
+
 struct GmresState {
   int j;          // completed iterations of this cycle (PCG: of this pass)
   int active;     // 1 while the cycle runs
