@@ -98,6 +98,16 @@ typedef struct {
  * GMRES otherwise; ADJ_PCG on a non-symmetric system is ADJ_E_ARG. */
 typedef enum { ADJ_AUTO = 0, ADJ_GMRES = 1, ADJ_PCG = 2 } adj_krylov;
 
+/* Preconditioner of the Krylov solve (single-scene calls; batches use the
+ * Woodbury one).  ADJ_PRECOND_WOODBURY: A^{-1} = S^T S with the contact
+ * blocks through the Woodbury identity (Sec. 5.4, the paper's choice);
+ * ADJ_PRECOND_SPARSE_INVERSE: S^T S alone (the contact blocks are left to
+ * the Krylov method); ADJ_PRECOND_JACOBI: the inverses of the 3x3 diagonal
+ * blocks of Acal^T.  The latter two are the comparison preconditioners the
+ * paper's backward-solver study measures against; all three give the same
+ * solution to the tolerance. */
+typedef enum { ADJ_PRECOND_WOODBURY = 0, ADJ_PRECOND_SPARSE_INVERSE = 1, ADJ_PRECOND_JACOBI = 2 } adj_precond;
+
 typedef struct {
   double rtol;          /* relative residual |b - Acal^T z| / |b| (Sec. 6.1: 1e-8) */
   int32_t maxit;        /* total Krylov iterations over all restarts */
@@ -106,6 +116,7 @@ typedef struct {
   adj_precision prec;
   int32_t reuse_delassus; /* 1: keep H A^{-1} H^T while the contact vertex set is unchanged */
   adj_krylov method;
+  adj_precond precond;  /* 0 (zero-initialised options): Woodbury */
 } adj_solve_opts;
 
 typedef struct {

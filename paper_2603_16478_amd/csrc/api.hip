@@ -47,6 +47,10 @@ void launch_gj_pad(hipStream_t, int, int, double*);
 void launch_gj_step(hipStream_t, int, int, const double*, double*, int*);
 void launch_spmv_csr3(hipStream_t, int, const long long*, const int*, const double*, const double*,
                       long long, const double*, const GmresState*, double*);
+void launch_block_jacobi(hipStream_t, int, const int*, const double*, const double*, long long, const double*,
+                         const GmresState*, double*);
+void launch_block_jacobi(hipStream_t, int, const int*, const float*, const double*, long long, const double*,
+                         const GmresState*, double*);
 void launch_spmv_tasks(hipStream_t, int, const int4*, const long long*, const int*, const double*,
                        const double*, long long, const double*, const GmresState*, double*);
 void launch_spmv_tasks(hipStream_t, int, const int4*, const long long*, const int*, const float*,
@@ -201,6 +205,10 @@ struct adj_scene {
   // captured Krylov chunks (tuning.graph = 1), rebuilt after every setup
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t chunk_exec[4] = {nullptr, nullptr, nullptr, nullptr};  // [pcg][f32]
+  // preconditioner of the Krylov solves (adj_precond), set per solve;
+  // woodbury_ready: the last setup built the capacitance inverse
+  int precond = ADJ_PRECOND_WOODBURY;
+  bool woodbury_ready = false;
   // live kernel timing (adj_profile_begin / adj_profile_end)
   int prof_kernel = -1;
   std::vector<hipEvent_t> prof_ev;
@@ -464,7 +472,7 @@ static void drop_chunk_graphs(adj_scene* s) {
 
 // Delassus matrix / Z (rebuilt only when the contact vertex set changes).
 static adj_status contact_layout(adj_scene* s, hipStream_t st, int nc, const std::vector<int>& vid,
-                                 const std::vector<int>& fric, bool reuse) {
+                                 const std::vector<int>& fric, bool reuse, bool delassus = true) {
   drop_chunk_graphs(s);  // captured chunks hold the contact layout
   std::vector<int> cv, cv_ptr, cmap(nc), row_c, row_i, c_row0(nc), c_nrow(nc);
   for (int c = 0; c < nc; ++c) {
@@ -498,7 +506,7 @@ static adj_status contact_layout(adj_scene* s, hipStream_t st, int nc, const std
     HIPCHK(hipStreamSynchronize(st));  // host vectors go out of scope
   }
   s->delassus_rebuilt = 0;
-  if (nc && !(reuse && s->delassus_valid && cv == s->cv_cached)) {
+  if (nc && delassus && !(reuse && s->delassus_valid && cv == s->cv_cached)) {
     adj_status a;
     size_t capY = s->cap_ncv ? (size_t)s->nv * s->cap_ncv : 0, capD = s->cap_ncv * s->cap_ncv, capZ = capY;
     if ((size_t)ncv > s->cap_ncv) capY = capZ = capD = 0;
@@ -590,10 +598,13 @@ extern "C" adj_status adjoint_setup(adj_scene* s, const adj_contact_state* cst, 
   launch_contact_blocks(st, nc, cst->fric, cst->frame, cst->delta, cst->lambda, cst->mu, nullptr, s->hs.eps, h2, 1,
                         s->d_Wt, s->d_Q, s->d_kh, s->d_Kc, s->d_kmu);
   launch_contact_fold(st, nc, cst->vid, s->d_diag_slot, s->d_Wt, s->d_val);
-  // a4: Delassus (cached per contact vertex set), capacitance, its inverse
-  adj_status a = contact_layout(s, st, nc, vid, fric, opts ? opts->reuse_delassus != 0 : true);
+  // a4: Delassus (cached per contact vertex set), capacitance, its inverse;
+  // skipped when the solves will use a comparison preconditioner
+  const bool woodbury = !opts || opts->precond == ADJ_PRECOND_WOODBURY;
+  adj_status a = contact_layout(s, st, nc, vid, fric, opts ? opts->reuse_delassus != 0 : true, woodbury);
   if (a != ADJ_OK) return a;
-  if ((a = build_capacitance(s, st, cst->mu, 1)) != ADJ_OK) return a;
+  if (woodbury && (a = build_capacitance(s, st, cst->mu, 1)) != ADJ_OK) return a;
+  s->woodbury_ready = woodbury;
   s->mixed_ready = false;
   if (opts && opts->prec == ADJ_MIXED) {
     // FP32 storage of the block matrix read by the inner solve (S and S^T
@@ -625,6 +636,14 @@ extern "C" adj_status adj_check_status(adj_scene* s, void* stream) {
 static void apply_precond(adj_scene* s, hipStream_t st, const double* x, long long stride,
                           const double* scale, const GmresState* state, double* out, bool f32 = false) {
   const double h2 = s->hs.h * s->hs.h;
+  if (s->precond == ADJ_PRECOND_JACOBI) {
+    if (f32)
+      launch_block_jacobi(st, s->nv, s->d_diag_slot, s->d_val32, x, stride, scale, state, out);
+    else
+      launch_block_jacobi(st, s->nv, s->d_diag_slot, s->d_val, x, stride, scale, state, out);
+    return;
+  }
+  const bool woodbury = s->nc > 0 && s->precond == ADJ_PRECOND_WOODBURY;
   {
     ProfScope p(s, 0, st);
     if (f32)
@@ -634,7 +653,7 @@ static void apply_precond(adj_scene* s, hipStream_t st, const double* x, long lo
       launch_spmv_tasks(st, s->nS_tasks, (const int4*)s->d_Stasks, s->d_Sp, s->d_Sj, s->d_Sx, x, stride,
                         scale, state, s->d_t1);
   }
-  double* u = (s->nc == 0) ? out : s->d_u;
+  double* u = woodbury ? s->d_u : out;
   {
     ProfScope p(s, 1, st);
     if (f32)
@@ -644,7 +663,7 @@ static void apply_precond(adj_scene* s, hipStream_t st, const double* x, long lo
       launch_spmv_tasks(st, s->nST_tasks, (const int4*)s->d_STtasks, s->d_STp, s->d_STj, s->d_STx, s->d_t1,
                         0, nullptr, state, u);
   }
-  if (s->nc == 0) return;
+  if (!woodbury) return;
   {
     ProfScope p(s, 2, st);
     launch_wb_gather(st, s->m, s->mp, s->d_row_c, s->d_row_i, s->cur_vid, s->d_Q, s->d_X, s->d_u, state,
@@ -894,6 +913,15 @@ extern "C" adj_status adjoint_solve(adj_scene* s, const double* dL_dq, const dou
   if (opts->prec != ADJ_FP64 && opts->prec != ADJ_MIXED) return fail(ADJ_E_ARG, "unknown precision");
   if (opts->method != ADJ_AUTO && opts->method != ADJ_GMRES && opts->method != ADJ_PCG)
     return fail(ADJ_E_ARG, "unknown Krylov method");
+  if (opts->precond != ADJ_PRECOND_WOODBURY && opts->precond != ADJ_PRECOND_SPARSE_INVERSE &&
+      opts->precond != ADJ_PRECOND_JACOBI)
+    return fail(ADJ_E_ARG, "unknown preconditioner");
+  if (opts->precond == ADJ_PRECOND_WOODBURY && s->nc > 0 && !s->woodbury_ready)
+    return fail(ADJ_E_ARG, "the last adjoint_setup skipped the Woodbury factors (it ran with another precond)");
+  if (opts->precond != s->precond) {
+    drop_chunk_graphs(s);  // captured chunks hold the preconditioner's launches
+    s->precond = opts->precond;
+  }
   if (opts->method == ADJ_PCG && !s->symmetric)
     return fail(ADJ_E_ARG, "PCG needs a symmetric system (no frictional contact, or mu = 0)");
   const bool use_pcg = opts->method == ADJ_PCG || (opts->method == ADJ_AUTO && s->symmetric);

@@ -110,6 +110,38 @@ __global__ void __launch_bounds__(256) k_spmv_tasks(const int4* __restrict__ tas
   }
 }
 
+// Block-Jacobi preconditioner: y_v = B_v^{-1} x_v with B_v the 3x3
+// diagonal block of the assembled matrix (row v's block at slot
+// diag_slot[v], row-major), inverted per apply by the adjugate (B_v is the
+// mass block plus stiffness and contact terms, far from singular).  The
+// input vector follows the same lazily scaled basis convention as the
+// sparse-inverse product.
+template <class MT>
+__global__ void k_block_jacobi(int nv, const int* __restrict__ diag_slot, const MT* __restrict__ val,
+                               const double* __restrict__ xbase, long long stride, const double* __restrict__ scale,
+                               const GmresState* __restrict__ st, int use_j, double* __restrict__ y) {
+  if (gm_inactive(st)) return;
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= nv) return;
+  const double* x = xbase;
+  double sc = 1.0;
+  if (use_j) {
+    x = xbase + (long long)st->j * stride;
+    sc = scale[st->j];
+  }
+  const MT* b = val + 9LL * diag_slot[v];
+  const double a00 = b[0], a01 = b[1], a02 = b[2], a10 = b[3], a11 = b[4], a12 = b[5], a20 = b[6], a21 = b[7],
+               a22 = b[8];
+  const double c00 = a11 * a22 - a12 * a21, c01 = a02 * a21 - a01 * a22, c02 = a01 * a12 - a02 * a11;
+  const double c10 = a12 * a20 - a10 * a22, c11 = a00 * a22 - a02 * a20, c12 = a02 * a10 - a00 * a12;
+  const double c20 = a10 * a21 - a11 * a20, c21 = a01 * a20 - a00 * a21, c22 = a00 * a11 - a01 * a10;
+  const double inv = sc / (a00 * c00 + a01 * c10 + a02 * c20);
+  const double x0 = x[3 * v], x1 = x[3 * v + 1], x2 = x[3 * v + 2];
+  y[3 * v] = inv * (c00 * x0 + c01 * x1 + c02 * x2);
+  y[3 * v + 1] = inv * (c10 * x0 + c11 * x1 + c12 * x2);
+  y[3 * v + 2] = inv * (c20 * x0 + c21 * x1 + c22 * x2);
+}
+
 // t = X (Hq u): each block first forms g = Hq u (m entries) in LDS, then one
 // wavefront per row of X.
 template <class MT>
@@ -556,6 +588,16 @@ void launch_spmv_tasks(hipStream_t s, int ntasks, const int4* tasks, const long 
   spmv_tasks_impl(s, ntasks, tasks, rp, cj, cx, xbase, stride, scale, st, y);
 }
 
+void launch_block_jacobi(hipStream_t s, int nv, const int* diag_slot, const double* val, const double* x,
+                         long long stride, const double* scale, const GmresState* st, double* y) {
+  const int use_j = (st != nullptr && scale != nullptr) ? 1 : 0;
+  k_block_jacobi<double><<<(nv + 255) / 256, 256, 0, s>>>(nv, diag_slot, val, x, stride, scale, st, use_j, y);
+}
+void launch_block_jacobi(hipStream_t s, int nv, const int* diag_slot, const float* val, const double* x,
+                         long long stride, const double* scale, const GmresState* st, double* y) {
+  const int use_j = (st != nullptr && scale != nullptr) ? 1 : 0;
+  k_block_jacobi<float><<<(nv + 255) / 256, 256, 0, s>>>(nv, diag_slot, val, x, stride, scale, st, use_j, y);
+}
 template <class MT>
 static void wb_gather_impl(hipStream_t s, int m, int mp, const int* row_c, const int* row_i, const int* vid,
                            const double* Q, const MT* X, const double* u, const GmresState* st, double* t) {

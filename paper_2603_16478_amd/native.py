@@ -22,6 +22,7 @@ STATUS = {0: "ADJ_OK", -1: "ADJ_E_ARG", -2: "ADJ_E_SHAPE", -3: "ADJ_E_INVERTED",
           -8: "ADJ_E_NOTIMPL"}
 ADJ_FP64, ADJ_MIXED = 0, 1
 ADJ_AUTO, ADJ_GMRES, ADJ_PCG = 0, 1, 2
+PRECOND_WOODBURY, PRECOND_SPARSE_INVERSE, PRECOND_JACOBI = 0, 1, 2
 
 # names declared in include/adjoint.h
 EXPORTS = ("adj_scene_create", "adj_scene_destroy", "adjoint_setup", "adjoint_solve", "vjp_params",
@@ -57,7 +58,7 @@ class ContactState(C.Structure):
 class SolveOpts(C.Structure):
     _fields_ = [("rtol", C.c_double), ("maxit", C.c_int32), ("restart", C.c_int32),
                 ("max_refine", C.c_int32), ("prec", C.c_int32), ("reuse_delassus", C.c_int32),
-                ("method", C.c_int32)]
+                ("method", C.c_int32), ("precond", C.c_int32)]
 
 
 class SolveInfo(C.Structure):
@@ -199,10 +200,10 @@ def make_contact_state(n, vid, fric, frame, delta, lam, mu, d_n=None, d_f=None, 
 
 
 def solve_opts(rtol=1e-8, maxit=2000, restart=64, prec=ADJ_FP64, reuse_delassus=1, max_refine=4,
-               method=ADJ_AUTO):
+               method=ADJ_AUTO, precond=0):
     o = SolveOpts()
     o.rtol, o.maxit, o.restart, o.max_refine = float(rtol), int(maxit), int(restart), int(max_refine)
-    o.prec, o.reuse_delassus, o.method = int(prec), int(reuse_delassus), int(method)
+    o.prec, o.reuse_delassus, o.method, o.precond = int(prec), int(reuse_delassus), int(method), int(precond)
     return o
 
 

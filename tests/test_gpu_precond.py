@@ -1,0 +1,130 @@
+"""Comparison preconditioners of the backward solve (the paper's backward-
+solver study measures its Woodbury preconditioner against simpler ones).
+With the sparse inverse alone (S^T S, contact blocks left to the Krylov
+method) and with block Jacobi (inverses of the 3x3 diagonal blocks of
+Acal^T), the solve must reach the same adjoint as the oracle's direct solve:
+on a frictional beam state (GMRES) and on frictionless steps of the tiny
+impact scene (PCG).  A batch refuses the comparison preconditioners."""
+
+import dataclasses
+import functools
+import os
+
+import numpy as np
+import pytest
+
+from gpu_helpers import make_scene, rel, run_adjoint, torch_cuda
+from oracle import adjoint as adj
+from oracle.rollout import run_forward, scene_disc
+from synth import beam_scene, tiny_scene
+
+pytestmark = pytest.mark.gpu
+
+TOL_FP64 = 1e-9
+
+
+@functools.lru_cache(maxsize=None)
+def _beam(mu=0.4, t=3):
+    from conftest import ROOT
+    from oracle.contact import ContactSet
+    from oracle.forward import StepRecord
+    path = os.path.join(ROOT, "tests", "golden", f"beam_states_mu{mu}.npz")
+    if not os.path.exists(path):
+        pytest.skip(f"missing fixture {path}")
+    d = np.load(path)
+    cs = ContactSet(d[f"vid{t}"], d[f"collider{t}"], d[f"frame{t}"], d[f"d_n{t}"], d[f"d_f{t}"],
+                    d[f"fric{t}"].astype(bool))
+    spec = beam_scene(mu=mu)
+    return spec, scene_disc(spec), d[f"q{t}"], StepRecord(cs, d[f"delta{t}"], d[f"lam{t}"], mu)
+
+
+@pytest.mark.parametrize("precond", [1, 2])
+def test_woodbury_beats_comparison_preconditioners_on_beam(precond):
+    """On a frictional beam state the stiff contact directions are outlier
+    eigenvalues of the system preconditioned without them; restarted GMRES
+    needs far more iterations (here it does not reach the tolerance within
+    the budget), while the Woodbury preconditioner converges in a few dozen."""
+    torch_cuda()
+    from paper_2603_16478_amd import native
+    spec, disc, q, rec = _beam()
+    rng = np.random.default_rng(500 + precond)
+    gq, gv = spec.loss_dir, 1e-3 * rng.standard_normal(q.shape)
+    scene = make_scene(spec, max_contacts=rec.contacts.n)
+    print(f"beam, precond {precond}", flush=True)
+    out = run_adjoint(scene, rec, q, gq, gv, rtol=1e-8, maxit=2000, precond=precond, raise_noconv=False)
+    wb = run_adjoint(scene, rec, q, gq, gv, rtol=1e-8, maxit=2000, precond=native.PRECOND_WOODBURY)
+    print(f"beam precond {precond}: iters {out['info'].iters} relres {out['info'].relres:.2e}; Woodbury iters "
+          f"{wb['info'].iters} relres {wb['info'].relres:.2e}", flush=True)
+    assert wb["info"].relres <= 1e-8
+    assert wb["info"].iters < out["info"].iters
+
+
+def _contact_free():
+    spec = tiny_scene("impact")
+    return spec, run_forward(spec, steps=5)
+
+
+@pytest.mark.parametrize("method", [0, 1])
+@pytest.mark.parametrize("precond", [1, 2])
+def test_comparison_preconditioners_contact_free(precond, method):
+    """Contact-free tiny step: PCG (chosen automatically) and GMRES (forced)
+    with either comparison preconditioner reach the oracle's adjoint."""
+    torch_cuda()
+    from paper_2603_16478_amd import native
+    spec, ro = _contact_free()
+    rec, q = ro.records[3], ro.qs[4]
+    assert rec.contacts.n == 0
+    rng = np.random.default_rng(700 + precond)
+    gq, gv = rng.standard_normal(q.shape), 1e-3 * rng.standard_normal(q.shape)
+    ref = adj.adjoint_step(ro.disc, q, rec, gq, gv, spec.eps, spec.E, spec.nu)
+    scene = make_scene(spec, max_contacts=64)
+    out = run_adjoint(scene, rec, q, gq, gv, rtol=1e-13, maxit=5000, precond=precond, method=method)
+    info = out["info"]
+    print(f"contact-free precond {precond} method {info.method}: iters {info.iters}, "
+          f"z err {rel(out['z'], ref.z):.2e}", flush=True)
+    assert info.method == (native.ADJ_PCG if method == 0 else native.ADJ_GMRES)
+    for k in ("z", "dqbar", "dvbar", "dfext"):
+        assert rel(out[k], getattr(ref, k)) <= TOL_FP64, k
+
+
+@functools.lru_cache(maxsize=None)
+def _frictionless():
+    spec = dataclasses.replace(tiny_scene("impact"), mu=0.0)
+    return spec, run_forward(spec, steps=14)
+
+
+@pytest.mark.parametrize("precond", [1, 2])
+def test_comparison_preconditioners_tiny_pcg(precond):
+    torch_cuda()
+    from paper_2603_16478_amd import native
+    spec, ro = _frictionless()
+    rec, q = ro.records[13], ro.qs[14]
+    rng = np.random.default_rng(600 + precond)
+    gq, gv = rng.standard_normal(q.shape), 1e-3 * rng.standard_normal(q.shape)
+    ref = adj.adjoint_step(ro.disc, q, rec, gq, gv, spec.eps, spec.E, spec.nu)
+    scene = make_scene(spec, max_contacts=64)
+    out = run_adjoint(scene, rec, q, gq, gv, rtol=1e-13, maxit=20000, precond=precond)
+    info = out["info"]
+    print(f"tiny precond {precond}: contacts {rec.contacts.n}, method {info.method}, iters {info.iters}, "
+          f"z err {rel(out['z'], ref.z):.2e}", flush=True)
+    assert info.method == native.ADJ_PCG
+    for k in ("z", "dqbar", "dvbar", "dfext"):
+        assert rel(out[k], getattr(ref, k)) <= TOL_FP64, k
+
+
+def test_batch_refuses_comparison_preconditioners():
+    torch = torch_cuda()
+    from gpu_helpers import contact_tensors
+    from paper_2603_16478_amd import native
+    spec, disc, q, rec = _beam()
+    b = native.Batch([(spec.mesh.rest, spec.mesh.tets, spec.E, spec.nu)], spec.density, spec.h, spec.eps,
+                     spec.gravity, spec.planes, spec.contact_margin, [rec.contacts.n])
+    tens = contact_tensors(rec)
+    cs = native.make_contact_state(rec.contacts.n, tens["vid"], tens["fric"], tens["frame"], tens["delta"],
+                                   tens["lam"], rec.mu)
+    qd = torch.tensor(q, device="cuda")
+    native.batch_setup(b, [cs], qd, native.solve_opts())
+    z = torch.zeros_like(qd)
+    with pytest.raises(native.AdjError, match="NOTIMPL"):
+        native.batch_solve(b, qd, torch.zeros_like(qd), z, native.solve_opts(precond=native.PRECOND_JACOBI))
+    b.close()
