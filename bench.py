@@ -397,8 +397,8 @@ def main():
     # ---- backward-solver comparison: the same solves with the comparison
     # preconditioners (sparse inverse S^T S alone, block Jacobi), 2000
     # iterations at most; the setup skips the Woodbury factors for them ----
-    def run_precond(pc, nsteps):
-        o = native.solve_opts(rtol=args.rtol, maxit=2000, restart=64, precond=pc)
+    def run_precond(pc, nsteps, method=native.ADJ_AUTO):
+        o = native.solve_opts(rtol=args.rtol, maxit=2000, restart=64, precond=pc, method=method)
         its, conv, worst = [], 0, 0.0
         for i in range(2):  # warm-up
             t = dstates[i % len(dstates)]
@@ -422,7 +422,9 @@ def main():
     n_pc = min(args.steps, len(dstates))
     precond_cmp = {"woodbury": run_precond(native.PRECOND_WOODBURY, n_pc),
                    "sparse_inverse_only": run_precond(native.PRECOND_SPARSE_INVERSE, n_pc),
-                   "block_jacobi": run_precond(native.PRECOND_JACOBI, n_pc)}
+                   "block_jacobi": run_precond(native.PRECOND_JACOBI, n_pc),
+                   "point_jacobi": run_precond(native.PRECOND_POINT_JACOBI, n_pc),
+                   "semi_implicit": run_precond(native.PRECOND_SPARSE_INVERSE, n_pc, native.ADJ_SEMI_IMPLICIT)}
 
     abytes = s_product_bytes(uinfo)
     avg_ms = kms / max(launches, 1)
@@ -505,7 +507,9 @@ def main():
         "single_scene": {"fp64": single, "mixed": single_mixed,
                          "batched_speedup_fp64": bfp64["value"] / single["value"]},
         "preconditioners": precond_cmp | {"note": "single scene, FP64, one solve per recorded scene-step, "
-                                                  "GMRES(64) to 1e-8 or 2000 iterations"},
+                                                  "GMRES(64) to 1e-8 or 2000 iterations; semi_implicit: the "
+                                                  "fixed-point iteration x <- x + A^-1 (b - Acal^T x), stopped "
+                                                  "when its residual exceeds 1e6 |b|"},
         "large_batch": big,
     }
     if not args.no_cpu_baseline:

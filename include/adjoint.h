@@ -96,17 +96,28 @@ typedef struct {
  * ADJ_AUTO picks PCG when no contact is frictional or mu = 0 (then every
  * contact block, hence Acal^T and the Woodbury preconditioner, is symmetric),
  * GMRES otherwise; ADJ_PCG on a non-symmetric system is ADJ_E_ARG. */
-typedef enum { ADJ_AUTO = 0, ADJ_GMRES = 1, ADJ_PCG = 2 } adj_krylov;
+/* ADJ_SEMI_IMPLICIT (single-scene FP64 solves): the fixed-point iteration
+ * x <- x + A^{-1} (b - Acal^T x) of the semi-implicit baselines the paper
+ * compares against (Sec. 6.2); it converges only while the spectral radius
+ * of I - A^{-1} Acal^T stays below one and is reported as ADJ_E_NOCONV
+ * (outputs: the last iterate) when it does not reach the tolerance or
+ * grows past 1e6 |b|. */
+typedef enum { ADJ_AUTO = 0, ADJ_GMRES = 1, ADJ_PCG = 2, ADJ_SEMI_IMPLICIT = 3 } adj_krylov;
 
 /* Preconditioner of the Krylov solve (single-scene calls; batches use the
  * Woodbury one).  ADJ_PRECOND_WOODBURY: A^{-1} = S^T S with the contact
  * blocks through the Woodbury identity (Sec. 5.4, the paper's choice);
  * ADJ_PRECOND_SPARSE_INVERSE: S^T S alone (the contact blocks are left to
  * the Krylov method); ADJ_PRECOND_JACOBI: the inverses of the 3x3 diagonal
- * blocks of Acal^T.  The latter two are the comparison preconditioners the
- * paper's backward-solver study measures against; all three give the same
- * solution to the tolerance. */
-typedef enum { ADJ_PRECOND_WOODBURY = 0, ADJ_PRECOND_SPARSE_INVERSE = 1, ADJ_PRECOND_JACOBI = 2 } adj_precond;
+ * blocks of Acal^T; ADJ_PRECOND_POINT_JACOBI: the inverse of its diagonal.
+ * These are the comparison preconditioners of the paper's backward-solver
+ * study (Sec. 6.2); all give the same solution to the tolerance. */
+typedef enum {
+  ADJ_PRECOND_WOODBURY = 0,
+  ADJ_PRECOND_SPARSE_INVERSE = 1,
+  ADJ_PRECOND_JACOBI = 2,
+  ADJ_PRECOND_POINT_JACOBI = 3
+} adj_precond;
 
 typedef struct {
   double rtol;          /* relative residual |b - Acal^T z| / |b| (Sec. 6.1: 1e-8) */

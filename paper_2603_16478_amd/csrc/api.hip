@@ -48,9 +48,9 @@ void launch_gj_step(hipStream_t, int, int, const double*, double*, int*);
 void launch_spmv_csr3(hipStream_t, int, const long long*, const int*, const double*, const double*,
                       long long, const double*, const GmresState*, double*);
 void launch_block_jacobi(hipStream_t, int, const int*, const double*, const double*, long long, const double*,
-                         const GmresState*, double*);
+                         const GmresState*, int, double*);
 void launch_block_jacobi(hipStream_t, int, const int*, const float*, const double*, long long, const double*,
-                         const GmresState*, double*);
+                         const GmresState*, int, double*);
 void launch_spmv_tasks(hipStream_t, int, const int4*, const long long*, const int*, const double*,
                        const double*, long long, const double*, const GmresState*, double*);
 void launch_spmv_tasks(hipStream_t, int, const int4*, const long long*, const int*, const float*,
@@ -636,11 +636,12 @@ extern "C" adj_status adj_check_status(adj_scene* s, void* stream) {
 static void apply_precond(adj_scene* s, hipStream_t st, const double* x, long long stride,
                           const double* scale, const GmresState* state, double* out, bool f32 = false) {
   const double h2 = s->hs.h * s->hs.h;
-  if (s->precond == ADJ_PRECOND_JACOBI) {
+  if (s->precond == ADJ_PRECOND_JACOBI || s->precond == ADJ_PRECOND_POINT_JACOBI) {
+    const int point = s->precond == ADJ_PRECOND_POINT_JACOBI ? 1 : 0;
     if (f32)
-      launch_block_jacobi(st, s->nv, s->d_diag_slot, s->d_val32, x, stride, scale, state, out);
+      launch_block_jacobi(st, s->nv, s->d_diag_slot, s->d_val32, x, stride, scale, state, point, out);
     else
-      launch_block_jacobi(st, s->nv, s->d_diag_slot, s->d_val, x, stride, scale, state, out);
+      launch_block_jacobi(st, s->nv, s->d_diag_slot, s->d_val, x, stride, scale, state, point, out);
     return;
   }
   const bool woodbury = s->nc > 0 && s->precond == ADJ_PRECOND_WOODBURY;
@@ -898,6 +899,49 @@ static adj_status pcg_solve(adj_scene* s, hipStream_t st, const double* b, doubl
   return ADJ_OK;
 }
 
+// Semi-implicit fixed-point iteration x <- x + A^{-1} (b - Acal^T x)
+// (A^{-1} = S^T S), FP64; the residual is checked every 16 sweeps; stops at
+// the tolerance, at maxit, or when the residual exceeds 1e6 |b| (diverged).
+static adj_status semi_implicit_solve(adj_scene* s, hipStream_t st, const double* b, double* x, double rtol,
+                                      int maxit, int* iters, double* relres, bool* conv) {
+  const long long n3 = s->n3;
+  launch_fill_zero(st, (size_t)n3, x);
+  auto residual = [&]() {  // d_r = b - Acal^T x
+    bsr(s, st, x, s->d_r, 0, nullptr, false);
+    launch_axpy(st, n3, -1.0, b, s->d_r);
+    launch_scale_vec(st, n3, s->d_r, -1.0, s->d_r);
+  };
+  double nb[2];
+  launch_norms(st, n3, b, s->P3(), s->d_norms);
+  HIPCHK(hipMemcpyAsync(nb, s->d_norms, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  const double bnorm = std::sqrt(nb[0]);
+  double rn = bnorm;
+  int it = 0;
+  while (it < maxit && rn > rtol * bnorm) {
+    const int chunk = std::min(16, maxit - it);
+    for (int k = 0; k < chunk; ++k) {
+      residual();
+      launch_spmv_tasks(st, s->nS_tasks, (const int4*)s->d_Stasks, s->d_Sp, s->d_Sj, s->d_Sx, s->d_r, 0, nullptr,
+                        nullptr, s->d_t1);
+      launch_spmv_tasks(st, s->nST_tasks, (const int4*)s->d_STtasks, s->d_STp, s->d_STj, s->d_STx, s->d_t1, 0,
+                        nullptr, nullptr, s->d_dz);
+      launch_axpy(st, n3, 1.0, s->d_dz, x);
+    }
+    it += chunk;
+    residual();
+    launch_norms(st, n3, s->d_r, s->P3(), s->d_norms);
+    HIPCHK(hipMemcpyAsync(nb, s->d_norms, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    rn = std::sqrt(nb[0]);
+    if (!std::isfinite(rn) || rn > 1e6 * bnorm) break;  // diverged
+  }
+  *iters = it;
+  *relres = bnorm > 0 ? rn / bnorm : 0.0;
+  *conv = rn <= rtol * bnorm;
+  return ADJ_OK;
+}
+
 static adj_status krylov_solve(adj_scene* s, hipStream_t st, bool use_pcg, const double* b, double* x,
                                double rtol, int maxit, int R, int* iters, double* relres, bool* conv, bool f32) {
   if (use_pcg) return pcg_solve(s, st, b, x, rtol, maxit, iters, relres, conv, f32);
@@ -911,10 +955,13 @@ extern "C" adj_status adjoint_solve(adj_scene* s, const double* dL_dq, const dou
   if (!(opts->rtol > 0) || opts->maxit <= 0 || opts->restart < 1 || opts->restart > kMaxRestart)
     return fail(ADJ_E_ARG, "invalid solve options");
   if (opts->prec != ADJ_FP64 && opts->prec != ADJ_MIXED) return fail(ADJ_E_ARG, "unknown precision");
-  if (opts->method != ADJ_AUTO && opts->method != ADJ_GMRES && opts->method != ADJ_PCG)
+  if (opts->method != ADJ_AUTO && opts->method != ADJ_GMRES && opts->method != ADJ_PCG &&
+      opts->method != ADJ_SEMI_IMPLICIT)
     return fail(ADJ_E_ARG, "unknown Krylov method");
+  if (opts->method == ADJ_SEMI_IMPLICIT && opts->prec != ADJ_FP64)
+    return fail(ADJ_E_NOTIMPL, "the semi-implicit iteration runs in FP64");
   if (opts->precond != ADJ_PRECOND_WOODBURY && opts->precond != ADJ_PRECOND_SPARSE_INVERSE &&
-      opts->precond != ADJ_PRECOND_JACOBI)
+      opts->precond != ADJ_PRECOND_JACOBI && opts->precond != ADJ_PRECOND_POINT_JACOBI)
     return fail(ADJ_E_ARG, "unknown preconditioner");
   if (opts->precond == ADJ_PRECOND_WOODBURY && s->nc > 0 && !s->woodbury_ready)
     return fail(ADJ_E_ARG, "the last adjoint_setup skipped the Woodbury factors (it ran with another precond)");
@@ -936,7 +983,10 @@ extern "C" adj_status adjoint_solve(adj_scene* s, const double* dL_dq, const dou
   double relres = 0.0;
   bool converged = false;
   adj_status a;
-  if (opts->prec == ADJ_FP64) {
+  if (opts->method == ADJ_SEMI_IMPLICIT) {
+    a = semi_implicit_solve(s, st, s->d_rhs, z, opts->rtol, opts->maxit, &total, &relres, &converged);
+    if (a != ADJ_OK) return a;
+  } else if (opts->prec == ADJ_FP64) {
     a = krylov_solve(s, st, use_pcg, s->d_rhs, z, opts->rtol, opts->maxit, opts->restart, &total, &relres,
                      &converged, false);
     if (a != ADJ_OK) return a;
@@ -982,7 +1032,7 @@ extern "C" adj_status adjoint_solve(adj_scene* s, const double* dL_dq, const dou
     info->m_rows = s->m;
     info->relres = relres;
     info->delassus_rebuilt = s->delassus_rebuilt;
-    info->method = use_pcg ? ADJ_PCG : ADJ_GMRES;
+    info->method = opts->method == ADJ_SEMI_IMPLICIT ? ADJ_SEMI_IMPLICIT : (use_pcg ? ADJ_PCG : ADJ_GMRES);
   }
   if (!converged) return fail(ADJ_E_NOCONV, "Krylov solve did not reach rtol");
   return ADJ_OK;

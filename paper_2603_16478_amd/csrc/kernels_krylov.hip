@@ -113,13 +113,14 @@ __global__ void __launch_bounds__(256) k_spmv_tasks(const int4* __restrict__ tas
 // Block-Jacobi preconditioner: y_v = B_v^{-1} x_v with B_v the 3x3
 // diagonal block of the assembled matrix (row v's block at slot
 // diag_slot[v], row-major), inverted per apply by the adjugate (B_v is the
-// mass block plus stiffness and contact terms, far from singular).  The
+// mass block plus stiffness and contact terms, far from singular); with
+// `point` set, only the block's diagonal is inverted (point Jacobi).  The
 // input vector follows the same lazily scaled basis convention as the
 // sparse-inverse product.
 template <class MT>
 __global__ void k_block_jacobi(int nv, const int* __restrict__ diag_slot, const MT* __restrict__ val,
                                const double* __restrict__ xbase, long long stride, const double* __restrict__ scale,
-                               const GmresState* __restrict__ st, int use_j, double* __restrict__ y) {
+                               const GmresState* __restrict__ st, int use_j, int point, double* __restrict__ y) {
   if (gm_inactive(st)) return;
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= nv) return;
@@ -130,6 +131,12 @@ __global__ void k_block_jacobi(int nv, const int* __restrict__ diag_slot, const 
     sc = scale[st->j];
   }
   const MT* b = val + 9LL * diag_slot[v];
+  if (point) {
+    y[3 * v] = sc * x[3 * v] / (double)b[0];
+    y[3 * v + 1] = sc * x[3 * v + 1] / (double)b[4];
+    y[3 * v + 2] = sc * x[3 * v + 2] / (double)b[8];
+    return;
+  }
   const double a00 = b[0], a01 = b[1], a02 = b[2], a10 = b[3], a11 = b[4], a12 = b[5], a20 = b[6], a21 = b[7],
                a22 = b[8];
   const double c00 = a11 * a22 - a12 * a21, c01 = a02 * a21 - a01 * a22, c02 = a01 * a12 - a02 * a11;
@@ -589,14 +596,16 @@ void launch_spmv_tasks(hipStream_t s, int ntasks, const int4* tasks, const long 
 }
 
 void launch_block_jacobi(hipStream_t s, int nv, const int* diag_slot, const double* val, const double* x,
-                         long long stride, const double* scale, const GmresState* st, double* y) {
+                         long long stride, const double* scale, const GmresState* st, int point, double* y) {
   const int use_j = (st != nullptr && scale != nullptr) ? 1 : 0;
-  k_block_jacobi<double><<<(nv + 255) / 256, 256, 0, s>>>(nv, diag_slot, val, x, stride, scale, st, use_j, y);
+  k_block_jacobi<double><<<(nv + 255) / 256, 256, 0, s>>>(nv, diag_slot, val, x, stride, scale, st, use_j, point,
+                                                          y);
 }
 void launch_block_jacobi(hipStream_t s, int nv, const int* diag_slot, const float* val, const double* x,
-                         long long stride, const double* scale, const GmresState* st, double* y) {
+                         long long stride, const double* scale, const GmresState* st, int point, double* y) {
   const int use_j = (st != nullptr && scale != nullptr) ? 1 : 0;
-  k_block_jacobi<float><<<(nv + 255) / 256, 256, 0, s>>>(nv, diag_slot, val, x, stride, scale, st, use_j, y);
+  k_block_jacobi<float><<<(nv + 255) / 256, 256, 0, s>>>(nv, diag_slot, val, x, stride, scale, st, use_j, point,
+                                                         y);
 }
 template <class MT>
 static void wb_gather_impl(hipStream_t s, int m, int mp, const int* row_c, const int* row_i, const int* vid,

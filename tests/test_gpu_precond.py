@@ -1,10 +1,12 @@
-"""Comparison preconditioners of the backward solve (the paper's backward-
-solver study measures its Woodbury preconditioner against simpler ones).
-With the sparse inverse alone (S^T S, contact blocks left to the Krylov
-method) and with block Jacobi (inverses of the 3x3 diagonal blocks of
-Acal^T), the solve must reach the same adjoint as the oracle's direct solve:
-on a frictional beam state (GMRES) and on frictionless steps of the tiny
-impact scene (PCG).  A batch refuses the comparison preconditioners."""
+"""The backward-solver comparison of Sec. 6.2: the Krylov solve with the
+sparse inverse alone (S^T S, contact blocks left to the Krylov method), block
+Jacobi (3x3 diagonal blocks of Acal^T) or point Jacobi as the
+preconditioner must reach the oracle's adjoint on contact-free (PCG and
+GMRES) and frictionless (PCG) steps of the tiny impact scene; on a
+frictional beam state the Woodbury preconditioner needs the fewest
+iterations.  The semi-implicit fixed-point iteration converges to the
+oracle's adjoint without contact and diverges with frictional contact.  A
+batch refuses the comparison preconditioners."""
 
 import dataclasses
 import functools
@@ -38,12 +40,12 @@ def _beam(mu=0.4, t=3):
     return spec, scene_disc(spec), d[f"q{t}"], StepRecord(cs, d[f"delta{t}"], d[f"lam{t}"], mu)
 
 
-@pytest.mark.parametrize("precond", [1, 2])
+@pytest.mark.parametrize("precond", [1, 2, 3])
 def test_woodbury_beats_comparison_preconditioners_on_beam(precond):
-    """On a frictional beam state the stiff contact directions are outlier
-    eigenvalues of the system preconditioned without them; restarted GMRES
-    needs far more iterations (here it does not reach the tolerance within
-    the budget), while the Woodbury preconditioner converges in a few dozen."""
+    """Frictional beam state: the Woodbury preconditioner needs fewer GMRES
+    iterations than each comparison preconditioner (with the sparse inverse
+    alone the stiff contact directions are outlier eigenvalues and GMRES(64)
+    stalls within the budget)."""
     torch_cuda()
     from paper_2603_16478_amd import native
     spec, disc, q, rec = _beam()
@@ -65,7 +67,7 @@ def _contact_free():
 
 
 @pytest.mark.parametrize("method", [0, 1])
-@pytest.mark.parametrize("precond", [1, 2])
+@pytest.mark.parametrize("precond", [1, 2, 3])
 def test_comparison_preconditioners_contact_free(precond, method):
     """Contact-free tiny step: PCG (chosen automatically) and GMRES (forced)
     with either comparison preconditioner reach the oracle's adjoint."""
@@ -93,7 +95,7 @@ def _frictionless():
     return spec, run_forward(spec, steps=14)
 
 
-@pytest.mark.parametrize("precond", [1, 2])
+@pytest.mark.parametrize("precond", [1, 2, 3])
 def test_comparison_preconditioners_tiny_pcg(precond):
     torch_cuda()
     from paper_2603_16478_amd import native
@@ -110,6 +112,37 @@ def test_comparison_preconditioners_tiny_pcg(precond):
     assert info.method == native.ADJ_PCG
     for k in ("z", "dqbar", "dvbar", "dfext"):
         assert rel(out[k], getattr(ref, k)) <= TOL_FP64, k
+
+
+def test_semi_implicit_contact_free_matches_oracle():
+    torch_cuda()
+    from paper_2603_16478_amd import native
+    spec, ro = _contact_free()
+    rec, q = ro.records[3], ro.qs[4]
+    rng = np.random.default_rng(800)
+    gq, gv = rng.standard_normal(q.shape), 1e-3 * rng.standard_normal(q.shape)
+    ref = adj.adjoint_step(ro.disc, q, rec, gq, gv, spec.eps, spec.E, spec.nu)
+    scene = make_scene(spec, max_contacts=64)
+    out = run_adjoint(scene, rec, q, gq, gv, rtol=1e-13, maxit=5000, precond=native.PRECOND_SPARSE_INVERSE,
+                      method=native.ADJ_SEMI_IMPLICIT)
+    info = out["info"]
+    print(f"semi-implicit contact-free: iters {info.iters}, relres {info.relres:.2e}, "
+          f"z err {rel(out['z'], ref.z):.2e}", flush=True)
+    assert info.method == native.ADJ_SEMI_IMPLICIT
+    for k in ("z", "dqbar", "dvbar", "dfext"):
+        assert rel(out[k], getattr(ref, k)) <= TOL_FP64, k
+
+
+def test_semi_implicit_diverges_with_frictional_contact():
+    torch_cuda()
+    from paper_2603_16478_amd import native
+    spec, disc, q, rec = _beam()
+    scene = make_scene(spec, max_contacts=rec.contacts.n)
+    out = run_adjoint(scene, rec, q, spec.loss_dir, np.zeros_like(q), rtol=1e-8, maxit=2000,
+                      precond=native.PRECOND_SPARSE_INVERSE, method=native.ADJ_SEMI_IMPLICIT, raise_noconv=False)
+    info = out["info"]
+    print(f"semi-implicit beam: iters {info.iters}, relres {info.relres:.2e}", flush=True)
+    assert info.relres > 1.0
 
 
 def test_batch_refuses_comparison_preconditioners():
