@@ -12,6 +12,9 @@ infrastructure only.
                 w_i = 2 mu_i V_i so the per-volume formulas gain V_i)
     dL/dE, dL/dnu by the chain rule through mu = E/(2(1+nu)),
                 lam = E nu/((1+nu)(1-2nu)).
+    Bindings (eq:binding; eq:differential_2 rhs_d_b and rhs_E_b), with
+    lambda_b = -(q_b - d_b) / E_b:
+    dL/dd_b = h^2 E_b^{-1} z_b,   dL/dE_b = -h^2 E_b^{-1} lambda_b . z_b
 
 The solve is a direct sparse LU of Acal^T (the plain definition of z) followed
 by iterative refinement whose residual is formed in extended precision
@@ -81,6 +84,8 @@ class StepGradients:
     dlam_tet: np.ndarray
     dE_tet: np.ndarray
     dnu_tet: np.ndarray
+    dtarget: np.ndarray | None = None  # (n_b, 3) dL/dd_b
+    dE_bind: np.ndarray | None = None  # (n_b,) dL/dE_b
 
     @property
     def dE(self) -> float:
@@ -133,7 +138,15 @@ def vjp(disc: Discretisation, sysm: AdjointSystem, q: np.ndarray, record: StepRe
     E = np.broadcast_to(np.asarray(E, float), V.shape)
     nu = np.broadcast_to(np.asarray(nu, float), V.shape)
     dE_tet, dnu_tet = lame_chain(dmu_tet, dlam_tet, E, nu)
-    return StepGradients(z3.copy(), dqbar, dvbar, dfext, dmu_fric, dmu_tet, dlam_tet, dE_tet, dnu_tet)
+    dtarget = dE_bind = None
+    b = disc.bindings
+    if b is not None and len(b.vid):
+        zb = z3[b.vid]
+        lam_b = -(q.reshape(n_v, 3)[b.vid] - record.targets) / b.E[:, None]
+        dtarget = h * h * zb / b.E[:, None]
+        dE_bind = -h * h * np.einsum("bk,bk->b", lam_b, zb) / b.E
+    return StepGradients(z3.copy(), dqbar, dvbar, dfext, dmu_fric, dmu_tet, dlam_tet, dE_tet, dnu_tet,
+                         dtarget, dE_bind)
 
 
 def adjoint_step(disc: Discretisation, q, record: StepRecord, dL_dq, dL_dv, eps, E, nu,

@@ -69,6 +69,23 @@ def global_G(n_verts: int, tets: np.ndarray, Bt: np.ndarray) -> sp.csr_matrix:
 
 
 @dataclasses.dataclass
+class Bindings:
+    """Bilateral bindings (Sec. 3.2, eq:binding): vertex vid[b] is held to a
+    target d_b (given per step) by a linear spring of compliance E[b]:
+    phi_b = (q_vid - d_b) + E_b lambda_b = 0, so the binding force on the
+    vertex is lambda_b = -(q_vid - d_b) / E_b."""
+    vid: np.ndarray  # (n_b,) int, distinct vertices
+    E: np.ndarray  # (n_b,) > 0
+
+    def matrix(self, n_verts: int, h: float) -> sp.csr_matrix:
+        """h^2 J_b^T E_b^{-1} J_b (the binding term of the system matrix)."""
+        d = np.zeros(3 * n_verts)
+        for v, e in zip(self.vid, self.E):
+            d[3 * v:3 * v + 3] += h * h / e
+        return sp.diags(d).tocsr()
+
+
+@dataclasses.dataclass
 class Discretisation:
     n_verts: int
     tets: np.ndarray
@@ -81,14 +98,15 @@ class Discretisation:
     lam: np.ndarray  # per tet
     w: np.ndarray  # per tet, 2 mu V
     h: float
-    A: sp.csr_matrix  # (3 n_v, 3 n_v)
+    A: sp.csr_matrix  # (3 n_v, 3 n_v), binding term included
+    bindings: Bindings | None = None
 
     @property
     def M(self) -> sp.dia_matrix:
         return sp.diags(np.repeat(self.mass, 3))
 
 
-def discretise(rest, tets, density, E, nu, h) -> Discretisation:
+def discretise(rest, tets, density, E, nu, h, bindings: Bindings | None = None) -> Discretisation:
     n_v = rest.shape[0]
     Bm, vol, Bt = rest_operators(rest, tets)
     mass = lumped_mass(n_v, tets, vol, density)
@@ -99,4 +117,6 @@ def discretise(rest, tets, density, E, nu, h) -> Discretisation:
     w = 2.0 * mu * vol
     Wd = sp.diags(np.repeat(w, 9))
     A = (sp.diags(np.repeat(mass, 3)) + h * h * (G.T @ Wd @ G)).tocsr()
-    return Discretisation(n_v, tets, Bm, vol, Bt, mass, G, mu.copy(), lam.copy(), w, h, A)
+    if bindings is not None and len(bindings.vid):
+        A = (A + bindings.matrix(n_v, h)).tocsr()
+    return Discretisation(n_v, tets, Bm, vol, Bt, mass, G, mu.copy(), lam.copy(), w, h, A, bindings)

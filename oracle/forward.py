@@ -57,6 +57,7 @@ class StepRecord:
     mu: float
     newton_iters: int = 0
     residual: float = 0.0
+    targets: np.ndarray | None = None  # (n_b, 3) binding targets d_b of the step
 
 
 def elastic_force_terms(disc: Discretisation, q: np.ndarray):
@@ -81,13 +82,18 @@ def _contact_state(cs, u, g0, lam_n, s):
     return delta, x, dhat, lam
 
 
-def _residuals(disc, u, utilde, cs, qbar, g0, lam_n, s, mu, eps, k):
+def _residuals(disc, u, utilde, cs, qbar, g0, lam_n, s, mu, eps, k, targets=None):
     """Rows at the step displacement u = q - qbar (utilde = qtilde - qbar)."""
     h = disc.h
     rec, Gq = elastic_force_terms(disc, qbar + u)
     Pv = vec(rec.P).reshape(-1)
     wv = np.repeat(disc.w, 9)
     r = np.repeat(disc.mass, 3) * (u - utilde).reshape(-1) + h * h * (disc.G.T @ (wv * (Gq - Pv)))
+    b = disc.bindings
+    if b is not None and len(b.vid):
+        # -h^2 J_b^T lambda_b with lambda_b = -(q_b - d_b) / E_b (eq:binding)
+        qb = (qbar + u)[b.vid]
+        np.add.at(r.reshape(-1, 3), b.vid, h * h * (qb - targets) / b.E[:, None])
     delta, x, dhat, lam = _contact_state(cs, u, g0, lam_n, s)
     if cs.n:
         fw = np.einsum("cki,ck->ci", cs.frame, lam)  # world-frame contact force per contact
@@ -103,7 +109,8 @@ def _merit(r, phin, phif, h):
 
 
 def elastic_tangent(disc: Discretisation, rec: ProjectionRecord) -> sp.csr_matrix:
-    """A - dA = M + h^2 sum_i w_i G_i^T (I - J_i) G_i (Sec. 5.4 contact-free)."""
+    """A - dA = M + h^2 sum_i w_i G_i^T (I - J_i) G_i (Sec. 5.4 contact-free),
+    plus h^2 J_b^T E_b^{-1} J_b when the scene has bindings (eq:differential_2)."""
     h = disc.h
     n_t = disc.tets.shape[0]
     J = rec.jacobian()  # (n_t, 9, 9)
@@ -112,7 +119,10 @@ def elastic_tangent(disc: Discretisation, rec: ProjectionRecord) -> sp.csr_matri
     rows = (9 * np.arange(n_t))[:, None, None] + np.arange(9)[None, :, None] + 0 * np.arange(9)[None, None, :]
     cols = (9 * np.arange(n_t))[:, None, None] + 0 * np.arange(9)[None, :, None] + np.arange(9)[None, None, :]
     Bd = sp.csr_matrix((IJ.reshape(-1), (rows.reshape(-1), cols.reshape(-1))), shape=(9 * n_t, 9 * n_t))
-    return (disc.M + h * h * (disc.G.T @ Bd @ disc.G)).tocsr()
+    T = disc.M + h * h * (disc.G.T @ Bd @ disc.G)
+    if disc.bindings is not None and len(disc.bindings.vid):
+        T = T + disc.bindings.matrix(disc.n_verts, h)
+    return T.tocsr()
 
 
 def contact_matrix(n_verts: int, cs: ct.ContactSet, K: np.ndarray, h: float) -> sp.csr_matrix:
@@ -150,13 +160,13 @@ def _newton_K(cs, delta, x, dhat, lam_n, s, mu, eps, k):
     return a, b, beta_n, beta_f, R, K
 
 
-def _newton(disc, utilde, qbar, g0, cs, q, lam_n, s, mu, eps, k, maxit, tol_force, tol_phi):
+def _newton(disc, utilde, qbar, g0, cs, q, lam_n, s, mu, eps, k, maxit, tol_force, tol_phi, targets=None):
     """Damped Newton on (q, lambda_n, s) for the rows smoothed with eps (per
     contact, eps may be an array).  Returns (q, lam_n, s, state, iters, ok)."""
     h = disc.h
     n_v = disc.n_verts
     nc = cs.n
-    state = _residuals(disc, q, utilde, cs, qbar, g0, lam_n, s, mu, eps, k)
+    state = _residuals(disc, q, utilde, cs, qbar, g0, lam_n, s, mu, eps, k, targets)
     merit = _merit(state[1], state[2], state[3], h)
     it = 0
     ok = False
@@ -194,7 +204,8 @@ def _newton(disc, utilde, qbar, g0, cs, q, lam_n, s, mu, eps, k, maxit, tol_forc
         for _ in range(40):
             qn = q + alpha * dq
             try:
-                st = _residuals(disc, qn, utilde, cs, qbar, g0, lam_n + alpha * dlam_n, s + alpha * ds, mu, eps, k)
+                st = _residuals(disc, qn, utilde, cs, qbar, g0, lam_n + alpha * dlam_n, s + alpha * ds, mu, eps, k,
+                                targets)
             except ValueError:  # inverted element
                 alpha *= 0.5
                 continue
@@ -227,7 +238,7 @@ def _newton(disc, utilde, qbar, g0, cs, q, lam_n, s, mu, eps, k, maxit, tol_forc
 
 def solve_step(disc: Discretisation, qbar, vbar, f_ext, gravity, mu, eps, planes,
                spheres_old=np.zeros((0, 4)), spheres_new=np.zeros((0, 4)), margin=2e-3,
-               warm=None, maxit=60, tol_force=1e-11, tol_phi=1e-13, demote=()):
+               warm=None, maxit=60, tol_force=1e-11, tol_phi=1e-13, demote=(), targets=None):
     """One implicit step; returns (q, v, StepRecord, warm-start dict).
 
     A direct Newton solve is tried first; if it stalls, the step is re-solved
@@ -251,7 +262,10 @@ def solve_step(disc: Discretisation, qbar, vbar, f_ext, gravity, mu, eps, planes
             if key in warm:
                 lam0[c], s0[c] = warm[key]
     s0[~cs.fric] = 0.0
-    k = disc.A.diagonal()[3 * cs.vid] / (h * h)
+    adiag = disc.A.diagonal()
+    if disc.bindings is not None and len(disc.bindings.vid):
+        adiag = adiag - disc.bindings.matrix(disc.n_verts, h).diagonal()  # contact scale from M + elastic
+    k = adiag[3 * cs.vid] / (h * h)
     utilde = h * vbar + (h * h) * acc
     g0 = ct.gap_at(cs, qbar)
     u, lam_n, s = utilde.copy(), lam0.copy(), s0.copy()
@@ -259,7 +273,7 @@ def solve_step(disc: Discretisation, qbar, vbar, f_ext, gravity, mu, eps, planes
     while True:
         start = (u.copy(), lam_n.copy(), s.copy())
         u, lam_n, s, state, its, ok = _newton(disc, utilde, qbar, g0, cs, u, lam_n, s, mu, eps, k,
-                                              maxit, tol_force, tol_phi)
+                                              maxit, tol_force, tol_phi, targets)
         total += its
         if not ok:
             u, lam_n, s = start
@@ -270,7 +284,7 @@ def solve_step(disc: Discretisation, qbar, vbar, f_ext, gravity, mu, eps, planes
                 tf = tol_force if last else 1e-7
                 tp = tol_phi if last else 1e-7
                 u, lam_n, s, state, its, ok = _newton(disc, utilde, qbar, g0, cs, u, lam_n, s, mu, e_j,
-                                                      k, maxit, tf, tp)
+                                                      k, maxit, tf, tp, targets)
                 total += its
                 if last:
                     break
@@ -290,6 +304,7 @@ def solve_step(disc: Discretisation, qbar, vbar, f_ext, gravity, mu, eps, planes
     pf = np.where(cs.fric, fb.phi_eps(x, mu * lam[:, 0] - s, eps), 0.0)
     resid = max(np.max(np.abs(r)) / (h * h), np.max(np.abs(pn), initial=0.0),
                 np.max(np.abs(pf), initial=0.0))
-    record = StepRecord(cs, delta, lam, mu, total, resid)
+    record = StepRecord(cs, delta, lam, mu, total, resid,
+                        None if targets is None else np.array(targets, dtype=np.float64))
     new_warm = {(int(cs.vid[c]), int(cs.collider[c])): (lam_n[c], s[c]) for c in range(nc)}
     return q, v, record, new_warm
