@@ -53,7 +53,12 @@ typedef struct adj_scene adj_scene; /* opaque */
  * orientation, density, Young's modulus E and Poisson ratio nu (scalars, or
  * one value per tet when per_tet_material = 1).  Contact colliders: planes
  * (n, d) with gap n.x - d, unit n.  h = time step, eps = smoothing parameter
- * of phi_eps(x,y) = x + y - sqrt(x^2 + y^2 + 2 eps^2) (Sec. 5.2). */
+ * of phi_eps(x,y) = x + y - sqrt(x^2 + y^2 + 2 eps^2) (Sec. 5.2).
+ * Bilateral bindings (Sec. 3.2 eq:binding): vertex binding_vid[b] is held to
+ * a target d_b, given per step (adj_binding_vjp), by a linear spring of
+ * compliance binding_E[b] > 0; the vertices are distinct.  The binding term
+ * h^2 J_b^T E_b^{-1} J_b is constant, so it is part of the prefactored system
+ * matrix A.  Leave n_bindings = 0 (zero-initialised description) for none. */
 typedef struct {
   int32_t n_verts;
   int32_t n_tets;
@@ -69,6 +74,9 @@ typedef struct {
   int32_t n_planes;
   const double* planes;   /* host [n_planes*4] */
   double contact_margin;  /* candidate if predicted gap <= margin */
+  int32_t n_bindings;
+  const int32_t* binding_vid; /* host [n_bindings] */
+  const double* binding_E;    /* host [n_bindings] */
 } adj_scene_desc;
 
 /* Converged contact state of one step (the forward step record).  All
@@ -227,6 +235,18 @@ adj_status adj_check_status(adj_scene* scene, void* stream);
  * is smaller (ADJ_E_SHAPE).  For tests and debugging. */
 adj_status adj_debug_export(const adj_scene* scene, int32_t what, void* host_out, int64_t capacity_bytes,
                             int64_t* size_bytes);
+
+/* Binding gradients of the last adjoint_setup's step (Sec. 5.1
+ * eq:differential_2, rhs_d_b and rhs_E_b): with z from adjoint_solve, q the
+ * converged state and targets the step's binding targets d_b (device
+ * [n_bindings][3]), writes dL/dd_b = h^2 z_b / E_b (device [n_bindings][3])
+ * and dL/dE_b = -h^2 (lambda_b . z_b) / E_b with lambda_b = -(q_b - d_b) / E_b
+ * (device [n_bindings]).  A scene without bindings returns ADJ_OK at once.
+ * (The forward step does not take bindings: sim_forward_step returns
+ * ADJ_E_NOTIMPL on a scene with bindings; converged states come from the
+ * caller.) */
+adj_status adj_binding_vjp(adj_scene* scene, const double* z, const double* q, const double* targets,
+                           double* dL_dtargets, double* dL_dE, void* stream);
 
 /* Live timing of one kernel class: after adj_profile_begin(scene, kernel),
  * every launch of that kernel made by this scene's calls is bracketed by HIP

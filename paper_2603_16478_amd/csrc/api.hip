@@ -33,6 +33,9 @@ void launch_contact_blocks(hipStream_t, int, const int*, const double*, const do
                            double, const double*, double, double, int, double*, double*, double*, double*,
                            double*);
 void launch_contact_fold(hipStream_t, int, const int*, const int*, const double*, double*);
+void launch_binding_fold(hipStream_t, int, const int*, const double*, double, const int*, double*);
+void launch_binding_vjp(hipStream_t, int, const int*, const double*, double, const double*, const double*,
+                        const double*, double*, double*);
 void launch_capacitance(hipStream_t, int, int, const int*, const int*, const int*, int, const double*,
                         const double*, const double*, double, double, int, double*);
 void launch_vjp_contacts(hipStream_t, int, const int*, const double*, const double*, const double*,
@@ -141,6 +144,9 @@ struct adj_scene {
   HostScene hs;
   adj_tuning tune{64, 16, 8, 0};
   int nv = 0, nt = 0, nnzb = 0, max_contacts = 0;
+  int nb = 0;  // bilateral bindings: vertex ids and compliances on the device
+  int* d_bvid = nullptr;
+  double* d_bE = nullptr;
   long long n3 = 0;
   int restart = 0;
   // constant device data
@@ -262,7 +268,7 @@ static void free_scene(adj_scene* s) {
                   s->d_mask,     s->d_fvid,   s->d_force, s->d_utilde,      s->d_qtilde,
                   s->d_fu,       s->d_du,     s->d_ut,    s->d_qcur,        s->d_rq,
                   s->d_rhs,      s->d_cvec,   s->d_cu,    s->d_norms,       s->d_Sx32,
-                  s->d_STx32,    s->d_val32,  s->d_Pws,   s->d_x_pcg};
+                  s->d_STx32,    s->d_val32,  s->d_Pws,   s->d_x_pcg, s->d_bvid, s->d_bE};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (s->h_state) (void)hipHostFree(s->h_state);
@@ -327,6 +333,11 @@ static adj_status scene_create(const adj_scene_desc* desc, int32_t max_contacts,
   UP(s->d_col, h.col);
   UP(s->d_row_of_slot, h.row_of_slot);
   UP(s->d_diag_slot, h.diag_slot);
+  s->nb = (int)h.bvid.size();
+  if (s->nb) {
+    UP(s->d_bvid, h.bvid);
+    UP(s->d_bE, h.bE);
+  }
   UP(s->d_slot_ptr, h.slot_ptr);
   UP(s->d_slot_code, h.slot_code);
   UP(s->d_Bt, h.Bt);
@@ -598,6 +609,7 @@ extern "C" adj_status adjoint_setup(adj_scene* s, const adj_contact_state* cst, 
   launch_contact_blocks(st, nc, cst->fric, cst->frame, cst->delta, cst->lambda, cst->mu, nullptr, s->hs.eps, h2, 1,
                         s->d_Wt, s->d_Q, s->d_kh, s->d_Kc, s->d_kmu);
   launch_contact_fold(st, nc, cst->vid, s->d_diag_slot, s->d_Wt, s->d_val);
+  launch_binding_fold(st, s->nb, s->d_bvid, s->d_bE, h2, s->d_diag_slot, s->d_val);
   // a4: Delassus (cached per contact vertex set), capacitance, its inverse;
   // skipped when the solves will use a comparison preconditioner
   const bool woodbury = !opts || opts->precond == ADJ_PRECOND_WOODBURY;
@@ -1055,6 +1067,17 @@ extern "C" adj_status vjp_params(adj_scene* s, const double* z, const double* dL
   return ADJ_OK;
 }
 
+extern "C" adj_status adj_binding_vjp(adj_scene* s, const double* z, const double* q, const double* targets,
+                                      double* dL_dtargets, double* dL_dE, void* stream) {
+  if (!s || !z || !q) return fail(ADJ_E_ARG, "null argument");
+  if (!s->nb) return ADJ_OK;
+  if (!targets || !dL_dtargets || !dL_dE) return fail(ADJ_E_ARG, "null binding array");
+  const double h2 = s->hs.h * s->hs.h;
+  launch_binding_vjp((hipStream_t)stream, s->nb, s->d_bvid, s->d_bE, h2, z, q, targets, dL_dtargets, dL_dE);
+  HIPCHK(hipGetLastError());
+  return ADJ_OK;
+}
+
 static bool valid_tuning(const adj_tuning& t) {
   const bool gs = t.gs_rows == 64 || t.gs_rows == 128 || t.gs_rows == 256;
   const bool ln = t.bsr_lanes == 4 || t.bsr_lanes == 8 || t.bsr_lanes == 16 || t.bsr_lanes == 32;
@@ -1505,6 +1528,7 @@ extern "C" adj_status sim_forward_step(adj_scene* s, const double* qbar, const d
                                        adj_contact_state* out, void* stream) {
   if (!s || !qbar || !vbar || !f_ext || !q || !v || !out) return fail(ADJ_E_ARG, "null argument");
   if (!std::isfinite(mu) || mu < 0) return fail(ADJ_E_ARG, "mu must be finite and >= 0");
+  if (s->nb) return fail(ADJ_E_NOTIMPL, "the forward step does not take bindings");
   hipStream_t st = (hipStream_t)stream;
   const double h = s->hs.h;
   const long long n3 = s->n3;

@@ -162,6 +162,23 @@ adj_status build_host_scene(const adj_scene_desc* d, HostScene& s, std::string& 
       err = "tet references a vertex out of range";
       return ADJ_E_ARG;
     }
+  if (d->n_bindings < 0 || (d->n_bindings > 0 && (!d->binding_vid || !d->binding_E))) {
+    err = "scene_desc: binding arrays missing";
+    return ADJ_E_ARG;
+  }
+  s.bvid.assign(d->binding_vid, d->binding_vid + std::max(0, d->n_bindings));
+  s.bE.assign(d->binding_E, d->binding_E + std::max(0, d->n_bindings));
+  {
+    std::vector<char> seen(nv, 0);
+    for (size_t b = 0; b < s.bvid.size(); ++b) {
+      const int32_t v = s.bvid[b];
+      if (v < 0 || v >= nv || seen[v] || !(s.bE[b] > 0) || !std::isfinite(s.bE[b])) {
+        err = "bindings: vertex out of range or repeated, or compliance not positive";
+        return ADJ_E_ARG;
+      }
+      seen[v] = 1;
+    }
+  }
   s.Bm.resize(9 * (size_t)nt);
   s.Bt.resize(12 * (size_t)nt);
   s.vol.resize(nt);
@@ -256,6 +273,8 @@ adj_status build_host_scene(const adj_scene_desc* d, HostScene& s, std::string& 
       }
   }
   for (int v = 0; v < nv; ++v) s.As[s.diag_slot[v]] += s.mass[v];
+  // bindings: h^2 J_b^T E_b^{-1} J_b (a scalar on the vertex's diagonal)
+  for (size_t b = 0; b < s.bvid.size(); ++b) s.As[s.diag_slot[s.bvid[b]]] += h2 / s.bE[b];
   // vertex incidence (for gathering element forces)
   s.vptr.assign(nv + 1, 0);
   for (int t = 0; t < nt; ++t)

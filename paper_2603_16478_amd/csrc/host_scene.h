@@ -29,6 +29,9 @@ struct HostScene {
   std::vector<double> Bt;      // [nt*12] row-major 4x3: [-1^T B_m; B_m]
   std::vector<double> vol, lmu, llam, E, nu;  // per tet (Lame mu, lambda; E, nu)
   std::vector<double> mass;    // per vertex
+  // bilateral bindings: vertex and compliance per binding
+  std::vector<int32_t> bvid;
+  std::vector<double> bE;
   // Block pattern of Acal: rows = vertices, sorted columns, diagonal included.
   std::vector<int32_t> rowptr, col, diag_slot, row_of_slot;
   // Element-to-entry map: contributions to each block slot, ordered by

@@ -212,6 +212,52 @@ void launch_contact_blocks(hipStream_t st, int nc, const int* fric, const double
                                                    Wt, Q, kh, Kc, kmu);
 }
 
+// Bilateral bindings (eq:binding): h^2 E_b^{-1} I onto the diagonal block of
+// each bound vertex (the vertices are distinct: one writer per block).
+__global__ void k_binding_fold(int nb, const int* __restrict__ bvid, const double* __restrict__ bE, double h2,
+                               const int* __restrict__ diag_slot, double* __restrict__ val) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nb) return;
+  double* d = val + 9LL * diag_slot[bvid[b]];
+  const double c = h2 / bE[b];
+  d[0] += c;
+  d[4] += c;
+  d[8] += c;
+}
+
+// Binding gradients (eq:differential_2, rhs_d_b and rhs_E_b) with the binding
+// force lambda_b = -(q_b - d_b) / E_b:  dL/dd_b = h^2 z_b / E_b,
+// dL/dE_b = -h^2 (lambda_b . z_b) / E_b.
+__global__ void k_binding_vjp(int nb, const int* __restrict__ bvid, const double* __restrict__ bE, double h2,
+                              const double* __restrict__ z, const double* __restrict__ q,
+                              const double* __restrict__ target, double* __restrict__ dtarget,
+                              double* __restrict__ dE) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nb) return;
+  const int v = bvid[b];
+  const double e = bE[b];
+  double dot = 0.0;
+  for (int k = 0; k < 3; ++k) {
+    const double zk = z[3 * v + k];
+    const double lam = -(q[3 * v + k] - target[3 * b + k]) / e;
+    dtarget[3 * b + k] = h2 * zk / e;
+    dot += lam * zk;
+  }
+  dE[b] = -h2 * dot / e;
+}
+
+void launch_binding_fold(hipStream_t st, int nb, const int* bvid, const double* bE, double h2, const int* diag_slot,
+                         double* val) {
+  if (nb == 0) return;
+  k_binding_fold<<<(nb + 63) / 64, 64, 0, st>>>(nb, bvid, bE, h2, diag_slot, val);
+}
+
+void launch_binding_vjp(hipStream_t st, int nb, const int* bvid, const double* bE, double h2, const double* z,
+                        const double* q, const double* target, double* dtarget, double* dE) {
+  if (nb == 0) return;
+  k_binding_vjp<<<(nb + 63) / 64, 64, 0, st>>>(nb, bvid, bE, h2, z, q, target, dtarget, dE);
+}
+
 void launch_contact_fold(hipStream_t st, int nc, const int* vid, const int* diag_slot,
                          const double* Wt, double* val) {
   if (nc == 0) return;

@@ -30,7 +30,8 @@ EXPORTS = ("adj_scene_create", "adj_scene_destroy", "adjoint_setup", "adjoint_so
            "adj_profile_begin", "adj_profile_end", "adj_forward_stats", "adj_forward_reset",
            "adj_set_tuning", "adj_get_tuning", "adj_autotune", "adj_batch_create", "adj_batch_destroy",
            "adj_batch_info", "adj_batch_setup", "adj_batch_solve", "adj_batch_vjp", "adj_batch_check_status",
-           "adj_batch_debug_export", "adj_batch_scene", "adj_batch_reverse", "adj_last_error")
+           "adj_batch_debug_export", "adj_batch_scene", "adj_batch_reverse", "adj_binding_vjp",
+           "adj_last_error")
 KERNELS = {"S": 0, "ST": 1, "capinv": 2, "Z": 3, "bsr": 4, "tet": 5, "assemble": 6, "gj": 7,
            "gs_pass2": 8, "gs_pass1": 9, "gj_step": 10}
 
@@ -46,7 +47,8 @@ class SceneDesc(C.Structure):
                 ("tets", C.c_void_p), ("density", C.c_double), ("h", C.c_double), ("eps", C.c_double),
                 ("E", C.c_void_p), ("nu", C.c_void_p), ("per_tet_material", C.c_int32),
                 ("gravity", C.c_double * 3), ("n_planes", C.c_int32), ("planes", C.c_void_p),
-                ("contact_margin", C.c_double)]
+                ("contact_margin", C.c_double), ("n_bindings", C.c_int32), ("binding_vid", C.c_void_p),
+                ("binding_E", C.c_void_p)]
 
 
 class ContactState(C.Structure):
@@ -112,6 +114,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.adj_batch_check_status.argtypes = [vp, vp]
     lib.adj_batch_debug_export.argtypes = [vp, C.c_int32, C.c_int32, vp, C.c_int64, C.POINTER(C.c_int64)]
     lib.adj_batch_scene.argtypes = [vp, C.POINTER(vp)]
+    lib.adj_binding_vjp.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     lib.adj_batch_reverse.argtypes = [vp, vp, C.c_int32, C.POINTER(ContactState), C.POINTER(vp), vp, vp,
                                       C.POINTER(vp), vp, C.POINTER(SolveOpts), C.POINTER(SolveInfo), vp]
     for name in EXPORTS:
@@ -145,7 +148,8 @@ class Scene:
     """Owns an adj_scene (adj_scene_create / adj_scene_destroy)."""
 
     def __init__(self, rest, tets, density, h, eps, E, nu, gravity, planes, contact_margin,
-                 max_contacts):
+                 max_contacts, bindings=None):
+        """bindings: None or (vertex ids, compliances) of bilateral bindings."""
         lib = load()
         self._keep = []
         rest = np.ascontiguousarray(rest, dtype=np.float64)
@@ -164,6 +168,14 @@ class Scene:
         d.n_planes = planes.shape[0]
         d.planes = planes.ctypes.data if planes.shape[0] else None
         d.contact_margin = float(contact_margin)
+        self.n_bindings = 0
+        if bindings is not None:
+            bvid = np.ascontiguousarray(bindings[0], dtype=np.int32)
+            bE = np.ascontiguousarray(np.broadcast_to(np.asarray(bindings[1], dtype=np.float64), bvid.shape))
+            self._keep += [bvid, bE]
+            d.n_bindings = bvid.shape[0]
+            d.binding_vid, d.binding_E = bvid.ctypes.data, bE.ctypes.data
+            self.n_bindings = int(bvid.shape[0])
         handle = C.c_void_p()
         check(lib.adj_scene_create(C.byref(d), int(max_contacts), C.byref(handle)))
         self.handle = handle
@@ -247,6 +259,12 @@ def profile_end(scene: Scene):
     ms, n = C.c_double(), C.c_int64()
     check(load().adj_profile_end(scene.handle, C.byref(ms), C.byref(n)))
     return ms.value, n.value
+
+
+def binding_vjp(scene: Scene, z, q, targets, dL_dtargets, dL_dE, stream=None):
+    """dL/dd_b and dL/dE_b of the bilateral bindings (adj_binding_vjp)."""
+    check(load().adj_binding_vjp(scene.handle, _ptr(z), _ptr(q), _ptr(targets), _ptr(dL_dtargets), _ptr(dL_dE),
+                                 _stream(stream)))
 
 
 def check_status(scene: Scene, stream=None):
@@ -335,7 +353,8 @@ class Batch:
     """Owns an adj_batch: several scenes solved together (adj_batch_create).
     specs: sequence of (rest, tets, E, nu); density, h, eps are shared."""
 
-    def __init__(self, specs, density, h, eps, gravity, planes, contact_margin, max_contacts):
+    def __init__(self, specs, density, h, eps, gravity, planes, contact_margin, max_contacts, bindings=None):
+        """bindings: None, or per scene None / (vertex ids, compliances)."""
         lib = load()
         self._keep = []
         n = len(specs)
@@ -358,6 +377,12 @@ class Batch:
             d.n_planes = planes.shape[0]
             d.planes = planes.ctypes.data if planes.shape[0] else None
             d.contact_margin = float(contact_margin)
+            if bindings is not None and bindings[k] is not None:
+                bvid = np.ascontiguousarray(bindings[k][0], dtype=np.int32)
+                bE = np.ascontiguousarray(np.broadcast_to(np.asarray(bindings[k][1], dtype=np.float64), bvid.shape))
+                self._keep += [bvid, bE]
+                d.n_bindings = bvid.shape[0]
+                d.binding_vid, d.binding_E = bvid.ctypes.data, bE.ctypes.data
         mc = (C.c_int32 * n)(*[int(m) for m in max_contacts])
         handle = C.c_void_p()
         check(lib.adj_batch_create(n, descs, mc, C.byref(handle)))

@@ -1,0 +1,138 @@
+"""GPU parity of the bilateral bindings (Sec. 3.2 eq:binding; Sec. 5.1
+eq:differential_2): a tiny cube hung by four top-face vertices (no ground),
+and the tiny impact cube held by its top corners while it lands on the
+ground with friction; states from the oracle's forward solve.  With the
+binding term in the prefactored system matrix and folded into the assembled
+blocks, the adjoint and every gradient, including dL/dd_b and dL/dE_b, must
+match the FP64 oracle at 1e-9, single scene and in a batch of two hung
+cubes."""
+
+import numpy as np
+import pytest
+
+from gpu_helpers import contact_tensors, rel, torch_cuda
+from oracle import adjoint as adj
+import test_oracle_bindings as tob
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-9
+
+
+def _state(step=3):
+    spec, b, disc, d, states = tob._hanging(step)
+    (qbar, vbar), (q, v) = states[-2], states[-1]
+    rec = tob._step(spec, disc, qbar, vbar, d)[2]
+    return spec, b, disc, d, q, rec
+
+
+def _scene(spec, b):
+    from paper_2603_16478_amd import native
+    return native.Scene(spec.mesh.rest, spec.mesh.tets, spec.density, spec.h, spec.eps, spec.E, spec.nu,
+                        spec.gravity, spec.planes, spec.contact_margin, 64, bindings=(b.vid, b.E))
+
+
+def test_bindings_single_scene_match_oracle():
+    torch = torch_cuda()
+    from gpu_helpers import run_adjoint
+    from paper_2603_16478_amd import native
+    spec, b, disc, d, q, rec = _state()
+    rng = np.random.default_rng(21)
+    gq, gv = rng.standard_normal(q.shape), 1e-3 * rng.standard_normal(q.shape)
+    ref = adj.adjoint_step(disc, q, rec, gq, gv, spec.eps, spec.E, spec.nu)
+    scene = _scene(spec, b)
+    out = run_adjoint(scene, rec, q, gq, gv, rtol=1e-13, want_tet=True)
+    zd = torch.tensor(out["z"], device="cuda")
+    qd = torch.tensor(q, device="cuda")
+    dt = torch.tensor(d, device="cuda")
+    gt = torch.empty_like(dt)
+    gE = torch.empty(b.vid.size, dtype=torch.float64, device="cuda")
+    native.binding_vjp(scene, zd, qd, dt, gt, gE)
+    torch.cuda.synchronize()
+    print(f"bindings: iters {out['info'].iters} ({out['info'].method}), z err {rel(out['z'], ref.z):.2e}, "
+          f"dtarget err {rel(gt.cpu().numpy(), ref.dtarget):.2e}, dE_b err {rel(gE.cpu().numpy(), ref.dE_bind):.2e}",
+          flush=True)
+    for k in ("z", "dqbar", "dvbar", "dfext", "dE_tet", "dnu_tet"):
+        assert rel(out[k], getattr(ref, k)) <= TOL, k
+    assert rel(gt.cpu().numpy(), ref.dtarget) <= TOL
+    assert rel(gE.cpu().numpy(), ref.dE_bind) <= TOL
+    # the forward step does not take bindings
+    with pytest.raises(native.AdjError, match="NOTIMPL"):
+        native.sim_forward_step(scene, qd, torch.zeros_like(qd), torch.zeros_like(qd), 0.5, torch.empty_like(qd),
+                                torch.empty_like(qd), native.ContactBuffers(64).state)
+    scene.close()
+
+
+def test_bindings_with_frictional_contact_match_oracle():
+    torch = torch_cuda()
+    import functools
+    from gpu_helpers import run_adjoint
+    from oracle.forward import solve_step
+    from paper_2603_16478_amd import native
+    from synth import tiny_scene
+    spec = tiny_scene("impact")
+    b = tob._bindings(spec, E=3e-3)
+    disc = tob._disc(spec, b)
+    d = spec.mesh.rest[b.vid] + np.array([2e-3, 0.0, -8e-3])
+    q, v = spec.q0.copy(), spec.v0.copy()  # dropped with the scene's seeded initial velocity
+    warm = None
+    for _ in range(11):
+        q, v, rec, warm = solve_step(disc, q, v, np.zeros_like(q), spec.gravity, spec.mu, spec.eps, spec.planes,
+                                     margin=spec.contact_margin, warm=warm, targets=d)
+    assert rec.residual < 1e-9 and rec.contacts.fric.any()
+    rng = np.random.default_rng(23)
+    gq, gv = rng.standard_normal(q.shape), 1e-3 * rng.standard_normal(q.shape)
+    ref = adj.adjoint_step(disc, q, rec, gq, gv, spec.eps, spec.E, spec.nu)
+    scene = native.Scene(spec.mesh.rest, spec.mesh.tets, spec.density, spec.h, spec.eps, spec.E, spec.nu,
+                         spec.gravity, spec.planes, spec.contact_margin, 64, bindings=(b.vid, b.E))
+    out = run_adjoint(scene, rec, q, gq, gv, rtol=1e-13, want_tet=True, raise_noconv=False)
+    zd = torch.tensor(out["z"], device="cuda")
+    gt = torch.empty((b.vid.size, 3), dtype=torch.float64, device="cuda")
+    gE = torch.empty(b.vid.size, dtype=torch.float64, device="cuda")
+    native.binding_vjp(scene, zd, torch.tensor(q, device="cuda"), torch.tensor(d, device="cuda"), gt, gE)
+    torch.cuda.synchronize()
+    info = out["info"]
+    print(f"bindings + contact: {rec.contacts.n} contacts ({int(rec.contacts.fric.sum())} frictional), "
+          f"iters {info.iters} ({info.method}), relres {info.relres:.2e}, z err {rel(out['z'], ref.z):.2e}",
+          flush=True)
+    assert info.method == native.ADJ_GMRES and info.relres <= 1e-11
+    for k in ("z", "dqbar", "dvbar", "dfext", "dE_tet", "dnu_tet"):
+        assert rel(out[k], getattr(ref, k)) <= TOL, k
+    assert rel(gt.cpu().numpy(), ref.dtarget) <= TOL
+    assert rel(gE.cpu().numpy(), ref.dE_bind) <= TOL
+    scene.close()
+
+
+def test_bindings_in_a_batch_match_oracle():
+    torch = torch_cuda()
+    from paper_2603_16478_amd import native
+    spec, b, disc, d, q, rec = _state()
+    spec2, b2, disc2, d2, q2, rec2 = _state(2)
+    cases = [(disc, q, rec, b), (disc2, q2, rec2, b2)]
+    bt = native.Batch([(spec.mesh.rest, spec.mesh.tets, spec.E, spec.nu)] * 2, spec.density, spec.h, spec.eps,
+                      spec.gravity, spec.planes, spec.contact_margin, [1, 1],
+                      bindings=[(b.vid, b.E), (b2.vid, b2.E)])
+    keep, states = [], []
+    for _, _, r, _ in cases:
+        tens = contact_tensors(r)
+        keep.append(tens)
+        states.append(native.make_contact_state(r.contacts.n, tens["vid"], tens["fric"], tens["frame"],
+                                                tens["delta"], tens["lam"], r.mu))
+    rng = np.random.default_rng(22)
+    gqs = [rng.standard_normal(c[1].shape) for c in cases]
+    qd = torch.tensor(np.concatenate([c[1] for c in cases]), device="cuda")
+    gqd = torch.tensor(np.concatenate(gqs), device="cuda")
+    gvd = torch.zeros_like(gqd)
+    z = torch.zeros_like(gqd)
+    opts = native.solve_opts(rtol=1e-13, maxit=3000)
+    native.batch_setup(bt, states, qd, opts)
+    infos = native.batch_solve(bt, gqd, gvd, z, opts, raise_noconv=False)
+    zc = z.cpu().numpy().reshape(-1, 3)
+    for k, (dk, qk, rk, bk) in enumerate(cases):
+        ref = adj.adjoint_step(dk, qk, rk, gqs[k], np.zeros_like(qk), spec.eps, spec.E, spec.nu)
+        zk = zc[bt.voff[k]:bt.voff[k + 1]]
+        print(f"batch scene {k}: iters {infos[k].iters}, relres {infos[k].relres:.2e}, z err {rel(zk, ref.z):.2e}",
+              flush=True)
+        assert infos[k].relres <= 1e-11
+        assert rel(zk, ref.z) <= TOL
+    bt.close()
