@@ -17,7 +17,9 @@ step runs on a second stream while a step is solved; a bench step is one
 time step of the pass (three solves).  Also reported: the pass in mixed
 precision and without the pipelining, one batch per step with a fixed
 right-hand side (FP64 and mixed; the roofline kernels are timed there),
-each scene solved alone (FP64 and mixed), a large batch (the
+each scene solved alone (FP64 and mixed), the comparison preconditioners
+of the backward solve, the beam with its end face held by bilateral
+bindings (single scene, FP64), a large batch (the
 twelve recorded scene-steps four times: 48 scenes per launch, FP64 and
 mixed, with the sparse-inverse product's bandwidth), the rooflines of the
 two largest kernels, the batched Gauss-Jordan step and the batched
@@ -138,7 +140,8 @@ def batch_mps(native, batch, n_scenes):
 
 
 def cpu_baseline(spec, states, sample):
-    """The oracle (direct sparse LU + refinement) on `sample` scene-steps."""
+    """The oracle (direct sparse LU + refinement) on `sample` scene-steps,
+    cycling over the recorded ones."""
     from threadpoolctl import threadpool_limits
 
     from oracle import adjoint as adj
@@ -151,14 +154,16 @@ def cpu_baseline(spec, states, sample):
     gv = np.zeros_like(gq)
     t0 = time.perf_counter()
     with threadpool_limits(limits=1):
-        for st in states[:sample]:
+        for i in range(sample):
+            st = states[i % len(states)]
             cs = ContactSet(st["vid"], st["collider"], st["frame"], st["d_n"], st["d_f"], st["fric"].astype(bool))
             rec = StepRecord(cs, st["delta"], st["lam"], st["mu"])
             adj.adjoint_step(disc, st["q"], rec, gq, gv, spec.eps, spec.E, spec.nu)
     dt = time.perf_counter() - t0
     return {"value": sample / dt, "unit": "adjoint solves/s", "cores": 1, "kind": "oracle",
-            "sample": f"{sample} beam scene-steps (setup + direct sparse LU solve with long-double "
-                      f"refinement + gradient contractions), single thread, {dt:.1f} s"}
+            "sample": f"{sample} beam scene-steps, cycling over the {len(states)} recorded ones (setup + direct "
+                      f"sparse LU solve with long-double refinement + gradient contractions), single thread, "
+                      f"{dt:.1f} s"}
 
 
 def main():
@@ -167,7 +172,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=4)
     ap.add_argument("--rtol", type=float, default=1e-8)
-    ap.add_argument("--cpu-sample", type=int, default=3)
+    ap.add_argument("--cpu-sample", type=int, default=40,
+                    help="scene-steps the oracle solves for cpu_baseline (cycling over the recorded ones)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--big-batch", type=int, default=4,
@@ -426,6 +432,45 @@ def main():
                    "point_jacobi": run_precond(native.PRECOND_POINT_JACOBI, n_pc),
                    "semi_implicit": run_precond(native.PRECOND_SPARSE_INVERSE, n_pc, native.ADJ_SEMI_IMPLICIT)}
 
+    # ---- bilateral bindings: the beam's x = 0 end face held by compliant
+    # bindings to its rest positions (the binding term changes only the
+    # diagonal of the prefactored matrix and of the assembled blocks, so the
+    # recorded contact states serve as they are) ----
+    rest = spec.mesh.rest
+    bvid = np.flatnonzero(np.isclose(rest[:, 0], rest[:, 0].min())).astype(np.int32)
+    bE = 1e-6
+    bscene = native.Scene(rest, spec.mesh.tets, spec.density, spec.h, spec.eps, spec.E, spec.nu, spec.gravity,
+                          spec.planes, spec.contact_margin, max_c, bindings=(bvid, bE))
+    btarget = torch.tensor(rest[bvid], dtype=torch.float64, device=dev)
+    bdt = torch.empty_like(btarget)
+    bdE = torch.empty(bvid.size, dtype=torch.float64, device=dev)
+
+    def run_bound(nsteps, warm):
+        o = native.solve_opts(rtol=args.rtol, maxit=5000, restart=64)
+        its = []
+        t0b = time.perf_counter()
+        for i in range(warm + nsteps):
+            if i == warm:
+                torch.cuda.synchronize()
+                its.clear()
+                t0b = time.perf_counter()
+            t = dstates[i % len(dstates)]
+            native.adjoint_setup(bscene, t["cs"], t["q"], o)
+            inf = native.adjoint_solve(bscene, gq, gv, z, o)
+            native.vjp_params(bscene, z, gv, dqbar, dvbar, dfext, grad3)
+            native.binding_vjp(bscene, z, t["q"], btarget, bdt, bdE)
+            its.append(inf.iters)
+        torch.cuda.synchronize()
+        dtb = time.perf_counter() - t0b
+        return {"value": nsteps / dtb, "unit": "adjoint solves/s", "ms_per_step": 1e3 * dtb / nsteps,
+                "krylov_iters_mean": float(np.mean(its))}
+
+    bound = run_bound(args.steps, args.warmup) | {
+        "n_bindings": int(bvid.size), "binding_compliance": bE,
+        "vs_unbound_single_scene_fp64": None}
+    bound["vs_unbound_single_scene_fp64"] = bound["value"] / single["value"]
+    bscene.close()
+
     abytes = s_product_bytes(uinfo)
     avg_ms = kms / max(launches, 1)
     achieved = abytes / (avg_ms * 1e-3) / 1e9 if launches else 0.0
@@ -511,6 +556,9 @@ def main():
                                                   "fixed-point iteration x <- x + A^-1 (b - Acal^T x), stopped "
                                                   "when its residual exceeds 1e6 |b|"},
         "large_batch": big,
+        "bindings": bound | {"note": "single scene, FP64, the beam's 81 x = 0 face vertices bound to their rest "
+                                     "positions (compliance 1e-6 m/N), GMRES(64) + Woodbury to 1e-8; setup + "
+                                     "solve + VJP + binding VJP per recorded scene-step"},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(spec, states, args.cpu_sample)
