@@ -17,4 +17,5 @@ from .configs import (  # noqa: F401
     batched_scenes,
     beam_push_force,
     loss_vector,
+    slope_scene,
 )

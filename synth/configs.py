@@ -197,3 +197,33 @@ def batched_scenes(n_scenes: int = 256, seed: int = 3, tmax: float = 1e5):
             loss_dir=loss_vector(rng, mesh.n_verts), seed=seed * 1000 + s,
         ))
     return out
+
+
+SLOPE_DEG = 10.0
+# the two friction coefficients straddle the slip threshold tan(slope) by
+# +-4e-4 (a 1e-3-scale friction difference)
+SLOPE_DMU = 4e-4
+
+
+def slope_scene(side: str = "slip", two_eps2: float = 1e-12, seed: int = 5, h: float = 1e-2,
+                duration: float = 30.0, E: float = 1e7) -> SceneSpec:
+    """Stiff rubber-like cube (4x4x4 cells, 384 tets, side 0.1 m) resting on
+    a 10-degree slope, for the smoothing sweep.  The slope is expressed by
+    tilting gravity about the y axis (ground z = 0, down-slope direction +x),
+    which is the same physics as a tilted plane under vertical gravity.
+    ``side``: "slip" (mu = tan(slope) - 4e-4) or "stick" (mu = tan(slope) +
+    4e-4).  ``two_eps2`` is the smoothing 2 eps^2."""
+    if side not in ("slip", "stick"):
+        raise ValueError(side)
+    rng = np.random.default_rng(seed)
+    th = np.deg2rad(SLOPE_DEG)
+    mu = float(np.tan(th)) + (SLOPE_DMU if side == "stick" else -SLOPE_DMU)
+    mesh = box_mesh(4, 4, 4, 0.025, origin=(0.0, 0.0, 0.0))
+    g = 9.81 * np.array([np.sin(th), 0.0, -np.cos(th)])
+    steps = int(round(duration / h))
+    return SceneSpec(
+        name=f"slope-{side}-{two_eps2:g}", mesh=mesh, density=1100.0, E=E, nu=0.45, mu=mu, h=h,
+        eps=float(np.sqrt(0.5 * two_eps2)), steps=steps, gravity=g, planes=GROUND.copy(),
+        contact_margin=2e-3, q0=mesh.rest.copy(), v0=np.zeros((mesh.n_verts, 3)),
+        loss_dir=loss_vector(rng, mesh.n_verts), seed=seed,
+    )
