@@ -219,12 +219,18 @@ def _newton(disc, utilde, qbar, g0, cs, q, lam_n, s, mu, eps, k, maxit, tol_forc
         q = qn
         lam_n = lam_n + alpha * dlam_n
         s = s + alpha * ds
+        prev = merit
         state, merit = st, mn
         fmax = np.max(np.abs(state[1])) / (h * h)
         pmax = max(np.max(np.abs(state[2]), initial=0.0), np.max(np.abs(state[3]), initial=0.0))
         small = np.max(np.abs(alpha * dq)) <= 4e-16 * max(1.0, np.max(np.abs(q)))
         if alpha == 1.0 and ((fmax <= tol_force and pmax <= tol_phi) or small):
             ok = fmax <= 1e3 * tol_force and pmax <= 1e3 * tol_phi
+            break
+        # rounding floor: within 1e3 of the tolerances and the step no longer
+        # halves the residual (merit is its square)
+        if fmax <= 1e3 * tol_force and pmax <= 1e3 * tol_phi and merit > 0.25 * prev:
+            ok = True
             break
     else:
         fmax = np.max(np.abs(state[1])) / (h * h)

@@ -1499,6 +1499,7 @@ static adj_status fwd_newton(adj_scene* s, hipStream_t st, const double* qbar, F
     lam_n = lt;
     sf = stt;
     cs = ct;
+    const double prev = merit;
     merit = mt;
     fmax = ft;
     pmax = pt;
@@ -1514,6 +1515,12 @@ static adj_status fwd_newton(adj_scene* s, hipStream_t st, const double* qbar, F
     const bool small = nd[1] <= 4e-16 * std::max(1.0, nu[1]);
     if (alpha == 1.0 && ((fmax <= tol_f && pmax <= tol_p) || small)) {
       ok = fmax <= 1e3 * tol_f && pmax <= 1e3 * tol_p;
+      break;
+    }
+    // rounding floor: within 1e3 of the tolerances and the step no longer
+    // halves the residual (the merit is its square)
+    if (fmax <= 1e3 * tol_f && pmax <= 1e3 * tol_p && merit > 0.25 * prev) {
+      ok = true;
       break;
     }
   }
