@@ -166,6 +166,64 @@ def cpu_baseline(spec, states, sample):
                       f"{dt:.1f} s"}
 
 
+def eps_sweep_one(two_eps2, side, seconds):
+    """Down-slope displacement of one cube on the slope after `seconds` of
+    simulated time with the GPU forward step (h = 0.01 s, warm-started
+    multipliers); prints one JSON object."""
+    import torch
+
+    from paper_2603_16478_amd.rollout import GpuSim
+    from synth import slope_scene
+
+    spec = slope_scene(side, two_eps2, duration=seconds)
+    sim = GpuSim(spec, max_contacts=64)
+    q = torch.tensor(spec.q0, device="cuda")
+    v = torch.tensor(spec.v0, device="cuda")
+    f = torch.zeros_like(q)
+    x0 = torch.tensor(spec.q0[:, 0], device="cuda")
+    track = []
+    t0 = time.perf_counter()
+    for t in range(spec.steps):
+        q, v, _ = sim.step(q, v, f, spec.mu)
+        if (t + 1) % max(1, spec.steps // 20) == 0:
+            track.append(float((q[:, 0] - x0).mean()))
+            print(f"2eps^2 {two_eps2:g} {side}: t = {(t + 1) * spec.h:.1f} s, {track[-1]:.4e} m", file=sys.stderr,
+                  flush=True)
+    dt = time.perf_counter() - t0
+    sim.scene.close()
+    print(json.dumps({"mu": spec.mu, "displacement_m": float((q[:, 0] - x0).mean()), "trajectory_m": track,
+                      "ms_per_step": 1e3 * dt / spec.steps}))
+
+
+def eps_sweep(seconds):
+    """The smoothing sweep: the sliding and the sticking cube (friction
+    tan(10 deg) -/+ 4e-4) at each 2 eps^2, one child process per run, all
+    sharing the GPU (each run is bound by the forward step's host round
+    trips).  This process itself does not use the GPU.  Prints one JSON
+    line."""
+    import subprocess
+
+    runs = [(e, side) for e in (1e-15, 1e-12, 1e-9, 1e-6) for side in ("slip", "stick")]
+    procs = [subprocess.Popen([sys.executable, os.path.abspath(__file__), "--eps-sweep-one", f"{e:g}", side,
+                               f"{seconds:g}"], stdout=subprocess.PIPE, text=True) for e, side in runs]
+    rows = {}
+    status = 0
+    for (e, side), p in zip(runs, procs):
+        out, _ = p.communicate()
+        if p.returncode != 0:
+            status = p.returncode
+            continue
+        rows.setdefault(f"{e:g}", {})[side] = json.loads(out.strip().splitlines()[-1])
+    for row in rows.values():
+        if "slip" in row and "stick" in row:
+            row["slip_over_stick"] = row["slip"]["displacement_m"] / row["stick"]["displacement_m"]
+    print(json.dumps({"study": "smoothing sweep on the slope cube (10 deg, 4x4x4 cells, E 1e7 Pa, h 0.01 s)",
+                      "seconds": seconds, "analytic_slip_m": 0.5 * 9.81 * np.cos(np.deg2rad(10.0)) * 4e-4
+                      * seconds ** 2, "by_two_eps2": rows}))
+    if status:
+        sys.exit(status)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -176,6 +234,10 @@ def main():
                     help="scene-steps the oracle solves for cpu_baseline (cycling over the recorded ones)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--eps-sweep", type=float, default=0.0, metavar="SECONDS",
+                    help="instead of the benchmark: the smoothing sweep on the slope cube, SECONDS of simulated "
+                         "time per run on the GPU forward step")
+    ap.add_argument("--eps-sweep-one", nargs=3, metavar=("TWO_EPS2", "SIDE", "SECONDS"), help=argparse.SUPPRESS)
     ap.add_argument("--big-batch", type=int, default=4,
                     help="copies of the twelve recorded scene-steps in the large-batch leg (0: skip)")
     args = ap.parse_args()
@@ -183,6 +245,13 @@ def main():
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; --gpus above 1 is not supported",
                           "n_gpus": args.gpus}))
         sys.exit(2)
+
+    if args.eps_sweep_one:
+        eps_sweep_one(float(args.eps_sweep_one[0]), args.eps_sweep_one[1], float(args.eps_sweep_one[2]))
+        return
+    if args.eps_sweep > 0:
+        eps_sweep(args.eps_sweep)
+        return
 
     import torch
 
