@@ -48,6 +48,15 @@ typedef enum { ADJ_FP64 = 0, ADJ_MIXED = 1 } adj_precision;
 
 typedef struct adj_scene adj_scene; /* opaque */
 
+/* Material model of the local projection step (App. B.2): the singular
+ * values theta of the projected F minimise w/2 |theta - sigma|^2 + zeta(theta)
+ * with w = 2 mu.  Neo-Hookean: zeta from the stable Neo-Hookean energy
+ * (Newton on the optimality condition); ARAP: theta = 1 (the projection is
+ * the rotation of F, W = 0); co-rotational: zeta = mu |theta - 1|^2 +
+ * lam/2 (sum(theta - 1))^2 (linear optimality condition, constant W).  A
+ * batch's scenes share the model. */
+typedef enum { ADJ_MAT_NEO_HOOKEAN = 0, ADJ_MAT_ARAP = 1, ADJ_MAT_COROT = 2 } adj_material;
+
 /* Scene description (host memory, read during adj_scene_create only).
  * Mesh and material (Sec. 3.1, 3.3): rest positions, tets with positive
  * orientation, density, Young's modulus E and Poisson ratio nu (scalars, or
@@ -77,6 +86,7 @@ typedef struct {
   int32_t n_bindings;
   const int32_t* binding_vid; /* host [n_bindings] */
   const double* binding_E;    /* host [n_bindings] */
+  int32_t material;           /* adj_material; 0 (zero-initialised) = Neo-Hookean */
 } adj_scene_desc;
 
 /* Converged contact state of one step (the forward step record).  All

@@ -45,7 +45,7 @@ class AdjointSystem:
 
 def assemble(disc: Discretisation, q: np.ndarray, record: StepRecord, eps: float) -> AdjointSystem:
     F = deformation_gradient(q, disc.tets, disc.Bm)
-    rec = ProjectionRecord(F, disc.mu, disc.lam)
+    rec = ProjectionRecord(F, disc.mu, disc.lam, disc.model)
     blocks = ct.contact_blocks(record.contacts, record.delta, record.lam, record.mu, eps)
     Acal = elastic_tangent(disc, rec) + contact_matrix(disc.n_verts, record.contacts, blocks.K, disc.h)
     return AdjointSystem(Acal.tocsr(), rec, blocks)

@@ -100,13 +100,14 @@ class Discretisation:
     h: float
     A: sp.csr_matrix  # (3 n_v, 3 n_v), binding term included
     bindings: Bindings | None = None
+    model: str = "nh"  # local projection: "nh", "arap" or "corot" (App. B.2)
 
     @property
     def M(self) -> sp.dia_matrix:
         return sp.diags(np.repeat(self.mass, 3))
 
 
-def discretise(rest, tets, density, E, nu, h, bindings: Bindings | None = None) -> Discretisation:
+def discretise(rest, tets, density, E, nu, h, bindings: Bindings | None = None, model: str = "nh") -> Discretisation:
     n_v = rest.shape[0]
     Bm, vol, Bt = rest_operators(rest, tets)
     mass = lumped_mass(n_v, tets, vol, density)
@@ -119,4 +120,4 @@ def discretise(rest, tets, density, E, nu, h, bindings: Bindings | None = None) 
     A = (sp.diags(np.repeat(mass, 3)) + h * h * (G.T @ Wd @ G)).tocsr()
     if bindings is not None and len(bindings.vid):
         A = (A + bindings.matrix(n_v, h)).tocsr()
-    return Discretisation(n_v, tets, Bm, vol, Bt, mass, G, mu.copy(), lam.copy(), w, h, A, bindings)
+    return Discretisation(n_v, tets, Bm, vol, Bt, mass, G, mu.copy(), lam.copy(), w, h, A, bindings, model)

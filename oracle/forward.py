@@ -62,7 +62,7 @@ class StepRecord:
 
 def elastic_force_terms(disc: Discretisation, q: np.ndarray):
     F = deformation_gradient(q, disc.tets, disc.Bm)
-    rec = ProjectionRecord(F, disc.mu, disc.lam)
+    rec = ProjectionRecord(F, disc.mu, disc.lam, disc.model)
     Gq = vec(F).reshape(-1)
     return rec, Gq
 

@@ -30,7 +30,8 @@ class Rollout:
 
 def scene_disc(spec, E=None, nu=None):
     return discretise(spec.mesh.rest, spec.mesh.tets, spec.density,
-                      spec.E if E is None else E, spec.nu if nu is None else nu, spec.h)
+                      spec.E if E is None else E, spec.nu if nu is None else nu, spec.h,
+                      model=getattr(spec, "material", "nh"))
 
 
 def run_forward(spec, steps=None, E=None, nu=None, mu=None, v0=None, q0=None, disc=None,

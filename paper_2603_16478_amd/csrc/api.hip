@@ -23,12 +23,12 @@ namespace adj {
 
 // kernels (defined in the .hip kernel files)
 void launch_tet_blocks(hipStream_t, int, const int*, const double*, const double*, const double*,
-                       const double*, double, const double*, double*, int*);
+                       const double*, double, const double*, double*, int*, int);
 void launch_assemble(hipStream_t, int, const int*, const int*, const double*, const int*, const int*,
                      const double*, double*);
 void launch_vjp_tets(hipStream_t, int, const int*, const double*, const double*, const double*,
                      const double*, const double*, const double*, double, const double*, const double*,
-                     double*, double*, double*, double*);
+                     double*, double*, double*, double*, int);
 void launch_contact_blocks(hipStream_t, int, const int*, const double*, const double*, const double*,
                            double, const double*, double, double, int, double*, double*, double*, double*,
                            double*);
@@ -95,7 +95,7 @@ void launch_fwd_detect(hipStream_t, int, const double*, int, const double*, doub
 void launch_add_vec(hipStream_t, long long, const double*, const double*, double, double*);
 void launch_scale_vec(hipStream_t, long long, const double*, double, double*);
 void launch_tet_force(hipStream_t, int, const int*, const double*, const double*, const double*,
-                      const double*, double, const double*, double*, int*);
+                      const double*, double, const double*, double*, int*, int);
 void launch_gather_force(hipStream_t, int, const int*, const int*, const double*, const double*,
                          const double*, const double*, double*);
 void launch_add_contact_vec(hipStream_t, int, const int*, const double*, double*);
@@ -144,6 +144,7 @@ struct adj_scene {
   HostScene hs;
   adj_tuning tune{64, 16, 8, 0};
   int nv = 0, nt = 0, nnzb = 0, max_contacts = 0;
+  int material = 0;  // adj_material of the local projection
   int nb = 0;  // bilateral bindings: vertex ids and compliances on the device
   int* d_bvid = nullptr;
   double* d_bE = nullptr;
@@ -334,6 +335,7 @@ static adj_status scene_create(const adj_scene_desc* desc, int32_t max_contacts,
   UP(s->d_row_of_slot, h.row_of_slot);
   UP(s->d_diag_slot, h.diag_slot);
   s->nb = (int)h.bvid.size();
+  s->material = h.material;
   if (s->nb) {
     UP(s->d_bvid, h.bvid);
     UP(s->d_bE, h.bE);
@@ -598,7 +600,7 @@ extern "C" adj_status adjoint_setup(adj_scene* s, const adj_contact_state* cst, 
   {
     ProfScope p(s, 5, st);
     launch_tet_blocks(st, s->nt, s->d_tets, s->d_Bt, s->d_vol, s->d_lmu, s->d_llam, h2, q, s->d_tetblk,
-                      s->d_err);
+                      s->d_err, s->material);
   }
   {
     ProfScope p(s, 6, st);
@@ -1062,7 +1064,7 @@ extern "C" adj_status vjp_params(adj_scene* s, const double* z, const double* dL
   launch_vjp_contacts(st, s->nc, s->cur_vid, s->cur_frame, s->d_Kc, s->d_kmu, z, h2, dL_dqbar,
                       s->P1(), grad3, nullptr);
   launch_vjp_tets(st, s->nt, s->d_tets, s->d_Bt, s->d_vol, s->d_lmu, s->d_llam, s->d_E, s->d_nu, h2,
-                  s->cur_q, z, dE_tet, dnu_tet, s->P2(), grad3);
+                  s->cur_q, z, dE_tet, dnu_tet, s->P2(), grad3, s->material);
   HIPCHK(hipGetLastError());
   return ADJ_OK;
 }
@@ -1309,7 +1311,7 @@ static adj_status fwd_eval(adj_scene* s, hipStream_t st, const double* qbar, con
   launch_add_vec(st, n3, qbar, u_dev, 1.0, s->d_qcur);
   HIPCHK(hipMemsetAsync(s->d_err + 1, 0, sizeof(int), st));
   launch_tet_force(st, s->nt, s->d_tets, s->d_Bt, s->d_vol, s->d_lmu, s->d_llam, h2, s->d_qcur, s->d_force,
-                   s->d_err);
+                   s->d_err, s->material);
   launch_gather_force(st, s->nv, s->d_vptr, s->d_vcode, s->d_force, s->d_mass, u_dev, s->d_utilde, s->d_rq);
   std::vector<double> uc(3 * (size_t)C.n);
   if (C.n) {
@@ -1368,7 +1370,7 @@ static adj_status fwd_newton(adj_scene* s, hipStream_t st, const double* qbar, F
     // Newton matrix: elastic blocks at q = qbar + u, contact blocks at the iterate
     launch_add_vec(st, n3, qbar, s->d_fu, 1.0, s->d_qcur);
     launch_tet_blocks(st, s->nt, s->d_tets, s->d_Bt, s->d_vol, s->d_lmu, s->d_llam, h2, s->d_qcur,
-                      s->d_tetblk, s->d_err);
+                      s->d_tetblk, s->d_err, s->material);
     launch_assemble(st, s->nnzb, s->d_slot_ptr, s->d_slot_code, s->d_tetblk, s->d_row_of_slot, s->d_col,
                     s->d_mass, s->d_val);
     for (int c = 0; c < nc; ++c) {

@@ -162,6 +162,11 @@ adj_status build_host_scene(const adj_scene_desc* d, HostScene& s, std::string& 
       err = "tet references a vertex out of range";
       return ADJ_E_ARG;
     }
+  if (d->material < 0 || d->material > 2) {
+    err = "scene_desc: material must be 0 (Neo-Hookean), 1 (ARAP) or 2 (co-rotational)";
+    return ADJ_E_ARG;
+  }
+  s.material = d->material;
   if (d->n_bindings < 0 || (d->n_bindings > 0 && (!d->binding_vid || !d->binding_E))) {
     err = "scene_desc: binding arrays missing";
     return ADJ_E_ARG;

@@ -32,6 +32,7 @@ struct HostScene {
   // bilateral bindings: vertex and compliance per binding
   std::vector<int32_t> bvid;
   std::vector<double> bE;
+  int material = 0;            // adj_material
   // Block pattern of Acal: rows = vertices, sorted columns, diagonal included.
   std::vector<int32_t> rowptr, col, diag_slot, row_of_slot;
   // Element-to-entry map: contributions to each block slot, ordered by

@@ -42,7 +42,8 @@ __global__ void __launch_bounds__(128) k_tet_blocks(int nt, const int* __restric
                                                     const double* __restrict__ lmu,
                                                     const double* __restrict__ llam, double h2,
                                                     const double* __restrict__ q,
-                                                    double* __restrict__ out, int* __restrict__ err) {
+                                                    double* __restrict__ out, int* __restrict__ err,
+                                                    int model) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= nt) return;
   double x[4][3], B[4][3];
@@ -59,10 +60,9 @@ __global__ void __launch_bounds__(128) k_tet_blocks(int nt, const int* __restric
   double U[3][3], s[3], V[3][3];
   svd3(F, U, s, V);
   NHLocal L;
-  nh_theta(s, mu, lam, L);
-  double W[3][3], M[3][3], N[3][3];
-  nh_W(L, mu, lam, W);
-  nh_MN(L, s, mu, lam, M, N);
+  double th[3], W[3][3], qd[3][3], M[3][3], N[3][3];
+  local_projection(model, s, mu, lam, th, W, qd, L);
+  local_MN(th, s, qd, M, N);
   double BV[4][3];
 #pragma unroll
   for (int k = 0; k < 4; ++k)
@@ -161,7 +161,7 @@ __global__ void __launch_bounds__(256) k_vjp_tets(int nt, const int* __restrict_
                                                   const double* __restrict__ z,
                                                   double* __restrict__ dE_tet,
                                                   double* __restrict__ dnu_tet,
-                                                  double* __restrict__ partial) {
+                                                  double* __restrict__ partial, int model) {
   __shared__ double lds[32];
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   double gE = 0.0, gnu = 0.0;
@@ -180,15 +180,9 @@ __global__ void __launch_bounds__(256) k_vjp_tets(int nt, const int* __restrict_
     double U[3][3], s[3], V[3][3];
     svd3(F, U, s, V);
     NHLocal L;
-    nh_theta(s, mu, lam, L);
-    double gmu[3], glam[3], dmu[3], dlam[3];
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      gmu[i] = -(3.0 * L.th[i] - 2.0 * s[i] - L.u[i]);
-      glam[i] = -(L.logJ * L.u[i]);
-    }
-    sm_solve(L.Dd, L.u, lam, gmu, dmu);
-    sm_solve(L.Dd, L.u, lam, glam, dlam);
+    double th[3], W[3][3], qd[3][3], dmu[3], dlam[3];
+    local_projection(model, s, mu, lam, th, W, qd, L);
+    local_param_derivs(model, s, th, mu, lam, L, dmu, dlam);
     // (G z) . vec(U Diag(d) V^T) = sum_i d_i (U^T Fz V)_ii ; (G z).(p - G q) = Fz : (P - F)
     double zmu = 0.0, zlam = 0.0, zp = 0.0;
 #pragma unroll
@@ -200,7 +194,7 @@ __global__ void __launch_bounds__(256) k_vjp_tets(int nt, const int* __restrict_
         for (int c = 0; c < 3; ++c) xi += U[r][i] * Fz[r][c] * V[c][i];
       zmu += dmu[i] * xi;
       zlam += dlam[i] * xi;
-      zp += L.th[i] * xi;  // Fz : P
+      zp += th[i] * xi;  // Fz : P
     }
     double zf = 0.0;
 #pragma unroll
@@ -244,8 +238,8 @@ void launch_add_partials(hipStream_t st, const double* partial, int nb, int k, d
 
 void launch_tet_blocks(hipStream_t st, int nt, const int* tets, const double* Bt, const double* vol,
                        const double* lmu, const double* llam, double h2, const double* q, double* out,
-                       int* err) {
-  k_tet_blocks<<<(nt + 127) / 128, 128, 0, st>>>(nt, tets, Bt, vol, lmu, llam, h2, q, out, err);
+                       int* err, int model) {
+  k_tet_blocks<<<(nt + 127) / 128, 128, 0, st>>>(nt, tets, Bt, vol, lmu, llam, h2, q, out, err, model);
 }
 
 void launch_assemble(hipStream_t st, int nnzb, const int* slot_ptr, const int* slot_code,
@@ -258,9 +252,10 @@ void launch_assemble(hipStream_t st, int nnzb, const int* slot_ptr, const int* s
 void launch_vjp_tets(hipStream_t st, int nt, const int* tets, const double* Bt, const double* vol,
                      const double* lmu, const double* llam, const double* Ev, const double* nuv,
                      double h2, const double* q, const double* z, double* dE_tet, double* dnu_tet,
-                     double* partial, double* grad) {
+                     double* partial, double* grad, int model) {
   const int nb = (nt + 255) / 256;
-  k_vjp_tets<<<nb, 256, 0, st>>>(nt, tets, Bt, vol, lmu, llam, Ev, nuv, h2, q, z, dE_tet, dnu_tet, partial);
+  k_vjp_tets<<<nb, 256, 0, st>>>(nt, tets, Bt, vol, lmu, llam, Ev, nuv, h2, q, z, dE_tet, dnu_tet, partial,
+                                 model);
   if (grad) launch_add_partials(st, partial, nb, 2, grad);
 }
 

@@ -64,7 +64,7 @@ __global__ void __launch_bounds__(128) k_tet_force(int nt, const int* __restrict
                                                    const double* __restrict__ lmu,
                                                    const double* __restrict__ llam, double h2,
                                                    const double* __restrict__ q, double* __restrict__ out,
-                                                   int* __restrict__ err) {
+                                                   int* __restrict__ err, int model) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= nt) return;
   double x[4][3], B[4][3];
@@ -87,14 +87,14 @@ __global__ void __launch_bounds__(128) k_tet_force(int nt, const int* __restrict
   const double mu = lmu[t], lam = llam[t];
   double U[3][3], s[3], V[3][3];
   svd3(F, U, s, V);
-  NHLocal L;
-  nh_theta(s, mu, lam, L);
+  double th[3];
+  local_theta(model, s, mu, lam, th);
   double Dm[3][3];
 #pragma unroll
   for (int r = 0; r < 3; ++r)
 #pragma unroll
     for (int c = 0; c < 3; ++c)
-      Dm[r][c] = F[r][c] - (U[r][0] * L.th[0] * V[c][0] + U[r][1] * L.th[1] * V[c][1] + U[r][2] * L.th[2] * V[c][2]);
+      Dm[r][c] = F[r][c] - (U[r][0] * th[0] * V[c][0] + U[r][1] * th[1] * V[c][1] + U[r][2] * th[2] * V[c][2]);
   const double sc = h2 * 2.0 * mu * vol[t];
 #pragma unroll
   for (int k = 0; k < 4; ++k)
@@ -210,8 +210,9 @@ void launch_scale_vec(hipStream_t st, long long n, const double* a, double alpha
 }
 
 void launch_tet_force(hipStream_t st, int nt, const int* tets, const double* Bt, const double* vol,
-                      const double* lmu, const double* llam, double h2, const double* q, double* out, int* err) {
-  k_tet_force<<<(nt + 127) / 128, 128, 0, st>>>(nt, tets, Bt, vol, lmu, llam, h2, q, out, err);
+                      const double* lmu, const double* llam, double h2, const double* q, double* out, int* err,
+                      int model) {
+  k_tet_force<<<(nt + 127) / 128, 128, 0, st>>>(nt, tets, Bt, vol, lmu, llam, h2, q, out, err, model);
 }
 
 void launch_gather_force(hipStream_t st, int nv, const int* vptr, const int* vcode, const double* force,

@@ -1,5 +1,6 @@
-// Per-element Neo-Hookean local projection and its SVD quantities, in
-// registers (Sec. 5.3; App. B.0-B.4).  Used by the Jacobian/assembly kernel,
+// Per-element local projection (Neo-Hookean, as-rigid-as-possible,
+// co-rotational) and its SVD quantities, in registers (Sec. 5.3;
+// App. B.0-B.4).  Used by the Jacobian/assembly kernel,
 // the gradient kernel and the forward residual kernel.
 #pragma once
 
@@ -161,11 +162,67 @@ __device__ __forceinline__ void nh_W(const NHLocal& L, double mu, double lam, do
       W[i][j] = 2.0 * mu * (((i == j) ? 1.0 / L.Dd[i] : 0.0) - lam * a[i] * a[j] / L.den);
 }
 
-// M_ij, N_ij with the cancellation-free divided difference
-// q_ij = (theta_i - theta_j)/(sigma_i - sigma_j) = 2mu/(3mu + (mu - lam log J)/(theta_i theta_j)),
-// exact at the root and equal to W_ii - W_ij when sigma_i = sigma_j (App. B.4).
-__device__ __forceinline__ void nh_MN(const NHLocal& L, const double s[3], double mu, double lam,
-                                      double M[3][3], double N[3][3]) {
+// ---- material models of the local step (App. B.2) ----
+// 0 Neo-Hookean (above), 1 as-rigid-as-possible (theta = 1: the projection is
+// the rotation of the polar decomposition, W = 0), 2 co-rotational (zeta =
+// mu |theta - 1|^2 + lam/2 (sum(theta - 1))^2, so the optimality condition is
+// linear: (4 mu I + lam 1 1^T)(theta - 1) = 2 mu (sigma - 1) and W is the
+// constant 2 mu (4 mu I + lam 1 1^T)^{-1}).
+enum : int { MAT_NEO_HOOKEAN = 0, MAT_ARAP = 1, MAT_COROT = 2 };
+
+// x = (4 mu I + lam 1 1^T)^{-1} b by Sherman-Morrison
+__device__ __forceinline__ void corot_solve(double mu, double lam, const double b[3], double x[3]) {
+  const double f = lam * (b[0] + b[1] + b[2]) / (4.0 * mu + 3.0 * lam);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) x[i] = (b[i] - f) / (4.0 * mu);
+}
+
+// Singular values theta of the projection, the singular-value Jacobian W and
+// the off-diagonal divided differences q_ij = (theta_i - theta_j)/(sigma_i -
+// sigma_j) in their cancellation-free forms (NH: q_ij from g_i - g_j = 0;
+// ARAP: 0; co-rot: 1/2).  For NH, L receives the Newton record (for the
+// parameter derivatives).
+__device__ __forceinline__ void local_projection(int model, const double s[3], double mu, double lam,
+                                                 double th[3], double W[3][3], double qd[3][3], NHLocal& L) {
+  if (model == MAT_ARAP) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      th[i] = 1.0;
+#pragma unroll
+      for (int j = 0; j < 3; ++j) W[i][j] = qd[i][j] = 0.0;
+    }
+    return;
+  }
+  if (model == MAT_COROT) {
+    double b[3] = {2.0 * mu * (s[0] - 1.0), 2.0 * mu * (s[1] - 1.0), 2.0 * mu * (s[2] - 1.0)}, d[3];
+    corot_solve(mu, lam, b, d);
+    const double cw = lam / (4.0 * mu + 3.0 * lam);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      th[i] = 1.0 + d[i];
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        W[i][j] = 0.5 * (((i == j) ? 1.0 : 0.0) - cw);
+        qd[i][j] = 0.5;
+      }
+    }
+    return;
+  }
+  nh_theta(s, mu, lam, L);
+  nh_W(L, mu, lam, W);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    th[i] = L.th[i];
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      qd[i][j] = 2.0 * mu / (3.0 * mu + (mu - lam * L.logJ) / (L.th[i] * L.th[j]));
+  }
+}
+
+// M_ij = (q_ij + avg_ij)/2, N_ij = (q_ij - avg_ij)/2 with avg_ij = (theta_i +
+// theta_j)/(sigma_i + sigma_j), zero on the diagonal (App. B.0).
+__device__ __forceinline__ void local_MN(const double th[3], const double s[3], const double qd[3][3],
+                                         double M[3][3], double N[3][3]) {
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
@@ -174,12 +231,61 @@ __device__ __forceinline__ void nh_MN(const NHLocal& L, const double s[3], doubl
         M[i][j] = 0.0;
         N[i][j] = 0.0;
       } else {
-        double q = 2.0 * mu / (3.0 * mu + (mu - lam * L.logJ) / (L.th[i] * L.th[j]));
-        double avg = (L.th[i] + L.th[j]) / (s[i] + s[j]);
-        M[i][j] = 0.5 * (q + avg);
-        N[i][j] = 0.5 * (q - avg);
+        const double avg = (th[i] + th[j]) / (s[i] + s[j]);
+        M[i][j] = 0.5 * (qd[i][j] + avg);
+        N[i][j] = 0.5 * (qd[i][j] - avg);
       }
     }
+}
+
+// dtheta/dmu and dtheta/dlam at fixed sigma: -(dg/dtheta)^{-1} dg/dmu and
+// -(dg/dtheta)^{-1} dg/dlam (App. B.3), with g the optimality condition of
+// the model (ARAP: theta does not depend on the parameters).
+__device__ __forceinline__ void local_param_derivs(int model, const double s[3], const double th[3], double mu,
+                                                   double lam, const NHLocal& L, double dmu[3], double dlam[3]) {
+  if (model == MAT_ARAP) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) dmu[i] = dlam[i] = 0.0;
+    return;
+  }
+  double gmu[3], glam[3];
+  if (model == MAT_COROT) {
+    const double tr = (th[0] - 1.0) + (th[1] - 1.0) + (th[2] - 1.0);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      gmu[i] = -2.0 * (2.0 * th[i] - s[i] - 1.0);
+      glam[i] = -tr;
+    }
+    corot_solve(mu, lam, gmu, dmu);
+    corot_solve(mu, lam, glam, dlam);
+    return;
+  }
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    gmu[i] = -(3.0 * L.th[i] - 2.0 * s[i] - L.u[i]);
+    glam[i] = -(L.logJ * L.u[i]);
+  }
+  sm_solve(L.Dd, L.u, lam, gmu, dmu);
+  sm_solve(L.Dd, L.u, lam, glam, dlam);
+}
+
+// theta alone (the forward residual)
+__device__ __forceinline__ void local_theta(int model, const double s[3], double mu, double lam, double th[3]) {
+  if (model == MAT_ARAP) {
+    th[0] = th[1] = th[2] = 1.0;
+    return;
+  }
+  if (model == MAT_COROT) {
+    double b[3] = {2.0 * mu * (s[0] - 1.0), 2.0 * mu * (s[1] - 1.0), 2.0 * mu * (s[2] - 1.0)}, d[3];
+    corot_solve(mu, lam, b, d);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) th[i] = 1.0 + d[i];
+    return;
+  }
+  NHLocal L;
+  nh_theta(s, mu, lam, L);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) th[i] = L.th[i];
 }
 
 }  // namespace adj

@@ -23,6 +23,8 @@ STATUS = {0: "ADJ_OK", -1: "ADJ_E_ARG", -2: "ADJ_E_SHAPE", -3: "ADJ_E_INVERTED",
 ADJ_FP64, ADJ_MIXED = 0, 1
 ADJ_AUTO, ADJ_GMRES, ADJ_PCG, ADJ_SEMI_IMPLICIT = 0, 1, 2, 3
 PRECOND_WOODBURY, PRECOND_SPARSE_INVERSE, PRECOND_JACOBI, PRECOND_POINT_JACOBI = 0, 1, 2, 3
+MAT_NEO_HOOKEAN, MAT_ARAP, MAT_COROT = 0, 1, 2
+MATERIAL_CODES = {"nh": MAT_NEO_HOOKEAN, "arap": MAT_ARAP, "corot": MAT_COROT}
 
 # names declared in include/adjoint.h
 EXPORTS = ("adj_scene_create", "adj_scene_destroy", "adjoint_setup", "adjoint_solve", "vjp_params",
@@ -48,7 +50,7 @@ class SceneDesc(C.Structure):
                 ("E", C.c_void_p), ("nu", C.c_void_p), ("per_tet_material", C.c_int32),
                 ("gravity", C.c_double * 3), ("n_planes", C.c_int32), ("planes", C.c_void_p),
                 ("contact_margin", C.c_double), ("n_bindings", C.c_int32), ("binding_vid", C.c_void_p),
-                ("binding_E", C.c_void_p)]
+                ("binding_E", C.c_void_p), ("material", C.c_int32)]
 
 
 class ContactState(C.Structure):
@@ -148,8 +150,9 @@ class Scene:
     """Owns an adj_scene (adj_scene_create / adj_scene_destroy)."""
 
     def __init__(self, rest, tets, density, h, eps, E, nu, gravity, planes, contact_margin,
-                 max_contacts, bindings=None):
-        """bindings: None or (vertex ids, compliances) of bilateral bindings."""
+                 max_contacts, bindings=None, material=0):
+        """bindings: None or (vertex ids, compliances) of bilateral bindings;
+        material: MAT_NEO_HOOKEAN, MAT_ARAP or MAT_COROT."""
         lib = load()
         self._keep = []
         rest = np.ascontiguousarray(rest, dtype=np.float64)
@@ -168,6 +171,7 @@ class Scene:
         d.n_planes = planes.shape[0]
         d.planes = planes.ctypes.data if planes.shape[0] else None
         d.contact_margin = float(contact_margin)
+        d.material = int(material)
         self.n_bindings = 0
         if bindings is not None:
             bvid = np.ascontiguousarray(bindings[0], dtype=np.int32)
@@ -353,8 +357,10 @@ class Batch:
     """Owns an adj_batch: several scenes solved together (adj_batch_create).
     specs: sequence of (rest, tets, E, nu); density, h, eps are shared."""
 
-    def __init__(self, specs, density, h, eps, gravity, planes, contact_margin, max_contacts, bindings=None):
-        """bindings: None, or per scene None / (vertex ids, compliances)."""
+    def __init__(self, specs, density, h, eps, gravity, planes, contact_margin, max_contacts, bindings=None,
+                 material=0):
+        """bindings: None, or per scene None / (vertex ids, compliances);
+        material: the scenes' common material model."""
         lib = load()
         self._keep = []
         n = len(specs)
@@ -377,6 +383,7 @@ class Batch:
             d.n_planes = planes.shape[0]
             d.planes = planes.ctypes.data if planes.shape[0] else None
             d.contact_margin = float(contact_margin)
+            d.material = int(material)
             if bindings is not None and bindings[k] is not None:
                 bvid = np.ascontiguousarray(bindings[k][0], dtype=np.int32)
                 bE = np.ascontiguousarray(np.broadcast_to(np.asarray(bindings[k][1], dtype=np.float64), bvid.shape))

@@ -35,7 +35,8 @@ class GpuSim:
         self.E = float(spec.E if E is None else E)
         self.nu = float(spec.nu if nu is None else nu)
         self.scene = native.Scene(spec.mesh.rest, spec.mesh.tets, spec.density, spec.h, spec.eps, self.E,
-                                  self.nu, spec.gravity, spec.planes, spec.contact_margin, self.max_contacts)
+                                  self.nu, spec.gravity, spec.planes, spec.contact_margin, self.max_contacts,
+                                  material=native.MATERIAL_CODES[getattr(spec, "material", "nh")])
         self.buf = native.ContactBuffers(self.max_contacts)
         self.dev = "cuda"
 

@@ -44,6 +44,8 @@ class SceneSpec:
     spheres: list = dataclasses.field(default_factory=list)
     # external force on vertices at step t (without gravity), (n_verts, 3)
     f_ext: Optional[Callable[[int], np.ndarray]] = None
+    # material model of the local projection: "nh", "arap" or "corot"
+    material: str = "nh"
 
     @property
     def n_verts(self) -> int:

@@ -16,7 +16,8 @@ def torch_cuda():
 def make_scene(spec, max_contacts):
     from paper_2603_16478_amd import native
     return native.Scene(spec.mesh.rest, spec.mesh.tets, spec.density, spec.h, spec.eps, spec.E, spec.nu,
-                        spec.gravity, spec.planes, spec.contact_margin, max_contacts)
+                        spec.gravity, spec.planes, spec.contact_margin, max_contacts,
+                        material=native.MATERIAL_CODES[spec.material])
 
 
 def contact_tensors(record, device="cuda"):
