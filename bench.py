@@ -19,7 +19,8 @@ precision and without the pipelining, one batch per step with a fixed
 right-hand side (FP64 and mixed; the roofline kernels are timed there),
 each scene solved alone (FP64 and mixed), the comparison preconditioners
 of the backward solve, the beam with its end face held by bilateral
-bindings (single scene, FP64), a large batch (the
+bindings (single scene, FP64), the as-rigid-as-possible and co-rotational
+local steps (single scene, FP64), a large batch (the
 twelve recorded scene-steps four times: 48 scenes per launch, FP64 and
 mixed, with the sparse-inverse product's bandwidth), the rooflines of the
 two largest kernels, the batched Gauss-Jordan step and the batched
@@ -540,6 +541,34 @@ def main():
     bound["vs_unbound_single_scene_fp64"] = bound["value"] / single["value"]
     bscene.close()
 
+    # ---- material models of the local step: the same single-scene solves
+    # with the as-rigid-as-possible and co-rotational projections ----
+    def run_material(code, nsteps, warm):
+        mscene = native.Scene(spec.mesh.rest, spec.mesh.tets, spec.density, spec.h, spec.eps, spec.E, spec.nu,
+                              spec.gravity, spec.planes, spec.contact_margin, max_c, material=code)
+        o = native.solve_opts(rtol=args.rtol, maxit=5000, restart=64)
+        its = []
+        t0m = time.perf_counter()
+        for i in range(warm + nsteps):
+            if i == warm:
+                torch.cuda.synchronize()
+                its.clear()
+                t0m = time.perf_counter()
+            t = dstates[i % len(dstates)]
+            native.adjoint_setup(mscene, t["cs"], t["q"], o)
+            inf = native.adjoint_solve(mscene, gq, gv, z, o)
+            native.vjp_params(mscene, z, gv, dqbar, dvbar, dfext, grad3)
+            its.append(inf.iters)
+        torch.cuda.synchronize()
+        dtm = time.perf_counter() - t0m
+        mscene.close()
+        return {"value": nsteps / dtm, "unit": "adjoint solves/s", "krylov_iters_mean": float(np.mean(its))}
+
+    materials = {"neo_hookean": {"value": single["value"], "unit": "adjoint solves/s",
+                                 "krylov_iters_mean": single["krylov_iters_mean"]},
+                 "arap": run_material(native.MAT_ARAP, args.steps, args.warmup),
+                 "corotational": run_material(native.MAT_COROT, args.steps, args.warmup)}
+
     abytes = s_product_bytes(uinfo)
     avg_ms = kms / max(launches, 1)
     achieved = abytes / (avg_ms * 1e-3) / 1e9 if launches else 0.0
@@ -625,6 +654,9 @@ def main():
                                                   "fixed-point iteration x <- x + A^-1 (b - Acal^T x), stopped "
                                                   "when its residual exceeds 1e6 |b|"},
         "large_batch": big,
+        "materials": materials | {"note": "single scene, FP64, GMRES(64) + Woodbury to 1e-8, the recorded beam "
+                                          "states with the local step of each model (the states were converged "
+                                          "with Neo-Hookean; the adjoint system is defined at any state)"},
         "bindings": bound | {"note": "single scene, FP64, the beam's 81 x = 0 face vertices bound to their rest "
                                      "positions (compliance 1e-6 m/N), GMRES(64) + Woodbury to 1e-8; setup + "
                                      "solve + VJP + binding VJP per recorded scene-step"},
