@@ -196,6 +196,76 @@ def eps_sweep_one(two_eps2, side, seconds):
                       "ms_per_step": 1e3 * dt / spec.steps}))
 
 
+def slab_leg(nsolve):
+    """The slab workload at full size (64x32x32 cells, 393,216 tets, 70,785
+    vertices, sphere of radius 0.3 x width): the adjoint at the seeded
+    deformed state with the 2,190 contacts of tests/golden/slab_contacts.npz
+    and seeded sticking contact values, timed `nsolve` times in FP64 and in
+    mixed precision (setup + solve + VJP), with the sparse-inverse product's
+    bandwidth.  Prints one JSON line."""
+    import torch
+
+    from paper_2603_16478_amd import native
+    from synth.configs import contact_values, perturbed_state, slab_scene
+
+    d = np.load(os.path.join(ROOT, "tests", "golden", "slab_contacts.npz"))
+    spec = slab_scene()
+    n = int(d["vid"].shape[0])
+    delta, lam = contact_values(n, spec.mu)
+    t0 = time.perf_counter()
+    scene = native.Scene(spec.mesh.rest, spec.mesh.tets, spec.density, spec.h, spec.eps, spec.E, spec.nu,
+                         spec.gravity, spec.planes, spec.contact_margin, n)
+    t_build = time.perf_counter() - t0
+    info = scene.info()
+    print(f"slab scene built in {t_build:.1f} s (nnz(S) {info['nnz_S']})", file=sys.stderr, flush=True)
+    dev = "cuda"
+    tens = {"vid": torch.tensor(d["vid"].astype(np.int32), device=dev),
+            "fric": torch.tensor(d["fric"].astype(np.int32), device=dev),
+            "frame": torch.tensor(d["frame"].reshape(n, 9), dtype=torch.float64, device=dev),
+            "delta": torch.tensor(delta, dtype=torch.float64, device=dev),
+            "lam": torch.tensor(lam, dtype=torch.float64, device=dev)}
+    cs = native.make_contact_state(n, tens["vid"], tens["fric"], tens["frame"], tens["delta"], tens["lam"], spec.mu)
+    q = torch.tensor(perturbed_state(spec), device=dev)
+    gq = torch.tensor(spec.loss_dir, device=dev)
+    gv = torch.zeros_like(gq)
+    z = torch.zeros_like(gq)
+    dq, dv, df = torch.empty_like(gq), torch.empty_like(gq), torch.empty_like(gq)
+    grad3 = torch.zeros(3, dtype=torch.float64, device=dev)
+    legs = {}
+    sbytes = info["nnz_S"] * (8 + 4) + (spec.n_verts + 1) * 8 + 2 * 3 * spec.n_verts * 8
+    for name, prec in (("fp64", native.ADJ_FP64), ("mixed", native.ADJ_MIXED)):
+        o = native.solve_opts(rtol=1e-8, maxit=3000, restart=64, prec=prec, max_refine=8)
+        t1 = time.perf_counter()
+        native.adjoint_setup(scene, cs, q, o)  # warm-up; builds the Delassus matrix of this contact set
+        native.adjoint_solve(scene, gq, gv, z, o)
+        torch.cuda.synchronize()
+        t_first = time.perf_counter() - t1
+        its = []
+        native.profile_begin(scene, "S")
+        t2 = time.perf_counter()
+        for _ in range(nsolve):
+            native.adjoint_setup(scene, cs, q, o)
+            inf = native.adjoint_solve(scene, gq, gv, z, o)
+            native.vjp_params(scene, z, gv, dq, dv, df, grad3)
+            its.append(inf.iters)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t2
+        sms, sl = native.profile_end(scene)
+        gbs = sbytes / (sms / max(sl, 1) * 1e-3) / 1e9 if sl else None
+        legs[name] = {"value": nsolve / dt, "unit": "adjoint solves/s", "ms_per_solve": 1e3 * dt / nsolve,
+                      "krylov_iters_mean": float(np.mean(its)), "first_solve_s_incl_delassus": t_first,
+                      "s_product_GB/s": gbs, "s_product_frac": gbs / HBM_PEAK_GBPS if gbs else None}
+        print(f"slab adjoint {name}: {legs[name]['ms_per_solve']:.1f} ms per solve, iterations "
+              f"{legs[name]['krylov_iters_mean']:.1f}, S product {gbs:.0f} GB/s, first solve {t_first:.2f} s",
+              file=sys.stderr, flush=True)
+    legs["mixed"]["speedup_vs_fp64"] = legs["mixed"]["value"] / legs["fp64"]["value"]
+    scene.close()
+    print(json.dumps({"workload": "slab 64x32x32 cells (393,216 tets, 70,785 vertices), sphere indenter; seeded "
+                                  "deformed state, 2,190 detected contacts with seeded sticking values",
+                      "scene_build_s": t_build, "nnz_S": info["nnz_S"], "contacts": n, "adjoint": legs,
+                      "s_product_bytes": sbytes}))
+
+
 def eps_sweep(seconds):
     """The smoothing sweep: the sliding and the sticking cube (friction
     tan(10 deg) -/+ 4e-4) at each 2 eps^2, one child process per run, all
@@ -238,6 +308,9 @@ def main():
     ap.add_argument("--eps-sweep", type=float, default=0.0, metavar="SECONDS",
                     help="instead of the benchmark: the smoothing sweep on the slope cube, SECONDS of simulated "
                          "time per run on the GPU forward step")
+    ap.add_argument("--slab", type=int, default=0, metavar="SOLVES",
+                    help="instead of the benchmark: the full-size slab adjoint, SOLVES timed solves in FP64 and in "
+                         "mixed precision")
     ap.add_argument("--eps-sweep-one", nargs=3, metavar=("TWO_EPS2", "SIDE", "SECONDS"), help=argparse.SUPPRESS)
     ap.add_argument("--big-batch", type=int, default=4,
                     help="copies of the twelve recorded scene-steps in the large-batch leg (0: skip)")
@@ -247,6 +320,9 @@ def main():
                           "n_gpus": args.gpus}))
         sys.exit(2)
 
+    if args.slab > 0:
+        slab_leg(args.slab)
+        return
     if args.eps_sweep_one:
         eps_sweep_one(float(args.eps_sweep_one[0]), args.eps_sweep_one[1], float(args.eps_sweep_one[2]))
         return

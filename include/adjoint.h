@@ -129,12 +129,18 @@ typedef enum { ADJ_AUTO = 0, ADJ_GMRES = 1, ADJ_PCG = 2, ADJ_SEMI_IMPLICIT = 3 }
  * the Krylov method); ADJ_PRECOND_JACOBI: the inverses of the 3x3 diagonal
  * blocks of Acal^T; ADJ_PRECOND_POINT_JACOBI: the inverse of its diagonal.
  * These are the comparison preconditioners of the paper's backward-solver
- * study (Sec. 6.2); all give the same solution to the tolerance. */
+ * study (Sec. 6.2); all give the same solution to the tolerance.
+ * ADJ_PRECOND_WOODBURY_NO_Z: the Woodbury preconditioner with its correction
+ * A^{-1} H^T t applied by two more sparse-inverse products per apply instead
+ * of the cached dense Z = A^{-1} H^T.  ADJ_PRECOND_WOODBURY switches to this
+ * form by itself when forming Z would cost more than 2e10 multiply-adds
+ * (nnz(S) x contact vertices; the slab workload). */
 typedef enum {
   ADJ_PRECOND_WOODBURY = 0,
   ADJ_PRECOND_SPARSE_INVERSE = 1,
   ADJ_PRECOND_JACOBI = 2,
-  ADJ_PRECOND_POINT_JACOBI = 3
+  ADJ_PRECOND_POINT_JACOBI = 3,
+  ADJ_PRECOND_WOODBURY_NO_Z = 4
 } adj_precond;
 
 typedef struct {
@@ -224,6 +230,16 @@ adj_status adj_forward_stats(const adj_scene* scene, double* out);
 
 /* Forget the warm start of the contact multipliers. */
 adj_status adj_forward_reset(adj_scene* scene);
+
+/* Kinematic sphere colliders of the next sim_forward_step calls (the slab
+ * workload's indenter): n spheres, old_pose and new_pose host [n][4] =
+ * (centre x, y, z, radius) at the start and the end of the step.  A vertex
+ * meets sphere s on the plane with normal n = (qbar_v - c_old)/|qbar_v -
+ * c_old| and offset n . c_new + r_new, frozen for the step (Sec. 5.2); the
+ * tangential motion of the sphere enters the friction displacement.  Spheres
+ * count after the planes as colliders (at most 15 together).  n = 0 removes
+ * them.  Copies the poses to the device (synchronously). */
+adj_status adj_set_spheres(adj_scene* scene, int32_t n, const double* old_pose, const double* new_pose);
 
 /* Scene sizes and host-side statistics: out[0] n_verts, out[1] n_tets,
  * out[2] nnz blocks of Acal, out[3] nnz(L), out[4] nnz(S), out[5]

@@ -43,6 +43,8 @@ void launch_vjp_contacts(hipStream_t, int, const int*, const double*, const doub
 void launch_vjp_vectors(hipStream_t, int, const double*, const double*, const double*, double, double*,
                         double*, double*);
 void launch_fill_zero(hipStream_t, size_t, double*);
+void launch_scatter_ht(hipStream_t, int, const int*, const int*, const int*, const int*, const double*,
+                       const double*, const GmresState*, double*);
 void launch_delassus(hipStream_t, int, int, const int*, const long long*, const int*, const double*,
                      double*, double*, double*, double*);
 int delassus_slices(int, int);
@@ -91,7 +93,8 @@ void launch_gm_finish(hipStream_t, long long, const GmresState*, const double*, 
 void launch_axpy(hipStream_t, long long, double, const double*, double*);
 void launch_fwd_predict(hipStream_t, int, const double*, const double*, const double*, const double*, double,
                         const double*, double*, double*);
-void launch_fwd_detect(hipStream_t, int, const double*, int, const double*, double, int*);
+void launch_fwd_detect(hipStream_t, int, const double*, const double*, int, const double*, int, const double*,
+                       const double*, double, int*);
 void launch_add_vec(hipStream_t, long long, const double*, const double*, double, double*);
 void launch_scale_vec(hipStream_t, long long, const double*, double, double*);
 void launch_tet_force(hipStream_t, int, const int*, const double*, const double*, const double*,
@@ -173,7 +176,10 @@ struct adj_scene {
   bool symmetric = true;      // Acal^T symmetric: no frictional contact, or mu = 0  // D computed on FP32 matrix cores (mixed precision)
   double* d_Pws = nullptr;    // K-slice partials of the Delassus product
   size_t cap_pws = 0;
-  size_t cap_ncv = 0, cap_m = 0;
+  size_t cap_ncv = 0, cap_m = 0, cap_z = 0;
+  long long nnzS = 0;   // entries of S
+  size_t lds_max = 0;   // bytes of LDS one block may use on the scene's device
+  long long mixed_fallbacks = 0;  // mixed solves finished in FP64 (refinement stalled)
   double *d_Y = nullptr, *d_D = nullptr, *d_Z = nullptr, *d_C = nullptr, *d_P = nullptr,
          *d_colbuf = nullptr, *d_tvec = nullptr;
   // current step
@@ -202,6 +208,15 @@ struct adj_scene {
   bool mixed_ready = false;
   // forward step
   double* d_planes = nullptr;
+  // kinematic spheres of the next forward step: [old pose][new pose], each
+  // n_spheres x (centre, radius), host copy and device copy
+  // Woodbury correction through the cached Z (use_z) or through S^T S with
+  // the scatter buffer d_wz and the product d_wz2 ([3 n_v] each)
+  bool use_z = true, z_built = false;
+  double *d_wz = nullptr, *d_wz2 = nullptr;
+  int n_spheres = 0, sph_cap = 0;  // sph_cap: spheres d_sph has room for
+  std::vector<double> sph;
+  double* d_sph = nullptr;
   int *d_vptr = nullptr, *d_vcode = nullptr, *d_mask = nullptr, *d_fvid = nullptr;
   double *d_force = nullptr, *d_utilde = nullptr, *d_qtilde = nullptr, *d_fu = nullptr, *d_du = nullptr,
          *d_ut = nullptr, *d_qcur = nullptr, *d_rq = nullptr, *d_rhs = nullptr, *d_cvec = nullptr,
@@ -265,7 +280,8 @@ static void free_scene(adj_scene* s) {
                   s->d_cs,       s->d_sn,     s->d_g,     s->d_hbuf,        s->d_coef,
                   s->d_partial,  s->d_counter, s->d_state, s->d_t1,         s->d_u,
                   s->d_y,        s->d_r,      s->d_b,     s->d_dz,          s->d_xt,
-                  s->d_Stasks,   s->d_STtasks, s->d_planes,  s->d_vptr,   s->d_vcode,
+                  s->d_Stasks,   s->d_STtasks, s->d_planes,  s->d_vptr,   s->d_vcode, s->d_sph,
+                  s->d_wz,       s->d_wz2,
                   s->d_mask,     s->d_fvid,   s->d_force, s->d_utilde,      s->d_qtilde,
                   s->d_fu,       s->d_du,     s->d_ut,    s->d_qcur,        s->d_rq,
                   s->d_rhs,      s->d_cvec,   s->d_cu,    s->d_norms,       s->d_Sx32,
@@ -320,6 +336,16 @@ static adj_status scene_create(const adj_scene_desc* desc, int32_t max_contacts,
   s->n3 = 3LL * h.nv;
   s->max_contacts = max_contacts;
   s->restart = 64;
+  s->nnzS = (long long)h.Sj.size();
+  {
+    int dev = 0, lds = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || lds <= 0) {
+      free_scene(s);
+      return fail(ADJ_E_DEVICE, "cannot query the device's LDS size");
+    }
+    s->lds_max = (size_t)lds;
+  }
 #define UP(dst, src)                                   \
   do {                                                 \
     hipError_t e_ = upload(&dst, src);                 \
@@ -484,8 +510,13 @@ static void drop_chunk_graphs(adj_scene* s) {
 }
 
 // Delassus matrix / Z (rebuilt only when the contact vertex set changes).
+// Forming Z = S^T (S E) costs nnz(S) x n_cv multiply-adds; above this the
+// Woodbury correction goes through S^T S at every apply instead.
+static const double kZBudget = 2e10;
+
 static adj_status contact_layout(adj_scene* s, hipStream_t st, int nc, const std::vector<int>& vid,
-                                 const std::vector<int>& fric, bool reuse, bool delassus = true) {
+                                 const std::vector<int>& fric, bool reuse, bool delassus = true,
+                                 bool force_no_z = false) {
   drop_chunk_graphs(s);  // captured chunks hold the contact layout
   std::vector<int> cv, cv_ptr, cmap(nc), row_c, row_i, c_row0(nc), c_nrow(nc);
   for (int c = 0; c < nc; ++c) {
@@ -519,21 +550,36 @@ static adj_status contact_layout(adj_scene* s, hipStream_t st, int nc, const std
     HIPCHK(hipStreamSynchronize(st));  // host vectors go out of scope
   }
   s->delassus_rebuilt = 0;
-  if (nc && delassus && !(reuse && s->delassus_valid && cv == s->cv_cached)) {
+  const bool use_z = !force_no_z && (double)s->nnzS * (double)ncv <= kZBudget;
+  if (nc && delassus && !(reuse && s->delassus_valid && cv == s->cv_cached && (s->z_built || !use_z))) {
     adj_status a;
-    size_t capY = s->cap_ncv ? (size_t)s->nv * s->cap_ncv : 0, capD = s->cap_ncv * s->cap_ncv, capZ = capY;
-    if ((size_t)ncv > s->cap_ncv) capY = capZ = capD = 0;
+    // the Woodbury kernels stage m (gather) and 3 n_cv (Z correction)
+    // doubles in LDS
+    if ((size_t)8 * m > s->lds_max || (use_z && (size_t)24 * ncv > s->lds_max))
+      return fail(ADJ_E_SHAPE, "capacitance or contact-vertex count beyond the LDS staging of the Woodbury kernels");
+    size_t capY = s->cap_ncv ? (size_t)s->nv * s->cap_ncv : 0, capD = s->cap_ncv * s->cap_ncv;
+    size_t capZ = s->cap_z;
+    if ((size_t)ncv > s->cap_ncv) capY = capD = 0;
     if ((a = grow(&s->d_Y, &capY, (size_t)s->nv * ncv)) != ADJ_OK) return a;
-    if ((a = grow(&s->d_Z, &capZ, (size_t)s->nv * ncv)) != ADJ_OK) return a;
     if ((a = grow(&s->d_D, &capD, (size_t)ncv * ncv)) != ADJ_OK) return a;
+    if (use_z && (a = grow(&s->d_Z, &capZ, (size_t)s->nv * ncv)) != ADJ_OK) return a;
+    s->cap_z = capZ;
     s->cap_ncv = std::max(s->cap_ncv, (size_t)ncv);
+    if (!use_z) {
+      size_t cw = s->d_wz ? (size_t)s->n3 : 0, cw2 = cw;
+      if ((a = grow(&s->d_wz, &cw, (size_t)s->n3)) != ADJ_OK) return a;
+      if ((a = grow(&s->d_wz2, &cw2, (size_t)s->n3)) != ADJ_OK) return a;
+    }
     const int ks = delassus_slices(s->nv, ncv);
     if (ks > 1 && (a = grow(&s->d_Pws, &s->cap_pws, (size_t)ks * ncv * ncv)) != ADJ_OK) return a;
-    launch_delassus(st, s->nv, ncv, s->d_cv, s->d_STp, s->d_STj, s->d_STx, s->d_Y, s->d_D, s->d_Z, s->d_Pws);
+    launch_delassus(st, s->nv, ncv, s->d_cv, s->d_STp, s->d_STj, s->d_STx, s->d_Y, s->d_D, use_z ? s->d_Z : nullptr,
+                    s->d_Pws);
     s->cv_cached = cv;
     s->delassus_valid = true;
     s->delassus_rebuilt = 1;
+    s->z_built = use_z;
   }
+  s->use_z = use_z;
   return ADJ_OK;
 }
 
@@ -614,8 +660,10 @@ extern "C" adj_status adjoint_setup(adj_scene* s, const adj_contact_state* cst, 
   launch_binding_fold(st, s->nb, s->d_bvid, s->d_bE, h2, s->d_diag_slot, s->d_val);
   // a4: Delassus (cached per contact vertex set), capacitance, its inverse;
   // skipped when the solves will use a comparison preconditioner
-  const bool woodbury = !opts || opts->precond == ADJ_PRECOND_WOODBURY;
-  adj_status a = contact_layout(s, st, nc, vid, fric, opts ? opts->reuse_delassus != 0 : true, woodbury);
+  const bool woodbury =
+      !opts || opts->precond == ADJ_PRECOND_WOODBURY || opts->precond == ADJ_PRECOND_WOODBURY_NO_Z;
+  adj_status a = contact_layout(s, st, nc, vid, fric, opts ? opts->reuse_delassus != 0 : true, woodbury,
+                                opts && opts->precond == ADJ_PRECOND_WOODBURY_NO_Z);
   if (a != ADJ_OK) return a;
   if (woodbury && (a = build_capacitance(s, st, cst->mu, 1)) != ADJ_OK) return a;
   s->woodbury_ready = woodbury;
@@ -658,7 +706,8 @@ static void apply_precond(adj_scene* s, hipStream_t st, const double* x, long lo
       launch_block_jacobi(st, s->nv, s->d_diag_slot, s->d_val, x, stride, scale, state, point, out);
     return;
   }
-  const bool woodbury = s->nc > 0 && s->precond == ADJ_PRECOND_WOODBURY;
+  const bool woodbury =
+      s->nc > 0 && (s->precond == ADJ_PRECOND_WOODBURY || s->precond == ADJ_PRECOND_WOODBURY_NO_Z);
   {
     ProfScope p(s, 0, st);
     if (f32)
@@ -684,11 +733,24 @@ static void apply_precond(adj_scene* s, hipStream_t st, const double* x, long lo
     launch_wb_gather(st, s->m, s->mp, s->d_row_c, s->d_row_i, s->cur_vid, s->d_Q, s->d_X, s->d_u, state,
                      s->d_tvec);
   }
-  {
-    ProfScope p(s, 3, st);
+  ProfScope p(s, 3, st);
+  if (s->use_z) {
     launch_wb_correct(st, s->nv, s->ncv, s->d_cv_ptr, s->d_c_row0, s->d_c_nrow, s->d_Q, s->d_tvec, s->d_Z, h2,
                       s->d_u, state, out);
+    return;
   }
+  // out = u - h^2 S^T S (H^T t'): scatter the contact-space vector, two
+  // sparse-inverse products, one update.  These products stay FP64 in the
+  // mixed mode as Z does: for stiff contacts the correction cancels A^{-1} r
+  // almost exactly, and its rounding would be amplified by the contact-to-
+  // elastic stiffness ratio.
+  launch_fill_zero(st, (size_t)s->n3, s->d_wz);
+  launch_scatter_ht(st, s->ncv, s->d_cv, s->d_cv_ptr, s->d_c_row0, s->d_c_nrow, s->d_Q, s->d_tvec, state, s->d_wz);
+  launch_spmv_tasks(st, s->nS_tasks, (const int4*)s->d_Stasks, s->d_Sp, s->d_Sj, s->d_Sx, s->d_wz, 0, nullptr, state,
+                    s->d_t1);
+  launch_spmv_tasks(st, s->nST_tasks, (const int4*)s->d_STtasks, s->d_STp, s->d_STj, s->d_STx, s->d_t1, 0, nullptr,
+                    state, s->d_wz2);
+  launch_add_vec(st, s->n3, s->d_u, s->d_wz2, -h2, out);
 }
 
 static void bsr(adj_scene* s, hipStream_t st, const double* x, double* outbase, long long stride,
@@ -975,9 +1037,11 @@ extern "C" adj_status adjoint_solve(adj_scene* s, const double* dL_dq, const dou
   if (opts->method == ADJ_SEMI_IMPLICIT && opts->prec != ADJ_FP64)
     return fail(ADJ_E_NOTIMPL, "the semi-implicit iteration runs in FP64");
   if (opts->precond != ADJ_PRECOND_WOODBURY && opts->precond != ADJ_PRECOND_SPARSE_INVERSE &&
-      opts->precond != ADJ_PRECOND_JACOBI && opts->precond != ADJ_PRECOND_POINT_JACOBI)
+      opts->precond != ADJ_PRECOND_JACOBI && opts->precond != ADJ_PRECOND_POINT_JACOBI &&
+      opts->precond != ADJ_PRECOND_WOODBURY_NO_Z)
     return fail(ADJ_E_ARG, "unknown preconditioner");
-  if (opts->precond == ADJ_PRECOND_WOODBURY && s->nc > 0 && !s->woodbury_ready)
+  if ((opts->precond == ADJ_PRECOND_WOODBURY || opts->precond == ADJ_PRECOND_WOODBURY_NO_Z) && s->nc > 0 &&
+      !s->woodbury_ready)
     return fail(ADJ_E_ARG, "the last adjoint_setup skipped the Woodbury factors (it ran with another precond)");
   if (opts->precond != s->precond) {
     drop_chunk_graphs(s);  // captured chunks hold the preconditioner's launches
@@ -1026,15 +1090,40 @@ extern "C" adj_status adjoint_solve(adj_scene* s, const double* dL_dq, const dou
                             &rr, &cv, true)) != ADJ_OK)
         return a;
       total += it;
+      const double r_before = rnorm;
+      auto residual = [&]() -> adj_status {
+        // r = b - Acal^T z in FP64
+        bsr(s, st, z, s->d_fu, 0, nullptr, false);
+        launch_add_vec(st, n3, s->d_rhs, s->d_fu, -1.0, s->d_fu);
+        launch_norms(st, n3, s->d_fu, s->P3(), s->d_norms);
+        HIPCHK(hipMemcpyAsync(nb, s->d_norms, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        rnorm = std::sqrt(nb[0]);
+        relres = rnorm / bnorm;
+        return ADJ_OK;
+      };
       launch_axpy(st, n3, 1.0, s->d_du, z);
-      // r = b - Acal^T z in FP64
-      bsr(s, st, z, s->d_fu, 0, nullptr, false);
-      launch_add_vec(st, n3, s->d_rhs, s->d_fu, -1.0, s->d_fu);
-      launch_norms(st, n3, s->d_fu, s->P3(), s->d_norms);
-      HIPCHK(hipMemcpyAsync(nb, s->d_norms, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
-      HIPCHK(hipStreamSynchronize(st));
-      rnorm = std::sqrt(nb[0]);
-      relres = rnorm / bnorm;
+      if ((a = residual()) != ADJ_OK) return a;
+      if (!(rnorm < r_before)) {
+        // The FP32 inner solve did not reduce the residual (contacts so stiff
+        // that FP32 rounding of A^{-1} r is amplified past the correction):
+        // undo the pass and finish in FP64 from the last good iterate.
+        launch_axpy(st, n3, -1.0, s->d_du, z);
+        if ((a = residual()) != ADJ_OK) return a;
+        s->mixed_fallbacks++;
+        int it2 = 0;
+        double rr2 = 0.0;
+        bool cv2 = false;
+        if ((a = krylov_solve(s, st, use_pcg, s->d_fu, s->d_du, std::min(1.0, opts->rtol * bnorm / rnorm),
+                              std::max(1, opts->maxit - total), opts->restart, &it2, &rr2, &cv2, false)) != ADJ_OK)
+          return a;
+        total += it2;
+        launch_axpy(st, n3, 1.0, s->d_du, z);
+        if ((a = residual()) != ADJ_OK) return a;
+        ++refine;
+        converged = relres <= opts->rtol;
+        break;
+      }
       if (!std::isfinite(relres)) return fail(ADJ_E_SINGULAR, "non-finite residual in the refinement");
       converged = relres <= opts->rtol;
     }
@@ -1542,24 +1631,32 @@ extern "C" adj_status sim_forward_step(adj_scene* s, const double* qbar, const d
   const double h = s->hs.h;
   const long long n3 = s->n3;
   const int np = (int)(s->hs.planes.size() / 4);
-  if (np > 15) return fail(ADJ_E_ARG, "at most 15 planes");
+  const int ns = s->n_spheres;
+  if (np + ns > 15) return fail(ADJ_E_ARG, "at most 15 colliders (planes and spheres)");
   // prediction and candidates
   launch_fwd_predict(st, s->nv, qbar, vbar, f_ext, s->d_mass, h, s->hs.gravity, s->d_utilde, s->d_qtilde);
-  launch_fwd_detect(st, s->nv, s->d_qtilde, np, s->d_planes, s->hs.margin, s->d_mask);
+  launch_fwd_detect(st, s->nv, qbar, s->d_qtilde, np, s->d_planes, ns, s->d_sph, s->d_sph + 4 * ns, s->hs.margin,
+                    s->d_mask);
   std::vector<int> mask(s->nv);
   HIPCHK(hipMemcpyAsync(mask.data(), s->d_mask, s->nv * sizeof(int), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   FwdContacts C;
+  std::vector<int> sph_rows;  // contacts with a sphere: their frames follow below
   for (int vv = 0; vv < s->nv; ++vv)
-    for (int p = 0; p < np; ++p)
+    for (int p = 0; p < np + ns; ++p)
       if (mask[vv] & (1 << (2 * p))) {
         C.vid.push_back(vv);
         C.collider.push_back(p);
         C.fric.push_back((mask[vv] >> (2 * p + 1)) & 1);
-        double F[9];
-        tangent_frame(&s->hs.planes[4 * p], F);
+        double F[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+        if (p < np) {
+          tangent_frame(&s->hs.planes[4 * p], F);
+          C.d_n.push_back(s->hs.planes[4 * p + 3]);
+        } else {
+          sph_rows.push_back((int)C.vid.size() - 1);
+          C.d_n.push_back(0.0);
+        }
         C.frame.insert(C.frame.end(), F, F + 9);
-        C.d_n.push_back(s->hs.planes[4 * p + 3]);
         C.d_f.push_back(0.0);
         C.d_f.push_back(0.0);
         C.k.push_back(s->hs.As[s->hs.diag_slot[vv]] / (h * h));
@@ -1568,6 +1665,31 @@ extern "C" adj_status sim_forward_step(adj_scene* s, const double* qbar, const d
   const int nc = C.n;
   if (nc > s->max_contacts || nc > out->capacity)
     return fail(ADJ_E_SHAPE, "more contacts than max_contacts / the output capacity");
+  if (!sph_rows.empty()) {
+    // frames of the sphere contacts from qbar (the same expressions as the
+    // detection kernel, evaluated left to right)
+    std::vector<int> rows_v(sph_rows.size());
+    for (size_t i = 0; i < sph_rows.size(); ++i) rows_v[i] = C.vid[sph_rows[i]];
+    HIPCHK(hipMemcpyAsync(s->d_fvid, rows_v.data(), rows_v.size() * sizeof(int), hipMemcpyHostToDevice, st));
+    launch_gather_contact_rows(st, (int)rows_v.size(), s->d_fvid, qbar, s->d_cu);
+    std::vector<double> xs(3 * rows_v.size());
+    HIPCHK(hipMemcpyAsync(xs.data(), s->d_cu, xs.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    for (size_t i = 0; i < sph_rows.size(); ++i) {
+      const int c = sph_rows[i], sp = C.collider[c] - np;
+      const double* c0 = &s->sph[4 * sp];
+      const double* c1 = &s->sph[4 * (ns + sp)];
+      const double d0 = xs[3 * i] - c0[0], d1 = xs[3 * i + 1] - c0[1], d2 = xs[3 * i + 2] - c0[2];
+      const double nrm = std::sqrt((d0 * d0 + d1 * d1) + d2 * d2);
+      const double n[3] = {d0 / nrm, d1 / nrm, d2 / nrm};
+      double* F = &C.frame[9 * (size_t)c];
+      tangent_frame(n, F);
+      C.d_n[c] = ((n[0] * c1[0] + n[1] * c1[1]) + n[2] * c1[2]) + c1[3];
+      const double dc[3] = {c1[0] - c0[0], c1[1] - c0[1], c1[2] - c0[2]};
+      C.d_f[2 * c] = (F[3] * dc[0] + F[4] * dc[1]) + F[5] * dc[2];
+      C.d_f[2 * c + 1] = (F[6] * dc[0] + F[7] * dc[1]) + F[8] * dc[2];
+    }
+  }
   if (nc && (!out->vid || !out->fric || !out->frame || !out->delta || !out->lambda))
     return fail(ADJ_E_ARG, "contact output arrays missing");
   // gap at the start of the step, n . xbar - d_n
@@ -1669,6 +1791,29 @@ extern "C" adj_status sim_forward_step(adj_scene* s, const double* qbar, const d
   }
   s->fwd_residual = worst;
   if (!(worst <= 1e-8)) return fail(ADJ_E_NOCONV, "forward Newton residual " + std::to_string(worst));
+  return ADJ_OK;
+}
+
+extern "C" adj_status adj_set_spheres(adj_scene* s, int32_t n, const double* old_pose, const double* new_pose) {
+  if (!s) return fail(ADJ_E_ARG, "scene is null");
+  if (n < 0 || (n > 0 && (!old_pose || !new_pose))) return fail(ADJ_E_ARG, "sphere poses missing");
+  const int np = (int)(s->hs.planes.size() / 4);
+  if (np + n > 15) return fail(ADJ_E_ARG, "at most 15 colliders (planes and spheres)");
+  for (int i = 0; i < 4 * n; ++i)
+    if (!std::isfinite(old_pose[i]) || !std::isfinite(new_pose[i])) return fail(ADJ_E_ARG, "non-finite pose");
+  for (int i = 0; i < n; ++i)
+    if (!(new_pose[4 * i + 3] > 0)) return fail(ADJ_E_ARG, "sphere radius must be positive");
+  if (n > s->sph_cap) {
+    if (s->d_sph) HIPCHK(hipFree(s->d_sph));
+    s->d_sph = nullptr;
+    s->sph_cap = 0;
+    if (hipMalloc(&s->d_sph, 8 * (size_t)n * sizeof(double)) != hipSuccess) return fail(ADJ_E_OOM, "spheres");
+    s->sph_cap = n;
+  }
+  s->sph.assign(old_pose, old_pose + 4 * n);
+  s->sph.insert(s->sph.end(), new_pose, new_pose + 4 * n);
+  if (n > 0) HIPCHK(hipMemcpy(s->d_sph, s->sph.data(), 8 * (size_t)n * sizeof(double), hipMemcpyHostToDevice));
+  s->n_spheres = n;
   return ADJ_OK;
 }
 

@@ -523,7 +523,7 @@ void launch_delassus(hipStream_t st, int nv, int ncv, const int* cv, const long 
     const size_t n = (size_t)ncv * ncv;
     k_syrk_reduce<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(ncv, ks, Pws, D);
   }
-  k_spmm_Z<<<nv, 256, 0, st>>>(nv, ncv, STp, STj, STx, Y, Z);
+  if (Z) k_spmm_Z<<<nv, 256, 0, st>>>(nv, ncv, STp, STj, STx, Y, Z);
 }
 
 // Inverse of the m x m capacitance held in the top-left of the row-major

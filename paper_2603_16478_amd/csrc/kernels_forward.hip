@@ -26,9 +26,14 @@ __global__ void k_fwd_predict(int nv, const double* __restrict__ qbar, const dou
   utilde[i] = h * vbar[i] + hh * acc;
 }
 
-// mask bit 2p: gap to plane p at qtilde <= margin; bit 2p+1: gap <= 0
-__global__ void k_fwd_detect(int nv, const double* __restrict__ qtilde, int nplanes,
-                             const double* __restrict__ planes, double margin, int* __restrict__ mask) {
+// mask bit 2p: gap to collider p at qtilde <= margin; bit 2p+1: gap <= 0.
+// Colliders 0..nplanes-1 are the planes, then the kinematic spheres: a
+// sphere's contact plane has the normal n = (qbar_v - c_old)/|qbar_v - c_old|
+// and the offset n . c_new + r (the tangent plane at the step's new pose).
+__global__ void k_fwd_detect(int nv, const double* __restrict__ qbar, const double* __restrict__ qtilde,
+                             int nplanes, const double* __restrict__ planes, int nspheres,
+                             const double* __restrict__ sph_old, const double* __restrict__ sph_new, double margin,
+                             int* __restrict__ mask) {
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= nv) return;
   int mk = 0;
@@ -36,6 +41,19 @@ __global__ void k_fwd_detect(int nv, const double* __restrict__ qtilde, int npla
   for (int p = 0; p < nplanes && p < 15; ++p) {
     const double* pl = planes + 4 * p;
     const double gap = ((pl[0] * x0 + pl[1] * x1) + pl[2] * x2) - pl[3];
+    if (gap <= margin) mk |= 1 << (2 * p);
+    if (gap <= 0.0) mk |= 1 << (2 * p + 1);
+  }
+  for (int s = 0; s < nspheres && nplanes + s < 15; ++s) {
+    const double* c0 = sph_old + 4 * s;
+    const double* c1 = sph_new + 4 * s;
+    const double d0 = qbar[3 * v] - c0[0], d1 = qbar[3 * v + 1] - c0[1], d2 = qbar[3 * v + 2] - c0[2];
+    const double nrm = sqrt((d0 * d0 + d1 * d1) + d2 * d2);
+    if (nrm == 0.0) continue;
+    const double n0 = d0 / nrm, n1 = d1 / nrm, n2 = d2 / nrm;
+    const double dn = ((n0 * c1[0] + n1 * c1[1]) + n2 * c1[2]) + c1[3];
+    const double gap = ((n0 * x0 + n1 * x1) + n2 * x2) - dn;
+    const int p = nplanes + s;
     if (gap <= margin) mk |= 1 << (2 * p);
     if (gap <= 0.0) mk |= 1 << (2 * p + 1);
   }
@@ -196,9 +214,11 @@ void launch_fwd_predict(hipStream_t st, int nv, const double* qbar, const double
                                                       qtilde);
 }
 
-void launch_fwd_detect(hipStream_t st, int nv, const double* qtilde, int nplanes, const double* planes,
+void launch_fwd_detect(hipStream_t st, int nv, const double* qbar, const double* qtilde, int nplanes,
+                       const double* planes, int nspheres, const double* sph_old, const double* sph_new,
                        double margin, int* mask) {
-  k_fwd_detect<<<(nv + 255) / 256, 256, 0, st>>>(nv, qtilde, nplanes, planes, margin, mask);
+  k_fwd_detect<<<(nv + 255) / 256, 256, 0, st>>>(nv, qbar, qtilde, nplanes, planes, nspheres, sph_old, sph_new,
+                                                 margin, mask);
 }
 
 void launch_add_vec(hipStream_t st, long long n, const double* a, const double* b, double alpha, double* out) {

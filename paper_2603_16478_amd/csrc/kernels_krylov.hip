@@ -628,6 +628,36 @@ static void wb_correct_impl(hipStream_t s, int nv, int ncv, const int* cv_ptr, c
                                                                                         c_row0, c_nrow, Q, t, Z, h2,
                                                                                         u, st, y);
 }
+// w[cv_a] = sum over the contacts c at contact vertex a of Q_c^T t_c (H^T t
+// in world coordinates; w is zero elsewhere).  One thread per contact vertex.
+__global__ void k_scatter_ht(int ncv, const int* __restrict__ cv, const int* __restrict__ cv_ptr,
+                             const int* __restrict__ c_row0, const int* __restrict__ c_nrow,
+                             const double* __restrict__ Q, const double* __restrict__ t,
+                             const GmresState* __restrict__ st, double* __restrict__ w) {
+  if (gm_inactive(st)) return;
+  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= ncv) return;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+  for (int c = cv_ptr[a]; c < cv_ptr[a + 1]; ++c)
+    for (int i = 0; i < c_nrow[c]; ++i) {
+      const double tv = t[c_row0[c] + i];
+      const double* q = Q + 9 * c + 3 * i;
+      s0 += q[0] * tv;
+      s1 += q[1] * tv;
+      s2 += q[2] * tv;
+    }
+  const int v = cv[a];
+  w[3 * v] = s0;
+  w[3 * v + 1] = s1;
+  w[3 * v + 2] = s2;
+}
+
+void launch_scatter_ht(hipStream_t s, int ncv, const int* cv, const int* cv_ptr, const int* c_row0,
+                       const int* c_nrow, const double* Q, const double* t, const GmresState* st, double* w) {
+  if (ncv <= 0) return;
+  k_scatter_ht<<<(ncv + 255) / 256, 256, 0, s>>>(ncv, cv, cv_ptr, c_row0, c_nrow, Q, t, st, w);
+}
+
 void launch_wb_correct(hipStream_t s, int nv, int ncv, const int* cv_ptr, const int* c_row0, const int* c_nrow,
                        const double* Q, const double* t, const double* Z, double h2, const double* u,
                        const GmresState* st, double* y) {

@@ -23,13 +23,14 @@ STATUS = {0: "ADJ_OK", -1: "ADJ_E_ARG", -2: "ADJ_E_SHAPE", -3: "ADJ_E_INVERTED",
 ADJ_FP64, ADJ_MIXED = 0, 1
 ADJ_AUTO, ADJ_GMRES, ADJ_PCG, ADJ_SEMI_IMPLICIT = 0, 1, 2, 3
 PRECOND_WOODBURY, PRECOND_SPARSE_INVERSE, PRECOND_JACOBI, PRECOND_POINT_JACOBI = 0, 1, 2, 3
+PRECOND_WOODBURY_NO_Z = 4
 MAT_NEO_HOOKEAN, MAT_ARAP, MAT_COROT = 0, 1, 2
 MATERIAL_CODES = {"nh": MAT_NEO_HOOKEAN, "arap": MAT_ARAP, "corot": MAT_COROT}
 
 # names declared in include/adjoint.h
 EXPORTS = ("adj_scene_create", "adj_scene_destroy", "adjoint_setup", "adjoint_solve", "vjp_params",
            "sim_forward_step", "adj_scene_info", "adj_check_status", "adj_debug_export",
-           "adj_profile_begin", "adj_profile_end", "adj_forward_stats", "adj_forward_reset",
+           "adj_profile_begin", "adj_profile_end", "adj_forward_stats", "adj_forward_reset", "adj_set_spheres",
            "adj_set_tuning", "adj_get_tuning", "adj_autotune", "adj_batch_create", "adj_batch_destroy",
            "adj_batch_info", "adj_batch_setup", "adj_batch_solve", "adj_batch_vjp", "adj_batch_check_status",
            "adj_batch_debug_export", "adj_batch_scene", "adj_batch_reverse", "adj_binding_vjp",
@@ -103,6 +104,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.adj_profile_begin.argtypes = [vp, C.c_int32]
     lib.adj_forward_stats.argtypes = [vp, C.POINTER(C.c_double)]
     lib.adj_forward_reset.argtypes = [vp]
+    lib.adj_set_spheres.argtypes = [vp, C.c_int32, vp, vp]
     lib.adj_profile_end.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
     lib.adj_set_tuning.argtypes = [vp, C.POINTER(Tuning)]
     lib.adj_get_tuning.argtypes = [vp, C.POINTER(Tuning)]
@@ -288,6 +290,17 @@ def forward_stats(scene: Scene):
 
 def forward_reset(scene: Scene):
     check(load().adj_forward_reset(scene.handle))
+
+
+def set_spheres(scene: Scene, old_pose, new_pose):
+    """Kinematic spheres of the next forward steps (adj_set_spheres); poses
+    (n, 4) host arrays of (centre, radius)."""
+    old = np.ascontiguousarray(np.asarray(old_pose, dtype=np.float64).reshape(-1, 4))
+    new = np.ascontiguousarray(np.asarray(new_pose, dtype=np.float64).reshape(-1, 4))
+    if old.shape != new.shape:
+        raise ValueError("old and new sphere poses differ in shape")
+    n = old.shape[0]
+    check(load().adj_set_spheres(scene.handle, n, old.ctypes.data if n else None, new.ctypes.data if n else None))
 
 
 class ContactBuffers:

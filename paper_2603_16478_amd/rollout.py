@@ -40,7 +40,11 @@ class GpuSim:
         self.buf = native.ContactBuffers(self.max_contacts)
         self.dev = "cuda"
 
-    def step(self, qbar, vbar, f_ext, mu):
+    def step(self, qbar, vbar, f_ext, mu, t=None):
+        """One forward step; with t given, the spec's kinematic spheres move
+        from their pose at t to their pose at t + 1 during the step."""
+        if t is not None and self.spec.spheres:
+            native.set_spheres(self.scene, self.spec.sphere_array(t), self.spec.sphere_array(t + 1))
         q = torch.empty_like(qbar)
         v = torch.empty_like(qbar)
         native.sim_forward_step(self.scene, qbar, vbar, f_ext, mu, q, v, self.buf.state)

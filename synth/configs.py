@@ -132,25 +132,29 @@ def beam_scene(mu: float = 0.4, seed: int = 1, steps: int = 100,
     )
 
 
-def slab_scene(seed: int = 2, steps: int = 50) -> SceneSpec:
+def slab_scene(seed: int = 2, steps: int = 50, nx: int = 64, ny: int = 32, nz: int = 32,
+               cell: float = 0.01) -> SceneSpec:
     """64x32x32-cell slab (393,216 tets, 70,785 verts), cell 0.01 m, pressed
-    into the ground by a kinematic sphere of radius 0.3 x 0.64 m descending
-    at constant speed to an indentation of 0.093 m at the last step."""
+    into the ground by a kinematic sphere of radius 0.3 x the slab width
+    descending at constant speed to an indentation of 0.093 m x (width /
+    0.64 m) at the last step.  Smaller nx, ny, nz give the same set-up at a
+    reduced size."""
     rng = np.random.default_rng(seed)
-    mesh = box_mesh(64, 32, 32, 0.01, origin=(0.0, 0.0, 0.0))
-    R = 0.3 * 0.64
-    top = 0.32
-    depth = 0.093
-    cx, cy = 0.32, 0.16
+    mesh = box_mesh(nx, ny, nz, cell, origin=(0.0, 0.0, 0.0))
+    width = nx * cell
+    R = 0.3 * width
+    top = nz * cell
+    depth = 0.093 * width / 0.64
+    cx, cy = 0.5 * nx * cell, 0.5 * ny * cell
 
     def centre(t: int) -> np.ndarray:
         return np.array([cx, cy, top + R - depth * t / steps])
 
     loss = loss_vector(rng, mesh.n_verts)
     return SceneSpec(
-        name="slab", mesh=mesh, density=1000.0, E=5e5, nu=0.45, mu=0.5, h=1e-3,
-        eps=np.sqrt(0.5e-12), steps=steps, gravity=GRAVITY.copy(), planes=GROUND.copy(),
-        contact_margin=2e-3, q0=mesh.rest.copy(), v0=np.zeros((mesh.n_verts, 3)),
+        name="slab" if (nx, ny, nz) == (64, 32, 32) else f"slab{nx}x{ny}x{nz}", mesh=mesh, density=1000.0,
+        E=5e5, nu=0.45, mu=0.5, h=1e-3, eps=np.sqrt(0.5e-12), steps=steps, gravity=GRAVITY.copy(),
+        planes=GROUND.copy(), contact_margin=2e-3, q0=mesh.rest.copy(), v0=np.zeros((mesh.n_verts, 3)),
         loss_dir=loss, seed=seed, spheres=[(R, centre)],
     )
 
@@ -229,3 +233,29 @@ def slope_scene(side: str = "slip", two_eps2: float = 1e-12, seed: int = 5, h: f
         contact_margin=2e-3, q0=mesh.rest.copy(), v0=np.zeros((mesh.n_verts, 3)),
         loss_dir=loss_vector(rng, mesh.n_verts), seed=seed,
     )
+
+
+def perturbed_state(spec: SceneSpec, seed: int = 12, scale: float = 1e-5) -> np.ndarray:
+    """Rest positions with a seeded N(0, scale^2) perturbation per coordinate
+    (a deformed state at which an adjoint system can be set up)."""
+    rng = np.random.default_rng(seed)
+    return spec.mesh.rest + scale * rng.standard_normal(spec.mesh.rest.shape)
+
+
+def contact_values(n: int, mu: float, seed: int = 13):
+    """Seeded contact displacements and multipliers in frame coordinates for n
+    sticking contacts: normal gaps U[1e-13, 1e-11] m, normal forces
+    U[0.01, 1] N, tangential displacements of magnitude U[1e-13, 1e-11] m and
+    tangential forces of magnitude U[0, 0.9] mu lambda_n pointing against
+    them.  Returns (delta, lam), each (n, 3)."""
+    rng = np.random.default_rng(seed)
+    delta = np.zeros((n, 3))
+    lam = np.zeros((n, 3))
+    delta[:, 0] = rng.uniform(1e-13, 1e-11, n)
+    lam[:, 0] = rng.uniform(0.01, 1.0, n)
+    ang = rng.uniform(0.0, 2.0 * np.pi, n)
+    dmag = rng.uniform(1e-13, 1e-11, n)
+    fmag = rng.uniform(0.0, 0.9, n) * mu * lam[:, 0]
+    delta[:, 1], delta[:, 2] = dmag * np.cos(ang), dmag * np.sin(ang)
+    lam[:, 1], lam[:, 2] = -fmag * np.cos(ang), -fmag * np.sin(ang)
+    return delta, lam

@@ -1,0 +1,155 @@
+"""The slab workload (a slab pressed into the ground by a kinematic sphere)
+at a reduced size, 8x4x4 cells: the GPU forward step with the sphere collider
+reproduces the oracle's step (contact list with collider ids and frames bit
+for bit, positions and multipliers), and the GPU adjoint on the oracle's
+states (ground and sphere contacts) reaches the oracle's gradients at the
+FP64 bar."""
+
+import functools
+
+import numpy as np
+import pytest
+
+from gpu_helpers import make_scene, rel, run_adjoint, torch_cuda
+from oracle import adjoint as adj
+from oracle.forward import solve_step
+from oracle.rollout import run_forward
+from synth.configs import slab_scene
+
+pytestmark = pytest.mark.gpu
+
+TOL_FP64 = 1e-9
+
+
+@functools.lru_cache(maxsize=None)
+def _run():
+    spec = slab_scene(nx=8, ny=4, nz=4)
+    return spec, run_forward(spec, steps=14)
+
+
+@pytest.mark.parametrize("step", [4, 11, 13])
+def test_forward_step_with_sphere_matches_oracle(step):
+    torch = torch_cuda()
+    from paper_2603_16478_amd.rollout import GpuSim
+    spec, ro = _run()
+    q_ref, _, ref, _ = solve_step(ro.disc, ro.qs[step], ro.vs[step], spec.force(step), spec.gravity, spec.mu,
+                                  spec.eps, spec.planes, spec.sphere_array(step), spec.sphere_array(step + 1),
+                                  margin=spec.contact_margin)
+    sim = GpuSim(spec, max_contacts=256)
+    q, v, rec = sim.step(torch.tensor(ro.qs[step], device="cuda"), torch.tensor(ro.vs[step], device="cuda"),
+                         torch.tensor(spec.force(step), device="cuda"), spec.mu, t=step)
+    n = rec.n
+    n_sph = int((ref.contacts.collider == spec.planes.shape[0]).sum())
+    print(f"mini slab step {step}: contacts {n} (oracle {ref.contacts.n}, {n_sph} on the sphere)", flush=True)
+    assert n == ref.contacts.n and n_sph > 0
+    np.testing.assert_array_equal(rec.vid[:n].cpu().numpy(), ref.contacts.vid)
+    np.testing.assert_array_equal(rec.fric[:n].cpu().numpy().astype(bool), ref.contacts.fric)
+    np.testing.assert_array_equal(rec.frame[:n].cpu().numpy().reshape(-1, 3, 3), ref.contacts.frame)
+    np.testing.assert_array_equal(rec.d_n[:n].cpu().numpy(), ref.contacts.d_n)
+    assert rel(rec.d_f[:n].cpu().numpy(), ref.contacts.d_f) <= 1e-15
+    e_q = rel(q.cpu().numpy() - ro.qs[step], q_ref - ro.qs[step])
+    e_l = rel(rec.lam[:n].cpu().numpy(), ref.lam)
+    print(f"  step displacement err {e_q:.2e}, multiplier err {e_l:.2e}", flush=True)
+    assert e_q <= 1e-7
+    assert e_l <= 1e-6
+
+
+@pytest.mark.parametrize("step", [11, 13])
+def test_adjoint_with_sphere_contacts_matches_oracle(step):
+    torch_cuda()
+    spec, ro = _run()
+    rec, q = ro.records[step], ro.qs[step + 1]
+    rng = np.random.default_rng(500 + step)
+    gq, gv = rng.standard_normal(q.shape), 1e-3 * rng.standard_normal(q.shape)
+    ref = adj.adjoint_step(ro.disc, q, rec, gq, gv, spec.eps, spec.E, spec.nu)
+    scene = make_scene(spec, max_contacts=256)
+    # the stiff sticking rows (2 eps^2 = 1e-12) put the FP64 floor of the
+    # relative residual near 1e-9; z is accurate well below that
+    out = run_adjoint(scene, rec, q, gq, gv, rtol=1e-10, maxit=1000, want_tet=True, raise_noconv=False)
+    errs = {k: rel(out[k], getattr(ref, k)) for k in ("z", "dqbar", "dvbar", "dfext", "dE_tet", "dnu_tet")}
+    print(f"mini slab adjoint step {step}: contacts {rec.contacts.n}, iters {out['info'].iters}, relres "
+          f"{out['info'].relres:.2e}, " + ", ".join(f"{k} {e:.1e}" for k, e in errs.items()), flush=True)
+    assert out["info"].relres <= 1e-8
+    for k, e in errs.items():
+        assert e <= TOL_FP64, k
+    assert abs(out["grad3"][2] - ref.dmu_fric) <= TOL_FP64 * max(abs(ref.dmu_fric), 1e-30) + 1e-20
+    scene.close()
+
+
+def test_full_size_slab_adjoint_properties():
+    """The slab at full size (64x32x32 cells, 393,216 tets, 70,785 vertices)
+    with the 2,190 contacts that the detection finds at a seeded deformed
+    state (2,145 on the ground, 45 under the sphere; seeded sticking contact
+    values, tests/golden/slab_contacts.npz): the GPU adjoint in FP64 and in
+    mixed precision (the Woodbury correction goes through S^T S here, Z would
+    cost 5e11 multiply-adds).  Checked at any size: the GPU z satisfies the
+    oracle's assembled system to the solve's tolerance (1e-8), the oracle's
+    gradient contractions from that z equal the GPU's (FP64 bar), and the
+    mixed-precision z agrees with the FP64 one to the mixed bar."""
+    torch = torch_cuda()
+    import os
+
+    from conftest import ROOT
+    from gpu_helpers import contact_tensors
+    from oracle.contact import ContactSet
+    from oracle.forward import StepRecord
+    from oracle.rollout import scene_disc
+    from paper_2603_16478_amd import native
+    from synth.configs import contact_values, perturbed_state
+    path = os.path.join(ROOT, "tests", "golden", "slab_contacts.npz")
+    if not os.path.exists(path):
+        pytest.skip(f"missing fixture {path}")
+    d = np.load(path)
+    spec = slab_scene()
+    qn = perturbed_state(spec)
+    n = int(d["vid"].shape[0])
+    delta, lam = contact_values(n, spec.mu)
+    orec = StepRecord(ContactSet(d["vid"], d["collider"], d["frame"], d["d_n"], d["d_f"], d["fric"]), delta, lam,
+                      spec.mu)
+    print(f"full slab: {spec.n_verts} vertices, {spec.n_tets} tets, {n} contacts; building the scene", flush=True)
+    scene = make_scene(spec, max_contacts=n)
+    print(f"  nnz(S) {scene.info()['nnz_S']}", flush=True)
+    tens = contact_tensors(orec)
+    cs = native.make_contact_state(n, tens["vid"], tens["fric"], tens["frame"], tens["delta"], tens["lam"], spec.mu)
+    q = torch.tensor(qn, device="cuda")
+    rng = np.random.default_rng(77)
+    gvn = 1e-3 * rng.standard_normal(qn.shape)
+    gq = torch.tensor(spec.loss_dir, device="cuda")
+    gv = torch.tensor(gvn, device="cuda")
+    outs = {}
+    for prec in (native.ADJ_FP64, native.ADJ_MIXED):
+        opts = native.solve_opts(rtol=1e-10 if prec == native.ADJ_FP64 else 1e-8, maxit=600, restart=64,
+                                 prec=prec, max_refine=8)
+        native.adjoint_setup(scene, cs, q, opts)
+        native.check_status(scene)
+        z = torch.zeros_like(q)
+        inf = native.adjoint_solve(scene, gq, gv, z, opts, raise_noconv=False)
+        dq, dv, df = torch.empty_like(q), torch.empty_like(q), torch.empty_like(q)
+        grad3 = torch.zeros(3, dtype=torch.float64, device="cuda")
+        dE = torch.zeros(spec.n_tets, dtype=torch.float64, device="cuda")
+        dnu = torch.zeros(spec.n_tets, dtype=torch.float64, device="cuda")
+        native.vjp_params(scene, z, gv, dq, dv, df, grad3, dE, dnu)
+        torch.cuda.synchronize()
+        print(f"  adjoint prec {prec}: iters {inf.iters}, refinements {inf.refine_steps}, relres {inf.relres:.2e}",
+              flush=True)
+        assert inf.relres <= 1e-8
+        outs[prec] = {"z": z.cpu().numpy(), "dqbar": dq.cpu().numpy(), "dvbar": dv.cpu().numpy(),
+                      "dfext": df.cpu().numpy(), "dE_tet": dE.cpu().numpy(), "dnu_tet": dnu.cpu().numpy(),
+                      "grad3": grad3.cpu().numpy()}
+    scene.close()
+    disc = scene_disc(spec)
+    sysm = adj.assemble(disc, qn, orec, spec.eps)
+    b = spec.loss_dir.reshape(-1) + gvn.reshape(-1) / spec.h
+    o = outs[native.ADJ_FP64]
+    res = np.linalg.norm(sysm.Acal.T @ o["z"].reshape(-1) - b) / np.linalg.norm(b)
+    print(f"  oracle residual of the GPU z: {res:.2e}", flush=True)
+    assert res <= 1e-8
+    ref = adj.vjp(disc, sysm, qn, orec, o["z"].reshape(-1), gvn, spec.E, spec.nu)
+    errs = {k: rel(o[k], getattr(ref, k)) for k in ("dqbar", "dvbar", "dfext", "dE_tet", "dnu_tet")}
+    print("  contractions: " + ", ".join(f"{k} {e:.1e}" for k, e in errs.items()), flush=True)
+    for k, e in errs.items():
+        assert e <= TOL_FP64, k
+    assert abs(o["grad3"][2] - ref.dmu_fric) <= TOL_FP64 * max(abs(ref.dmu_fric), 1e-30) + 1e-20
+    e_mixed = rel(outs[native.ADJ_MIXED]["z"], o["z"])
+    print(f"  mixed z against FP64 z: {e_mixed:.2e}", flush=True)
+    assert e_mixed <= 1e-4
