@@ -20,7 +20,7 @@ right-hand side (FP64 and mixed; the roofline kernels are timed there),
 each scene solved alone (FP64 and mixed), the comparison preconditioners
 of the backward solve, the beam with its end face held by bilateral
 bindings (single scene, FP64), the as-rigid-as-possible and co-rotational
-local steps (single scene, FP64), a large batch (the
+local steps (single scene, FP64), the full-size slab (FP64 and mixed), a large batch (the
 twelve recorded scene-steps four times: 48 scenes per launch, FP64 and
 mixed, with the sparse-inverse product's bandwidth), the rooflines of the
 two largest kernels, the batched Gauss-Jordan step and the batched
@@ -106,13 +106,19 @@ def _function_text(src, name):
     return m.group(0) if m else src
 
 
+GJ_FUNCTIONS = ("readlane_d", "rcp_newton", "max_dpp", "gj_rows_step", "invert32_rows", "gj_tile", "gj_next_pivot",
+                "kb_gj_step_mfma")
+
+
 def kernel_source_hash(kernel):
     """Hash of the source text the kernel's counters depend on."""
     if kernel == "s_product":
         text = (_function_text(open(os.path.join(CSRC, "kernels_batch.hip")).read(), "kb_spmv_tasks") +
                 _function_text(open(os.path.join(CSRC, "device_common.h")).read(), "row_dot3"))
     else:
-        text = open(os.path.join(CSRC, "kernels_dense.hip")).read()
+        src = open(os.path.join(CSRC, "kernels_dense.hip")).read()
+        m = re.search(r"struct GjShared \{.*?\};", src, re.S)
+        text = "".join(_function_text(src, f) for f in GJ_FUNCTIONS) + (m.group(0) if m else src)
     return hashlib.sha1(text.encode()).hexdigest()
 
 
@@ -202,7 +208,7 @@ def slab_leg(nsolve):
     deformed state with the 2,190 contacts of tests/golden/slab_contacts.npz
     and seeded sticking contact values, timed `nsolve` times in FP64 and in
     mixed precision (setup + solve + VJP), with the sparse-inverse product's
-    bandwidth.  Prints one JSON line."""
+    bandwidth.  Returns a dict."""
     import torch
 
     from paper_2603_16478_amd import native
@@ -251,19 +257,23 @@ def slab_leg(nsolve):
         torch.cuda.synchronize()
         dt = time.perf_counter() - t2
         sms, sl = native.profile_end(scene)
-        gbs = sbytes / (sms / max(sl, 1) * 1e-3) / 1e9 if sl else None
+        avg_us = 1e3 * sms / max(sl, 1)
         legs[name] = {"value": nsolve / dt, "unit": "adjoint solves/s", "ms_per_solve": 1e3 * dt / nsolve,
                       "krylov_iters_mean": float(np.mean(its)), "first_solve_s_incl_delassus": t_first,
-                      "s_product_GB/s": gbs, "s_product_frac": gbs / HBM_PEAK_GBPS if gbs else None}
+                      "s_product_avg_launch_us": avg_us, "s_product_launches": sl}
+        if prec == native.ADJ_FP64 and sl:
+            gbs = sbytes / (avg_us * 1e-6) / 1e9
+            legs[name] |= {"s_product_GB/s": gbs, "s_product_frac": gbs / HBM_PEAK_GBPS}
         print(f"slab adjoint {name}: {legs[name]['ms_per_solve']:.1f} ms per solve, iterations "
-              f"{legs[name]['krylov_iters_mean']:.1f}, S product {gbs:.0f} GB/s, first solve {t_first:.2f} s",
-              file=sys.stderr, flush=True)
+              f"{legs[name]['krylov_iters_mean']:.1f}, S product {avg_us:.0f} us per launch, first solve "
+              f"{t_first:.2f} s", file=sys.stderr, flush=True)
     legs["mixed"]["speedup_vs_fp64"] = legs["mixed"]["value"] / legs["fp64"]["value"]
     scene.close()
-    print(json.dumps({"workload": "slab 64x32x32 cells (393,216 tets, 70,785 vertices), sphere indenter; seeded "
-                                  "deformed state, 2,190 detected contacts with seeded sticking values",
-                      "scene_build_s": t_build, "nnz_S": info["nnz_S"], "contacts": n, "adjoint": legs,
-                      "s_product_bytes": sbytes}))
+    return {"workload": "slab 64x32x32 cells (393,216 tets, 70,785 vertices), sphere indenter; seeded deformed "
+                        "state, 2,190 detected contacts with seeded sticking values; GMRES(64) + Woodbury (correction "
+                        "through S^T S) to 1e-8",
+            "scene_build_s": t_build, "nnz_S": info["nnz_S"], "contacts": n, "adjoint": legs,
+            "s_product_bytes": sbytes}
 
 
 def eps_sweep(seconds):
@@ -311,6 +321,7 @@ def main():
     ap.add_argument("--slab", type=int, default=0, metavar="SOLVES",
                     help="instead of the benchmark: the full-size slab adjoint, SOLVES timed solves in FP64 and in "
                          "mixed precision")
+    ap.add_argument("--no-slab", action="store_true", help="skip the full-size slab leg")
     ap.add_argument("--eps-sweep-one", nargs=3, metavar=("TWO_EPS2", "SIDE", "SECONDS"), help=argparse.SUPPRESS)
     ap.add_argument("--big-batch", type=int, default=4,
                     help="copies of the twelve recorded scene-steps in the large-batch leg (0: skip)")
@@ -321,7 +332,7 @@ def main():
         sys.exit(2)
 
     if args.slab > 0:
-        slab_leg(args.slab)
+        print(json.dumps(slab_leg(args.slab)))
         return
     if args.eps_sweep_one:
         eps_sweep_one(float(args.eps_sweep_one[0]), args.eps_sweep_one[1], float(args.eps_sweep_one[2]))
@@ -737,6 +748,12 @@ def main():
                                      "positions (compliance 1e-6 m/N), GMRES(64) + Woodbury to 1e-8; setup + "
                                      "solve + VJP + binding VJP per recorded scene-step"},
     }
+    if not args.no_slab:
+        # the full-size slab (about 20 s of host factorisation, then two timed
+        # solves per precision)
+        scene.close()
+        torch.cuda.synchronize()
+        out["slab"] = slab_leg(2)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(spec, states, args.cpu_sample)
     print(json.dumps(out))
