@@ -50,6 +50,9 @@ void launch_delassus(hipStream_t, int, int, const int*, const long long*, const 
 int delassus_slices(int, int);
 void launch_gj_pad(hipStream_t, int, int, double*);
 void launch_gj_step(hipStream_t, int, int, const double*, double*, int*);
+void launchb_gj_pivot(hipStream_t, int, const int*, const long long*, const int*, const double*, double*, int*);
+void launchb_gj_step(hipStream_t, int, const int*, int, const int4*, int, const long long*, const int*, const double*,
+                     double*, const double*, double*, int*);
 void launch_spmv_csr3(hipStream_t, int, const long long*, const int*, const double*, const double*,
                       long long, const double*, const GmresState*, double*);
 void launch_block_jacobi(hipStream_t, int, const int*, const double*, const double*, long long, const double*,
@@ -175,6 +178,14 @@ struct adj_scene {
   bool delassus_f32 = false;
   bool symmetric = true;      // Acal^T symmetric: no frictional contact, or mu = 0  // D computed on FP32 matrix cores (mixed precision)
   double* d_Pws = nullptr;    // K-slice partials of the Delassus product
+  // Gauss-Jordan with the pivot lookahead (the batched step kernels on a
+  // batch of one): tile list of the padded size gj_mp, scene list {0},
+  // offset {0}, size {gj_mp}, two pivot slots
+  int gj_mp = 0;
+  int4* d_gj_tiles = nullptr;
+  int* d_gj_one = nullptr;        // [0] = scene 0, [1] = padded size
+  long long* d_gj_xoff = nullptr;
+  double* d_gj_P = nullptr;
   size_t cap_pws = 0;
   size_t cap_ncv = 0, cap_m = 0, cap_z = 0;
   long long nnzS = 0;   // entries of S
@@ -281,7 +292,7 @@ static void free_scene(adj_scene* s) {
                   s->d_partial,  s->d_counter, s->d_state, s->d_t1,         s->d_u,
                   s->d_y,        s->d_r,      s->d_b,     s->d_dz,          s->d_xt,
                   s->d_Stasks,   s->d_STtasks, s->d_planes,  s->d_vptr,   s->d_vcode, s->d_sph,
-                  s->d_wz,       s->d_wz2,
+                  s->d_wz,       s->d_wz2,    s->d_gj_tiles, s->d_gj_one, s->d_gj_xoff, s->d_gj_P,
                   s->d_mask,     s->d_fvid,   s->d_force, s->d_utilde,      s->d_qtilde,
                   s->d_fu,       s->d_du,     s->d_ut,    s->d_qcur,        s->d_rq,
                   s->d_rhs,      s->d_cvec,   s->d_cu,    s->d_norms,       s->d_Sx32,
@@ -601,14 +612,46 @@ static adj_status build_capacitance(adj_scene* s, hipStream_t st, double mu, int
   s->cap_m = std::max(s->cap_m, (size_t)mp);
   launch_capacitance(st, m, mp, s->d_row_c, s->d_row_i, s->d_cmap, s->ncv, s->d_D, s->d_Q, s->d_kh, mu, h2,
                      transpose, s->d_C);
+  if (mp != s->gj_mp) {
+    // tiles {scene 0, I, J} of the padded matrix, the same at every step
+    const int nt = mp / 64;
+    std::vector<int4> tiles((size_t)nt * nt);
+    for (int i = 0; i < nt; ++i)
+      for (int j = 0; j < nt; ++j) tiles[(size_t)i * nt + j] = make_int4(0, i, j, 0);
+    const int one[2] = {0, mp};
+    const long long zero = 0;
+    HIPCHK(hipStreamSynchronize(st));  // the previous tile list may still be read
+    for (void* p : {(void*)s->d_gj_tiles, (void*)s->d_gj_one, (void*)s->d_gj_xoff, (void*)s->d_gj_P})
+      if (p) HIPCHK(hipFree(p));
+    s->d_gj_tiles = nullptr;
+    s->d_gj_one = nullptr;
+    s->d_gj_xoff = nullptr;
+    s->d_gj_P = nullptr;
+    s->gj_mp = 0;
+    if (hipMalloc(&s->d_gj_tiles, tiles.size() * sizeof(int4)) != hipSuccess ||
+        hipMalloc(&s->d_gj_one, 2 * sizeof(int)) != hipSuccess ||
+        hipMalloc(&s->d_gj_xoff, sizeof(long long)) != hipSuccess ||
+        hipMalloc(&s->d_gj_P, 2 * 32 * 32 * sizeof(double)) != hipSuccess)
+      return fail(ADJ_E_OOM, "Gauss-Jordan tables");
+    HIPCHK(hipMemcpy(s->d_gj_tiles, tiles.data(), tiles.size() * sizeof(int4), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(s->d_gj_one, one, 2 * sizeof(int), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(s->d_gj_xoff, &zero, sizeof(long long), hipMemcpyHostToDevice));
+    s->gj_mp = mp;
+  }
   {
+    // block Gauss-Jordan; the pivot block of step k + 1 is formed and
+    // inverted beside the tiles of step k (two pivot slots)
     ProfScope p(s, 7, st);
     launch_gj_pad(st, m, mp, s->d_C);
     double* A = s->d_C;
     double* B = s->d_colbuf;
-    for (int k = 0; k < mp / 32; ++k) {
+    const int ntiles = (mp / 64) * (mp / 64), nsteps = mp / 32;
+    launchb_gj_pivot(st, 1, s->d_gj_one, s->d_gj_xoff, s->d_gj_one + 1, A, s->d_gj_P, s->d_err);
+    for (int k = 0; k < nsteps; ++k) {
       ProfScope pk(s, 10, st);
-      launch_gj_step(st, mp, k, A, B, s->d_err);
+      const bool next = k + 1 < nsteps;
+      launchb_gj_step(st, next ? 1 : 0, next ? s->d_gj_one : nullptr, ntiles, s->d_gj_tiles, 32 * k, s->d_gj_xoff,
+                      s->d_gj_one + 1, A, B, s->d_gj_P + (k % 2) * 1024, s->d_gj_P + ((k + 1) % 2) * 1024, s->d_err);
       std::swap(A, B);
     }
     s->d_X = A;
