@@ -49,7 +49,6 @@ void launch_delassus(hipStream_t, int, int, const int*, const long long*, const 
                      double*, double*, double*, double*);
 int delassus_slices(int, int);
 void launch_gj_pad(hipStream_t, int, int, double*);
-void launch_gj_step(hipStream_t, int, int, const double*, double*, int*);
 void launchb_gj_pivot(hipStream_t, int, const int*, const long long*, const int*, const double*, double*, int*);
 void launchb_gj_step(hipStream_t, int, const int*, int, const int4*, int, const long long*, const int*, const double*,
                      double*, const double*, double*, int*);

@@ -278,13 +278,13 @@ __device__ __forceinline__ void invert32_rows(const double* __restrict__ Akk, in
 //   Rhat_j = A_kj (column j outside the pivot columns), e_j (pivot column j),
 // which gives P A_kj in the pivot rows, -A_ik P in the pivot columns, P in
 // the pivot block and A_ij - A_ik P A_kj elsewhere.
-// One 256-thread block per 64x64 output tile (mp a multiple of 64); wave 0
-// inverts A_kk in registers while the other waves stage the panels; the two
-// products (What for the tile rows, then the update) are 16x16x4 FP64 MFMAs
-// with 2x2 (What) and 2x2 (update) accumulator tiles per wave.
+// One 256-thread block per 64x64 output tile (mp a multiple of 64), with P
+// inverted beforehand (the lookahead below); the two products (What for the
+// tile rows, then the update) are 16x16x4 FP64 MFMAs with 2x2 (What) and 2x2
+// (update) accumulator tiles per wave.
 constexpr int kGT = 64;
 
-// 42 KB, so three blocks fit in one CU's LDS; the step kernels are held to
+// 42 KB, so three blocks fit in one CU's LDS; the step kernel is held to
 // 168 registers (three waves per SIMD) with the A tile loaded after the
 // panels are staged.
 struct GjShared {
@@ -296,12 +296,10 @@ struct GjShared {
 
 // One 64x64 output tile (I0, J0) of the block step at pivot k0.  Offsets
 // into the matrix are 32-bit (mp^2 < 2^32 for any capacitance size the
-// library accepts), which halves the address registers of the hoisted loads.  With
-// Pg == nullptr wavefront 0 inverts the pivot block itself; otherwise P is
-// read from Pg (32 x 32, row-major), inverted once per step beforehand.
+// library accepts), which halves the address registers of the hoisted loads.  P
+// is read from Pg (32 x 32, row-major), inverted once per step beforehand.
 __device__ __forceinline__ void gj_tile(int mp, int k0, int I0, int J0, const double* __restrict__ A,
-                                        double* __restrict__ B, int* __restrict__ err, GjShared& sh,
-                                        const double* __restrict__ Pg = nullptr) {
+                                        double* __restrict__ B, GjShared& sh, const double* __restrict__ Pg) {
   auto& Ps = sh.Ps;
   auto& Cs = sh.Cs;
   auto& Rs = sh.Rs;
@@ -310,11 +308,7 @@ __device__ __forceinline__ void gj_tile(int mp, int k0, int I0, int J0, const do
   const int li = lane & 15, lk = lane >> 4;
   // output sub-tiles of this wave: rows wr + 16 p, cols wc + 16 q (p, q < 2)
   const int wr = 32 * (w >> 1), wc = 32 * (w & 1);
-  if (Pg) {
-    for (int e = tid; e < kNB * kNB; e += 256) Ps[e / kNB][e % kNB] = Pg[e];
-  } else if (w == 0) {
-    invert32_rows(A + (size_t)k0 * mp + k0, mp, Ps, sh.prow, err);
-  }
+  for (int e = tid; e < kNB * kNB; e += 256) Ps[e / kNB][e % kNB] = Pg[e];
   for (int e = tid; e < kGT * kNB; e += 256) {
     const int r = e / kNB, c = e % kNB;
     Cs[r][c] = A[(unsigned)((I0 + r) * mp + k0 + c)];
@@ -387,13 +381,6 @@ __device__ __forceinline__ void gj_tile(int mp, int k0, int I0, int J0, const do
         const int j = J0 + wc + 16 * q + li;
         B[(unsigned)(i * mp + j)] = acc[p][q][e];
       }
-}
-
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
-k_gj_step_mfma(int mp, int k0, const double* __restrict__ A,
-                                                      double* __restrict__ B, int* __restrict__ err) {
-  __shared__ GjShared sh;
-  gj_tile(mp, k0, blockIdx.y * kGT, blockIdx.x * kGT, A, B, err, sh);
 }
 
 // Batched block steps with a one-step lookahead on the pivot chain.
@@ -481,7 +468,7 @@ kb_gj_step_mfma(const int* __restrict__ next_scenes, int npiv,
   }
   const int4 e = tiles[blockIdx.x - npiv];
   const long long o = xoff[e.x];
-  gj_tile(mps[e.x], k0, e.y * kGT, e.z * kGT, A + o, B + o, err, sh, Pcur + (size_t)e.x * kNB * kNB);
+  gj_tile(mps[e.x], k0, e.y * kGT, e.z * kGT, A + o, B + o, sh, Pcur + (size_t)e.x * kNB * kNB);
 }
 
 // identity padding of rows/cols m..mp-1 of a row-major mp x mp matrix
@@ -528,19 +515,14 @@ void launch_delassus(hipStream_t st, int nv, int ncv, const int* cv, const long 
 
 // Inverse of the m x m capacitance held in the top-left of the row-major
 // mp x mp buffer C0 (mp a multiple of 64): launch_gj_pad sets the padding
-// rows and columns to the identity, then launch_gj_step runs block step k
-// (k = 0 .. mp/32 - 1) from A into B, the two buffers swapping roles each
-// step; after the last step the inverse is in C0 when mp/32 is even, else
-// in C1.
+// rows and columns to the identity; then kb_gj_pivot inverts the first
+// pivot block and launchb_gj_step runs block step k (k = 0 .. mp/32 - 1)
+// from A into B, the two buffers swapping roles each step; after the last
+// step the inverse is in C0 when mp/32 is even, else in C1.
 void launch_gj_pad(hipStream_t st, int m, int mp, double* C0) {
   if (mp <= m) return;
   dim3 gpad((mp + 255) / 256, mp);
   k_pad_identity<<<gpad, 256, 0, st>>>(m, mp, C0);
-}
-
-void launch_gj_step(hipStream_t st, int mp, int k, const double* A, double* B, int* err) {
-  dim3 g(mp / kGT, mp / kGT);
-  k_gj_step_mfma<<<g, 256, 0, st>>>(mp, k * kNB, A, B, err);
 }
 
 void launchb_gj_pivot(hipStream_t st, int nscenes, const int* scenes, const long long* xoff, const int* mps,
