@@ -736,6 +736,36 @@ void launchb_norms(hipStream_t s, int nblk, int ns, const int4* tab, const int2*
   kb_norm_partials<<<nblk, 256, 0, s>>>(tab, x, P);
   kb_norm_finish<<<ns, 256, 0, s>>>(rng, P, out);
 }
+// w[cv_a] = sum over the contacts at union contact vertex a of Q_c^T t_c for
+// the active scenes (w zero elsewhere); one thread per contact vertex.
+__global__ void kb_scatter_ht(int ncv, const int* __restrict__ cv, const int* __restrict__ cvscene,
+                              const int* __restrict__ cv_ptr, const int* __restrict__ c_row0,
+                              const int* __restrict__ c_nrow, const double* __restrict__ Q,
+                              const double* __restrict__ t, const GmresState* __restrict__ st,
+                              double* __restrict__ w) {
+  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= ncv || st[cvscene[a]].active == 0) return;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+  for (int c = cv_ptr[a]; c < cv_ptr[a + 1]; ++c)
+    for (int i = 0; i < c_nrow[c]; ++i) {
+      const double tv = t[c_row0[c] + i];
+      const double* q = Q + 9 * c + 3 * i;
+      s0 += q[0] * tv;
+      s1 += q[1] * tv;
+      s2 += q[2] * tv;
+    }
+  const int v = cv[a];
+  w[3 * v] = s0;
+  w[3 * v + 1] = s1;
+  w[3 * v + 2] = s2;
+}
+
+void launchb_scatter_ht(hipStream_t s, int ncv, const int* cv, const int* cvscene, const int* cv_ptr,
+                        const int* c_row0, const int* c_nrow, const double* Q, const double* t, const GmresState* st,
+                        double* w) {
+  if (ncv > 0) kb_scatter_ht<<<(ncv + 255) / 256, 256, 0, s>>>(ncv, cv, cvscene, cv_ptr, c_row0, c_nrow, Q, t, st, w);
+}
+
 void launchb_delassus(hipStream_t s, int ncv_total, int ntiles, int nzv, const int* cv, const int* cvscene,
                       const int* cvoff, const int* voff, const int* vscene, const int* rloc, const long long* yoff,
                       const long long* doff, const int4* tiles, const int* zv, const long long* STp, const int* STj,

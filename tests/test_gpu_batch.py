@@ -50,7 +50,7 @@ def _cases():
     return cases
 
 
-def _run_batch(prec, rtol):
+def _run_batch(prec, rtol, precond=0):
     torch = torch_cuda()
     from paper_2603_16478_amd import native
     cases = _cases()
@@ -70,7 +70,7 @@ def _run_batch(prec, rtol):
     gq = torch.tensor(np.concatenate([c[4] for c in cases]), device=dev)
     gv = torch.tensor(np.concatenate([c[5] for c in cases]), device=dev)
     z = torch.zeros_like(q)
-    opts = native.solve_opts(rtol=rtol, maxit=3000, restart=64, prec=prec)
+    opts = native.solve_opts(rtol=rtol, maxit=3000, restart=64, prec=prec, precond=precond)
     native.batch_setup(batch, states, q, opts)
     native.batch_check_status(batch)
     infos = native.batch_solve(batch, gq, gv, z, opts, raise_noconv=False)
@@ -174,3 +174,14 @@ def test_batch_mixed_matches_oracle():
     from paper_2603_16478_amd import native
     out = _run_batch(native.ADJ_MIXED, 1e-8)
     _check_against_oracle(out, 1e-4)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_batch_without_z_matches_oracle(prec):
+    """The batched Woodbury correction through S^T S of the union (no cached
+    Z; the form large batches use), FP64 and mixed, against the oracle."""
+    from paper_2603_16478_amd import native
+    if prec == native.ADJ_FP64:
+        _check_against_oracle(_run_batch(native.ADJ_FP64, 1e-12, native.PRECOND_WOODBURY_NO_Z), 1e-9)
+    else:
+        _check_against_oracle(_run_batch(native.ADJ_MIXED, 1e-8, native.PRECOND_WOODBURY_NO_Z), 1e-4)
