@@ -20,7 +20,8 @@ right-hand side (FP64 and mixed; the roofline kernels are timed there),
 each scene solved alone (FP64 and mixed), the comparison preconditioners
 of the backward solve, the beam with its end face held by bilateral
 bindings (single scene, FP64), the as-rigid-as-possible and co-rotational
-local steps (single scene, FP64), the full-size slab (FP64 and mixed), a large batch (the
+local steps (single scene, FP64), the full-size slab (FP64 and mixed), the
+batched workload's boxes over their full size range (FP64 and mixed), a large batch (the
 twelve recorded scene-steps four times: 48 scenes per launch, FP64 and
 mixed, with the sparse-inverse product's bandwidth), the rooflines of the
 two largest kernels, the batched Gauss-Jordan step and the batched
@@ -173,6 +174,79 @@ def cpu_baseline(spec, states, sample):
                       f"{dt:.1f} s"}
 
 
+def boxes_leg(n_boxes, nsolve):
+    """The batched workload (boxes with log-uniform tet counts in [2k, 100k]):
+    the first `n_boxes` of the seeded 256, each at its seeded deformed state
+    with the ground contacts of tests/golden/batch_contacts.npz and seeded
+    sticking contact values, solved as one batch (setup + solve + VJP), FP64
+    and mixed, timed `nsolve` times after one untimed.  Returns a dict."""
+    import torch
+
+    from paper_2603_16478_amd import native
+    from synth.configs import batched_scenes, contact_values, perturbed_state
+
+    d = np.load(os.path.join(ROOT, "tests", "golden", "batch_contacts.npz"))
+    specs = batched_scenes(256, seed=3, tmax=1e5)[:n_boxes]
+    off = d["off"]
+    dev = "cuda"
+    keep, states, qs = [], [], []
+    for k, spec in enumerate(specs):
+        a, b = int(off[k]), int(off[k + 1])
+        n = b - a
+        delta, lam = contact_values(n, spec.mu, seed=200 + k)
+        t = {"vid": torch.tensor(d["vid"][a:b] if n else np.zeros(1, np.int32), dtype=torch.int32, device=dev),
+             "fric": torch.tensor(d["fric"][a:b].astype(np.int32) if n else np.zeros(1, np.int32), device=dev),
+             "frame": torch.tensor(d["frame"][a:b] if n else np.zeros((1, 9)), dtype=torch.float64, device=dev),
+             "delta": torch.tensor(delta if n else np.zeros((1, 3)), dtype=torch.float64, device=dev),
+             "lam": torch.tensor(lam if n else np.zeros((1, 3)), dtype=torch.float64, device=dev)}
+        keep.append(t)
+        states.append(native.make_contact_state(n, t["vid"], t["fric"], t["frame"], t["delta"], t["lam"], spec.mu))
+        qs.append(perturbed_state(spec, seed=100 + k))
+    s0 = specs[0]
+    t0 = time.perf_counter()
+    batch = native.Batch([(sp.mesh.rest, sp.mesh.tets, sp.E, sp.nu) for sp in specs], s0.density, s0.h, s0.eps,
+                         s0.gravity, s0.planes, s0.contact_margin,
+                         [max(1, int(off[k + 1] - off[k])) for k in range(len(specs))])
+    t_build = time.perf_counter() - t0
+    info = batch.union_scene().info()
+    print(f"{len(specs)} boxes: batch built in {t_build:.1f} s (nnz(S) {info['nnz_S']})", file=sys.stderr, flush=True)
+    rng = np.random.default_rng(300)
+    q = torch.tensor(np.concatenate(qs), device=dev)
+    gq = torch.tensor(rng.standard_normal(q.shape), device=dev)
+    gv = torch.zeros_like(gq)
+    z = torch.zeros_like(gq)
+    dq, dv, df = torch.empty_like(gq), torch.empty_like(gq), torch.empty_like(gq)
+    grad = torch.zeros(3 * len(specs), dtype=torch.float64, device=dev)
+    legs = {}
+    for name, prec in (("fp64", native.ADJ_FP64), ("mixed", native.ADJ_MIXED)):
+        o = native.solve_opts(rtol=1e-8, maxit=3000, restart=64, prec=prec, max_refine=8)
+        native.batch_setup(batch, states, q, o)  # warm-up (Delassus of this contact set)
+        native.batch_solve(batch, gq, gv, z, o, raise_noconv=False)
+        torch.cuda.synchronize()
+        its = []
+        t2 = time.perf_counter()
+        for _ in range(nsolve):
+            native.batch_setup(batch, states, q, o)
+            infos = native.batch_solve(batch, gq, gv, z, o, raise_noconv=False)
+            native.batch_vjp(batch, z, gv, dq, dv, df, grad)
+            its.append(max(i.iters for i in infos))
+            worst = max(i.relres for i in infos)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t2
+        legs[name] = {"value": len(specs) * nsolve / dt, "unit": "adjoint solves/s",
+                      "ms_per_batch": 1e3 * dt / nsolve, "krylov_iters_max_mean": float(np.mean(its)),
+                      "max_relres": worst}
+        print(f"{len(specs)} boxes {name}: {legs[name]['ms_per_batch']:.1f} ms per batch, "
+              f"{legs[name]['value']:.1f} solves/s, max relres {worst:.1e}", file=sys.stderr, flush=True)
+    legs["mixed"]["speedup_vs_fp64"] = legs["mixed"]["value"] / legs["fp64"]["value"]
+    batch.close()
+    return {"workload": f"batched boxes: the first {len(specs)} of 256 seeded boxes (log-uniform 2k-100k tets), "
+                        f"{sum(sp.n_tets for sp in specs)} tets, {sum(sp.n_verts for sp in specs)} vertices, "
+                        f"{int(off[len(specs)])} ground contacts; seeded deformed states and sticking values; "
+                        "GMRES(64) + Woodbury to 1e-8",
+            "batch_build_s": t_build, "nnz_S": info["nnz_S"], "adjoint": legs}
+
+
 def eps_sweep_one(two_eps2, side, seconds):
     """Down-slope displacement of one cube on the slope after `seconds` of
     simulated time with the GPU forward step (h = 0.01 s, warm-started
@@ -322,6 +396,10 @@ def main():
                     help="instead of the benchmark: the full-size slab adjoint, SOLVES timed solves in FP64 and in "
                          "mixed precision")
     ap.add_argument("--no-slab", action="store_true", help="skip the full-size slab leg")
+    ap.add_argument("--boxes", type=int, default=16,
+                    help="boxes of the batched-workload leg (first of the seeded 256; 0: skip)")
+    ap.add_argument("--boxes-only", action="store_true",
+                    help="instead of the benchmark: only the batched-workload leg, printed as one JSON line")
     ap.add_argument("--eps-sweep-one", nargs=3, metavar=("TWO_EPS2", "SIDE", "SECONDS"), help=argparse.SUPPRESS)
     ap.add_argument("--big-batch", type=int, default=4,
                     help="copies of the twelve recorded scene-steps in the large-batch leg (0: skip)")
@@ -333,6 +411,9 @@ def main():
 
     if args.slab > 0:
         print(json.dumps(slab_leg(args.slab)))
+        return
+    if args.boxes_only:
+        print(json.dumps(boxes_leg(args.boxes, max(1, args.steps // 10))))
         return
     if args.eps_sweep_one:
         eps_sweep_one(float(args.eps_sweep_one[0]), args.eps_sweep_one[1], float(args.eps_sweep_one[2]))
@@ -748,6 +829,8 @@ def main():
                                      "positions (compliance 1e-6 m/N), GMRES(64) + Woodbury to 1e-8; setup + "
                                      "solve + VJP + binding VJP per recorded scene-step"},
     }
+    if args.boxes > 0:
+        out["batched_boxes"] = boxes_leg(args.boxes, 2)
     if not args.no_slab:
         # the full-size slab (about 20 s of host factorisation, then two timed
         # solves per precision)
