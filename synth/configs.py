@@ -259,3 +259,34 @@ def contact_values(n: int, mu: float, seed: int = 13):
     delta[:, 1], delta[:, 2] = dmag * np.cos(ang), dmag * np.sin(ang)
     lam[:, 1], lam[:, 2] = -fmag * np.cos(ang), -fmag * np.sin(ang)
     return delta, lam
+
+
+def actuation_groups(mesh: VoxelMesh, n_groups: int = 64, seed: int = 6):
+    """Per-tet actuation group and fibre direction for an actuated mesh (the
+    quadruped's 64 muscle groups): the tets are binned by their centroid on
+    an 8 x 8 grid over (x, z) of the bounding box, each bin is one group, and
+    every group gets one seeded unit fibre direction.  Returns (group int32
+    [n_tets] in 0..n_groups-1, fibre [n_tets, 3])."""
+    if n_groups != 64:
+        raise ValueError("the grouping is an 8 x 8 grid")
+    rng = np.random.default_rng(seed)
+    c = mesh.rest[mesh.tets].mean(axis=1)
+    lo, hi = mesh.rest.min(axis=0), mesh.rest.max(axis=0)
+    ix = np.clip(((c[:, 0] - lo[0]) / (hi[0] - lo[0]) * 8).astype(int), 0, 7)
+    iz = np.clip(((c[:, 2] - lo[2]) / (hi[2] - lo[2]) * 8).astype(int), 0, 7)
+    group = (8 * ix + iz).astype(np.int32)
+    d = rng.standard_normal((n_groups, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    return group, d[group]
+
+
+def actuation_params(steps: int, n_groups: int = 64, h: float = 1e-3, amplitude: float = 1e4, seed: int = 7):
+    """Seeded sinusoidal actuation parameters a[t, k] = A_k sin(2 pi f_k t h +
+    phi_k) (active stress magnitudes, Pa), A_k ~ U[0.5, 1] amplitude, f_k ~
+    U[1, 4] Hz, phi_k ~ U[0, 2 pi].  Returns (steps, n_groups)."""
+    rng = np.random.default_rng(seed)
+    A = amplitude * rng.uniform(0.5, 1.0, n_groups)
+    f = rng.uniform(1.0, 4.0, n_groups)
+    ph = rng.uniform(0.0, 2.0 * np.pi, n_groups)
+    t = np.arange(steps)[:, None] * h
+    return A[None, :] * np.sin(2.0 * np.pi * f[None, :] * t + ph[None, :])
