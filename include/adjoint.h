@@ -241,6 +241,22 @@ adj_status adj_forward_reset(adj_scene* scene);
  * them.  Copies the poses to the device (synchronously). */
 adj_status adj_set_spheres(adj_scene* scene, int32_t n, const double* old_pose, const double* new_pose);
 
+/* Actuation by active stress (the actuated-body workloads): tet t belongs to
+ * group group[t] (host [n_tets], 0 .. n_groups-1) and has the fibre
+ * direction fibre[t] (host [n_tets][3]); with the group parameters a (Pa) it
+ * carries the first Piola stress a_g d d^T, whose nodal forces are
+ * f_v = -V_t a_g (d d^T) grad N_v.  The force is linear in a: f = Phi a.
+ * Copies the tables to the device (synchronises it). */
+adj_status adj_set_actuation(adj_scene* scene, int32_t n_groups, const int32_t* group, const double* fibre);
+
+/* f = Phi a: a device [n_groups], f device [n_verts*3] (overwritten), to be
+ * passed to sim_forward_step as (part of) the external force. */
+adj_status adj_actuation_force(adj_scene* scene, const double* a, double* f, void* stream);
+
+/* dL/da = Phi^T dL/df: dL_df device [n_verts*3] (the step's dL/df_ext from
+ * vjp_params), dL_da device [n_groups] (overwritten; fixed-order sums). */
+adj_status adj_actuation_vjp(adj_scene* scene, const double* dL_df, double* dL_da, void* stream);
+
 /* Scene sizes and host-side statistics: out[0] n_verts, out[1] n_tets,
  * out[2] nnz blocks of Acal, out[3] nnz(L), out[4] nnz(S), out[5]
  * max_contacts.  out: host [6]. */

@@ -43,6 +43,10 @@ void launch_vjp_contacts(hipStream_t, int, const int*, const double*, const doub
 void launch_vjp_vectors(hipStream_t, int, const double*, const double*, const double*, double, double*,
                         double*, double*);
 void launch_fill_zero(hipStream_t, size_t, double*);
+void launch_actuation_force(hipStream_t, int, int, const int*, const double*, const double*, const double*,
+                            const int*, const int*, const double*, double*, double*);
+void launch_actuation_vjp(hipStream_t, int, int, const int*, const double*, const double*, const double*,
+                          const int*, const int*, const double*, double*, double*);
 void launch_scatter_ht(hipStream_t, int, const int*, const int*, const int*, const int*, const double*,
                        const double*, const GmresState*, double*);
 void launch_delassus(hipStream_t, int, int, const int*, const long long*, const int*, const double*,
@@ -224,6 +228,11 @@ struct adj_scene {
   // the scatter buffer d_wz and the product d_wz2 ([3 n_v] each)
   bool use_z = true, z_built = false;
   double *d_wz = nullptr, *d_wz2 = nullptr;
+  // actuation (active stress per tet group): group and fibre per tet, the
+  // tets of each group (CSR), per-tet scratch
+  int n_act = 0;
+  int *d_act_group = nullptr, *d_act_gptr = nullptr, *d_act_gtets = nullptr;
+  double *d_act_fibre = nullptr, *d_act12 = nullptr, *d_act_s = nullptr;
   int n_spheres = 0, sph_cap = 0;  // sph_cap: spheres d_sph has room for
   std::vector<double> sph;
   double* d_sph = nullptr;
@@ -292,6 +301,7 @@ static void free_scene(adj_scene* s) {
                   s->d_y,        s->d_r,      s->d_b,     s->d_dz,          s->d_xt,
                   s->d_Stasks,   s->d_STtasks, s->d_planes,  s->d_vptr,   s->d_vcode, s->d_sph,
                   s->d_wz,       s->d_wz2,    s->d_gj_tiles, s->d_gj_one, s->d_gj_xoff, s->d_gj_P,
+                  s->d_act_group, s->d_act_gptr, s->d_act_gtets, s->d_act_fibre, s->d_act12, s->d_act_s,
                   s->d_mask,     s->d_fvid,   s->d_force, s->d_utilde,      s->d_qtilde,
                   s->d_fu,       s->d_du,     s->d_ut,    s->d_qcur,        s->d_rq,
                   s->d_rhs,      s->d_cvec,   s->d_cu,    s->d_norms,       s->d_Sx32,
@@ -1833,6 +1843,62 @@ extern "C" adj_status sim_forward_step(adj_scene* s, const double* qbar, const d
   }
   s->fwd_residual = worst;
   if (!(worst <= 1e-8)) return fail(ADJ_E_NOCONV, "forward Newton residual " + std::to_string(worst));
+  return ADJ_OK;
+}
+
+extern "C" adj_status adj_set_actuation(adj_scene* s, int32_t n_groups, const int32_t* group, const double* fibre) {
+  if (!s) return fail(ADJ_E_ARG, "scene is null");
+  if (n_groups < 1 || n_groups > 65536 || !group || !fibre) return fail(ADJ_E_ARG, "invalid actuation groups");
+  std::vector<int> gptr(n_groups + 1, 0), gtets(s->nt);
+  for (int t = 0; t < s->nt; ++t) {
+    if (group[t] < 0 || group[t] >= n_groups) return fail(ADJ_E_ARG, "actuation group out of range");
+    const double* d = fibre + 3 * (size_t)t;
+    if (!std::isfinite(d[0]) || !std::isfinite(d[1]) || !std::isfinite(d[2])) return fail(ADJ_E_ARG, "non-finite fibre");
+    gptr[group[t] + 1]++;
+  }
+  for (int g = 0; g < n_groups; ++g) gptr[g + 1] += gptr[g];
+  {
+    std::vector<int> fill(gptr.begin(), gptr.end() - 1);
+    for (int t = 0; t < s->nt; ++t) gtets[fill[group[t]]++] = t;  // tets of a group in index order
+  }
+  HIPCHK(hipDeviceSynchronize());  // earlier actuation calls may still read the old tables
+  for (void* p : {(void*)s->d_act_group, (void*)s->d_act_gptr, (void*)s->d_act_gtets, (void*)s->d_act_fibre,
+                  (void*)s->d_act12, (void*)s->d_act_s})
+    if (p) HIPCHK(hipFree(p));
+  s->d_act_group = s->d_act_gptr = s->d_act_gtets = nullptr;
+  s->d_act_fibre = s->d_act12 = s->d_act_s = nullptr;
+  s->n_act = 0;
+  const size_t nt = (size_t)s->nt;
+  if (hipMalloc(&s->d_act_group, nt * sizeof(int)) != hipSuccess ||
+      hipMalloc(&s->d_act_gptr, (n_groups + 1) * sizeof(int)) != hipSuccess ||
+      hipMalloc(&s->d_act_gtets, nt * sizeof(int)) != hipSuccess ||
+      hipMalloc(&s->d_act_fibre, 3 * nt * sizeof(double)) != hipSuccess ||
+      hipMalloc(&s->d_act12, 12 * nt * sizeof(double)) != hipSuccess ||
+      hipMalloc(&s->d_act_s, nt * sizeof(double)) != hipSuccess)
+    return fail(ADJ_E_OOM, "actuation tables");
+  HIPCHK(hipMemcpy(s->d_act_group, group, nt * sizeof(int), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(s->d_act_gptr, gptr.data(), (n_groups + 1) * sizeof(int), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(s->d_act_gtets, gtets.data(), nt * sizeof(int), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(s->d_act_fibre, fibre, 3 * nt * sizeof(double), hipMemcpyHostToDevice));
+  s->n_act = n_groups;
+  return ADJ_OK;
+}
+
+extern "C" adj_status adj_actuation_force(adj_scene* s, const double* a, double* f, void* stream) {
+  if (!s || !a || !f) return fail(ADJ_E_ARG, "null argument");
+  if (!s->n_act) return fail(ADJ_E_ARG, "adj_set_actuation has not run on this scene");
+  launch_actuation_force((hipStream_t)stream, s->nt, s->nv, s->d_act_group, s->d_act_fibre, s->d_Bt, s->d_vol,
+                         s->d_vptr, s->d_vcode, a, s->d_act12, f);
+  HIPCHK(hipGetLastError());
+  return ADJ_OK;
+}
+
+extern "C" adj_status adj_actuation_vjp(adj_scene* s, const double* dL_df, double* dL_da, void* stream) {
+  if (!s || !dL_df || !dL_da) return fail(ADJ_E_ARG, "null argument");
+  if (!s->n_act) return fail(ADJ_E_ARG, "adj_set_actuation has not run on this scene");
+  launch_actuation_vjp((hipStream_t)stream, s->nt, s->n_act, s->d_tets, s->d_act_fibre, s->d_Bt, s->d_vol,
+                       s->d_act_gptr, s->d_act_gtets, dL_df, s->d_act_s, dL_da);
+  HIPCHK(hipGetLastError());
   return ADJ_OK;
 }
 

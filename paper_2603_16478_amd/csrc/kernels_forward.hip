@@ -221,6 +221,88 @@ void launch_fwd_detect(hipStream_t st, int nv, const double* qbar, const double*
                                                  margin, mask);
 }
 
+// ---- active stress of an actuated body: tet t of group g carries the
+// first Piola stress a_g d d^T (fibre d), nodal force -V a_g (d d^T) grad N_k.
+
+__global__ void k_act_tet(int nt, const int* __restrict__ group, const double* __restrict__ fibre,
+                          const double* __restrict__ Bt, const double* __restrict__ vol, const double* __restrict__ a,
+                          double* __restrict__ out) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nt) return;
+  const double d0 = fibre[3 * t], d1 = fibre[3 * t + 1], d2 = fibre[3 * t + 2];
+  const double sc = -vol[t] * a[group[t]];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const double* g = Bt + 12 * (size_t)t + 3 * k;
+    const double c = sc * (d0 * g[0] + d1 * g[1] + d2 * g[2]);
+    double* o = out + 12 * (size_t)t + 3 * k;
+    o[0] = c * d0;
+    o[1] = c * d1;
+    o[2] = c * d2;
+  }
+}
+
+// out_v = sum over the incident (tet, corner) pairs of the per-tet values
+__global__ void k_gather_vec(int nv, const int* __restrict__ vptr, const int* __restrict__ vcode,
+                             const double* __restrict__ v12, double* __restrict__ out) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= nv) return;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+  for (int p = vptr[v]; p < vptr[v + 1]; ++p) {
+    const int code = vcode[p];
+    const double* f = v12 + 12 * (size_t)(code >> 2) + 3 * (code & 3);
+    a0 += f[0];
+    a1 += f[1];
+    a2 += f[2];
+  }
+  out[3 * v] = a0;
+  out[3 * v + 1] = a1;
+  out[3 * v + 2] = a2;
+}
+
+// s_t = -V_t sum_k (g_{v_k} . d)(d . grad N_k): tet t's share of dL/da_g
+__global__ void k_act_vjp_tet(int nt, const int* __restrict__ tets, const double* __restrict__ fibre,
+                              const double* __restrict__ Bt, const double* __restrict__ vol,
+                              const double* __restrict__ g, double* __restrict__ s) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nt) return;
+  const double d0 = fibre[3 * t], d1 = fibre[3 * t + 1], d2 = fibre[3 * t + 2];
+  double acc = 0.0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int v = tets[4 * t + k];
+    const double* b = Bt + 12 * (size_t)t + 3 * k;
+    acc += (g[3 * v] * d0 + g[3 * v + 1] * d1 + g[3 * v + 2] * d2) * (d0 * b[0] + d1 * b[1] + d2 * b[2]);
+  }
+  s[t] = -vol[t] * acc;
+}
+
+// out[g] = sum of s over the tets of group g in list order (one block per group)
+__global__ void __launch_bounds__(256) k_group_sum(int ng, const int* __restrict__ gptr, const int* __restrict__ gtets,
+                                                   const double* __restrict__ s, double* __restrict__ out) {
+  __shared__ double lds[32];
+  const int g = blockIdx.x;
+  if (g >= ng) return;
+  double a = 0.0;
+  for (int p = gptr[g] + threadIdx.x; p < gptr[g + 1]; p += blockDim.x) a += s[gtets[p]];
+  a = block_sum(a, lds);
+  if (threadIdx.x == 0) out[g] = a;
+}
+
+void launch_actuation_force(hipStream_t st, int nt, int nv, const int* group, const double* fibre, const double* Bt,
+                            const double* vol, const int* vptr, const int* vcode, const double* a, double* buf12,
+                            double* f) {
+  k_act_tet<<<(nt + 255) / 256, 256, 0, st>>>(nt, group, fibre, Bt, vol, a, buf12);
+  k_gather_vec<<<(nv + 255) / 256, 256, 0, st>>>(nv, vptr, vcode, buf12, f);
+}
+
+void launch_actuation_vjp(hipStream_t st, int nt, int ng, const int* tets, const double* fibre, const double* Bt,
+                          const double* vol, const int* gptr, const int* gtets, const double* g, double* s,
+                          double* da) {
+  k_act_vjp_tet<<<(nt + 255) / 256, 256, 0, st>>>(nt, tets, fibre, Bt, vol, g, s);
+  k_group_sum<<<ng, 256, 0, st>>>(ng, gptr, gtets, s, da);
+}
+
 void launch_add_vec(hipStream_t st, long long n, const double* a, const double* b, double alpha, double* out) {
   k_add_vec<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(n, a, b, alpha, out);
 }

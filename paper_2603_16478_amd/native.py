@@ -31,6 +31,7 @@ MATERIAL_CODES = {"nh": MAT_NEO_HOOKEAN, "arap": MAT_ARAP, "corot": MAT_COROT}
 EXPORTS = ("adj_scene_create", "adj_scene_destroy", "adjoint_setup", "adjoint_solve", "vjp_params",
            "sim_forward_step", "adj_scene_info", "adj_check_status", "adj_debug_export",
            "adj_profile_begin", "adj_profile_end", "adj_forward_stats", "adj_forward_reset", "adj_set_spheres",
+           "adj_set_actuation", "adj_actuation_force", "adj_actuation_vjp",
            "adj_set_tuning", "adj_get_tuning", "adj_autotune", "adj_batch_create", "adj_batch_destroy",
            "adj_batch_info", "adj_batch_setup", "adj_batch_solve", "adj_batch_vjp", "adj_batch_check_status",
            "adj_batch_debug_export", "adj_batch_scene", "adj_batch_reverse", "adj_binding_vjp",
@@ -105,6 +106,9 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.adj_forward_stats.argtypes = [vp, C.POINTER(C.c_double)]
     lib.adj_forward_reset.argtypes = [vp]
     lib.adj_set_spheres.argtypes = [vp, C.c_int32, vp, vp]
+    lib.adj_set_actuation.argtypes = [vp, C.c_int32, vp, vp]
+    lib.adj_actuation_force.argtypes = [vp, vp, vp, vp]
+    lib.adj_actuation_vjp.argtypes = [vp, vp, vp, vp]
     lib.adj_profile_end.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
     lib.adj_set_tuning.argtypes = [vp, C.POINTER(Tuning)]
     lib.adj_get_tuning.argtypes = [vp, C.POINTER(Tuning)]
@@ -290,6 +294,26 @@ def forward_stats(scene: Scene):
 
 def forward_reset(scene: Scene):
     check(load().adj_forward_reset(scene.handle))
+
+
+def set_actuation(scene: Scene, group, fibre, n_groups):
+    """Actuation groups (0 .. n_groups-1) and fibre directions per tet
+    (adj_set_actuation)."""
+    g = np.ascontiguousarray(group, dtype=np.int32)
+    d = np.ascontiguousarray(np.asarray(fibre, dtype=np.float64).reshape(-1, 3))
+    if g.shape[0] != scene.n_tets or d.shape[0] != scene.n_tets:
+        raise ValueError("one group and one fibre per tet")
+    check(load().adj_set_actuation(scene.handle, int(n_groups), g.ctypes.data, d.ctypes.data))
+
+
+def actuation_force(scene: Scene, a, f, stream=None):
+    """f = Phi a (adj_actuation_force)."""
+    check(load().adj_actuation_force(scene.handle, _ptr(a), _ptr(f), _stream(stream)))
+
+
+def actuation_vjp(scene: Scene, dL_df, dL_da, stream=None):
+    """dL/da = Phi^T dL/df (adj_actuation_vjp)."""
+    check(load().adj_actuation_vjp(scene.handle, _ptr(dL_df), _ptr(dL_da), _stream(stream)))
 
 
 def set_spheres(scene: Scene, old_pose, new_pose):

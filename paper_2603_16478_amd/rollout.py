@@ -138,6 +138,30 @@ class Rollout(torch.autograd.Function):
         return out["dq0"], out["dv0"], out["dforces"], None, None, None
 
 
+class Actuation(torch.autograd.Function):
+    """a[T, G] -> forces[T, n, 3]: the external force of each step from the
+    actuation parameters, f_t = Phi a_t (adj_actuation_force); backward
+    dL/da_t = Phi^T dL/df_t (adj_actuation_vjp).  The scene's actuation
+    tables come from native.set_actuation."""
+
+    @staticmethod
+    def forward(ctx, a, sim):
+        T, G = a.shape
+        f = torch.empty((T, sim.spec.n_verts, 3), dtype=torch.float64, device=a.device)
+        for t in range(T):
+            native.actuation_force(sim.scene, a[t].contiguous(), f[t])
+        ctx.sim, ctx.G = sim, G
+        return f
+
+    @staticmethod
+    def backward(ctx, gf):
+        T = gf.shape[0]
+        da = torch.empty((T, ctx.G), dtype=torch.float64, device=gf.device)
+        for t in range(T):
+            native.actuation_vjp(ctx.sim.scene, gf[t].contiguous(), da[t])
+        return da, None
+
+
 def rollout_with_param_grads(sim, q0, v0, forces, mu, loss_dir, checkpoint=None):
     """Forward + backward for the linear loss L = sum(loss_dir * q_T).
     Returns (L, grads) with grads = dq0, dv0, dforces, dE, dnu, dmu."""

@@ -263,18 +263,18 @@ def contact_values(n: int, mu: float, seed: int = 13):
 
 def actuation_groups(mesh: VoxelMesh, n_groups: int = 64, seed: int = 6):
     """Per-tet actuation group and fibre direction for an actuated mesh (the
-    quadruped's 64 muscle groups): the tets are binned by their centroid on
-    an 8 x 8 grid over (x, z) of the bounding box, each bin is one group, and
-    every group gets one seeded unit fibre direction.  Returns (group int32
-    [n_tets] in 0..n_groups-1, fibre [n_tets, 3])."""
-    if n_groups != 64:
-        raise ValueError("the grouping is an 8 x 8 grid")
+    quadruped's 64 muscle groups): the tets are split by centroid x into 8
+    slices of equal count, each slice by centroid z into 8 groups of equal
+    count, and every group gets one seeded unit fibre direction.  Returns
+    (group int32 [n_tets] in 0..n_groups-1, fibre [n_tets, 3])."""
+    if n_groups != 64 or mesh.n_tets < 64:
+        raise ValueError("the grouping is 8 x 8 equal-count bins")
     rng = np.random.default_rng(seed)
     c = mesh.rest[mesh.tets].mean(axis=1)
-    lo, hi = mesh.rest.min(axis=0), mesh.rest.max(axis=0)
-    ix = np.clip(((c[:, 0] - lo[0]) / (hi[0] - lo[0]) * 8).astype(int), 0, 7)
-    iz = np.clip(((c[:, 2] - lo[2]) / (hi[2] - lo[2]) * 8).astype(int), 0, 7)
-    group = (8 * ix + iz).astype(np.int32)
+    group = np.zeros(mesh.n_tets, dtype=np.int32)
+    for ix, sl in enumerate(np.array_split(np.lexsort((c[:, 2], c[:, 0])), 8)):
+        for iz, part in enumerate(np.array_split(sl[np.lexsort((c[sl, 0], c[sl, 2]))], 8)):
+            group[part] = 8 * ix + iz
     d = rng.standard_normal((n_groups, 3))
     d /= np.linalg.norm(d, axis=1, keepdims=True)
     return group, d[group]
