@@ -247,6 +247,53 @@ def boxes_leg(n_boxes, nsolve):
             "batch_build_s": t_build, "nnz_S": info["nnz_S"], "adjoint": legs}
 
 
+def quadruped_leg(steps, checkpoint):
+    """The actuated quadruped (30,720 tets, 6,649 vertices, feet on the
+    ground, mu 0.8): `steps` GPU forward steps driven by 64 seeded sinusoidal
+    active-stress parameters per step, then the gradient of the
+    centre-of-mass x shift with respect to the steps x 64 parameters through
+    the Actuation and Rollout autograd layers (checkpoints every
+    `checkpoint` steps, segments recomputed).  Returns a dict."""
+    import torch
+
+    from paper_2603_16478_amd import native
+    from paper_2603_16478_amd.rollout import Actuation, GpuSim, Rollout
+    from synth.configs import actuation_groups, actuation_params, quadruped_scene
+
+    spec = quadruped_scene()
+    group, fibre = actuation_groups(spec.mesh)
+    sim = GpuSim(spec, max_contacts=400)
+    native.set_actuation(sim.scene, group, fibre, 64)
+    dev = "cuda"
+    q0 = torch.tensor(spec.q0, device=dev)
+    v0 = torch.tensor(spec.v0, device=dev)
+    # centre-of-mass weights: the lumped vertex masses (density x a quarter
+    # of each incident tet's volume)
+    x = spec.mesh.rest[spec.mesh.tets]
+    vol = np.abs(np.linalg.det(np.stack([x[:, 1] - x[:, 0], x[:, 2] - x[:, 0], x[:, 3] - x[:, 0]], axis=2))) / 6.0
+    m = np.zeros(spec.n_verts)
+    np.add.at(m, spec.mesh.tets.reshape(-1), np.repeat(vol / 4.0, 4))
+    w = np.zeros((spec.n_verts, 3))
+    w[:, 0] = -m / m.sum()
+    wt = torch.tensor(w, device=dev)
+    a = torch.tensor(actuation_params(steps, amplitude=2e3), device=dev, requires_grad=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    qT, _ = Rollout.apply(q0, v0, Actuation.apply(a, sim), sim, spec.mu, checkpoint)
+    L = torch.sum(wt * qT)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    L.backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    print(f"quadruped: {steps} steps, forward {t1 - t0:.1f} s, backward {t2 - t1:.1f} s", file=sys.stderr, flush=True)
+    return {"workload": f"actuated quadruped (30,720 tets, 6,649 vertices), {steps} steps at h = 1e-3, 64 seeded "
+                        f"sinusoidal active-stress parameters per step, checkpoints every {checkpoint} steps",
+            "forward_steps_per_s": steps / (t1 - t0), "backward_steps_per_s": steps / (t2 - t1),
+            "com_x_shift_m": -float(L.detach()) - float(np.sum(-w[:, 0] * spec.q0[:, 0])),
+            "grad_norm": float(a.grad.norm())}
+
+
 def eps_sweep_one(two_eps2, side, seconds):
     """Down-slope displacement of one cube on the slope after `seconds` of
     simulated time with the GPU forward step (h = 0.01 s, warm-started
@@ -396,6 +443,8 @@ def main():
                     help="instead of the benchmark: the full-size slab adjoint, SOLVES timed solves in FP64 and in "
                          "mixed precision")
     ap.add_argument("--no-slab", action="store_true", help="skip the full-size slab leg")
+    ap.add_argument("--quadruped", type=int, default=0, metavar="STEPS",
+                    help="instead of the benchmark: the actuated quadruped rollout and its actuation gradient")
     ap.add_argument("--boxes", type=int, default=16,
                     help="boxes of the batched-workload leg (first of the seeded 256; 0: skip)")
     ap.add_argument("--boxes-only", action="store_true",
@@ -411,6 +460,9 @@ def main():
 
     if args.slab > 0:
         print(json.dumps(slab_leg(args.slab)))
+        return
+    if args.quadruped > 0:
+        print(json.dumps(quadruped_leg(args.quadruped, max(1, args.quadruped // 4))))
         return
     if args.boxes_only:
         print(json.dumps(boxes_leg(args.boxes, max(1, args.steps // 10))))
