@@ -3,7 +3,8 @@ Test infrastructure only.
 
 The paper takes the forward solver from prior work and does not restate it;
 the adjoint only needs its converged fixed point.  This module solves the same
-residual with a damped Newton method (reading documented in the design doc):
+residual with a damped Newton method (a reading of our own, since the paper
+does not give one):
 
   unknowns   q (3 n_v), lambda_n per contact, s per frictional contact, where
              the friction force is lambda_f = -s delta_f/|delta_f| (its
