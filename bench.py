@@ -56,7 +56,8 @@ CSRC = os.path.join(ROOT, "paper_2603_16478_amd", "csrc")
 # calibrated HBM traffic per launch from the committed counter runs, one file
 # per kernel, each tagged with a hash of the source it was measured on
 COUNTERS = {"s_product": os.path.join(ROOT, "profiles", "s_product_batched_beam_counters.json"),
-            "gj_step": os.path.join(ROOT, "profiles", "gj_step_batched_beam_counters.json")}
+            "gj_step": os.path.join(ROOT, "profiles", "gj_step_batched_beam_counters.json"),
+            "s_product_single": os.path.join(ROOT, "profiles", "s_product_slab_counters.json")}
 
 
 def load_states():
@@ -115,6 +116,9 @@ def kernel_source_hash(kernel):
     """Hash of the source text the kernel's counters depend on."""
     if kernel == "s_product":
         text = (_function_text(open(os.path.join(CSRC, "kernels_batch.hip")).read(), "kb_spmv_tasks") +
+                _function_text(open(os.path.join(CSRC, "device_common.h")).read(), "row_dot3"))
+    elif kernel == "s_product_single":
+        text = (_function_text(open(os.path.join(CSRC, "kernels_krylov.hip")).read(), "k_spmv_tasks") +
                 _function_text(open(os.path.join(CSRC, "device_common.h")).read(), "row_dot3"))
     else:
         src = open(os.path.join(CSRC, "kernels_dense.hip")).read()
@@ -384,7 +388,8 @@ def slab_leg(nsolve):
                       "s_product_avg_launch_us": avg_us, "s_product_launches": sl}
         if prec == native.ADJ_FP64 and sl:
             gbs = sbytes / (avg_us * 1e-6) / 1e9
-            legs[name] |= {"s_product_GB/s": gbs, "s_product_frac": gbs / HBM_PEAK_GBPS}
+            legs[name] |= {"s_product_GB/s": gbs, "s_product_frac": gbs / HBM_PEAK_GBPS,
+                           "s_product_traffic": measured_traffic("s_product_single")}
         print(f"slab adjoint {name}: {legs[name]['ms_per_solve']:.1f} ms per solve, iterations "
               f"{legs[name]['krylov_iters_mean']:.1f}, S product {avg_us:.0f} us per launch, first solve "
               f"{t_first:.2f} s", file=sys.stderr, flush=True)
