@@ -55,3 +55,26 @@ def test_binding_declares_argument_types_of_every_entry_point():
     lib = native.load()
     missing = [n for n in native.EXPORTS if n != "adj_last_error" and getattr(lib, n).argtypes is None]
     assert not missing, missing
+
+
+def test_enum_values_agree_with_the_binding():
+    """The enumerators of include/adjoint.h and the constants of the Python
+    binding (the two sides of the ABI) carry the same values."""
+    from paper_2603_16478_amd import native
+    src = re.sub(r"/\*.*?\*/", "", open(os.path.join(ROOT, "include", "adjoint.h")).read(), flags=re.S)
+    enums = {}
+    for body in re.findall(r"typedef enum\s*\{(.*?)\}", src, flags=re.S):
+        for name, val in re.findall(r"(\w+)\s*=\s*(-?\d+)", body):
+            enums[name] = int(val)
+    pairs = {"ADJ_FP64": native.ADJ_FP64, "ADJ_MIXED": native.ADJ_MIXED, "ADJ_AUTO": native.ADJ_AUTO,
+             "ADJ_GMRES": native.ADJ_GMRES, "ADJ_PCG": native.ADJ_PCG, "ADJ_SEMI_IMPLICIT": native.ADJ_SEMI_IMPLICIT,
+             "ADJ_PRECOND_WOODBURY": native.PRECOND_WOODBURY,
+             "ADJ_PRECOND_SPARSE_INVERSE": native.PRECOND_SPARSE_INVERSE,
+             "ADJ_PRECOND_JACOBI": native.PRECOND_JACOBI, "ADJ_PRECOND_POINT_JACOBI": native.PRECOND_POINT_JACOBI,
+             "ADJ_PRECOND_WOODBURY_NO_Z": native.PRECOND_WOODBURY_NO_Z,
+             "ADJ_MAT_NEO_HOOKEAN": native.MAT_NEO_HOOKEAN, "ADJ_MAT_ARAP": native.MAT_ARAP,
+             "ADJ_MAT_COROT": native.MAT_COROT}
+    for name, val in pairs.items():
+        assert enums[name] == val, name
+    for code, name in native.STATUS.items():
+        assert enums[name] == code, name
