@@ -78,3 +78,35 @@ def test_enum_values_agree_with_the_binding():
         assert enums[name] == val, name
     for code, name in native.STATUS.items():
         assert enums[name] == code, name
+
+
+def test_struct_layouts_agree_with_the_header(tmp_path):
+    """Size and field offsets of every struct of include/adjoint.h, as a C
+    compiler lays them out, equal those of the binding's ctypes mirrors."""
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        import pytest
+        pytest.skip("no C compiler")
+    from paper_2603_16478_amd import native
+    mirrors = {"adj_scene_desc": native.SceneDesc, "adj_contact_state": native.ContactState,
+               "adj_solve_opts": native.SolveOpts, "adj_solve_info": native.SolveInfo, "adj_tuning": native.Tuning}
+    # fields the binding names differently (a Python keyword in C)
+    cfield = {("adj_contact_state", "lam"): "lambda"}
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "adjoint.h"', "int main(void) {"]
+    for cname, py in mirrors.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            cf = cfield.get((cname, fname), fname)
+            lines.append(f'  printf("{cname} {fname} %zu\\n", offsetof({cname}, {cf}));')
+    lines.append("  return 0;\n}")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cname, py in mirrors.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
