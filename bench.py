@@ -283,7 +283,7 @@ def quadruped_leg(steps, checkpoint):
     a = torch.tensor(actuation_params(steps, amplitude=2e3), device=dev, requires_grad=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    qT, _ = Rollout.apply(q0, v0, Actuation.apply(a, sim), sim, spec.mu, checkpoint)
+    qT, _ = Rollout.apply(q0, v0, Actuation.apply(a, sim), sim.params(spec.mu), sim, checkpoint)
     L = torch.sum(wt * qT)
     torch.cuda.synchronize()
     t1 = time.perf_counter()

@@ -182,9 +182,11 @@ adj_status adj_scene_destroy(adj_scene* scene);
  * K^{-T} + h^2 H A^{-1} H^T with its inverse (eq:woodbury_formula).
  * q: device [n_verts*3] converged positions.  The contact state must stay
  * alive and unchanged until adjoint_solve and vjp_params have run.
- * Errors: ADJ_E_SHAPE (n_contacts > max_contacts), ADJ_E_ARG,
- * ADJ_E_INVERTED (reported after the stream synchronises, see
- * adj_check_status). */
+ * Errors: ADJ_E_SHAPE (n_contacts > max_contacts), ADJ_E_ARG.  Errors
+ * found on the device (ADJ_E_INVERTED: a tet with det F <= 0, whose blocks
+ * are then zero; ADJ_E_SINGULAR: a zero or non-finite capacitance pivot)
+ * raise a flag that this call clears first; they are returned by the next
+ * adjoint_solve (or adj_check_status) of the same scene. */
 adj_status adjoint_setup(adj_scene* scene, const adj_contact_state* contacts, const double* q,
                          const adj_solve_opts* opts, void* stream);
 
@@ -192,7 +194,10 @@ adj_status adjoint_setup(adj_scene* scene, const adj_contact_state* contacts, co
  * the Woodbury preconditioner (Sec. 5.4).  dL_dq, dL_dv: device
  * [n_verts*3]; z: device [n_verts*3] output.  Synchronises the stream at
  * the end (the iteration count and residual are host values).  Returns
- * ADJ_E_NOCONV if rtol was not met within maxit (z holds the last iterate). */
+ * ADJ_E_INVERTED or ADJ_E_SINGULAR when the last adjoint_setup raised that
+ * device flag (z is then meaningless), else ADJ_E_NOCONV if rtol was not
+ * met within maxit (z holds the last iterate), ADJ_E_SINGULAR for a
+ * non-finite residual. */
 adj_status adjoint_solve(adj_scene* scene, const double* dL_dq, const double* dL_dv, double* z,
                          const adj_solve_opts* opts, adj_solve_info* info, void* stream);
 
@@ -263,7 +268,8 @@ adj_status adj_actuation_vjp(adj_scene* scene, const double* dL_df, double* dL_d
 adj_status adj_scene_info(const adj_scene* scene, int64_t* out);
 
 /* Synchronise the stream and report device-side errors of the last setup
- * (ADJ_E_INVERTED when a tet had det F <= 0). */
+ * (ADJ_E_INVERTED when a tet had det F <= 0, ADJ_E_SINGULAR for a zero or
+ * non-finite capacitance pivot).  The flag is cleared by the next setup. */
 adj_status adj_check_status(adj_scene* scene, void* stream);
 
 /* Diagnostics: copy an internal array of the last adjoint_setup to host
@@ -359,7 +365,10 @@ adj_status adj_batch_setup(adj_batch* batch, const adj_contact_state* contacts, 
 /* One GMRES per scene on Acal_s^T z_s = dL_dq_s + dL_dv_s / h to opts->rtol
  * (each scene's own right-hand side norm); ADJ_MIXED as for adjoint_solve.
  * dL_dq, dL_dv, z: device packed; info: host [n_scenes] or NULL.
- * ADJ_E_NOCONV if any scene did not converge (z holds the best iterate). */
+ * ADJ_E_INVERTED / ADJ_E_SINGULAR when the last adj_batch_setup raised the
+ * device error flag (an inverted tet or a singular capacitance pivot in any
+ * scene), else ADJ_E_NOCONV if any scene did not converge (z holds the best
+ * iterate). */
 adj_status adj_batch_solve(adj_batch* batch, const double* dL_dq, const double* dL_dv, double* z,
                            const adj_solve_opts* opts, adj_solve_info* info, void* stream);
 

@@ -43,6 +43,7 @@ void launch_vjp_contacts(hipStream_t, int, const int*, const double*, const doub
 void launch_vjp_vectors(hipStream_t, int, const double*, const double*, const double*, double, double*,
                         double*, double*);
 void launch_fill_zero(hipStream_t, size_t, double*);
+void launch_fill_int(hipStream_t, size_t, int*, int);
 void launch_actuation_force(hipStream_t, int, int, const int*, const double*, const double*, const double*,
                             const int*, const int*, const double*, double*, double*);
 void launch_actuation_vjp(hipStream_t, int, int, const int*, const double*, const double*, const double*,
@@ -66,8 +67,8 @@ void launch_spmv_tasks(hipStream_t, int, const int4*, const long long*, const in
                        const double*, long long, const double*, const GmresState*, double*);
 void launch_spmv_tasks(hipStream_t, int, const int4*, const long long*, const int*, const float*,
                        const double*, long long, const double*, const GmresState*, double*);
-void launch_bsr_spmv(hipStream_t, int, int, const int*, const int*, const float*, const double*, double*,
-                     long long, const GmresState*);
+void launch_bsr_spmv(hipStream_t, int, int, const int*, const int*, const float*, const double*, const double*,
+                     double*, long long, const GmresState*);
 void launch_to_f32(hipStream_t, long long, const double*, float*);
 void launch_wb_gather(hipStream_t, int, int, const int*, const int*, const int*, const double*,
                       const double*, const double*, const GmresState*, double*);
@@ -80,8 +81,12 @@ int bsr_blocks(int, int);
 int vec_blocks(long long);
 void launch_bsr_dots(hipStream_t, int, int, const int*, const int*, const double*, const double*, double*,
                      long long, const GmresState*, int, double*);
-void launch_bsr_dots(hipStream_t, int, int, const int*, const int*, const float*, const double*, double*,
-                     long long, const GmresState*, int, double*);
+void launch_bsr_dots(hipStream_t, int, int, const int*, const int*, const float*, const double*, const double*,
+                     double*, long long, const GmresState*, int, double*);
+void launch_fold_partials(hipStream_t, double*, int, const GmresState*, int);
+void launch_spmv_tasks_acc(hipStream_t, int, const int4*, const long long*, const int*, const double*,
+                           const double*, double, const GmresState*, double*);
+void launch_gather_values(hipStream_t, long long, const long long*, const double*, double*);
 void launch_gm_update(hipStream_t, long long, int, double*, long long, const double*, const GmresState*,
                       const double*, int, double*, double*, int);
 void launch_gm_givens(hipStream_t, GmresState*, const double*, int, double*, const double*, double*, double*,
@@ -228,6 +233,16 @@ struct adj_scene {
   // the scatter buffer d_wz and the product d_wz2 ([3 n_v] each)
   bool use_z = true, z_built = false;
   double *d_wz = nullptr, *d_wz2 = nullptr;
+  // Without Z the correction is applied through Y = S E (the columns of S at
+  // the contact vertices, CSR by elimination row; columns are vertex ids):
+  // one S and one S^T product per apply plus two products with Y.  Tasks of
+  // the Y rows with entries, and of the contact-vertex rows of S^T.
+  long long *d_Yp = nullptr, *d_Ysrc = nullptr;
+  int *d_Ycol = nullptr, *d_Ytasks = nullptr, *d_CTtasks = nullptr;
+  double* d_Yval = nullptr;
+  int nY_tasks = 0, nCT_tasks = 0;
+  size_t cap_ynnz = 0, cap_ytasks = 0, cap_cttasks = 0;
+  long long y_nnz = 0;
   // actuation (active stress per tet group): group and fibre per tet, the
   // tets of each group (CSR), per-tet scratch
   int n_act = 0;
@@ -305,7 +320,8 @@ static void free_scene(adj_scene* s) {
                   s->d_mask,     s->d_fvid,   s->d_force, s->d_utilde,      s->d_qtilde,
                   s->d_fu,       s->d_du,     s->d_ut,    s->d_qcur,        s->d_rq,
                   s->d_rhs,      s->d_cvec,   s->d_cu,    s->d_norms,       s->d_Sx32,
-                  s->d_STx32,    s->d_val32,  s->d_Pws,   s->d_x_pcg, s->d_bvid, s->d_bE};
+                  s->d_STx32,    s->d_val32,  s->d_Pws,   s->d_x_pcg, s->d_bvid, s->d_bE,
+                  s->d_Yp,       s->d_Ysrc,   s->d_Ycol,  s->d_Ytasks,      s->d_CTtasks, s->d_Yval};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (s->h_state) (void)hipHostFree(s->h_state);
@@ -534,6 +550,82 @@ static void drop_chunk_graphs(adj_scene* s) {
 // Woodbury correction goes through S^T S at every apply instead.
 static const double kZBudget = 2e10;
 
+// Y = S E as CSR by elimination row (the correction without Z): column k of
+// Y is the column of S at contact vertex cv[k], i.e. row cv[k] of S^T, which
+// is nonzero exactly on the elimination-tree path from that vertex to the
+// root.  Rows list their contact vertices in increasing k (vertex order);
+// values are gathered on the device from S^T.  Also the task list of the
+// contact-vertex rows of S^T (the contact entries of A^{-1} r).
+static adj_status int_upload(int** p, size_t* cap, const std::vector<int32_t>& v, hipStream_t st) {
+  if (v.size() > *cap || !*p) {
+    if (*p) {
+      (void)hipDeviceSynchronize();
+      (void)hipFree(*p);
+    }
+    *p = nullptr;
+    *cap = 0;
+    if (hipMalloc(p, std::max<size_t>(v.size(), 1) * sizeof(int)) != hipSuccess) return fail(ADJ_E_OOM, "tasks");
+    *cap = v.size();
+  }
+  if (!v.empty()) HIPCHK(hipMemcpyAsync(*p, v.data(), v.size() * sizeof(int), hipMemcpyHostToDevice, st));
+  return ADJ_OK;
+}
+
+static adj_status build_y_rows(adj_scene* s, hipStream_t st, const std::vector<int>& cv) {
+  const HostScene& h = s->hs;
+  const int nv = s->nv, ncv = (int)cv.size();
+  std::vector<int64_t> yp(nv + 1, 0);
+  for (int k = 0; k < ncv; ++k)
+    for (int64_t p = h.STp[cv[k]]; p < h.STp[cv[k] + 1]; ++p) yp[h.STj[p] + 1]++;
+  for (int r = 0; r < nv; ++r) yp[r + 1] += yp[r];
+  const long long nnz = yp[nv];
+  std::vector<int32_t> ycol(nnz);
+  std::vector<int64_t> ysrc(nnz);
+  {
+    std::vector<int64_t> pos(yp.begin(), yp.end() - 1);
+    for (int k = 0; k < ncv; ++k)
+      for (int64_t p = h.STp[cv[k]]; p < h.STp[cv[k] + 1]; ++p) {
+        const int64_t o = pos[h.STj[p]]++;
+        ycol[o] = cv[k];
+        ysrc[o] = p;
+      }
+  }
+  const std::vector<int32_t> ytasks = make_row_tasks(yp, 1024, nullptr, true);
+  std::vector<int32_t> rows(cv.begin(), cv.end());
+  const std::vector<int32_t> cttasks = make_row_tasks(h.STp, 1024, &rows);
+  if ((size_t)nnz > s->cap_ynnz || !s->d_Ycol) {
+    (void)hipDeviceSynchronize();
+    for (void* p : {(void*)s->d_Ycol, (void*)s->d_Ysrc, (void*)s->d_Yval})
+      if (p) (void)hipFree(p);
+    s->d_Ycol = nullptr;
+    s->d_Ysrc = nullptr;
+    s->d_Yval = nullptr;
+    s->cap_ynnz = 0;
+    const size_t n = std::max<long long>(nnz, 1);
+    if (hipMalloc(&s->d_Ycol, n * sizeof(int)) != hipSuccess ||
+        hipMalloc(&s->d_Ysrc, n * sizeof(long long)) != hipSuccess ||
+        hipMalloc(&s->d_Yval, n * sizeof(double)) != hipSuccess)
+      return fail(ADJ_E_OOM, "Y rows of the Woodbury correction");
+    s->cap_ynnz = nnz;
+  }
+  if (!s->d_Yp && hipMalloc(&s->d_Yp, (size_t)(nv + 1) * sizeof(long long)) != hipSuccess)
+    return fail(ADJ_E_OOM, "Y row pointer");
+  HIPCHK(hipMemcpyAsync(s->d_Yp, yp.data(), (nv + 1) * sizeof(long long), hipMemcpyHostToDevice, st));
+  if (nnz) {
+    HIPCHK(hipMemcpyAsync(s->d_Ycol, ycol.data(), nnz * sizeof(int), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(s->d_Ysrc, ysrc.data(), nnz * sizeof(long long), hipMemcpyHostToDevice, st));
+  }
+  adj_status a;
+  if ((a = int_upload(&s->d_Ytasks, &s->cap_ytasks, ytasks, st)) != ADJ_OK) return a;
+  if ((a = int_upload(&s->d_CTtasks, &s->cap_cttasks, cttasks, st)) != ADJ_OK) return a;
+  launch_gather_values(st, nnz, s->d_Ysrc, s->d_STx, s->d_Yval);
+  HIPCHK(hipStreamSynchronize(st));  // the host vectors go out of scope
+  s->nY_tasks = (int)(ytasks.size() / 4);
+  s->nCT_tasks = (int)(cttasks.size() / 4);
+  s->y_nnz = nnz;
+  return ADJ_OK;
+}
+
 static adj_status contact_layout(adj_scene* s, hipStream_t st, int nc, const std::vector<int>& vid,
                                  const std::vector<int>& fric, bool reuse, bool delassus = true,
                                  bool force_no_z = false) {
@@ -594,6 +686,7 @@ static adj_status contact_layout(adj_scene* s, hipStream_t st, int nc, const std
     if (ks > 1 && (a = grow(&s->d_Pws, &s->cap_pws, (size_t)ks * ncv * ncv)) != ADJ_OK) return a;
     launch_delassus(st, s->nv, ncv, s->d_cv, s->d_STp, s->d_STj, s->d_STx, s->d_Y, s->d_D, use_z ? s->d_Z : nullptr,
                     s->d_Pws);
+    if (!use_z && (a = build_y_rows(s, st, cv)) != ADJ_OK) return a;
     s->cv_cached = cv;
     s->delassus_valid = true;
     s->delassus_rebuilt = 1;
@@ -694,7 +787,9 @@ extern "C" adj_status adjoint_setup(adj_scene* s, const adj_contact_state* cst, 
   s->cur_vid = cst->vid;
   s->cur_frame = cst->frame;
   s->cur_q = q;
-  // a1 + a2: per-tet Jacobians, gather assembly of Acal^T
+  // a1 + a2: per-tet Jacobians, gather assembly of Acal^T; the device error
+  // flag (inverted element, singular capacitance pivot) starts clear
+  launch_fill_int(st, 1, s->d_err, 0);
   {
     ProfScope p(s, 5, st);
     launch_tet_blocks(st, s->nt, s->d_tets, s->d_Bt, s->d_vol, s->d_lmu, s->d_llam, h2, q, s->d_tetblk,
@@ -752,10 +847,8 @@ static void apply_precond(adj_scene* s, hipStream_t st, const double* x, long lo
   const double h2 = s->hs.h * s->hs.h;
   if (s->precond == ADJ_PRECOND_JACOBI || s->precond == ADJ_PRECOND_POINT_JACOBI) {
     const int point = s->precond == ADJ_PRECOND_POINT_JACOBI ? 1 : 0;
-    if (f32)
-      launch_block_jacobi(st, s->nv, s->d_diag_slot, s->d_val32, x, stride, scale, state, point, out);
-    else
-      launch_block_jacobi(st, s->nv, s->d_diag_slot, s->d_val, x, stride, scale, state, point, out);
+    // the diagonal blocks are read in FP64 in both modes (they hold the stiff contact terms)
+    launch_block_jacobi(st, s->nv, s->d_diag_slot, s->d_val, x, stride, scale, state, point, out);
     return;
   }
   const bool woodbury =
@@ -768,6 +861,43 @@ static void apply_precond(adj_scene* s, hipStream_t st, const double* x, long lo
     else
       launch_spmv_tasks(st, s->nS_tasks, (const int4*)s->d_Stasks, s->d_Sp, s->d_Sj, s->d_Sx, x, stride,
                         scale, state, s->d_t1);
+  }
+  if (woodbury && !s->use_z) {
+    // Correction through Y = S E:  A^{-1} r - h^2 A^{-1} H^T t' =
+    // S^T (S r - h^2 Y H^T t'), with t' = X H A^{-1} r and H A^{-1} r the
+    // contact-vertex rows of S^T (S r) (= Y^T S r).  One S and one S^T
+    // product per apply; Y and the contact rows are FP64 in both modes, so
+    // that H out = (I - h^2 Y^T Y X) H A^{-1} r holds with the same Y as the
+    // Delassus matrix D = Y^T Y of X: for stiff contacts the correction
+    // cancels A^{-1} r almost exactly in the contact directions, and any
+    // inconsistency there would be amplified by the contact-to-elastic
+    // stiffness ratio.  With FP32 products the contact rows of the result
+    // are therefore recomputed in FP64 from the same S r.
+    launch_spmv_tasks(st, s->nCT_tasks, (const int4*)s->d_CTtasks, s->d_STp, s->d_STj, s->d_STx, s->d_t1, 0, nullptr,
+                      state, s->d_u);
+    {
+      ProfScope p(s, 2, st);
+      launch_wb_gather(st, s->m, s->mp, s->d_row_c, s->d_row_i, s->cur_vid, s->d_Q, s->d_X, s->d_u, state,
+                       s->d_tvec);
+    }
+    ProfScope p(s, 3, st);
+    launch_fill_zero(st, (size_t)s->n3, s->d_wz);
+    launch_scatter_ht(st, s->ncv, s->d_cv, s->d_cv_ptr, s->d_c_row0, s->d_c_nrow, s->d_Q, s->d_tvec, state, s->d_wz);
+    launch_spmv_tasks_acc(st, s->nY_tasks, (const int4*)s->d_Ytasks, s->d_Yp, s->d_Ycol, s->d_Yval, s->d_wz, -h2,
+                          state, s->d_t1);
+    {
+      ProfScope p1(s, 1, st);
+      if (f32)
+        launch_spmv_tasks(st, s->nST_tasks, (const int4*)s->d_STtasks, s->d_STp, s->d_STj, s->d_STx32, s->d_t1,
+                          0, nullptr, state, out);
+      else
+        launch_spmv_tasks(st, s->nST_tasks, (const int4*)s->d_STtasks, s->d_STp, s->d_STj, s->d_STx, s->d_t1,
+                          0, nullptr, state, out);
+    }
+    if (f32)
+      launch_spmv_tasks(st, s->nCT_tasks, (const int4*)s->d_CTtasks, s->d_STp, s->d_STj, s->d_STx, s->d_t1, 0,
+                        nullptr, state, out);
+    return;
   }
   double* u = woodbury ? s->d_u : out;
   {
@@ -791,24 +921,13 @@ static void apply_precond(adj_scene* s, hipStream_t st, const double* x, long lo
                       s->d_u, state, out);
     return;
   }
-  // out = u - h^2 S^T S (H^T t'): scatter the contact-space vector, two
-  // sparse-inverse products, one update.  These products stay FP64 in the
-  // mixed mode as Z does: for stiff contacts the correction cancels A^{-1} r
-  // almost exactly, and its rounding would be amplified by the contact-to-
-  // elastic stiffness ratio.
-  launch_fill_zero(st, (size_t)s->n3, s->d_wz);
-  launch_scatter_ht(st, s->ncv, s->d_cv, s->d_cv_ptr, s->d_c_row0, s->d_c_nrow, s->d_Q, s->d_tvec, state, s->d_wz);
-  launch_spmv_tasks(st, s->nS_tasks, (const int4*)s->d_Stasks, s->d_Sp, s->d_Sj, s->d_Sx, s->d_wz, 0, nullptr, state,
-                    s->d_t1);
-  launch_spmv_tasks(st, s->nST_tasks, (const int4*)s->d_STtasks, s->d_STp, s->d_STj, s->d_STx, s->d_t1, 0, nullptr,
-                    state, s->d_wz2);
-  launch_add_vec(st, s->n3, s->d_u, s->d_wz2, -h2, out);
 }
 
 static void bsr(adj_scene* s, hipStream_t st, const double* x, double* outbase, long long stride,
                 const GmresState* state, bool f32) {
   if (f32)
-    launch_bsr_spmv(st, s->tune.bsr_lanes, s->nv, s->d_rowptr, s->d_col, s->d_val32, x, outbase, stride, state);
+    launch_bsr_spmv(st, s->tune.bsr_lanes, s->nv, s->d_rowptr, s->d_col, s->d_val32, s->d_val, x, outbase, stride,
+                    state);
   else
     launch_bsr_spmv(st, s->tune.bsr_lanes, s->nv, s->d_rowptr, s->d_col, s->d_val, x, outbase, stride, state);
 }
@@ -819,28 +938,34 @@ static void bsr(adj_scene* s, hipStream_t st, const double* x, double* outbase, 
 // one-block Givens step.
 static void gmres_chunk(adj_scene* s, hipStream_t st, bool f32) {
   const long long n3 = s->n3, stride = n3;
-  const int nb1 = bsr_blocks(s->nv, s->tune.bsr_lanes), nb2 = gm_blocks(n3, s->tune.gs_rows);
+  // above kFoldAt partial blocks the Gram-Schmidt dots are folded once by a
+  // separate launch instead of re-added by every block of the next kernel
+  constexpr int kFoldAt = 256;
+  const int nb1_raw = bsr_blocks(s->nv, s->tune.bsr_lanes), nb2_raw = gm_blocks(n3, s->tune.gs_rows);
+  const int nb1 = nb1_raw > kFoldAt ? 1 : nb1_raw, nb2 = nb2_raw > kFoldAt ? 1 : nb2_raw;
   for (int k = 0; k < s->tune.chunk; ++k) {
     apply_precond(s, st, s->d_Vt, stride, s->d_scale, s->d_state, s->d_y, f32);
     {
       ProfScope p(s, 4, st);
       if (f32)
-        launch_bsr_dots(st, s->tune.bsr_lanes, s->nv, s->d_rowptr, s->d_col, s->d_val32, s->d_y, s->d_Vt, stride,
+        launch_bsr_dots(st, s->tune.bsr_lanes, s->nv, s->d_rowptr, s->d_col, s->d_val32, s->d_val, s->d_y, s->d_Vt, stride,
                         s->d_state, -1, s->P1());
       else
         launch_bsr_dots(st, s->tune.bsr_lanes, s->nv, s->d_rowptr, s->d_col, s->d_val, s->d_y, s->d_Vt, stride,
                         s->d_state, -1, s->P1());
     }
+    if (nb1_raw > kFoldAt) launch_fold_partials(st, s->P1(), nb1_raw, s->d_state, 0);
     {
       ProfScope p(s, 9, st);
       launch_gm_update(st, n3, s->tune.gs_rows, s->d_Vt, stride, s->d_scale, s->d_state, s->P1(), nb1, s->P2(),
                        s->d_hbuf, 0);
     }
+    if (nb2_raw > kFoldAt) launch_fold_partials(st, s->P2(), nb2_raw, s->d_state, 0);
     {
       ProfScope p(s, 8, st);
       launch_gm_update(st, n3, s->tune.gs_rows, s->d_Vt, stride, s->d_scale, s->d_state, s->P2(), nb2, s->P3(),
                        s->d_hbuf, 1);
-      launch_gm_givens(st, s->d_state, s->P3(), nb2, s->d_scale, s->d_hbuf, s->d_H, s->d_cs, s->d_sn, s->d_g);
+      launch_gm_givens(st, s->d_state, s->P3(), nb2_raw, s->d_scale, s->d_hbuf, s->d_H, s->d_cs, s->d_sn, s->d_g);
     }
   }
 }
@@ -857,7 +982,7 @@ static void pcg_chunk(adj_scene* s, hipStream_t st, bool f32) {
     {
       ProfScope pr(s, 4, st);
       if (f32)
-        launch_bsr_dots(st, s->tune.bsr_lanes, s->nv, s->d_rowptr, s->d_col, s->d_val32, p, s->d_Vt, n3,
+        launch_bsr_dots(st, s->tune.bsr_lanes, s->nv, s->d_rowptr, s->d_col, s->d_val32, s->d_val, p, s->d_Vt, n3,
                         s->d_state, 0, s->P1());
       else
         launch_bsr_dots(st, s->tune.bsr_lanes, s->nv, s->d_rowptr, s->d_col, s->d_val, p, s->d_Vt, n3,
@@ -924,6 +1049,7 @@ static adj_status gmres_solve(adj_scene* s, hipStream_t st, const double* b, dou
   HIPCHK(hipStreamSynchronize(st));
   const double bnorm = s->h_state->rnorm;
   const double tol = rtol * bnorm;
+  if (!std::isfinite(bnorm)) return fail(ADJ_E_ARG, "non-finite right-hand side");
   GmresState cur = *s->h_state;
   cur.tol = tol;
   cur.restart = R;
@@ -984,6 +1110,7 @@ static adj_status pcg_solve(adj_scene* s, hipStream_t st, const double* b, doubl
   HIPCHK(hipStreamSynchronize(st));
   const double bnorm = s->h_state->rnorm;
   const double tol = rtol * bnorm;
+  if (!std::isfinite(bnorm)) return fail(ADJ_E_ARG, "non-finite right-hand side");
   double rnorm = bnorm;
   int total = 0;
   bool converged = !(bnorm > tol);
@@ -1045,6 +1172,7 @@ static adj_status semi_implicit_solve(adj_scene* s, hipStream_t st, const double
   HIPCHK(hipStreamSynchronize(st));
   const double bnorm = std::sqrt(nb[0]);
   double rn = bnorm;
+  if (!std::isfinite(bnorm)) return fail(ADJ_E_ARG, "non-finite right-hand side");
   int it = 0;
   while (it < maxit && rn > rtol * bnorm) {
     const int chunk = std::min(16, maxit - it);
@@ -1076,8 +1204,21 @@ static adj_status krylov_solve(adj_scene* s, hipStream_t st, bool use_pcg, const
   return gmres_solve(s, st, b, x, rtol, maxit, R, iters, relres, conv, f32);
 }
 
+static adj_status adjoint_solve_impl(adj_scene* s, const double* dL_dq, const double* dL_dv, double* z,
+                                     const adj_solve_opts* opts, adj_solve_info* info, void* stream);
+
+// The device error flag raised by the last setup (inverted element,
+// singular capacitance pivot) takes precedence over the solve's own status.
 extern "C" adj_status adjoint_solve(adj_scene* s, const double* dL_dq, const double* dL_dv, double* z,
                                     const adj_solve_opts* opts, adj_solve_info* info, void* stream) {
+  const adj_status a = adjoint_solve_impl(s, dL_dq, dL_dv, z, opts, info, stream);
+  if (a == ADJ_E_ARG || a == ADJ_E_SHAPE || a == ADJ_E_NOTIMPL) return a;
+  const adj_status e = adj_check_status(s, stream);
+  return e != ADJ_OK ? e : a;
+}
+
+static adj_status adjoint_solve_impl(adj_scene* s, const double* dL_dq, const double* dL_dv, double* z,
+                                     const adj_solve_opts* opts, adj_solve_info* info, void* stream) {
   if (!s || !dL_dq || !dL_dv || !z || !opts) return fail(ADJ_E_ARG, "null argument");
   if (!s->setup_done) return fail(ADJ_E_ARG, "adjoint_setup has not run");
   if (!(opts->rtol > 0) || opts->maxit <= 0 || opts->restart < 1 || opts->restart > kMaxRestart)
@@ -1131,6 +1272,7 @@ extern "C" adj_status adjoint_solve(adj_scene* s, const double* dL_dq, const dou
     HIPCHK(hipStreamSynchronize(st));
     const double bnorm = std::sqrt(nb[0]);
     double rnorm = bnorm;
+    if (!std::isfinite(bnorm)) return fail(ADJ_E_ARG, "non-finite right-hand side");
     relres = bnorm > 0 ? 1.0 : 0.0;
     converged = !(bnorm > 0);
     for (refine = 0; refine <= std::max(0, opts->max_refine) && !converged && total < opts->maxit; ++refine) {

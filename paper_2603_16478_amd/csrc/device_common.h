@@ -23,6 +23,31 @@ __device__ __forceinline__ double group_sum(double v) {
   return v;
 }
 
+// a += B x for one 3x3 block p of the block-sparse Acal^T.  With FP32
+// block values (mixed precision) the diagonal blocks are read from the FP64
+// values instead: vertex-obstacle contacts and bindings put their stiffness
+// (up to ~1/eps^2 times the elastic scale) on the diagonal blocks only, and
+// FP32 rounding of those terms would make the inner solves diverge from the
+// FP64 refinement residual; off-diagonal blocks are purely elastic.
+template <class MT>
+__device__ __forceinline__ void block_madd(const MT* __restrict__ val, const double* __restrict__ val64, size_t p,
+                                           bool diag, double x0, double x1, double x2, double& a0, double& a1,
+                                           double& a2) {
+  if constexpr (sizeof(MT) == 4) {
+    if (diag) {
+      const double* b = val64 + 9 * p;
+      a0 += b[0] * x0 + b[1] * x1 + b[2] * x2;
+      a1 += b[3] * x0 + b[4] * x1 + b[5] * x2;
+      a2 += b[6] * x0 + b[7] * x1 + b[8] * x2;
+      return;
+    }
+  }
+  const MT* b = val + 9 * p;
+  a0 += (double)b[0] * x0 + (double)b[1] * x1 + (double)b[2] * x2;
+  a1 += (double)b[3] * x0 + (double)b[4] * x1 + (double)b[5] * x2;
+  a2 += (double)b[6] * x0 + (double)b[7] * x1 + (double)b[8] * x2;
+}
+
 // Block-wide sum for blockDim.x <= 1024; result valid in thread 0.
 __device__ __forceinline__ double block_sum(double v, double* lds /* >= 16 */) {
   v = wave_sum(v);

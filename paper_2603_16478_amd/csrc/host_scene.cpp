@@ -107,15 +107,22 @@ void nested_dissection(const std::vector<int32_t>& verts, const std::vector<doub
 
 }  // namespace
 
-std::vector<int32_t> make_row_tasks(const std::vector<int64_t>& rowptr, int64_t big) {
+std::vector<int32_t> make_row_tasks(const std::vector<int64_t>& rowptr, int64_t big,
+                                    const std::vector<int32_t>* rows, bool skip_empty) {
   std::vector<int32_t> t;
   std::vector<int32_t> small;
-  const int n = (int)rowptr.size() - 1;
   // longest rows first: blocks are dispatched in grid order, so the rows that
   // bound the launch start earliest, and the rows sharing a block have
   // similar lengths
-  std::vector<int32_t> order(n);
-  for (int r = 0; r < n; ++r) order[r] = r;
+  std::vector<int32_t> order;
+  if (rows) {
+    order = *rows;
+  } else {
+    const int n = (int)rowptr.size() - 1;
+    order.reserve(n);
+    for (int r = 0; r < n; ++r)
+      if (!skip_empty || rowptr[r + 1] > rowptr[r]) order.push_back(r);
+  }
   std::stable_sort(order.begin(), order.end(),
                    [&](int32_t a, int32_t b) { return rowptr[a + 1] - rowptr[a] > rowptr[b + 1] - rowptr[b]; });
   for (int r : order) {

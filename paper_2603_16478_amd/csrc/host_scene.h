@@ -57,8 +57,10 @@ struct HostScene {
 
 // Pack CSR rows into blocks: rows longer than `big` get a block each (flag
 // 0x40000000), shorter rows go four to a block; -1 marks an empty slot.
-// Tasks are ordered by decreasing row length.
-std::vector<int32_t> make_row_tasks(const std::vector<int64_t>& rowptr, int64_t big);
+// Tasks are ordered by decreasing row length.  `rows` restricts the tasks to
+// the listed rows; `skip_empty` leaves out rows without entries.
+std::vector<int32_t> make_row_tasks(const std::vector<int64_t>& rowptr, int64_t big,
+                                    const std::vector<int32_t>* rows = nullptr, bool skip_empty = false);
 
 // Returns ADJ_OK or an error code with a message in err.
 adj_status build_host_scene(const adj_scene_desc* d, HostScene& s, std::string& err);

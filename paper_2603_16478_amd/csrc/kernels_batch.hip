@@ -148,6 +148,7 @@ __global__ void __launch_bounds__(256) kb_wb_correct(const int4* __restrict__ ta
 template <class MT, int LANES>
 __global__ void __launch_bounds__(256) kb_bsr_dots(const int4* __restrict__ tab, const int* __restrict__ rowptr,
                                                    const int* __restrict__ col, const MT* __restrict__ val,
+                                                   const double* __restrict__ val64,
                                                    const double* __restrict__ y, double* __restrict__ Vt,
                                                    long long stride, const GmresState* __restrict__ st,
                                                    double* __restrict__ P) {
@@ -163,12 +164,9 @@ __global__ void __launch_bounds__(256) kb_bsr_dots(const int4* __restrict__ tab,
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
   if (row < e.z) {
     for (int p = rowptr[row] + sub; p < rowptr[row + 1]; p += LANES) {
-      const MT* b = val + 9 * (size_t)p;
       const int c = col[p];
       const double x0 = y[3 * c], x1 = y[3 * c + 1], x2 = y[3 * c + 2];
-      a0 += (double)b[0] * x0 + (double)b[1] * x1 + (double)b[2] * x2;
-      a1 += (double)b[3] * x0 + (double)b[4] * x1 + (double)b[5] * x2;
-      a2 += (double)b[6] * x0 + (double)b[7] * x1 + (double)b[8] * x2;
+      block_madd<MT>(val, val64, (size_t)p, c == row, x0, x1, x2, a0, a1, a2);
     }
   }
   a0 = group_sum<LANES>(a0);
@@ -614,7 +612,8 @@ template <class MT>
 __global__ void __launch_bounds__(256) kb_bsr_active(int nv, const int* __restrict__ vscene,
                                                      const GmresState* __restrict__ st,
                                                      const int* __restrict__ rowptr, const int* __restrict__ col,
-                                                     const MT* __restrict__ val, const double* __restrict__ x,
+                                                     const MT* __restrict__ val,
+                                                     const double* __restrict__ val64, const double* __restrict__ x,
                                                      double* __restrict__ out) {
   const int sub = threadIdx.x & 15;
   const int row = blockIdx.x * 16 + threadIdx.x / 16;
@@ -622,12 +621,9 @@ __global__ void __launch_bounds__(256) kb_bsr_active(int nv, const int* __restri
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
   if (on) {
     for (int p = rowptr[row] + sub; p < rowptr[row + 1]; p += 16) {
-      const MT* b = val + 9 * (size_t)p;
       const int c = col[p];
       const double x0 = x[3 * c], x1 = x[3 * c + 1], x2 = x[3 * c + 2];
-      a0 += (double)b[0] * x0 + (double)b[1] * x1 + (double)b[2] * x2;
-      a1 += (double)b[3] * x0 + (double)b[4] * x1 + (double)b[5] * x2;
-      a2 += (double)b[6] * x0 + (double)b[7] * x1 + (double)b[8] * x2;
+      block_madd<MT>(val, val64, (size_t)p, c == row, x0, x1, x2, a0, a1, a2);
     }
   }
   a0 = group_sum<16>(a0);
@@ -689,11 +685,12 @@ void launchb_wb_correct(hipStream_t s, int nblk, int max_ncv, const int4* tab, c
 }
 void launchb_bsr_dots(hipStream_t s, int nblk, const int4* tab, const int* rowptr, const int* col, const double* val,
                       const double* y, double* Vt, long long stride, const GmresState* st, double* P) {
-  kb_bsr_dots<double, 16><<<nblk, 256, 0, s>>>(tab, rowptr, col, val, y, Vt, stride, st, P);
+  kb_bsr_dots<double, 16><<<nblk, 256, 0, s>>>(tab, rowptr, col, val, nullptr, y, Vt, stride, st, P);
 }
 void launchb_bsr_dots(hipStream_t s, int nblk, const int4* tab, const int* rowptr, const int* col, const float* val,
-                      const double* y, double* Vt, long long stride, const GmresState* st, double* P) {
-  kb_bsr_dots<float, 16><<<nblk, 256, 0, s>>>(tab, rowptr, col, val, y, Vt, stride, st, P);
+                      const double* val64, const double* y, double* Vt, long long stride, const GmresState* st,
+                      double* P) {
+  kb_bsr_dots<float, 16><<<nblk, 256, 0, s>>>(tab, rowptr, col, val, val64, y, Vt, stride, st, P);
 }
 void launchb_gm_update(hipStream_t s, int nblk, const int4* tab, int rpb, const int2* rng_in, const double* Pin,
                        double* Pout, double* Vt, long long stride, const double* scale, int lds, const GmresState* st,
@@ -725,11 +722,11 @@ void launchb_axpy_active(hipStream_t s, long long n, const int* vscene, const Gm
 }
 void launchb_bsr_active(hipStream_t s, int nv, const int* vscene, const GmresState* st, const int* rowptr,
                         const int* col, const double* val, const double* x, double* out) {
-  kb_bsr_active<double><<<(nv + 15) / 16, 256, 0, s>>>(nv, vscene, st, rowptr, col, val, x, out);
+  kb_bsr_active<double><<<(nv + 15) / 16, 256, 0, s>>>(nv, vscene, st, rowptr, col, val, nullptr, x, out);
 }
 void launchb_bsr_active(hipStream_t s, int nv, const int* vscene, const GmresState* st, const int* rowptr,
-                        const int* col, const float* val, const double* x, double* out) {
-  kb_bsr_active<float><<<(nv + 15) / 16, 256, 0, s>>>(nv, vscene, st, rowptr, col, val, x, out);
+                        const int* col, const float* val, const double* val64, const double* x, double* out) {
+  kb_bsr_active<float><<<(nv + 15) / 16, 256, 0, s>>>(nv, vscene, st, rowptr, col, val, val64, x, out);
 }
 void launchb_norms(hipStream_t s, int nblk, int ns, const int4* tab, const int2* rng, const double* x, double* P,
                    double* out) {

@@ -471,6 +471,211 @@ kb_gj_step_mfma(const int* __restrict__ next_scenes, int npiv,
   gj_tile(mps[e.x], k0, e.y * kGT, e.z * kGT, A + o, B + o, sh, Pcur + (size_t)e.x * kNB * kNB);
 }
 
+// Wide block Gauss-Jordan for large single capacitances (mp a multiple of
+// 128): 128 pivot columns per step instead of 32, so the matrix is read and
+// written mp/128 times instead of mp/32 times and every step is a rank-128
+// update (16 flop per byte moved, above the chip's FP64 ridge) on the
+// matrix cores.  The same B = Ahat - What Rhat step as above, with K the
+// 128 pivot indices k0 .. k0 + 127 and P = A_KK^{-1}; per step three
+// launches:
+//   k_gjw_pivot  one block inverts the 128 x 128 pivot block in LDS by four
+//                Gauss-Jordan sub-steps on its 32 x 32 diagonal blocks (the
+//                same 32-block partial pivoting as the narrow kernels);
+//   k_gjw_panel  What (mp x 128): A_{i,K} P for rows i outside K, -P_i in K;
+//   k_gjw_tiles  the 128 x 128 output tiles of B.
+constexpr int kWB = 128;        // pivot block width
+constexpr int kWL = kWB + 1;    // LDS row stride of the pivot block
+constexpr int kWKC = 32;        // k-chunk of the staged panels
+
+__global__ void __launch_bounds__(256) k_gjw_pivot(int mp, int k0, const double* __restrict__ A,
+                                                   double* __restrict__ Pout, int* __restrict__ err) {
+  __shared__ double M[kWB * kWL];
+  __shared__ double Ps[kNB][kNB + 1];
+  __shared__ double prow[2 * kNB];
+  const int tid = threadIdx.x;
+  for (int e = tid; e < kWB * kWB; e += 256) {
+    const int r = e / kWB, c = e % kWB;
+    M[r * kWL + c] = A[(size_t)(k0 + r) * mp + k0 + c];
+  }
+  __syncthreads();
+  constexpr int kOut = kWB - kNB;  // rows (columns) outside the sub-step's pivot block
+  for (int sb = 0; sb < kWB; sb += kNB) {
+    if (tid < 64) invert32_rows(M + sb * kWL + sb, kWL, Ps, prow, err);
+    __syncthreads();
+    // (a) What_i = M_{i,sb..} P32 for the rows outside the sub-block, stored
+    // negated in place of M_{i,sb..} (two threads per row, 16 columns each)
+    double a[kNB];
+    const int ia = (tid >> 1) < sb ? (tid >> 1) : (tid >> 1) + kNB;
+    const bool ra = tid < 2 * kOut;
+    if (ra) {
+#pragma unroll
+      for (int c = 0; c < kNB; ++c) a[c] = M[ia * kWL + sb + c];
+    }
+    __syncthreads();
+    if (ra) {
+      const int h = (tid & 1) * 16;
+#pragma unroll
+      for (int cc = 0; cc < 16; ++cc) {
+        double v = 0.0;
+#pragma unroll
+        for (int c = 0; c < kNB; ++c) v = fma(a[c], Ps[c][h + cc], v);
+        M[ia * kWL + sb + h + cc] = -v;
+      }
+    }
+    __syncthreads();
+    // (b) M_ij += (-What_i) M_{sb..,j} for i, j outside the sub-block: a 6 x 6
+    // register tile per thread over the 96 x 96 outer part
+    {
+      const int tr = tid >> 4, tc = tid & 15;
+      int ii[6], jj[6];
+#pragma unroll
+      for (int u = 0; u < 6; ++u) {
+        const int x = 6 * tr + u, y = 6 * tc + u;
+        ii[u] = x < sb ? x : x + kNB;
+        jj[u] = y < sb ? y : y + kNB;
+      }
+      double acc[6][6];
+#pragma unroll
+      for (int u = 0; u < 6; ++u)
+#pragma unroll
+        for (int v = 0; v < 6; ++v) acc[u][v] = M[ii[u] * kWL + jj[v]];
+      for (int k = 0; k < kNB; ++k) {
+        double wv[6], rv[6];
+#pragma unroll
+        for (int u = 0; u < 6; ++u) {
+          wv[u] = M[ii[u] * kWL + sb + k];
+          rv[u] = M[(sb + k) * kWL + jj[u]];
+        }
+#pragma unroll
+        for (int u = 0; u < 6; ++u)
+#pragma unroll
+          for (int v = 0; v < 6; ++v) acc[u][v] = fma(wv[u], rv[v], acc[u][v]);
+      }
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < 6; ++u)
+#pragma unroll
+        for (int v = 0; v < 6; ++v) M[ii[u] * kWL + jj[v]] = acc[u][v];
+    }
+    __syncthreads();
+    // (c) pivot rows outside the sub-block's columns: M_{sb..,j} = P32 M_{sb..,j}
+    // (two threads per column); (d) the sub-block itself becomes P32
+    if (tid < 2 * kOut) {
+      const int y = tid >> 1;
+      const int j = y < sb ? y : y + kNB;
+      double col[kNB];
+#pragma unroll
+      for (int r = 0; r < kNB; ++r) col[r] = M[(sb + r) * kWL + j];
+      __builtin_amdgcn_wave_barrier();  // both threads of the column are in this wavefront
+      const int h = (tid & 1) * 16;
+#pragma unroll
+      for (int rr = 0; rr < 16; ++rr) {
+        double v = 0.0;
+#pragma unroll
+        for (int r = 0; r < kNB; ++r) v = fma(Ps[h + rr][r], col[r], v);
+        M[(sb + h + rr) * kWL + j] = v;
+      }
+    } else {
+      for (int e = tid - 2 * kOut; e < kNB * kNB; e += 256 - 2 * kOut)
+        M[(sb + e / kNB) * kWL + sb + e % kNB] = Ps[e / kNB][e % kNB];
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < kWB * kWB; e += 256) Pout[e] = M[(e / kWB) * kWL + e % kWB];
+}
+
+__global__ void __launch_bounds__(256) k_gjw_panel(int mp, int k0, const double* __restrict__ A,
+                                                   const double* __restrict__ P, double* __restrict__ W) {
+  __shared__ double As[64][kWKC + 1];
+  __shared__ double Bs[kWKC][kWB + 1];
+  const int r0 = blockIdx.x * 64;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, li = lane & 15, lk = lane >> 4;
+  if (r0 >= k0 && r0 < k0 + kWB) {  // pivot rows (64-row slabs never straddle K: k0 % 128 == 0)
+    for (int e = tid; e < 64 * kWB; e += 256) {
+      const int r = e / kWB, c = e % kWB;
+      W[(size_t)(r0 + r) * kWB + c] = -P[(size_t)(r0 - k0 + r) * kWB + c];
+    }
+    return;
+  }
+  d4 acc[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) acc[q] = d4{0, 0, 0, 0};
+  for (int kc = 0; kc < kWB; kc += kWKC) {
+    for (int e = tid; e < 64 * kWKC; e += 256) {
+      const int r = e / kWKC, c = e % kWKC;
+      As[r][c] = A[(size_t)(r0 + r) * mp + k0 + kc + c];
+    }
+    for (int e = tid; e < kWKC * kWB; e += 256) {
+      const int r = e / kWB, c = e % kWB;
+      Bs[r][c] = P[(size_t)(kc + r) * kWB + c];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k4 = 0; k4 < kWKC; k4 += 4) {
+      const double a = As[16 * w + li][k4 + lk];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Bs[k4 + lk][16 * q + li], acc[q], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int q = 0; q < 8; ++q)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) W[(size_t)(r0 + 16 * w + lk + 4 * e) * kWB + 16 * q + li] = acc[q][e];
+}
+
+__global__ void __launch_bounds__(256, 2) k_gjw_tiles(int mp, int k0, const double* __restrict__ A,
+                                                      const double* __restrict__ W, double* __restrict__ B) {
+  __shared__ double Ws[kWB][kWKC + 1];
+  __shared__ double Rs[kWKC][kWB + 1];
+  const int nt = mp / kWB;
+  const int I0 = (blockIdx.x / nt) * kWB, J0 = (blockIdx.x % nt) * kWB;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, li = lane & 15, lk = lane >> 4;
+  const int wr = 64 * (w >> 1), wc = 64 * (w & 1);
+  const bool rowsK = I0 == k0, colsK = J0 == k0;  // tiles are aligned with K
+  d4 acc[4][4];
+#pragma unroll
+  for (int p = 0; p < 4; ++p)
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int i = I0 + wr + 16 * p + lk + 4 * e, j = J0 + wc + 16 * q + li;
+        acc[p][q][e] = (rowsK || colsK) ? 0.0 : A[(size_t)i * mp + j];
+      }
+  for (int kc = 0; kc < kWB; kc += kWKC) {
+    for (int e = tid; e < kWB * kWKC; e += 256) {
+      const int r = e / kWKC, c = e % kWKC;
+      Ws[r][c] = W[(size_t)(I0 + r) * kWB + kc + c];
+    }
+    for (int e = tid; e < kWKC * kWB; e += 256) {
+      const int r = e / kWB, c = e % kWB;
+      Rs[r][c] = colsK ? ((c == kc + r) ? 1.0 : 0.0) : A[(size_t)(k0 + kc + r) * mp + J0 + c];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k4 = 0; k4 < kWKC; k4 += 4) {
+      double av[4], bv[4];
+#pragma unroll
+      for (int p = 0; p < 4; ++p) av[p] = -Ws[wr + 16 * p + li][k4 + lk];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) bv[q] = Rs[k4 + lk][wc + 16 * q + li];
+#pragma unroll
+      for (int p = 0; p < 4; ++p)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[p][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[p], bv[q], acc[p][q], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int p = 0; p < 4; ++p)
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        B[(size_t)(I0 + wr + 16 * p + lk + 4 * e) * mp + J0 + wc + 16 * q + li] = acc[p][q][e];
+}
+
 // identity padding of rows/cols m..mp-1 of a row-major mp x mp matrix
 __global__ void k_pad_identity(int m, int mp, double* __restrict__ C) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
@@ -478,6 +683,16 @@ __global__ void k_pad_identity(int m, int mp, double* __restrict__ C) {
   if (j >= mp || i >= mp) return;
   if (i < m && j < m) return;
   C[(size_t)i * mp + j] = (i == j) ? 1.0 : 0.0;
+}
+
+__global__ void k_fill_int(size_t n, int* __restrict__ a, int v) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = v;
+}
+
+void launch_fill_int(hipStream_t st, size_t n, int* a, int v) {
+  if (n == 0) return;
+  k_fill_int<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(n, a, v);
 }
 
 void launch_fill_zero(hipStream_t st, size_t n, double* a) {
@@ -537,5 +752,24 @@ void launchb_gj_step(hipStream_t st, int npiv, const int* next_scenes, int ntile
   if (!ntiles) return;
   kb_gj_step_mfma<<<npiv + ntiles, 256, 0, st>>>(next_scenes, npiv, tiles, k0, xoff, mps, A, B, Pcur, Pnext, err);
 }
+
+// Wide Gauss-Jordan (mp a multiple of 128): the inverse of the padded matrix
+// in C0 after mp/128 steps, ping-ponging between C0 and C1; returns the
+// buffer holding it.  P: 128 x 128 scratch, W: mp x 128 scratch.
+double* launch_gj_wide(hipStream_t st, int mp, double* C0, double* C1, double* P, double* W, int* err) {
+  double* A = C0;
+  double* B = C1;
+  const int nt = mp / kWB;
+  for (int k0 = 0; k0 < mp; k0 += kWB) {
+    k_gjw_pivot<<<1, 256, 0, st>>>(mp, k0, A, P, err);
+    k_gjw_panel<<<mp / 64, 256, 0, st>>>(mp, k0, A, P, W);
+    k_gjw_tiles<<<nt * nt, 256, 0, st>>>(mp, k0, A, W, B);
+    std::swap(A, B);
+  }
+  return A;
+}
+
+// LDS one block of the wide Gauss-Jordan pivot kernel needs
+size_t gj_wide_lds_bytes() { return sizeof(double) * ((size_t)kWB * kWL + kNB * (kNB + 1) + 2 * kNB); }
 
 }  // namespace adj

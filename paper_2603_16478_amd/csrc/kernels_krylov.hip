@@ -64,7 +64,9 @@ __global__ void __launch_bounds__(256) k_spmv_csr3(int nrows, const long long* _
 // four short rows are handled by one wavefront each (-1 = empty slot).
 constexpr int kBigRow = 0x40000000;
 
-template <class MT>
+// ACC: y[row] += alpha * (row . x) instead of y[row] = scale * (row . x)
+// (rows not listed in the tasks keep their values).
+template <class MT, bool ACC = false>
 __global__ void __launch_bounds__(256) k_spmv_tasks(const int4* __restrict__ tasks,
                                                     const long long* __restrict__ rp,
                                                     const int* __restrict__ cj,
@@ -72,7 +74,7 @@ __global__ void __launch_bounds__(256) k_spmv_tasks(const int4* __restrict__ tas
                                                     const double* __restrict__ xbase, long long stride,
                                                     const double* __restrict__ scale,
                                                     const GmresState* __restrict__ st, int use_j,
-                                                    double* __restrict__ y) {
+                                                    double* __restrict__ y, double alpha = 0.0) {
   if (gm_inactive(st)) return;
   __shared__ double lds[32];
   const int4 t = tasks[blockIdx.x];
@@ -90,9 +92,15 @@ __global__ void __launch_bounds__(256) k_spmv_tasks(const int4* __restrict__ tas
     a1 = block_sum(a1, lds);
     a2 = block_sum(a2, lds);
     if (threadIdx.x == 0) {
-      y[3 * row] = sc * a0;
-      y[3 * row + 1] = sc * a1;
-      y[3 * row + 2] = sc * a2;
+      if constexpr (ACC) {
+        y[3 * row] += alpha * a0;
+        y[3 * row + 1] += alpha * a1;
+        y[3 * row + 2] += alpha * a2;
+      } else {
+        y[3 * row] = sc * a0;
+        y[3 * row + 1] = sc * a1;
+        y[3 * row + 2] = sc * a2;
+      }
     }
     return;
   }
@@ -104,10 +112,29 @@ __global__ void __launch_bounds__(256) k_spmv_tasks(const int4* __restrict__ tas
   a1 = wave_sum(a1);
   a2 = wave_sum(a2);
   if (lane == 0) {
-    y[3 * row] = sc * a0;
-    y[3 * row + 1] = sc * a1;
-    y[3 * row + 2] = sc * a2;
+    if constexpr (ACC) {
+      y[3 * row] += alpha * a0;
+      y[3 * row + 1] += alpha * a1;
+      y[3 * row + 2] += alpha * a2;
+    } else {
+      y[3 * row] = sc * a0;
+      y[3 * row + 1] = sc * a1;
+      y[3 * row + 2] = sc * a2;
+    }
   }
+}
+
+// Y values of the Woodbury correction gathered from the rows of S^T:
+// yval[e] = STx[src[e]].
+__global__ void k_gather_values(long long n, const long long* __restrict__ src, const double* __restrict__ STx,
+                                double* __restrict__ yval) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) yval[e] = STx[src[e]];
+}
+
+void launch_gather_values(hipStream_t s, long long n, const long long* src, const double* STx, double* yval) {
+  if (n <= 0) return;
+  k_gather_values<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, src, STx, yval);
 }
 
 // Block-Jacobi preconditioner: y_v = B_v^{-1} x_v with B_v the 3x3
@@ -212,6 +239,7 @@ template <class MT, int LANES>
 __global__ void __launch_bounds__(256) k_bsr_spmv(int nv, const int* __restrict__ rowptr,
                                                   const int* __restrict__ col,
                                                   const MT* __restrict__ val,
+                                                  const double* __restrict__ val64,
                                                   const double* __restrict__ x,
                                                   double* __restrict__ outbase, long long stride,
                                                   const GmresState* __restrict__ st) {
@@ -221,12 +249,9 @@ __global__ void __launch_bounds__(256) k_bsr_spmv(int nv, const int* __restrict_
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
   if (row < nv) {
     for (int p = rowptr[row] + sub; p < rowptr[row + 1]; p += LANES) {
-      const MT* b = val + 9 * (size_t)p;
       const int c = col[p];
       const double x0 = x[3 * c], x1 = x[3 * c + 1], x2 = x[3 * c + 2];
-      a0 += (double)b[0] * x0 + (double)b[1] * x1 + (double)b[2] * x2;
-      a1 += (double)b[3] * x0 + (double)b[4] * x1 + (double)b[5] * x2;
-      a2 += (double)b[6] * x0 + (double)b[7] * x1 + (double)b[8] * x2;
+      block_madd<MT>(val, val64, (size_t)p, c == row, x0, x1, x2, a0, a1, a2);
     }
   }
   a0 = group_sum<LANES>(a0);
@@ -256,6 +281,7 @@ constexpr int kLd = 130;  // partials of one block: [0 .. 129], basis index i
 template <class MT, int LANES>
 __global__ void __launch_bounds__(256) k_bsr_dots(int nv, const int* __restrict__ rowptr,
                                                   const int* __restrict__ col, const MT* __restrict__ val,
+                                                  const double* __restrict__ val64,
                                                   const double* __restrict__ y, double* __restrict__ Vt,
                                                   long long stride, const GmresState* __restrict__ st, int jfix,
                                                   double* __restrict__ P) {
@@ -269,12 +295,9 @@ __global__ void __launch_bounds__(256) k_bsr_dots(int nv, const int* __restrict_
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
   if (row < nv) {
     for (int p = rowptr[row] + sub; p < rowptr[row + 1]; p += LANES) {
-      const MT* b = val + 9 * (size_t)p;
       const int c = col[p];
       const double x0 = y[3 * c], x1 = y[3 * c + 1], x2 = y[3 * c + 2];
-      a0 += (double)b[0] * x0 + (double)b[1] * x1 + (double)b[2] * x2;
-      a1 += (double)b[3] * x0 + (double)b[4] * x1 + (double)b[5] * x2;
-      a2 += (double)b[6] * x0 + (double)b[7] * x1 + (double)b[8] * x2;
+      block_madd<MT>(val, val64, (size_t)p, c == row, x0, x1, x2, a0, a1, a2);
     }
   }
   a0 = group_sum<LANES>(a0);
@@ -594,6 +617,12 @@ void launch_spmv_tasks(hipStream_t s, int ntasks, const int4* tasks, const long 
                        const GmresState* st, double* y) {
   spmv_tasks_impl(s, ntasks, tasks, rp, cj, cx, xbase, stride, scale, st, y);
 }
+// y[row] += alpha * (row . x) over the listed rows (FP64)
+void launch_spmv_tasks_acc(hipStream_t s, int ntasks, const int4* tasks, const long long* rp, const int* cj,
+                           const double* cx, const double* x, double alpha, const GmresState* st, double* y) {
+  if (ntasks <= 0) return;
+  k_spmv_tasks<double, true><<<ntasks, 256, 0, s>>>(tasks, rp, cj, cx, x, 0, nullptr, st, 0, y, alpha);
+}
 
 void launch_block_jacobi(hipStream_t s, int nv, const int* diag_slot, const double* val, const double* x,
                          long long stride, const double* scale, const GmresState* st, int point, double* y) {
@@ -665,23 +694,25 @@ void launch_wb_correct(hipStream_t s, int nv, int ncv, const int* cv_ptr, const 
 }
 template <class MT>
 static void bsr_impl(hipStream_t s, int lanes, int nv, const int* rowptr, const int* col, const MT* val,
-                     const double* x, double* outbase, long long stride, const GmresState* st) {
+                     const double* val64, const double* x, double* outbase, long long stride,
+                     const GmresState* st) {
   const int rows = 256 / lanes;
   const unsigned g = (unsigned)((nv + rows - 1) / rows);
   switch (lanes) {
-    case 4: k_bsr_spmv<MT, 4><<<g, 256, 0, s>>>(nv, rowptr, col, val, x, outbase, stride, st); break;
-    case 8: k_bsr_spmv<MT, 8><<<g, 256, 0, s>>>(nv, rowptr, col, val, x, outbase, stride, st); break;
-    case 32: k_bsr_spmv<MT, 32><<<g, 256, 0, s>>>(nv, rowptr, col, val, x, outbase, stride, st); break;
-    default: k_bsr_spmv<MT, 16><<<g, 256, 0, s>>>(nv, rowptr, col, val, x, outbase, stride, st); break;
+    case 4: k_bsr_spmv<MT, 4><<<g, 256, 0, s>>>(nv, rowptr, col, val, val64, x, outbase, stride, st); break;
+    case 8: k_bsr_spmv<MT, 8><<<g, 256, 0, s>>>(nv, rowptr, col, val, val64, x, outbase, stride, st); break;
+    case 32: k_bsr_spmv<MT, 32><<<g, 256, 0, s>>>(nv, rowptr, col, val, val64, x, outbase, stride, st); break;
+    default: k_bsr_spmv<MT, 16><<<g, 256, 0, s>>>(nv, rowptr, col, val, val64, x, outbase, stride, st); break;
   }
 }
 void launch_bsr_spmv(hipStream_t s, int lanes, int nv, const int* rowptr, const int* col, const double* val,
                      const double* x, double* outbase, long long stride, const GmresState* st) {
-  bsr_impl(s, lanes, nv, rowptr, col, val, x, outbase, stride, st);
+  bsr_impl(s, lanes, nv, rowptr, col, val, (const double*)nullptr, x, outbase, stride, st);
 }
+// FP32 block values with the diagonal blocks from val64 (see block_madd)
 void launch_bsr_spmv(hipStream_t s, int lanes, int nv, const int* rowptr, const int* col, const float* val,
-                     const double* x, double* outbase, long long stride, const GmresState* st) {
-  bsr_impl(s, lanes, nv, rowptr, col, val, x, outbase, stride, st);
+                     const double* val64, const double* x, double* outbase, long long stride, const GmresState* st) {
+  bsr_impl(s, lanes, nv, rowptr, col, val, val64, x, outbase, stride, st);
 }
 
 __global__ void k_to_f32(long long n, const double* __restrict__ a, float* __restrict__ out) {
@@ -693,28 +724,50 @@ void launch_to_f32(hipStream_t s, long long n, const double* a, float* out) {
   k_to_f32<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, a, out);
 }
 
+// Partial sums of many blocks folded once: entry i (i <= j + extra, j the
+// current basis index) of P[b * ld + i] summed over the nb blocks in fixed
+// order into P[i] (block row 0), one 256-thread block per entry.  The
+// consumers then read one partial instead of re-adding nb of them in each of
+// their own blocks, which costs nb x (j + 1) loads per block on large scenes.
+__global__ void __launch_bounds__(256) k_fold_partials(double* __restrict__ P, int nb, int ld,
+                                                       const GmresState* __restrict__ st, int extra) {
+  if (st->active == 0) return;
+  const int i = blockIdx.x;
+  if (i > st->j + extra) return;
+  __shared__ double tmp[256];
+  double a = 0.0;
+  for (int b = threadIdx.x; b < nb; b += 256) a += P[(size_t)b * ld + i];
+  a = block_sum(a, tmp);
+  if (threadIdx.x == 0) P[i] = a;
+}
+
+void launch_fold_partials(hipStream_t s, double* P, int nb, const GmresState* st, int extra) {
+  k_fold_partials<<<kLd, 256, 0, s>>>(P, nb, kLd, st, extra);
+}
+
 int gm_blocks(long long n, int rpb) { return (int)((n + rpb - 1) / rpb); }
 int bsr_blocks(int nv, int lanes) { return (nv + 256 / lanes - 1) / (256 / lanes); }
 
 template <class MT>
 static void bsr_dots_impl(hipStream_t s, int lanes, int nv, const int* rowptr, const int* col, const MT* val,
-                          const double* y, double* Vt, long long stride, const GmresState* st, int jfix,
-                          double* P) {
+                          const double* val64, const double* y, double* Vt, long long stride, const GmresState* st,
+                          int jfix, double* P) {
   const unsigned g = (unsigned)bsr_blocks(nv, lanes);
   switch (lanes) {
-    case 4: k_bsr_dots<MT, 4><<<g, 256, 0, s>>>(nv, rowptr, col, val, y, Vt, stride, st, jfix, P); break;
-    case 8: k_bsr_dots<MT, 8><<<g, 256, 0, s>>>(nv, rowptr, col, val, y, Vt, stride, st, jfix, P); break;
-    case 32: k_bsr_dots<MT, 32><<<g, 256, 0, s>>>(nv, rowptr, col, val, y, Vt, stride, st, jfix, P); break;
-    default: k_bsr_dots<MT, 16><<<g, 256, 0, s>>>(nv, rowptr, col, val, y, Vt, stride, st, jfix, P); break;
+    case 4: k_bsr_dots<MT, 4><<<g, 256, 0, s>>>(nv, rowptr, col, val, val64, y, Vt, stride, st, jfix, P); break;
+    case 8: k_bsr_dots<MT, 8><<<g, 256, 0, s>>>(nv, rowptr, col, val, val64, y, Vt, stride, st, jfix, P); break;
+    case 32: k_bsr_dots<MT, 32><<<g, 256, 0, s>>>(nv, rowptr, col, val, val64, y, Vt, stride, st, jfix, P); break;
+    default: k_bsr_dots<MT, 16><<<g, 256, 0, s>>>(nv, rowptr, col, val, val64, y, Vt, stride, st, jfix, P); break;
   }
 }
 void launch_bsr_dots(hipStream_t s, int lanes, int nv, const int* rowptr, const int* col, const double* val,
                      const double* y, double* Vt, long long stride, const GmresState* st, int jfix, double* P) {
-  bsr_dots_impl(s, lanes, nv, rowptr, col, val, y, Vt, stride, st, jfix, P);
+  bsr_dots_impl(s, lanes, nv, rowptr, col, val, (const double*)nullptr, y, Vt, stride, st, jfix, P);
 }
 void launch_bsr_dots(hipStream_t s, int lanes, int nv, const int* rowptr, const int* col, const float* val,
-                     const double* y, double* Vt, long long stride, const GmresState* st, int jfix, double* P) {
-  bsr_dots_impl(s, lanes, nv, rowptr, col, val, y, Vt, stride, st, jfix, P);
+                     const double* val64, const double* y, double* Vt, long long stride, const GmresState* st,
+                     int jfix, double* P) {
+  bsr_dots_impl(s, lanes, nv, rowptr, col, val, val64, y, Vt, stride, st, jfix, P);
 }
 
 void launch_gm_update(hipStream_t s, long long n, int rpb, double* Vt, long long stride, const double* scale,

@@ -39,6 +39,13 @@ class GpuSim:
                                   material=native.MATERIAL_CODES[getattr(spec, "material", "nh")])
         self.buf = native.ContactBuffers(self.max_contacts)
         self.dev = "cuda"
+        # options of the adjoint solves in backward_pass (relative residual 1e-10 by default)
+        self.opts = native.solve_opts(rtol=1e-10, maxit=4000, restart=64)
+
+    def params(self, mu, requires_grad=True):
+        """The (E, nu, mu) tensor of Rollout.apply for this scene."""
+        return torch.tensor([self.E, self.nu, float(mu)], dtype=torch.float64, device=self.dev,
+                            requires_grad=requires_grad)
 
     def step(self, qbar, vbar, f_ext, mu, t=None):
         """One forward step; with t given, the spec's kinematic spheres move
@@ -88,7 +95,7 @@ def backward_pass(sim: GpuSim, forces, mu, ckpt, gq_T, gv_T, checkpoint=None, re
     dq0, dv0, dforces (T, n, 3), grad3 = (dL/dE, dL/dnu, dL/dmu), iters."""
     T = forces.shape[0]
     K = T if checkpoint is None else int(checkpoint)
-    opts = opts or native.solve_opts(rtol=1e-10, maxit=4000, restart=64)
+    opts = opts or sim.opts
     gq, gv = gq_T.clone(), gv_T.clone()
     grad3 = torch.zeros(3, dtype=torch.float64, device=gq.device)
     dforces = torch.zeros_like(forces)
@@ -115,13 +122,18 @@ def backward_pass(sim: GpuSim, forces, mu, ckpt, gq_T, gv_T, checkpoint=None, re
 
 
 class Rollout(torch.autograd.Function):
-    """(q0, v0, forces[T, n, 3]) -> (q_T, v_T) through T implicit steps on the
-    GPU; backward is the analytical adjoint with checkpointing.  The material
-    and friction parameters are fixed for a call; their gradients are
-    returned by `rollout_with_param_grads`."""
+    """(q0, v0, forces[T, n, 3], params[3]) -> (q_T, v_T) through T implicit
+    steps on the GPU; backward is the analytical adjoint with checkpointing.
+    params = (E, nu, mu) as a float64 tensor (`GpuSim.params`): E and nu must
+    be the scene's (its prefactored system matrix depends on them), mu is
+    the friction coefficient of every step.  The gradient of params is
+    (dL/dE, dL/dnu, dL/dmu) accumulated over the steps."""
 
     @staticmethod
-    def forward(ctx, q0, v0, forces, sim, mu, checkpoint):
+    def forward(ctx, q0, v0, forces, params, sim, checkpoint):
+        E, nu, mu = (float(x) for x in params.detach().cpu())
+        if E != sim.E or nu != sim.nu:
+            raise ValueError("params (E, nu) must be the scene's; build a GpuSim with the new values")
         qT, vT, ckpt, recs = forward_pass(sim, q0, v0, forces, mu, checkpoint)
         ctx.sim, ctx.mu, ctx.checkpoint = sim, mu, checkpoint
         ctx.ckpt, ctx.records = ckpt, (recs if checkpoint is None else None)
@@ -134,8 +146,7 @@ class Rollout(torch.autograd.Function):
         gq = torch.zeros_like(forces[0]) if gq is None else gq.contiguous()
         gv = torch.zeros_like(forces[0]) if gv is None else gv.contiguous()
         out = backward_pass(ctx.sim, forces, ctx.mu, ctx.ckpt, gq, gv, ctx.checkpoint, ctx.records)
-        ctx.param_grads = out["grad3"]
-        return out["dq0"], out["dv0"], out["dforces"], None, None, None
+        return out["dq0"], out["dv0"], out["dforces"], out["grad3"], None, None
 
 
 class Actuation(torch.autograd.Function):

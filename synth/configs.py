@@ -242,6 +242,27 @@ def perturbed_state(spec: SceneSpec, seed: int = 12, scale: float = 1e-5) -> np.
     return spec.mesh.rest + scale * rng.standard_normal(spec.mesh.rest.shape)
 
 
+def slab_indented_state(spec: SceneSpec, t: int) -> np.ndarray:
+    """The slab with its top face pressed onto the sphere's surface at the
+    sphere's pose of step t: every vertex moves straight down by
+    delta(x, y) z / H, where H is the slab height and delta the depth of the
+    sphere's lower surface below the undeformed top face at (x, y) (zero
+    outside the sphere's footprint).  Top-face vertices under the sphere lie
+    on its surface, the bottom face stays on the ground, and every tet keeps
+    det F = 1 - delta / H > 0 (a vertical displacement linear in z)."""
+    R, centre = spec.spheres[0]
+    c = np.asarray(centre(t), dtype=np.float64)
+    q = spec.mesh.rest.copy()
+    H = float(q[:, 2].max())
+    r2 = (q[:, 0] - c[0]) ** 2 + (q[:, 1] - c[1]) ** 2
+    inside = r2 < R * R
+    zs = np.full(q.shape[0], np.inf)
+    zs[inside] = c[2] - np.sqrt(R * R - r2[inside])
+    depth = np.maximum(0.0, H - zs)
+    q[:, 2] -= depth * q[:, 2] / H
+    return q
+
+
 def contact_values(n: int, mu: float, seed: int = 13):
     """Seeded contact displacements and multipliers in frame coordinates for n
     sticking contacts: normal gaps U[1e-13, 1e-11] m, normal forces

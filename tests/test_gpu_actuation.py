@@ -64,7 +64,7 @@ def test_actuated_rollout_gradient_matches_oracle():
     a = torch.tensor(a_np, device="cuda", requires_grad=True)
     q0 = torch.tensor(spec.q0, device="cuda")
     v0 = torch.tensor(spec.v0, device="cuda")
-    qT, vT = Rollout.apply(q0, v0, Actuation.apply(a, sim), sim, spec.mu, 3)
+    qT, vT = Rollout.apply(q0, v0, Actuation.apply(a, sim), sim.params(spec.mu), sim, 3)
     loss = torch.sum(torch.tensor(w, device="cuda") * qT)
     loss.backward()
     L_ref = float(np.sum(w * ro.qs[-1]))
@@ -93,7 +93,7 @@ def test_quadruped_actuation_gradient_matches_fd():
     a0 = torch.tensor(actuation_params(T, amplitude=2e3), device="cuda")
 
     def loss_of(a):
-        qT, _ = Rollout.apply(q0, v0, Actuation.apply(a, sim), sim, spec.mu, K)
+        qT, _ = Rollout.apply(q0, v0, Actuation.apply(a, sim), sim.params(spec.mu, False), sim, K)
         return torch.sum(w * qT)
 
     t0 = time.perf_counter()
