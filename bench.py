@@ -56,6 +56,7 @@ CSRC = os.path.join(ROOT, "paper_2603_16478_amd", "csrc")
 # calibrated HBM traffic per launch from the committed counter runs, one file
 # per kernel, each tagged with a hash of the source it was measured on
 COUNTERS = {"s_product": os.path.join(ROOT, "profiles", "s_product_batched_beam_counters.json"),
+            "gj_wide": os.path.join(ROOT, "profiles", "gj_wide_slab_counters.json"),
             "gj_step": os.path.join(ROOT, "profiles", "gj_step_batched_beam_counters.json"),
             "s_product_single": os.path.join(ROOT, "profiles", "s_product_slab_counters.json")}
 
@@ -110,6 +111,8 @@ def _function_text(src, name):
 
 GJ_FUNCTIONS = ("readlane_d", "rcp_newton", "max_dpp", "gj_rows_step", "invert32_rows", "gj_tile", "gj_next_pivot",
                 "kb_gj_step_mfma")
+GJW_FUNCTIONS = ("readlane_d", "rcp_newton", "max_dpp", "gj_rows_step", "invert32_rows", "k_gjw_pivot", "k_gjw_panel",
+                 "k_gjw_tiles")
 
 
 def kernel_source_hash(kernel):
@@ -120,6 +123,9 @@ def kernel_source_hash(kernel):
     elif kernel == "s_product_single":
         text = (_function_text(open(os.path.join(CSRC, "kernels_krylov.hip")).read(), "k_spmv_tasks") +
                 _function_text(open(os.path.join(CSRC, "device_common.h")).read(), "row_dot3"))
+    elif kernel == "gj_wide":
+        src = open(os.path.join(CSRC, "kernels_dense.hip")).read()
+        text = "".join(_function_text(src, f) for f in GJW_FUNCTIONS)
     else:
         src = open(os.path.join(CSRC, "kernels_dense.hip")).read()
         m = re.search(r"struct GjShared \{.*?\};", src, re.S)
@@ -327,28 +333,50 @@ def eps_sweep_one(two_eps2, side, seconds):
                       "ms_per_step": 1e3 * dt / spec.steps}))
 
 
-def slab_leg(nsolve):
-    """The slab workload at full size (64x32x32 cells, 393,216 tets, 70,785
-    vertices, sphere of radius 0.3 x width): the adjoint at the seeded
-    deformed state with the 2,190 contacts of tests/golden/slab_contacts.npz
-    and seeded sticking contact values, timed `nsolve` times in FP64 and in
-    mixed precision (setup + solve + VJP), with the sparse-inverse product's
-    bandwidth.  Returns a dict."""
+SLAB_FIXTURE = os.path.join(ROOT, "tests", "golden", "slab_step50.npz")
+FP64_PEAK_TFLOPS = 78.6
+
+
+def slab_inputs():
+    """The slab workload's measured step: the contact set stored with the
+    oracle's solution (tests/golden/slab_step50.npz, written by
+    tests/golden/make_oracle_z.py), the seeded state, contact values and
+    right-hand side of synth (the same inputs the oracle solved)."""
+    from synth.configs import contact_values, slab_last_step, slab_scene
+    spec = slab_scene()
+    d = np.load(SLAB_FIXTURE)
+    _, q, gq, gv = slab_last_step(spec)
+    delta, lam = contact_values(int(d["vid"].shape[0]), spec.mu)
+    return spec, d, q, gq, gv, delta, lam
+
+
+def _rel(a, b):
+    return float(np.max(np.abs(np.asarray(a) - np.asarray(b))) / np.max(np.abs(b)))
+
+
+def slab_headline(args):
+    """Headline: the slab workload (64x32x32 cells, 393,216 tets, 70,785
+    vertices, pressed by the sphere) at its last step, 3,022 contacts and
+    9,018 capacitance rows.  One adjoint solve = adjoint_setup + adjoint_solve
+    + vjp_params.  Cold: the Delassus product is rebuilt every solve (a new
+    contact vertex set); warm: it is reused (the same contact vertex set, as
+    along consecutive steps).  FP64 and mixed, each against the oracle's z.
+    The kernels are timed live (HIP events on the launch stream) per class;
+    the class with the largest time per solve is `roofline`."""
     import torch
 
     from paper_2603_16478_amd import native
-    from synth.configs import contact_values, perturbed_state, slab_scene
 
-    d = np.load(os.path.join(ROOT, "tests", "golden", "slab_contacts.npz"))
-    spec = slab_scene()
+    spec, d, qn, gqn, gvn, delta, lam = slab_inputs()
     n = int(d["vid"].shape[0])
-    delta, lam = contact_values(n, spec.mu)
+    nfric = int(d["fric"].sum())
     t0 = time.perf_counter()
     scene = native.Scene(spec.mesh.rest, spec.mesh.tets, spec.density, spec.h, spec.eps, spec.E, spec.nu,
                          spec.gravity, spec.planes, spec.contact_margin, n)
     t_build = time.perf_counter() - t0
     info = scene.info()
-    print(f"slab scene built in {t_build:.1f} s (nnz(S) {info['nnz_S']})", file=sys.stderr, flush=True)
+    print(f"slab scene built in {t_build:.1f} s (nnz(L) {info['nnz_L']}, nnz(S) {info['nnz_S']})", file=sys.stderr,
+          flush=True)
     dev = "cuda"
     tens = {"vid": torch.tensor(d["vid"].astype(np.int32), device=dev),
             "fric": torch.tensor(d["fric"].astype(np.int32), device=dev),
@@ -356,50 +384,208 @@ def slab_leg(nsolve):
             "delta": torch.tensor(delta, dtype=torch.float64, device=dev),
             "lam": torch.tensor(lam, dtype=torch.float64, device=dev)}
     cs = native.make_contact_state(n, tens["vid"], tens["fric"], tens["frame"], tens["delta"], tens["lam"], spec.mu)
-    q = torch.tensor(perturbed_state(spec), device=dev)
-    gq = torch.tensor(spec.loss_dir, device=dev)
-    gv = torch.zeros_like(gq)
+    q = torch.tensor(qn, device=dev)
+    gq = torch.tensor(gqn, device=dev)
+    gv = torch.tensor(gvn, device=dev)
     z = torch.zeros_like(gq)
     dq, dv, df = torch.empty_like(gq), torch.empty_like(gq), torch.empty_like(gq)
     grad3 = torch.zeros(3, dtype=torch.float64, device=dev)
-    legs = {}
-    sbytes = info["nnz_S"] * (8 + 4) + (spec.n_verts + 1) * 8 + 2 * 3 * spec.n_verts * 8
-    for name, prec in (("fp64", native.ADJ_FP64), ("mixed", native.ADJ_MIXED)):
-        o = native.solve_opts(rtol=1e-8, maxit=3000, restart=64, prec=prec, max_refine=8)
+    zref = d["z"]
+
+    def opts(prec, reuse):
+        return native.solve_opts(rtol=args.rtol, maxit=3000, restart=64, prec=prec, max_refine=8,
+                                 reuse_delassus=reuse)
+
+    def solve(o):
+        native.adjoint_setup(scene, cs, q, o)
+        inf = native.adjoint_solve(scene, gq, gv, z, o)
+        native.vjp_params(scene, z, gv, dq, dv, df, grad3)
+        return inf
+
+    def timed(o, k):
+        its, ref = [], []
+        torch.cuda.synchronize()
         t1 = time.perf_counter()
-        native.adjoint_setup(scene, cs, q, o)  # warm-up; builds the Delassus matrix of this contact set
-        native.adjoint_solve(scene, gq, gv, z, o)
-        torch.cuda.synchronize()
-        t_first = time.perf_counter() - t1
-        its = []
-        native.profile_begin(scene, "S")
-        t2 = time.perf_counter()
-        for _ in range(nsolve):
-            native.adjoint_setup(scene, cs, q, o)
-            inf = native.adjoint_solve(scene, gq, gv, z, o)
-            native.vjp_params(scene, z, gv, dq, dv, df, grad3)
+        for _ in range(k):
+            inf = solve(o)
             its.append(inf.iters)
+            ref.append(inf.refine_steps)
         torch.cuda.synchronize()
-        dt = time.perf_counter() - t2
-        sms, sl = native.profile_end(scene)
-        avg_us = 1e3 * sms / max(sl, 1)
-        legs[name] = {"value": nsolve / dt, "unit": "adjoint solves/s", "ms_per_solve": 1e3 * dt / nsolve,
-                      "krylov_iters_mean": float(np.mean(its)), "first_solve_s_incl_delassus": t_first,
-                      "s_product_avg_launch_us": avg_us, "s_product_launches": sl}
-        if prec == native.ADJ_FP64 and sl:
-            gbs = sbytes / (avg_us * 1e-6) / 1e9
-            legs[name] |= {"s_product_GB/s": gbs, "s_product_frac": gbs / HBM_PEAK_GBPS,
-                           "s_product_traffic": measured_traffic("s_product_single")}
-        print(f"slab adjoint {name}: {legs[name]['ms_per_solve']:.1f} ms per solve, iterations "
-              f"{legs[name]['krylov_iters_mean']:.1f}, S product {avg_us:.0f} us per launch, first solve "
-              f"{t_first:.2f} s", file=sys.stderr, flush=True)
-    legs["mixed"]["speedup_vs_fp64"] = legs["mixed"]["value"] / legs["fp64"]["value"]
+        dt = time.perf_counter() - t1
+        return {"value": k / dt, "ms_per_solve": 1e3 * dt / k, "solves": k, "krylov_iters_mean": float(np.mean(its)),
+                "refinements_mean": float(np.mean(ref))}
+
+    legs = {}
+    m_rows = None
+    for name, prec in (("fp64", native.ADJ_FP64), ("mixed", native.ADJ_MIXED)):
+        for _ in range(max(1, args.warmup)):
+            inf = solve(opts(prec, 1))
+        m_rows = inf.m_rows
+        cold = timed(opts(prec, 0), max(2, args.steps // 5))
+        warm = timed(opts(prec, 1), args.steps)
+        torch.cuda.synchronize()
+        legs[name] = {"warm": warm, "cold": cold, "z_rel_err_vs_oracle": _rel(z.cpu().numpy(), zref)}
+        print(f"slab {name}: warm {warm['ms_per_solve']:.1f} ms ({warm['krylov_iters_mean']:.0f} its), cold "
+              f"{cold['ms_per_solve']:.1f} ms, z err {legs[name]['z_rel_err_vs_oracle']:.1e}", file=sys.stderr,
+              flush=True)
+    # live per-class kernel times, FP64, warm (the Delassus product on cold solves)
+    nprof = 2
+    prof = {}
+    for cls in ("gj", "S", "ST", "correction", "capinv", "bsr", "tet", "assemble", "gs_pass1", "gs_pass2",
+                "delassus"):
+        o = opts(native.ADJ_FP64, 0 if cls == "delassus" else 1)
+        solve(o)
+        torch.cuda.synchronize()
+        native.profile_begin(scene, cls)
+        for _ in range(nprof):
+            solve(o)
+        ms, nl = native.profile_end(scene)
+        prof[cls] = {"ms_per_solve": ms / nprof, "regions": nl, "avg_us": 1e3 * ms / max(nl, 1)}
     scene.close()
-    return {"workload": "slab 64x32x32 cells (393,216 tets, 70,785 vertices), sphere indenter; seeded deformed "
-                        "state, 2,190 detected contacts with seeded sticking values; GMRES(64) + Woodbury (correction "
-                        "through S^T S) to 1e-8",
-            "scene_build_s": t_build, "nnz_S": info["nnz_S"], "contacts": n, "adjoint": legs,
-            "s_product_bytes": sbytes}
+    torch.cuda.synchronize()
+    mp = ((m_rows + 127) // 128) * 128
+    nv, nt, nnzb, ncv = info["n_verts"], info["n_tets"], info["nnz_blocks"], int(np.unique(d["vid"]).size)
+    # capacitance inversion: algorithmic work 2/3 m^3 (an LU of the m x m
+    # capacitance; Gauss-Jordan's explicit inverse executes 2 mp^3)
+    gj = prof["gj"]
+    gj_alg = 2.0 / 3.0 * m_rows ** 3
+    gj_ach = gj_alg / (gj["avg_us"] * 1e-6) / 1e12
+    roof_gj = {"kernel": "capacitance inverse (wide Gauss-Jordan: k_gjw_pivot + k_gjw_panel + k_gjw_tiles per "
+                         "128-column step), one region per adjoint setup",
+               "bound": "mfma", "achieved": gj_ach, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+               "frac": gj_ach / FP64_PEAK_TFLOPS, "traffic": measured_traffic("gj_wide"),
+               "algorithmic_flops_per_launch": gj_alg, "executed_flops_per_launch": 2.0 * mp ** 3,
+               "executed_tflops": 2.0 * mp ** 3 / (gj["avg_us"] * 1e-6) / 1e12,
+               "avg_launch_us": gj["avg_us"], "launches_timed": gj["regions"], "ms_per_solve": gj["ms_per_solve"]}
+    sb = s_product_bytes(info)
+    sp_ms = prof["S"]["ms_per_solve"] + prof["ST"]["ms_per_solve"]
+    sp_avg = 1e3 * (prof["S"]["ms_per_solve"] + prof["ST"]["ms_per_solve"]) * nprof / max(
+        prof["S"]["regions"] + prof["ST"]["regions"], 1)
+    sp_ach = sb / (sp_avg * 1e-6) / 1e9
+    roof_s = {"kernel": "sparse-inverse products S x and S^T x (k_spmv_tasks), one of each per preconditioner "
+                        "apply", "bound": "hbm", "achieved": sp_ach, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+              "frac": sp_ach / HBM_PEAK_GBPS, "traffic": measured_traffic("s_product_single"),
+              "algorithmic_bytes_per_launch": sb, "avg_launch_us": sp_avg,
+              "launches_timed": prof["S"]["regions"] + prof["ST"]["regions"], "ms_per_solve": sp_ms}
+    if roof_gj["ms_per_solve"] >= roof_s["ms_per_solve"]:
+        roofline, roofline_other = roof_gj, roof_s
+    else:
+        roofline, roofline_other = roof_s, roof_gj
+    mvb = bsr_bytes(info)
+    mv = prof["bsr"]
+    tet_bytes = nt * (16 + 14 * 8) + nnzb * 9 * 8
+    tet_us = prof["tet"]["avg_us"] + prof["assemble"]["avg_us"]
+    dl = prof["delassus"]
+    syrk_flops = float(nv) * ncv * ncv  # dense-equivalent Y^T Y (n_v x n_cv), symmetric half
+    warm_m, warm_f = legs["mixed"]["warm"], legs["fp64"]["warm"]
+    return {
+        "metric": METRIC,
+        "value": warm_m["value"],
+        "unit": "adjoint solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": warm_m["ms_per_solve"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "mixed f32/f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "slab 64x32x32 cells (393,216 tets, 70,785 vertices), E=5e5 Pa, nu=0.45, mu=0.5, pressed "
+                        "into the ground by a kinematic sphere of radius 0.192 m; its last step (top face on the "
+                        "sphere at 0.093 m indentation): 3,022 contacts (2,145 ground, 877 sphere), 9,018 "
+                        "capacitance rows; one step = one adjoint solve (setup + solve + VJP) to rel. residual "
+                        "1e-8, GMRES(64) + Woodbury, Delassus product reused (warm); value = mixed precision",
+            "n_contacts": n, "frictional": nfric, "m_rows": m_rows, "contact_vertices": ncv,
+            "nnz_L": info["nnz_L"], "nnz_S": info["nnz_S"], "scene_build_s": t_build,
+        },
+        "fp64": warm_f | {"z_rel_err_vs_oracle": legs["fp64"]["z_rel_err_vs_oracle"], "cold": legs["fp64"]["cold"]},
+        "mixed": warm_m | {"z_rel_err_vs_oracle": legs["mixed"]["z_rel_err_vs_oracle"],
+                           "cold": legs["mixed"]["cold"], "speedup_vs_fp64": warm_m["value"] / warm_f["value"]},
+        "roofline": roofline,
+        "roofline_other": roofline_other,
+        "matvec": {"kernel": "Acal^T product fused with the first Gram-Schmidt dots (k_bsr_dots)",
+                   "bytes_per_launch": mvb, "avg_launch_us": mv["avg_us"],
+                   "GB/s": mvb / (mv["avg_us"] * 1e-6) / 1e9 if mv["regions"] else None,
+                   "frac": mvb / (mv["avg_us"] * 1e-6) / 1e9 / HBM_PEAK_GBPS if mv["regions"] else None},
+        "svd_jacobian": {"kernel": "per-tet SVD / Neo-Hookean projection Jacobian blocks (k_tet_blocks) + gather "
+                                   "assembly (k_assemble)",
+                         "algorithmic_bytes": tet_bytes, "us": tet_us,
+                         "GB/s": tet_bytes / (tet_us * 1e-6) / 1e9,
+                         "frac": tet_bytes / (tet_us * 1e-6) / 1e9 / HBM_PEAK_GBPS},
+        "delassus_syrk": {"kernel": "Y = S E, D = Y^T Y on FP64 matrix cores (k_syrk_mfma), cold solves only",
+                          "dense_equivalent_flops": syrk_flops, "ms": dl["avg_us"] / 1e3,
+                          "tflops": syrk_flops / (dl["avg_us"] * 1e-6) / 1e12 if dl["regions"] else None,
+                          "mfma_frac": syrk_flops / (dl["avg_us"] * 1e-6) / 1e12 / FP64_PEAK_TFLOPS
+                          if dl["regions"] else None},
+        "kernel_ms_per_solve": {k: v["ms_per_solve"] for k, v in prof.items()},
+    }
+
+
+def _oracle_box(k):
+    """One oracle adjoint solve of box k of the batched workload (for the
+    all-core baseline; runs in a worker process)."""
+    from threadpoolctl import threadpool_limits
+    sys.path.insert(0, os.path.join(ROOT, "tests", "golden"))
+    from make_oracle_z import boxes_cases
+
+    from oracle import adjoint as adj
+    from oracle.rollout import scene_disc
+    spec, q, rec, gq, gv = boxes_cases(k + 1)[k]
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        adj.adjoint_step(scene_disc(spec), q, rec, gq, gv, spec.eps, spec.E, spec.nu)
+        return time.perf_counter() - t0
+
+
+def slab_cpu_baseline(args):
+    """The oracle on the GPU host: one adjoint step of the slab workload at
+    1/8 of its cells (32x16x16, the same recipe; SuperLU on the full slab
+    takes tens of minutes) on one core, and the batched workload's first
+    boxes over all cores (one box per worker process)."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import adjoint as adj
+    from oracle.rollout import scene_disc
+    sys.path.insert(0, os.path.join(ROOT, "tests", "golden"))
+    from make_oracle_z import slab_case
+    from synth.configs import slab_scene
+
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    nproc = len(os.sched_getaffinity(0))
+    spec, _, q, rec, gq, gv = slab_case(slab_scene(nx=32, ny=16, nz=16))
+    disc = scene_disc(spec)
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        adj.adjoint_step(disc, q, rec, gq, gv, spec.eps, spec.E, spec.nu)
+        dt = time.perf_counter() - t0
+    out = {"value": 1.0 / dt, "unit": "adjoint solves/s", "cores": 1, "kind": "oracle",
+           "sample": f"one adjoint step (assembly, direct sparse LU with long-double refinement, contractions) of "
+                     f"the slab workload at 32x16x16 cells ({spec.n_tets} tets, {rec.contacts.n} contacts), the "
+                     f"same recipe at 1/8 of the cells, single thread, {dt:.1f} s",
+           "host_cpus": nproc, "cpu_model": model}
+    if args.cpu_boxes > 0:
+        import multiprocessing as mp
+        workers = max(1, min(16, nproc, args.cpu_boxes))
+        ctx = mp.get_context("spawn")
+        t0 = time.perf_counter()
+        with ctx.Pool(workers) as pool:
+            times = pool.map(_oracle_box, range(args.cpu_boxes), chunksize=1)
+        wall = time.perf_counter() - t0
+        out["all_core"] = {"value": args.cpu_boxes / wall, "unit": "adjoint solves/s", "cores": workers,
+                           "kind": "oracle",
+                           "sample": f"the first {args.cpu_boxes} boxes of the batched workload (one scene-step "
+                                     f"each, {workers} worker processes, one thread each), wall {wall:.1f} s, "
+                                     f"sum of per-box times {sum(times):.1f} s"}
+    return out
 
 
 def eps_sweep(seconds):
@@ -431,54 +617,12 @@ def eps_sweep(seconds):
         sys.exit(status)
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=4)
-    ap.add_argument("--rtol", type=float, default=1e-8)
-    ap.add_argument("--cpu-sample", type=int, default=40,
-                    help="scene-steps the oracle solves for cpu_baseline (cycling over the recorded ones)")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-autotune", action="store_true")
-    ap.add_argument("--eps-sweep", type=float, default=0.0, metavar="SECONDS",
-                    help="instead of the benchmark: the smoothing sweep on the slope cube, SECONDS of simulated "
-                         "time per run on the GPU forward step")
-    ap.add_argument("--slab", type=int, default=0, metavar="SOLVES",
-                    help="instead of the benchmark: the full-size slab adjoint, SOLVES timed solves in FP64 and in "
-                         "mixed precision")
-    ap.add_argument("--no-slab", action="store_true", help="skip the full-size slab leg")
-    ap.add_argument("--quadruped", type=int, default=0, metavar="STEPS",
-                    help="instead of the benchmark: the actuated quadruped rollout and its actuation gradient")
-    ap.add_argument("--boxes", type=int, default=16,
-                    help="boxes of the batched-workload leg (first of the seeded 256; 0: skip)")
-    ap.add_argument("--boxes-only", action="store_true",
-                    help="instead of the benchmark: only the batched-workload leg, printed as one JSON line")
-    ap.add_argument("--eps-sweep-one", nargs=3, metavar=("TWO_EPS2", "SIDE", "SECONDS"), help=argparse.SUPPRESS)
-    ap.add_argument("--big-batch", type=int, default=4,
-                    help="copies of the twelve recorded scene-steps in the large-batch leg (0: skip)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on exactly one GPU; --gpus above 1 is not supported",
-                          "n_gpus": args.gpus}))
-        sys.exit(2)
-
-    if args.slab > 0:
-        print(json.dumps(slab_leg(args.slab)))
-        return
-    if args.quadruped > 0:
-        print(json.dumps(quadruped_leg(args.quadruped, max(1, args.quadruped // 4))))
-        return
-    if args.boxes_only:
-        print(json.dumps(boxes_leg(args.boxes, max(1, args.steps // 10))))
-        return
-    if args.eps_sweep_one:
-        eps_sweep_one(float(args.eps_sweep_one[0]), args.eps_sweep_one[1], float(args.eps_sweep_one[2]))
-        return
-    if args.eps_sweep > 0:
-        eps_sweep(args.eps_sweep)
-        return
-
+def beam_legs(args):
+    """The beam workload (three runs at mu 1.0 / 0.1 / 0.4, recorded converged
+    steps): the pipelined reverse pass, batched and single-scene solves, the
+    launch-shape autotuner, the backward-solver comparison, the material
+    models and bindings, with their own roofline kernels and oracle baseline.
+    Returns a dict."""
     import torch
 
     from paper_2603_16478_amd import native
@@ -886,17 +1030,75 @@ def main():
                                      "positions (compliance 1e-6 m/N), GMRES(64) + Woodbury to 1e-8; setup + "
                                      "solve + VJP + binding VJP per recorded scene-step"},
     }
-    if args.boxes > 0:
-        out["batched_boxes"] = boxes_leg(args.boxes, 2)
-    if not args.no_slab:
-        # the full-size slab (about 20 s of host factorisation, then two timed
-        # solves per precision)
-        scene.close()
-        torch.cuda.synchronize()
-        out["slab"] = slab_leg(2)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(spec, states, args.cpu_sample)
-    print(json.dumps(out))
+        out["cpu_baseline_beam"] = cpu_baseline(spec, states, args.cpu_sample)
+    scene.close()
+    batch.close()
+    torch.cuda.synchronize()
+    for k in ("metric", "n_gpus", "steps", "warmup", "higher_is_better", "scaling", "vs_baseline", "data"):
+        out.pop(k, None)
+    return out
+
+
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=4)
+    ap.add_argument("--rtol", type=float, default=1e-8)
+    ap.add_argument("--cpu-sample", type=int, default=40,
+                    help="scene-steps the oracle solves for the beam legs' baseline (cycling over the recorded ones)")
+    ap.add_argument("--cpu-boxes", type=int, default=16,
+                    help="boxes of the batched workload the oracle solves for the all-core baseline (0: skip)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--eps-sweep", type=float, default=0.0, metavar="SECONDS",
+                    help="instead of the benchmark: the smoothing sweep on the slope cube, SECONDS of simulated "
+                         "time per run on the GPU forward step")
+    ap.add_argument("--slab-only", action="store_true",
+                    help="only the headline (the full-size slab), without the beam, boxes and oracle legs")
+    ap.add_argument("--no-beam", action="store_true", help="skip the beam legs")
+    ap.add_argument("--quadruped", type=int, default=0, metavar="STEPS",
+                    help="instead of the benchmark: the actuated quadruped rollout and its actuation gradient")
+    ap.add_argument("--boxes", type=int, default=16,
+                    help="boxes of the batched-workload leg (first of the seeded 256; 0: skip)")
+    ap.add_argument("--boxes-only", action="store_true",
+                    help="instead of the benchmark: only the batched-workload leg, printed as one JSON line")
+    ap.add_argument("--eps-sweep-one", nargs=3, metavar=("TWO_EPS2", "SIDE", "SECONDS"), help=argparse.SUPPRESS)
+    ap.add_argument("--big-batch", type=int, default=4,
+                    help="copies of the twelve recorded scene-steps in the large-batch leg (0: skip)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU; --gpus above 1 is not supported",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    if args.slab_only:
+        print(json.dumps(slab_headline(args)))
+        return
+    if args.quadruped > 0:
+        print(json.dumps(quadruped_leg(args.quadruped, max(1, args.quadruped // 4))))
+        return
+    if args.boxes_only:
+        print(json.dumps(boxes_leg(args.boxes, max(1, args.steps // 10))))
+        return
+    if args.eps_sweep_one:
+        eps_sweep_one(float(args.eps_sweep_one[0]), args.eps_sweep_one[1], float(args.eps_sweep_one[2]))
+        return
+    if args.eps_sweep > 0:
+        eps_sweep(args.eps_sweep)
+        return
+
+    line = slab_headline(args)
+    if not args.no_beam:
+        line["beam"] = beam_legs(args)
+    if args.boxes > 0:
+        line["batched_boxes"] = boxes_leg(args.boxes, 2)
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = slab_cpu_baseline(args)
+    print(json.dumps(line))
 
 
 if __name__ == "__main__":

@@ -301,12 +301,14 @@ adj_status adj_binding_vjp(adj_scene* scene, const double* z, const double* q, c
  * events on the stream it is launched on; adj_profile_end synchronises and
  * returns the summed kernel time (ms) and the launch count, then disarms.
  * kernel: 0 = S product, 1 = S^T product, 2 = capacitance-inverse product,
- * 3 = Z product, 4 = block-sparse Acal^T product (in the Krylov loop fused
+ * 3 = Woodbury correction (Z product, or without Z the scatter and Y
+ * product), 4 = block-sparse Acal^T product (in the Krylov loop fused
  * with the first Gram-Schmidt dots), 5 = per-tet Jacobian blocks, 6 = gather
  * assembly, 7 = the whole capacitance inversion, 8 = second Gram-Schmidt
  * update with the Givens step, 9 = first Gram-Schmidt update, 10 = one
- * Gauss-Jordan block step of the capacitance inversion.  At most 65536 launches
- * are timed per region (later ones are not). */
+ * narrow Gauss-Jordan block step of the capacitance inversion, 11 = the
+ * Delassus product (Y, D = Y^T Y and Z when cached).  At most 65536
+ * bracketed regions are timed per profile (later ones are not). */
 adj_status adj_profile_begin(adj_scene* scene, int32_t kernel);
 adj_status adj_profile_end(adj_scene* scene, double* total_ms, int64_t* launches);
 
@@ -314,12 +316,18 @@ adj_status adj_profile_end(adj_scene* scene, double* total_ms, int64_t* launches
  * over the GPU and the order of floating-point sums inside reductions (so
  * results are bitwise reproducible for a fixed tuning, and agree across
  * tunings to rounding).  Defaults: gs_rows 64, bsr_lanes 16, chunk 8,
- * graph 0. */
+ * graph 0, gj_wide_min 2048, a_inv 0. */
 typedef struct {
   int32_t gs_rows;   /* rows per 256-thread block of the Gram-Schmidt kernels: 64, 128, 256 */
   int32_t bsr_lanes; /* lanes per block row of the Acal^T product: 4, 8, 16, 32 */
   int32_t chunk;     /* Krylov iterations enqueued between host checks: 1..64 */
   int32_t graph;     /* 1: each chunk is captured once per setup as a HIP graph and replayed */
+  int32_t gj_wide_min; /* padded capacitance size (a multiple of 128, >= 128) from which its inverse
+                          runs the wide Gauss-Jordan steps (128 pivot columns per step) instead of
+                          the 32-column ones; default 2048 */
+  int32_t a_inv;     /* A^{-1} in the preconditioner: 1 = the sparse-inverse products S^T S, 2 = level-
+                        scheduled sweeps with the Cholesky factor L, 0 = automatic (sweeps when S holds
+                        more than 32 million and more than 4 nnz(L) entries) */
 } adj_tuning;
 
 /* Set or read the scene's launch shapes.  ADJ_E_ARG on a value outside the

@@ -84,9 +84,16 @@ void launch_bsr_dots(hipStream_t, int, int, const int*, const int*, const double
 void launch_bsr_dots(hipStream_t, int, int, const int*, const int*, const float*, const double*, const double*,
                      double*, long long, const GmresState*, int, double*);
 void launch_fold_partials(hipStream_t, double*, int, const GmresState*, int);
+double* launch_gj_wide(hipStream_t, int, double*, double*, double*, double*, int*);
+size_t gj_wide_lds_bytes();
 void launch_spmv_tasks_acc(hipStream_t, int, const int4*, const long long*, const int*, const double*,
                            const double*, double, const GmresState*, double*);
 void launch_gather_values(hipStream_t, long long, const long long*, const double*, double*);
+void launch_spmv_tasks_acc(hipStream_t, int, const int4*, const long long*, const int*, const float*,
+                           const double*, double, const GmresState*, double*);
+void launch_perm_gather(hipStream_t, int, const int*, const double*, long long, const double*, const GmresState*,
+                        double*);
+void launch_perm_scatter(hipStream_t, int, const int*, const double*, const GmresState*, double*);
 void launch_gm_update(hipStream_t, long long, int, double*, long long, const double*, const GmresState*,
                       const double*, int, double*, double*, int);
 void launch_gm_givens(hipStream_t, GmresState*, const double*, int, double*, const double*, double*, double*,
@@ -156,7 +163,7 @@ hipError_t upload(T** p, const std::vector<T>& v) {
 
 struct adj_scene {
   HostScene hs;
-  adj_tuning tune{64, 16, 8, 0};
+  adj_tuning tune{64, 16, 8, 0, 2048, 0};
   int nv = 0, nt = 0, nnzb = 0, max_contacts = 0;
   int material = 0;  // adj_material of the local projection
   int nb = 0;  // bilateral bindings: vertex ids and compliances on the device
@@ -190,6 +197,10 @@ struct adj_scene {
   // batch of one): tile list of the padded size gj_mp, scene list {0},
   // offset {0}, size {gj_mp}, two pivot slots
   int gj_mp = 0;
+  // wide Gauss-Jordan (128 pivot columns per step, from the padded size
+  // tune.gj_wide_min up): its pivot block and panel scratch
+  double *d_gjw_P = nullptr, *d_gjw_W = nullptr;
+  size_t cap_gjw_W = 0;
   int4* d_gj_tiles = nullptr;
   int* d_gj_one = nullptr;        // [0] = scene 0, [1] = padded size
   long long* d_gj_xoff = nullptr;
@@ -243,6 +254,16 @@ struct adj_scene {
   int nY_tasks = 0, nCT_tasks = 0;
   size_t cap_ynnz = 0, cap_ytasks = 0, cap_cttasks = 0;
   long long y_nnz = 0;
+  // A^{-1} through level-scheduled sweeps with L instead of the S products
+  // (use_sweeps, from tune.a_inv): device copies of the host sweep arrays
+  // (FP64 and FP32 values), the permutation, two work vectors [3 n_v]
+  bool sweeps_built = false, use_sweeps = false;
+  int n_levels = 0;
+  long long *d_Fp = nullptr, *d_Bp = nullptr, *d_Ip = nullptr, *d_ITp = nullptr;
+  int *d_Fj = nullptr, *d_Bj = nullptr, *d_Ij = nullptr, *d_ITj = nullptr, *d_perm = nullptr;
+  double *d_Fx = nullptr, *d_Bx = nullptr, *d_Ix = nullptr, *d_ITx = nullptr, *d_lt = nullptr, *d_lz = nullptr;
+  float *d_Fx32 = nullptr, *d_Bx32 = nullptr, *d_Ix32 = nullptr, *d_ITx32 = nullptr;
+  int *d_fA = nullptr, *d_fB = nullptr, *d_bA = nullptr, *d_bB = nullptr;
   // actuation (active stress per tet group): group and fibre per tet, the
   // tets of each group (CSR), per-tet scratch
   int n_act = 0;
@@ -321,7 +342,11 @@ static void free_scene(adj_scene* s) {
                   s->d_fu,       s->d_du,     s->d_ut,    s->d_qcur,        s->d_rq,
                   s->d_rhs,      s->d_cvec,   s->d_cu,    s->d_norms,       s->d_Sx32,
                   s->d_STx32,    s->d_val32,  s->d_Pws,   s->d_x_pcg, s->d_bvid, s->d_bE,
-                  s->d_Yp,       s->d_Ysrc,   s->d_Ycol,  s->d_Ytasks,      s->d_CTtasks, s->d_Yval};
+                  s->d_Yp,       s->d_Ysrc,   s->d_Ycol,  s->d_Ytasks,      s->d_CTtasks, s->d_Yval,
+                  s->d_gjw_P,    s->d_gjw_W,
+                  s->d_Fp, s->d_Bp, s->d_Ip, s->d_ITp, s->d_Fj, s->d_Bj, s->d_Ij, s->d_ITj, s->d_perm,
+                  s->d_Fx, s->d_Bx, s->d_Ix, s->d_ITx, s->d_lt, s->d_lz, s->d_Fx32, s->d_Bx32, s->d_Ix32, s->d_ITx32,
+                  s->d_fA, s->d_fB, s->d_bA, s->d_bB};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (s->h_state) (void)hipHostFree(s->h_state);
@@ -424,6 +449,29 @@ static adj_status scene_create(const adj_scene_desc* desc, int32_t max_contacts,
   UP(s->d_STtasks, h.ST_tasks);
   s->nS_tasks = (int)(h.S_tasks.size() / 4);
   s->nST_tasks = (int)(h.ST_tasks.size() / 4);
+  if (h.n_levels > 0) {
+    std::vector<long long> Fp(h.Fp.begin(), h.Fp.end()), Bp(h.Bp.begin(), h.Bp.end()),
+        Ip(h.Ip.begin(), h.Ip.end()), ITp(h.ITp.begin(), h.ITp.end());
+    UP(s->d_Fp, Fp);
+    UP(s->d_Bp, Bp);
+    UP(s->d_Ip, Ip);
+    UP(s->d_ITp, ITp);
+    UP(s->d_Fj, h.Fj);
+    UP(s->d_Bj, h.Bj);
+    UP(s->d_Ij, h.Ij);
+    UP(s->d_ITj, h.ITj);
+    UP(s->d_Fx, h.Fx);
+    UP(s->d_Bx, h.Bx);
+    UP(s->d_Ix, h.Ix);
+    UP(s->d_ITx, h.ITx);
+    UP(s->d_perm, h.perm);
+    UP(s->d_fA, h.fA_tasks);
+    UP(s->d_fB, h.fB_tasks);
+    UP(s->d_bA, h.bA_tasks);
+    UP(s->d_bB, h.bB_tasks);
+    s->n_levels = h.n_levels;
+    s->sweeps_built = true;
+  }
 #undef UP
   bool ok = true;
   const size_t mc = (size_t)std::max(1, max_contacts);
@@ -490,6 +538,22 @@ static adj_status scene_create(const adj_scene_desc* desc, int32_t max_contacts,
   if (!ok) {
     free_scene(s);
     return fail(ADJ_E_OOM, "device workspace allocation failed");
+  }
+  if (s->sweeps_built) {
+    ok &= dalloc(&s->d_lt, (size_t)s->n3) == hipSuccess;
+    ok &= dalloc(&s->d_lz, (size_t)s->n3) == hipSuccess;
+    ok &= dalloc(&s->d_Fx32, std::max<size_t>(h.Fx.size(), 1)) == hipSuccess;
+    ok &= dalloc(&s->d_Bx32, std::max<size_t>(h.Bx.size(), 1)) == hipSuccess;
+    ok &= dalloc(&s->d_Ix32, std::max<size_t>(h.Ix.size(), 1)) == hipSuccess;
+    ok &= dalloc(&s->d_ITx32, std::max<size_t>(h.ITx.size(), 1)) == hipSuccess;
+    if (!ok) {
+      free_scene(s);
+      return fail(ADJ_E_OOM, "device workspace allocation failed (sweeps)");
+    }
+    launch_to_f32(nullptr, (long long)h.Fx.size(), s->d_Fx, s->d_Fx32);
+    launch_to_f32(nullptr, (long long)h.Bx.size(), s->d_Bx, s->d_Bx32);
+    launch_to_f32(nullptr, (long long)h.Ix.size(), s->d_Ix, s->d_Ix32);
+    launch_to_f32(nullptr, (long long)h.ITx.size(), s->d_ITx, s->d_ITx32);
   }
   launch_to_f32(nullptr, (long long)h.Sx.size(), s->d_Sx, s->d_Sx32);
   launch_to_f32(nullptr, (long long)h.STx.size(), s->d_STx, s->d_STx32);
@@ -684,8 +748,11 @@ static adj_status contact_layout(adj_scene* s, hipStream_t st, int nc, const std
     }
     const int ks = delassus_slices(s->nv, ncv);
     if (ks > 1 && (a = grow(&s->d_Pws, &s->cap_pws, (size_t)ks * ncv * ncv)) != ADJ_OK) return a;
-    launch_delassus(st, s->nv, ncv, s->d_cv, s->d_STp, s->d_STj, s->d_STx, s->d_Y, s->d_D, use_z ? s->d_Z : nullptr,
-                    s->d_Pws);
+    {
+      ProfScope p(s, 11, st);
+      launch_delassus(st, s->nv, ncv, s->d_cv, s->d_STp, s->d_STj, s->d_STx, s->d_Y, s->d_D,
+                      use_z ? s->d_Z : nullptr, s->d_Pws);
+    }
     if (!use_z && (a = build_y_rows(s, st, cv)) != ADJ_OK) return a;
     s->cv_cached = cv;
     s->delassus_valid = true;
@@ -703,8 +770,12 @@ static adj_status build_capacitance(adj_scene* s, hipStream_t st, double mu, int
   drop_chunk_graphs(s);  // captured chunks hold the contact layout and the address of X
   if (!s->nc) return ADJ_OK;
   const double h2 = s->hs.h * s->hs.h;
-  const int m = s->m, mp = ((m + 63) / 64) * 64;  // Gauss-Jordan tiles are 64 x 64
+  const int m = s->m;
   if (m > 3 * kMaxContacts) return fail(ADJ_E_SHAPE, "more than 10000 contacts in one capacitance");
+  // narrow Gauss-Jordan tiles are 64 x 64, the wide steps 128 columns
+  const int mpw = ((m + 127) / 128) * 128;
+  const bool wide = mpw >= s->tune.gj_wide_min && s->lds_max >= gj_wide_lds_bytes();
+  const int mp = wide ? mpw : ((m + 63) / 64) * 64;
   s->mp = mp;
   size_t capC = s->cap_m * s->cap_m, capB = capC;
   if ((size_t)mp > s->cap_m) capC = capB = 0;
@@ -714,6 +785,15 @@ static adj_status build_capacitance(adj_scene* s, hipStream_t st, double mu, int
   s->cap_m = std::max(s->cap_m, (size_t)mp);
   launch_capacitance(st, m, mp, s->d_row_c, s->d_row_i, s->d_cmap, s->ncv, s->d_D, s->d_Q, s->d_kh, mu, h2,
                      transpose, s->d_C);
+  if (wide) {
+    size_t capP = s->d_gjw_P ? (size_t)128 * 128 : 0;
+    if ((a = grow(&s->d_gjw_P, &capP, (size_t)128 * 128)) != ADJ_OK) return a;
+    if ((a = grow(&s->d_gjw_W, &s->cap_gjw_W, (size_t)mp * 128)) != ADJ_OK) return a;
+    ProfScope p(s, 7, st);
+    launch_gj_pad(st, m, mp, s->d_C);
+    s->d_X = launch_gj_wide(st, mp, s->d_C, s->d_colbuf, s->d_gjw_P, s->d_gjw_W, s->d_err);
+    return ADJ_OK;
+  }
   if (mp != s->gj_mp) {
     // tiles {scene 0, I, J} of the padded matrix, the same at every step
     const int nt = mp / 64;
@@ -842,6 +922,83 @@ extern "C" adj_status adj_check_status(adj_scene* s, void* stream) {
 
 // P x -> out (x and out distinct from the scratch vectors t1, u, tvec).
 // f32: S and S^T are read from their FP32 copies (vectors, X and Z stay FP64).
+// A_s^{-1} = S^T S with S = L^{-1} P, applied either as the two sparse-inverse
+// products or as two level-scheduled sweeps with L (s->use_sweeps).
+// s_forward: y = S x (x vertex-indexed, the current basis vector scaled when
+// state and scale are given; y in elimination order).
+static void s_forward(adj_scene* s, hipStream_t st, const double* x, long long stride, const double* scale,
+                      const GmresState* state, double* y, bool f32) {
+  if (!s->use_sweeps) {
+    if (f32)
+      launch_spmv_tasks(st, s->nS_tasks, (const int4*)s->d_Stasks, s->d_Sp, s->d_Sj, s->d_Sx32, x, stride, scale,
+                        state, y);
+    else
+      launch_spmv_tasks(st, s->nS_tasks, (const int4*)s->d_Stasks, s->d_Sp, s->d_Sj, s->d_Sx, x, stride, scale,
+                        state, y);
+    return;
+  }
+  const HostScene& h = s->hs;
+  launch_perm_gather(st, s->nv, s->d_perm, x, stride, scale, state, s->d_lt);
+  for (int l = 0; l < s->n_levels; ++l) {
+    const int a0 = h.fA_off[l], na = h.fA_off[l + 1] - a0, b0 = h.fB_off[l], nb = h.fB_off[l + 1] - b0;
+    const int4* ta = (const int4*)s->d_fA + a0;
+    const int4* tb = (const int4*)s->d_fB + b0;
+    if (f32) {
+      launch_spmv_tasks_acc(st, na, ta, s->d_Fp, s->d_Fj, s->d_Fx32, y, -1.0, state, s->d_lt);
+      if (nb) launch_spmv_tasks(st, nb, tb, s->d_Ip, s->d_Ij, s->d_Ix32, s->d_lt, 0, nullptr, state, y);
+    } else {
+      launch_spmv_tasks_acc(st, na, ta, s->d_Fp, s->d_Fj, s->d_Fx, y, -1.0, state, s->d_lt);
+      if (nb) launch_spmv_tasks(st, nb, tb, s->d_Ip, s->d_Ij, s->d_Ix, s->d_lt, 0, nullptr, state, y);
+    }
+  }
+}
+
+// s_transpose: out = S^T y (y in elimination order, out vertex-indexed).
+static void s_transpose(adj_scene* s, hipStream_t st, const double* y, const GmresState* state, double* out,
+                        bool f32) {
+  if (!s->use_sweeps) {
+    if (f32)
+      launch_spmv_tasks(st, s->nST_tasks, (const int4*)s->d_STtasks, s->d_STp, s->d_STj, s->d_STx32, y, 0, nullptr,
+                        state, out);
+    else
+      launch_spmv_tasks(st, s->nST_tasks, (const int4*)s->d_STtasks, s->d_STp, s->d_STj, s->d_STx, y, 0, nullptr,
+                        state, out);
+    return;
+  }
+  const HostScene& h = s->hs;
+  (void)hipMemcpyAsync(s->d_lt, y, (size_t)s->n3 * sizeof(double), hipMemcpyDeviceToDevice, st);
+  for (int l = s->n_levels - 1; l >= 0; --l) {
+    const int a0 = h.bA_off[l], na = h.bA_off[l + 1] - a0, b0 = h.bB_off[l], nb = h.bB_off[l + 1] - b0;
+    const int4* ta = (const int4*)s->d_bA + a0;
+    const int4* tb = (const int4*)s->d_bB + b0;
+    if (f32) {
+      launch_spmv_tasks_acc(st, na, ta, s->d_Bp, s->d_Bj, s->d_Bx32, s->d_lz, -1.0, state, s->d_lt);
+      if (nb) launch_spmv_tasks(st, nb, tb, s->d_ITp, s->d_ITj, s->d_ITx32, s->d_lt, 0, nullptr, state, s->d_lz);
+    } else {
+      launch_spmv_tasks_acc(st, na, ta, s->d_Bp, s->d_Bj, s->d_Bx, s->d_lz, -1.0, state, s->d_lt);
+      if (nb) launch_spmv_tasks(st, nb, tb, s->d_ITp, s->d_ITj, s->d_ITx, s->d_lt, 0, nullptr, state, s->d_lz);
+    }
+  }
+  launch_perm_scatter(st, s->nv, s->d_perm, s->d_lz, state, out);
+}
+
+// Sweeps or products: tune.a_inv 2 / 1, or automatically sweeps when S holds
+// far more entries than L (large scenes, where the products are bound by
+// streaming S) and the products otherwise (small scenes, where the sweeps'
+// level launches would dominate).
+static void choose_a_inv(adj_scene* s) {
+  const long long nnzL = (long long)s->hs.Li.size();
+  const bool big = s->nnzS >= 32000000LL && s->nnzS >= 4 * nnzL;
+  const bool want = s->tune.a_inv == 2 || (s->tune.a_inv == 0 && big);
+  if (want && s->sweeps_built) {
+    if (!s->use_sweeps) drop_chunk_graphs(s);
+    s->use_sweeps = true;
+  } else {
+    if (s->use_sweeps) drop_chunk_graphs(s);
+    s->use_sweeps = false;
+  }
+}
+
 static void apply_precond(adj_scene* s, hipStream_t st, const double* x, long long stride,
                           const double* scale, const GmresState* state, double* out, bool f32 = false) {
   const double h2 = s->hs.h * s->hs.h;
@@ -855,12 +1012,7 @@ static void apply_precond(adj_scene* s, hipStream_t st, const double* x, long lo
       s->nc > 0 && (s->precond == ADJ_PRECOND_WOODBURY || s->precond == ADJ_PRECOND_WOODBURY_NO_Z);
   {
     ProfScope p(s, 0, st);
-    if (f32)
-      launch_spmv_tasks(st, s->nS_tasks, (const int4*)s->d_Stasks, s->d_Sp, s->d_Sj, s->d_Sx32, x, stride,
-                        scale, state, s->d_t1);
-    else
-      launch_spmv_tasks(st, s->nS_tasks, (const int4*)s->d_Stasks, s->d_Sp, s->d_Sj, s->d_Sx, x, stride,
-                        scale, state, s->d_t1);
+    s_forward(s, st, x, stride, scale, state, s->d_t1, f32);
   }
   if (woodbury && !s->use_z) {
     // Correction through Y = S E:  A^{-1} r - h^2 A^{-1} H^T t' =
@@ -887,12 +1039,7 @@ static void apply_precond(adj_scene* s, hipStream_t st, const double* x, long lo
                           state, s->d_t1);
     {
       ProfScope p1(s, 1, st);
-      if (f32)
-        launch_spmv_tasks(st, s->nST_tasks, (const int4*)s->d_STtasks, s->d_STp, s->d_STj, s->d_STx32, s->d_t1,
-                          0, nullptr, state, out);
-      else
-        launch_spmv_tasks(st, s->nST_tasks, (const int4*)s->d_STtasks, s->d_STp, s->d_STj, s->d_STx, s->d_t1,
-                          0, nullptr, state, out);
+      s_transpose(s, st, s->d_t1, state, out, f32);
     }
     if (f32)
       launch_spmv_tasks(st, s->nCT_tasks, (const int4*)s->d_CTtasks, s->d_STp, s->d_STj, s->d_STx, s->d_t1, 0,
@@ -902,12 +1049,7 @@ static void apply_precond(adj_scene* s, hipStream_t st, const double* x, long lo
   double* u = woodbury ? s->d_u : out;
   {
     ProfScope p(s, 1, st);
-    if (f32)
-      launch_spmv_tasks(st, s->nST_tasks, (const int4*)s->d_STtasks, s->d_STp, s->d_STj, s->d_STx32, s->d_t1,
-                        0, nullptr, state, u);
-    else
-      launch_spmv_tasks(st, s->nST_tasks, (const int4*)s->d_STtasks, s->d_STp, s->d_STj, s->d_STx, s->d_t1,
-                        0, nullptr, state, u);
+    s_transpose(s, st, s->d_t1, state, u, f32);
   }
   if (!woodbury) return;
   {
@@ -1247,6 +1389,7 @@ static adj_status adjoint_solve_impl(adj_scene* s, const double* dL_dq, const do
     return fail(ADJ_E_ARG, "adjoint_setup must run with ADJ_MIXED before a mixed solve");
   hipStream_t st = (hipStream_t)stream;
   const long long n3 = s->n3;
+  choose_a_inv(s);
   // b = dL_dq + dL_dv / h
   HIPCHK(hipMemcpyAsync(s->d_rhs, dL_dq, n3 * sizeof(double), hipMemcpyDeviceToDevice, st));
   launch_axpy(st, n3, 1.0 / s->hs.h, dL_dv, s->d_rhs);
@@ -1366,7 +1509,9 @@ extern "C" adj_status adj_binding_vjp(adj_scene* s, const double* z, const doubl
 static bool valid_tuning(const adj_tuning& t) {
   const bool gs = t.gs_rows == 64 || t.gs_rows == 128 || t.gs_rows == 256;
   const bool ln = t.bsr_lanes == 4 || t.bsr_lanes == 8 || t.bsr_lanes == 16 || t.bsr_lanes == 32;
-  return gs && ln && t.chunk >= 1 && t.chunk <= 64 && (t.graph == 0 || t.graph == 1);
+  const bool gw = t.gj_wide_min >= 128 && t.gj_wide_min % 128 == 0;
+  const bool ai = t.a_inv >= 0 && t.a_inv <= 2;
+  return gs && ln && gw && ai && t.chunk >= 1 && t.chunk <= 64 && (t.graph == 0 || t.graph == 1);
 }
 
 extern "C" adj_status adj_set_tuning(adj_scene* s, const adj_tuning* t) {
@@ -1450,7 +1595,7 @@ extern "C" adj_status adj_autotune(adj_scene* s, const double* dL_dq, const doub
 }
 
 extern "C" adj_status adj_profile_begin(adj_scene* s, int32_t kernel) {
-  if (!s || kernel < 0 || kernel > 10) return fail(ADJ_E_ARG, "bad profile request");
+  if (!s || kernel < 0 || kernel > 11) return fail(ADJ_E_ARG, "bad profile request");
   s->prof_kernel = kernel;
   s->prof_used = 0;
   return ADJ_OK;

@@ -11,6 +11,7 @@
 #include <thread>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <numeric>
 
@@ -46,16 +47,23 @@ void inv3(const double* a, double* out, double* det_out) {
 
 // Geometric nested dissection on the vertex graph: split the longest axis of
 // the bounding box at the median, take as separator the vertices of the
-// first half that touch the second half, recurse, separator last.
-void nested_dissection(const std::vector<int32_t>& verts, const std::vector<double>& pos,
-                       const std::vector<std::vector<int32_t>>& adj, std::vector<int32_t>& out,
-                       std::vector<int8_t>& side) {
+// first half that touch the second half, recurse, separator last.  Every
+// leaf subdomain and every separator is recorded as a segment of the
+// ordering with its height in the separator tree (leaves 0, a separator one
+// above the higher of its two halves); returns the height of the subtree
+// (-1 when it recorded no segment).  L couples a segment only with its
+// descendants and ancestors, so segments of equal height are independent.
+int nested_dissection(const std::vector<int32_t>& verts, const std::vector<double>& pos,
+                      const std::vector<std::vector<int32_t>>& adj, std::vector<int32_t>& out,
+                      std::vector<int8_t>& side, std::vector<NdSegment>& segs) {
   const size_t kLeaf = 48;
+  if (verts.empty()) return -1;
   if (verts.size() <= kLeaf) {
     std::vector<int32_t> v = verts;
     std::sort(v.begin(), v.end());
+    segs.push_back({(int32_t)out.size(), (int32_t)v.size(), 0});
     out.insert(out.end(), v.begin(), v.end());
-    return;
+    return 0;
   }
   double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
   for (int32_t v : verts)
@@ -96,13 +104,18 @@ void nested_dissection(const std::vector<int32_t>& verts, const std::vector<doub
   for (int32_t a : v) side[a] = 0;
   if (left.empty() || right.empty()) {
     std::sort(v.begin(), v.end());
+    segs.push_back({(int32_t)out.size(), (int32_t)v.size(), 0});
     out.insert(out.end(), v.begin(), v.end());
-    return;
+    return 0;
   }
-  nested_dissection(left, pos, adj, out, side);
-  nested_dissection(right, pos, adj, out, side);
+  const int hl = nested_dissection(left, pos, adj, out, side, segs);
+  const int hr = nested_dissection(right, pos, adj, out, side, segs);
+  const int h = std::max(hl, hr);
+  if (sep.empty()) return h;
   std::sort(sep.begin(), sep.end());
+  segs.push_back({(int32_t)out.size(), (int32_t)sep.size(), h + 1});
   out.insert(out.end(), sep.begin(), sep.end());
+  return h + 1;
 }
 
 }  // namespace
@@ -141,6 +154,158 @@ std::vector<int32_t> make_row_tasks(const std::vector<int64_t>& rowptr, int64_t 
     t.insert(t.end(), small.begin(), small.end());
   }
   return t;
+}
+
+// Level-scheduled triangular sweeps with the Cholesky factor (A_s^{-1} =
+// P^T L^{-T} L^{-1} P).  Per segment of the nested dissection (a leaf
+// subdomain or a separator, contiguous in the elimination order) the
+// diagonal block L_ss is inverted densely; the remaining entries of L couple
+// a segment only to its descendants (rows) or ancestors (columns).  Forward
+// sweep, levels by increasing height:  t_s -= L_{s,desc} y_desc, then
+// y_s = L_ss^{-1} t_s.  Backward, levels by decreasing height:
+// t_s -= L_{anc,s}^T z_anc, then z_s = L_ss^{-T} t_s.  All four parts are
+// CSR over elimination rows, with per-level task lists of the rows that
+// have entries.
+void build_sweeps(HostScene& s) {
+  const int nv = s.nv;
+  std::vector<int32_t> seg_of(nv, -1);
+  int levels = 0;
+  for (size_t g = 0; g < s.segs.size(); ++g) {
+    for (int32_t i = 0; i < s.segs[g].len; ++i) seg_of[s.segs[g].start + i] = (int32_t)g;
+    levels = std::max(levels, s.segs[g].height + 1);
+  }
+  for (int i = 0; i < nv; ++i)
+    if (seg_of[i] < 0) return;  // not a complete segmentation: no sweeps
+  // off-diagonal-block entries: forward rows (row i of L, columns j < i in
+  // other segments) by counting from the CSC columns; backward rows (column
+  // j of L below its segment) straight from the columns
+  s.Fp.assign(nv + 1, 0);
+  s.Bp.assign(nv + 1, 0);
+  for (int j = 0; j < nv; ++j)
+    for (int32_t p = s.Lp[j] + 1; p < s.Lp[j + 1]; ++p)
+      if (seg_of[s.Li[p]] != seg_of[j]) {
+        s.Fp[s.Li[p] + 1]++;
+        s.Bp[j + 1]++;
+      }
+  for (int i = 0; i < nv; ++i) {
+    s.Fp[i + 1] += s.Fp[i];
+    s.Bp[i + 1] += s.Bp[i];
+  }
+  s.Fj.resize(s.Fp[nv]);
+  s.Fx.resize(s.Fp[nv]);
+  s.Bj.resize(s.Bp[nv]);
+  s.Bx.resize(s.Bp[nv]);
+  {
+    std::vector<int64_t> fpos(s.Fp.begin(), s.Fp.end() - 1);
+    for (int j = 0; j < nv; ++j) {
+      int64_t b = s.Bp[j];
+      for (int32_t p = s.Lp[j] + 1; p < s.Lp[j + 1]; ++p)
+        if (seg_of[s.Li[p]] != seg_of[j]) {
+          const int64_t o = fpos[s.Li[p]]++;
+          s.Fj[o] = j;
+          s.Fx[o] = s.Lx[p];
+          s.Bj[b] = s.Li[p];
+          s.Bx[b++] = s.Lx[p];
+        }
+    }
+  }
+  // dense inverses of the diagonal blocks, segments spread over host threads
+  const size_t nseg = s.segs.size();
+  std::vector<std::vector<double>> inv(nseg);
+  auto invert = [&](size_t g) {
+    const int32_t s0 = s.segs[g].start, n = s.segs[g].len;
+    std::vector<double> Ld((size_t)n * n, 0.0);  // row-major lower-triangular block
+    for (int32_t c = 0; c < n; ++c)
+      for (int32_t p = s.Lp[s0 + c]; p < s.Lp[s0 + c + 1]; ++p) {
+        const int32_t r = s.Li[p] - s0;
+        if (r < n) Ld[(size_t)r * n + c] = s.Lx[p];
+      }
+    std::vector<double>& X = inv[g];
+    X.assign((size_t)n * n, 0.0);  // row-major inverse, lower-triangular
+    for (int32_t c = 0; c < n; ++c) {
+      // column c of the inverse: forward substitution of e_c
+      X[(size_t)c * n + c] = 1.0 / Ld[(size_t)c * n + c];
+      for (int32_t r = c + 1; r < n; ++r) {
+        double acc = 0.0;
+        for (int32_t k = c; k < r; ++k) acc += Ld[(size_t)r * n + k] * X[(size_t)k * n + c];
+        X[(size_t)r * n + c] = -acc / Ld[(size_t)r * n + r];
+      }
+    }
+  };
+  {
+    std::vector<size_t> order(nseg);
+    for (size_t g = 0; g < nseg; ++g) order[g] = g;
+    std::sort(order.begin(), order.end(), [&](size_t a, size_t b) { return s.segs[a].len > s.segs[b].len; });
+    const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+    const int nthreads = (int)std::min<unsigned>(16u, hw);
+    std::atomic<size_t> next{0};
+    auto work = [&]() {
+      for (size_t k = next++; k < nseg; k = next++) invert(order[k]);
+    };
+    std::vector<std::thread> pool;
+    for (int t = 1; t < nthreads; ++t) pool.emplace_back(work);
+    work();
+    for (auto& th : pool) th.join();
+  }
+  s.Ip.assign(nv + 1, 0);
+  s.ITp.assign(nv + 1, 0);
+  for (size_t g = 0; g < nseg; ++g) {
+    const int32_t s0 = s.segs[g].start, n = s.segs[g].len;
+    const std::vector<double>& X = inv[g];
+    for (int32_t r = 0; r < n; ++r)
+      for (int32_t c = 0; c < n; ++c)
+        if (X[(size_t)r * n + c] != 0.0) {
+          s.Ip[s0 + r + 1]++;
+          s.ITp[s0 + c + 1]++;
+        }
+  }
+  for (int i = 0; i < nv; ++i) {
+    s.Ip[i + 1] += s.Ip[i];
+    s.ITp[i + 1] += s.ITp[i];
+  }
+  s.Ij.resize(s.Ip[nv]);
+  s.Ix.resize(s.Ip[nv]);
+  s.ITj.resize(s.ITp[nv]);
+  s.ITx.resize(s.ITp[nv]);
+  {
+    std::vector<int64_t> ip(s.Ip.begin(), s.Ip.end() - 1), itp(s.ITp.begin(), s.ITp.end() - 1);
+    for (size_t g = 0; g < nseg; ++g) {
+      const int32_t s0 = s.segs[g].start, n = s.segs[g].len;
+      const std::vector<double>& X = inv[g];
+      for (int32_t r = 0; r < n; ++r)
+        for (int32_t c = 0; c < n; ++c) {
+          const double v = X[(size_t)r * n + c];
+          if (v == 0.0) continue;
+          const int64_t o = ip[s0 + r]++;
+          s.Ij[o] = s0 + c;
+          s.Ix[o] = v;
+          const int64_t o2 = itp[s0 + c]++;  // row s0 + c of L_ss^{-T}: columns s0 + r >= s0 + c
+          s.ITj[o2] = s0 + r;
+          s.ITx[o2] = v;
+        }
+    }
+  }
+  // per-level task lists of each phase
+  s.n_levels = levels;
+  std::vector<std::vector<int32_t>> rows(levels);
+  for (size_t g = 0; g < nseg; ++g)
+    for (int32_t i = 0; i < s.segs[g].len; ++i) rows[s.segs[g].height].push_back(s.segs[g].start + i);
+  auto lists = [&](const std::vector<int64_t>& rp, std::vector<int32_t>& tasks, std::vector<int32_t>& off) {
+    tasks.clear();
+    off.assign(levels + 1, 0);
+    for (int l = 0; l < levels; ++l) {
+      std::vector<int32_t> r;
+      for (int32_t i : rows[l])
+        if (rp[i + 1] > rp[i]) r.push_back(i);
+      const std::vector<int32_t> t = make_row_tasks(rp, 1024, &r);
+      tasks.insert(tasks.end(), t.begin(), t.end());
+      off[l + 1] = (int32_t)(tasks.size() / 4);
+    }
+  };
+  lists(s.Fp, s.fA_tasks, s.fA_off);
+  lists(s.Ip, s.fB_tasks, s.fB_off);
+  lists(s.Bp, s.bA_tasks, s.bA_off);
+  lists(s.ITp, s.bB_tasks, s.bB_off);
 }
 
 adj_status build_host_scene(const adj_scene_desc* d, HostScene& s, std::string& err) {
@@ -306,7 +471,7 @@ adj_status build_host_scene(const adj_scene_desc* d, HostScene& s, std::string& 
     std::vector<int8_t> side(nv, 0);
     s.perm.clear();
     s.perm.reserve(nv);
-    nested_dissection(all, s.rest, adj, s.perm, side);
+    nested_dissection(all, s.rest, adj, s.perm, side, s.segs);
     s.iperm.assign(nv, -1);
     for (int i = 0; i < nv; ++i) s.iperm[s.perm[i]] = i;
   }
@@ -444,6 +609,7 @@ adj_status build_host_scene(const adj_scene_desc* d, HostScene& s, std::string& 
     }
   s.S_tasks = make_row_tasks(s.Sp, 1024);
   s.ST_tasks = make_row_tasks(s.STp, 1024);
+  build_sweeps(s);
   return ADJ_OK;
 }
 

@@ -17,6 +17,12 @@ extern const int kPairK[10];
 extern const int kPairL[10];
 int pair_index(int k, int l);  // k <= l
 
+// A segment of the nested-dissection ordering: a leaf subdomain or a
+// separator, positions [start, start + len), with its separator-tree height.
+struct NdSegment {
+  int32_t start, len, height;
+};
+
 struct HostScene {
   int nv = 0, nt = 0;
   double h = 0, eps = 0, density = 0;
@@ -53,7 +59,21 @@ struct HostScene {
   std::vector<double> Sx, STx;
   // load-balanced row tasks for the S and S^T products (4 ints per block)
   std::vector<int32_t> S_tasks, ST_tasks;
+  // Level-scheduled sweeps with L (build_sweeps): nested-dissection segments;
+  // off-diagonal-block rows of L (F) and of L^T (B); rows of the inverted
+  // diagonal blocks L_ss^{-1} (I) and L_ss^{-T} (IT); per phase the row tasks
+  // of every level, concatenated, with task offsets [n_levels + 1].  Empty
+  // when the ordering has no complete segmentation.
+  std::vector<NdSegment> segs;
+  int n_levels = 0;
+  std::vector<int64_t> Fp, Bp, Ip, ITp;
+  std::vector<int32_t> Fj, Bj, Ij, ITj;
+  std::vector<double> Fx, Bx, Ix, ITx;
+  std::vector<int32_t> fA_tasks, fB_tasks, bA_tasks, bB_tasks;
+  std::vector<int32_t> fA_off, fB_off, bA_off, bB_off;
 };
+
+void build_sweeps(HostScene& s);
 
 // Pack CSR rows into blocks: rows longer than `big` get a block each (flag
 // 0x40000000), shorter rows go four to a block; -1 marks an empty slot.

@@ -624,7 +624,13 @@ __global__ void __launch_bounds__(256) k_gjw_panel(int mp, int k0, const double*
     for (int e = 0; e < 4; ++e) W[(size_t)(r0 + 16 * w + lk + 4 * e) * kWB + 16 * q + li] = acc[q][e];
 }
 
-__global__ void __launch_bounds__(256, 2) k_gjw_tiles(int mp, int k0, const double* __restrict__ A,
+// The panels of the next k-chunk are loaded into registers while the
+// current chunk's products run, and stored to LDS after them (one LDS
+// buffer, two blocks per CU).  The chunk-0 panels are requested before the
+// output tile, so that their wait does not include the tile's loads.
+constexpr int kWPre = kWB * kWKC / 256;  // panel entries per thread and chunk
+
+__global__ void __launch_bounds__(256, 1) k_gjw_tiles(int mp, int k0, const double* __restrict__ A,
                                                       const double* __restrict__ W, double* __restrict__ B) {
   __shared__ double Ws[kWB][kWKC + 1];
   __shared__ double Rs[kWKC][kWB + 1];
@@ -633,6 +639,26 @@ __global__ void __launch_bounds__(256, 2) k_gjw_tiles(int mp, int k0, const doub
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, li = lane & 15, lk = lane >> 4;
   const int wr = 64 * (w >> 1), wc = 64 * (w & 1);
   const bool rowsK = I0 == k0, colsK = J0 == k0;  // tiles are aligned with K
+  double wpre[kWPre], rpre[kWPre];
+  auto load_chunk = [&](int kc) {
+#pragma unroll
+    for (int u = 0; u < kWPre; ++u) {
+      const int e = tid + 256 * u;
+      const int rw = e / kWKC, cw = e % kWKC;
+      wpre[u] = W[(size_t)(I0 + rw) * kWB + kc + cw];
+      const int rr = e / kWB, cr = e % kWB;
+      rpre[u] = colsK ? ((cr == kc + rr) ? 1.0 : 0.0) : A[(size_t)(k0 + kc + rr) * mp + J0 + cr];
+    }
+  };
+  auto store_chunk = [&]() {
+#pragma unroll
+    for (int u = 0; u < kWPre; ++u) {
+      const int e = tid + 256 * u;
+      Ws[e / kWKC][e % kWKC] = wpre[u];
+      Rs[e / kWB][e % kWB] = rpre[u];
+    }
+  };
+  load_chunk(0);
   d4 acc[4][4];
 #pragma unroll
   for (int p = 0; p < 4; ++p)
@@ -643,16 +669,11 @@ __global__ void __launch_bounds__(256, 2) k_gjw_tiles(int mp, int k0, const doub
         const int i = I0 + wr + 16 * p + lk + 4 * e, j = J0 + wc + 16 * q + li;
         acc[p][q][e] = (rowsK || colsK) ? 0.0 : A[(size_t)i * mp + j];
       }
+  store_chunk();
+  __syncthreads();
   for (int kc = 0; kc < kWB; kc += kWKC) {
-    for (int e = tid; e < kWB * kWKC; e += 256) {
-      const int r = e / kWKC, c = e % kWKC;
-      Ws[r][c] = W[(size_t)(I0 + r) * kWB + kc + c];
-    }
-    for (int e = tid; e < kWKC * kWB; e += 256) {
-      const int r = e / kWB, c = e % kWB;
-      Rs[r][c] = colsK ? ((c == kc + r) ? 1.0 : 0.0) : A[(size_t)(k0 + kc + r) * mp + J0 + c];
-    }
-    __syncthreads();
+    const bool more = kc + kWKC < kWB;
+    if (more) load_chunk(kc + kWKC);
 #pragma unroll
     for (int k4 = 0; k4 < kWKC; k4 += 4) {
       double av[4], bv[4];
@@ -666,6 +687,10 @@ __global__ void __launch_bounds__(256, 2) k_gjw_tiles(int mp, int k0, const doub
         for (int q = 0; q < 4; ++q) acc[p][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[p], bv[q], acc[p][q], 0, 0, 0);
     }
     __syncthreads();
+    if (more) {
+      store_chunk();
+      __syncthreads();
+    }
   }
 #pragma unroll
   for (int p = 0; p < 4; ++p)

@@ -623,6 +623,49 @@ void launch_spmv_tasks_acc(hipStream_t s, int ntasks, const int4* tasks, const l
   if (ntasks <= 0) return;
   k_spmv_tasks<double, true><<<ntasks, 256, 0, s>>>(tasks, rp, cj, cx, x, 0, nullptr, st, 0, y, alpha);
 }
+void launch_spmv_tasks_acc(hipStream_t s, int ntasks, const int4* tasks, const long long* rp, const int* cj,
+                           const float* cx, const double* x, double alpha, const GmresState* st, double* y) {
+  if (ntasks <= 0) return;
+  k_spmv_tasks<float, true><<<ntasks, 256, 0, s>>>(tasks, rp, cj, cx, x, 0, nullptr, st, 0, y, alpha);
+}
+
+// Permutation into and out of the elimination order of the sweeps:
+// t[i] = sc x[perm[i]] (x the current basis vector and sc its scale when
+// use_j), and out[perm[i]] = z[i]; three components per entry.
+__global__ void k_perm_gather(int n, const int* __restrict__ perm, const double* __restrict__ xbase,
+                              long long stride, const double* __restrict__ scale,
+                              const GmresState* __restrict__ st, int use_j, double* __restrict__ t) {
+  if (gm_inactive(st)) return;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= 3 * n) return;
+  const double* x = xbase;
+  double sc = 1.0;
+  if (use_j) {
+    x = xbase + (long long)st->j * stride;
+    sc = scale[st->j];
+  }
+  const int i = e / 3, c = e - 3 * i;
+  t[e] = sc * x[3 * perm[i] + c];
+}
+
+__global__ void k_perm_scatter(int n, const int* __restrict__ perm, const double* __restrict__ z,
+                               const GmresState* __restrict__ st, double* __restrict__ out) {
+  if (gm_inactive(st)) return;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= 3 * n) return;
+  const int i = e / 3, c = e - 3 * i;
+  out[3 * perm[i] + c] = z[e];
+}
+
+void launch_perm_gather(hipStream_t s, int n, const int* perm, const double* xbase, long long stride,
+                        const double* scale, const GmresState* st, double* t) {
+  const int use_j = (st != nullptr && scale != nullptr) ? 1 : 0;
+  k_perm_gather<<<(3 * n + 255) / 256, 256, 0, s>>>(n, perm, xbase, stride, scale, st, use_j, t);
+}
+void launch_perm_scatter(hipStream_t s, int n, const int* perm, const double* z, const GmresState* st,
+                         double* out) {
+  k_perm_scatter<<<(3 * n + 255) / 256, 256, 0, s>>>(n, perm, z, st, out);
+}
 
 void launch_block_jacobi(hipStream_t s, int nv, const int* diag_slot, const double* val, const double* x,
                          long long stride, const double* scale, const GmresState* st, int point, double* y) {

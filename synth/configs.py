@@ -263,6 +263,19 @@ def slab_indented_state(spec: SceneSpec, t: int) -> np.ndarray:
     return q
 
 
+def slab_last_step(spec: SceneSpec):
+    """Inputs of the slab workload's measured step, its last one (the most
+    contacts): positions at the start (qbar) and end (q) of the step with the
+    top face on the sphere (slab_indented_state at the sphere's poses of
+    steps T - 1 and T), and the seeded adjoint right-hand side g_q = the loss
+    direction, g_v = 1e-3 N(0, 1).  Returns (qbar, q, g_q, g_v)."""
+    T = spec.steps
+    qbar = slab_indented_state(spec, T - 1)
+    q = slab_indented_state(spec, T)
+    gv = 1e-3 * np.random.default_rng(77).standard_normal(q.shape)
+    return qbar, q, spec.loss_dir.copy(), gv
+
+
 def contact_values(n: int, mu: float, seed: int = 13):
     """Seeded contact displacements and multipliers in frame coordinates for n
     sticking contacts: normal gaps U[1e-13, 1e-11] m, normal forces

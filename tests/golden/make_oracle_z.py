@@ -25,7 +25,7 @@ from oracle import adjoint as adj  # noqa: E402
 from oracle.contact import ContactSet, detect, predict  # noqa: E402
 from oracle.forward import StepRecord  # noqa: E402
 from oracle.rollout import scene_disc  # noqa: E402
-from synth.configs import (batched_scenes, contact_values, perturbed_state, slab_indented_state,  # noqa: E402
+from synth.configs import (batched_scenes, contact_values, perturbed_state, slab_last_step,  # noqa: E402
                            slab_scene)
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -35,14 +35,11 @@ def slab_case(spec=None):
     """(spec, qbar, q, record, g_q, g_v) of the slab's measured step."""
     spec = spec or slab_scene()
     T = spec.steps
-    qbar = slab_indented_state(spec, T - 1)
-    q = slab_indented_state(spec, T)
+    qbar, q, gq, gv = slab_last_step(spec)
     qt = predict(qbar, np.zeros_like(qbar), np.broadcast_to(spec.gravity, qbar.shape), spec.h)
     cs = detect(qbar, qt, spec.planes, spec.sphere_array(T - 1), spec.sphere_array(T), spec.contact_margin)
     delta, lam = contact_values(cs.n, spec.mu)
-    rng = np.random.default_rng(77)
-    gv = 1e-3 * rng.standard_normal(q.shape)
-    return spec, qbar, q, StepRecord(cs, delta, lam, spec.mu), spec.loss_dir.copy(), gv
+    return spec, qbar, q, StepRecord(cs, delta, lam, spec.mu), gq, gv
 
 
 def boxes_cases(n=16):

@@ -189,19 +189,23 @@ def test_beam_delassus_matches_oracle_inverse(prec, tol):
     assert err <= tol
 
 
-@pytest.mark.parametrize("which", ["tiny", "beam"])
+@pytest.mark.parametrize("which", ["tiny", "beam", "tiny-wide", "beam-wide"])
 def test_capacitance_inverse_matches_oracle(which):
     """a4: the Gauss-Jordan inverse X of the transposed-system capacitance
     K^{-T} + h^2 H A^{-1} H^T (Sec. 5.4) against the oracle's capacitance:
     X C = I on the rows the oracle keeps (rows with a zero K entry are
     decoupled on the GPU and dropped by the oracle).  The beam's 891 rows pad
-    to 896 (matrix-core step), the tiny cube's to 128."""
+    to 896 (matrix-core step), the tiny cube's to 128.  "-wide": the same with
+    the 128-column Gauss-Jordan steps (one step on the tiny cube, seven on
+    the beam)."""
     torch = torch_cuda()
     import scipy.sparse.linalg as spla
     from paper_2603_16478_amd import native
     from oracle import contact as ct
     from oracle.woodbury import contact_rows
     from gpu_helpers import contact_tensors
+    wide = which.endswith("-wide")
+    which = which.split("-")[0]
     if which == "tiny":
         spec, ro = _tiny(20)
         rec, q, disc = ro.records[12], ro.qs[13], ro.disc
@@ -226,6 +230,8 @@ def test_capacitance_inverse_matches_oracle(which):
         row += 3
     m = row
     scene = make_scene(spec, max_contacts=rec.contacts.n)
+    if wide:
+        native.set_tuning(scene, gj_wide_min=128)
     tens = contact_tensors(rec)
     cs = native.make_contact_state(rec.contacts.n, tens["vid"], tens["fric"], tens["frame"], tens["delta"],
                                    tens["lam"], rec.mu)
@@ -234,7 +240,7 @@ def test_capacitance_inverse_matches_oracle(which):
     native.check_status(scene)
     X = native.debug_export(scene, 3)
     mp = int(round(np.sqrt(X.size)))
-    assert mp % 64 == 0 and mp >= m
+    assert mp % (128 if wide else 64) == 0 and mp >= m
     X = X.reshape(mp, mp)[np.ix_(keep, keep)]
     res = np.abs(X @ Cref - np.eye(len(keep))).max()
     print(f"capacitance {which}: m {m} (kept {len(keep)}), mp {mp}, |X C - I| {res:.2e}, "

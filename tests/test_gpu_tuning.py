@@ -27,11 +27,11 @@ def _beam(mu=0.4, t=3):
     return beam_scene(mu=mu), d[f"q{t}"], StepRecord(cs, d[f"delta{t}"], d[f"lam{t}"], mu)
 
 
-TUNINGS = [dict(gs_rows=64, bsr_lanes=16, chunk=8, graph=0),
-           dict(gs_rows=128, bsr_lanes=8, chunk=4, graph=0),
-           dict(gs_rows=256, bsr_lanes=32, chunk=16, graph=0),
-           dict(gs_rows=64, bsr_lanes=4, chunk=8, graph=1),
-           dict(gs_rows=128, bsr_lanes=16, chunk=32, graph=1)]
+TUNINGS = [dict(gs_rows=64, bsr_lanes=16, chunk=8, graph=0, gj_wide_min=2048, a_inv=0),
+           dict(gs_rows=128, bsr_lanes=8, chunk=4, graph=0, gj_wide_min=2048, a_inv=2),
+           dict(gs_rows=256, bsr_lanes=32, chunk=16, graph=0, gj_wide_min=128, a_inv=1),
+           dict(gs_rows=64, bsr_lanes=4, chunk=8, graph=1, gj_wide_min=2048, a_inv=2),
+           dict(gs_rows=128, bsr_lanes=16, chunk=32, graph=1, gj_wide_min=128, a_inv=0)]
 
 
 def test_tunings_agree_with_oracle():
@@ -77,7 +77,7 @@ def test_autotune_returns_supported_shape():
     best = native.autotune(scene, gq, gv, z, opts, reps=2)
     print("autotuned", best, flush=True)
     assert best["gs_rows"] in (64, 128, 256) and best["bsr_lanes"] in (4, 8, 16, 32)
-    assert 1 <= best["chunk"] <= 64 and best["graph"] in (0, 1)
+    assert 1 <= best["chunk"] <= 64 and best["graph"] in (0, 1) and best["a_inv"] in (0, 1, 2)
     assert native.get_tuning(scene) == best
     with pytest.raises(native.AdjError):
         native.set_tuning(scene, gs_rows=96)
