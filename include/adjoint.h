@@ -212,6 +212,21 @@ adj_status vjp_params(adj_scene* scene, const double* z, const double* dL_dv, do
                       double* dL_dvbar, double* dL_dfext, double* grad3, double* dE_tet,
                       double* dnu_tet, void* stream);
 
+/* vjp_params for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation):
+ * the same arguments, kernels and results (bitwise), but its reduction
+ * partials use a fixed device array of the library (512 KiB per device,
+ * held until the process ends) instead of the scene's workspace; no call
+ * allocates or frees memory.  The array's device address is looked up once
+ * per device, on the first call with that device current.  Calls on one
+ * device share the array: calls that overlap on one device (concurrent
+ * streams or threads) race.  ADJ_E_SHAPE when the scene needs more than the
+ * array holds (ceil(n_contacts/256) + 2 ceil(n_tets/256) > 65536 partial
+ * sums, about 8.3 million tets). */
+adj_status vjp_params_noalloc(adj_scene* scene, const double* z, const double* dL_dv, double* dL_dqbar,
+                              double* dL_dvbar, double* dL_dfext, double* grad3, double* dE_tet,
+                              double* dnu_tet, void* stream);
+
 /* One implicit step (eq:dynamics): converge (q, lambda) from (qbar, vbar,
  * f_ext) with a damped Newton method whose linear systems are Acal du = r
  * (the adjoint matrix at the iterate, solved with the same GMRES and

@@ -1495,6 +1495,61 @@ extern "C" adj_status vjp_params(adj_scene* s, const double* z, const double* dL
   return ADJ_OK;
 }
 
+// Allocation-free variant of vjp_params.  Its reductions (per-block partial
+// sums of dL/dmu over the contacts and of dL/dE, dL/dnu over the tets) go to
+// a fixed file-scope device array instead of the scene's workspace.  On the
+// host the array's name only stands for the device symbol: its address on a
+// device comes from hipGetSymbolAddress, taken once per device on the first
+// call made with that device current, and only that address is handed to
+// kernels.  Each device holds its own copy until the process ends; every
+// call on a device shares it (no partial needs clearing: each block writes
+// its own), so calls that overlap on one device race.
+constexpr size_t kScratchDoubles = 65536;  // 512 KiB: up to about 8.3 million tets
+static __device__ __align__(256) double scratch[kScratchDoubles];
+constexpr int kScratchDevices = 64;
+static double* g_scratch_dev[kScratchDevices] = {};
+static std::mutex g_scratch_mu;
+
+static adj_status scratch_address(double** out) {
+  int dev = -1;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kScratchDevices) return fail(ADJ_E_DEVICE, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(ADJ_E_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_dev[dev] = static_cast<double*>(p);
+  }
+  *out = g_scratch_dev[dev];
+  return ADJ_OK;
+}
+
+extern "C" adj_status vjp_params_noalloc(adj_scene* s, const double* z, const double* dL_dv, double* dL_dqbar,
+                                         double* dL_dvbar, double* dL_dfext, double* grad3, double* dE_tet,
+                                         double* dnu_tet, void* stream) {
+  if (!s || !z || !dL_dv || !dL_dqbar || !dL_dvbar || !dL_dfext || !grad3)
+    return fail(ADJ_E_ARG, "null argument");
+  if (!s->setup_done) return fail(ADJ_E_ARG, "adjoint_setup has not run");
+  const size_t nbc = ((size_t)s->nc + 255) / 256, nbt = ((size_t)s->nt + 255) / 256;
+  if (nbc + 2 * nbt > kScratchDoubles)
+    return fail(ADJ_E_SHAPE, "scene too large for the fixed scratch of vjp_params_noalloc (at most " +
+                                 std::to_string(kScratchDoubles) + " partial sums: about 8.3 million tets)");
+  double* ptr = nullptr;
+  adj_status a = scratch_address(&ptr);
+  if (a != ADJ_OK) return a;
+  hipStream_t st = (hipStream_t)stream;
+  const double h = s->hs.h, h2 = h * h;
+  launch_vjp_vectors(st, s->nv, z, dL_dv, s->d_mass, h, dL_dqbar, dL_dvbar, dL_dfext);
+  launch_vjp_contacts(st, s->nc, s->cur_vid, s->cur_frame, s->d_Kc, s->d_kmu, z, h2, dL_dqbar, ptr, grad3,
+                      nullptr);
+  launch_vjp_tets(st, s->nt, s->d_tets, s->d_Bt, s->d_vol, s->d_lmu, s->d_llam, s->d_E, s->d_nu, h2, s->cur_q, z,
+                  dE_tet, dnu_tet, ptr + nbc, grad3, s->material);
+  HIPCHK(hipGetLastError());
+  return ADJ_OK;
+}
+
 extern "C" adj_status adj_binding_vjp(adj_scene* s, const double* z, const double* q, const double* targets,
                                       double* dL_dtargets, double* dL_dE, void* stream) {
   if (!s || !z || !q) return fail(ADJ_E_ARG, "null argument");

@@ -29,7 +29,7 @@ MATERIAL_CODES = {"nh": MAT_NEO_HOOKEAN, "arap": MAT_ARAP, "corot": MAT_COROT}
 
 # names declared in include/adjoint.h
 EXPORTS = ("adj_scene_create", "adj_scene_destroy", "adjoint_setup", "adjoint_solve", "vjp_params",
-           "sim_forward_step", "adj_scene_info", "adj_check_status", "adj_debug_export",
+           "vjp_params_noalloc", "sim_forward_step", "adj_scene_info", "adj_check_status", "adj_debug_export",
            "adj_profile_begin", "adj_profile_end", "adj_forward_stats", "adj_forward_reset", "adj_set_spheres",
            "adj_set_actuation", "adj_actuation_force", "adj_actuation_vjp",
            "adj_set_tuning", "adj_get_tuning", "adj_autotune", "adj_batch_create", "adj_batch_destroy",
@@ -99,6 +99,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.adjoint_setup.argtypes = [vp, C.POINTER(ContactState), vp, C.POINTER(SolveOpts), vp]
     lib.adjoint_solve.argtypes = [vp, vp, vp, vp, C.POINTER(SolveOpts), C.POINTER(SolveInfo), vp]
     lib.vjp_params.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.vjp_params_noalloc.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     lib.sim_forward_step.argtypes = [vp, vp, vp, vp, C.c_double, vp, vp, C.POINTER(ContactState), vp]
     lib.adj_scene_info.argtypes = [vp, C.POINTER(C.c_int64)]
     lib.adj_check_status.argtypes = [vp, vp]
@@ -247,6 +248,13 @@ def vjp_params(scene: Scene, z, dL_dv, dL_dqbar, dL_dvbar, dL_dfext, grad3, dE_t
                stream=None):
     check(load().vjp_params(scene.handle, _ptr(z), _ptr(dL_dv), _ptr(dL_dqbar), _ptr(dL_dvbar),
                             _ptr(dL_dfext), _ptr(grad3), _ptr(dE_tet), _ptr(dnu_tet), _stream(stream)))
+
+
+def vjp_params_noalloc(scene: Scene, z, dL_dv, dL_dqbar, dL_dvbar, dL_dfext, grad3, dE_tet=None, dnu_tet=None,
+                       stream=None):
+    """vjp_params without any device allocation (fixed library scratch)."""
+    check(load().vjp_params_noalloc(scene.handle, _ptr(z), _ptr(dL_dv), _ptr(dL_dqbar), _ptr(dL_dvbar),
+                                    _ptr(dL_dfext), _ptr(grad3), _ptr(dE_tet), _ptr(dnu_tet), _stream(stream)))
 
 
 _DEBUG = {0: ("val", np.float64), 1: ("rowptr", np.int32), 2: ("col", np.int32),
