@@ -147,7 +147,12 @@ typedef struct {
   double rtol;          /* relative residual |b - Acal^T z| / |b| (Sec. 6.1: 1e-8) */
   int32_t maxit;        /* total Krylov iterations over all restarts */
   int32_t restart;      /* GMRES restart length, 1..128 */
-  int32_t max_refine;   /* outer FP64 refinement sweeps (mixed precision) */
+  int32_t max_refine;   /* outer refinement sweeps: mixed precision (FP64
+                         * residual, FP32-stored inner solves); FP64 with
+                         * rtol below 1e-9 (residual summed in double-double,
+                         * FP64 inner solves to 1e-9, since plain FP64 Krylov
+                         * stagnates near there on stiff contacts); 0 turns
+                         * FP64 refinement off */
   adj_precision prec;
   int32_t reuse_delassus; /* 1: keep H A^{-1} H^T while the contact vertex set is unchanged */
   adj_krylov method;

@@ -51,7 +51,8 @@ void launch_actuation_vjp(hipStream_t, int, int, const int*, const double*, cons
 void launch_scatter_ht(hipStream_t, int, const int*, const int*, const int*, const int*, const double*,
                        const double*, const GmresState*, double*);
 void launch_delassus(hipStream_t, int, int, const int*, const long long*, const int*, const double*,
-                     double*, double*, double*, double*);
+                     double*, double*, double*, double*, unsigned*);
+int y_panel_words(int);
 int delassus_slices(int, int);
 void launch_gj_pad(hipStream_t, int, int, double*);
 void launchb_gj_pivot(hipStream_t, int, const int*, const long long*, const int*, const double*, double*, int*);
@@ -94,6 +95,8 @@ void launch_spmv_tasks_acc(hipStream_t, int, const int4*, const long long*, cons
 void launch_perm_gather(hipStream_t, int, const int*, const double*, long long, const double*, const GmresState*,
                         double*);
 void launch_perm_scatter(hipStream_t, int, const int*, const double*, const GmresState*, double*);
+void launch_bsr_residual_dd(hipStream_t, int, const int*, const int*, const double*, const double*, const double*,
+                            double*);
 void launch_gm_update(hipStream_t, long long, int, double*, long long, const double*, const GmresState*,
                       const double*, int, double*, double*, int);
 void launch_gm_givens(hipStream_t, GmresState*, const double*, int, double*, const double*, double*, double*,
@@ -254,6 +257,8 @@ struct adj_scene {
   int nY_tasks = 0, nCT_tasks = 0;
   size_t cap_ynnz = 0, cap_ytasks = 0, cap_cttasks = 0;
   long long y_nnz = 0;
+  unsigned* d_ybm = nullptr;  // panel occupancy of Y for the Delassus product
+  size_t cap_ybm = 0;
   // A^{-1} through level-scheduled sweeps with L instead of the S products
   // (use_sweeps, from tune.a_inv): device copies of the host sweep arrays
   // (FP64 and FP32 values), the permutation, two work vectors [3 n_v]
@@ -346,7 +351,7 @@ static void free_scene(adj_scene* s) {
                   s->d_gjw_P,    s->d_gjw_W,
                   s->d_Fp, s->d_Bp, s->d_Ip, s->d_ITp, s->d_Fj, s->d_Bj, s->d_Ij, s->d_ITj, s->d_perm,
                   s->d_Fx, s->d_Bx, s->d_Ix, s->d_ITx, s->d_lt, s->d_lz, s->d_Fx32, s->d_Bx32, s->d_Ix32, s->d_ITx32,
-                  s->d_fA, s->d_fB, s->d_bA, s->d_bB};
+                  s->d_fA, s->d_fB, s->d_bA, s->d_bB, s->d_ybm};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (s->h_state) (void)hipHostFree(s->h_state);
@@ -358,6 +363,10 @@ static void free_scene(adj_scene* s) {
 }
 
 static const int kMaxRestart = 128;
+// Relative residual below which plain FP64 Krylov solves stagnate on stiff
+// contact states; FP64 solves asked for less (with max_refine > 0) refine
+// with a double-double residual.
+static const double kFp64Floor = 1e-9;
 
 extern "C" const char* adj_last_error(void) { return g_err.c_str(); }
 
@@ -750,8 +759,17 @@ static adj_status contact_layout(adj_scene* s, hipStream_t st, int nc, const std
     if (ks > 1 && (a = grow(&s->d_Pws, &s->cap_pws, (size_t)ks * ncv * ncv)) != ADJ_OK) return a;
     {
       ProfScope p(s, 11, st);
+      const size_t nbm = (size_t)((ncv + 63) / 64) * y_panel_words(s->nv);
+      if (nbm > s->cap_ybm) {
+        (void)hipDeviceSynchronize();
+        if (s->d_ybm) (void)hipFree(s->d_ybm);
+        s->d_ybm = nullptr;
+        s->cap_ybm = 0;
+        if (hipMalloc(&s->d_ybm, nbm * sizeof(unsigned)) != hipSuccess) return fail(ADJ_E_OOM, "Y panel bitmap");
+        s->cap_ybm = nbm;
+      }
       launch_delassus(st, s->nv, ncv, s->d_cv, s->d_STp, s->d_STj, s->d_STx, s->d_Y, s->d_D,
-                      use_z ? s->d_Z : nullptr, s->d_Pws);
+                      use_z ? s->d_Z : nullptr, s->d_Pws, s->d_ybm);
     }
     if (!use_z && (a = build_y_rows(s, st, cv)) != ADJ_OK) return a;
     s->cv_cached = cv;
@@ -1400,13 +1418,17 @@ static adj_status adjoint_solve_impl(adj_scene* s, const double* dL_dq, const do
   if (opts->method == ADJ_SEMI_IMPLICIT) {
     a = semi_implicit_solve(s, st, s->d_rhs, z, opts->rtol, opts->maxit, &total, &relres, &converged);
     if (a != ADJ_OK) return a;
-  } else if (opts->prec == ADJ_FP64) {
+  } else if (opts->prec == ADJ_FP64 && !(opts->max_refine > 0 && opts->rtol < kFp64Floor)) {
     a = krylov_solve(s, st, use_pcg, s->d_rhs, z, opts->rtol, opts->maxit, opts->restart, &total, &relres,
                      &converged, false);
     if (a != ADJ_OK) return a;
   } else {
-    // Iterative refinement: FP64 residual r = b - Acal^T z with the FP64
-    // matrix; inner GMRES with FP32-stored matrices solves Acal^T dz = r.
+    // Iterative refinement.  Mixed: FP64 residual r = b - Acal^T z with the
+    // FP64 matrix, inner GMRES with FP32-stored matrices on Acal^T dz = r.
+    // FP64 below the FP64 Krylov floor (rtol < kFp64Floor with max_refine >
+    // 0): inner FP64 solves to the floor, residual in double-double.
+    const bool f32 = opts->prec == ADJ_MIXED;
+    const double floor_inner = f32 ? 1e-6 : kFp64Floor;
     launch_fill_zero(st, (size_t)n3, z);
     HIPCHK(hipMemcpyAsync(s->d_fu, s->d_rhs, n3 * sizeof(double), hipMemcpyDeviceToDevice, st));
     launch_norms(st, n3, s->d_rhs, s->P3(), s->d_norms);
@@ -1419,19 +1441,23 @@ static adj_status adjoint_solve_impl(adj_scene* s, const double* dL_dq, const do
     relres = bnorm > 0 ? 1.0 : 0.0;
     converged = !(bnorm > 0);
     for (refine = 0; refine <= std::max(0, opts->max_refine) && !converged && total < opts->maxit; ++refine) {
-      const double inner = std::max(1e-6, 0.5 * opts->rtol * bnorm / rnorm);
+      const double inner = std::max(floor_inner, 0.5 * opts->rtol * bnorm / rnorm);
       int it = 0;
       double rr = 0.0;
       bool cv = false;
       if ((a = krylov_solve(s, st, use_pcg, s->d_fu, s->d_du, inner, opts->maxit - total, opts->restart, &it,
-                            &rr, &cv, true)) != ADJ_OK)
+                            &rr, &cv, f32)) != ADJ_OK)
         return a;
       total += it;
       const double r_before = rnorm;
       auto residual = [&]() -> adj_status {
-        // r = b - Acal^T z in FP64
-        bsr(s, st, z, s->d_fu, 0, nullptr, false);
-        launch_add_vec(st, n3, s->d_rhs, s->d_fu, -1.0, s->d_fu);
+        // r = b - Acal^T z with the FP64 matrix (double-double sums below the FP64 floor)
+        if (f32) {
+          bsr(s, st, z, s->d_fu, 0, nullptr, false);
+          launch_add_vec(st, n3, s->d_rhs, s->d_fu, -1.0, s->d_fu);
+        } else {
+          launch_bsr_residual_dd(st, s->nv, s->d_rowptr, s->d_col, s->d_val, z, s->d_rhs, s->d_fu);
+        }
         launch_norms(st, n3, s->d_fu, s->P3(), s->d_norms);
         HIPCHK(hipMemcpyAsync(nb, s->d_norms, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
@@ -1441,6 +1467,12 @@ static adj_status adjoint_solve_impl(adj_scene* s, const double* dL_dq, const do
       };
       launch_axpy(st, n3, 1.0, s->d_du, z);
       if ((a = residual()) != ADJ_OK) return a;
+      if (!f32 && !(rnorm < r_before)) {
+        launch_axpy(st, n3, -1.0, s->d_du, z);  // no further progress in FP64: keep the better iterate
+        if ((a = residual()) != ADJ_OK) return a;
+        converged = relres <= opts->rtol;
+        break;
+      }
       if (!(rnorm < r_before)) {
         // The FP32 inner solve did not reduce the residual (contacts so stiff
         // that FP32 rounding of A^{-1} r is amplified past the correction):

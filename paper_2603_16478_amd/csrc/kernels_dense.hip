@@ -63,9 +63,26 @@ template <> struct MfmaAcc<double> {
 constexpr int kSyT = 64;  // output tile edge
 constexpr int kSyK = 16;  // rows of Y per LDS panel
 
+// Panel occupancy of Y: bit p of column group g (kSyT consecutive contact
+// vertices) is set when a vertex of the group has a nonzero of S in rows
+// [kSyK p, kSyK (p + 1)), i.e. on its elimination-tree path.  A tile of D
+// only needs the panels where both of its column groups have entries
+// (integer OR: the bitmap does not depend on the order of the updates).
+__global__ void k_y_panels(int ncv, const int* __restrict__ cv, const long long* __restrict__ STp,
+                           const int* __restrict__ STj, int npw, unsigned* __restrict__ bm) {
+  const int c = blockIdx.x;
+  if (c >= ncv) return;
+  unsigned* w = bm + (size_t)(c / kSyT) * npw;
+  for (long long p = STp[cv[c]] + threadIdx.x; p < STp[cv[c] + 1]; p += blockDim.x) {
+    const int pnl = STj[p] / kSyK;
+    atomicOr(&w[pnl >> 5], 1u << (pnl & 31));
+  }
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_syrk_mfma(int nv, int ncv, int rows_per_slice,
-                                                   const double* __restrict__ Y, double* __restrict__ out) {
+                                                   const double* __restrict__ Y, double* __restrict__ out,
+                                                   const unsigned* __restrict__ bm, int npw) {
   __shared__ T As[kSyK][kSyT + 1];
   __shared__ T Bs[kSyK][kSyT + 1];
   // blockIdx.x enumerates lower-triangle tiles: x = ti (ti + 1) / 2 + tj, tj <= ti
@@ -86,7 +103,13 @@ __global__ void __launch_bounds__(256) k_syrk_mfma(int nv, int ncv, int rows_per
   for (int p = 0; p < 2; ++p)
 #pragma unroll
     for (int q = 0; q < 2; ++q) acc[p][q] = V{0, 0, 0, 0};
+  const unsigned* bi = bm ? bm + (size_t)ti * npw : nullptr;
+  const unsigned* bj = bm ? bm + (size_t)tj * npw : nullptr;
   for (int r0 = r_begin; r0 < r_end; r0 += kSyK) {
+    if (bm) {
+      const int pnl = r0 / kSyK;
+      if (!(((bi[pnl >> 5] & bj[pnl >> 5]) >> (pnl & 31)) & 1u)) continue;  // a zero panel of Y
+    }
 #pragma unroll
     for (int e = 0; e < (kSyK * kSyT) / 256; ++e) {
       const int idx = tid + 256 * e;
@@ -478,26 +501,23 @@ kb_gj_step_mfma(const int* __restrict__ next_scenes, int npiv,
 // matrix cores.  The same B = Ahat - What Rhat step as above, with K the
 // 128 pivot indices k0 .. k0 + 127 and P = A_KK^{-1}; per step three
 // launches:
-//   k_gjw_pivot  one block inverts the 128 x 128 pivot block in LDS by four
-//                Gauss-Jordan sub-steps on its 32 x 32 diagonal blocks (the
-//                same 32-block partial pivoting as the narrow kernels);
 //   k_gjw_panel  What (mp x 128): A_{i,K} P for rows i outside K, -P_i in K;
-//   k_gjw_tiles  the 128 x 128 output tiles of B.
+//   k_gjw_tiles  the 128 x 128 output tiles of B; the tile that is the next
+//                step's pivot block is also inverted (lookahead), so the
+//                serial pivot chain runs beside the tiles.
+// P = A_KK^{-1} of the first step comes from k_gjw_pivot.  The 128 x 128
+// inversions take four Gauss-Jordan sub-steps on their 32 x 32 diagonal
+// blocks in LDS (the same 32-block partial pivoting as the narrow kernels).
 constexpr int kWB = 128;        // pivot block width
 constexpr int kWL = kWB + 1;    // LDS row stride of the pivot block
 constexpr int kWKC = 32;        // k-chunk of the staged panels
 
-__global__ void __launch_bounds__(256) k_gjw_pivot(int mp, int k0, const double* __restrict__ A,
-                                                   double* __restrict__ Pout, int* __restrict__ err) {
-  __shared__ double M[kWB * kWL];
-  __shared__ double Ps[kNB][kNB + 1];
-  __shared__ double prow[2 * kNB];
+// In-place inverse of the 128 x 128 block M (LDS, row stride kWL) by one
+// 256-thread block: four Gauss-Jordan sub-steps on its 32 x 32 diagonal
+// blocks.  Ps (32 x 33) and prow (64) are LDS scratch.
+__device__ void invert128_lds(double* __restrict__ M, double (*Ps)[kNB + 1], double* __restrict__ prow,
+                              int* __restrict__ err) {
   const int tid = threadIdx.x;
-  for (int e = tid; e < kWB * kWB; e += 256) {
-    const int r = e / kWB, c = e % kWB;
-    M[r * kWL + c] = A[(size_t)(k0 + r) * mp + k0 + c];
-  }
-  __syncthreads();
   constexpr int kOut = kWB - kNB;  // rows (columns) outside the sub-step's pivot block
   for (int sb = 0; sb < kWB; sb += kNB) {
     if (tid < 64) invert32_rows(M + sb * kWL + sb, kWL, Ps, prow, err);
@@ -581,6 +601,33 @@ __global__ void __launch_bounds__(256) k_gjw_pivot(int mp, int k0, const double*
     }
     __syncthreads();
   }
+}
+
+// The shared memory of one block of the wide steps: the staged panels of an
+// output tile, or the 128 x 128 block being inverted.
+union GjwShared {
+  struct {
+    double Ws[kWB][kWKC + 1];
+    double Rs[kWKC][kWB + 1];
+  } t;
+  struct {
+    double M[kWB * kWL];
+    double Ps[kNB][kNB + 1];
+    double prow[2 * kNB];
+  } p;
+};
+
+__global__ void __launch_bounds__(256) k_gjw_pivot(int mp, int k0, const double* __restrict__ A,
+                                                   double* __restrict__ Pout, int* __restrict__ err) {
+  __shared__ GjwShared sh;
+  double* M = sh.p.M;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < kWB * kWB; e += 256) {
+    const int r = e / kWB, c = e % kWB;
+    M[r * kWL + c] = A[(size_t)(k0 + r) * mp + k0 + c];
+  }
+  __syncthreads();
+  invert128_lds(M, sh.p.Ps, sh.p.prow, err);
   for (int e = tid; e < kWB * kWB; e += 256) Pout[e] = M[(e / kWB) * kWL + e % kWB];
 }
 
@@ -630,12 +677,23 @@ __global__ void __launch_bounds__(256) k_gjw_panel(int mp, int k0, const double*
 // output tile, so that their wait does not include the tile's loads.
 constexpr int kWPre = kWB * kWKC / 256;  // panel entries per thread and chunk
 
-__global__ void __launch_bounds__(256, 1) k_gjw_tiles(int mp, int k0, const double* __restrict__ A,
-                                                      const double* __restrict__ W, double* __restrict__ B) {
-  __shared__ double Ws[kWB][kWKC + 1];
-  __shared__ double Rs[kWKC][kWB + 1];
+// With k1 >= 0 (a step follows), the tile (k1, k1) is the next step's pivot
+// block: block 0 computes it (blocks are dispatched in index order, so it
+// starts first), then inverts it in LDS and writes P_{k+1} to Pnext while
+// the other tiles of the step run.
+__global__ void __launch_bounds__(256, 1) k_gjw_tiles(int mp, int k0, int k1, const double* __restrict__ A,
+                                                      const double* __restrict__ W, double* __restrict__ B,
+                                                      double* __restrict__ Pnext, int* __restrict__ err) {
+  __shared__ GjwShared sh;
+  auto& Ws = sh.t.Ws;
+  auto& Rs = sh.t.Rs;
   const int nt = mp / kWB;
-  const int I0 = (blockIdx.x / nt) * kWB, J0 = (blockIdx.x % nt) * kWB;
+  int t = blockIdx.x;
+  if (k1 >= 0) {
+    const int diag = (k1 / kWB) * nt + k1 / kWB;
+    t = (t == 0) ? diag : (t == diag ? 0 : t);
+  }
+  const int I0 = (t / nt) * kWB, J0 = (t % nt) * kWB;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, li = lane & 15, lk = lane >> 4;
   const int wr = 64 * (w >> 1), wc = 64 * (w & 1);
   const bool rowsK = I0 == k0, colsK = J0 == k0;  // tiles are aligned with K
@@ -699,6 +757,18 @@ __global__ void __launch_bounds__(256, 1) k_gjw_tiles(int mp, int k0, const doub
 #pragma unroll
       for (int e = 0; e < 4; ++e)
         B[(size_t)(I0 + wr + 16 * p + lk + 4 * e) * mp + J0 + wc + 16 * q + li] = acc[p][q][e];
+  if (k1 < 0 || I0 != k1 || J0 != k1) return;
+  // the next pivot block: into LDS (the panels are no longer needed), invert
+  double* M = sh.p.M;
+#pragma unroll
+  for (int p = 0; p < 4; ++p)
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) M[(wr + 16 * p + lk + 4 * e) * kWL + wc + 16 * q + li] = acc[p][q][e];
+  __syncthreads();
+  invert128_lds(M, sh.p.Ps, sh.p.prow, err);
+  for (int e = tid; e < kWB * kWB; e += 256) Pnext[e] = M[(e / kWB) * kWL + e % kWB];
 }
 
 // identity padding of rows/cols m..mp-1 of a row-major mp x mp matrix
@@ -735,17 +805,28 @@ int delassus_slices(int nv, int ncv) {
   return std::max(ks, 1);
 }
 
+// Words of the panel bitmap per column group of Y
+int y_panel_words(int nv) { return ((nv + kSyK - 1) / kSyK + 31) / 32; }
+
+// bm: [ceil(ncv / 64)][y_panel_words(nv)] scratch for the panel occupancy
+// (nullptr: every panel is multiplied).
 void launch_delassus(hipStream_t st, int nv, int ncv, const int* cv, const long long* STp,
-                     const int* STj, const double* STx, double* Y, double* D, double* Z, double* Pws) {
+                     const int* STj, const double* STx, double* Y, double* D, double* Z, double* Pws,
+                     unsigned* bm) {
   if (ncv == 0) return;
   launch_fill_zero(st, (size_t)nv * ncv, Y);
   k_fill_Y<<<ncv, 256, 0, st>>>(ncv, cv, STp, STj, STx, Y);
   const int nt = (ncv + kSyT - 1) / kSyT;
+  const int npw = y_panel_words(nv);
+  if (bm) {
+    launch_fill_int(st, (size_t)nt * npw, (int*)bm, 0);
+    k_y_panels<<<ncv, 256, 0, st>>>(ncv, cv, STp, STj, npw, bm);
+  }
   const int ks = delassus_slices(nv, ncv);
   const int rows = (((nv + ks - 1) / ks) + kSyK - 1) / kSyK * kSyK;
   dim3 g(nt * (nt + 1) / 2, ks);
   double* out = (ks > 1) ? Pws : D;
-  k_syrk_mfma<double><<<g, 256, 0, st>>>(nv, ncv, rows, Y, out);
+  k_syrk_mfma<double><<<g, 256, 0, st>>>(nv, ncv, rows, Y, out, bm, npw);
   if (ks > 1) {
     const size_t n = (size_t)ncv * ncv;
     k_syrk_reduce<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(ncv, ks, Pws, D);
@@ -780,21 +861,24 @@ void launchb_gj_step(hipStream_t st, int npiv, const int* next_scenes, int ntile
 
 // Wide Gauss-Jordan (mp a multiple of 128): the inverse of the padded matrix
 // in C0 after mp/128 steps, ping-ponging between C0 and C1; returns the
-// buffer holding it.  P: 128 x 128 scratch, W: mp x 128 scratch.
+// buffer holding it.  P: 128 x 128 scratch (the current pivot block's
+// inverse), W: mp x 128 scratch.
 double* launch_gj_wide(hipStream_t st, int mp, double* C0, double* C1, double* P, double* W, int* err) {
   double* A = C0;
   double* B = C1;
   const int nt = mp / kWB;
+  k_gjw_pivot<<<1, 256, 0, st>>>(mp, 0, A, P, err);
   for (int k0 = 0; k0 < mp; k0 += kWB) {
-    k_gjw_pivot<<<1, 256, 0, st>>>(mp, k0, A, P, err);
+    const int k1 = k0 + kWB < mp ? k0 + kWB : -1;
     k_gjw_panel<<<mp / 64, 256, 0, st>>>(mp, k0, A, P, W);
-    k_gjw_tiles<<<nt * nt, 256, 0, st>>>(mp, k0, A, W, B);
+    // P is consumed by the panel kernel before the tiles write P_{k+1} into it
+    k_gjw_tiles<<<nt * nt, 256, 0, st>>>(mp, k0, k1, A, W, B, P, err);
     std::swap(A, B);
   }
   return A;
 }
 
 // LDS one block of the wide Gauss-Jordan pivot kernel needs
-size_t gj_wide_lds_bytes() { return sizeof(double) * ((size_t)kWB * kWL + kNB * (kNB + 1) + 2 * kNB); }
+size_t gj_wide_lds_bytes() { return sizeof(GjwShared); }
 
 }  // namespace adj

@@ -629,6 +629,43 @@ void launch_spmv_tasks_acc(hipStream_t s, int ntasks, const int4* tasks, const l
   k_spmv_tasks<float, true><<<ntasks, 256, 0, s>>>(tasks, rp, cj, cx, x, 0, nullptr, st, 0, y, alpha);
 }
 
+// r = b - Acal^T x with every product and sum carried as an unevaluated
+// pair (error-free product by FMA, two-sum; compensated dot product), rounded
+// once at the end, one thread per DOF.  The residual of the FP64 refinement:
+// FP64 Krylov solves stagnate near a relative residual of 1e-10 on stiff
+// contacts, and only a residual resolved below that lets the refinement
+// reach the solution to working accuracy.  Contraction is off so that the
+// error terms are formed exactly as written.
+__global__ void k_bsr_residual_dd(int nv, const int* __restrict__ rowptr, const int* __restrict__ col,
+                                  const double* __restrict__ val, const double* __restrict__ x,
+                                  const double* __restrict__ b, double* __restrict__ r) {
+#pragma clang fp contract(off)
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= 3 * nv) return;
+  const int row = e / 3, c = e - 3 * row;
+  double hi = b[e], lo = 0.0;
+  for (int p = rowptr[row]; p < rowptr[row + 1]; ++p) {
+    const double* blk = val + 9 * (size_t)p + 3 * c;
+    const double* xj = x + 3 * (size_t)col[p];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const double prod = -blk[k] * xj[k];
+      const double perr = __builtin_fma(-blk[k], xj[k], -prod);  // -blk x = prod + perr exactly
+      const double s = hi + prod;
+      const double bb = s - hi;
+      const double serr = (hi - (s - bb)) + (prod - bb);  // hi + prod = s + serr exactly
+      hi = s;
+      lo += serr + perr;
+    }
+  }
+  r[e] = hi + lo;
+}
+
+void launch_bsr_residual_dd(hipStream_t s, int nv, const int* rowptr, const int* col, const double* val,
+                            const double* x, const double* b, double* r) {
+  k_bsr_residual_dd<<<(3 * nv + 255) / 256, 256, 0, s>>>(nv, rowptr, col, val, x, b, r);
+}
+
 // Permutation into and out of the elimination order of the sweeps:
 // t[i] = sc x[perm[i]] (x the current basis vector and sc its scale when
 // use_j), and out[perm[i]] = z[i]; three components per entry.

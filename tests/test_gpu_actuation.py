@@ -89,7 +89,14 @@ def test_quadruped_actuation_gradient_matches_fd():
     sim = GpuSim(spec, max_contacts=400)
     native.set_actuation(sim.scene, group, fibre, 64)
     q0 = torch.tensor(spec.q0, device="cuda")
-    v0 = torch.tensor(spec.v0, device="cuda")
+    # The quadruped slides at 0.2 m/s along x: a foot that stands still under
+    # almost no tangential load converges with a friction magnitude s of
+    # either sign, decided by the slip direction of the first Newton iterate,
+    # and the forward demotes a contact with s < 0 to normal-only, so probes
+    # of 1e-8 relative switch branches there.  Sliding feet carry s = mu
+    # lambda_n, far from that switch, for the whole test.
+    v0 = torch.zeros_like(q0)
+    v0[:, 0] = 0.2
     a0 = torch.tensor(actuation_params(T, amplitude=2e3), device="cuda")
 
     def loss_of(a):
@@ -111,21 +118,32 @@ def test_quadruped_actuation_gradient_matches_fd():
         state = [(r.vid[:r.n].cpu().numpy().tobytes(), r.fric[:r.n].cpu().numpy().tobytes()) for _, r in recs]
         return float(torch.sum(w * qT)), state
 
-    _, base = run(a0)
+    L0, base = run(a0)
+    _, again = run(a0)
+    assert again == base  # the forward rollout is deterministic
     rng = np.random.default_rng(9)
+    checked = 0
     with torch.no_grad():
-        for i in range(3):
+        for i in range(8):
             d = torch.tensor(rng.standard_normal(a0.shape), device="cuda")
             ad = float(torch.sum(a.grad * d))
             # central differences where neither side changes a contact's
-            # stick/slip state or the contact set (the step map is not
-            # differentiable across those changes); parameters are ~2e3 Pa
-            for eta in (0.02, 0.002, 0.0002):
+            # frictional flag or the contact set (the step map is not
+            # differentiable across those changes); parameters are ~2e3 Pa.
+            # A direction along which every probe step changes the contact
+            # state (a contact at its switching threshold) is skipped.
+            for eta in (0.02, 0.002, 0.0002, 0.00002):
                 (lp, sp), (lm, sm) = run(a0 + eta * d), run(a0 - eta * d)
                 if sp == base and sm == base:
                     break
             else:
-                pytest.fail(f"direction {i}: the contact state changes under every probe step")
+                bad = [t for t in range(T) if sp[t] != base[t] or sm[t] != base[t]]
+                print(f"  direction {i}: the contact state changes at steps {bad} under every probe step", flush=True)
+                continue
             fd = (lp - lm) / (2 * eta)
             print(f"  direction {i}: adjoint {ad:.6e}, central difference {fd:.6e} (step {eta} Pa)", flush=True)
             assert abs(ad - fd) <= 1e-5 * abs(fd)
+            checked += 1
+            if checked == 3:
+                break
+    assert checked == 3
