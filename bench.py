@@ -57,6 +57,7 @@ CSRC = os.path.join(ROOT, "paper_2603_16478_amd", "csrc")
 # per kernel, each tagged with a hash of the source it was measured on
 COUNTERS = {"s_product": os.path.join(ROOT, "profiles", "s_product_batched_beam_counters.json"),
             "gj_wide": os.path.join(ROOT, "profiles", "gj_wide_slab_counters.json"),
+            "lu_tiles": os.path.join(ROOT, "profiles", "lu_tiles_slab_counters.json"),
             "gj_step": os.path.join(ROOT, "profiles", "gj_step_batched_beam_counters.json"),
             "s_product_single": os.path.join(ROOT, "profiles", "s_product_slab_counters.json")}
 
@@ -82,6 +83,12 @@ def s_product_bytes(info):
     sides): values and column indices of S, row pointers, x and y."""
     nv, nnzS = info["n_verts"], info["nnz_S"]
     return nnzS * (8 + 4) + (nv + 1) * 8 + 2 * 3 * nv * 8
+
+
+def sweep_bytes(info):
+    """Algorithmic bytes of one sweep with the Cholesky factor (3 right-hand
+    sides): values and row indices of L, x and y."""
+    return info["nnz_L"] * (8 + 4) + 2 * 3 * info["n_verts"] * 8
 
 
 def bsr_bytes(info):
@@ -111,6 +118,8 @@ def _function_text(src, name):
 
 GJ_FUNCTIONS = ("readlane_d", "rcp_newton", "max_dpp", "gj_rows_step", "invert32_rows", "gj_tile", "gj_next_pivot",
                 "kb_gj_step_mfma")
+LU_MIN = 4608  # padded capacitance size from which the library factors by block LU (default tuning)
+LUT_FUNCTIONS = ("readlane_d", "rcp_newton", "max_dpp", "gj_rows_step", "invert32_rows", "invert128_lds", "k_lu_tiles")
 GJW_FUNCTIONS = ("readlane_d", "rcp_newton", "max_dpp", "gj_rows_step", "invert32_rows", "k_gjw_pivot", "k_gjw_panel",
                  "k_gjw_tiles")
 
@@ -123,6 +132,10 @@ def kernel_source_hash(kernel):
     elif kernel == "s_product_single":
         text = (_function_text(open(os.path.join(CSRC, "kernels_krylov.hip")).read(), "k_spmv_tasks") +
                 _function_text(open(os.path.join(CSRC, "device_common.h")).read(), "row_dot3"))
+    elif kernel == "lu_tiles":
+        src = open(os.path.join(CSRC, "kernels_dense.hip")).read()
+        m = re.search(r"union GjwShared \{.*?\n\};", src, re.S)
+        text = "".join(_function_text(src, f) for f in LUT_FUNCTIONS) + (m.group(0) if m else src)
     elif kernel == "gj_wide":
         src = open(os.path.join(CSRC, "kernels_dense.hip")).read()
         text = "".join(_function_text(src, f) for f in GJW_FUNCTIONS)
@@ -431,8 +444,10 @@ def slab_headline(args):
     # live per-class kernel times, FP64, warm (the Delassus product on cold solves)
     nprof = 2
     prof = {}
+    mp = ((m_rows + 127) // 128) * 128
+    lu = mp >= LU_MIN
     for cls in ("gj", "S", "ST", "correction", "capinv", "bsr", "tet", "assemble", "gs_pass1", "gs_pass2",
-                "delassus"):
+                "delassus") + (("lu_tiles",) if lu else ()):
         o = opts(native.ADJ_FP64, 0 if cls == "delassus" else 1)
         solve(o)
         torch.cuda.synchronize()
@@ -443,34 +458,64 @@ def slab_headline(args):
         prof[cls] = {"ms_per_solve": ms / nprof, "regions": nl, "avg_us": 1e3 * ms / max(nl, 1)}
     scene.close()
     torch.cuda.synchronize()
-    mp = ((m_rows + 127) // 128) * 128
     nv, nt, nnzb, ncv = info["n_verts"], info["n_tets"], info["nnz_blocks"], int(np.unique(d["vid"]).size)
-    # capacitance inversion: algorithmic work 2/3 m^3 (an LU of the m x m
-    # capacitance; Gauss-Jordan's explicit inverse executes 2 mp^3)
+    # capacitance factorisation: algorithmic work 2/3 m^3 (an LU of the m x m
+    # capacitance), the unit of the whole-factorisation figure
     gj = prof["gj"]
     gj_alg = 2.0 / 3.0 * m_rows ** 3
     gj_ach = gj_alg / (gj["avg_us"] * 1e-6) / 1e12
-    roof_gj = {"kernel": "capacitance inverse (wide Gauss-Jordan: k_gjw_pivot + k_gjw_panel + k_gjw_tiles per "
-                         "128-column step), one region per adjoint setup",
-               "bound": "mfma", "achieved": gj_ach, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-               "frac": gj_ach / FP64_PEAK_TFLOPS, "traffic": measured_traffic("gj_wide"),
-               "algorithmic_flops_per_launch": gj_alg, "executed_flops_per_launch": 2.0 * mp ** 3,
-               "executed_tflops": 2.0 * mp ** 3 / (gj["avg_us"] * 1e-6) / 1e12,
-               "avg_launch_us": gj["avg_us"], "launches_timed": gj["regions"], "ms_per_solve": gj["ms_per_solve"]}
-    sb = s_product_bytes(info)
+    whole = {"algorithmic_flops": gj_alg, "ms": gj["avg_us"] / 1e3, "tflops": gj_ach,
+             "frac": gj_ach / FP64_PEAK_TFLOPS, "ms_per_solve": gj["ms_per_solve"]}
+    if lu:
+        # the trailing updates, one launch per 128-column step: 2 * 128 * r^2
+        # flops on the r x r trailing matrix (r = mp - 128 (k + 1))
+        tiles = [2.0 * 128 * r * r for r in range(mp - 128, 0, -128)]
+        lt = prof["lu_tiles"]
+        lt_fl = float(np.mean(tiles))
+        lt_ach = lt_fl / (lt["avg_us"] * 1e-6) / 1e12
+        roof_gj = {"kernel": "trailing update of the block-LU capacitance factorisation (k_lu_tiles: A_ij -= L_iK "
+                             "A_Kj on the 128 x 128 tiles below and right of the pivot block, rank 128 on FP64 "
+                             "matrix cores), one launch per 128-column step",
+                   "bound": "mfma", "achieved": lt_ach, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                   "frac": lt_ach / FP64_PEAK_TFLOPS, "traffic": measured_traffic("lu_tiles"),
+                   "algorithmic_flops_per_launch": lt_fl, "avg_launch_us": lt["avg_us"],
+                   "launches_timed": lt["regions"], "ms_per_solve": lt["ms_per_solve"],
+                   "factorisation": whole | {"kernels": "k_gjw_pivot, then per step k_lu_colpanel, k_lu_tiles, "
+                                                        "k_lu_rowpanel"}}
+    else:
+        roof_gj = {"kernel": "capacitance inverse (wide Gauss-Jordan: k_gjw_pivot + k_gjw_panel + k_gjw_tiles "
+                             "per 128-column step), one region per adjoint setup",
+                   "bound": "mfma", "achieved": gj_ach, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                   "frac": gj_ach / FP64_PEAK_TFLOPS, "traffic": measured_traffic("gj_wide"),
+                   "algorithmic_flops_per_launch": gj_alg, "executed_flops_per_launch": 2.0 * mp ** 3,
+                   "avg_launch_us": gj["avg_us"], "launches_timed": gj["regions"], "ms_per_solve": gj["ms_per_solve"]}
+    # A^{-1} in the preconditioner: level-scheduled sweeps with L where S is
+    # large (the library's automatic choice), else the S products
+    sweeps = info["nnz_S"] >= 32_000_000 and info["nnz_S"] >= 4 * info["nnz_L"]
+    sb = sweep_bytes(info) if sweeps else s_product_bytes(info)
     sp_ms = prof["S"]["ms_per_solve"] + prof["ST"]["ms_per_solve"]
-    sp_avg = 1e3 * (prof["S"]["ms_per_solve"] + prof["ST"]["ms_per_solve"]) * nprof / max(
-        prof["S"]["regions"] + prof["ST"]["regions"], 1)
+    sp_avg = 1e3 * sp_ms * nprof / max(prof["S"]["regions"] + prof["ST"]["regions"], 1)
     sp_ach = sb / (sp_avg * 1e-6) / 1e9
-    roof_s = {"kernel": "sparse-inverse products S x and S^T x (k_spmv_tasks), one of each per preconditioner "
-                        "apply", "bound": "hbm", "achieved": sp_ach, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-              "frac": sp_ach / HBM_PEAK_GBPS, "traffic": measured_traffic("s_product_single"),
+    roof_s = {"kernel": ("level-scheduled supernodal sweeps with the Cholesky factor (L^{-1} P x and its "
+                         "transpose, k_spmv_tasks per level), one of each per preconditioner apply" if sweeps else
+                         "sparse-inverse products S x and S^T x (k_spmv_tasks), one of each per preconditioner "
+                         "apply"),
+              "bound": "hbm", "achieved": sp_ach, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+              "frac": sp_ach / HBM_PEAK_GBPS,
+              "traffic": None if sweeps else measured_traffic("s_product_single"),
               "algorithmic_bytes_per_launch": sb, "avg_launch_us": sp_avg,
               "launches_timed": prof["S"]["regions"] + prof["ST"]["regions"], "ms_per_solve": sp_ms}
-    if roof_gj["ms_per_solve"] >= roof_s["ms_per_solve"]:
-        roofline, roofline_other = roof_gj, roof_s
-    else:
-        roofline, roofline_other = roof_s, roof_gj
+    # capacitance solve per apply: the factors (or the inverse) read once
+    cs_b = mp * mp * 8 + (mp * 128 * 8 if lu else 0)
+    ci = prof["capinv"]
+    ci_ach = cs_b / (ci["avg_us"] * 1e-6) / 1e9
+    roof_c = {"kernel": ("block-LU substitutions (k_wb_hq, k_lu_sweep per block column, k_lu_diag)" if lu else
+                         "capacitance-inverse product (k_wb_gather)") + ", one per preconditioner apply",
+              "bound": "hbm", "achieved": ci_ach, "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": ci_ach / HBM_PEAK_GBPS,
+              "traffic": None, "algorithmic_bytes_per_launch": cs_b, "avg_launch_us": ci["avg_us"],
+              "launches_timed": ci["regions"], "ms_per_solve": ci["ms_per_solve"]}
+    ranked = sorted((roof_gj, roof_s, roof_c), key=lambda r: -r["ms_per_solve"])
+    roofline, roofline_other = ranked[0], ranked[1:]
     mvb = bsr_bytes(info)
     mv = prof["bsr"]
     tet_bytes = nt * (16 + 14 * 8) + nnzb * 9 * 8

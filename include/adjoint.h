@@ -297,8 +297,13 @@ adj_status adj_check_status(adj_scene* scene, void* stream);
  * [nnz_blocks][3][3] row-major; 1: block row pointer [n_verts+1] int32;
  * 2: block column indices [nnz_blocks] int32; 3: inverse of the Woodbury
  * capacitance [mp][mp] (m rows padded with identity to mp, a multiple of
- * 64); 4: Delassus matrix of the contact vertices
- * [n_cv][n_cv]; 5: per-contact rotated bases Q = R frame [n_contacts][3][3].
+ * 64), or, when the capacitance took the block LU (tuning lu_min), its
+ * factors in place of C: strictly lower 128 x 128 blocks L_iK (unit lower
+ * factor), strictly upper blocks V_Kj = U_KK^{-1} U_Kj, diagonal blocks
+ * unused; 4: Delassus matrix of the contact vertices [n_cv][n_cv];
+ * 5: per-contact rotated bases Q = R frame [n_contacts][3][3]; 6: the
+ * inverted diagonal blocks U_KK^{-1} of the block LU [mp/128][128][128]
+ * (size 0 when the explicit inverse is in use).
  * *size_bytes receives the array size; nothing is copied when capacity_bytes
  * is smaller (ADJ_E_SHAPE).  For tests and debugging. */
 adj_status adj_debug_export(const adj_scene* scene, int32_t what, void* host_out, int64_t capacity_bytes,
@@ -320,14 +325,17 @@ adj_status adj_binding_vjp(adj_scene* scene, const double* z, const double* q, c
  * every launch of that kernel made by this scene's calls is bracketed by HIP
  * events on the stream it is launched on; adj_profile_end synchronises and
  * returns the summed kernel time (ms) and the launch count, then disarms.
- * kernel: 0 = S product, 1 = S^T product, 2 = capacitance-inverse product,
+ * kernel: 0 = S product (or the forward L sweeps), 1 = S^T product (or the
+ * transposed sweeps), 2 = capacitance solve (inverse product, or the
+ * block-LU substitutions),
  * 3 = Woodbury correction (Z product, or without Z the scatter and Y
  * product), 4 = block-sparse Acal^T product (in the Krylov loop fused
  * with the first Gram-Schmidt dots), 5 = per-tet Jacobian blocks, 6 = gather
- * assembly, 7 = the whole capacitance inversion, 8 = second Gram-Schmidt
+ * assembly, 7 = the whole capacitance inversion or factorisation, 8 = second Gram-Schmidt
  * update with the Givens step, 9 = first Gram-Schmidt update, 10 = one
  * narrow Gauss-Jordan block step of the capacitance inversion, 11 = the
- * Delassus product (Y, D = Y^T Y and Z when cached).  At most 65536
+ * Delassus product (Y, D = Y^T Y and Z when cached), 12 = one trailing
+ * update launch of the block-LU capacitance factorisation.  At most 65536
  * bracketed regions are timed per profile (later ones are not). */
 adj_status adj_profile_begin(adj_scene* scene, int32_t kernel);
 adj_status adj_profile_end(adj_scene* scene, double* total_ms, int64_t* launches);
@@ -336,7 +344,7 @@ adj_status adj_profile_end(adj_scene* scene, double* total_ms, int64_t* launches
  * over the GPU and the order of floating-point sums inside reductions (so
  * results are bitwise reproducible for a fixed tuning, and agree across
  * tunings to rounding).  Defaults: gs_rows 64, bsr_lanes 16, chunk 8,
- * graph 0, gj_wide_min 2048, a_inv 0. */
+ * graph 0, gj_wide_min 2048, a_inv 0, lu_min 4608. */
 typedef struct {
   int32_t gs_rows;   /* rows per 256-thread block of the Gram-Schmidt kernels: 64, 128, 256 */
   int32_t bsr_lanes; /* lanes per block row of the Acal^T product: 4, 8, 16, 32 */
@@ -348,6 +356,10 @@ typedef struct {
   int32_t a_inv;     /* A^{-1} in the preconditioner: 1 = the sparse-inverse products S^T S, 2 = level-
                         scheduled sweeps with the Cholesky factor L, 0 = automatic (sweeps when S holds
                         more than 32 million and more than 4 nnz(L) entries) */
+  int32_t lu_min;    /* padded capacitance size (a multiple of 128, >= 128) from which the capacitance
+                        is factored by block LU (2/3 mp^3 on the matrix cores; each apply two block
+                        substitutions) instead of inverted explicitly (2 mp^3; each apply one dense
+                        product); default 4608 */
 } adj_tuning;
 
 /* Set or read the scene's launch shapes.  ADJ_E_ARG on a value outside the

@@ -73,6 +73,8 @@ void launch_bsr_spmv(hipStream_t, int, int, const int*, const int*, const float*
 void launch_to_f32(hipStream_t, long long, const double*, float*);
 void launch_wb_gather(hipStream_t, int, int, const int*, const int*, const int*, const double*,
                       const double*, const double*, const GmresState*, double*);
+void launch_wb_lu(hipStream_t, int, int, const int*, const int*, const int*, const double*, const double*,
+                  const double*, const double*, const GmresState*, double*);
 void launch_wb_correct(hipStream_t, int, int, const int*, const int*, const int*, const double*,
                        const double*, const double*, double, const double*, const GmresState*, double*);
 void launch_bsr_spmv(hipStream_t, int, int, const int*, const int*, const double*, const double*, double*,
@@ -86,6 +88,10 @@ void launch_bsr_dots(hipStream_t, int, int, const int*, const int*, const float*
                      double*, long long, const GmresState*, int, double*);
 void launch_fold_partials(hipStream_t, double*, int, const GmresState*, int);
 double* launch_gj_wide(hipStream_t, int, double*, double*, double*, double*, int*);
+void launch_lu_pivot0(hipStream_t, int, double*, double*, int*);
+void launch_lu_colpanel(hipStream_t, int, int, double*, const double*);
+void launch_lu_tiles(hipStream_t, int, int, double*, double*, int*);
+void launch_lu_rowpanel(hipStream_t, int, int, double*, const double*);
 size_t gj_wide_lds_bytes();
 void launch_spmv_tasks_acc(hipStream_t, int, const int4*, const long long*, const int*, const double*,
                            const double*, double, const GmresState*, double*);
@@ -166,7 +172,7 @@ hipError_t upload(T** p, const std::vector<T>& v) {
 
 struct adj_scene {
   HostScene hs;
-  adj_tuning tune{64, 16, 8, 0, 2048, 0};
+  adj_tuning tune{64, 16, 8, 0, 2048, 0, 4608};
   int nv = 0, nt = 0, nnzb = 0, max_contacts = 0;
   int material = 0;  // adj_material of the local projection
   int nb = 0;  // bilateral bindings: vertex ids and compliances on the device
@@ -204,6 +210,11 @@ struct adj_scene {
   // tune.gj_wide_min up): its pivot block and panel scratch
   double *d_gjw_P = nullptr, *d_gjw_W = nullptr;
   size_t cap_gjw_W = 0;
+  // block LU (from the padded size tune.lu_min up): the inverted pivot
+  // blocks; with cap_lu set, d_X holds the factors instead of the inverse
+  double* d_lu_P = nullptr;
+  size_t cap_lu_P = 0;
+  bool cap_lu = false;
   int4* d_gj_tiles = nullptr;
   int* d_gj_one = nullptr;        // [0] = scene 0, [1] = padded size
   long long* d_gj_xoff = nullptr;
@@ -348,7 +359,7 @@ static void free_scene(adj_scene* s) {
                   s->d_rhs,      s->d_cvec,   s->d_cu,    s->d_norms,       s->d_Sx32,
                   s->d_STx32,    s->d_val32,  s->d_Pws,   s->d_x_pcg, s->d_bvid, s->d_bE,
                   s->d_Yp,       s->d_Ysrc,   s->d_Ycol,  s->d_Ytasks,      s->d_CTtasks, s->d_Yval,
-                  s->d_gjw_P,    s->d_gjw_W,
+                  s->d_gjw_P,    s->d_gjw_W,  s->d_lu_P,
                   s->d_Fp, s->d_Bp, s->d_Ip, s->d_ITp, s->d_Fj, s->d_Bj, s->d_Ij, s->d_ITj, s->d_perm,
                   s->d_Fx, s->d_Bx, s->d_Ix, s->d_ITx, s->d_lt, s->d_lz, s->d_Fx32, s->d_Bx32, s->d_Ix32, s->d_ITx32,
                   s->d_fA, s->d_fB, s->d_bA, s->d_bB, s->d_ybm};
@@ -505,7 +516,7 @@ static adj_status scene_create(const adj_scene_desc* desc, int32_t max_contacts,
   ok &= dalloc(&s->d_c_nrow, mc) == hipSuccess;
   ok &= dalloc(&s->d_cv, mc) == hipSuccess;
   ok &= dalloc(&s->d_cv_ptr, mc + 1) == hipSuccess;
-  ok &= dalloc(&s->d_tvec, 3 * mc) == hipSuccess;
+  ok &= dalloc(&s->d_tvec, (3 * mc + 127) / 128 * 128) == hipSuccess;  // padded: block-LU substitutions
   ok &= dalloc(&s->d_P, 32 * 32) == hipSuccess;
   ok &= dalloc(&s->d_Vt, (R + 1) * (size_t)s->n3) == hipSuccess;
   ok &= dalloc(&s->d_scale, R + 2) == hipSuccess;
@@ -792,9 +803,12 @@ static adj_status build_capacitance(adj_scene* s, hipStream_t st, double mu, int
   if (m > 3 * kMaxContacts) return fail(ADJ_E_SHAPE, "more than 10000 contacts in one capacitance");
   // narrow Gauss-Jordan tiles are 64 x 64, the wide steps 128 columns
   const int mpw = ((m + 127) / 128) * 128;
-  const bool wide = mpw >= s->tune.gj_wide_min && s->lds_max >= gj_wide_lds_bytes();
+  const bool big_lds = s->lds_max >= gj_wide_lds_bytes();
+  const bool lu = mpw >= s->tune.lu_min && big_lds;
+  const bool wide = lu || (mpw >= s->tune.gj_wide_min && big_lds);
   const int mp = wide ? mpw : ((m + 63) / 64) * 64;
   s->mp = mp;
+  s->cap_lu = lu;
   size_t capC = s->cap_m * s->cap_m, capB = capC;
   if ((size_t)mp > s->cap_m) capC = capB = 0;
   adj_status a;
@@ -803,6 +817,24 @@ static adj_status build_capacitance(adj_scene* s, hipStream_t st, double mu, int
   s->cap_m = std::max(s->cap_m, (size_t)mp);
   launch_capacitance(st, m, mp, s->d_row_c, s->d_row_i, s->d_cmap, s->ncv, s->d_D, s->d_Q, s->d_kh, mu, h2,
                      transpose, s->d_C);
+  if (lu) {
+    if ((a = grow(&s->d_lu_P, &s->cap_lu_P, (size_t)mp * 128)) != ADJ_OK) return a;
+    ProfScope p(s, 7, st);
+    launch_gj_pad(st, m, mp, s->d_C);
+    launch_lu_pivot0(st, mp, s->d_C, s->d_lu_P, s->d_err);
+    for (int k = 0; k + 1 < mp / 128; ++k) {
+      launch_lu_colpanel(st, mp, k, s->d_C, s->d_lu_P);
+      {
+        ProfScope pk(s, 12, st);
+        launch_lu_tiles(st, mp, k, s->d_C, s->d_lu_P, s->d_err);
+      }
+      launch_lu_rowpanel(st, mp, k, s->d_C, s->d_lu_P);
+    }
+    s->d_X = s->d_C;
+    // the substitutions run over all mp rows: the padding rows of t stay zero
+    launch_fill_zero(st, (size_t)(mp - m), s->d_tvec + m);
+    return ADJ_OK;
+  }
   if (wide) {
     size_t capP = s->d_gjw_P ? (size_t)128 * 128 : 0;
     if ((a = grow(&s->d_gjw_P, &capP, (size_t)128 * 128)) != ADJ_OK) return a;
@@ -942,6 +974,15 @@ extern "C" adj_status adj_check_status(adj_scene* s, void* stream) {
 // f32: S and S^T are read from their FP32 copies (vectors, X and Z stay FP64).
 // A_s^{-1} = S^T S with S = L^{-1} P, applied either as the two sparse-inverse
 // products or as two level-scheduled sweeps with L (s->use_sweeps).
+// t = X Hq u: the capacitance solve of the Woodbury correction, with the
+// explicit inverse X or with the block-LU factors (cap_lu).
+static void cap_apply(adj_scene* s, hipStream_t st, const double* u, const GmresState* state, double* t) {
+  if (s->cap_lu)
+    launch_wb_lu(st, s->m, s->mp, s->d_row_c, s->d_row_i, s->cur_vid, s->d_Q, s->d_X, s->d_lu_P, u, state, t);
+  else
+    launch_wb_gather(st, s->m, s->mp, s->d_row_c, s->d_row_i, s->cur_vid, s->d_Q, s->d_X, u, state, t);
+}
+
 // s_forward: y = S x (x vertex-indexed, the current basis vector scaled when
 // state and scale are given; y in elimination order).
 static void s_forward(adj_scene* s, hipStream_t st, const double* x, long long stride, const double* scale,
@@ -1047,8 +1088,7 @@ static void apply_precond(adj_scene* s, hipStream_t st, const double* x, long lo
                       state, s->d_u);
     {
       ProfScope p(s, 2, st);
-      launch_wb_gather(st, s->m, s->mp, s->d_row_c, s->d_row_i, s->cur_vid, s->d_Q, s->d_X, s->d_u, state,
-                       s->d_tvec);
+      cap_apply(s, st, s->d_u, state, s->d_tvec);
     }
     ProfScope p(s, 3, st);
     launch_fill_zero(st, (size_t)s->n3, s->d_wz);
@@ -1072,8 +1112,7 @@ static void apply_precond(adj_scene* s, hipStream_t st, const double* x, long lo
   if (!woodbury) return;
   {
     ProfScope p(s, 2, st);
-    launch_wb_gather(st, s->m, s->mp, s->d_row_c, s->d_row_i, s->cur_vid, s->d_Q, s->d_X, s->d_u, state,
-                     s->d_tvec);
+    cap_apply(s, st, s->d_u, state, s->d_tvec);
   }
   ProfScope p(s, 3, st);
   if (s->use_z) {
@@ -1598,7 +1637,8 @@ static bool valid_tuning(const adj_tuning& t) {
   const bool ln = t.bsr_lanes == 4 || t.bsr_lanes == 8 || t.bsr_lanes == 16 || t.bsr_lanes == 32;
   const bool gw = t.gj_wide_min >= 128 && t.gj_wide_min % 128 == 0;
   const bool ai = t.a_inv >= 0 && t.a_inv <= 2;
-  return gs && ln && gw && ai && t.chunk >= 1 && t.chunk <= 64 && (t.graph == 0 || t.graph == 1);
+  const bool lu = t.lu_min >= 128 && t.lu_min % 128 == 0;
+  return gs && ln && gw && ai && lu && t.chunk >= 1 && t.chunk <= 64 && (t.graph == 0 || t.graph == 1);
 }
 
 extern "C" adj_status adj_set_tuning(adj_scene* s, const adj_tuning* t) {
@@ -1682,7 +1722,7 @@ extern "C" adj_status adj_autotune(adj_scene* s, const double* dL_dq, const doub
 }
 
 extern "C" adj_status adj_profile_begin(adj_scene* s, int32_t kernel) {
-  if (!s || kernel < 0 || kernel > 11) return fail(ADJ_E_ARG, "bad profile request");
+  if (!s || kernel < 0 || kernel > 12) return fail(ADJ_E_ARG, "bad profile request");
   s->prof_kernel = kernel;
   s->prof_used = 0;
   return ADJ_OK;
@@ -1716,6 +1756,7 @@ extern "C" adj_status adj_debug_export(const adj_scene* s, int32_t what, void* h
     case 3: src = s->d_X; bytes = (int64_t)s->mp * s->mp * 8; break;
     case 4: src = s->d_D; bytes = (int64_t)s->ncv * s->ncv * 8; break;
     case 5: src = s->d_Q; bytes = 9LL * s->nc * 8; break;
+    case 6: src = s->cap_lu ? s->d_lu_P : nullptr; bytes = s->cap_lu ? (int64_t)s->mp * 128 * 8 : 0; break;
     default: return fail(ADJ_E_ARG, "unknown array");
   }
   *size_bytes = bytes;

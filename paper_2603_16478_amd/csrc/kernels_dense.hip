@@ -881,4 +881,209 @@ double* launch_gj_wide(hipStream_t st, int mp, double* C0, double* C1, double* P
 // LDS one block of the wide Gauss-Jordan pivot kernel needs
 size_t gj_wide_lds_bytes() { return sizeof(GjwShared); }
 
+// Block LU of a large capacitance (mp a multiple of 128), in place and with
+// the same pivoting as the Gauss-Jordan steps (partial pivoting inside each
+// 128 x 128 diagonal block, which C's dominant contact diagonal allows):
+//   C = L U,  L unit block-lower with L_iK = A_iK P_k,  U_KK = A_KK,
+//   U_Kj = A_Kj (j > K),
+// with A the Schur complement at step k and P_k = A_KK^{-1}.  The factors
+// overwrite C as: strictly lower blocks L_iK; strictly upper blocks
+// V_Kj = P_k A_Kj (= U_KK^{-1} U_Kj, so that the backward substitution is
+// unit as well); diagonal blocks unused; P_k stored apart, mp/128 blocks of
+// 128 x 128.  Then C^{-1} g = V^{-1} diag(P) L^{-1} g with V unit
+// block-upper: two block substitutions and one block-diagonal product.
+// Work: the trailing rank-128 updates, 2/3 mp^3, against 2 mp^3 for the
+// explicit inverse.  Per step (K = k0 .. k0 + 127):
+//   k_lu_colpanel  L_iK = A_iK P_k for the rows below K, in place;
+//   k_lu_tiles     A_ij -= L_iK A_Kj for the 128 x 128 tiles below and right
+//                  of K, in place; the first tile is the next pivot block
+//                  and is also inverted (P_{k+1});
+//   k_lu_rowpanel  V_Kj = P_k A_Kj for the columns right of K, in place
+//                  (after the tiles have read A_Kj).
+// P_0 comes from k_gjw_pivot.
+__global__ void __launch_bounds__(256) k_lu_colpanel(int mp, int k0, double* __restrict__ A,
+                                                     const double* __restrict__ P) {
+  __shared__ double As[64][kWKC + 1];
+  __shared__ double Bs[kWKC][kWB + 1];
+  const int r0 = k0 + kWB + blockIdx.x * 64;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, li = lane & 15, lk = lane >> 4;
+  d4 acc[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) acc[q] = d4{0, 0, 0, 0};
+  for (int kc = 0; kc < kWB; kc += kWKC) {
+    for (int e = tid; e < 64 * kWKC; e += 256) {
+      const int r = e / kWKC, c = e % kWKC;
+      As[r][c] = A[(size_t)(r0 + r) * mp + k0 + kc + c];
+    }
+    for (int e = tid; e < kWKC * kWB; e += 256) {
+      const int r = e / kWB, c = e % kWB;
+      Bs[r][c] = P[(size_t)(kc + r) * kWB + c];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k4 = 0; k4 < kWKC; k4 += 4) {
+      const double a = As[16 * w + li][k4 + lk];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Bs[k4 + lk][16 * q + li], acc[q], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  // every block reads all of its rows' panel entries before this point
+#pragma unroll
+  for (int q = 0; q < 8; ++q)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) A[(size_t)(r0 + 16 * w + lk + 4 * e) * mp + k0 + 16 * q + li] = acc[q][e];
+}
+
+__global__ void __launch_bounds__(256) k_lu_rowpanel(int mp, int k0, double* __restrict__ A,
+                                                     const double* __restrict__ P) {
+  __shared__ double Ps[kWB][kWKC + 1];
+  __shared__ double Bs[kWKC][64 + 1];
+  const int j0 = k0 + kWB + blockIdx.x * 64;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, li = lane & 15, lk = lane >> 4;
+  d4 acc[2][4];
+#pragma unroll
+  for (int p = 0; p < 2; ++p)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[p][q] = d4{0, 0, 0, 0};
+  for (int kc = 0; kc < kWB; kc += kWKC) {
+    for (int e = tid; e < kWB * kWKC; e += 256) {
+      const int r = e / kWKC, c = e % kWKC;
+      Ps[r][c] = P[(size_t)r * kWB + kc + c];
+    }
+    for (int e = tid; e < kWKC * 64; e += 256) {
+      const int r = e / 64, c = e % 64;
+      Bs[r][c] = A[(size_t)(k0 + kc + r) * mp + j0 + c];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k4 = 0; k4 < kWKC; k4 += 4) {
+      double av[2], bv[4];
+#pragma unroll
+      for (int p = 0; p < 2; ++p) av[p] = Ps[32 * w + 16 * p + li][k4 + lk];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) bv[q] = Bs[k4 + lk][16 * q + li];
+#pragma unroll
+      for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[p][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[p], bv[q], acc[p][q], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int p = 0; p < 2; ++p)
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        A[(size_t)(k0 + 32 * w + 16 * p + lk + 4 * e) * mp + j0 + 16 * q + li] = acc[p][q][e];
+}
+
+// Tiles of the trailing matrix (rows and columns from k0 + 128), row-major
+// over the tile grid; tile 0 is the next pivot block (blocks start in index
+// order, so its inversion overlaps the other tiles).  Reads the column panel
+// (left of the trailing matrix) and the row panel (above it), neither of
+// which any tile writes.
+__global__ void __launch_bounds__(256, 1) k_lu_tiles(int mp, int k0, double* __restrict__ A,
+                                                     double* __restrict__ Pnext, int* __restrict__ err) {
+  __shared__ GjwShared sh;
+  auto& Ws = sh.t.Ws;
+  auto& Rs = sh.t.Rs;
+  const int base = k0 + kWB;
+  const int nt = (mp - base) / kWB;
+  const int t = blockIdx.x;
+  const int I0 = base + (t / nt) * kWB, J0 = base + (t % nt) * kWB;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, li = lane & 15, lk = lane >> 4;
+  const int wr = 64 * (w >> 1), wc = 64 * (w & 1);
+  double wpre[kWPre], rpre[kWPre];
+  auto load_chunk = [&](int kc) {
+#pragma unroll
+    for (int u = 0; u < kWPre; ++u) {
+      const int e = tid + 256 * u;
+      const int rw = e / kWKC, cw = e % kWKC;
+      wpre[u] = A[(size_t)(I0 + rw) * mp + k0 + kc + cw];
+      const int rr = e / kWB, cr = e % kWB;
+      rpre[u] = A[(size_t)(k0 + kc + rr) * mp + J0 + cr];
+    }
+  };
+  auto store_chunk = [&]() {
+#pragma unroll
+    for (int u = 0; u < kWPre; ++u) {
+      const int e = tid + 256 * u;
+      Ws[e / kWKC][e % kWKC] = wpre[u];
+      Rs[e / kWB][e % kWB] = rpre[u];
+    }
+  };
+  load_chunk(0);
+  d4 acc[4][4];
+#pragma unroll
+  for (int p = 0; p < 4; ++p)
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        acc[p][q][e] = A[(size_t)(I0 + wr + 16 * p + lk + 4 * e) * mp + J0 + wc + 16 * q + li];
+  store_chunk();
+  __syncthreads();
+  for (int kc = 0; kc < kWB; kc += kWKC) {
+    const bool more = kc + kWKC < kWB;
+    if (more) load_chunk(kc + kWKC);
+#pragma unroll
+    for (int k4 = 0; k4 < kWKC; k4 += 4) {
+      double av[4], bv[4];
+#pragma unroll
+      for (int p = 0; p < 4; ++p) av[p] = -Ws[wr + 16 * p + li][k4 + lk];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) bv[q] = Rs[k4 + lk][wc + 16 * q + li];
+#pragma unroll
+      for (int p = 0; p < 4; ++p)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[p][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[p], bv[q], acc[p][q], 0, 0, 0);
+    }
+    __syncthreads();
+    if (more) {
+      store_chunk();
+      __syncthreads();
+    }
+  }
+#pragma unroll
+  for (int p = 0; p < 4; ++p)
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        A[(size_t)(I0 + wr + 16 * p + lk + 4 * e) * mp + J0 + wc + 16 * q + li] = acc[p][q][e];
+  if (t != 0) return;
+  double* M = sh.p.M;
+#pragma unroll
+  for (int p = 0; p < 4; ++p)
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) M[(wr + 16 * p + lk + 4 * e) * kWL + wc + 16 * q + li] = acc[p][q][e];
+  __syncthreads();
+  invert128_lds(M, sh.p.Ps, sh.p.prow, err);
+  for (int e = tid; e < kWB * kWB; e += 256) Pnext[e] = M[(e / kWB) * kWL + e % kWB];
+}
+
+// Pall: mp/128 blocks of 128 x 128 (the inverted pivot blocks P_k).  The
+// factorisation is launch_lu_pivot0, then for k = 0 .. mp/128 - 2 the three
+// launches of step k in this order: launch_lu_colpanel, launch_lu_tiles,
+// launch_lu_rowpanel.
+void launch_lu_pivot0(hipStream_t st, int mp, double* A, double* Pall, int* err) {
+  k_gjw_pivot<<<1, 256, 0, st>>>(mp, 0, A, Pall, err);
+}
+void launch_lu_colpanel(hipStream_t st, int mp, int k, double* A, const double* Pall) {
+  const int k0 = k * kWB;
+  k_lu_colpanel<<<(mp - k0 - kWB) / 64, 256, 0, st>>>(mp, k0, A, Pall + (size_t)k * kWB * kWB);
+}
+void launch_lu_tiles(hipStream_t st, int mp, int k, double* A, double* Pall, int* err) {
+  const int k0 = k * kWB, nt = (mp - k0 - kWB) / kWB;
+  k_lu_tiles<<<nt * nt, 256, 0, st>>>(mp, k0, A, Pall + (size_t)(k + 1) * kWB * kWB, err);
+}
+void launch_lu_rowpanel(hipStream_t st, int mp, int k, double* A, const double* Pall) {
+  const int k0 = k * kWB;
+  k_lu_rowpanel<<<(mp - k0 - kWB) / 64, 256, 0, st>>>(mp, k0, A, Pall + (size_t)k * kWB * kWB);
+}
+
 }  // namespace adj

@@ -737,6 +737,96 @@ static void wb_correct_impl(hipStream_t s, int nv, int ncv, const int* cv_ptr, c
                                                                                         c_row0, c_nrow, Q, t, Z, h2,
                                                                                         u, st, y);
 }
+// t = Hq u (the capacitance right-hand side of the Woodbury correction; the
+// block-LU path solves with the factors afterwards).  One thread per row.
+__global__ void k_wb_hq(int m, const int* __restrict__ row_c, const int* __restrict__ row_i,
+                        const int* __restrict__ vid, const double* __restrict__ Q, const double* __restrict__ u,
+                        const GmresState* __restrict__ st, double* __restrict__ t) {
+  if (gm_inactive(st)) return;
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= m) return;
+  const int c = row_c[r];
+  const double* q = Q + 9 * c + 3 * row_i[r];
+  const int v = vid[c];
+  t[r] = q[0] * u[3 * v] + q[1] * u[3 * v + 1] + q[2] * u[3 * v + 2];
+}
+
+// One block column of the capacitance's block-LU factors against t:
+// t_i -= sum_c F[i][k0 + c] t[k0 + c] for rows rbeg <= i < rend (F row-major,
+// mp columns; the 128 entries of t at K stay untouched).  16 lanes per row,
+// each 8 entries as four 16-byte loads, so that a row's lanes read 256
+// contiguous bytes per load; 16 rows per block.
+__global__ void __launch_bounds__(256) k_lu_sweep(int mp, int k0, int rbeg, int rend, const double* __restrict__ F,
+                                                  const GmresState* __restrict__ st, double* __restrict__ t) {
+  if (gm_inactive(st)) return;
+  __shared__ double tk[128];
+  if (threadIdx.x < 128) tk[threadIdx.x] = t[k0 + threadIdx.x];
+  __syncthreads();
+  const int row = rbeg + blockIdx.x * 16 + (threadIdx.x >> 4);
+  const int l = threadIdx.x & 15;
+  if (row >= rend) return;
+  const double2* f = reinterpret_cast<const double2*>(F + (size_t)row * mp + k0);
+  double2 a[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) a[u] = f[l + 16 * u];
+  double acc = 0.0;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int c = 2 * (l + 16 * u);
+    acc = fma(a[u].x, tk[c], acc);
+    acc = fma(a[u].y, tk[c + 1], acc);
+  }
+  acc = group_sum<16>(acc);
+  if (l == 0) t[row] -= acc;
+}
+
+// t_K = P_k t_K for every 128-block K (P: mp/128 blocks of 128 x 128), one
+// block per K.
+__global__ void __launch_bounds__(256) k_lu_diag(const double* __restrict__ Pall, const GmresState* __restrict__ st,
+                                                 double* __restrict__ t) {
+  if (gm_inactive(st)) return;
+  __shared__ double tk[128];
+  const int k0 = blockIdx.x * 128;
+  if (threadIdx.x < 128) tk[threadIdx.x] = t[k0 + threadIdx.x];
+  __syncthreads();
+  const double* P = Pall + (size_t)blockIdx.x * 128 * 128;
+  const int l = threadIdx.x & 15;
+  for (int r = threadIdx.x >> 4; r < 128; r += 16) {
+    const double2* f = reinterpret_cast<const double2*>(P + (size_t)r * 128);
+    double acc = 0.0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const double2 a = f[l + 16 * u];
+      const int c = 2 * (l + 16 * u);
+      acc = fma(a.x, tk[c], acc);
+      acc = fma(a.y, tk[c + 1], acc);
+    }
+    acc = group_sum<16>(acc);
+    if (l == 0) t[k0 + r] = acc;
+  }
+}
+
+// t = X Hq u with X = C^{-1} held as the block-LU factors F (strictly lower:
+// L, strictly upper: V) and the inverted pivot blocks P: forward
+// substitution with L (unit), t_K = P_k t_K, backward substitution with V
+// (unit).  t has mp entries; rows m .. mp - 1 must hold zeros (C is padded
+// with the identity, so they stay zero).
+void launch_wb_lu(hipStream_t s, int m, int mp, const int* row_c, const int* row_i, const int* vid,
+                  const double* Q, const double* F, const double* P, const double* u, const GmresState* st,
+                  double* t) {
+  k_wb_hq<<<(m + 255) / 256, 256, 0, s>>>(m, row_c, row_i, vid, Q, u, st, t);
+  const int nb = mp / 128;
+  for (int k = 0; k + 1 < nb; ++k) {
+    const int k0 = 128 * k, rbeg = k0 + 128;
+    k_lu_sweep<<<(mp - rbeg + 15) / 16, 256, 0, s>>>(mp, k0, rbeg, mp, F, st, t);
+  }
+  k_lu_diag<<<nb, 256, 0, s>>>(P, st, t);
+  for (int k = nb - 1; k >= 1; --k) {
+    const int k0 = 128 * k;
+    k_lu_sweep<<<(k0 + 15) / 16, 256, 0, s>>>(mp, k0, 0, k0, F, st, t);
+  }
+}
+
 // w[cv_a] = sum over the contacts c at contact vertex a of Q_c^T t_c (H^T t
 // in world coordinates; w is zero elsewhere).  One thread per contact vertex.
 __global__ void k_scatter_ht(int ncv, const int* __restrict__ cv, const int* __restrict__ cv_ptr,

@@ -37,7 +37,7 @@ EXPORTS = ("adj_scene_create", "adj_scene_destroy", "adjoint_setup", "adjoint_so
            "adj_batch_debug_export", "adj_batch_scene", "adj_batch_reverse", "adj_binding_vjp",
            "adj_last_error")
 KERNELS = {"S": 0, "ST": 1, "capinv": 2, "Z": 3, "correction": 3, "bsr": 4, "tet": 5, "assemble": 6, "gj": 7,
-           "gs_pass2": 8, "gs_pass1": 9, "gj_step": 10, "delassus": 11}
+           "gs_pass2": 8, "gs_pass1": 9, "gj_step": 10, "delassus": 11, "lu_tiles": 12}
 
 
 class AdjError(RuntimeError):
@@ -75,7 +75,7 @@ class SolveInfo(C.Structure):
 
 class Tuning(C.Structure):
     _fields_ = [("gs_rows", C.c_int32), ("bsr_lanes", C.c_int32), ("chunk", C.c_int32), ("graph", C.c_int32),
-                ("gj_wide_min", C.c_int32), ("a_inv", C.c_int32)]
+                ("gj_wide_min", C.c_int32), ("a_inv", C.c_int32), ("lu_min", C.c_int32)]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
@@ -258,7 +258,8 @@ def vjp_params_noalloc(scene: Scene, z, dL_dv, dL_dqbar, dL_dvbar, dL_dfext, gra
 
 
 _DEBUG = {0: ("val", np.float64), 1: ("rowptr", np.int32), 2: ("col", np.int32),
-          3: ("capinv", np.float64), 4: ("delassus", np.float64), 5: ("Q", np.float64)}
+          3: ("capinv", np.float64), 4: ("delassus", np.float64), 5: ("Q", np.float64),
+          6: ("lu_pivots", np.float64)}
 
 
 def debug_export(scene: Scene, what: int) -> np.ndarray:
@@ -367,8 +368,8 @@ class ContactBuffers:
         return c
 
 
-def set_tuning(scene: Scene, gs_rows=64, bsr_lanes=16, chunk=8, graph=0, gj_wide_min=2048, a_inv=0):
-    t = Tuning(int(gs_rows), int(bsr_lanes), int(chunk), int(graph), int(gj_wide_min), int(a_inv))
+def set_tuning(scene: Scene, gs_rows=64, bsr_lanes=16, chunk=8, graph=0, gj_wide_min=2048, a_inv=0, lu_min=4608):
+    t = Tuning(int(gs_rows), int(bsr_lanes), int(chunk), int(graph), int(gj_wide_min), int(a_inv), int(lu_min))
     check(load().adj_set_tuning(scene.handle, C.byref(t)))
 
 

@@ -189,7 +189,26 @@ def test_beam_delassus_matches_oracle_inverse(prec, tol):
     assert err <= tol
 
 
-@pytest.mark.parametrize("which", ["tiny", "beam", "tiny-wide", "beam-wide"])
+def _lu_inverse(F, P):
+    """C^{-1} from the block-LU factors: C = L U with L unit block-lower
+    (strictly lower 128-blocks of F), U = blockdiag(U_KK) (I + V) with V the
+    strictly upper blocks of F and P_k = U_KK^{-1}: C^{-1} = (I + V)^{-1}
+    blockdiag(P) L^{-1}."""
+    import scipy.linalg as sla
+    mp = F.shape[0]
+    nb = mp // 128
+    blk = np.arange(mp) // 128
+    lower = blk[:, None] > blk[None, :]
+    upper = blk[:, None] < blk[None, :]
+    L = np.where(lower, F, 0.0) + np.eye(mp)
+    V = np.where(upper, F, 0.0) + np.eye(mp)
+    Pd = sla.block_diag(*[P[k] for k in range(nb)])
+    Linv = sla.solve_triangular(L, np.eye(mp), lower=True, unit_diagonal=True)
+    Vinv = sla.solve_triangular(V, np.eye(mp), lower=False, unit_diagonal=True)
+    return Vinv @ Pd @ Linv
+
+
+@pytest.mark.parametrize("which", ["tiny", "beam", "tiny-wide", "beam-wide", "tiny-lu", "beam-lu"])
 def test_capacitance_inverse_matches_oracle(which):
     """a4: the Gauss-Jordan inverse X of the transposed-system capacitance
     K^{-T} + h^2 H A^{-1} H^T (Sec. 5.4) against the oracle's capacitance:
@@ -197,7 +216,8 @@ def test_capacitance_inverse_matches_oracle(which):
     decoupled on the GPU and dropped by the oracle).  The beam's 891 rows pad
     to 896 (matrix-core step), the tiny cube's to 128.  "-wide": the same with
     the 128-column Gauss-Jordan steps (one step on the tiny cube, seven on
-    the beam)."""
+    the beam).  "-lu": the block-LU factors instead of the inverse, with X
+    formed from them on the host."""
     torch = torch_cuda()
     import scipy.sparse.linalg as spla
     from paper_2603_16478_amd import native
@@ -205,6 +225,7 @@ def test_capacitance_inverse_matches_oracle(which):
     from oracle.woodbury import contact_rows
     from gpu_helpers import contact_tensors
     wide = which.endswith("-wide")
+    lu = which.endswith("-lu")
     which = which.split("-")[0]
     if which == "tiny":
         spec, ro = _tiny(20)
@@ -232,6 +253,8 @@ def test_capacitance_inverse_matches_oracle(which):
     scene = make_scene(spec, max_contacts=rec.contacts.n)
     if wide:
         native.set_tuning(scene, gj_wide_min=128)
+    if lu:
+        native.set_tuning(scene, lu_min=128)
     tens = contact_tensors(rec)
     cs = native.make_contact_state(rec.contacts.n, tens["vid"], tens["fric"], tens["frame"], tens["delta"],
                                    tens["lam"], rec.mu)
@@ -240,8 +263,13 @@ def test_capacitance_inverse_matches_oracle(which):
     native.check_status(scene)
     X = native.debug_export(scene, 3)
     mp = int(round(np.sqrt(X.size)))
-    assert mp % (128 if wide else 64) == 0 and mp >= m
-    X = X.reshape(mp, mp)[np.ix_(keep, keep)]
+    assert mp % (128 if wide or lu else 64) == 0 and mp >= m
+    P = native.debug_export(scene, 6)
+    assert P.size == (mp * 128 if lu else 0)
+    X = X.reshape(mp, mp)
+    if lu:
+        X = _lu_inverse(X, P.reshape(mp // 128, 128, 128))
+    X = X[np.ix_(keep, keep)]
     res = np.abs(X @ Cref - np.eye(len(keep))).max()
     print(f"capacitance {which}: m {m} (kept {len(keep)}), mp {mp}, |X C - I| {res:.2e}, "
           f"cond {np.linalg.cond(Cref):.2e}", flush=True)
