@@ -91,7 +91,7 @@ double* launch_gj_wide(hipStream_t, int, double*, double*, double*, double*, int
 void launch_lu_pivot0(hipStream_t, int, double*, double*, int*);
 void launch_lu_colpanel(hipStream_t, int, int, double*, const double*);
 void launch_lu_tiles(hipStream_t, int, int, double*, double*, int*);
-void launch_lu_rowpanel(hipStream_t, int, int, double*, const double*);
+void launch_lu_rowpanels(hipStream_t, int, double*, const double*);
 size_t gj_wide_lds_bytes();
 void launch_spmv_tasks_acc(hipStream_t, int, const int4*, const long long*, const int*, const double*,
                            const double*, double, const GmresState*, double*);
@@ -828,8 +828,8 @@ static adj_status build_capacitance(adj_scene* s, hipStream_t st, double mu, int
         ProfScope pk(s, 12, st);
         launch_lu_tiles(st, mp, k, s->d_C, s->d_lu_P, s->d_err);
       }
-      launch_lu_rowpanel(st, mp, k, s->d_C, s->d_lu_P);
     }
+    launch_lu_rowpanels(st, mp, s->d_C, s->d_lu_P);
     s->d_X = s->d_C;
     // the substitutions run over all mp rows: the padding rows of t stay zero
     launch_fill_zero(st, (size_t)(mp - m), s->d_tvec + m);
@@ -1135,14 +1135,14 @@ static void bsr(adj_scene* s, hipStream_t st, const double* x, double* outbase, 
 // block-sparse product fused with the first Gram-Schmidt dots, the two
 // Gram-Schmidt updates (classical Gram-Schmidt applied twice) and the
 // one-block Givens step.
-static void gmres_chunk(adj_scene* s, hipStream_t st, bool f32) {
+static void gmres_chunk(adj_scene* s, hipStream_t st, bool f32, int n) {
   const long long n3 = s->n3, stride = n3;
   // above kFoldAt partial blocks the Gram-Schmidt dots are folded once by a
   // separate launch instead of re-added by every block of the next kernel
   constexpr int kFoldAt = 256;
   const int nb1_raw = bsr_blocks(s->nv, s->tune.bsr_lanes), nb2_raw = gm_blocks(n3, s->tune.gs_rows);
   const int nb1 = nb1_raw > kFoldAt ? 1 : nb1_raw, nb2 = nb2_raw > kFoldAt ? 1 : nb2_raw;
-  for (int k = 0; k < s->tune.chunk; ++k) {
+  for (int k = 0; k < n; ++k) {
     apply_precond(s, st, s->d_Vt, stride, s->d_scale, s->d_state, s->d_y, f32);
     {
       ProfScope p(s, 4, st);
@@ -1196,12 +1196,13 @@ static void pcg_chunk(adj_scene* s, hipStream_t st, bool f32) {
 }
 
 // One chunk of Krylov iterations (kind 0 GMRES, 1 PCG) on `st`: launched
-// directly, or (tuning.graph = 1, no live profiling) replayed from a graph
-// captured on the scene's private stream after the last setup.
-static hipError_t run_chunk(adj_scene* s, hipStream_t st, int kind, bool f32) {
+// directly (n GMRES iterations), or (tuning.graph = 1, no live profiling)
+// replayed from a graph of tuning.chunk iterations captured on the scene's
+// private stream after the last setup.
+static hipError_t run_chunk(adj_scene* s, hipStream_t st, int kind, bool f32, int n) {
   if (!s->tune.graph || s->prof_kernel >= 0) {
     if (kind == 0)
-      gmres_chunk(s, st, f32);
+      gmres_chunk(s, st, f32, n);
     else
       pcg_chunk(s, st, f32);
     return hipGetLastError();
@@ -1213,7 +1214,7 @@ static hipError_t run_chunk(adj_scene* s, hipStream_t st, int kind, bool f32) {
       return e;
     if ((e = hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal)) != hipSuccess) return e;
     if (kind == 0)
-      gmres_chunk(s, s->cap_stream, f32);
+      gmres_chunk(s, s->cap_stream, f32, s->tune.chunk);
     else
       pcg_chunk(s, s->cap_stream, f32);
     hipGraph_t g = nullptr;
@@ -1257,15 +1258,35 @@ static adj_status gmres_solve(adj_scene* s, hipStream_t st, const double* b, dou
   int total = 0;
   double relres = (bnorm > 0) ? cur.rnorm / bnorm : 0.0;
   bool converged = !(bnorm > tol);
+  // Iterations per chunk: tuning.chunk at first, then the number the mean
+  // residual reduction per iteration so far predicts to reach tol (at least
+  // one), so that few iterations past convergence are enqueued (each costs
+  // its launches even when the state mask makes its kernels return early).
+  double rate = 0.0;
+  auto predicted = [&](double res) {
+    if (!(rate > 0.0 && rate < 1.0) || !(res > tol)) return s->tune.chunk;
+    const double need = std::ceil(std::log(tol / res) / std::log(rate));
+    return (int)std::max(1.0, std::min((double)s->tune.chunk, need));
+  };
+  double r_cycle = cur.rnorm;
   while (!converged && total < maxit) {
     int done_in_cycle = 0;
+    int n = predicted(r_cycle);
+    double r_prev = r_cycle;
+    int j_prev = 0;
     while (true) {
-      HIPCHK(run_chunk(s, st, 0, f32));
+      HIPCHK(run_chunk(s, st, 0, f32, n));
       HIPCHK(hipGetLastError());
       HIPCHK(hipMemcpyAsync(s->h_state, s->d_state, sizeof(GmresState), hipMemcpyDeviceToHost, st));
       HIPCHK(hipStreamSynchronize(st));
       done_in_cycle = s->h_state->j;
       if (!s->h_state->active || total + done_in_cycle >= maxit) break;
+      const double res = s->h_state->res;
+      if (done_in_cycle > j_prev && res > 0.0 && res < r_prev)
+        rate = std::pow(res / r_prev, 1.0 / (done_in_cycle - j_prev));
+      r_prev = res;
+      j_prev = done_in_cycle;
+      n = predicted(res);
     }
     total += done_in_cycle;
     launch_gm_finish(st, n3, s->d_state, s->d_H, s->d_g, s->d_scale, s->d_Vt, stride, s->d_coef, s->d_xt);
@@ -1280,6 +1301,7 @@ static adj_status gmres_solve(adj_scene* s, hipStream_t st, const double* b, dou
     relres = (bnorm > 0) ? s->h_state->rnorm / bnorm : 0.0;
     if (!std::isfinite(relres)) return fail(ADJ_E_SINGULAR, "non-finite residual in the Krylov solve");
     converged = s->h_state->rnorm <= tol;
+    r_cycle = s->h_state->rnorm;
     if (done_in_cycle == 0 && !converged) break;  // no progress possible
   }
   *iters_out = total;
@@ -1328,7 +1350,7 @@ static adj_status pcg_solve(adj_scene* s, hipStream_t st, const double* b, doubl
     launch_pcg_p(st, n3, z, p, s->d_state, sc);
     int done = 0;
     while (true) {
-      HIPCHK(run_chunk(s, st, 1, f32));
+      HIPCHK(run_chunk(s, st, 1, f32, s->tune.chunk));
       HIPCHK(hipGetLastError());
       HIPCHK(hipMemcpyAsync(s->h_state, s->d_state, sizeof(GmresState), hipMemcpyDeviceToHost, st));
       HIPCHK(hipStreamSynchronize(st));

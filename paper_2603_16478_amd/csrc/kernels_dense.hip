@@ -514,91 +514,77 @@ constexpr int kWKC = 32;        // k-chunk of the staged panels
 
 // In-place inverse of the 128 x 128 block M (LDS, row stride kWL) by one
 // 256-thread block: four Gauss-Jordan sub-steps on its 32 x 32 diagonal
-// blocks.  Ps (32 x 33) and prow (64) are LDS scratch.
-__device__ void invert128_lds(double* __restrict__ M, double (*Ps)[kNB + 1], double* __restrict__ prow,
-                              int* __restrict__ err) {
-  const int tid = threadIdx.x;
-  constexpr int kOut = kWB - kNB;  // rows (columns) outside the sub-step's pivot block
+// blocks (P32 of each from invert32_rows, partial pivoting inside the
+// sub-block); the sub-step's products run on the matrix cores, 16 x 16
+// output tiles spread over the four wavefronts.  Ps (32 x 33) and prow (64)
+// are LDS scratch.  Every sub-step, with O = the 96 indices outside it:
+//   (a) W = M_{O,sb} P32, stored negated in place of M_{O,sb};
+//   (b) M_{O,O} += (-W) M_{sb,O};
+//   (c) M_{sb,O} = P32 M_{sb,O} (from the pivot rows as they were before);
+//   (d) M_{sb,sb} = P32.
+__device__ __forceinline__ void invert128_lds(double* __restrict__ M, double (*Ps)[kNB + 1], double* __restrict__ prow,
+                                              int* __restrict__ err) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, li = lane & 15, lk = lane >> 4;
+#pragma unroll 1
   for (int sb = 0; sb < kWB; sb += kNB) {
     if (tid < 64) invert32_rows(M + sb * kWL + sb, kWL, Ps, prow, err);
     __syncthreads();
-    // (a) What_i = M_{i,sb..} P32 for the rows outside the sub-block, stored
-    // negated in place of M_{i,sb..} (two threads per row, 16 columns each)
-    double a[kNB];
-    const int ia = (tid >> 1) < sb ? (tid >> 1) : (tid >> 1) + kNB;
-    const bool ra = tid < 2 * kOut;
-    if (ra) {
+    // first row (column) of outer 16-tile t: tiles never straddle the sub-block
+    auto outer = [&](int t) { return 16 * t < sb ? 16 * t : 16 * t + kNB; };
+    // (a): 6 x 2 tiles, three per wavefront
+    d4 wa[3];
 #pragma unroll
-      for (int c = 0; c < kNB; ++c) a[c] = M[ia * kWL + sb + c];
+    for (int u = 0; u < 3; ++u) {
+      const int t = 3 * w + u, r0 = outer(t >> 1), c0 = 16 * (t & 1);
+      d4 acc = d4{0, 0, 0, 0};
+#pragma unroll
+      for (int k4 = 0; k4 < kNB; k4 += 4)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(M[(r0 + li) * kWL + sb + k4 + lk], Ps[k4 + lk][c0 + li], acc, 0,
+                                                   0, 0);
+      wa[u] = acc;
     }
     __syncthreads();
-    if (ra) {
-      const int h = (tid & 1) * 16;
 #pragma unroll
-      for (int cc = 0; cc < 16; ++cc) {
-        double v = 0.0;
+    for (int u = 0; u < 3; ++u) {
+      const int t = 3 * w + u, r0 = outer(t >> 1), c0 = 16 * (t & 1);
 #pragma unroll
-        for (int c = 0; c < kNB; ++c) v = fma(a[c], Ps[c][h + cc], v);
-        M[ia * kWL + sb + h + cc] = -v;
-      }
+      for (int e = 0; e < 4; ++e) M[(r0 + lk + 4 * e) * kWL + sb + c0 + li] = -wa[u][e];
     }
     __syncthreads();
-    // (b) M_ij += (-What_i) M_{sb..,j} for i, j outside the sub-block: a 6 x 6
-    // register tile per thread over the 96 x 96 outer part
-    {
-      const int tr = tid >> 4, tc = tid & 15;
-      int ii[6], jj[6];
+    // (b): 6 x 6 tiles, nine per wavefront, in place
+#pragma unroll 1
+    for (int u = 0; u < 9; ++u) {
+      const int t = 9 * w + u, r0 = outer(t / 6), c0 = outer(t % 6);
+      d4 acc;
 #pragma unroll
-      for (int u = 0; u < 6; ++u) {
-        const int x = 6 * tr + u, y = 6 * tc + u;
-        ii[u] = x < sb ? x : x + kNB;
-        jj[u] = y < sb ? y : y + kNB;
-      }
-      double acc[6][6];
+      for (int e = 0; e < 4; ++e) acc[e] = M[(r0 + lk + 4 * e) * kWL + c0 + li];
 #pragma unroll
-      for (int u = 0; u < 6; ++u)
+      for (int k4 = 0; k4 < kNB; k4 += 4)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(M[(r0 + li) * kWL + sb + k4 + lk], M[(sb + k4 + lk) * kWL + c0 + li],
+                                                   acc, 0, 0, 0);
 #pragma unroll
-        for (int v = 0; v < 6; ++v) acc[u][v] = M[ii[u] * kWL + jj[v]];
-      for (int k = 0; k < kNB; ++k) {
-        double wv[6], rv[6];
+      for (int e = 0; e < 4; ++e) M[(r0 + lk + 4 * e) * kWL + c0 + li] = acc[e];
+    }
+    // (c): 2 x 6 tiles, three per wavefront, held until (b) has read the pivot rows
+    d4 ca[3];
 #pragma unroll
-        for (int u = 0; u < 6; ++u) {
-          wv[u] = M[ii[u] * kWL + sb + k];
-          rv[u] = M[(sb + k) * kWL + jj[u]];
-        }
+    for (int u = 0; u < 3; ++u) {
+      const int t = 3 * w + u, r0 = 16 * (t / 6), c0 = outer(t % 6);
+      d4 acc = d4{0, 0, 0, 0};
 #pragma unroll
-        for (int u = 0; u < 6; ++u)
-#pragma unroll
-          for (int v = 0; v < 6; ++v) acc[u][v] = fma(wv[u], rv[v], acc[u][v]);
-      }
-      __syncthreads();
-#pragma unroll
-      for (int u = 0; u < 6; ++u)
-#pragma unroll
-        for (int v = 0; v < 6; ++v) M[ii[u] * kWL + jj[v]] = acc[u][v];
+      for (int k4 = 0; k4 < kNB; k4 += 4)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Ps[r0 + li][k4 + lk], M[(sb + k4 + lk) * kWL + c0 + li], acc, 0, 0,
+                                                   0);
+      ca[u] = acc;
     }
     __syncthreads();
-    // (c) pivot rows outside the sub-block's columns: M_{sb..,j} = P32 M_{sb..,j}
-    // (two threads per column); (d) the sub-block itself becomes P32
-    if (tid < 2 * kOut) {
-      const int y = tid >> 1;
-      const int j = y < sb ? y : y + kNB;
-      double col[kNB];
 #pragma unroll
-      for (int r = 0; r < kNB; ++r) col[r] = M[(sb + r) * kWL + j];
-      __builtin_amdgcn_wave_barrier();  // both threads of the column are in this wavefront
-      const int h = (tid & 1) * 16;
+    for (int u = 0; u < 3; ++u) {
+      const int t = 3 * w + u, r0 = 16 * (t / 6), c0 = outer(t % 6);
 #pragma unroll
-      for (int rr = 0; rr < 16; ++rr) {
-        double v = 0.0;
-#pragma unroll
-        for (int r = 0; r < kNB; ++r) v = fma(Ps[h + rr][r], col[r], v);
-        M[(sb + h + rr) * kWL + j] = v;
-      }
-    } else {
-      for (int e = tid - 2 * kOut; e < kNB * kNB; e += 256 - 2 * kOut)
-        M[(sb + e / kNB) * kWL + sb + e % kNB] = Ps[e / kNB][e % kNB];
+      for (int e = 0; e < 4; ++e) M[(sb + r0 + lk + 4 * e) * kWL + c0 + li] = ca[u][e];
     }
+    for (int e = tid; e < kNB * kNB; e += 256) M[(sb + e / kNB) * kWL + sb + e % kNB] = Ps[e / kNB][e % kNB];
     __syncthreads();
   }
 }
@@ -898,8 +884,9 @@ size_t gj_wide_lds_bytes() { return sizeof(GjwShared); }
 //   k_lu_tiles     A_ij -= L_iK A_Kj for the 128 x 128 tiles below and right
 //                  of K, in place; the first tile is the next pivot block
 //                  and is also inverted (P_{k+1});
-//   k_lu_rowpanel  V_Kj = P_k A_Kj for the columns right of K, in place
-//                  (after the tiles have read A_Kj).
+// and after the last step k_lu_rowpanels: V_Kj = P_k A_Kj for every K and
+// the columns right of it, in place (row panels are not read again once
+// their step's trailing update has run).
 // P_0 comes from k_gjw_pivot.
 __global__ void __launch_bounds__(256) k_lu_colpanel(int mp, int k0, double* __restrict__ A,
                                                      const double* __restrict__ P) {
@@ -907,19 +894,38 @@ __global__ void __launch_bounds__(256) k_lu_colpanel(int mp, int k0, double* __r
   __shared__ double Bs[kWKC][kWB + 1];
   const int r0 = k0 + kWB + blockIdx.x * 64;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, li = lane & 15, lk = lane >> 4;
+  // chunk kc of the panel (64 x 32) and of P (32 x 128), staged through
+  // registers; the next chunk is in flight during the current products
+  double ap[8], bp[16];
+  auto load = [&](int kc) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = tid + 256 * u;
+      ap[u] = A[(size_t)(r0 + (e >> 5)) * mp + k0 + kc + (e & 31)];
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int e = tid + 256 * u;
+      bp[u] = P[(size_t)(kc + (e >> 7)) * kWB + (e & 127)];
+    }
+  };
   d4 acc[8];
 #pragma unroll
   for (int q = 0; q < 8; ++q) acc[q] = d4{0, 0, 0, 0};
+  load(0);
   for (int kc = 0; kc < kWB; kc += kWKC) {
-    for (int e = tid; e < 64 * kWKC; e += 256) {
-      const int r = e / kWKC, c = e % kWKC;
-      As[r][c] = A[(size_t)(r0 + r) * mp + k0 + kc + c];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = tid + 256 * u;
+      As[e >> 5][e & 31] = ap[u];
     }
-    for (int e = tid; e < kWKC * kWB; e += 256) {
-      const int r = e / kWB, c = e % kWB;
-      Bs[r][c] = P[(size_t)(kc + r) * kWB + c];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int e = tid + 256 * u;
+      Bs[e >> 7][e & 127] = bp[u];
     }
     __syncthreads();
+    if (kc + kWKC < kWB) load(kc + kWKC);
 #pragma unroll
     for (int k4 = 0; k4 < kWKC; k4 += 4) {
       const double a = As[16 * w + li][k4 + lk];
@@ -935,27 +941,54 @@ __global__ void __launch_bounds__(256) k_lu_colpanel(int mp, int k0, double* __r
     for (int e = 0; e < 4; ++e) A[(size_t)(r0 + 16 * w + lk + 4 * e) * mp + k0 + 16 * q + li] = acc[q][e];
 }
 
-__global__ void __launch_bounds__(256) k_lu_rowpanel(int mp, int k0, double* __restrict__ A,
-                                                     const double* __restrict__ P) {
+// V_Kj = P_k A_Kj for every step k at once (after the last trailing
+// update: no step reads a row panel again once its own trailing update has
+// run), one block per 128 x 64 column slab right of each diagonal block;
+// block b is slab b - S(k) of step k, S(k) = sum_{i<k} 2 (nb - 1 - i).
+__global__ void __launch_bounds__(256) k_lu_rowpanels(int mp, double* __restrict__ A, const double* __restrict__ Pall) {
   __shared__ double Ps[kWB][kWKC + 1];
   __shared__ double Bs[kWKC][64 + 1];
-  const int j0 = k0 + kWB + blockIdx.x * 64;
+  const int nb = mp / kWB;
+  int k = 0, b = blockIdx.x;
+  while (b >= 2 * (nb - 1 - k)) {
+    b -= 2 * (nb - 1 - k);
+    ++k;
+  }
+  const int k0 = k * kWB, j0 = k0 + kWB + 64 * b;
+  const double* P = Pall + (size_t)k * kWB * kWB;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, li = lane & 15, lk = lane >> 4;
+  double pp[16], ap[8];
+  auto load = [&](int kc) {
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int e = tid + 256 * u;
+      pp[u] = P[(size_t)(e >> 5) * kWB + kc + (e & 31)];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = tid + 256 * u;
+      ap[u] = A[(size_t)(k0 + kc + (e >> 6)) * mp + j0 + (e & 63)];
+    }
+  };
   d4 acc[2][4];
 #pragma unroll
   for (int p = 0; p < 2; ++p)
 #pragma unroll
     for (int q = 0; q < 4; ++q) acc[p][q] = d4{0, 0, 0, 0};
+  load(0);
   for (int kc = 0; kc < kWB; kc += kWKC) {
-    for (int e = tid; e < kWB * kWKC; e += 256) {
-      const int r = e / kWKC, c = e % kWKC;
-      Ps[r][c] = P[(size_t)r * kWB + kc + c];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int e = tid + 256 * u;
+      Ps[e >> 5][e & 31] = pp[u];
     }
-    for (int e = tid; e < kWKC * 64; e += 256) {
-      const int r = e / 64, c = e % 64;
-      Bs[r][c] = A[(size_t)(k0 + kc + r) * mp + j0 + c];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = tid + 256 * u;
+      Bs[e >> 6][e & 63] = ap[u];
     }
     __syncthreads();
+    if (kc + kWKC < kWB) load(kc + kWKC);
 #pragma unroll
     for (int k4 = 0; k4 < kWKC; k4 += 4) {
       double av[2], bv[4];
@@ -970,6 +1003,7 @@ __global__ void __launch_bounds__(256) k_lu_rowpanel(int mp, int k0, double* __r
     }
     __syncthreads();
   }
+  // the block has read all of its slab before this point
 #pragma unroll
   for (int p = 0; p < 2; ++p)
 #pragma unroll
@@ -1067,9 +1101,9 @@ __global__ void __launch_bounds__(256, 1) k_lu_tiles(int mp, int k0, double* __r
 }
 
 // Pall: mp/128 blocks of 128 x 128 (the inverted pivot blocks P_k).  The
-// factorisation is launch_lu_pivot0, then for k = 0 .. mp/128 - 2 the three
-// launches of step k in this order: launch_lu_colpanel, launch_lu_tiles,
-// launch_lu_rowpanel.
+// factorisation is launch_lu_pivot0, then for k = 0 .. mp/128 - 2 the two
+// launches of step k in this order: launch_lu_colpanel, launch_lu_tiles;
+// then launch_lu_rowpanels once.
 void launch_lu_pivot0(hipStream_t st, int mp, double* A, double* Pall, int* err) {
   k_gjw_pivot<<<1, 256, 0, st>>>(mp, 0, A, Pall, err);
 }
@@ -1081,9 +1115,9 @@ void launch_lu_tiles(hipStream_t st, int mp, int k, double* A, double* Pall, int
   const int k0 = k * kWB, nt = (mp - k0 - kWB) / kWB;
   k_lu_tiles<<<nt * nt, 256, 0, st>>>(mp, k0, A, Pall + (size_t)(k + 1) * kWB * kWB, err);
 }
-void launch_lu_rowpanel(hipStream_t st, int mp, int k, double* A, const double* Pall) {
-  const int k0 = k * kWB;
-  k_lu_rowpanel<<<(mp - k0 - kWB) / 64, 256, 0, st>>>(mp, k0, A, Pall + (size_t)k * kWB * kWB);
+void launch_lu_rowpanels(hipStream_t st, int mp, double* A, const double* Pall) {
+  const int nb = mp / kWB;
+  if (nb > 1) k_lu_rowpanels<<<nb * (nb - 1), 256, 0, st>>>(mp, A, Pall);
 }
 
 }  // namespace adj
