@@ -298,9 +298,14 @@ adj_status adj_check_status(adj_scene* scene, void* stream);
  * 2: block column indices [nnz_blocks] int32; 3: inverse of the Woodbury
  * capacitance [mp][mp] (m rows padded with identity to mp, a multiple of
  * 64), or, when the capacitance took the block LU (tuning lu_min), its
- * factors in place of C: strictly lower 128 x 128 blocks L_iK (unit lower
- * factor), strictly upper blocks V_Kj = U_KK^{-1} U_Kj, diagonal blocks
- * unused; 4: Delassus matrix of the contact vertices [n_cv][n_cv];
+ * factors in place of C, C = L D V with L unit block-lower, V unit
+ * block-upper (128 x 128 blocks) and D = diag(U_KK), rewritten for the
+ * grouped substitutions: per group of 4 consecutive diagonal blocks, the
+ * strictly lower and strictly upper blocks inside the group hold the
+ * inverses of the group's unit lower and unit upper parts, the lower blocks
+ * below the group L_iG times the first, the upper blocks above it V_iG times
+ * the second, diagonal blocks unused; 4: Delassus matrix of the contact
+ * vertices [n_cv][n_cv];
  * 5: per-contact rotated bases Q = R frame [n_contacts][3][3]; 6: the
  * inverted diagonal blocks U_KK^{-1} of the block LU [mp/128][128][128]
  * (size 0 when the explicit inverse is in use).

@@ -74,7 +74,9 @@ void launch_to_f32(hipStream_t, long long, const double*, float*);
 void launch_wb_gather(hipStream_t, int, int, const int*, const int*, const int*, const double*,
                       const double*, const double*, const GmresState*, double*);
 void launch_wb_lu(hipStream_t, int, int, const int*, const int*, const int*, const double*, const double*,
-                  const double*, const double*, const GmresState*, double*);
+                  const double*, int, const double*, const GmresState*, double*, double*);
+void launch_lu_groups(hipStream_t, int, double*);
+int lu_group_blocks();
 void launch_wb_correct(hipStream_t, int, int, const int*, const int*, const int*, const double*,
                        const double*, const double*, double, const double*, const GmresState*, double*);
 void launch_bsr_spmv(hipStream_t, int, int, const int*, const int*, const double*, const double*, double*,
@@ -212,8 +214,8 @@ struct adj_scene {
   size_t cap_gjw_W = 0;
   // block LU (from the padded size tune.lu_min up): the inverted pivot
   // blocks; with cap_lu set, d_X holds the factors instead of the inverse
-  double* d_lu_P = nullptr;
-  size_t cap_lu_P = 0;
+  double *d_lu_P = nullptr, *d_lu_y = nullptr;  // pivot inverses; the substitutions' second vector
+  size_t cap_lu_P = 0, cap_lu_y = 0;
   bool cap_lu = false;
   int4* d_gj_tiles = nullptr;
   int* d_gj_one = nullptr;        // [0] = scene 0, [1] = padded size
@@ -359,7 +361,7 @@ static void free_scene(adj_scene* s) {
                   s->d_rhs,      s->d_cvec,   s->d_cu,    s->d_norms,       s->d_Sx32,
                   s->d_STx32,    s->d_val32,  s->d_Pws,   s->d_x_pcg, s->d_bvid, s->d_bE,
                   s->d_Yp,       s->d_Ysrc,   s->d_Ycol,  s->d_Ytasks,      s->d_CTtasks, s->d_Yval,
-                  s->d_gjw_P,    s->d_gjw_W,  s->d_lu_P,
+                  s->d_gjw_P,    s->d_gjw_W,  s->d_lu_P,  s->d_lu_y,
                   s->d_Fp, s->d_Bp, s->d_Ip, s->d_ITp, s->d_Fj, s->d_Bj, s->d_Ij, s->d_ITj, s->d_perm,
                   s->d_Fx, s->d_Bx, s->d_Ix, s->d_ITx, s->d_lt, s->d_lz, s->d_Fx32, s->d_Bx32, s->d_Ix32, s->d_ITx32,
                   s->d_fA, s->d_fB, s->d_bA, s->d_bB, s->d_ybm};
@@ -819,6 +821,7 @@ static adj_status build_capacitance(adj_scene* s, hipStream_t st, double mu, int
                      transpose, s->d_C);
   if (lu) {
     if ((a = grow(&s->d_lu_P, &s->cap_lu_P, (size_t)mp * 128)) != ADJ_OK) return a;
+    if ((a = grow(&s->d_lu_y, &s->cap_lu_y, (size_t)mp)) != ADJ_OK) return a;
     ProfScope p(s, 7, st);
     launch_gj_pad(st, m, mp, s->d_C);
     launch_lu_pivot0(st, mp, s->d_C, s->d_lu_P, s->d_err);
@@ -830,6 +833,7 @@ static adj_status build_capacitance(adj_scene* s, hipStream_t st, double mu, int
       }
     }
     launch_lu_rowpanels(st, mp, s->d_C, s->d_lu_P);
+    launch_lu_groups(st, mp, s->d_C);
     s->d_X = s->d_C;
     // the substitutions run over all mp rows: the padding rows of t stay zero
     launch_fill_zero(st, (size_t)(mp - m), s->d_tvec + m);
@@ -978,7 +982,8 @@ extern "C" adj_status adj_check_status(adj_scene* s, void* stream) {
 // explicit inverse X or with the block-LU factors (cap_lu).
 static void cap_apply(adj_scene* s, hipStream_t st, const double* u, const GmresState* state, double* t) {
   if (s->cap_lu)
-    launch_wb_lu(st, s->m, s->mp, s->d_row_c, s->d_row_i, s->cur_vid, s->d_Q, s->d_X, s->d_lu_P, u, state, t);
+    launch_wb_lu(st, s->m, s->mp, s->d_row_c, s->d_row_i, s->cur_vid, s->d_Q, s->d_X, s->d_lu_P, lu_group_blocks(), u,
+                 state, t, s->d_lu_y);
   else
     launch_wb_gather(st, s->m, s->mp, s->d_row_c, s->d_row_i, s->cur_vid, s->d_Q, s->d_X, u, state, t);
 }

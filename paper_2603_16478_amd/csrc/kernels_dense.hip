@@ -1120,4 +1120,149 @@ void launch_lu_rowpanels(hipStream_t st, int mp, double* A, const double* Pall) 
   if (nb > 1) k_lu_rowpanels<<<nb * (nb - 1), 256, 0, st>>>(mp, A, Pall);
 }
 
+
+// ---- Grouped substitutions ----
+// The substitutions with the block-LU factors take one launch per group of
+// kLuGroup consecutive diagonal blocks instead of one per block: with G a
+// group, L_GG its unit block-lower diagonal part and V_GG its unit
+// block-upper one, the factors are rewritten once after the factorisation:
+//   strictly lower blocks inside G   <- L_GG^{-1}   (unit diagonal implied),
+//   strictly upper blocks inside G   <- V_GG^{-1},
+//   lower blocks left of G, below it <- L_iG L_GG^{-1},
+//   upper blocks right of G, above   <- V_iG V_GG^{-1}.
+// Forward, group by group: y_G = L_GG^{-1} t_G, and t_i -= (L_iG L_GG^{-1})
+// t_G for the rows below, both from the group's t before the launch; the
+// backward pass mirrors it with V.  Extra work at setup: about
+// 2 kLuGroup-1/kLuGroup 128 mp^2 flops; per solve, about a quarter of the
+// launches.
+constexpr int kLuGroup = 4;
+
+struct LuGemmShared {
+  double Ws[kWB][kWKC + 1];
+  double Rs[kWKC][kWB + 1];
+};
+
+// acc (each wavefront's 64 x 64 quadrant of a 128 x 128 block, the
+// k_lu_tiles layout) += Ablk Bblk, both 128 x 128 blocks of a row-major
+// matrix with leading dimension ld, staged through LDS in 32-wide chunks.
+__device__ __forceinline__ void mma128(d4 (&acc)[4][4], const double* __restrict__ Ab, const double* __restrict__ Bb,
+                                       int ld, LuGemmShared& sh) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, li = lane & 15, lk = lane >> 4;
+  const int wr = 64 * (w >> 1), wc = 64 * (w & 1);
+  for (int kc = 0; kc < kWB; kc += kWKC) {
+    double wv[kWPre], rv[kWPre];
+#pragma unroll
+    for (int u = 0; u < kWPre; ++u) {
+      const int e = tid + 256 * u;
+      wv[u] = Ab[(size_t)(e / kWKC) * ld + kc + e % kWKC];
+      rv[u] = Bb[(size_t)(kc + e / kWB) * ld + e % kWB];
+    }
+    __syncthreads();  // the previous chunk's products have read the panels
+#pragma unroll
+    for (int u = 0; u < kWPre; ++u) {
+      const int e = tid + 256 * u;
+      sh.Ws[e / kWKC][e % kWKC] = wv[u];
+      sh.Rs[e / kWB][e % kWB] = rv[u];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k4 = 0; k4 < kWKC; k4 += 4) {
+      double av[4], bv[4];
+#pragma unroll
+      for (int p = 0; p < 4; ++p) av[p] = sh.Ws[wr + 16 * p + li][k4 + lk];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) bv[q] = sh.Rs[k4 + lk][wc + 16 * q + li];
+#pragma unroll
+      for (int p = 0; p < 4; ++p)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[p][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[p], bv[q], acc[p][q], 0, 0, 0);
+    }
+  }
+}
+
+__device__ __forceinline__ void acc_io(d4 (&acc)[4][4], double* __restrict__ Cb, int ld, bool store, double sgn) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, li = lane & 15, lk = lane >> 4;
+  const int wr = 64 * (w >> 1), wc = 64 * (w & 1);
+#pragma unroll
+  for (int p = 0; p < 4; ++p)
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        double* c = Cb + (size_t)(wr + 16 * p + lk + 4 * e) * ld + wc + 16 * q + li;
+        if (store)
+          *c = sgn * acc[p][q][e];
+        else
+          acc[p][q][e] = *c;
+      }
+}
+
+// Blocks written here are read back by other wavefronts of the block: the
+// stores complete device-wide before the barrier, and every wavefront's
+// view of the cache is refreshed after it.
+__device__ __forceinline__ void publish_block() {
+  __threadfence();
+  __syncthreads();
+  __threadfence();
+}
+
+// L_GG^{-1} and V_GG^{-1} of every group in place, one block per group:
+//   Linv_ab = -(L_ab + sum_{b<c<a} L_ac Linv_cb)  (a > b; columns b ascending,
+//             rows a ascending, so L_ac is still the factor),
+//   Vinv_ab = -(V_ab + sum_{a<c<b} V_ac Vinv_cb)  (a < b; columns b
+//             descending, rows a descending).
+__global__ void __launch_bounds__(256) k_lu_group_inv(int mp, double* __restrict__ A) {
+  __shared__ LuGemmShared sh;
+  const int nb = mp / kWB, b0 = blockIdx.x * kLuGroup, g = min(kLuGroup, nb - b0);
+  auto blk = [&](int a, int b) { return A + (size_t)(b0 + a) * kWB * mp + (size_t)(b0 + b) * kWB; };
+  d4 acc[4][4];
+  for (int b = 0; b + 1 < g; ++b)
+    for (int a = b + 1; a < g; ++a) {
+      acc_io(acc, blk(a, b), mp, false, 1.0);
+      for (int c = b + 1; c < a; ++c) mma128(acc, blk(a, c), blk(c, b), mp, sh);
+      acc_io(acc, blk(a, b), mp, true, -1.0);
+      publish_block();
+    }
+  for (int b = g - 1; b >= 1; --b)
+    for (int a = b - 1; a >= 0; --a) {
+      acc_io(acc, blk(a, b), mp, false, 1.0);
+      for (int c = a + 1; c < b; ++c) mma128(acc, blk(a, c), blk(c, b), mp, sh);
+      acc_io(acc, blk(a, b), mp, true, -1.0);
+      publish_block();
+    }
+}
+
+// The blocks outside the groups, one block per (128-row block r, group):
+// below the group (lower) L_rb <- L_rb + sum_{c>b} L_rc Linv_cb, columns b
+// ascending; above it (upper) V_rb <- V_rb + sum_{c<b} V_rc Vinv_cb, columns
+// b descending.  Each output is written once and not read again here.
+__global__ void __launch_bounds__(256) k_lu_group_apply(int mp, double* __restrict__ A) {
+  __shared__ LuGemmShared sh;
+  const int nb = mp / kWB, r = blockIdx.x, b0 = blockIdx.y * kLuGroup, g = min(kLuGroup, nb - b0);
+  auto blk = [&](int i, int j) { return A + (size_t)i * kWB * mp + (size_t)j * kWB; };
+  d4 acc[4][4];
+  if (r >= b0 + g) {
+    for (int b = 0; b + 1 < g; ++b) {
+      acc_io(acc, blk(r, b0 + b), mp, false, 1.0);
+      for (int c = b + 1; c < g; ++c) mma128(acc, blk(r, b0 + c), blk(b0 + c, b0 + b), mp, sh);
+      acc_io(acc, blk(r, b0 + b), mp, true, 1.0);
+    }
+  } else if (r < b0) {
+    for (int b = g - 1; b >= 1; --b) {
+      acc_io(acc, blk(r, b0 + b), mp, false, 1.0);
+      for (int c = 0; c < b; ++c) mma128(acc, blk(r, b0 + c), blk(b0 + c, b0 + b), mp, sh);
+      acc_io(acc, blk(r, b0 + b), mp, true, 1.0);
+    }
+  }
+}
+
+void launch_lu_groups(hipStream_t st, int mp, double* A) {
+  const int nb = mp / kWB, ng = (nb + kLuGroup - 1) / kLuGroup;
+  if (nb < 2) return;
+  k_lu_group_inv<<<ng, 256, 0, st>>>(mp, A);
+  k_lu_group_apply<<<dim3(nb, ng), 256, 0, st>>>(mp, A);
+}
+
+int lu_group_blocks() { return kLuGroup; }
+
 }  // namespace adj

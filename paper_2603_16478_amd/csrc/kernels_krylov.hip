@@ -751,35 +751,6 @@ __global__ void k_wb_hq(int m, const int* __restrict__ row_c, const int* __restr
   t[r] = q[0] * u[3 * v] + q[1] * u[3 * v + 1] + q[2] * u[3 * v + 2];
 }
 
-// One block column of the capacitance's block-LU factors against t:
-// t_i -= sum_c F[i][k0 + c] t[k0 + c] for rows rbeg <= i < rend (F row-major,
-// mp columns; the 128 entries of t at K stay untouched).  16 lanes per row,
-// each 8 entries as four 16-byte loads, so that a row's lanes read 256
-// contiguous bytes per load; 16 rows per block.
-__global__ void __launch_bounds__(256) k_lu_sweep(int mp, int k0, int rbeg, int rend, const double* __restrict__ F,
-                                                  const GmresState* __restrict__ st, double* __restrict__ t) {
-  if (gm_inactive(st)) return;
-  __shared__ double tk[128];
-  if (threadIdx.x < 128) tk[threadIdx.x] = t[k0 + threadIdx.x];
-  __syncthreads();
-  const int row = rbeg + blockIdx.x * 16 + (threadIdx.x >> 4);
-  const int l = threadIdx.x & 15;
-  if (row >= rend) return;
-  const double2* f = reinterpret_cast<const double2*>(F + (size_t)row * mp + k0);
-  double2 a[4];
-#pragma unroll
-  for (int u = 0; u < 4; ++u) a[u] = f[l + 16 * u];
-  double acc = 0.0;
-#pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    const int c = 2 * (l + 16 * u);
-    acc = fma(a[u].x, tk[c], acc);
-    acc = fma(a[u].y, tk[c + 1], acc);
-  }
-  acc = group_sum<16>(acc);
-  if (l == 0) t[row] -= acc;
-}
-
 // t_K = P_k t_K for every 128-block K (P: mp/128 blocks of 128 x 128), one
 // block per K.
 __global__ void __launch_bounds__(256) k_lu_diag(const double* __restrict__ Pall, const GmresState* __restrict__ st,
@@ -806,24 +777,65 @@ __global__ void __launch_bounds__(256) k_lu_diag(const double* __restrict__ Pall
   }
 }
 
-// t = X Hq u with X = C^{-1} held as the block-LU factors F (strictly lower:
-// L, strictly upper: V) and the inverted pivot blocks P: forward
-// substitution with L (unit), t_K = P_k t_K, backward substitution with V
-// (unit).  t has mp entries; rows m .. mp - 1 must hold zeros (C is padded
-// with the identity, so they stay zero).
-void launch_wb_lu(hipStream_t s, int m, int mp, const int* row_c, const int* row_i, const int* vid,
-                  const double* Q, const double* F, const double* P, const double* u, const GmresState* st,
-                  double* t) {
-  k_wb_hq<<<(m + 255) / 256, 256, 0, s>>>(m, row_c, row_i, vid, Q, u, st, t);
-  const int nb = mp / 128;
-  for (int k = 0; k + 1 < nb; ++k) {
-    const int k0 = 128 * k, rbeg = k0 + 128;
-    k_lu_sweep<<<(mp - rbeg + 15) / 16, 256, 0, s>>>(mp, k0, rbeg, mp, F, st, t);
+// One group [c0, c1) of the grouped substitutions (group inverses inside,
+// transformed blocks outside; see the factor kernels): with the group's
+// entries a_G of a (read before the launch changes anything),
+//   rows r of the group:  b_r = a_r + sum_c F[r][c] a_c over the group's
+//                         columns strictly before (fwd) / after (bwd) r's
+//                         128-block;
+//   rows r outside:       a_r -= sum_{c in [c0, c1)} F[r][c] a_c,
+// for rows [c0, mp) (fwd: below and in the group) or [0, c1) (bwd).  No row
+// reads what another row writes.  16 lanes per row, 16 rows per block.
+__global__ void __launch_bounds__(256) k_lu_gsweep(int mp, int c0, int c1, int fwd, const double* __restrict__ F,
+                                                   const GmresState* __restrict__ st, double* __restrict__ a,
+                                                   double* __restrict__ b) {
+  if (gm_inactive(st)) return;
+  __shared__ double ag[512];
+  for (int c = threadIdx.x; c < c1 - c0; c += 256) ag[c] = a[c0 + c];
+  __syncthreads();
+  const int rbeg = fwd ? c0 : 0, rend = fwd ? mp : c1;
+  const int row = rbeg + blockIdx.x * 16 + (threadIdx.x >> 4);
+  const int l = threadIdx.x & 15;
+  if (row >= rend) return;
+  const bool in = row >= c0 && row < c1;
+  const int rb = row & ~127;
+  const int cb = in ? (fwd ? c0 : rb + 128) : c0, ce = in ? (fwd ? rb : c1) : c1;
+  const double2* f = reinterpret_cast<const double2*>(F + (size_t)row * mp);
+  double acc = 0.0;
+  const int n2 = (ce - cb) / 32;  // double2 loads per lane
+#pragma unroll 4
+  for (int u = 0; u < n2; ++u) {
+    const int c = cb + 2 * l + 32 * u;
+    const double2 v = f[c >> 1];
+    acc = fma(v.x, ag[c - c0], acc);
+    acc = fma(v.y, ag[c - c0 + 1], acc);
   }
-  k_lu_diag<<<nb, 256, 0, s>>>(P, st, t);
-  for (int k = nb - 1; k >= 1; --k) {
-    const int k0 = 128 * k;
-    k_lu_sweep<<<(k0 + 15) / 16, 256, 0, s>>>(mp, k0, 0, k0, F, st, t);
+  acc = group_sum<16>(acc);
+  if (l == 0) {
+    if (in)
+      b[row] = a[row] + acc;
+    else
+      a[row] -= acc;
+  }
+}
+
+// t = X Hq u with X = C^{-1} held as the grouped block-LU factors F and the
+// inverted pivot blocks P: forward substitution group by group (t -> y),
+// y_K = P_k y_K, backward substitution (y -> t).  t and y have mp entries;
+// rows m .. mp - 1 of t must hold zeros (C is padded with the identity).
+void launch_wb_lu(hipStream_t s, int m, int mp, const int* row_c, const int* row_i, const int* vid,
+                  const double* Q, const double* F, const double* P, int group, const double* u,
+                  const GmresState* st, double* t, double* y) {
+  k_wb_hq<<<(m + 255) / 256, 256, 0, s>>>(m, row_c, row_i, vid, Q, u, st, t);
+  const int gw = 128 * group, ng = (mp + gw - 1) / gw;
+  for (int G = 0; G < ng; ++G) {
+    const int c0 = G * gw, c1 = c0 + gw < mp ? c0 + gw : mp;
+    k_lu_gsweep<<<(mp - c0 + 15) / 16, 256, 0, s>>>(mp, c0, c1, 1, F, st, t, y);
+  }
+  k_lu_diag<<<mp / 128, 256, 0, s>>>(P, st, y);
+  for (int G = ng - 1; G >= 0; --G) {
+    const int c0 = G * gw, c1 = c0 + gw < mp ? c0 + gw : mp;
+    k_lu_gsweep<<<(c1 + 15) / 16, 256, 0, s>>>(mp, c0, c1, 0, F, st, y, t);
   }
 }
 

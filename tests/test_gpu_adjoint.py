@@ -189,23 +189,37 @@ def test_beam_delassus_matches_oracle_inverse(prec, tol):
     assert err <= tol
 
 
-def _lu_inverse(F, P):
-    """C^{-1} from the block-LU factors: C = L U with L unit block-lower
-    (strictly lower 128-blocks of F), U = blockdiag(U_KK) (I + V) with V the
-    strictly upper blocks of F and P_k = U_KK^{-1}: C^{-1} = (I + V)^{-1}
-    blockdiag(P) L^{-1}."""
-    import scipy.linalg as sla
+def _lu_inverse(F, P, group=4):
+    """C^{-1} from the exported block-LU factors, by the substitutions
+    applied to the identity's columns (numpy).  The factor matrix holds, per
+    group of `group` diagonal 128-blocks, the inverses of the group's unit
+    lower and unit upper parts inside the group (unit diagonals implied) and
+    the blocks outside multiplied by them; P_k are the inverted pivot blocks.
+    Forward, group by group: y_G = Linv_G t_G, t_below -= F_below,G t_G;
+    then y_K = P_k y_K; backward: x_G = Vinv_G y_G, y_above -= F_above,G y_G."""
     mp = F.shape[0]
     nb = mp // 128
+    gw = 128 * group
+    t = np.eye(mp)
+    y = np.zeros((mp, mp))
     blk = np.arange(mp) // 128
-    lower = blk[:, None] > blk[None, :]
-    upper = blk[:, None] < blk[None, :]
-    L = np.where(lower, F, 0.0) + np.eye(mp)
-    V = np.where(upper, F, 0.0) + np.eye(mp)
-    Pd = sla.block_diag(*[P[k] for k in range(nb)])
-    Linv = sla.solve_triangular(L, np.eye(mp), lower=True, unit_diagonal=True)
-    Vinv = sla.solve_triangular(V, np.eye(mp), lower=False, unit_diagonal=True)
-    return Vinv @ Pd @ Linv
+    for c0 in range(0, mp, gw):
+        c1 = min(mp, c0 + gw)
+        G = slice(c0, c1)
+        low = np.where(blk[G][:, None] > blk[G][None, :], F[G, G], 0.0)
+        tg = t[G].copy()
+        y[G] = tg + low @ tg
+        t[c1:] -= F[c1:, G] @ tg
+    for k in range(nb):
+        y[128 * k:128 * (k + 1)] = P[k] @ y[128 * k:128 * (k + 1)]
+    for c0 in reversed(range(0, mp, gw)):
+        c1 = min(mp, c0 + gw)
+        G = slice(c0, c1)
+        up = np.where(blk[G][:, None] < blk[G][None, :], F[G, G], 0.0)
+        yg = y[G].copy()
+        t[G] = yg + up @ yg
+        y[:c0] -= F[:c0, G] @ yg
+    return t
 
 
 @pytest.mark.parametrize("which", ["tiny", "beam", "tiny-wide", "beam-wide", "tiny-lu", "beam-lu"])
@@ -217,7 +231,7 @@ def test_capacitance_inverse_matches_oracle(which):
     to 896 (matrix-core step), the tiny cube's to 128.  "-wide": the same with
     the 128-column Gauss-Jordan steps (one step on the tiny cube, seven on
     the beam).  "-lu": the block-LU factors instead of the inverse, with X
-    formed from them on the host."""
+    formed from them on the host by the same grouped substitutions."""
     torch = torch_cuda()
     import scipy.sparse.linalg as spla
     from paper_2603_16478_amd import native
