@@ -119,7 +119,7 @@ def _function_text(src, name):
 GJ_FUNCTIONS = ("readlane_d", "rcp_newton", "max_dpp", "gj_rows_step", "invert32_rows", "gj_tile", "gj_next_pivot",
                 "kb_gj_step_mfma")
 LU_MIN = 4608  # padded capacitance size from which the library factors by block LU (default tuning)
-LUT_FUNCTIONS = ("readlane_d", "rcp_newton", "max_dpp", "gj_rows_step", "invert32_rows", "invert128_lds", "k_lu_tiles")
+LUT_FUNCTIONS = ("lu_tile", "k_lu_tiles_rest")
 GJW_FUNCTIONS = ("readlane_d", "rcp_newton", "max_dpp", "gj_rows_step", "invert32_rows", "k_gjw_pivot", "k_gjw_panel",
                  "k_gjw_tiles")
 
@@ -134,8 +134,7 @@ def kernel_source_hash(kernel):
                 _function_text(open(os.path.join(CSRC, "device_common.h")).read(), "row_dot3"))
     elif kernel == "lu_tiles":
         src = open(os.path.join(CSRC, "kernels_dense.hip")).read()
-        m = re.search(r"union GjwShared \{.*?\n\};", src, re.S)
-        text = "".join(_function_text(src, f) for f in LUT_FUNCTIONS) + (m.group(0) if m else src)
+        text = "".join(_function_text(src, f) for f in LUT_FUNCTIONS)
     elif kernel == "gj_wide":
         src = open(os.path.join(CSRC, "kernels_dense.hip")).read()
         text = "".join(_function_text(src, f) for f in GJW_FUNCTIONS)
@@ -467,21 +466,25 @@ def slab_headline(args):
     whole = {"algorithmic_flops": gj_alg, "ms": gj["avg_us"] / 1e3, "tflops": gj_ach,
              "frac": gj_ach / FP64_PEAK_TFLOPS, "ms_per_solve": gj["ms_per_solve"]}
     if lu:
-        # the trailing updates, one launch per 128-column step: 2 * 128 * r^2
-        # flops on the r x r trailing matrix (r = mp - 128 (k + 1))
-        tiles = [2.0 * 128 * r * r for r in range(mp - 128, 0, -128)]
+        # the trailing updates but their first tile column (that column and
+        # the next pivot inverse run beside them): 2 * 128 * r (r - 128)
+        # flops on the r x r trailing matrix (r = mp - 128 (k + 1)), one
+        # launch per step with r > 128
+        tiles = [2.0 * 128 * r * (r - 128) for r in range(mp - 128, 128, -128)]
         lt = prof["lu_tiles"]
         lt_fl = float(np.mean(tiles))
         lt_ach = lt_fl / (lt["avg_us"] * 1e-6) / 1e12
-        roof_gj = {"kernel": "trailing update of the block-LU capacitance factorisation (k_lu_tiles: A_ij -= L_iK "
-                             "A_Kj on the 128 x 128 tiles below and right of the pivot block, rank 128 on FP64 "
-                             "matrix cores), one launch per 128-column step",
+        roof_gj = {"kernel": "trailing update of the block-LU capacitance factorisation (k_lu_tiles_rest: A_ij -= "
+                             "L_iK A_Kj on the 128 x 128 tiles below the pivot block and right of the next panel, "
+                             "rank 128 on FP64 matrix cores, two blocks per CU), one launch per 128-column step",
                    "bound": "mfma", "achieved": lt_ach, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                    "frac": lt_ach / FP64_PEAK_TFLOPS, "traffic": measured_traffic("lu_tiles"),
                    "algorithmic_flops_per_launch": lt_fl, "avg_launch_us": lt["avg_us"],
                    "launches_timed": lt["regions"], "ms_per_solve": lt["ms_per_solve"],
-                   "factorisation": whole | {"kernels": "k_gjw_pivot, then per step k_lu_colpanel and k_lu_tiles, "
-                                                        "then k_lu_rowpanels, k_lu_group_inv, k_lu_group_apply"}}
+                   "factorisation": whole | {"kernels": "k_gjw_pivot, then per step k_lu_colpanel, k_lu_tiles_next "
+                                                        "(next panel column and pivot inverse) beside "
+                                                        "k_lu_tiles_rest on a second stream, then k_lu_rowpanels, "
+                                                        "k_lu_group_inv, k_lu_group_apply"}}
     else:
         roof_gj = {"kernel": "capacitance inverse (wide Gauss-Jordan: k_gjw_pivot + k_gjw_panel + k_gjw_tiles "
                              "per 128-column step), one region per adjoint setup",

@@ -68,9 +68,10 @@ void launch_spmv_tasks(hipStream_t, int, const int4*, const long long*, const in
                        const double*, long long, const double*, const GmresState*, double*);
 void launch_spmv_tasks(hipStream_t, int, const int4*, const long long*, const int*, const float*,
                        const double*, long long, const double*, const GmresState*, double*);
-void launch_bsr_spmv(hipStream_t, int, int, const int*, const int*, const float*, const double*, const double*,
-                     double*, long long, const GmresState*);
+void launch_bsr_spmv(hipStream_t, int, int, const int*, const int*, const float*, const double*, long long,
+                     const double*, double*, long long, const GmresState*);
 void launch_to_f32(hipStream_t, long long, const double*, float*);
+void launch_bsr_soa(hipStream_t, long long, const double*, double*, float*);
 void launch_wb_gather(hipStream_t, int, int, const int*, const int*, const int*, const double*,
                       const double*, const double*, const GmresState*, double*);
 void launch_wb_lu(hipStream_t, int, int, const int*, const int*, const int*, const double*, const double*,
@@ -79,20 +80,21 @@ void launch_lu_groups(hipStream_t, int, double*);
 int lu_group_blocks();
 void launch_wb_correct(hipStream_t, int, int, const int*, const int*, const int*, const double*,
                        const double*, const double*, double, const double*, const GmresState*, double*);
-void launch_bsr_spmv(hipStream_t, int, int, const int*, const int*, const double*, const double*, double*,
+void launch_bsr_spmv(hipStream_t, int, int, const int*, const int*, const double*, long long, const double*, double*,
                      long long, const GmresState*);
 int gm_blocks(long long, int);
 int bsr_blocks(int, int);
 int vec_blocks(long long);
-void launch_bsr_dots(hipStream_t, int, int, const int*, const int*, const double*, const double*, double*,
+void launch_bsr_dots(hipStream_t, int, int, const int*, const int*, const double*, long long, const double*, double*,
                      long long, const GmresState*, int, double*);
-void launch_bsr_dots(hipStream_t, int, int, const int*, const int*, const float*, const double*, const double*,
-                     double*, long long, const GmresState*, int, double*);
+void launch_bsr_dots(hipStream_t, int, int, const int*, const int*, const float*, const double*, long long,
+                     const double*, double*, long long, const GmresState*, int, double*);
 void launch_fold_partials(hipStream_t, double*, int, const GmresState*, int);
 double* launch_gj_wide(hipStream_t, int, double*, double*, double*, double*, int*);
 void launch_lu_pivot0(hipStream_t, int, double*, double*, int*);
 void launch_lu_colpanel(hipStream_t, int, int, double*, const double*);
-void launch_lu_tiles(hipStream_t, int, int, double*, double*, int*);
+void launch_lu_tiles_next(hipStream_t, int, int, double*, double*, int*);
+void launch_lu_tiles_rest(hipStream_t, int, int, double*);
 void launch_lu_rowpanels(hipStream_t, int, double*, const double*);
 size_t gj_wide_lds_bytes();
 void launch_spmv_tasks_acc(hipStream_t, int, const int4*, const long long*, const int*, const double*,
@@ -251,6 +253,9 @@ struct adj_scene {
          *d_dz = nullptr, *d_xt = nullptr;
   // mixed precision: FP32 storage of the matrices used inside the inner solve
   float *d_Sx32 = nullptr, *d_STx32 = nullptr, *d_val32 = nullptr;
+  // entry-major copy of the block values read by the Krylov products
+  // (d_valT[k nnzb + p] = d_val[9 p + k]; d_val32 holds the same order in FP32)
+  double* d_valT = nullptr;
   bool mixed_ready = false;
   // forward step
   double* d_planes = nullptr;
@@ -299,6 +304,11 @@ struct adj_scene {
   double fwd_residual = 0.0;
   // captured Krylov chunks (tuning.graph = 1), rebuilt after every setup
   hipStream_t cap_stream = nullptr;
+  // second stream of the block-LU factorisation (the bulk of each trailing
+  // update runs there beside the next panel and its pivot inversion) and its
+  // two ordering events; default priority
+  hipStream_t lu_stream = nullptr;
+  hipEvent_t lu_ev[2] = {nullptr, nullptr};
   hipGraphExec_t chunk_exec[4] = {nullptr, nullptr, nullptr, nullptr};  // [pcg][f32]
   // preconditioner of the Krylov solves (adj_precond), set per solve;
   // woodbury_ready: the last setup built the capacitance inverse
@@ -359,7 +369,7 @@ static void free_scene(adj_scene* s) {
                   s->d_mask,     s->d_fvid,   s->d_force, s->d_utilde,      s->d_qtilde,
                   s->d_fu,       s->d_du,     s->d_ut,    s->d_qcur,        s->d_rq,
                   s->d_rhs,      s->d_cvec,   s->d_cu,    s->d_norms,       s->d_Sx32,
-                  s->d_STx32,    s->d_val32,  s->d_Pws,   s->d_x_pcg, s->d_bvid, s->d_bE,
+                  s->d_STx32,    s->d_val32,  s->d_valT,  s->d_Pws,   s->d_x_pcg, s->d_bvid, s->d_bE,
                   s->d_Yp,       s->d_Ysrc,   s->d_Ycol,  s->d_Ytasks,      s->d_CTtasks, s->d_Yval,
                   s->d_gjw_P,    s->d_gjw_W,  s->d_lu_P,  s->d_lu_y,
                   s->d_Fp, s->d_Bp, s->d_Ip, s->d_ITp, s->d_Fj, s->d_Bj, s->d_Ij, s->d_ITj, s->d_perm,
@@ -372,6 +382,9 @@ static void free_scene(adj_scene* s) {
   for (hipGraphExec_t& g : s->chunk_exec)
     if (g) (void)hipGraphExecDestroy(g);
   if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
+  for (hipEvent_t e : s->lu_ev)
+    if (e) (void)hipEventDestroy(e);
+  if (s->lu_stream) (void)hipStreamDestroy(s->lu_stream);
   delete s;
 }
 
@@ -544,6 +557,7 @@ static adj_status scene_create(const adj_scene_desc* desc, int32_t max_contacts,
   ok &= dalloc(&s->d_Sx32, h.Sx.size()) == hipSuccess;
   ok &= dalloc(&s->d_STx32, h.STx.size()) == hipSuccess;
   ok &= dalloc(&s->d_val32, 9 * (size_t)s->nnzb) == hipSuccess;
+  ok &= dalloc(&s->d_valT, 9 * (size_t)s->nnzb) == hipSuccess;
   ok &= dalloc(&s->d_fvid, mc) == hipSuccess;
   ok &= dalloc(&s->d_force, 12 * (size_t)s->nt) == hipSuccess;
   ok &= dalloc(&s->d_utilde, (size_t)s->n3) == hipSuccess;
@@ -824,14 +838,30 @@ static adj_status build_capacitance(adj_scene* s, hipStream_t st, double mu, int
     if ((a = grow(&s->d_lu_y, &s->cap_lu_y, (size_t)mp)) != ADJ_OK) return a;
     ProfScope p(s, 7, st);
     launch_gj_pad(st, m, mp, s->d_C);
+    if (!s->lu_stream && hipStreamCreateWithFlags(&s->lu_stream, hipStreamNonBlocking) != hipSuccess)
+      return fail(ADJ_E_DEVICE, "hipStreamCreateWithFlags failed");
+    for (hipEvent_t& e : s->lu_ev)
+      if (!e && hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
+        return fail(ADJ_E_DEVICE, "hipEventCreateWithFlags failed");
+    hipStream_t sb = s->lu_stream;
+    hipEvent_t e_cp = s->lu_ev[0], e_rest = s->lu_ev[1];
     launch_lu_pivot0(st, mp, s->d_C, s->d_lu_P, s->d_err);
+    // per step: the column panel on st; the bulk of the trailing update on
+    // sb once the panel is there; the next panel's column (and the next
+    // pivot inverse) on st once the previous step's bulk has updated it
     for (int k = 0; k + 1 < mp / 128; ++k) {
       launch_lu_colpanel(st, mp, k, s->d_C, s->d_lu_P);
+      HIPCHK(hipEventRecord(e_cp, st));
+      if (k > 0) HIPCHK(hipStreamWaitEvent(st, e_rest, 0));  // the rest of step k - 1
+      launch_lu_tiles_next(st, mp, k, s->d_C, s->d_lu_P, s->d_err);
+      HIPCHK(hipStreamWaitEvent(sb, e_cp, 0));
       {
-        ProfScope pk(s, 12, st);
-        launch_lu_tiles(st, mp, k, s->d_C, s->d_lu_P, s->d_err);
+        ProfScope pk(s, 12, sb);
+        launch_lu_tiles_rest(sb, mp, k, s->d_C);
       }
+      HIPCHK(hipEventRecord(e_rest, sb));
     }
+    if (mp / 128 > 1) HIPCHK(hipStreamWaitEvent(st, e_rest, 0));
     launch_lu_rowpanels(st, mp, s->d_C, s->d_lu_P);
     launch_lu_groups(st, mp, s->d_C);
     s->d_X = s->d_C;
@@ -949,15 +979,15 @@ extern "C" adj_status adjoint_setup(adj_scene* s, const adj_contact_state* cst, 
   if (woodbury && (a = build_capacitance(s, st, cst->mu, 1)) != ADJ_OK) return a;
   s->woodbury_ready = woodbury;
   s->mixed_ready = false;
-  if (opts && opts->prec == ADJ_MIXED) {
-    // FP32 storage of the block matrix read by the inner solve (S and S^T
-    // have FP32 copies from scene creation).  The Woodbury factors D, X and
-    // Z stay FP64: in the directions of stiff contacts the correction
-    // cancels A^{-1} r almost exactly, so their rounding would be amplified
-    // by the contact-to-elastic stiffness ratio.
-    launch_to_f32(st, 9LL * s->nnzb, s->d_val, s->d_val32);
-    s->mixed_ready = true;
-  }
+  // entry-major copy of the assembled matrix for the Krylov products, and
+  // with ADJ_MIXED its FP32 rounding read by the inner solve (S and S^T have
+  // FP32 copies from scene creation).  The Woodbury factors D, X and Z stay
+  // FP64: in the directions of stiff contacts the correction cancels
+  // A^{-1} r almost exactly, so their rounding would be amplified by the
+  // contact-to-elastic stiffness ratio.
+  const bool mixed = opts && opts->prec == ADJ_MIXED;
+  launch_bsr_soa(st, s->nnzb, s->d_val, s->d_valT, mixed ? s->d_val32 : nullptr);
+  s->mixed_ready = mixed;
   HIPCHK(hipGetLastError());
   s->setup_done = true;
   return ADJ_OK;
@@ -1130,10 +1160,10 @@ static void apply_precond(adj_scene* s, hipStream_t st, const double* x, long lo
 static void bsr(adj_scene* s, hipStream_t st, const double* x, double* outbase, long long stride,
                 const GmresState* state, bool f32) {
   if (f32)
-    launch_bsr_spmv(st, s->tune.bsr_lanes, s->nv, s->d_rowptr, s->d_col, s->d_val32, s->d_val, x, outbase, stride,
+    launch_bsr_spmv(st, s->tune.bsr_lanes, s->nv, s->d_rowptr, s->d_col, s->d_val32, s->d_valT, s->nnzb, x, outbase, stride,
                     state);
   else
-    launch_bsr_spmv(st, s->tune.bsr_lanes, s->nv, s->d_rowptr, s->d_col, s->d_val, x, outbase, stride, state);
+    launch_bsr_spmv(st, s->tune.bsr_lanes, s->nv, s->d_rowptr, s->d_col, s->d_valT, s->nnzb, x, outbase, stride, state);
 }
 
 // One GMRES iteration per pass of the loop: preconditioner (4 launches),
@@ -1152,10 +1182,10 @@ static void gmres_chunk(adj_scene* s, hipStream_t st, bool f32, int n) {
     {
       ProfScope p(s, 4, st);
       if (f32)
-        launch_bsr_dots(st, s->tune.bsr_lanes, s->nv, s->d_rowptr, s->d_col, s->d_val32, s->d_val, s->d_y, s->d_Vt, stride,
+        launch_bsr_dots(st, s->tune.bsr_lanes, s->nv, s->d_rowptr, s->d_col, s->d_val32, s->d_valT, s->nnzb, s->d_y, s->d_Vt, stride,
                         s->d_state, -1, s->P1());
       else
-        launch_bsr_dots(st, s->tune.bsr_lanes, s->nv, s->d_rowptr, s->d_col, s->d_val, s->d_y, s->d_Vt, stride,
+        launch_bsr_dots(st, s->tune.bsr_lanes, s->nv, s->d_rowptr, s->d_col, s->d_valT, s->nnzb, s->d_y, s->d_Vt, stride,
                         s->d_state, -1, s->P1());
     }
     if (nb1_raw > kFoldAt) launch_fold_partials(st, s->P1(), nb1_raw, s->d_state, 0);
@@ -1186,10 +1216,10 @@ static void pcg_chunk(adj_scene* s, hipStream_t st, bool f32) {
     {
       ProfScope pr(s, 4, st);
       if (f32)
-        launch_bsr_dots(st, s->tune.bsr_lanes, s->nv, s->d_rowptr, s->d_col, s->d_val32, s->d_val, p, s->d_Vt, n3,
+        launch_bsr_dots(st, s->tune.bsr_lanes, s->nv, s->d_rowptr, s->d_col, s->d_val32, s->d_valT, s->nnzb, p, s->d_Vt, n3,
                         s->d_state, 0, s->P1());
       else
-        launch_bsr_dots(st, s->tune.bsr_lanes, s->nv, s->d_rowptr, s->d_col, s->d_val, p, s->d_Vt, n3,
+        launch_bsr_dots(st, s->tune.bsr_lanes, s->nv, s->d_rowptr, s->d_col, s->d_valT, s->nnzb, p, s->d_Vt, n3,
                         s->d_state, 0, s->P1());
     }
     launch_pcg_xr(st, n3, s->d_x_pcg, s->d_r, p, w, s->P1(), nb1, s->d_state, s->d_coef, s->P3());
@@ -2016,6 +2046,7 @@ static adj_status fwd_newton(adj_scene* s, hipStream_t st, const double* qbar, F
       launch_contact_fold(st, nc, s->d_fvid, s->d_diag_slot, s->d_Wt, s->d_val);
       if ((a = build_capacitance(s, st, mu, 0)) != ADJ_OK) return a;
     }
+    launch_bsr_soa(st, s->nnzb, s->d_val, s->d_valT, nullptr);  // the Krylov products' copy
     // rhs = -r_q + h^2 sum F^T R^T e
     launch_scale_vec(st, n3, s->d_rq, -1.0, s->d_rhs);
     launch_add_contact_vec(st, nc, s->d_fvid, s->d_cvec, s->d_rhs);

@@ -32,20 +32,23 @@ __device__ __forceinline__ double group_sum(double v) {
 template <class MT>
 __device__ __forceinline__ void block_madd(const MT* __restrict__ val, const double* __restrict__ val64, size_t p,
                                            bool diag, double x0, double x1, double x2, double& a0, double& a1,
-                                           double& a2) {
+                                           double& a2, long long soa = 0) {
+  // entry k of block p: val[9 p + k] (soa = 0), or val[k soa + p] (the
+  // entry-major copy, soa = number of blocks: each entry's loads coalesce)
+  const size_t base = soa ? p : 9 * p, ks = soa ? (size_t)soa : 1;
   if constexpr (sizeof(MT) == 4) {
     if (diag) {
-      const double* b = val64 + 9 * p;
-      a0 += b[0] * x0 + b[1] * x1 + b[2] * x2;
-      a1 += b[3] * x0 + b[4] * x1 + b[5] * x2;
-      a2 += b[6] * x0 + b[7] * x1 + b[8] * x2;
+      const double* b = val64 + base;
+      a0 += b[0] * x0 + b[ks] * x1 + b[2 * ks] * x2;
+      a1 += b[3 * ks] * x0 + b[4 * ks] * x1 + b[5 * ks] * x2;
+      a2 += b[6 * ks] * x0 + b[7 * ks] * x1 + b[8 * ks] * x2;
       return;
     }
   }
-  const MT* b = val + 9 * p;
-  a0 += (double)b[0] * x0 + (double)b[1] * x1 + (double)b[2] * x2;
-  a1 += (double)b[3] * x0 + (double)b[4] * x1 + (double)b[5] * x2;
-  a2 += (double)b[6] * x0 + (double)b[7] * x1 + (double)b[8] * x2;
+  const MT* b = val + base;
+  a0 += (double)b[0] * x0 + (double)b[ks] * x1 + (double)b[2 * ks] * x2;
+  a1 += (double)b[3 * ks] * x0 + (double)b[4 * ks] * x1 + (double)b[5 * ks] * x2;
+  a2 += (double)b[6 * ks] * x0 + (double)b[7 * ks] * x1 + (double)b[8 * ks] * x2;
 }
 
 // Block-wide sum for blockDim.x <= 1024; result valid in thread 0.

@@ -881,9 +881,9 @@ size_t gj_wide_lds_bytes() { return sizeof(GjwShared); }
 // Work: the trailing rank-128 updates, 2/3 mp^3, against 2 mp^3 for the
 // explicit inverse.  Per step (K = k0 .. k0 + 127):
 //   k_lu_colpanel  L_iK = A_iK P_k for the rows below K, in place;
-//   k_lu_tiles     A_ij -= L_iK A_Kj for the 128 x 128 tiles below and right
-//                  of K, in place; the first tile is the next pivot block
-//                  and is also inverted (P_{k+1});
+//   k_lu_tiles_next, k_lu_tiles_rest  A_ij -= L_iK A_Kj for the 128 x 128
+//                  tiles below and right of K, in place; the first tile is
+//                  the next pivot block and is also inverted (P_{k+1});
 // and after the last step k_lu_rowpanels: V_Kj = P_k A_Kj for every K and
 // the columns right of it, in place (row panels are not read again once
 // their step's trailing update has run).
@@ -1013,43 +1013,36 @@ __global__ void __launch_bounds__(256) k_lu_rowpanels(int mp, double* __restrict
         A[(size_t)(k0 + 32 * w + 16 * p + lk + 4 * e) * mp + j0 + 16 * q + li] = acc[p][q][e];
 }
 
-// Tiles of the trailing matrix (rows and columns from k0 + 128), row-major
-// over the tile grid; tile 0 is the next pivot block (blocks start in index
-// order, so its inversion overlaps the other tiles).  Reads the column panel
-// (left of the trailing matrix) and the row panel (above it), neither of
-// which any tile writes.
-__global__ void __launch_bounds__(256, 1) k_lu_tiles(int mp, int k0, double* __restrict__ A,
-                                                     double* __restrict__ Pnext, int* __restrict__ err) {
-  __shared__ GjwShared sh;
-  auto& Ws = sh.t.Ws;
-  auto& Rs = sh.t.Rs;
-  const int base = k0 + kWB;
-  const int nt = (mp - base) / kWB;
-  const int t = blockIdx.x;
-  const int I0 = base + (t / nt) * kWB, J0 = base + (t % nt) * kWB;
+// One 128 x 128 tile (I0, J0) of the trailing update at step k0,
+// A_ij -= L_iK A_Kj, in place: the panels in KC-wide chunks through LDS
+// (the next chunk loaded into registers while the current one is
+// multiplied), each wavefront a 64 x 64 quadrant of 4 x 4 FP64 MFMA tiles.
+// On return acc holds the updated tile (already written to A).
+template <int KC>
+__device__ __forceinline__ void lu_tile(int mp, int k0, int I0, int J0, double* __restrict__ A,
+                                        double (*__restrict__ Ws)[KC + 1], double (*__restrict__ Rs)[kWB + 1],
+                                        d4 (&acc)[4][4]) {
+  constexpr int NP = kWB * KC / 256;  // panel entries per thread and chunk
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, li = lane & 15, lk = lane >> 4;
   const int wr = 64 * (w >> 1), wc = 64 * (w & 1);
-  double wpre[kWPre], rpre[kWPre];
+  double wpre[NP], rpre[NP];
   auto load_chunk = [&](int kc) {
 #pragma unroll
-    for (int u = 0; u < kWPre; ++u) {
+    for (int u = 0; u < NP; ++u) {
       const int e = tid + 256 * u;
-      const int rw = e / kWKC, cw = e % kWKC;
-      wpre[u] = A[(size_t)(I0 + rw) * mp + k0 + kc + cw];
-      const int rr = e / kWB, cr = e % kWB;
-      rpre[u] = A[(size_t)(k0 + kc + rr) * mp + J0 + cr];
+      wpre[u] = A[(size_t)(I0 + e / KC) * mp + k0 + kc + e % KC];
+      rpre[u] = A[(size_t)(k0 + kc + e / kWB) * mp + J0 + e % kWB];
     }
   };
   auto store_chunk = [&]() {
 #pragma unroll
-    for (int u = 0; u < kWPre; ++u) {
+    for (int u = 0; u < NP; ++u) {
       const int e = tid + 256 * u;
-      Ws[e / kWKC][e % kWKC] = wpre[u];
+      Ws[e / KC][e % KC] = wpre[u];
       Rs[e / kWB][e % kWB] = rpre[u];
     }
   };
   load_chunk(0);
-  d4 acc[4][4];
 #pragma unroll
   for (int p = 0; p < 4; ++p)
 #pragma unroll
@@ -1059,11 +1052,11 @@ __global__ void __launch_bounds__(256, 1) k_lu_tiles(int mp, int k0, double* __r
         acc[p][q][e] = A[(size_t)(I0 + wr + 16 * p + lk + 4 * e) * mp + J0 + wc + 16 * q + li];
   store_chunk();
   __syncthreads();
-  for (int kc = 0; kc < kWB; kc += kWKC) {
-    const bool more = kc + kWKC < kWB;
-    if (more) load_chunk(kc + kWKC);
+  for (int kc = 0; kc < kWB; kc += KC) {
+    const bool more = kc + KC < kWB;
+    if (more) load_chunk(kc + KC);
 #pragma unroll
-    for (int k4 = 0; k4 < kWKC; k4 += 4) {
+    for (int k4 = 0; k4 < KC; k4 += 4) {
       double av[4], bv[4];
 #pragma unroll
       for (int p = 0; p < 4; ++p) av[p] = -Ws[wr + 16 * p + li][k4 + lk];
@@ -1087,8 +1080,29 @@ __global__ void __launch_bounds__(256, 1) k_lu_tiles(int mp, int k0, double* __r
 #pragma unroll
       for (int e = 0; e < 4; ++e)
         A[(size_t)(I0 + wr + 16 * p + lk + 4 * e) * mp + J0 + wc + 16 * q + li] = acc[p][q][e];
-  if (t != 0) return;
+}
+
+// The trailing update of step k0 in two launches on two streams:
+//   k_lu_tiles_next  the first tile column (the next step's panel), one
+//                    block per tile and CU (141 KB of LDS); block 0 is the
+//                    next pivot block (blocks start in index order) and
+//                    also inverts it (P_{k+1});
+//   k_lu_tiles_rest  every other trailing tile, two blocks per CU (34 KB of
+//                    LDS, 16-wide chunks), no inversion,
+// so that the pivot chain runs beside the bulk of the update and the bulk
+// runs at two blocks per CU.  Both read the column panel left of the
+// trailing matrix and the row panel above it, which neither writes.
+__global__ void __launch_bounds__(256, 1) k_lu_tiles_next(int mp, int k0, double* __restrict__ A,
+                                                          double* __restrict__ Pnext, int* __restrict__ err) {
+  __shared__ GjwShared sh;
+  const int I0 = k0 + kWB + blockIdx.x * kWB, J0 = k0 + kWB;
+  d4 acc[4][4];
+  lu_tile<kWKC>(mp, k0, I0, J0, A, sh.t.Ws, sh.t.Rs, acc);
+  if (blockIdx.x != 0) return;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, li = lane & 15, lk = lane >> 4;
+  const int wr = 64 * (w >> 1), wc = 64 * (w & 1);
   double* M = sh.p.M;
+  __syncthreads();  // the panels in LDS are no longer read
 #pragma unroll
   for (int p = 0; p < 4; ++p)
 #pragma unroll
@@ -1100,10 +1114,21 @@ __global__ void __launch_bounds__(256, 1) k_lu_tiles(int mp, int k0, double* __r
   for (int e = tid; e < kWB * kWB; e += 256) Pnext[e] = M[(e / kWB) * kWL + e % kWB];
 }
 
+constexpr int kRestKC = 16;
+__global__ void __launch_bounds__(256, 2) k_lu_tiles_rest(int mp, int k0, double* __restrict__ A) {
+  __shared__ double Ws[kWB][kRestKC + 1];
+  __shared__ double Rs[kRestKC][kWB + 1];
+  const int base = k0 + kWB, nt = (mp - base) / kWB, nc = nt - 1;
+  const int I0 = base + (blockIdx.x / nc) * kWB, J0 = base + kWB + (blockIdx.x % nc) * kWB;
+  d4 acc[4][4];
+  lu_tile<kRestKC>(mp, k0, I0, J0, A, Ws, Rs, acc);
+}
+
 // Pall: mp/128 blocks of 128 x 128 (the inverted pivot blocks P_k).  The
-// factorisation is launch_lu_pivot0, then for k = 0 .. mp/128 - 2 the two
-// launches of step k in this order: launch_lu_colpanel, launch_lu_tiles;
-// then launch_lu_rowpanels once.
+// factorisation is launch_lu_pivot0, then per step k = 0 .. mp/128 - 2
+// launch_lu_colpanel, then launch_lu_tiles_next and launch_lu_tiles_rest
+// (concurrently; the next step's launch_lu_tiles_next also waits for this
+// step's rest); then launch_lu_rowpanels once.
 void launch_lu_pivot0(hipStream_t st, int mp, double* A, double* Pall, int* err) {
   k_gjw_pivot<<<1, 256, 0, st>>>(mp, 0, A, Pall, err);
 }
@@ -1111,9 +1136,15 @@ void launch_lu_colpanel(hipStream_t st, int mp, int k, double* A, const double* 
   const int k0 = k * kWB;
   k_lu_colpanel<<<(mp - k0 - kWB) / 64, 256, 0, st>>>(mp, k0, A, Pall + (size_t)k * kWB * kWB);
 }
-void launch_lu_tiles(hipStream_t st, int mp, int k, double* A, double* Pall, int* err) {
+// The trailing update of step k: the next panel's column with the pivot
+// inversion, and the other tiles (no launch when there are none).
+void launch_lu_tiles_next(hipStream_t st, int mp, int k, double* A, double* Pall, int* err) {
   const int k0 = k * kWB, nt = (mp - k0 - kWB) / kWB;
-  k_lu_tiles<<<nt * nt, 256, 0, st>>>(mp, k0, A, Pall + (size_t)(k + 1) * kWB * kWB, err);
+  k_lu_tiles_next<<<nt, 256, 0, st>>>(mp, k0, A, Pall + (size_t)(k + 1) * kWB * kWB, err);
+}
+void launch_lu_tiles_rest(hipStream_t st, int mp, int k, double* A) {
+  const int k0 = k * kWB, nt = (mp - k0 - kWB) / kWB;
+  if (nt > 1) k_lu_tiles_rest<<<nt * (nt - 1), 256, 0, st>>>(mp, k0, A);
 }
 void launch_lu_rowpanels(hipStream_t st, int mp, double* A, const double* Pall) {
   const int nb = mp / kWB;
@@ -1143,7 +1174,7 @@ struct LuGemmShared {
 };
 
 // acc (each wavefront's 64 x 64 quadrant of a 128 x 128 block, the
-// k_lu_tiles layout) += Ablk Bblk, both 128 x 128 blocks of a row-major
+// lu_tile layout) += Ablk Bblk, both 128 x 128 blocks of a row-major
 // matrix with leading dimension ld, staged through LDS in 32-wide chunks.
 __device__ __forceinline__ void mma128(d4 (&acc)[4][4], const double* __restrict__ Ab, const double* __restrict__ Bb,
                                        int ld, LuGemmShared& sh) {

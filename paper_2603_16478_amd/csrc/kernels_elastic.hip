@@ -11,9 +11,10 @@
 // so E_kl = h^2 w ((Bt_k . Bt_l) I - U Y^{kl} U^T).  The 10 blocks k <= l are
 // stored per tet (E_lk = E_kl^T): out[t*90 + pair*9 + 3r + c].
 //
-// k_assemble: one thread per block slot of Acal^T; sums the slot's element
-// contributions in the fixed order of the element-to-entry map (Sec. 5.4,
-// matrix assembly) and adds the lumped mass on the diagonal.
+// k_assemble: nine threads per block slot of Acal^T (one per entry); each
+// sums its entry over the slot's element contributions in the fixed order of
+// the element-to-entry map (Sec. 5.4, matrix assembly) and adds the lumped
+// mass on the diagonal.
 #include "device_common.h"
 #include "nh_local.h"
 
@@ -112,34 +113,27 @@ __global__ void __launch_bounds__(256) k_assemble(int nnzb, const int* __restric
                                                   const int* __restrict__ col,
                                                   const double* __restrict__ mass,
                                                   double* __restrict__ val) {
-  const int sl = blockIdx.x * blockDim.x + threadIdx.x;
-  if (sl >= nnzb) return;
-  double acc[9];
-#pragma unroll
-  for (int e = 0; e < 9; ++e) acc[e] = 0.0;
-  for (int p = slot_ptr[sl]; p < slot_ptr[sl + 1]; ++p) {
+  // nine threads per slot, one per entry: the nine threads of a slot read
+  // each element block's 72 contiguous bytes together, and the slots' values
+  // are written contiguously
+  const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= 9LL * nnzb) return;
+  const int sl = (int)(g / 9), e = (int)(g - 9LL * sl);
+  const int r = e / 3, c = e - 3 * r;
+  const int et = 3 * c + r;  // the same entry of the transposed block
+  double acc = 0.0;
+  const int p0 = slot_ptr[sl], p1 = slot_ptr[sl + 1];
+#pragma unroll 4
+  for (int p = p0; p < p1; ++p) {
     const int code = slot_code[p];
     const int t = code >> 5, pr = (code >> 1) & 15, tr = code & 1;
-    const double* b = tetblk + 90 * (size_t)t + 9 * pr;
-    if (tr) {
-#pragma unroll
-      for (int r = 0; r < 3; ++r)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) acc[3 * r + c] += b[3 * c + r];
-    } else {
-#pragma unroll
-      for (int e = 0; e < 9; ++e) acc[e] += b[e];
-    }
+    acc += tetblk[90 * (size_t)t + 9 * pr + (tr ? et : e)];
   }
-  const int row = row_of_slot[sl];
-  if (col[sl] == row) {
-    const double m = mass[row];
-    acc[0] += m;
-    acc[4] += m;
-    acc[8] += m;
+  if (r == c) {
+    const int row = row_of_slot[sl];
+    if (col[sl] == row) acc += mass[row];
   }
-#pragma unroll
-  for (int e = 0; e < 9; ++e) val[9 * (size_t)sl + e] = acc[e];
+  val[g] = acc;
 }
 
 // Per-tet parameter gradients (App. B.3, with w_i = 2 mu_i V_i):
@@ -245,7 +239,7 @@ void launch_tet_blocks(hipStream_t st, int nt, const int* tets, const double* Bt
 void launch_assemble(hipStream_t st, int nnzb, const int* slot_ptr, const int* slot_code,
                      const double* tetblk, const int* row_of_slot, const int* col, const double* mass,
                      double* val) {
-  k_assemble<<<(nnzb + 255) / 256, 256, 0, st>>>(nnzb, slot_ptr, slot_code, tetblk, row_of_slot, col,
+  k_assemble<<<(unsigned)((9LL * nnzb + 255) / 256), 256, 0, st>>>(nnzb, slot_ptr, slot_code, tetblk, row_of_slot, col,
                                                   mass, val);
 }
 

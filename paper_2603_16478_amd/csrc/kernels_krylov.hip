@@ -239,7 +239,7 @@ template <class MT, int LANES>
 __global__ void __launch_bounds__(256) k_bsr_spmv(int nv, const int* __restrict__ rowptr,
                                                   const int* __restrict__ col,
                                                   const MT* __restrict__ val,
-                                                  const double* __restrict__ val64,
+                                                  const double* __restrict__ val64, long long soa,
                                                   const double* __restrict__ x,
                                                   double* __restrict__ outbase, long long stride,
                                                   const GmresState* __restrict__ st) {
@@ -251,7 +251,7 @@ __global__ void __launch_bounds__(256) k_bsr_spmv(int nv, const int* __restrict_
     for (int p = rowptr[row] + sub; p < rowptr[row + 1]; p += LANES) {
       const int c = col[p];
       const double x0 = x[3 * c], x1 = x[3 * c + 1], x2 = x[3 * c + 2];
-      block_madd<MT>(val, val64, (size_t)p, c == row, x0, x1, x2, a0, a1, a2);
+      block_madd<MT>(val, val64, (size_t)p, c == row, x0, x1, x2, a0, a1, a2, soa);
     }
   }
   a0 = group_sum<LANES>(a0);
@@ -281,7 +281,7 @@ constexpr int kLd = 130;  // partials of one block: [0 .. 129], basis index i
 template <class MT, int LANES>
 __global__ void __launch_bounds__(256) k_bsr_dots(int nv, const int* __restrict__ rowptr,
                                                   const int* __restrict__ col, const MT* __restrict__ val,
-                                                  const double* __restrict__ val64,
+                                                  const double* __restrict__ val64, long long soa,
                                                   const double* __restrict__ y, double* __restrict__ Vt,
                                                   long long stride, const GmresState* __restrict__ st, int jfix,
                                                   double* __restrict__ P) {
@@ -294,10 +294,12 @@ __global__ void __launch_bounds__(256) k_bsr_dots(int nv, const int* __restrict_
   const int row0 = blockIdx.x * R, row = row0 + rl;
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
   if (row < nv) {
-    for (int p = rowptr[row] + sub; p < rowptr[row + 1]; p += LANES) {
+    const int pe = rowptr[row + 1];
+#pragma unroll 2
+    for (int p = rowptr[row] + sub; p < pe; p += LANES) {
       const int c = col[p];
       const double x0 = y[3 * c], x1 = y[3 * c + 1], x2 = y[3 * c + 2];
-      block_madd<MT>(val, val64, (size_t)p, c == row, x0, x1, x2, a0, a1, a2);
+      block_madd<MT>(val, val64, (size_t)p, c == row, x0, x1, x2, a0, a1, a2, soa);
     }
   }
   a0 = group_sum<LANES>(a0);
@@ -876,25 +878,45 @@ void launch_wb_correct(hipStream_t s, int nv, int ncv, const int* cv_ptr, const 
 }
 template <class MT>
 static void bsr_impl(hipStream_t s, int lanes, int nv, const int* rowptr, const int* col, const MT* val,
-                     const double* val64, const double* x, double* outbase, long long stride,
+                     const double* val64, long long soa, const double* x, double* outbase, long long stride,
                      const GmresState* st) {
   const int rows = 256 / lanes;
   const unsigned g = (unsigned)((nv + rows - 1) / rows);
   switch (lanes) {
-    case 4: k_bsr_spmv<MT, 4><<<g, 256, 0, s>>>(nv, rowptr, col, val, val64, x, outbase, stride, st); break;
-    case 8: k_bsr_spmv<MT, 8><<<g, 256, 0, s>>>(nv, rowptr, col, val, val64, x, outbase, stride, st); break;
-    case 32: k_bsr_spmv<MT, 32><<<g, 256, 0, s>>>(nv, rowptr, col, val, val64, x, outbase, stride, st); break;
-    default: k_bsr_spmv<MT, 16><<<g, 256, 0, s>>>(nv, rowptr, col, val, val64, x, outbase, stride, st); break;
+    case 4: k_bsr_spmv<MT, 4><<<g, 256, 0, s>>>(nv, rowptr, col, val, val64, soa, x, outbase, stride, st); break;
+    case 8: k_bsr_spmv<MT, 8><<<g, 256, 0, s>>>(nv, rowptr, col, val, val64, soa, x, outbase, stride, st); break;
+    case 32: k_bsr_spmv<MT, 32><<<g, 256, 0, s>>>(nv, rowptr, col, val, val64, soa, x, outbase, stride, st); break;
+    default: k_bsr_spmv<MT, 16><<<g, 256, 0, s>>>(nv, rowptr, col, val, val64, soa, x, outbase, stride, st); break;
   }
 }
+// soa: 0 for block-major values (val[9 p + k]), else the number of blocks
+// of the entry-major copy (val[k soa + p])
 void launch_bsr_spmv(hipStream_t s, int lanes, int nv, const int* rowptr, const int* col, const double* val,
-                     const double* x, double* outbase, long long stride, const GmresState* st) {
-  bsr_impl(s, lanes, nv, rowptr, col, val, (const double*)nullptr, x, outbase, stride, st);
+                     long long soa, const double* x, double* outbase, long long stride, const GmresState* st) {
+  bsr_impl(s, lanes, nv, rowptr, col, val, (const double*)nullptr, soa, x, outbase, stride, st);
 }
 // FP32 block values with the diagonal blocks from val64 (see block_madd)
 void launch_bsr_spmv(hipStream_t s, int lanes, int nv, const int* rowptr, const int* col, const float* val,
-                     const double* val64, const double* x, double* outbase, long long stride, const GmresState* st) {
-  bsr_impl(s, lanes, nv, rowptr, col, val, val64, x, outbase, stride, st);
+                     const double* val64, long long soa, const double* x, double* outbase, long long stride,
+                     const GmresState* st) {
+  bsr_impl(s, lanes, nv, rowptr, col, val, val64, soa, x, outbase, stride, st);
+}
+
+// Entry-major copies of the block values (the Krylov products' layout):
+// soa[k nnzb + p] = aos[9 p + k], and the same rounded to FP32 into soa32
+// when it is given.
+__global__ void k_bsr_soa(long long nnzb, const double* __restrict__ aos, double* __restrict__ soa,
+                          float* __restrict__ soa32) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= 9 * nnzb) return;
+  const long long k = e / nnzb, p = e - k * nnzb;
+  const double v = aos[9 * p + k];
+  soa[e] = v;
+  if (soa32) soa32[e] = (float)v;
+}
+void launch_bsr_soa(hipStream_t s, long long nnzb, const double* aos, double* soa, float* soa32) {
+  if (nnzb <= 0) return;
+  k_bsr_soa<<<(unsigned)((9 * nnzb + 255) / 256), 256, 0, s>>>(nnzb, aos, soa, soa32);
 }
 
 __global__ void k_to_f32(long long n, const double* __restrict__ a, float* __restrict__ out) {
@@ -932,24 +954,25 @@ int bsr_blocks(int nv, int lanes) { return (nv + 256 / lanes - 1) / (256 / lanes
 
 template <class MT>
 static void bsr_dots_impl(hipStream_t s, int lanes, int nv, const int* rowptr, const int* col, const MT* val,
-                          const double* val64, const double* y, double* Vt, long long stride, const GmresState* st,
-                          int jfix, double* P) {
+                          const double* val64, long long soa, const double* y, double* Vt, long long stride,
+                          const GmresState* st, int jfix, double* P) {
   const unsigned g = (unsigned)bsr_blocks(nv, lanes);
   switch (lanes) {
-    case 4: k_bsr_dots<MT, 4><<<g, 256, 0, s>>>(nv, rowptr, col, val, val64, y, Vt, stride, st, jfix, P); break;
-    case 8: k_bsr_dots<MT, 8><<<g, 256, 0, s>>>(nv, rowptr, col, val, val64, y, Vt, stride, st, jfix, P); break;
-    case 32: k_bsr_dots<MT, 32><<<g, 256, 0, s>>>(nv, rowptr, col, val, val64, y, Vt, stride, st, jfix, P); break;
-    default: k_bsr_dots<MT, 16><<<g, 256, 0, s>>>(nv, rowptr, col, val, val64, y, Vt, stride, st, jfix, P); break;
+    case 4: k_bsr_dots<MT, 4><<<g, 256, 0, s>>>(nv, rowptr, col, val, val64, soa, y, Vt, stride, st, jfix, P); break;
+    case 8: k_bsr_dots<MT, 8><<<g, 256, 0, s>>>(nv, rowptr, col, val, val64, soa, y, Vt, stride, st, jfix, P); break;
+    case 32: k_bsr_dots<MT, 32><<<g, 256, 0, s>>>(nv, rowptr, col, val, val64, soa, y, Vt, stride, st, jfix, P); break;
+    default: k_bsr_dots<MT, 16><<<g, 256, 0, s>>>(nv, rowptr, col, val, val64, soa, y, Vt, stride, st, jfix, P); break;
   }
 }
 void launch_bsr_dots(hipStream_t s, int lanes, int nv, const int* rowptr, const int* col, const double* val,
-                     const double* y, double* Vt, long long stride, const GmresState* st, int jfix, double* P) {
-  bsr_dots_impl(s, lanes, nv, rowptr, col, val, (const double*)nullptr, y, Vt, stride, st, jfix, P);
+                     long long soa, const double* y, double* Vt, long long stride, const GmresState* st, int jfix,
+                     double* P) {
+  bsr_dots_impl(s, lanes, nv, rowptr, col, val, (const double*)nullptr, soa, y, Vt, stride, st, jfix, P);
 }
 void launch_bsr_dots(hipStream_t s, int lanes, int nv, const int* rowptr, const int* col, const float* val,
-                     const double* val64, const double* y, double* Vt, long long stride, const GmresState* st,
-                     int jfix, double* P) {
-  bsr_dots_impl(s, lanes, nv, rowptr, col, val, val64, y, Vt, stride, st, jfix, P);
+                     const double* val64, long long soa, const double* y, double* Vt, long long stride,
+                     const GmresState* st, int jfix, double* P) {
+  bsr_dots_impl(s, lanes, nv, rowptr, col, val, val64, soa, y, Vt, stride, st, jfix, P);
 }
 
 void launch_gm_update(hipStream_t s, long long n, int rpb, double* Vt, long long stride, const double* scale,
