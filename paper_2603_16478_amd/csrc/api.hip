@@ -24,7 +24,7 @@ namespace adj {
 // kernels (defined in the .hip kernel files)
 void launch_tet_blocks(hipStream_t, int, const int*, const double*, const double*, const double*,
                        const double*, double, const double*, double*, int*, int);
-void launch_assemble(hipStream_t, int, const int*, const int*, const double*, const int*, const int*,
+void launch_assemble(hipStream_t, int, int, const int*, const int*, const double*, const int*, const int*,
                      const double*, double*);
 void launch_vjp_tets(hipStream_t, int, const int*, const double*, const double*, const double*,
                      const double*, const double*, const double*, double, const double*, const double*,
@@ -961,7 +961,7 @@ extern "C" adj_status adjoint_setup(adj_scene* s, const adj_contact_state* cst, 
   }
   {
     ProfScope p(s, 6, st);
-    launch_assemble(st, s->nnzb, s->d_slot_ptr, s->d_slot_code, s->d_tetblk, s->d_row_of_slot, s->d_col,
+    launch_assemble(st, s->nnzb, s->nt, s->d_slot_ptr, s->d_slot_code, s->d_tetblk, s->d_row_of_slot, s->d_col,
                     s->d_mass, s->d_val);
   }
   // a3: contact blocks folded into the diagonal blocks of Acal^T
@@ -1984,7 +1984,7 @@ static adj_status fwd_newton(adj_scene* s, hipStream_t st, const double* qbar, F
     launch_add_vec(st, n3, qbar, s->d_fu, 1.0, s->d_qcur);
     launch_tet_blocks(st, s->nt, s->d_tets, s->d_Bt, s->d_vol, s->d_lmu, s->d_llam, h2, s->d_qcur,
                       s->d_tetblk, s->d_err, s->material);
-    launch_assemble(st, s->nnzb, s->d_slot_ptr, s->d_slot_code, s->d_tetblk, s->d_row_of_slot, s->d_col,
+    launch_assemble(st, s->nnzb, s->nt, s->d_slot_ptr, s->d_slot_code, s->d_tetblk, s->d_row_of_slot, s->d_col,
                     s->d_mass, s->d_val);
     for (int c = 0; c < nc; ++c) {
       const double k = C.k[c];

@@ -9,7 +9,7 @@
 // U Y^{kl} U^T where
 //     Y_ab = W_ab BV_ka BV_lb + [a=b] sum_{j!=a} M_aj BV_kj BV_lj + [a!=b] N_ab BV_kb BV_la,
 // so E_kl = h^2 w ((Bt_k . Bt_l) I - U Y^{kl} U^T).  The 10 blocks k <= l are
-// stored per tet (E_lk = E_kl^T): out[t*90 + pair*9 + 3r + c].
+// stored pair-major (E_lk = E_kl^T): out[(pair*nt + t)*9 + 3r + c].
 //
 // k_assemble: nine threads per block slot of Acal^T (one per entry); each
 // sums its entry over the slot's element contributions in the fixed order of
@@ -45,68 +45,85 @@ __global__ void __launch_bounds__(128) k_tet_blocks(int nt, const int* __restric
                                                     const double* __restrict__ q,
                                                     double* __restrict__ out, int* __restrict__ err,
                                                     int model) {
+  // pair-major output, out[(pr nt + t) 9 + 3r + c]: per pair the block's 128
+  // tets write one contiguous run, staged through LDS
+  __shared__ double stage[128 * 9];
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= nt) return;
-  double x[4][3], B[4][3];
-  int vid[4];
-  load_tet(t, tets, Bt, q, x, B, vid);
-  double F[3][3];
-  deformation_gradient(x, B, F);
-  if (!(det3(F) > 0.0)) {
-    err[0] = 1;  // inverted element
-    for (int e = 0; e < 90; ++e) out[90 * (size_t)t + e] = 0.0;
-    return;
+  const int t0 = blockIdx.x * blockDim.x, nloc = min((int)blockDim.x, nt - t0);
+  bool ok = false;
+  double U[3][3], B[4][3], W[3][3], M[3][3], N[3][3], BV[4][3];
+  double scale = 0.0;
+  if (t < nt) {
+    double x[4][3];
+    int vid[4];
+    load_tet(t, tets, Bt, q, x, B, vid);
+    double F[3][3];
+    deformation_gradient(x, B, F);
+    ok = det3(F) > 0.0;
+    if (!ok) {
+      err[0] = 1;  // inverted element: its blocks are written as zeros
+    } else {
+      const double mu = lmu[t], lam = llam[t];
+      double s[3], V[3][3];
+      svd3(F, U, s, V);
+      NHLocal L;
+      double th[3], qd[3][3];
+      local_projection(model, s, mu, lam, th, W, qd, L);
+      local_MN(th, s, qd, M, N);
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) BV[k][j] = B[k][0] * V[0][j] + B[k][1] * V[1][j] + B[k][2] * V[2][j];
+      scale = h2 * 2.0 * mu * vol[t];
+    }
   }
-  const double mu = lmu[t], lam = llam[t];
-  double U[3][3], s[3], V[3][3];
-  svd3(F, U, s, V);
-  NHLocal L;
-  double th[3], W[3][3], qd[3][3], M[3][3], N[3][3];
-  local_projection(model, s, mu, lam, th, W, qd, L);
-  local_MN(th, s, qd, M, N);
-  double BV[4][3];
-#pragma unroll
-  for (int k = 0; k < 4; ++k)
-#pragma unroll
-    for (int j = 0; j < 3; ++j) BV[k][j] = B[k][0] * V[0][j] + B[k][1] * V[1][j] + B[k][2] * V[2][j];
-  const double scale = h2 * 2.0 * mu * vol[t];
-  double* o = out + 90 * (size_t)t;
 #pragma unroll
   for (int pr = 0; pr < 10; ++pr) {
-    const int k = c_pairK[pr], l = c_pairL[pr];
-    double Y[3][3];
+    double o[9];
 #pragma unroll
-    for (int a = 0; a < 3; ++a)
+    for (int e = 0; e < 9; ++e) o[e] = 0.0;
+    if (ok) {
+      const int k = c_pairK[pr], l = c_pairL[pr];
+      double Y[3][3];
 #pragma unroll
-      for (int b = 0; b < 3; ++b) {
-        double y = W[a][b] * BV[k][a] * BV[l][b];
-        if (a == b) {
+      for (int a = 0; a < 3; ++a)
 #pragma unroll
-          for (int j = 0; j < 3; ++j)
-            if (j != a) y += M[a][j] * BV[k][j] * BV[l][j];
-        } else {
-          y += N[a][b] * BV[k][b] * BV[l][a];
+        for (int b = 0; b < 3; ++b) {
+          double y = W[a][b] * BV[k][a] * BV[l][b];
+          if (a == b) {
+#pragma unroll
+            for (int j = 0; j < 3; ++j)
+              if (j != a) y += M[a][j] * BV[k][j] * BV[l][j];
+          } else {
+            y += N[a][b] * BV[k][b] * BV[l][a];
+          }
+          Y[a][b] = y;
         }
-        Y[a][b] = y;
-      }
-    // T = U Y, R = T U^T
-    double T[3][3];
+      // T = U Y, R = T U^T
+      double T[3][3];
 #pragma unroll
-    for (int r = 0; r < 3; ++r)
+      for (int r = 0; r < 3; ++r)
 #pragma unroll
-      for (int b = 0; b < 3; ++b) T[r][b] = U[r][0] * Y[0][b] + U[r][1] * Y[1][b] + U[r][2] * Y[2][b];
-    const double bb = B[k][0] * B[l][0] + B[k][1] * B[l][1] + B[k][2] * B[l][2];
+        for (int b = 0; b < 3; ++b) T[r][b] = U[r][0] * Y[0][b] + U[r][1] * Y[1][b] + U[r][2] * Y[2][b];
+      const double bb = B[k][0] * B[l][0] + B[k][1] * B[l][1] + B[k][2] * B[l][2];
 #pragma unroll
-    for (int r = 0; r < 3; ++r)
+      for (int r = 0; r < 3; ++r)
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        double uyu = T[r][0] * U[c][0] + T[r][1] * U[c][1] + T[r][2] * U[c][2];
-        o[9 * pr + 3 * r + c] = scale * (((r == c) ? bb : 0.0) - uyu);
-      }
+        for (int c = 0; c < 3; ++c) {
+          double uyu = T[r][0] * U[c][0] + T[r][1] * U[c][1] + T[r][2] * U[c][2];
+          o[3 * r + c] = scale * (((r == c) ? bb : 0.0) - uyu);
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < 9; ++e) stage[9 * threadIdx.x + e] = o[e];
+    __syncthreads();
+    double* dst = out + ((size_t)pr * nt + t0) * 9;
+    for (int i = threadIdx.x; i < 9 * nloc; i += blockDim.x) dst[i] = stage[i];
+    __syncthreads();
   }
 }
 
-__global__ void __launch_bounds__(256) k_assemble(int nnzb, const int* __restrict__ slot_ptr,
+__global__ void __launch_bounds__(256) k_assemble(int nnzb, int nt, const int* __restrict__ slot_ptr,
                                                   const int* __restrict__ slot_code,
                                                   const double* __restrict__ tetblk,
                                                   const int* __restrict__ row_of_slot,
@@ -127,7 +144,7 @@ __global__ void __launch_bounds__(256) k_assemble(int nnzb, const int* __restric
   for (int p = p0; p < p1; ++p) {
     const int code = slot_code[p];
     const int t = code >> 5, pr = (code >> 1) & 15, tr = code & 1;
-    acc += tetblk[90 * (size_t)t + 9 * pr + (tr ? et : e)];
+    acc += tetblk[((size_t)pr * nt + t) * 9 + (tr ? et : e)];
   }
   if (r == c) {
     const int row = row_of_slot[sl];
@@ -236,11 +253,12 @@ void launch_tet_blocks(hipStream_t st, int nt, const int* tets, const double* Bt
   k_tet_blocks<<<(nt + 127) / 128, 128, 0, st>>>(nt, tets, Bt, vol, lmu, llam, h2, q, out, err, model);
 }
 
-void launch_assemble(hipStream_t st, int nnzb, const int* slot_ptr, const int* slot_code,
+// tetblk: the pair-major element blocks of k_tet_blocks for nt tets
+void launch_assemble(hipStream_t st, int nnzb, int nt, const int* slot_ptr, const int* slot_code,
                      const double* tetblk, const int* row_of_slot, const int* col, const double* mass,
                      double* val) {
-  k_assemble<<<(unsigned)((9LL * nnzb + 255) / 256), 256, 0, st>>>(nnzb, slot_ptr, slot_code, tetblk, row_of_slot, col,
-                                                  mass, val);
+  k_assemble<<<(unsigned)((9LL * nnzb + 255) / 256), 256, 0, st>>>(nnzb, nt, slot_ptr, slot_code, tetblk,
+                                                                    row_of_slot, col, mass, val);
 }
 
 void launch_vjp_tets(hipStream_t st, int nt, const int* tets, const double* Bt, const double* vol,
