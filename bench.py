@@ -261,6 +261,33 @@ def boxes_leg(n_boxes, nsolve):
         print(f"{len(specs)} boxes {name}: {legs[name]['ms_per_batch']:.1f} ms per batch, "
               f"{legs[name]['value']:.1f} solves/s, max relres {worst:.1e}", file=sys.stderr, flush=True)
     legs["mixed"]["speedup_vs_fp64"] = legs["mixed"]["value"] / legs["fp64"]["value"]
+    # launch shapes: graph replay of the Krylov chunks (captured once per
+    # setup), then the batched autotuner's choice, FP64
+    o = native.solve_opts(rtol=1e-8, maxit=3000, restart=64, prec=native.ADJ_FP64, max_refine=8)
+
+    def timed_fp64():
+        native.batch_setup(batch, states, q, o)
+        native.batch_solve(batch, gq, gv, z, o, raise_noconv=False)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        for _ in range(nsolve):
+            native.batch_setup(batch, states, q, o)
+            native.batch_solve(batch, gq, gv, z, o, raise_noconv=False)
+            native.batch_vjp(batch, z, gv, dq, dv, df, grad)
+        torch.cuda.synchronize()
+        return len(specs) * nsolve / (time.perf_counter() - t2)
+
+    native.batch_set_tuning(batch, chunk=8, graph=1)
+    graph_rate = timed_fp64()
+    native.batch_set_tuning(batch, chunk=8, graph=0)
+    native.batch_setup(batch, states, q, o)
+    best = native.batch_autotune(batch, gq, gv, z, o, reps=2)
+    tuned_rate = timed_fp64()
+    legs["launch_shapes"] = {"fp64_default": {"chunk": 8, "graph": 0, "value": legs["fp64"]["value"]},
+                             "fp64_graph": {"chunk": 8, "graph": 1, "value": graph_rate},
+                             "fp64_autotuned": best | {"value": tuned_rate}, "unit": "adjoint solves/s"}
+    print(f"{len(specs)} boxes fp64: graph replay {graph_rate:.1f} solves/s, autotuned {best} {tuned_rate:.1f}",
+          file=sys.stderr, flush=True)
     batch.close()
     return {"workload": f"batched boxes: the first {len(specs)} of 256 seeded boxes (log-uniform 2k-100k tets), "
                         f"{sum(sp.n_tets for sp in specs)} tets, {sum(sp.n_verts for sp in specs)} vertices, "
@@ -1113,8 +1140,9 @@ def main():
     ap.add_argument("--no-beam", action="store_true", help="skip the beam legs")
     ap.add_argument("--quadruped", type=int, default=0, metavar="STEPS",
                     help="instead of the benchmark: the actuated quadruped rollout and its actuation gradient")
-    ap.add_argument("--boxes", type=int, default=16,
-                    help="boxes of the batched-workload leg (first of the seeded 256; 0: skip)")
+    ap.add_argument("--boxes", type=int, default=256,
+                    help="boxes of the batched-workload leg (first of the seeded 256, all of them by default; "
+                         "0: skip)")
     ap.add_argument("--boxes-only", action="store_true",
                     help="instead of the benchmark: only the batched-workload leg, printed as one JSON line")
     ap.add_argument("--eps-sweep-one", nargs=3, metavar=("TWO_EPS2", "SIDE", "SECONDS"), help=argparse.SUPPRESS)

@@ -458,6 +458,29 @@ adj_status adj_batch_debug_export(const adj_batch* batch, int32_t what, int32_t 
  * adj_batch_destroy), for adj_debug_export and adj_scene_info. */
 adj_status adj_batch_scene(adj_batch* batch, adj_scene** out);
 
+/* Launch shapes of the batched Krylov loop.  chunk: iterations enqueued
+ * between host checks after the first chunk of a cycle (1..64; the first
+ * runs as many as the last solve of the same kind needed); graph: 1 replays
+ * each chunk from a HIP graph captured once per adj_batch_setup on the
+ * batch's private stream (the same kernels, so results are bitwise those of
+ * direct launches).  Defaults: chunk 8, graph 0.  ADJ_E_ARG outside these. */
+typedef struct {
+  int32_t chunk;
+  int32_t graph;
+} adj_batch_tuning;
+adj_status adj_batch_set_tuning(adj_batch* batch, const adj_batch_tuning* t);
+adj_status adj_batch_get_tuning(const adj_batch* batch, adj_batch_tuning* t);
+
+/* Batched autotuner (a9): after adj_batch_setup, times adj_batch_solve with
+ * the right-hand side (dL_dq, dL_dv) for chunk in {2, 4, 8, 16, 32} with
+ * direct launches, then graph replay at the best chunk (each candidate the
+ * best of `reps` timed solves, HIP events on `stream`, chunk graphs
+ * re-captured for every solve as after a fresh setup), keeps the fastest on
+ * the batch and writes it to *best.  z: device scratch [3 * total vertices]
+ * that receives the last solution.  Synchronises the stream. */
+adj_status adj_batch_autotune(adj_batch* batch, const double* dL_dq, const double* dL_dv, double* z,
+                              const adj_solve_opts* opts, int32_t reps, adj_batch_tuning* best, void* stream);
+
 const char* adj_last_error(void);
 
 #ifdef __cplusplus

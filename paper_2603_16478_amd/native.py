@@ -35,7 +35,7 @@ EXPORTS = ("adj_scene_create", "adj_scene_destroy", "adjoint_setup", "adjoint_so
            "adj_set_tuning", "adj_get_tuning", "adj_autotune", "adj_batch_create", "adj_batch_destroy",
            "adj_batch_info", "adj_batch_setup", "adj_batch_solve", "adj_batch_vjp", "adj_batch_check_status",
            "adj_batch_debug_export", "adj_batch_scene", "adj_batch_reverse", "adj_binding_vjp",
-           "adj_last_error")
+           "adj_batch_set_tuning", "adj_batch_get_tuning", "adj_batch_autotune", "adj_last_error")
 KERNELS = {"S": 0, "ST": 1, "capinv": 2, "Z": 3, "correction": 3, "bsr": 4, "tet": 5, "assemble": 6, "gj": 7,
            "gs_pass2": 8, "gs_pass1": 9, "gj_step": 10, "delassus": 11, "lu_tiles": 12}
 
@@ -71,6 +71,13 @@ class SolveInfo(C.Structure):
     _fields_ = [("iters", C.c_int32), ("refine_steps", C.c_int32), ("n_contacts", C.c_int32),
                 ("m_rows", C.c_int32), ("relres", C.c_double), ("delassus_rebuilt", C.c_int32),
                 ("method", C.c_int32)]
+
+
+class BatchTuning(C.Structure):
+    _fields_ = [("chunk", C.c_int32), ("graph", C.c_int32)]
+
+    def as_dict(self):
+        return {"chunk": self.chunk, "graph": self.graph}
 
 
 class Tuning(C.Structure):
@@ -115,6 +122,9 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.adj_set_tuning.argtypes = [vp, C.POINTER(Tuning)]
     lib.adj_get_tuning.argtypes = [vp, C.POINTER(Tuning)]
     lib.adj_autotune.argtypes = [vp, vp, vp, vp, C.POINTER(SolveOpts), C.c_int32, C.POINTER(Tuning), vp]
+    lib.adj_batch_set_tuning.argtypes = [vp, C.POINTER(BatchTuning)]
+    lib.adj_batch_get_tuning.argtypes = [vp, C.POINTER(BatchTuning)]
+    lib.adj_batch_autotune.argtypes = [vp, vp, vp, vp, C.POINTER(SolveOpts), C.c_int32, C.POINTER(BatchTuning), vp]
     lib.adj_batch_create.argtypes = [C.c_int32, C.POINTER(SceneDesc), C.POINTER(C.c_int32), C.POINTER(vp)]
     lib.adj_batch_destroy.argtypes = [vp]
     lib.adj_batch_info.argtypes = [vp, C.POINTER(C.c_int64)]
@@ -503,6 +513,25 @@ def batch_reverse(b0: Batch, b1: Batch, contacts, q, gq, gv, dfext, grad, opts: 
     if st != 0 and (raise_noconv or STATUS.get(st) != "ADJ_E_NOCONV"):
         check(st)
     return [list(infos[t * ns:(t + 1) * ns]) for t in range(T)]
+
+
+def batch_set_tuning(batch: Batch, chunk=8, graph=0):
+    t = BatchTuning(int(chunk), int(graph))
+    check(load().adj_batch_set_tuning(batch.handle, C.byref(t)))
+
+
+def batch_get_tuning(batch: Batch) -> dict:
+    t = BatchTuning()
+    check(load().adj_batch_get_tuning(batch.handle, C.byref(t)))
+    return t.as_dict()
+
+
+def batch_autotune(batch: Batch, dL_dq, dL_dv, z, opts: SolveOpts, reps=2, stream=None) -> dict:
+    """Time candidate chunk sizes and graph replay on the set-up batch and keep the fastest."""
+    t = BatchTuning()
+    check(load().adj_batch_autotune(batch.handle, _ptr(dL_dq), _ptr(dL_dv), _ptr(z), C.byref(opts), int(reps),
+                                    C.byref(t), _stream(stream)))
+    return t.as_dict()
 
 
 def batch_check_status(batch: Batch, stream=None):

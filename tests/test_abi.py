@@ -90,7 +90,8 @@ def test_struct_layouts_agree_with_the_header(tmp_path):
         pytest.skip("no C compiler")
     from paper_2603_16478_amd import native
     mirrors = {"adj_scene_desc": native.SceneDesc, "adj_contact_state": native.ContactState,
-               "adj_solve_opts": native.SolveOpts, "adj_solve_info": native.SolveInfo, "adj_tuning": native.Tuning}
+               "adj_solve_opts": native.SolveOpts, "adj_solve_info": native.SolveInfo, "adj_tuning": native.Tuning,
+               "adj_batch_tuning": native.BatchTuning}
     # fields the binding names differently (a Python keyword in C)
     cfield = {("adj_contact_state", "lam"): "lambda"}
     lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "adjoint.h"', "int main(void) {"]
