@@ -57,7 +57,7 @@ CSRC = os.path.join(ROOT, "paper_2603_16478_amd", "csrc")
 # per kernel, each tagged with a hash of the source it was measured on
 COUNTERS = {"s_product": os.path.join(ROOT, "profiles", "s_product_batched_beam_counters.json"),
             "gj_wide": os.path.join(ROOT, "profiles", "gj_wide_slab_counters.json"),
-            "lu_tiles": os.path.join(ROOT, "profiles", "lu_tiles_slab_counters.json"),
+            "lu_tiles": os.path.join(ROOT, "profiles", "lu_tiles_rest_slab_counters.json"),
             "gj_step": os.path.join(ROOT, "profiles", "gj_step_batched_beam_counters.json"),
             "s_product_single": os.path.join(ROOT, "profiles", "s_product_slab_counters.json")}
 
