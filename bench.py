@@ -78,6 +78,24 @@ def load_states():
     return states
 
 
+def load_onset_states():
+    """The beam's converged oracle states around its slip onsets (written by
+    tests/golden/make_beam_onset.py), in the order of the stored oracle
+    solutions of tests/golden/beam_onset_z.npz."""
+    oz = np.load(os.path.join(ROOT, "tests", "golden", "beam_onset_z.npz"))
+    states = []
+    for mu in (0.1, 0.4):
+        d = np.load(os.path.join(ROOT, "tests", "golden", f"beam_onset_mu{mu}.npz"))
+        for k in range(int(d["steps"])):
+            t = int(d[f"t{k}"])
+            idx = [i for i in range(oz["z"].shape[0]) if oz["mu"][i] == mu and int(oz["t"][i]) == t]
+            if len(idx) != 1:
+                raise SystemExit(f"no stored oracle solution for the beam at mu={mu}, step {t}")
+            states.append({key: d[f"{key}{k}"] for key in ("q", "vid", "fric", "frame", "delta", "lam")} |
+                          {"mu": mu, "t": t, "index": idx[0]})
+    return states
+
+
 def s_product_bytes(info):
     """Algorithmic bytes of one sparse-inverse product y = S x (3 right-hand
     sides): values and column indices of S, row pointers, x and y."""
@@ -917,6 +935,56 @@ def beam_legs(args):
     single = run_single(native.ADJ_FP64)
     single_mixed = run_single(native.ADJ_MIXED)
 
+    # ---- the slip onsets: the converged oracle states around the steps
+    # where the beam starts to slide (mu 0.1, steps 20-25; mu 0.4, steps
+    # 84-89), each solve checked against the oracle's stored z ----
+    onset = load_onset_states()
+    oz = np.load(os.path.join(ROOT, "tests", "golden", "beam_onset_z.npz"))
+    for st in onset:
+        n = int(st["vid"].shape[0])
+        st["dev"] = {"vid": torch.tensor(st["vid"].astype(np.int32), device=dev),
+                     "fric": torch.tensor(st["fric"].astype(np.int32), device=dev),
+                     "frame": torch.tensor(st["frame"].reshape(n, 9), dtype=torch.float64, device=dev),
+                     "delta": torch.tensor(st["delta"], dtype=torch.float64, device=dev),
+                     "lam": torch.tensor(st["lam"], dtype=torch.float64, device=dev),
+                     "q": torch.tensor(st["q"], dtype=torch.float64, device=dev)}
+        t = st["dev"]
+        t["cs"] = native.make_contact_state(n, t["vid"], t["fric"], t["frame"], t["delta"], t["lam"], st["mu"])
+
+    def run_onset(prec):
+        o = native.solve_opts(rtol=args.rtol, maxit=5000, restart=64, prec=prec, max_refine=8)
+        its, errs = [], []
+        for st in onset:  # untimed pass: the error of every solve against the oracle
+            native.adjoint_setup(scene, st["dev"]["cs"], st["dev"]["q"], o)
+            native.adjoint_solve(scene, gq, gv, z, o)
+            torch.cuda.synchronize()
+            errs.append(_rel(z.cpu().numpy(), oz["z"][st["index"]]))
+        torch.cuda.synchronize()
+        t0s = time.perf_counter()
+        nrep = max(1, args.steps // len(onset))
+        for _ in range(nrep):
+            for st in onset:
+                native.adjoint_setup(scene, st["dev"]["cs"], st["dev"]["q"], o)
+                inf = native.adjoint_solve(scene, gq, gv, z, o)
+                native.vjp_params(scene, z, gv, dqbar, dvbar, dfext, grad3)
+                its.append(inf.iters)
+        torch.cuda.synchronize()
+        dts = time.perf_counter() - t0s
+        nsolve = nrep * len(onset)
+        return {"value": nsolve / dts, "unit": "adjoint solves/s", "ms_per_step": 1e3 * dts / nsolve,
+                "krylov_iters_mean": float(np.mean(its)), "z_rel_err_vs_oracle_max": float(max(errs))}
+
+    onset_fp64 = run_onset(native.ADJ_FP64)
+    onset_mixed = run_onset(native.ADJ_MIXED)
+    slip_onset = {"steps": [f"mu={st['mu']} t={st['t']}" for st in onset], "fp64": onset_fp64,
+                  "mixed": onset_mixed | {"speedup_vs_fp64": onset_mixed["value"] / onset_fp64["value"]},
+                  "note": "single scene, the oracle's converged states around the slip onsets "
+                          "(tests/golden/beam_onset_mu*.npz), g_q = r, g_v = 0; z error against the oracle's "
+                          "stored solutions (tests/golden/beam_onset_z.npz)"}
+    print(f"slip onset: FP64 {onset_fp64['value']:.0f} solves/s (z err {onset_fp64['z_rel_err_vs_oracle_max']:.1e}), "
+          f"mixed {onset_mixed['value']:.0f} (z err {onset_mixed['z_rel_err_vs_oracle_max']:.1e})",
+          file=sys.stderr, flush=True)
+
     # ---- backward-solver comparison: the same solves with the comparison
     # preconditioners (sparse inverse S^T S alone, block Jacobi), 2000
     # iterations at most; the setup skips the Woodbury factors for them ----
@@ -1096,6 +1164,7 @@ def beam_legs(args):
                              "fp64": bfp64, "mixed": bmixed | {"speedup_vs_fp64": bmixed["value"] / bfp64["value"]}},
         "single_scene": {"fp64": single, "mixed": single_mixed,
                          "batched_speedup_fp64": bfp64["value"] / single["value"]},
+        "slip_onset": slip_onset,
         "preconditioners": precond_cmp | {"note": "single scene, FP64, one solve per recorded scene-step, "
                                                   "GMRES(64) to 1e-8 or 2000 iterations; semi_implicit: the "
                                                   "fixed-point iteration x <- x + A^-1 (b - Acal^T x), stopped "

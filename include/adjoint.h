@@ -349,7 +349,7 @@ adj_status adj_profile_end(adj_scene* scene, double* total_ms, int64_t* launches
  * over the GPU and the order of floating-point sums inside reductions (so
  * results are bitwise reproducible for a fixed tuning, and agree across
  * tunings to rounding).  Defaults: gs_rows 64, bsr_lanes 16, chunk 8,
- * graph 0, gj_wide_min 2048, a_inv 0, lu_min 4608. */
+ * graph 0, gj_wide_min 2048, a_inv 0, lu_min 4608, lu_pipe 1. */
 typedef struct {
   int32_t gs_rows;   /* rows per 256-thread block of the Gram-Schmidt kernels: 64, 128, 256 */
   int32_t bsr_lanes; /* lanes per block row of the Acal^T product: 4, 8, 16, 32 */
@@ -365,6 +365,9 @@ typedef struct {
                         is factored by block LU (2/3 mp^3 on the matrix cores; each apply two block
                         substitutions) instead of inverted explicitly (2 mp^3; each apply one dense
                         product); default 4608 */
+  int32_t lu_pipe;   /* 1: the block-LU substitutions run pipelined, one launch per pass (stripes of 16
+                        rows that wait for the values they need, published once each by atomic stores);
+                        0: one launch per group of four 128-blocks; default 1 */
 } adj_tuning;
 
 /* Set or read the scene's launch shapes.  ADJ_E_ARG on a value outside the

@@ -76,6 +76,10 @@ void launch_wb_gather(hipStream_t, int, int, const int*, const int*, const int*,
                       const double*, const double*, const GmresState*, double*);
 void launch_wb_lu(hipStream_t, int, int, const int*, const int*, const int*, const double*, const double*,
                   const double*, int, const double*, const GmresState*, double*, double*);
+void launch_wb_lu_pipe(hipStream_t, int, int, const int*, const int*, const int*, const double*, const double*,
+                       const double*, const double*, const GmresState*, double*, double*, double*, double*, unsigned*,
+                       int*);
+void launch_lu_pipe_init(hipStream_t, int, double*, double*, unsigned*);
 void launch_lu_groups(hipStream_t, int, double*);
 int lu_group_blocks();
 void launch_wb_correct(hipStream_t, int, int, const int*, const int*, const int*, const double*,
@@ -86,9 +90,9 @@ int gm_blocks(long long, int);
 int bsr_blocks(int, int);
 int vec_blocks(long long);
 void launch_bsr_dots(hipStream_t, int, int, const int*, const int*, const double*, long long, const double*, double*,
-                     long long, const GmresState*, int, double*);
+                     long long, const GmresState*, int, double*, double* Zb = nullptr);
 void launch_bsr_dots(hipStream_t, int, int, const int*, const int*, const float*, const double*, long long,
-                     const double*, double*, long long, const GmresState*, int, double*);
+                     const double*, double*, long long, const GmresState*, int, double*, double* Zb = nullptr);
 void launch_fold_partials(hipStream_t, double*, int, const GmresState*, int);
 double* launch_gj_wide(hipStream_t, int, double*, double*, double*, double*, int*);
 void launch_lu_pivot0(hipStream_t, int, double*, double*, int*);
@@ -176,7 +180,7 @@ hipError_t upload(T** p, const std::vector<T>& v) {
 
 struct adj_scene {
   HostScene hs;
-  adj_tuning tune{64, 16, 8, 0, 2048, 0, 4608};
+  adj_tuning tune{64, 16, 8, 0, 2048, 0, 4608, 1};
   int nv = 0, nt = 0, nnzb = 0, max_contacts = 0;
   int material = 0;  // adj_material of the local projection
   int nb = 0;  // bilateral bindings: vertex ids and compliances on the device
@@ -218,6 +222,10 @@ struct adj_scene {
   // blocks; with cap_lu set, d_X holds the factors instead of the inverse
   double *d_lu_P = nullptr, *d_lu_y = nullptr;  // pivot inverses; the substitutions' second vector
   size_t cap_lu_P = 0, cap_lu_y = 0;
+  // pipelined substitutions: the published values of each pass, two tickets
+  double *d_lu_A0 = nullptr, *d_lu_A1 = nullptr;
+  size_t cap_lu_A0 = 0, cap_lu_A1 = 0;
+  unsigned* d_lu_tick = nullptr;
   bool cap_lu = false;
   int4* d_gj_tiles = nullptr;
   int* d_gj_one = nullptr;        // [0] = scene 0, [1] = padded size
@@ -240,6 +248,7 @@ struct adj_scene {
   bool setup_done = false;
   int delassus_rebuilt = 0;
   // Krylov workspace
+  double* d_Zk = nullptr;  // flexible basis: the preconditioned vectors M^-1 v_j, [R][n3]
   double *d_Vt = nullptr, *d_scale = nullptr, *d_H = nullptr, *d_cs = nullptr, *d_sn = nullptr,
          *d_g = nullptr, *d_hbuf = nullptr, *d_coef = nullptr, *d_partial = nullptr;
   size_t preg = 0;  // doubles per partial-sum region (three regions in d_partial)
@@ -359,7 +368,7 @@ static void free_scene(adj_scene* s) {
                   s->d_kh,       s->d_Kc,     s->d_kmu,   s->d_row_c,       s->d_row_i,
                   s->d_cmap,     s->d_c_row0, s->d_c_nrow, s->d_cv,         s->d_cv_ptr,
                   s->d_Y,        s->d_D,      s->d_Z,     s->d_C,           s->d_P,
-                  s->d_colbuf,   s->d_tvec,   s->d_Vt,    s->d_scale,       s->d_H,
+                  s->d_colbuf,   s->d_tvec,   s->d_Vt,    s->d_Zk,  s->d_scale,       s->d_H,
                   s->d_cs,       s->d_sn,     s->d_g,     s->d_hbuf,        s->d_coef,
                   s->d_partial,  s->d_counter, s->d_state, s->d_t1,         s->d_u,
                   s->d_y,        s->d_r,      s->d_b,     s->d_dz,          s->d_xt,
@@ -371,7 +380,7 @@ static void free_scene(adj_scene* s) {
                   s->d_rhs,      s->d_cvec,   s->d_cu,    s->d_norms,       s->d_Sx32,
                   s->d_STx32,    s->d_val32,  s->d_valT,  s->d_Pws,   s->d_x_pcg, s->d_bvid, s->d_bE,
                   s->d_Yp,       s->d_Ysrc,   s->d_Ycol,  s->d_Ytasks,      s->d_CTtasks, s->d_Yval,
-                  s->d_gjw_P,    s->d_gjw_W,  s->d_lu_P,  s->d_lu_y,
+                  s->d_gjw_P,    s->d_gjw_W,  s->d_lu_P,  s->d_lu_y, s->d_lu_A0, s->d_lu_A1, s->d_lu_tick,
                   s->d_Fp, s->d_Bp, s->d_Ip, s->d_ITp, s->d_Fj, s->d_Bj, s->d_Ij, s->d_ITj, s->d_perm,
                   s->d_Fx, s->d_Bx, s->d_Ix, s->d_ITx, s->d_lt, s->d_lz, s->d_Fx32, s->d_Bx32, s->d_Ix32, s->d_ITx32,
                   s->d_fA, s->d_fB, s->d_bA, s->d_bB, s->d_ybm};
@@ -534,6 +543,7 @@ static adj_status scene_create(const adj_scene_desc* desc, int32_t max_contacts,
   ok &= dalloc(&s->d_tvec, (3 * mc + 127) / 128 * 128) == hipSuccess;  // padded: block-LU substitutions
   ok &= dalloc(&s->d_P, 32 * 32) == hipSuccess;
   ok &= dalloc(&s->d_Vt, (R + 1) * (size_t)s->n3) == hipSuccess;
+  ok &= dalloc(&s->d_Zk, R * (size_t)s->n3) == hipSuccess;
   ok &= dalloc(&s->d_scale, R + 2) == hipSuccess;
   ok &= dalloc(&s->d_H, (R + 1) * R) == hipSuccess;
   ok &= dalloc(&s->d_cs, R + 1) == hipSuccess;
@@ -836,6 +846,9 @@ static adj_status build_capacitance(adj_scene* s, hipStream_t st, double mu, int
   if (lu) {
     if ((a = grow(&s->d_lu_P, &s->cap_lu_P, (size_t)mp * 128)) != ADJ_OK) return a;
     if ((a = grow(&s->d_lu_y, &s->cap_lu_y, (size_t)mp)) != ADJ_OK) return a;
+    if ((a = grow(&s->d_lu_A0, &s->cap_lu_A0, (size_t)mp)) != ADJ_OK) return a;
+    if ((a = grow(&s->d_lu_A1, &s->cap_lu_A1, (size_t)mp)) != ADJ_OK) return a;
+    if (!s->d_lu_tick && dalloc(&s->d_lu_tick, 2) != hipSuccess) return fail(ADJ_E_OOM, "hipMalloc failed");
     ProfScope p(s, 7, st);
     launch_gj_pad(st, m, mp, s->d_C);
     if (!s->lu_stream && hipStreamCreateWithFlags(&s->lu_stream, hipStreamNonBlocking) != hipSuccess)
@@ -867,6 +880,7 @@ static adj_status build_capacitance(adj_scene* s, hipStream_t st, double mu, int
     s->d_X = s->d_C;
     // the substitutions run over all mp rows: the padding rows of t stay zero
     launch_fill_zero(st, (size_t)(mp - m), s->d_tvec + m);
+    launch_lu_pipe_init(st, mp, s->d_lu_A0, s->d_lu_A1, s->d_lu_tick);
     return ADJ_OK;
   }
   if (wide) {
@@ -954,6 +968,7 @@ extern "C" adj_status adjoint_setup(adj_scene* s, const adj_contact_state* cst, 
   // a1 + a2: per-tet Jacobians, gather assembly of Acal^T; the device error
   // flag (inverted element, singular capacitance pivot) starts clear
   launch_fill_int(st, 1, s->d_err, 0);
+  launch_fill_int(st, 1, s->d_err + 2, 0);
   {
     ProfScope p(s, 5, st);
     launch_tet_blocks(st, s->nt, s->d_tets, s->d_Bt, s->d_vol, s->d_lmu, s->d_llam, h2, q, s->d_tetblk,
@@ -1001,6 +1016,7 @@ extern "C" adj_status adj_check_status(adj_scene* s, void* stream) {
   HIPCHK(hipStreamSynchronize(st));
   if (err[0] == 1) return fail(ADJ_E_INVERTED, "a tet has det F <= 0");
   if (err[0] == 2) return fail(ADJ_E_SINGULAR, "capacitance block pivot is zero or not finite");
+  if (err[2]) return fail(ADJ_E_DEVICE, "a pipelined capacitance substitution waited past its limit");
   return ADJ_OK;
 }
 
@@ -1011,7 +1027,10 @@ extern "C" adj_status adj_check_status(adj_scene* s, void* stream) {
 // t = X Hq u: the capacitance solve of the Woodbury correction, with the
 // explicit inverse X or with the block-LU factors (cap_lu).
 static void cap_apply(adj_scene* s, hipStream_t st, const double* u, const GmresState* state, double* t) {
-  if (s->cap_lu)
+  if (s->cap_lu && s->tune.lu_pipe && lu_group_blocks() == 4)
+    launch_wb_lu_pipe(st, s->m, s->mp, s->d_row_c, s->d_row_i, s->cur_vid, s->d_Q, s->d_X, s->d_lu_P, u, state, t,
+                      s->d_lu_y, s->d_lu_A0, s->d_lu_A1, s->d_lu_tick, s->d_err);
+  else if (s->cap_lu)
     launch_wb_lu(st, s->m, s->mp, s->d_row_c, s->d_row_i, s->cur_vid, s->d_Q, s->d_X, s->d_lu_P, lu_group_blocks(), u,
                  state, t, s->d_lu_y);
   else
@@ -1183,10 +1202,10 @@ static void gmres_chunk(adj_scene* s, hipStream_t st, bool f32, int n) {
       ProfScope p(s, 4, st);
       if (f32)
         launch_bsr_dots(st, s->tune.bsr_lanes, s->nv, s->d_rowptr, s->d_col, s->d_val32, s->d_valT, s->nnzb, s->d_y, s->d_Vt, stride,
-                        s->d_state, -1, s->P1());
+                        s->d_state, -1, s->P1(), s->d_Zk);
       else
         launch_bsr_dots(st, s->tune.bsr_lanes, s->nv, s->d_rowptr, s->d_col, s->d_valT, s->nnzb, s->d_y, s->d_Vt, stride,
-                        s->d_state, -1, s->P1());
+                        s->d_state, -1, s->P1(), s->d_Zk);
     }
     if (nb1_raw > kFoldAt) launch_fold_partials(st, s->P1(), nb1_raw, s->d_state, 0);
     {
@@ -1268,7 +1287,7 @@ static hipError_t run_chunk(adj_scene* s, hipStream_t st, int kind, bool f32, in
 // contacts folded) with the current Woodbury preconditioner: x = A^{-1} b.
 static adj_status gmres_solve(adj_scene* s, hipStream_t st, const double* b, double* x, double rtol,
                               int maxit, int R, int* iters_out, double* relres_out, bool* converged_out,
-                              bool f32 = false) {
+                              bool f32 = false, bool verify = true) {
   const long long n3 = s->n3;
   const long long stride = n3;
   if (b != s->d_b) HIPCHK(hipMemcpyAsync(s->d_b, b, n3 * sizeof(double), hipMemcpyDeviceToDevice, st));
@@ -1324,9 +1343,17 @@ static adj_status gmres_solve(adj_scene* s, hipStream_t st, const double* b, dou
       n = predicted(res);
     }
     total += done_in_cycle;
-    launch_gm_finish(st, n3, s->d_state, s->d_H, s->d_g, s->d_scale, s->d_Vt, stride, s->d_coef, s->d_xt);
-    apply_precond(s, st, s->d_xt, 0, nullptr, nullptr, s->d_dz, f32);
+    // flexible GMRES: x += Zk y with the stored preconditioned vectors
+    // Zk_j = M^-1 v_j (no further preconditioner application)
+    launch_gm_finish(st, n3, s->d_state, s->d_H, s->d_g, nullptr, s->d_Zk, stride, s->d_coef, s->d_dz);
     launch_axpy(st, n3, 1.0, s->d_dz, x);
+    if (!verify && s->h_state->res <= tol) {
+      // an inner solve of the refinement: the caller forms the true
+      // residual itself, so the recurrence's estimate ends the solve
+      relres = (bnorm > 0) ? s->h_state->res / bnorm : 0.0;
+      converged = true;
+      break;
+    }
     bsr(s, st, x, s->d_r, 0, nullptr, f32);
     launch_residual(st, n3, s->d_b, s->d_r, s->d_Vt, s->P3(), s->d_state, s->d_scale,
                     s->d_g);
@@ -1455,9 +1482,10 @@ static adj_status semi_implicit_solve(adj_scene* s, hipStream_t st, const double
 }
 
 static adj_status krylov_solve(adj_scene* s, hipStream_t st, bool use_pcg, const double* b, double* x,
-                               double rtol, int maxit, int R, int* iters, double* relres, bool* conv, bool f32) {
+                               double rtol, int maxit, int R, int* iters, double* relres, bool* conv, bool f32,
+                               bool verify = true) {
   if (use_pcg) return pcg_solve(s, st, b, x, rtol, maxit, iters, relres, conv, f32);
-  return gmres_solve(s, st, b, x, rtol, maxit, R, iters, relres, conv, f32);
+  return gmres_solve(s, st, b, x, rtol, maxit, R, iters, relres, conv, f32, verify);
 }
 
 static adj_status adjoint_solve_impl(adj_scene* s, const double* dL_dq, const double* dL_dv, double* z,
@@ -1542,7 +1570,7 @@ static adj_status adjoint_solve_impl(adj_scene* s, const double* dL_dq, const do
       double rr = 0.0;
       bool cv = false;
       if ((a = krylov_solve(s, st, use_pcg, s->d_fu, s->d_du, inner, opts->maxit - total, opts->restart, &it,
-                            &rr, &cv, f32)) != ADJ_OK)
+                            &rr, &cv, f32, false)) != ADJ_OK)
         return a;
       total += it;
       const double r_before = rnorm;
@@ -1694,7 +1722,7 @@ static bool valid_tuning(const adj_tuning& t) {
   const bool ln = t.bsr_lanes == 4 || t.bsr_lanes == 8 || t.bsr_lanes == 16 || t.bsr_lanes == 32;
   const bool gw = t.gj_wide_min >= 128 && t.gj_wide_min % 128 == 0;
   const bool ai = t.a_inv >= 0 && t.a_inv <= 2;
-  const bool lu = t.lu_min >= 128 && t.lu_min % 128 == 0;
+  const bool lu = t.lu_min >= 128 && t.lu_min % 128 == 0 && (t.lu_pipe == 0 || t.lu_pipe == 1);
   return gs && ln && gw && ai && lu && t.chunk >= 1 && t.chunk <= 64 && (t.graph == 0 || t.graph == 1);
 }
 

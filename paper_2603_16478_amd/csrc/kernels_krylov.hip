@@ -277,14 +277,16 @@ constexpr int kLd = 130;  // partials of one block: [0 .. 129], basis index i
 // w = Acal^T y fused with the first Gram-Schmidt pass: the block writes its
 // rows of w = Vt_{j+1} and the partial dots Vt_i . w over those rows
 // (i <= j) to P[blockIdx.x * kLd + i].  jfix >= 0 overrides j (PCG: w =
-// Acal^T p with p = Vt_0, w = Vt_1, partial p . w).
+// Acal^T p with p = Vt_0, w = Vt_1, partial p . w).  With Zb given, the
+// block also stores its rows of y (the preconditioned basis vector) as
+// Zb_j, the flexible-GMRES basis the solution is formed from.
 template <class MT, int LANES>
 __global__ void __launch_bounds__(256) k_bsr_dots(int nv, const int* __restrict__ rowptr,
                                                   const int* __restrict__ col, const MT* __restrict__ val,
                                                   const double* __restrict__ val64, long long soa,
                                                   const double* __restrict__ y, double* __restrict__ Vt,
                                                   long long stride, const GmresState* __restrict__ st, int jfix,
-                                                  double* __restrict__ P) {
+                                                  double* __restrict__ P, double* __restrict__ Zb) {
   if (st->active == 0) return;
   constexpr int R = 256 / LANES;  // rows per block
   __shared__ double wl[3 * R];
@@ -315,6 +317,11 @@ __global__ void __launch_bounds__(256) k_bsr_dots(int nv, const int* __restrict_
       w[3 * row + 1] = a1;
       w[3 * row + 2] = a2;
     }
+  }
+  if (Zb) {
+    const long long e0 = 3LL * row0, ne = 3LL * min(R, nv - row0);
+    double* zj = Zb + (long long)j * stride;
+    for (long long e = threadIdx.x; e < ne; e += 256) zj[e0 + e] = y[e0 + e];
   }
   __syncthreads();
   const int lane = threadIdx.x & 63, wid = threadIdx.x / 64;
@@ -423,7 +430,8 @@ __global__ void __launch_bounds__(256) k_gm_givens(GmresState* __restrict__ st, 
 }
 
 // y_i = scale_i * (H^{-1} g)_i for the completed iterations (upper
-// triangular), by column-oriented back substitution in one wavefront:
+// triangular; scale null: y_i = (H^{-1} g)_i, the coefficients of the
+// flexible basis), by column-oriented back substitution in one wavefront:
 // step l divides y_l, then every lane i < l subtracts H[i][l] y_l (column l
 // of the column-major H is contiguous, so the reads coalesce).
 __global__ void __launch_bounds__(64) k_gm_solve_small(const GmresState* __restrict__ st,
@@ -444,7 +452,7 @@ __global__ void __launch_bounds__(64) k_gm_solve_small(const GmresState* __restr
     if (t == 0) y[l] = yl;
     __syncthreads();
   }
-  for (int i = t; i < k; i += 64) coef[i] = y[i] * scale[i];
+  for (int i = t; i < k; i += 64) coef[i] = scale ? y[i] * scale[i] : y[i];
   if (t == 0) coef[128] = (double)k;
 }
 
@@ -841,6 +849,160 @@ void launch_wb_lu(hipStream_t s, int m, int mp, const int* row_c, const int* row
   }
 }
 
+// Pipelined substitutions: the same forward pass, P_k step and backward
+// pass in two launches instead of one launch per group.  The rows are cut
+// into stripes of 16 (one block each, 16 lanes per row); a stripe computes
+// the final value of each of its rows in the left-looking form
+//   fwd:  a_r = t_r - sum_{c < c0(G)} F[r][c] a_c,   y_r = a_r + sum_{c0 <= c < rb} F[r][c] a_c,
+//   bwd:  a_r = (P y)_r - sum_{c >= c1(G)} F[r][c] a_c,   t_r = a_r + sum_{rb+128 <= c < c1} F[r][c] a_c,
+// (G the row's group [c0, c1), rb its 128-block), i.e. the group steps'
+// updates gathered per row, so each row reads its own part of F once.
+// Every a_r is published once, by an agent-scope atomic store, into a
+// buffer whose entries start as kLuPending (a signalling-NaN pattern that
+// arithmetic never produces); a stripe polls the entries it needs until
+// they are no longer pending.  The value is its own flag, so no fence is
+// needed.  Blocks take their stripe from a ticket counter in the order the
+// dependencies run (fwd: top stripe first; bwd: bottom first), so a stripe
+// only waits for stripes with smaller tickets, which blocks already running
+// hold: every wait ends.  A wait still pending after kLuSpin polls (not
+// possible unless the buffers were not reset) raises err[2] and stops all
+// waits.  Each pass resets the other pass's buffer and ticket for the next
+// launch (stream order separates them).
+constexpr unsigned long long kLuPending = 0x7FF4C0DE0000A11FULL;
+constexpr int kLuSpin = 1 << 18;
+constexpr int kLuGW = 512;  // group width of the pipelined passes (4 blocks of 128)
+
+__device__ __forceinline__ double lu_poll(double* p, int* err) {
+  unsigned long long* q = reinterpret_cast<unsigned long long*>(p);
+  unsigned long long v = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  for (int n = 1; v == kLuPending; ++n) {
+    if ((n & 1023) == 0 && (n >= kLuSpin || __hip_atomic_load(err + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
+      __hip_atomic_store(err + 2, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      break;
+    }
+    __builtin_amdgcn_s_sleep(2);
+    v = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  return __longlong_as_double((long long)v);
+}
+
+__device__ __forceinline__ void lu_publish(double* p, double v) {
+  __hip_atomic_store(reinterpret_cast<unsigned long long*>(p), (unsigned long long)__double_as_longlong(v),
+                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ double lu_pending() { return __longlong_as_double((long long)kLuPending); }
+
+// a . F[row][h0 .. h0 + w) for the 16 lanes of a row (lane l: columns
+// h0 + 2 l + 32 u), with a[h0 .. h0 + w) polled into ag; w <= kLuGW, a
+// multiple of 32.  The row's loads are issued before the wait.
+__device__ __forceinline__ double lu_pipe_dot(const double2* __restrict__ f, int h0, int w, double* A, double* ag,
+                                              int l, int* err) {
+  double2 fv[kLuGW / 32];
+#pragma unroll
+  for (int u = 0; u < kLuGW / 32; ++u)
+    if (32 * u < w) fv[u] = f[(h0 + 2 * l + 32 * u) >> 1];
+  for (int c = threadIdx.x; c < w; c += 256) ag[c] = lu_poll(A + h0 + c, err);
+  __syncthreads();
+  double acc = 0.0;
+#pragma unroll
+  for (int u = 0; u < kLuGW / 32; ++u)
+    if (32 * u < w) {
+      acc = fma(fv[u].x, ag[2 * l + 32 * u], acc);
+      acc = fma(fv[u].y, ag[2 * l + 32 * u + 1], acc);
+    }
+  __syncthreads();
+  return acc;
+}
+
+__global__ void __launch_bounds__(256) k_lu_fwd_pipe(int mp, const double* __restrict__ F,
+                                                     const GmresState* __restrict__ st, const double* __restrict__ t,
+                                                     double* A, double* __restrict__ y, double* Anext,
+                                                     unsigned* tick, int* err) {
+  if (gm_inactive(st)) return;
+  __shared__ double ag[kLuGW];
+  __shared__ int s_sp;
+  if (threadIdx.x == 0) s_sp = (int)atomicAdd(&tick[0], 1u);
+  __syncthreads();
+  const int sp = s_sp, r0 = 16 * sp;
+  if (sp == 0 && threadIdx.x == 0) __hip_atomic_store(&tick[1], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const int row = r0 + (threadIdx.x >> 4), l = threadIdx.x & 15;
+  if (l == 0) lu_publish(Anext + row, lu_pending());
+  const int c0 = (r0 / kLuGW) * kLuGW, rb = r0 & ~127;
+  const double2* f = reinterpret_cast<const double2*>(F + (size_t)row * mp);
+  double acc = 0.0;
+  for (int h0 = 0; h0 < c0; h0 += kLuGW) acc += lu_pipe_dot(f, h0, kLuGW, A, ag, l, err);
+  acc = group_sum<16>(acc);
+  const double a = t[row] - acc;
+  if (l == 0) lu_publish(A + row, a);
+  double acc2 = 0.0;
+  if (rb > c0) acc2 = group_sum<16>(lu_pipe_dot(f, c0, rb - c0, A, ag, l, err));
+  if (l == 0) y[row] = a + acc2;
+}
+
+__global__ void __launch_bounds__(256) k_lu_bwd_pipe(int mp, const double* __restrict__ F,
+                                                     const double* __restrict__ Pall,
+                                                     const GmresState* __restrict__ st, const double* __restrict__ y,
+                                                     double* A, double* __restrict__ t, double* Anext,
+                                                     unsigned* tick, int* err) {
+  if (gm_inactive(st)) return;
+  __shared__ double ag[kLuGW];
+  __shared__ int s_sp;
+  if (threadIdx.x == 0) s_sp = (int)atomicAdd(&tick[1], 1u);
+  __syncthreads();
+  const int sp = s_sp, r0 = mp - 16 * (sp + 1);
+  if (sp == 0 && threadIdx.x == 0) __hip_atomic_store(&tick[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const int row = r0 + (threadIdx.x >> 4), l = threadIdx.x & 15;
+  if (l == 0) lu_publish(Anext + row, lu_pending());
+  const int c0 = (r0 / kLuGW) * kLuGW, c1 = min(c0 + kLuGW, mp), rb = r0 & ~127;
+  // (P y)_row with the row's inverted pivot block
+  const double2* pr = reinterpret_cast<const double2*>(Pall + (size_t)(rb / 128) * 128 * 128 + (size_t)(row - rb) * 128);
+  double p = 0.0;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const double2 v = pr[l + 16 * u];
+    const int c = rb + 2 * (l + 16 * u);
+    p = fma(v.x, y[c], p);
+    p = fma(v.y, y[c + 1], p);
+  }
+  p = group_sum<16>(p);
+  const double2* f = reinterpret_cast<const double2*>(F + (size_t)row * mp);
+  double acc = 0.0;
+  for (int h0 = ((mp - 1) / kLuGW) * kLuGW; h0 >= c1; h0 -= kLuGW)
+    acc += lu_pipe_dot(f, h0, min(kLuGW, mp - h0), A, ag, l, err);
+  acc = group_sum<16>(acc);
+  const double a = p - acc;
+  if (l == 0) lu_publish(A + row, a);
+  double acc2 = 0.0;
+  if (c1 > rb + 128) acc2 = group_sum<16>(lu_pipe_dot(f, rb + 128, c1 - rb - 128, A, ag, l, err));
+  if (l == 0) t[row] = a + acc2;
+}
+
+__global__ void k_lu_pipe_init(int mp, double* __restrict__ A0, double* __restrict__ A1, unsigned* __restrict__ tick) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < mp) {
+    A0[i] = lu_pending();
+    A1[i] = lu_pending();
+  }
+  if (i < 2) tick[i] = 0u;
+}
+
+// Buffers of the pipelined passes to their starting state (both pending,
+// tickets zero): once per setup; each pass then leaves the other's ready.
+void launch_lu_pipe_init(hipStream_t s, int mp, double* A0, double* A1, unsigned* tick) {
+  k_lu_pipe_init<<<(mp + 255) / 256, 256, 0, s>>>(mp, A0, A1, tick);
+}
+
+// The pipelined form of launch_wb_lu (group of four 128-blocks): A0, A1 hold
+// mp doubles each, tick two counters, err[2] the wait flag.
+void launch_wb_lu_pipe(hipStream_t s, int m, int mp, const int* row_c, const int* row_i, const int* vid,
+                       const double* Q, const double* F, const double* P, const double* u, const GmresState* st,
+                       double* t, double* y, double* A0, double* A1, unsigned* tick, int* err) {
+  k_wb_hq<<<(m + 255) / 256, 256, 0, s>>>(m, row_c, row_i, vid, Q, u, st, t);
+  k_lu_fwd_pipe<<<mp / 16, 256, 0, s>>>(mp, F, st, t, A0, y, A1, tick, err);
+  k_lu_bwd_pipe<<<mp / 16, 256, 0, s>>>(mp, F, P, st, y, A1, t, A0, tick, err);
+}
+
 // w[cv_a] = sum over the contacts c at contact vertex a of Q_c^T t_c (H^T t
 // in world coordinates; w is zero elsewhere).  One thread per contact vertex.
 __global__ void k_scatter_ht(int ncv, const int* __restrict__ cv, const int* __restrict__ cv_ptr,
@@ -904,19 +1066,28 @@ void launch_bsr_spmv(hipStream_t s, int lanes, int nv, const int* rowptr, const 
 
 // Entry-major copies of the block values (the Krylov products' layout):
 // soa[k nnzb + p] = aos[9 p + k], and the same rounded to FP32 into soa32
-// when it is given.
-__global__ void k_bsr_soa(long long nnzb, const double* __restrict__ aos, double* __restrict__ soa,
-                          float* __restrict__ soa32) {
-  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= 9 * nnzb) return;
-  const long long k = e / nnzb, p = e - k * nnzb;
-  const double v = aos[9 * p + k];
-  soa[e] = v;
-  if (soa32) soa32[e] = (float)v;
+// when it is given.  A block transposes 256 consecutive blocks through LDS:
+// it reads their 2304 contiguous values and writes nine contiguous runs of
+// 256, so both sides coalesce.
+__global__ void __launch_bounds__(256) k_bsr_soa(long long nnzb, const double* __restrict__ aos,
+                                                 double* __restrict__ soa, float* __restrict__ soa32) {
+  __shared__ double tile[9 * 256];
+  const long long p0 = (long long)blockIdx.x * 256;
+  const int nloc = (int)min(256LL, nnzb - p0);
+  const double* src = aos + 9 * p0;
+  for (int i = threadIdx.x; i < 9 * nloc; i += 256) tile[i] = src[i];
+  __syncthreads();
+  if ((int)threadIdx.x >= nloc) return;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    const double v = tile[9 * threadIdx.x + k];
+    soa[k * nnzb + p0 + threadIdx.x] = v;
+    if (soa32) soa32[k * nnzb + p0 + threadIdx.x] = (float)v;
+  }
 }
 void launch_bsr_soa(hipStream_t s, long long nnzb, const double* aos, double* soa, float* soa32) {
   if (nnzb <= 0) return;
-  k_bsr_soa<<<(unsigned)((9 * nnzb + 255) / 256), 256, 0, s>>>(nnzb, aos, soa, soa32);
+  k_bsr_soa<<<(unsigned)((nnzb + 255) / 256), 256, 0, s>>>(nnzb, aos, soa, soa32);
 }
 
 __global__ void k_to_f32(long long n, const double* __restrict__ a, float* __restrict__ out) {
@@ -955,24 +1126,24 @@ int bsr_blocks(int nv, int lanes) { return (nv + 256 / lanes - 1) / (256 / lanes
 template <class MT>
 static void bsr_dots_impl(hipStream_t s, int lanes, int nv, const int* rowptr, const int* col, const MT* val,
                           const double* val64, long long soa, const double* y, double* Vt, long long stride,
-                          const GmresState* st, int jfix, double* P) {
+                          const GmresState* st, int jfix, double* P, double* Zb) {
   const unsigned g = (unsigned)bsr_blocks(nv, lanes);
   switch (lanes) {
-    case 4: k_bsr_dots<MT, 4><<<g, 256, 0, s>>>(nv, rowptr, col, val, val64, soa, y, Vt, stride, st, jfix, P); break;
-    case 8: k_bsr_dots<MT, 8><<<g, 256, 0, s>>>(nv, rowptr, col, val, val64, soa, y, Vt, stride, st, jfix, P); break;
-    case 32: k_bsr_dots<MT, 32><<<g, 256, 0, s>>>(nv, rowptr, col, val, val64, soa, y, Vt, stride, st, jfix, P); break;
-    default: k_bsr_dots<MT, 16><<<g, 256, 0, s>>>(nv, rowptr, col, val, val64, soa, y, Vt, stride, st, jfix, P); break;
+    case 4: k_bsr_dots<MT, 4><<<g, 256, 0, s>>>(nv, rowptr, col, val, val64, soa, y, Vt, stride, st, jfix, P, Zb); break;
+    case 8: k_bsr_dots<MT, 8><<<g, 256, 0, s>>>(nv, rowptr, col, val, val64, soa, y, Vt, stride, st, jfix, P, Zb); break;
+    case 32: k_bsr_dots<MT, 32><<<g, 256, 0, s>>>(nv, rowptr, col, val, val64, soa, y, Vt, stride, st, jfix, P, Zb); break;
+    default: k_bsr_dots<MT, 16><<<g, 256, 0, s>>>(nv, rowptr, col, val, val64, soa, y, Vt, stride, st, jfix, P, Zb); break;
   }
 }
 void launch_bsr_dots(hipStream_t s, int lanes, int nv, const int* rowptr, const int* col, const double* val,
                      long long soa, const double* y, double* Vt, long long stride, const GmresState* st, int jfix,
-                     double* P) {
-  bsr_dots_impl(s, lanes, nv, rowptr, col, val, (const double*)nullptr, soa, y, Vt, stride, st, jfix, P);
+                     double* P, double* Zb) {
+  bsr_dots_impl(s, lanes, nv, rowptr, col, val, (const double*)nullptr, soa, y, Vt, stride, st, jfix, P, Zb);
 }
 void launch_bsr_dots(hipStream_t s, int lanes, int nv, const int* rowptr, const int* col, const float* val,
                      const double* val64, long long soa, const double* y, double* Vt, long long stride,
-                     const GmresState* st, int jfix, double* P) {
-  bsr_dots_impl(s, lanes, nv, rowptr, col, val, val64, soa, y, Vt, stride, st, jfix, P);
+                     const GmresState* st, int jfix, double* P, double* Zb) {
+  bsr_dots_impl(s, lanes, nv, rowptr, col, val, val64, soa, y, Vt, stride, st, jfix, P, Zb);
 }
 
 void launch_gm_update(hipStream_t s, long long n, int rpb, double* Vt, long long stride, const double* scale,

@@ -8,8 +8,11 @@ only oracle/ and synth/):
   hand side b = r + g_v / h (direct sparse LU with long-double refinement).
 * boxes16_z.npz: the same for the first 16 boxes of the batched workload at
   their seeded deformed states (one z per box, packed).
+* beam_onset_z.npz: z for every converged beam step stored around the slip
+  onsets (beam_onset_mu0.1.npz, beam_onset_mu0.4.npz, written by
+  make_beam_onset.py), for the loss direction alone (g_q = r, g_v = 0).
 
-    python tests/golden/make_oracle_z.py [slab] [boxes]
+    python tests/golden/make_oracle_z.py [slab] [boxes] [onset]
 """
 
 import os
@@ -25,6 +28,7 @@ from oracle import adjoint as adj  # noqa: E402
 from oracle.contact import ContactSet, detect, predict  # noqa: E402
 from oracle.forward import StepRecord  # noqa: E402
 from oracle.rollout import scene_disc  # noqa: E402
+from synth import beam_scene  # noqa: E402
 from synth.configs import (batched_scenes, contact_values, perturbed_state, slab_last_step,  # noqa: E402
                            slab_scene)
 
@@ -90,8 +94,36 @@ def write_boxes():
                         voff=np.cumsum([0] + [z.shape[0] for z in zs]), residual=np.array(res))
 
 
+def onset_cases():
+    """(mu, t, q, record) of every stored slip-onset step, mu 0.1 then 0.4."""
+    out = []
+    for mu in (0.1, 0.4):
+        d = np.load(os.path.join(HERE, f"beam_onset_mu{mu}.npz"))
+        for k in range(int(d["steps"])):
+            cs = ContactSet(d[f"vid{k}"], d[f"collider{k}"], d[f"frame{k}"], d[f"d_n{k}"], d[f"d_f{k}"],
+                            d[f"fric{k}"].astype(bool))
+            out.append((mu, int(d[f"t{k}"]), d[f"q{k}"], StepRecord(cs, d[f"delta{k}"], d[f"lam{k}"], mu)))
+    return out
+
+
+def write_onset():
+    zs, mus, ts, res = [], [], [], []
+    for mu, t, q, rec in onset_cases():
+        spec = beam_scene(mu=mu)
+        z, r = _solve(spec, q, rec, spec.loss_dir, np.zeros_like(q))
+        zs.append(z)
+        mus.append(mu)
+        ts.append(t)
+        res.append(r)
+        print(f"beam mu={mu} step {t}: {rec.contacts.n} contacts, residual {r:.1e}", flush=True)
+    np.savez_compressed(os.path.join(HERE, "beam_onset_z.npz"), z=np.stack(zs), mu=np.array(mus), t=np.array(ts),
+                        residual=np.array(res))
+
+
 if __name__ == "__main__":
-    which = sys.argv[1:] or ["boxes", "slab"]
+    which = sys.argv[1:] or ["boxes", "slab", "onset"]
+    if "onset" in which:
+        write_onset()
     if "boxes" in which:
         write_boxes()
     if "slab" in which:

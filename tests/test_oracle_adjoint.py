@@ -147,3 +147,35 @@ def test_rollout_gradient_matches_fd():
     assert abs(g.dE - dE) <= 1e-5 * abs(dE)
     assert abs(g.dnu - dnu) <= 1e-5 * abs(dnu)
     assert abs(np.sum(g.dv0 * dv) - dv0) <= 1e-4 * abs(dv0)
+
+
+def test_stored_slip_onset_solutions_solve_the_oracle_system():
+    """The stored oracle z of the beam's slip-onset steps (the fixture the
+    GPU parity and the benchmark compare with) solves Acal^T z = r for the
+    oracle's own assembly of the stored states, one step per friction
+    coefficient, and the stored states really cross the onset: the number
+    of contacts at the friction bound grows over the stored steps."""
+    import os
+    from conftest import ROOT
+    from oracle.contact import ContactSet
+    from oracle.forward import StepRecord
+    from synth import beam_scene
+    zd = np.load(os.path.join(ROOT, "tests", "golden", "beam_onset_z.npz"))
+    for mu, k in ((0.1, 2), (0.4, 2)):
+        d = np.load(os.path.join(ROOT, "tests", "golden", f"beam_onset_mu{mu}.npz"))
+        at_bound = []
+        for j in range(int(d["steps"])):
+            lam = d[f"lam{j}"]
+            at_bound.append(int(np.sum(np.hypot(lam[:, 1], lam[:, 2]) > 0.99 * mu * lam[:, 0])))
+        if mu == 0.1:
+            assert at_bound[-2] > at_bound[0] + 40
+        cs = ContactSet(d[f"vid{k}"], d[f"collider{k}"], d[f"frame{k}"], d[f"d_n{k}"], d[f"d_f{k}"],
+                        d[f"fric{k}"].astype(bool))
+        rec = StepRecord(cs, d[f"delta{k}"], d[f"lam{k}"], mu)
+        spec = beam_scene(mu=mu)
+        i = [n for n in range(zd["z"].shape[0]) if zd["mu"][n] == mu and zd["t"][n] == int(d[f"t{k}"])]
+        assert len(i) == 1
+        sysm = adj.assemble(scene_disc(spec), d[f"q{k}"], rec, spec.eps)
+        b = spec.loss_dir.reshape(-1)
+        r = sysm.Acal.T @ zd["z"][i[0]].reshape(-1) - b
+        assert np.linalg.norm(r) <= 1e-9 * np.linalg.norm(b)
