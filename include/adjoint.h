@@ -44,7 +44,13 @@ typedef enum {
   ADJ_E_NOTIMPL = -8
 } adj_status;
 
-typedef enum { ADJ_FP64 = 0, ADJ_MIXED = 1 } adj_precision;
+/* ADJ_MIXED: iterative refinement, FP64 residual b - Acal^T z, inner GMRES
+ * (or PCG) with FP32 block values, FP32 sparse inverse or sweeps and FP64
+ * Woodbury factors.  ADJ_MIXED_PC: one FP64 flexible GMRES whose
+ * preconditioner applies the sparse inverse (or the sweeps) in FP32; the
+ * product, Gram-Schmidt and residual stay FP64 (PCG solves and batches take
+ * it as ADJ_MIXED). */
+typedef enum { ADJ_FP64 = 0, ADJ_MIXED = 1, ADJ_MIXED_PC = 2 } adj_precision;
 
 typedef struct adj_scene adj_scene; /* opaque */
 

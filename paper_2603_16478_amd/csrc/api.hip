@@ -318,7 +318,7 @@ struct adj_scene {
   // two ordering events; default priority
   hipStream_t lu_stream = nullptr;
   hipEvent_t lu_ev[2] = {nullptr, nullptr};
-  hipGraphExec_t chunk_exec[4] = {nullptr, nullptr, nullptr, nullptr};  // [pcg][f32]
+  hipGraphExec_t chunk_exec[8] = {};  // [pcg][FP32 preconditioner][FP32 product]
   // preconditioner of the Krylov solves (adj_precond), set per solve;
   // woodbury_ready: the last setup built the capacitance inverse
   int precond = ADJ_PRECOND_WOODBURY;
@@ -1000,7 +1000,7 @@ extern "C" adj_status adjoint_setup(adj_scene* s, const adj_contact_state* cst, 
   // FP64: in the directions of stiff contacts the correction cancels
   // A^{-1} r almost exactly, so their rounding would be amplified by the
   // contact-to-elastic stiffness ratio.
-  const bool mixed = opts && opts->prec == ADJ_MIXED;
+  const bool mixed = opts && (opts->prec == ADJ_MIXED || opts->prec == ADJ_MIXED_PC);
   launch_bsr_soa(st, s->nnzb, s->d_val, s->d_valT, mixed ? s->d_val32 : nullptr);
   s->mixed_ready = mixed;
   HIPCHK(hipGetLastError());
@@ -1189,7 +1189,8 @@ static void bsr(adj_scene* s, hipStream_t st, const double* x, double* outbase, 
 // block-sparse product fused with the first Gram-Schmidt dots, the two
 // Gram-Schmidt updates (classical Gram-Schmidt applied twice) and the
 // one-block Givens step.
-static void gmres_chunk(adj_scene* s, hipStream_t st, bool f32, int n) {
+// f32: FP32 block values in the product; pc32: FP32 preconditioner.
+static void gmres_chunk(adj_scene* s, hipStream_t st, bool f32, bool pc32, int n) {
   const long long n3 = s->n3, stride = n3;
   // above kFoldAt partial blocks the Gram-Schmidt dots are folded once by a
   // separate launch instead of re-added by every block of the next kernel
@@ -1197,7 +1198,7 @@ static void gmres_chunk(adj_scene* s, hipStream_t st, bool f32, int n) {
   const int nb1_raw = bsr_blocks(s->nv, s->tune.bsr_lanes), nb2_raw = gm_blocks(n3, s->tune.gs_rows);
   const int nb1 = nb1_raw > kFoldAt ? 1 : nb1_raw, nb2 = nb2_raw > kFoldAt ? 1 : nb2_raw;
   for (int k = 0; k < n; ++k) {
-    apply_precond(s, st, s->d_Vt, stride, s->d_scale, s->d_state, s->d_y, f32);
+    apply_precond(s, st, s->d_Vt, stride, s->d_scale, s->d_state, s->d_y, pc32);
     {
       ProfScope p(s, 4, st);
       if (f32)
@@ -1253,22 +1254,22 @@ static void pcg_chunk(adj_scene* s, hipStream_t st, bool f32) {
 // directly (n GMRES iterations), or (tuning.graph = 1, no live profiling)
 // replayed from a graph of tuning.chunk iterations captured on the scene's
 // private stream after the last setup.
-static hipError_t run_chunk(adj_scene* s, hipStream_t st, int kind, bool f32, int n) {
+static hipError_t run_chunk(adj_scene* s, hipStream_t st, int kind, bool f32, int n, bool pc32) {
   if (!s->tune.graph || s->prof_kernel >= 0) {
     if (kind == 0)
-      gmres_chunk(s, st, f32, n);
+      gmres_chunk(s, st, f32, pc32, n);
     else
       pcg_chunk(s, st, f32);
     return hipGetLastError();
   }
-  hipGraphExec_t& ex = s->chunk_exec[2 * kind + (f32 ? 1 : 0)];
+  hipGraphExec_t& ex = s->chunk_exec[4 * kind + (pc32 ? 2 : 0) + (f32 ? 1 : 0)];
   if (!ex) {
     hipError_t e;
     if (!s->cap_stream && (e = hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking)) != hipSuccess)
       return e;
     if ((e = hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal)) != hipSuccess) return e;
     if (kind == 0)
-      gmres_chunk(s, s->cap_stream, f32, s->tune.chunk);
+      gmres_chunk(s, s->cap_stream, f32, pc32, s->tune.chunk);
     else
       pcg_chunk(s, s->cap_stream, f32);
     hipGraph_t g = nullptr;
@@ -1287,7 +1288,8 @@ static hipError_t run_chunk(adj_scene* s, hipStream_t st, int kind, bool f32, in
 // contacts folded) with the current Woodbury preconditioner: x = A^{-1} b.
 static adj_status gmres_solve(adj_scene* s, hipStream_t st, const double* b, double* x, double rtol,
                               int maxit, int R, int* iters_out, double* relres_out, bool* converged_out,
-                              bool f32 = false, bool verify = true) {
+                              bool f32 = false, bool verify = true, bool pc32 = false) {
+  pc32 = pc32 || f32;
   const long long n3 = s->n3;
   const long long stride = n3;
   if (b != s->d_b) HIPCHK(hipMemcpyAsync(s->d_b, b, n3 * sizeof(double), hipMemcpyDeviceToDevice, st));
@@ -1329,7 +1331,7 @@ static adj_status gmres_solve(adj_scene* s, hipStream_t st, const double* b, dou
     double r_prev = r_cycle;
     int j_prev = 0;
     while (true) {
-      HIPCHK(run_chunk(s, st, 0, f32, n));
+      HIPCHK(run_chunk(s, st, 0, f32, n, pc32));
       HIPCHK(hipGetLastError());
       HIPCHK(hipMemcpyAsync(s->h_state, s->d_state, sizeof(GmresState), hipMemcpyDeviceToHost, st));
       HIPCHK(hipStreamSynchronize(st));
@@ -1412,7 +1414,7 @@ static adj_status pcg_solve(adj_scene* s, hipStream_t st, const double* b, doubl
     launch_pcg_p(st, n3, z, p, s->d_state, sc);
     int done = 0;
     while (true) {
-      HIPCHK(run_chunk(s, st, 1, f32, s->tune.chunk));
+      HIPCHK(run_chunk(s, st, 1, f32, s->tune.chunk, f32));
       HIPCHK(hipGetLastError());
       HIPCHK(hipMemcpyAsync(s->h_state, s->d_state, sizeof(GmresState), hipMemcpyDeviceToHost, st));
       HIPCHK(hipStreamSynchronize(st));
@@ -1507,7 +1509,8 @@ static adj_status adjoint_solve_impl(adj_scene* s, const double* dL_dq, const do
   if (!s->setup_done) return fail(ADJ_E_ARG, "adjoint_setup has not run");
   if (!(opts->rtol > 0) || opts->maxit <= 0 || opts->restart < 1 || opts->restart > kMaxRestart)
     return fail(ADJ_E_ARG, "invalid solve options");
-  if (opts->prec != ADJ_FP64 && opts->prec != ADJ_MIXED) return fail(ADJ_E_ARG, "unknown precision");
+  if (opts->prec != ADJ_FP64 && opts->prec != ADJ_MIXED && opts->prec != ADJ_MIXED_PC)
+    return fail(ADJ_E_ARG, "unknown precision");
   if (opts->method != ADJ_AUTO && opts->method != ADJ_GMRES && opts->method != ADJ_PCG &&
       opts->method != ADJ_SEMI_IMPLICIT)
     return fail(ADJ_E_ARG, "unknown Krylov method");
@@ -1527,8 +1530,8 @@ static adj_status adjoint_solve_impl(adj_scene* s, const double* dL_dq, const do
   if (opts->method == ADJ_PCG && !s->symmetric)
     return fail(ADJ_E_ARG, "PCG needs a symmetric system (no frictional contact, or mu = 0)");
   const bool use_pcg = opts->method == ADJ_PCG || (opts->method == ADJ_AUTO && s->symmetric);
-  if (opts->prec == ADJ_MIXED && !s->mixed_ready)
-    return fail(ADJ_E_ARG, "adjoint_setup must run with ADJ_MIXED before a mixed solve");
+  if (opts->prec != ADJ_FP64 && !s->mixed_ready)
+    return fail(ADJ_E_ARG, "adjoint_setup must run with ADJ_MIXED or ADJ_MIXED_PC before a mixed solve");
   hipStream_t st = (hipStream_t)stream;
   const long long n3 = s->n3;
   choose_a_inv(s);
@@ -1546,12 +1549,21 @@ static adj_status adjoint_solve_impl(adj_scene* s, const double* dL_dq, const do
     a = krylov_solve(s, st, use_pcg, s->d_rhs, z, opts->rtol, opts->maxit, opts->restart, &total, &relres,
                      &converged, false);
     if (a != ADJ_OK) return a;
+  } else if (opts->prec == ADJ_MIXED_PC && !use_pcg) {
+    // FP32 preconditioner inside FP64 flexible GMRES: the product, the
+    // Gram-Schmidt and the residual recurrence stay FP64, and the solution
+    // is formed from the stored preconditioned vectors, so the rounding of
+    // the FP32 sparse inverse (or sweeps) changes the iterates, not the
+    // residual that ends the solve (no refinement passes).
+    a = gmres_solve(s, st, s->d_rhs, z, opts->rtol, opts->maxit, opts->restart, &total, &relres, &converged, false,
+                    true, true);
+    if (a != ADJ_OK) return a;
   } else {
     // Iterative refinement.  Mixed: FP64 residual r = b - Acal^T z with the
     // FP64 matrix, inner GMRES with FP32-stored matrices on Acal^T dz = r.
     // FP64 below the FP64 Krylov floor (rtol < kFp64Floor with max_refine >
     // 0): inner FP64 solves to the floor, residual in double-double.
-    const bool f32 = opts->prec == ADJ_MIXED;
+    const bool f32 = opts->prec != ADJ_FP64;  // ADJ_MIXED_PC with PCG: as ADJ_MIXED
     const double floor_inner = f32 ? 1e-6 : kFp64Floor;
     launch_fill_zero(st, (size_t)n3, z);
     HIPCHK(hipMemcpyAsync(s->d_fu, s->d_rhs, n3 * sizeof(double), hipMemcpyDeviceToDevice, st));

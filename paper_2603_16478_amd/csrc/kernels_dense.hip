@@ -1119,7 +1119,15 @@ __global__ void __launch_bounds__(256, 2) k_lu_tiles_rest(int mp, int k0, double
   __shared__ double Ws[kWB][kRestKC + 1];
   __shared__ double Rs[kRestKC][kWB + 1];
   const int base = k0 + kWB, nt = (mp - base) / kWB, nc = nt - 1;
-  const int I0 = base + (blockIdx.x / nc) * kWB, J0 = base + kWB + (blockIdx.x % nc) * kWB;
+  // Tile order for the L2s: blocks go to the eight XCDs round-robin, so the
+  // logical index L gives XCD x one contiguous range of L, and L runs down
+  // groups of eight tile rows column by column, so the tiles an XCD holds at
+  // once share about eight row panels and eight column panels (2 MB of its
+  // 4 MB L2) instead of touching every column panel.
+  const unsigned nb = gridDim.x, q = nb / 8, r = nb % 8, x = blockIdx.x % 8;
+  const int L = (int)(x * q + min(x, r) + blockIdx.x / 8);
+  const int per = 8 * nc, g0 = (L / per) * 8, gh = min(8, nt - g0), w = L % per;
+  const int I0 = base + (g0 + w % gh) * kWB, J0 = base + kWB + (w / gh) * kWB;
   d4 acc[4][4];
   lu_tile<kRestKC>(mp, k0, I0, J0, A, Ws, Rs, acc);
 }

@@ -132,8 +132,13 @@ __global__ void __launch_bounds__(256) k_assemble(int nnzb, int nt, const int* _
                                                   double* __restrict__ val) {
   // nine threads per slot, one per entry: the nine threads of a slot read
   // each element block's 72 contiguous bytes together, and the slots' values
-  // are written contiguously
-  const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  // are written contiguously.  Blocks go to the eight XCDs round-robin, each
+  // with its own L2; the logical block index gives XCD x one contiguous
+  // range of rows, so the element blocks shared by nearby rows (a tet's
+  // blocks feed the rows of its four vertices) are fetched into one L2.
+  const unsigned nb = gridDim.x, q8 = nb / 8, r8 = nb % 8, x8 = blockIdx.x % 8;
+  const unsigned lb = x8 * q8 + min(x8, r8) + blockIdx.x / 8;
+  const long long g = (long long)lb * blockDim.x + threadIdx.x;
   if (g >= 9LL * nnzb) return;
   const int sl = (int)(g / 9), e = (int)(g - 9LL * sl);
   const int r = e / 3, c = e - 3 * r;

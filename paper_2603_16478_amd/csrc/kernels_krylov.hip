@@ -872,9 +872,9 @@ constexpr unsigned long long kLuPending = 0x7FF4C0DE0000A11FULL;
 constexpr int kLuSpin = 1 << 18;
 constexpr int kLuGW = 512;  // group width of the pipelined passes (4 blocks of 128)
 
-__device__ __forceinline__ double lu_poll(double* p, int* err) {
+// Waits until *p is no longer pending; v: a value of *p read earlier.
+__device__ __forceinline__ double lu_poll(double* p, unsigned long long v, int* err) {
   unsigned long long* q = reinterpret_cast<unsigned long long*>(p);
-  unsigned long long v = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   for (int n = 1; v == kLuPending; ++n) {
     if ((n & 1023) == 0 && (n >= kLuSpin || __hip_atomic_load(err + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
       __hip_atomic_store(err + 2, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -886,6 +886,11 @@ __device__ __forceinline__ double lu_poll(double* p, int* err) {
   return __longlong_as_double((long long)v);
 }
 
+__device__ __forceinline__ unsigned long long lu_peek(const double* p) {
+  return __hip_atomic_load(reinterpret_cast<unsigned long long*>(const_cast<double*>(p)), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+}
+
 __device__ __forceinline__ void lu_publish(double* p, double v) {
   __hip_atomic_store(reinterpret_cast<unsigned long long*>(p), (unsigned long long)__double_as_longlong(v),
                      __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -893,29 +898,58 @@ __device__ __forceinline__ void lu_publish(double* p, double v) {
 
 __device__ __forceinline__ double lu_pending() { return __longlong_as_double((long long)kLuPending); }
 
-// a . F[row][h0 .. h0 + w) for the 16 lanes of a row (lane l: columns
-// h0 + 2 l + 32 u), with a[h0 .. h0 + w) polled into ag; w <= kLuGW, a
-// multiple of 32.  The row's loads are issued before the wait.
-__device__ __forceinline__ double lu_pipe_dot(const double2* __restrict__ f, int h0, int w, double* A, double* ag,
-                                              int l, int* err) {
-  double2 fv[kLuGW / 32];
+// sum over the steps i < n of a[h_i .. h_i + w_i) . F[row][h_i .. h_i + w_i)
+// for the 16 lanes of a row (lane l: columns h_i + 2 l + 32 u), with
+// h_i = h + i dir kLuGW and w_i = min(kLuGW, mp - h_i) (a multiple of 32).
+// Step i + 1's row loads and its first reads of a are issued before step
+// i's products, so they are in flight while step i waits and computes.
+__device__ __forceinline__ double lu_pipe_span(const double2* __restrict__ f, int n, int h, int dir, int mp, double* A,
+                                               double* ag, int l, int* err) {
+  double2 cur[kLuGW / 32], nxt[kLuGW / 32];
+  unsigned long long pv[2];
+  auto issue = [&](int i, double2 (&fv)[kLuGW / 32]) {
+    const int h0 = h + i * dir * kLuGW, w = min(kLuGW, mp - h0);
 #pragma unroll
-  for (int u = 0; u < kLuGW / 32; ++u)
-    if (32 * u < w) fv[u] = f[(h0 + 2 * l + 32 * u) >> 1];
-  for (int c = threadIdx.x; c < w; c += 256) ag[c] = lu_poll(A + h0 + c, err);
-  __syncthreads();
-  double acc = 0.0;
+    for (int u = 0; u < kLuGW / 32; ++u)
+      if (32 * u < w) fv[u] = f[(h0 + 2 * l + 32 * u) >> 1];
 #pragma unroll
-  for (int u = 0; u < kLuGW / 32; ++u)
-    if (32 * u < w) {
-      acc = fma(fv[u].x, ag[2 * l + 32 * u], acc);
-      acc = fma(fv[u].y, ag[2 * l + 32 * u + 1], acc);
+    for (int k = 0; k < 2; ++k) {
+      const int c = threadIdx.x + 256 * k;
+      pv[k] = c < w ? lu_peek(A + h0 + c) : 0ull;
     }
-  __syncthreads();
+  };
+  double acc = 0.0;
+  if (n <= 0) return acc;
+  issue(0, cur);
+  for (int i = 0; i < n; ++i) {
+    const int h0 = h + i * dir * kLuGW, w = min(kLuGW, mp - h0);
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const int c = threadIdx.x + 256 * k;
+      if (c < w) ag[c] = lu_poll(A + h0 + c, pv[k], err);
+    }
+    __syncthreads();
+    if (i + 1 < n) issue(i + 1, nxt);
+#pragma unroll
+    for (int u = 0; u < kLuGW / 32; ++u)
+      if (32 * u < w) {
+        acc = fma(cur[u].x, ag[2 * l + 32 * u], acc);
+        acc = fma(cur[u].y, ag[2 * l + 32 * u + 1], acc);
+      }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < kLuGW / 32; ++u) cur[u] = nxt[u];
+  }
   return acc;
 }
 
-__global__ void __launch_bounds__(256) k_lu_fwd_pipe(int mp, const double* __restrict__ F,
+// a[c0 .. c0 + w) . F[row][c0 .. c0 + w) in one step (w <= kLuGW, a multiple of 32)
+__device__ __forceinline__ double lu_pipe_dot(const double2* __restrict__ f, int c0, int w, double* A, double* ag,
+                                              int l, int* err) {
+  return lu_pipe_span(f, 1, c0, 1, c0 + w, A, ag, l, err);
+}
+
+__global__ void __launch_bounds__(256, 3) k_lu_fwd_pipe(int mp, const double* __restrict__ F,
                                                      const GmresState* __restrict__ st, const double* __restrict__ t,
                                                      double* A, double* __restrict__ y, double* Anext,
                                                      unsigned* tick, int* err) {
@@ -930,9 +964,7 @@ __global__ void __launch_bounds__(256) k_lu_fwd_pipe(int mp, const double* __res
   if (l == 0) lu_publish(Anext + row, lu_pending());
   const int c0 = (r0 / kLuGW) * kLuGW, rb = r0 & ~127;
   const double2* f = reinterpret_cast<const double2*>(F + (size_t)row * mp);
-  double acc = 0.0;
-  for (int h0 = 0; h0 < c0; h0 += kLuGW) acc += lu_pipe_dot(f, h0, kLuGW, A, ag, l, err);
-  acc = group_sum<16>(acc);
+  const double acc = group_sum<16>(lu_pipe_span(f, c0 / kLuGW, 0, 1, mp, A, ag, l, err));
   const double a = t[row] - acc;
   if (l == 0) lu_publish(A + row, a);
   double acc2 = 0.0;
@@ -940,7 +972,7 @@ __global__ void __launch_bounds__(256) k_lu_fwd_pipe(int mp, const double* __res
   if (l == 0) y[row] = a + acc2;
 }
 
-__global__ void __launch_bounds__(256) k_lu_bwd_pipe(int mp, const double* __restrict__ F,
+__global__ void __launch_bounds__(256, 3) k_lu_bwd_pipe(int mp, const double* __restrict__ F,
                                                      const double* __restrict__ Pall,
                                                      const GmresState* __restrict__ st, const double* __restrict__ y,
                                                      double* A, double* __restrict__ t, double* Anext,
@@ -967,10 +999,9 @@ __global__ void __launch_bounds__(256) k_lu_bwd_pipe(int mp, const double* __res
   }
   p = group_sum<16>(p);
   const double2* f = reinterpret_cast<const double2*>(F + (size_t)row * mp);
-  double acc = 0.0;
-  for (int h0 = ((mp - 1) / kLuGW) * kLuGW; h0 >= c1; h0 -= kLuGW)
-    acc += lu_pipe_dot(f, h0, min(kLuGW, mp - h0), A, ag, l, err);
-  acc = group_sum<16>(acc);
+  const int hlast = ((mp - 1) / kLuGW) * kLuGW;
+  const double acc = group_sum<16>(lu_pipe_span(f, hlast >= c1 ? (hlast - c1) / kLuGW + 1 : 0, hlast, -1, mp, A, ag,
+                                                l, err));
   const double a = p - acc;
   if (l == 0) lu_publish(A + row, a);
   double acc2 = 0.0;

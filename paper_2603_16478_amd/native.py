@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(HERE, "libadjoint.so")
 STATUS = {0: "ADJ_OK", -1: "ADJ_E_ARG", -2: "ADJ_E_SHAPE", -3: "ADJ_E_INVERTED",
           -4: "ADJ_E_NOCONV", -5: "ADJ_E_SINGULAR", -6: "ADJ_E_DEVICE", -7: "ADJ_E_OOM",
           -8: "ADJ_E_NOTIMPL"}
-ADJ_FP64, ADJ_MIXED = 0, 1
+ADJ_FP64, ADJ_MIXED, ADJ_MIXED_PC = 0, 1, 2
 ADJ_AUTO, ADJ_GMRES, ADJ_PCG, ADJ_SEMI_IMPLICIT = 0, 1, 2, 3
 PRECOND_WOODBURY, PRECOND_SPARSE_INVERSE, PRECOND_JACOBI, PRECOND_POINT_JACOBI = 0, 1, 2, 3
 PRECOND_WOODBURY_NO_Z = 4

@@ -149,7 +149,7 @@ def test_beam_slip_onset_matches_oracle(mu, k):
     assert abs(g[2] - ref.dmu_fric) <= TOL_FP64 * max(abs(ref.dmu_fric), 1e-30)
 
 
-@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("prec", ["fp64", "mixed", "mixed_pc"])
 def test_beam_slip_onset_stored_oracle_z(prec):
     """All twelve slip-onset steps in one scene, in the benchmark's solve
     configuration (rtol 1e-8, GMRES(64), Woodbury), against the oracle's
@@ -169,7 +169,8 @@ def test_beam_slip_onset_stored_oracle_z(prec):
     gv = torch.zeros_like(gq)
     z = torch.zeros_like(gq)
     opts = native.solve_opts(rtol=1e-8, maxit=3000, restart=64, max_refine=8,
-                             prec=native.ADJ_MIXED if prec == "mixed" else native.ADJ_FP64)
+                             prec={"fp64": native.ADJ_FP64, "mixed": native.ADJ_MIXED,
+                                   "mixed_pc": native.ADJ_MIXED_PC}[prec])
     worst = 0.0
     for i, (mu, k) in enumerate(ONSET):
         q, rec = _beam_state(mu, k, fixture="beam_onset")
@@ -190,8 +191,9 @@ def test_beam_slip_onset_stored_oracle_z(prec):
     print(f"{prec}: worst z err {worst:.2e}", flush=True)
 
 
+@pytest.mark.parametrize("prec_name", ["ADJ_MIXED", "ADJ_MIXED_PC"])
 @pytest.mark.parametrize("mu,t", [(1.0, 3), (0.1, 2), (0.4, 3)])
-def test_beam_mixed_precision_matches_oracle(mu, t):
+def test_beam_mixed_precision_matches_oracle(mu, t, prec_name):
     """ADJ_MIXED (FP32-stored S, S^T and block matrix in the inner GMRES;
     FP64 Woodbury factors, Gram-Schmidt and refinement residual) against
     the FP64 oracle: 1e-4 relative on every output (the mixed-precision
@@ -212,7 +214,7 @@ def test_beam_mixed_precision_matches_oracle(mu, t):
     gq = torch.tensor(spec.loss_dir, device="cuda")
     gv = torch.zeros_like(gq)
     z = torch.zeros_like(gq)
-    opts = native.solve_opts(rtol=1e-8, maxit=3000, restart=64, prec=native.ADJ_MIXED, max_refine=8)
+    opts = native.solve_opts(rtol=1e-8, maxit=3000, restart=64, prec=getattr(native, prec_name), max_refine=8)
     native.adjoint_setup(scene, cs, qd, opts)
     native.check_status(scene)
     info = native.adjoint_solve(scene, gq, gv, z, opts)
@@ -221,7 +223,7 @@ def test_beam_mixed_precision_matches_oracle(mu, t):
     native.vjp_params(scene, z, gv, dq, dv, df, g3)
     torch.cuda.synchronize()
     err = rel(z.cpu().numpy(), ref.z)
-    print(f"mixed mu={mu} t={t}: iters {info.iters} refine {info.refine_steps} relres {info.relres:.2e} "
+    print(f"{prec_name} mu={mu} t={t}: iters {info.iters} refine {info.refine_steps} relres {info.relres:.2e} "
           f"z err {err:.2e}", flush=True)
     assert info.relres <= 1e-8
     assert err <= 1e-4

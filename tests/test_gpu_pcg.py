@@ -65,8 +65,10 @@ def test_pcg_rejected_on_frictional_system():
         run_adjoint(scene, rec, q, np.ones_like(q), np.zeros_like(q), method=native.ADJ_PCG)
 
 
-def test_pcg_mixed_precision_matches_oracle():
-    """Mixed precision with PCG inside the FP64 refinement loop: 1e-4."""
+@pytest.mark.parametrize("prec_name", ["ADJ_MIXED", "ADJ_MIXED_PC"])
+def test_pcg_mixed_precision_matches_oracle(prec_name):
+    """Mixed precision with PCG inside the FP64 refinement loop: 1e-4
+    (PCG takes ADJ_MIXED_PC as ADJ_MIXED)."""
     torch_cuda()
     from paper_2603_16478_amd import native
     spec, ro = _frictionless()
@@ -76,7 +78,7 @@ def test_pcg_mixed_precision_matches_oracle():
     gv = np.zeros_like(q)
     ref = adj.adjoint_step(ro.disc, q, rec, gq, gv, spec.eps, spec.E, spec.nu)
     scene = make_scene(spec, max_contacts=64)
-    out = run_adjoint(scene, rec, q, gq, gv, rtol=1e-8, prec=native.ADJ_MIXED)
+    out = run_adjoint(scene, rec, q, gq, gv, rtol=1e-8, prec=getattr(native, prec_name))
     print(f"pcg mixed: iters {out['info'].iters}, refine {out['info'].refine_steps}, "
           f"z err {rel(out['z'], ref.z):.2e}", flush=True)
     assert out["info"].method == native.ADJ_PCG

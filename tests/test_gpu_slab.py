@@ -81,7 +81,8 @@ def test_full_size_slab_against_stored_oracle():
     at its last step: top face pressed onto the sphere (synth's indented
     state), the 3,022 contacts the oracle's detection finds there (2,145 on
     the ground, 877 on the sphere; 9,018 capacitance rows) with seeded
-    sticking contact values.  The GPU adjoint in FP64 and in mixed precision
+    sticking contact values.  The GPU adjoint in FP64 and in both mixed
+    precision modes (refinement; FP32 preconditioner in FP64 flexible GMRES)
     is compared element by element with the oracle's z stored in
     tests/golden/slab_step50.npz (tests/golden/make_oracle_z.py: direct
     sparse LU with long-double refinement), at 1e-9 and 1e-4; the gradient
@@ -110,7 +111,7 @@ def test_full_size_slab_against_stored_oracle():
     gq = torch.tensor(gqn, device="cuda")
     gv = torch.tensor(gvn, device="cuda")
     outs = {}
-    for prec in (native.ADJ_FP64, native.ADJ_MIXED):
+    for prec in (native.ADJ_FP64, native.ADJ_MIXED, native.ADJ_MIXED_PC):
         opts = native.solve_opts(rtol=1e-12 if prec == native.ADJ_FP64 else 1e-8, maxit=800, restart=64,
                                  prec=prec, max_refine=8)
         native.adjoint_setup(scene, cs, q, opts)
@@ -134,7 +135,7 @@ def test_full_size_slab_against_stored_oracle():
     sysm = adj.assemble(disc, qn, orec, spec.eps)
     zref = d["z"]
     ref = adj.vjp(disc, sysm, qn, orec, zref.reshape(-1), gvn, spec.E, spec.nu)
-    for prec, bar in ((native.ADJ_FP64, TOL_FP64), (native.ADJ_MIXED, 1e-4)):
+    for prec, bar in ((native.ADJ_FP64, TOL_FP64), (native.ADJ_MIXED, 1e-4), (native.ADJ_MIXED_PC, 1e-4)):
         o = outs[prec]
         errs = {"z": rel(o["z"], zref)}
         errs |= {k: rel(o[k], getattr(ref, k)) for k in ("dqbar", "dvbar", "dfext", "dE_tet", "dnu_tet")}

@@ -67,7 +67,7 @@ def test_iteration_cap_reports_noconv():
     scene.close()
 
 
-@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("prec", [0, 1, 2])
 def test_inverted_element_is_reported_and_cleared_by_the_next_setup(prec):
     torch_cuda()
     spec, ro = _impact()
@@ -84,7 +84,7 @@ def test_inverted_element_is_reported_and_cleared_by_the_next_setup(prec):
     scene.close()
 
 
-@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("prec", [0, 1, 2])
 def test_non_finite_right_hand_side_is_an_argument_error(prec):
     torch_cuda()
     spec, ro = _impact()
