@@ -355,7 +355,7 @@ adj_status adj_profile_end(adj_scene* scene, double* total_ms, int64_t* launches
  * over the GPU and the order of floating-point sums inside reductions (so
  * results are bitwise reproducible for a fixed tuning, and agree across
  * tunings to rounding).  Defaults: gs_rows 64, bsr_lanes 16, chunk 8,
- * graph 0, gj_wide_min 2048, a_inv 0, lu_min 4608, lu_pipe 1. */
+ * graph 0, gj_wide_min 2048, a_inv 0, lu_min 4608, lu_pipe 1, sweep_fuse 0. */
 typedef struct {
   int32_t gs_rows;   /* rows per 256-thread block of the Gram-Schmidt kernels: 64, 128, 256 */
   int32_t bsr_lanes; /* lanes per block row of the Acal^T product: 4, 8, 16, 32 */
@@ -374,6 +374,10 @@ typedef struct {
   int32_t lu_pipe;   /* 1: the block-LU substitutions run pipelined, one launch per pass (stripes of 16
                         rows that wait for the values they need, published once each by atomic stores);
                         0: one launch per group of four 128-blocks; default 1 */
+  int32_t sweep_fuse; /* the lowest levels of each sweep with L run as one launch, one block per
+                         independent part (the rows that those levels couple): that many levels, 0 =
+                         none, -1 = automatic (the most levels that still split into at least 256
+                         parts); default 0 */
 } adj_tuning;
 
 /* Set or read the scene's launch shapes.  ADJ_E_ARG on a value outside the

@@ -80,6 +80,12 @@ void launch_wb_lu_pipe(hipStream_t, int, int, const int*, const int*, const int*
                        const double*, const double*, const GmresState*, double*, double*, double*, double*, unsigned*,
                        int*);
 void launch_lu_pipe_init(hipStream_t, int, double*, double*, unsigned*);
+void launch_sweep_parts(hipStream_t, int, int, int, const int*, const int*, const long long*, const int*,
+                        const double*, const long long*, const int*, const double*, const GmresState*, double*,
+                        double*);
+void launch_sweep_parts(hipStream_t, int, int, int, const int*, const int*, const long long*, const int*,
+                        const float*, const long long*, const int*, const float*, const GmresState*, double*,
+                        double*);
 void launch_lu_groups(hipStream_t, int, double*);
 int lu_group_blocks();
 void launch_wb_correct(hipStream_t, int, int, const int*, const int*, const int*, const double*,
@@ -180,7 +186,7 @@ hipError_t upload(T** p, const std::vector<T>& v) {
 
 struct adj_scene {
   HostScene hs;
-  adj_tuning tune{64, 16, 8, 0, 2048, 0, 4608, 1};
+  adj_tuning tune{64, 16, 8, 0, 2048, 0, 4608, 1, 0};
   int nv = 0, nt = 0, nnzb = 0, max_contacts = 0;
   int material = 0;  // adj_material of the local projection
   int nb = 0;  // bilateral bindings: vertex ids and compliances on the device
@@ -296,6 +302,10 @@ struct adj_scene {
   double *d_Fx = nullptr, *d_Bx = nullptr, *d_Ix = nullptr, *d_ITx = nullptr, *d_lt = nullptr, *d_lz = nullptr;
   float *d_Fx32 = nullptr, *d_Bx32 = nullptr, *d_Ix32 = nullptr, *d_ITx32 = nullptr;
   int *d_fA = nullptr, *d_fB = nullptr, *d_bA = nullptr, *d_bB = nullptr;
+  // the lowest fuse_k levels of each sweep in one launch (k_sweep_parts):
+  // n_parts independent parts, their rows and per-height offsets
+  int fuse_k = 0, n_parts = 0;
+  int *d_part_rows = nullptr, *d_part_off = nullptr;
   // actuation (active stress per tet group): group and fibre per tet, the
   // tets of each group (CSR), per-tet scratch
   int n_act = 0;
@@ -383,7 +393,7 @@ static void free_scene(adj_scene* s) {
                   s->d_gjw_P,    s->d_gjw_W,  s->d_lu_P,  s->d_lu_y, s->d_lu_A0, s->d_lu_A1, s->d_lu_tick,
                   s->d_Fp, s->d_Bp, s->d_Ip, s->d_ITp, s->d_Fj, s->d_Bj, s->d_Ij, s->d_ITj, s->d_perm,
                   s->d_Fx, s->d_Bx, s->d_Ix, s->d_ITx, s->d_lt, s->d_lz, s->d_Fx32, s->d_Bx32, s->d_Ix32, s->d_ITx32,
-                  s->d_fA, s->d_fB, s->d_bA, s->d_bB, s->d_ybm};
+                  s->d_fA, s->d_fB, s->d_bA, s->d_bB, s->d_ybm, s->d_part_rows, s->d_part_off};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (s->h_state) (void)hipHostFree(s->h_state);
@@ -413,6 +423,41 @@ constexpr int kMaxContacts = 10000;
 // scene holds the sum of its scenes' contacts; its capacitance stays per
 // scene).
 static adj_status scene_create(const adj_scene_desc* desc, int32_t max_contacts, adj_scene** out);
+
+// Levels of each sweep run as one launch (k_sweep_parts): tune.sweep_fuse
+// levels, or with -1 the most levels that still split into at least 256
+// independent parts (one block each); 0 or no sweeps: none.  Rebuilds the
+// device lists when the count changes (synchronous; not inside a capture).
+static adj_status prepare_sweep_parts(adj_scene* s) {
+  if (!s->sweeps_built) return ADJ_OK;
+  int k = s->tune.sweep_fuse;
+  std::vector<int32_t> rows, off;
+  if (k < 0) {
+    k = 0;
+    for (int c = 1; c < s->n_levels; ++c) {
+      if (sweep_parts(s->hs, c, rows, off) < 256) break;
+      k = c;
+    }
+  }
+  k = std::min(k, s->n_levels);
+  if (k == s->fuse_k && (k == 0 || s->d_part_rows)) return ADJ_OK;
+  (void)hipFree(s->d_part_rows);
+  (void)hipFree(s->d_part_off);
+  s->d_part_rows = s->d_part_off = nullptr;
+  s->fuse_k = s->n_parts = 0;
+  if (k == 0) return ADJ_OK;
+  const int np = sweep_parts(s->hs, k, rows, off);
+  if (np <= 0) return ADJ_OK;
+  if (dalloc(&s->d_part_rows, std::max<size_t>(rows.size(), 1)) != hipSuccess ||
+      dalloc(&s->d_part_off, off.size()) != hipSuccess)
+    return fail(ADJ_E_OOM, "hipMalloc failed (sweep parts)");
+  if (hipMemcpy(s->d_part_rows, rows.data(), rows.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(s->d_part_off, off.data(), off.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess)
+    return fail(ADJ_E_DEVICE, "hipMemcpy failed (sweep parts)");
+  s->fuse_k = k;
+  s->n_parts = np;
+  return ADJ_OK;
+}
 
 extern "C" adj_status adj_scene_create(const adj_scene_desc* desc, int32_t max_contacts,
                                        adj_scene** out) {
@@ -603,6 +648,10 @@ static adj_status scene_create(const adj_scene_desc* desc, int32_t max_contacts,
   }
   launch_to_f32(nullptr, (long long)h.Sx.size(), s->d_Sx, s->d_Sx32);
   launch_to_f32(nullptr, (long long)h.STx.size(), s->d_STx, s->d_STx32);
+  if (prepare_sweep_parts(s) != ADJ_OK) {
+    free_scene(s);
+    return fail(ADJ_E_OOM, "device workspace allocation failed (sweep parts)");
+  }
   if (hipMemset(s->d_counter, 0, 16 * sizeof(unsigned)) != hipSuccess ||
       hipMemset(s->d_err, 0, 4 * sizeof(int)) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
     free_scene(s);
@@ -1052,7 +1101,15 @@ static void s_forward(adj_scene* s, hipStream_t st, const double* x, long long s
   }
   const HostScene& h = s->hs;
   launch_perm_gather(st, s->nv, s->d_perm, x, stride, scale, state, s->d_lt);
-  for (int l = 0; l < s->n_levels; ++l) {
+  if (s->fuse_k > 0) {
+    if (f32)
+      launch_sweep_parts(st, s->n_parts, 1, s->fuse_k, s->d_part_rows, s->d_part_off, s->d_Fp, s->d_Fj, s->d_Fx32,
+                         s->d_Ip, s->d_Ij, s->d_Ix32, state, y, s->d_lt);
+    else
+      launch_sweep_parts(st, s->n_parts, 1, s->fuse_k, s->d_part_rows, s->d_part_off, s->d_Fp, s->d_Fj, s->d_Fx,
+                         s->d_Ip, s->d_Ij, s->d_Ix, state, y, s->d_lt);
+  }
+  for (int l = s->fuse_k; l < s->n_levels; ++l) {
     const int a0 = h.fA_off[l], na = h.fA_off[l + 1] - a0, b0 = h.fB_off[l], nb = h.fB_off[l + 1] - b0;
     const int4* ta = (const int4*)s->d_fA + a0;
     const int4* tb = (const int4*)s->d_fB + b0;
@@ -1080,7 +1137,7 @@ static void s_transpose(adj_scene* s, hipStream_t st, const double* y, const Gmr
   }
   const HostScene& h = s->hs;
   (void)hipMemcpyAsync(s->d_lt, y, (size_t)s->n3 * sizeof(double), hipMemcpyDeviceToDevice, st);
-  for (int l = s->n_levels - 1; l >= 0; --l) {
+  for (int l = s->n_levels - 1; l >= s->fuse_k; --l) {
     const int a0 = h.bA_off[l], na = h.bA_off[l + 1] - a0, b0 = h.bB_off[l], nb = h.bB_off[l + 1] - b0;
     const int4* ta = (const int4*)s->d_bA + a0;
     const int4* tb = (const int4*)s->d_bB + b0;
@@ -1091,6 +1148,14 @@ static void s_transpose(adj_scene* s, hipStream_t st, const double* y, const Gmr
       launch_spmv_tasks_acc(st, na, ta, s->d_Bp, s->d_Bj, s->d_Bx, s->d_lz, -1.0, state, s->d_lt);
       if (nb) launch_spmv_tasks(st, nb, tb, s->d_ITp, s->d_ITj, s->d_ITx, s->d_lt, 0, nullptr, state, s->d_lz);
     }
+  }
+  if (s->fuse_k > 0) {
+    if (f32)
+      launch_sweep_parts(st, s->n_parts, 0, s->fuse_k, s->d_part_rows, s->d_part_off, s->d_Bp, s->d_Bj, s->d_Bx32,
+                         s->d_ITp, s->d_ITj, s->d_ITx32, state, s->d_lz, s->d_lt);
+    else
+      launch_sweep_parts(st, s->n_parts, 0, s->fuse_k, s->d_part_rows, s->d_part_off, s->d_Bp, s->d_Bj, s->d_Bx,
+                         s->d_ITp, s->d_ITj, s->d_ITx, state, s->d_lz, s->d_lt);
   }
   launch_perm_scatter(st, s->nv, s->d_perm, s->d_lz, state, out);
 }
@@ -1734,7 +1799,8 @@ static bool valid_tuning(const adj_tuning& t) {
   const bool ln = t.bsr_lanes == 4 || t.bsr_lanes == 8 || t.bsr_lanes == 16 || t.bsr_lanes == 32;
   const bool gw = t.gj_wide_min >= 128 && t.gj_wide_min % 128 == 0;
   const bool ai = t.a_inv >= 0 && t.a_inv <= 2;
-  const bool lu = t.lu_min >= 128 && t.lu_min % 128 == 0 && (t.lu_pipe == 0 || t.lu_pipe == 1);
+  const bool lu = t.lu_min >= 128 && t.lu_min % 128 == 0 && (t.lu_pipe == 0 || t.lu_pipe == 1) &&
+                  t.sweep_fuse >= -1 && t.sweep_fuse <= 64;
   return gs && ln && gw && ai && lu && t.chunk >= 1 && t.chunk <= 64 && (t.graph == 0 || t.graph == 1);
 }
 
@@ -1743,7 +1809,7 @@ extern "C" adj_status adj_set_tuning(adj_scene* s, const adj_tuning* t) {
   if (!valid_tuning(*t)) return fail(ADJ_E_ARG, "tuning value outside the supported set");
   s->tune = *t;
   drop_chunk_graphs(s);
-  return ADJ_OK;
+  return prepare_sweep_parts(s);
 }
 
 extern "C" adj_status adj_get_tuning(const adj_scene* s, adj_tuning* t) {

@@ -308,6 +308,58 @@ void build_sweeps(HostScene& s) {
   lists(s.ITp, s.bB_tasks, s.bB_off);
 }
 
+int sweep_parts(const HostScene& s, int k, std::vector<int32_t>& rows, std::vector<int32_t>& off) {
+  rows.clear();
+  off.clear();
+  const int nv = s.nv;
+  if (k <= 0 || s.n_levels == 0 || (int)s.Fp.size() != nv + 1) return 0;
+  std::vector<int32_t> height(nv, -1), up(nv);
+  for (const NdSegment& g : s.segs)
+    for (int32_t i = 0; i < g.len; ++i) height[g.start + i] = g.height;
+  for (int i = 0; i < nv; ++i) up[i] = i;
+  auto find = [&](int a) {
+    while (up[a] != a) {
+      up[a] = up[up[a]];
+      a = up[a];
+    }
+    return a;
+  };
+  auto join = [&](int a, int b) {
+    a = find(a);
+    b = find(b);
+    if (a != b) up[std::max(a, b)] = std::min(a, b);
+  };
+  for (const NdSegment& g : s.segs)
+    if (g.height < k)
+      for (int32_t i = 1; i < g.len; ++i) join(g.start, g.start + i);
+  for (int i = 0; i < nv; ++i)
+    if (height[i] < k)
+      for (int64_t p = s.Fp[i]; p < s.Fp[i + 1]; ++p) join(i, s.Fj[p]);  // descendants: heights < height[i]
+  // parts in order of their smallest row; rows by (part, height, row)
+  std::vector<int32_t> part(nv, -1);
+  int np = 0;
+  for (int i = 0; i < nv; ++i)
+    if (height[i] >= 0 && height[i] < k) {
+      const int r = find(i);
+      if (part[r] < 0) part[r] = np++;
+      part[i] = part[r];
+    }
+  std::vector<int32_t> cnt((size_t)np * k + 1, 0);
+  for (int i = 0; i < nv; ++i)
+    if (part[i] >= 0) cnt[(size_t)part[i] * k + height[i] + 1]++;
+  for (size_t e = 1; e < cnt.size(); ++e) cnt[e] += cnt[e - 1];
+  rows.assign(cnt.back(), 0);
+  std::vector<int32_t> pos(cnt.begin(), cnt.end() - 1);
+  for (int i = 0; i < nv; ++i)
+    if (part[i] >= 0) rows[pos[(size_t)part[i] * k + height[i]]++] = i;
+  off.assign((size_t)np * (k + 1), 0);
+  for (int c = 0; c < np; ++c) {
+    for (int h = 0; h < k; ++h) off[(size_t)c * (k + 1) + h] = cnt[(size_t)c * k + h];
+    off[(size_t)c * (k + 1) + k] = cnt[(size_t)(c + 1) * k];
+  }
+  return np;
+}
+
 adj_status build_host_scene(const adj_scene_desc* d, HostScene& s, std::string& err) {
   if (!d || d->n_verts <= 0 || d->n_tets <= 0 || !d->rest_pos || !d->tets || !d->E || !d->nu) {
     err = "scene_desc: missing arrays or non-positive sizes";

@@ -75,6 +75,15 @@ struct HostScene {
 
 void build_sweeps(HostScene& s);
 
+// Rows of the k lowest sweep levels (heights < k) grouped into independent
+// parts: rows joined by an entry of L between different segments, and the
+// rows of one segment, fall in one part, so each part's sweep through those
+// levels reads only its own rows (and, backwards, rows above height k - 1).
+// rows: the parts one after another, each sorted by height then row; off:
+// [n_parts * (k + 1)] start of height h of part c at off[c (k + 1) + h],
+// the part's end at off[c (k + 1) + k].  Returns the number of parts.
+int sweep_parts(const HostScene& s, int k, std::vector<int32_t>& rows, std::vector<int32_t>& off);
+
 // Pack CSR rows into blocks: rows longer than `big` get a block each (flag
 // 0x40000000), shorter rows go four to a block; -1 marks an empty slot.
 // Tasks are ordered by decreasing row length.  `rows` restricts the tasks to

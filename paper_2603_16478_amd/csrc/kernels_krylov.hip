@@ -124,6 +124,77 @@ __global__ void __launch_bounds__(256) k_spmv_tasks(const int4* __restrict__ tas
   }
 }
 
+// The k lowest levels of a sweep in one launch, one block per independent
+// part of those levels (host: sweep_parts): per height h (forward: 0 .. k-1;
+// backward: k-1 .. 0) the block forms tmp[row] -= A_row . out for the part's
+// rows at h, then out[row] = D_row . tmp, with a block barrier after each
+// phase, since every entry an A row reads lies in the part (or, backwards,
+// above the fused levels, finished by the launches before).  Forward: A = the
+// rows of L left of their segment, D = the inverted diagonal blocks, out = y;
+// backward: A = the columns of L below their segment, D = the transposed
+// inverses, out = z.  16 lanes per row, 16 rows at a time.
+template <class MT>
+__global__ void __launch_bounds__(256) k_sweep_parts(int fwd, int k, const int* __restrict__ rows,
+                                                     const int* __restrict__ off, const long long* __restrict__ Ap,
+                                                     const int* __restrict__ Aj, const MT* __restrict__ Ax,
+                                                     const long long* __restrict__ Dp, const int* __restrict__ Dj,
+                                                     const MT* __restrict__ Dx, const GmresState* __restrict__ st,
+                                                     double* out, double* tmp) {
+  if (gm_inactive(st)) return;
+  const int* o = off + (size_t)blockIdx.x * (k + 1);
+  const int g = threadIdx.x >> 4, l = threadIdx.x & 15;
+  for (int s = 0; s < k; ++s) {
+    const int h = fwd ? s : k - 1 - s;
+    const int r0 = o[h], r1 = o[h + 1];
+    for (int i = r0 + g; i < r1; i += 16) {
+      const int row = rows[i];
+      double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+      row_dot3<16, 4>(Ap[row], Ap[row + 1], l, Aj, Ax, out, a0, a1, a2);
+      a0 = group_sum<16>(a0);
+      a1 = group_sum<16>(a1);
+      a2 = group_sum<16>(a2);
+      if (l == 0) {
+        tmp[3 * row] -= a0;
+        tmp[3 * row + 1] -= a1;
+        tmp[3 * row + 2] -= a2;
+      }
+    }
+    __syncthreads();
+    for (int i = r0 + g; i < r1; i += 16) {
+      const int row = rows[i];
+      double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+      row_dot3<16, 4>(Dp[row], Dp[row + 1], l, Dj, Dx, tmp, a0, a1, a2);
+      a0 = group_sum<16>(a0);
+      a1 = group_sum<16>(a1);
+      a2 = group_sum<16>(a2);
+      if (l == 0) {
+        out[3 * row] = a0;
+        out[3 * row + 1] = a1;
+        out[3 * row + 2] = a2;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <class MT>
+static void sweep_parts_impl(hipStream_t s, int nparts, int fwd, int k, const int* rows, const int* off,
+                             const long long* Ap, const int* Aj, const MT* Ax, const long long* Dp, const int* Dj,
+                             const MT* Dx, const GmresState* st, double* out, double* tmp) {
+  if (nparts <= 0 || k <= 0) return;
+  k_sweep_parts<MT><<<nparts, 256, 0, s>>>(fwd, k, rows, off, Ap, Aj, Ax, Dp, Dj, Dx, st, out, tmp);
+}
+void launch_sweep_parts(hipStream_t s, int nparts, int fwd, int k, const int* rows, const int* off,
+                        const long long* Ap, const int* Aj, const double* Ax, const long long* Dp, const int* Dj,
+                        const double* Dx, const GmresState* st, double* out, double* tmp) {
+  sweep_parts_impl(s, nparts, fwd, k, rows, off, Ap, Aj, Ax, Dp, Dj, Dx, st, out, tmp);
+}
+void launch_sweep_parts(hipStream_t s, int nparts, int fwd, int k, const int* rows, const int* off,
+                        const long long* Ap, const int* Aj, const float* Ax, const long long* Dp, const int* Dj,
+                        const float* Dx, const GmresState* st, double* out, double* tmp) {
+  sweep_parts_impl(s, nparts, fwd, k, rows, off, Ap, Aj, Ax, Dp, Dj, Dx, st, out, tmp);
+}
+
 // Y values of the Woodbury correction gathered from the rows of S^T:
 // yval[e] = STx[src[e]].
 __global__ void k_gather_values(long long n, const long long* __restrict__ src, const double* __restrict__ STx,

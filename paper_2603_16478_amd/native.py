@@ -82,7 +82,8 @@ class BatchTuning(C.Structure):
 
 class Tuning(C.Structure):
     _fields_ = [("gs_rows", C.c_int32), ("bsr_lanes", C.c_int32), ("chunk", C.c_int32), ("graph", C.c_int32),
-                ("gj_wide_min", C.c_int32), ("a_inv", C.c_int32), ("lu_min", C.c_int32), ("lu_pipe", C.c_int32)]
+                ("gj_wide_min", C.c_int32), ("a_inv", C.c_int32), ("lu_min", C.c_int32), ("lu_pipe", C.c_int32),
+                ("sweep_fuse", C.c_int32)]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
@@ -379,9 +380,9 @@ class ContactBuffers:
 
 
 def set_tuning(scene: Scene, gs_rows=64, bsr_lanes=16, chunk=8, graph=0, gj_wide_min=2048, a_inv=0, lu_min=4608,
-               lu_pipe=1):
+               lu_pipe=1, sweep_fuse=0):
     t = Tuning(int(gs_rows), int(bsr_lanes), int(chunk), int(graph), int(gj_wide_min), int(a_inv), int(lu_min),
-               int(lu_pipe))
+               int(lu_pipe), int(sweep_fuse))
     check(load().adj_set_tuning(scene.handle, C.byref(t)))
 
 

@@ -27,12 +27,20 @@ def _beam(mu=0.4, t=3):
     return beam_scene(mu=mu), d[f"q{t}"], StepRecord(cs, d[f"delta{t}"], d[f"lam{t}"], mu)
 
 
-TUNINGS = [dict(gs_rows=64, bsr_lanes=16, chunk=8, graph=0, gj_wide_min=2048, a_inv=0, lu_min=4608, lu_pipe=1),
-           dict(gs_rows=128, bsr_lanes=8, chunk=4, graph=0, gj_wide_min=2048, a_inv=2, lu_min=128, lu_pipe=1),
-           dict(gs_rows=128, bsr_lanes=8, chunk=4, graph=0, gj_wide_min=2048, a_inv=2, lu_min=128, lu_pipe=0),
-           dict(gs_rows=256, bsr_lanes=32, chunk=16, graph=0, gj_wide_min=128, a_inv=1, lu_min=4608, lu_pipe=1),
-           dict(gs_rows=64, bsr_lanes=4, chunk=8, graph=1, gj_wide_min=2048, a_inv=2, lu_min=128, lu_pipe=1),
-           dict(gs_rows=128, bsr_lanes=16, chunk=32, graph=1, gj_wide_min=128, a_inv=0, lu_min=4608, lu_pipe=0)]
+TUNINGS = [dict(gs_rows=64, bsr_lanes=16, chunk=8, graph=0, gj_wide_min=2048, a_inv=0, lu_min=4608, lu_pipe=1,
+                sweep_fuse=0),
+           dict(gs_rows=128, bsr_lanes=8, chunk=4, graph=0, gj_wide_min=2048, a_inv=2, lu_min=128, lu_pipe=1,
+                sweep_fuse=0),
+           dict(gs_rows=128, bsr_lanes=8, chunk=4, graph=0, gj_wide_min=2048, a_inv=2, lu_min=128, lu_pipe=0,
+                sweep_fuse=3),
+           dict(gs_rows=128, bsr_lanes=8, chunk=4, graph=0, gj_wide_min=2048, a_inv=2, lu_min=4608, lu_pipe=1,
+                sweep_fuse=64),
+           dict(gs_rows=256, bsr_lanes=32, chunk=16, graph=0, gj_wide_min=128, a_inv=1, lu_min=4608, lu_pipe=1,
+                sweep_fuse=-1),
+           dict(gs_rows=64, bsr_lanes=4, chunk=8, graph=1, gj_wide_min=2048, a_inv=2, lu_min=128, lu_pipe=1,
+                sweep_fuse=5),
+           dict(gs_rows=128, bsr_lanes=16, chunk=32, graph=1, gj_wide_min=128, a_inv=0, lu_min=4608, lu_pipe=0,
+                sweep_fuse=-1)]
 
 
 def test_tunings_agree_with_oracle():
