@@ -8,6 +8,7 @@
 #include <condition_variable>
 #include <mutex>
 #include <thread>
+#include <type_traits>
 #include <unordered_map>
 #include <cstdio>
 #include <cstring>
@@ -505,7 +506,15 @@ static adj_status scene_create(const adj_scene_desc* desc, int32_t max_contacts,
     }                                                  \
   } while (0)
   std::vector<long long> Sp(h.Sp.begin(), h.Sp.end()), STp(h.STp.begin(), h.STp.end());
-  UP(s->d_tets, h.tets);
+  // per-tet arrays entry-major on the device (entry e of tet t at e * n_t + t), so that the per-tet
+  // kernels' loads coalesce: the four vertex ids and the 12 entries of B~ per tet
+  auto entry_major = [&](const auto& v, int w) {
+    std::remove_const_t<std::remove_reference_t<decltype(v)>> out(v.size());
+    for (int t = 0; t < h.nt; ++t)
+      for (int e = 0; e < w; ++e) out[(size_t)e * h.nt + t] = v[(size_t)t * w + e];
+    return out;
+  };
+  UP(s->d_tets, entry_major(h.tets, 4));
   UP(s->d_rowptr, h.rowptr);
   UP(s->d_col, h.col);
   UP(s->d_row_of_slot, h.row_of_slot);
@@ -518,7 +527,7 @@ static adj_status scene_create(const adj_scene_desc* desc, int32_t max_contacts,
   }
   UP(s->d_slot_ptr, h.slot_ptr);
   UP(s->d_slot_code, h.slot_code);
-  UP(s->d_Bt, h.Bt);
+  UP(s->d_Bt, entry_major(h.Bt, 12));
   UP(s->d_vol, h.vol);
   UP(s->d_lmu, h.lmu);
   UP(s->d_llam, h.llam);

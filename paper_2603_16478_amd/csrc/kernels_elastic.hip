@@ -23,16 +23,17 @@ namespace adj {
 __constant__ int c_pairK[10] = {0, 0, 0, 0, 1, 1, 1, 2, 2, 3};
 __constant__ int c_pairL[10] = {0, 1, 2, 3, 1, 2, 3, 2, 3, 3};
 
-__device__ __forceinline__ void load_tet(int t, const int* __restrict__ tets,
+// tets and Bt entry-major: vertex k of tet t at tets[k nt + t], B~[k][c] at Bt[(3k + c) nt + t]
+__device__ __forceinline__ void load_tet(int t, int nt, const int* __restrict__ tets,
                                          const double* __restrict__ Bt, const double* __restrict__ q,
                                          double x[4][3], double B[4][3], int vid[4]) {
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    vid[k] = tets[4 * t + k];
+    vid[k] = tets[(size_t)k * nt + t];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       x[k][c] = q[3 * vid[k] + c];
-      B[k][c] = Bt[12 * t + 3 * k + c];
+      B[k][c] = Bt[(size_t)(3 * k + c) * nt + t];
     }
   }
 }
@@ -56,7 +57,7 @@ __global__ void __launch_bounds__(128) k_tet_blocks(int nt, const int* __restric
   if (t < nt) {
     double x[4][3];
     int vid[4];
-    load_tet(t, tets, Bt, q, x, B, vid);
+    load_tet(t, nt, tets, Bt, q, x, B, vid);
     double F[3][3];
     deformation_gradient(x, B, F);
     ok = det3(F) > 0.0;
@@ -184,7 +185,7 @@ __global__ void __launch_bounds__(256) k_vjp_tets(int nt, const int* __restrict_
   if (t < nt) {
     double x[4][3], B[4][3], zz[4][3];
     int vid[4];
-    load_tet(t, tets, Bt, q, x, B, vid);
+    load_tet(t, nt, tets, Bt, q, x, B, vid);
 #pragma unroll
     for (int k = 0; k < 4; ++k)
 #pragma unroll

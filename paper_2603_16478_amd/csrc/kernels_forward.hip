@@ -88,11 +88,11 @@ __global__ void __launch_bounds__(128) k_tet_force(int nt, const int* __restrict
   double x[4][3], B[4][3];
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    const int v = tets[4 * t + k];
+    const int v = tets[(size_t)k * nt + t];  // tets and Bt entry-major (entry e of tet t at e nt + t)
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       x[k][c] = q[3 * v + c];
-      B[k][c] = Bt[12 * t + 3 * k + c];
+      B[k][c] = Bt[(size_t)(3 * k + c) * nt + t];
     }
   }
   double F[3][3];
@@ -233,8 +233,8 @@ __global__ void k_act_tet(int nt, const int* __restrict__ group, const double* _
   const double sc = -vol[t] * a[group[t]];
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    const double* g = Bt + 12 * (size_t)t + 3 * k;
-    const double c = sc * (d0 * g[0] + d1 * g[1] + d2 * g[2]);
+    const double* g = Bt + (size_t)(3 * k) * nt + t;  // entry-major
+    const double c = sc * (d0 * g[0] + d1 * g[nt] + d2 * g[2 * (size_t)nt]);
     double* o = out + 12 * (size_t)t + 3 * k;
     o[0] = c * d0;
     o[1] = c * d1;
@@ -270,9 +270,9 @@ __global__ void k_act_vjp_tet(int nt, const int* __restrict__ tets, const double
   double acc = 0.0;
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    const int v = tets[4 * t + k];
-    const double* b = Bt + 12 * (size_t)t + 3 * k;
-    acc += (g[3 * v] * d0 + g[3 * v + 1] * d1 + g[3 * v + 2] * d2) * (d0 * b[0] + d1 * b[1] + d2 * b[2]);
+    const int v = tets[(size_t)k * nt + t];  // entry-major
+    const double* b = Bt + (size_t)(3 * k) * nt + t;
+    acc += (g[3 * v] * d0 + g[3 * v + 1] * d1 + g[3 * v + 2] * d2) * (d0 * b[0] + d1 * b[nt] + d2 * b[2 * (size_t)nt]);
   }
   s[t] = -vol[t] * acc;
 }
