@@ -249,7 +249,8 @@ adj_status vjp_params_noalloc(adj_scene* scene, const double* z, const double* d
  * same scene (adj_forward_reset clears them).  Synchronises the stream.
  * Invalidates the last adjoint_setup.  Returns ADJ_E_NOCONV if the paper's
  * residual rows did not fall below 1e-8, ADJ_E_INVERTED for an inverted
- * element at the initial guess. */
+ * element at the initial guess.  Scenes with bindings include the binding
+ * forces at the targets of adj_set_binding_targets (ADJ_E_ARG if unset). */
 adj_status sim_forward_step(adj_scene* scene, const double* qbar, const double* vbar,
                             const double* f_ext, double mu, double* q, double* v,
                             adj_contact_state* contacts, void* stream);
@@ -261,6 +262,14 @@ adj_status adj_forward_stats(const adj_scene* scene, double* out);
 
 /* Forget the warm start of the contact multipliers. */
 adj_status adj_forward_reset(adj_scene* scene);
+
+/* Binding targets d_b of the following sim_forward_step calls (Sec. 3.2
+ * eq:binding): host [n_bindings * 3], in the order of the scene's bindings;
+ * copied (synchronous).  A scene with bindings needs them before its first
+ * forward step (ADJ_E_ARG otherwise); each forward step then adds the
+ * binding force -(q_v - d_b) / E_b of every bound vertex.  ADJ_E_ARG for a
+ * scene without bindings or a non-finite target. */
+adj_status adj_set_binding_targets(adj_scene* scene, const double* targets);
 
 /* Kinematic sphere colliders of the next sim_forward_step calls (the slab
  * workload's indenter): n spheres, old_pose and new_pose host [n][4] =

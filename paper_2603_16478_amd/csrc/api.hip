@@ -35,6 +35,8 @@ void launch_contact_blocks(hipStream_t, int, const int*, const double*, const do
                            double*);
 void launch_contact_fold(hipStream_t, int, const int*, const int*, const double*, double*);
 void launch_binding_fold(hipStream_t, int, const int*, const double*, double, const int*, double*);
+void launch_binding_force(hipStream_t, int, const int*, const double*, double, const double*, const double*,
+                          double*);
 void launch_binding_vjp(hipStream_t, int, const int*, const double*, double, const double*, const double*,
                         const double*, double*, double*);
 void launch_capacitance(hipStream_t, int, int, const int*, const int*, const int*, int, const double*,
@@ -193,6 +195,8 @@ struct adj_scene {
   int nb = 0;  // bilateral bindings: vertex ids and compliances on the device
   int* d_bvid = nullptr;
   double* d_bE = nullptr;
+  double* d_btarget = nullptr;  // binding targets d_b of the next forward steps [n_b][3]
+  bool btarget_set = false;
   long long n3 = 0;
   int restart = 0;
   // constant device data
@@ -389,7 +393,7 @@ static void free_scene(adj_scene* s) {
                   s->d_mask,     s->d_fvid,   s->d_force, s->d_utilde,      s->d_qtilde,
                   s->d_fu,       s->d_du,     s->d_ut,    s->d_qcur,        s->d_rq,
                   s->d_rhs,      s->d_cvec,   s->d_cu,    s->d_norms,       s->d_Sx32,
-                  s->d_STx32,    s->d_val32,  s->d_valT,  s->d_Pws,   s->d_x_pcg, s->d_bvid, s->d_bE,
+                  s->d_STx32,    s->d_val32,  s->d_valT,  s->d_Pws,   s->d_x_pcg, s->d_bvid, s->d_bE, s->d_btarget,
                   s->d_Yp,       s->d_Ysrc,   s->d_Ycol,  s->d_Ytasks,      s->d_CTtasks, s->d_Yval,
                   s->d_gjw_P,    s->d_gjw_W,  s->d_lu_P,  s->d_lu_y, s->d_lu_A0, s->d_lu_A1, s->d_lu_tick,
                   s->d_Fp, s->d_Bp, s->d_Ip, s->d_ITp, s->d_Fj, s->d_Bj, s->d_Ij, s->d_ITj, s->d_perm,
@@ -524,6 +528,7 @@ static adj_status scene_create(const adj_scene_desc* desc, int32_t max_contacts,
   if (s->nb) {
     UP(s->d_bvid, h.bvid);
     UP(s->d_bE, h.bE);
+    UP(s->d_btarget, std::vector<double>(3 * h.bvid.size(), 0.0));
   }
   UP(s->d_slot_ptr, h.slot_ptr);
   UP(s->d_slot_code, h.slot_code);
@@ -2041,6 +2046,7 @@ static adj_status fwd_eval(adj_scene* s, hipStream_t st, const double* qbar, con
   launch_tet_force(st, s->nt, s->d_tets, s->d_Bt, s->d_vol, s->d_lmu, s->d_llam, h2, s->d_qcur, s->d_force,
                    s->d_err, s->material);
   launch_gather_force(st, s->nv, s->d_vptr, s->d_vcode, s->d_force, s->d_mass, u_dev, s->d_utilde, s->d_rq);
+  launch_binding_force(st, s->nb, s->d_bvid, s->d_bE, h2, s->d_qcur, s->d_btarget, s->d_rq);
   std::vector<double> uc(3 * (size_t)C.n);
   if (C.n) {
     launch_gather_contact_rows(st, C.n, s->d_fvid, u_dev, s->d_cu);
@@ -2101,6 +2107,7 @@ static adj_status fwd_newton(adj_scene* s, hipStream_t st, const double* qbar, F
                       s->d_tetblk, s->d_err, s->material);
     launch_assemble(st, s->nnzb, s->nt, s->d_slot_ptr, s->d_slot_code, s->d_tetblk, s->d_row_of_slot, s->d_col,
                     s->d_mass, s->d_val);
+    launch_binding_fold(st, s->nb, s->d_bvid, s->d_bE, h2, s->d_diag_slot, s->d_val);
     for (int c = 0; c < nc; ++c) {
       const double k = C.k[c];
       const double e2 = 2.0 * eps[c] * eps[c] * k;
@@ -2266,7 +2273,7 @@ extern "C" adj_status sim_forward_step(adj_scene* s, const double* qbar, const d
                                        adj_contact_state* out, void* stream) {
   if (!s || !qbar || !vbar || !f_ext || !q || !v || !out) return fail(ADJ_E_ARG, "null argument");
   if (!std::isfinite(mu) || mu < 0) return fail(ADJ_E_ARG, "mu must be finite and >= 0");
-  if (s->nb) return fail(ADJ_E_NOTIMPL, "the forward step does not take bindings");
+  if (s->nb && !s->btarget_set) return fail(ADJ_E_ARG, "binding targets not set (adj_set_binding_targets)");
   hipStream_t st = (hipStream_t)stream;
   const double h = s->hs.h;
   const long long n3 = s->n3;
@@ -2487,6 +2494,17 @@ extern "C" adj_status adj_actuation_vjp(adj_scene* s, const double* dL_df, doubl
   launch_actuation_vjp((hipStream_t)stream, s->nt, s->n_act, s->d_tets, s->d_act_fibre, s->d_Bt, s->d_vol,
                        s->d_act_gptr, s->d_act_gtets, dL_df, s->d_act_s, dL_da);
   HIPCHK(hipGetLastError());
+  return ADJ_OK;
+}
+
+extern "C" adj_status adj_set_binding_targets(adj_scene* s, const double* targets) {
+  if (!s) return fail(ADJ_E_ARG, "scene is null");
+  if (!s->nb) return fail(ADJ_E_ARG, "the scene has no bindings");
+  if (!targets) return fail(ADJ_E_ARG, "null targets");
+  for (int i = 0; i < 3 * s->nb; ++i)
+    if (!std::isfinite(targets[i])) return fail(ADJ_E_ARG, "non-finite binding target");
+  HIPCHK(hipMemcpy(s->d_btarget, targets, 3 * (size_t)s->nb * sizeof(double), hipMemcpyHostToDevice));
+  s->btarget_set = true;
   return ADJ_OK;
 }
 

@@ -246,6 +246,25 @@ __global__ void k_binding_vjp(int nb, const int* __restrict__ bvid, const double
   dE[b] = -h2 * dot / e;
 }
 
+// Binding rows of the forward residual (eq:binding): r_v += h^2 (q_v - d_b) / E_b,
+// i.e. -h^2 lambda_b with lambda_b = -(q_v - d_b) / E_b.  Bound vertices are
+// distinct, so no two threads add to one row.
+__global__ void k_binding_force(int nb, const int* __restrict__ bvid, const double* __restrict__ bE, double h2,
+                                const double* __restrict__ q, const double* __restrict__ target,
+                                double* __restrict__ r) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nb) return;
+  const int v = bvid[b];
+  const double c = h2 / bE[b];
+  for (int k = 0; k < 3; ++k) r[3 * v + k] += c * (q[3 * v + k] - target[3 * b + k]);
+}
+
+void launch_binding_force(hipStream_t st, int nb, const int* bvid, const double* bE, double h2, const double* q,
+                          const double* target, double* r) {
+  if (nb == 0) return;
+  k_binding_force<<<(nb + 63) / 64, 64, 0, st>>>(nb, bvid, bE, h2, q, target, r);
+}
+
 void launch_binding_fold(hipStream_t st, int nb, const int* bvid, const double* bE, double h2, const int* diag_slot,
                          double* val) {
   if (nb == 0) return;

@@ -31,6 +31,7 @@ MATERIAL_CODES = {"nh": MAT_NEO_HOOKEAN, "arap": MAT_ARAP, "corot": MAT_COROT}
 EXPORTS = ("adj_scene_create", "adj_scene_destroy", "adjoint_setup", "adjoint_solve", "vjp_params",
            "vjp_params_noalloc", "sim_forward_step", "adj_scene_info", "adj_check_status", "adj_debug_export",
            "adj_profile_begin", "adj_profile_end", "adj_forward_stats", "adj_forward_reset", "adj_set_spheres",
+           "adj_set_binding_targets",
            "adj_set_actuation", "adj_actuation_force", "adj_actuation_vjp",
            "adj_set_tuning", "adj_get_tuning", "adj_autotune", "adj_batch_create", "adj_batch_destroy",
            "adj_batch_info", "adj_batch_setup", "adj_batch_solve", "adj_batch_vjp", "adj_batch_check_status",
@@ -116,6 +117,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.adj_forward_stats.argtypes = [vp, C.POINTER(C.c_double)]
     lib.adj_forward_reset.argtypes = [vp]
     lib.adj_set_spheres.argtypes = [vp, C.c_int32, vp, vp]
+    lib.adj_set_binding_targets.argtypes = [vp, vp]
     lib.adj_set_actuation.argtypes = [vp, C.c_int32, vp, vp]
     lib.adj_actuation_force.argtypes = [vp, vp, vp, vp]
     lib.adj_actuation_vjp.argtypes = [vp, vp, vp, vp]
@@ -335,6 +337,13 @@ def actuation_force(scene: Scene, a, f, stream=None):
 def actuation_vjp(scene: Scene, dL_df, dL_da, stream=None):
     """dL/da = Phi^T dL/df (adj_actuation_vjp)."""
     check(load().adj_actuation_vjp(scene.handle, _ptr(dL_df), _ptr(dL_da), _stream(stream)))
+
+
+def set_binding_targets(scene: Scene, targets):
+    """Binding targets d_b of the next forward steps (adj_set_binding_targets);
+    targets (n_b, 3) host array in the order of the scene's bindings."""
+    t = np.ascontiguousarray(np.asarray(targets, dtype=np.float64).reshape(-1))
+    check(load().adj_set_binding_targets(scene.handle, t.ctypes.data))
 
 
 def set_spheres(scene: Scene, old_pose, new_pose):

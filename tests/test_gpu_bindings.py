@@ -56,10 +56,77 @@ def test_bindings_single_scene_match_oracle():
         assert rel(out[k], getattr(ref, k)) <= TOL, k
     assert rel(gt.cpu().numpy(), ref.dtarget) <= TOL
     assert rel(gE.cpu().numpy(), ref.dE_bind) <= TOL
-    # the forward step does not take bindings
-    with pytest.raises(native.AdjError, match="NOTIMPL"):
+    # a forward step of a scene with bindings needs its targets
+    with pytest.raises(native.AdjError, match="ARG"):
         native.sim_forward_step(scene, qd, torch.zeros_like(qd), torch.zeros_like(qd), 0.5, torch.empty_like(qd),
                                 torch.empty_like(qd), native.ContactBuffers(64).state)
+    scene.close()
+
+
+def test_forward_steps_with_bindings_match_oracle():
+    """sim_forward_step with bindings (eq:binding): the cube hung by four
+    top corners, three steps from rest, each GPU step from the oracle's
+    previous state against the oracle's converged step (no colliders)."""
+    torch = torch_cuda()
+    from paper_2603_16478_amd import native
+    spec, b, disc, d, states = tob._hanging(3)
+    scene = native.Scene(spec.mesh.rest, spec.mesh.tets, spec.density, spec.h, spec.eps, spec.E, spec.nu,
+                         spec.gravity, tob.NO_PLANES, spec.contact_margin, 64, bindings=(b.vid, b.E))
+    native.set_binding_targets(scene, d)
+    buf = native.ContactBuffers(64)
+    for k in range(3):
+        (qbar, vbar), (q_ref, v_ref) = states[k], states[k + 1]
+        qd, vd = torch.tensor(qbar, device="cuda"), torch.tensor(vbar, device="cuda")
+        q, v = torch.empty_like(qd), torch.empty_like(qd)
+        native.sim_forward_step(scene, qd, vd, torch.zeros_like(qd), spec.mu, q, v, buf.state)
+        torch.cuda.synchronize()
+        du, du_ref = q.cpu().numpy() - qbar, q_ref - qbar
+        print(f"hung cube step {k}: contacts {buf.state.n_contacts}, du err {rel(du, du_ref):.2e}, "
+              f"v err {rel(v.cpu().numpy(), v_ref):.2e}", flush=True)
+        assert buf.state.n_contacts == 0
+        assert rel(du, du_ref) <= 1e-8
+        assert rel(v.cpu().numpy(), v_ref) <= 1e-8
+    scene.close()
+
+
+def test_forward_step_with_bindings_and_friction_matches_oracle():
+    """The tiny impact cube held by its top corners while it lands on the
+    ground with friction: one GPU step from the oracle's state, both sides
+    started cold, against the oracle's step with the same targets (contact
+    list bit-exact, displacement and multipliers)."""
+    torch = torch_cuda()
+    from oracle.forward import solve_step
+    from paper_2603_16478_amd import native
+    from synth import tiny_scene
+    spec = tiny_scene("impact")
+    b = tob._bindings(spec, E=3e-3)
+    disc = tob._disc(spec, b)
+    d = spec.mesh.rest[b.vid] + np.array([2e-3, 0.0, -8e-3])
+    q, v = spec.q0.copy(), spec.v0.copy()
+    warm = None
+    for _ in range(10):
+        q, v, rec, warm = solve_step(disc, q, v, np.zeros_like(q), spec.gravity, spec.mu, spec.eps, spec.planes,
+                                     margin=spec.contact_margin, warm=warm, targets=d)
+    q_ref, v_ref, ref, _ = solve_step(disc, q, v, np.zeros_like(q), spec.gravity, spec.mu, spec.eps, spec.planes,
+                                      margin=spec.contact_margin, targets=d)
+    scene = native.Scene(spec.mesh.rest, spec.mesh.tets, spec.density, spec.h, spec.eps, spec.E, spec.nu,
+                         spec.gravity, spec.planes, spec.contact_margin, 64, bindings=(b.vid, b.E))
+    native.set_binding_targets(scene, d)
+    buf = native.ContactBuffers(64)
+    qd, vd = torch.tensor(q, device="cuda"), torch.tensor(v, device="cuda")
+    qn, vn = torch.empty_like(qd), torch.empty_like(qd)
+    native.sim_forward_step(scene, qd, vd, torch.zeros_like(qd), spec.mu, qn, vn, buf.state)
+    torch.cuda.synchronize()
+    n = buf.state.n_contacts
+    print(f"bound impact cube: contacts {n} (oracle {ref.contacts.n}), frictional "
+          f"{int(buf.fric[:n].sum())} (oracle {int(ref.contacts.fric.sum())})", flush=True)
+    assert n == ref.contacts.n and ref.contacts.fric.any()
+    np.testing.assert_array_equal(buf.vid[:n].cpu().numpy(), ref.contacts.vid)
+    np.testing.assert_array_equal(buf.fric[:n].cpu().numpy().astype(bool), ref.contacts.fric)
+    du, du_ref = qn.cpu().numpy() - q, q_ref - q
+    print(f"  du err {rel(du, du_ref):.2e}, lambda err {rel(buf.lam[:n].cpu().numpy(), ref.lam):.2e}", flush=True)
+    assert rel(du, du_ref) <= 1e-7
+    assert rel(buf.lam[:n].cpu().numpy(), ref.lam) <= 1e-6
     scene.close()
 
 
