@@ -334,10 +334,7 @@ adj_status adj_debug_export(const adj_scene* scene, int32_t what, void* host_out
  * converged state and targets the step's binding targets d_b (device
  * [n_bindings][3]), writes dL/dd_b = h^2 z_b / E_b (device [n_bindings][3])
  * and dL/dE_b = -h^2 (lambda_b . z_b) / E_b with lambda_b = -(q_b - d_b) / E_b
- * (device [n_bindings]).  A scene without bindings returns ADJ_OK at once.
- * (The forward step does not take bindings: sim_forward_step returns
- * ADJ_E_NOTIMPL on a scene with bindings; converged states come from the
- * caller.) */
+ * (device [n_bindings]).  A scene without bindings returns ADJ_OK at once. */
 adj_status adj_binding_vjp(adj_scene* scene, const double* z, const double* q, const double* targets,
                            double* dL_dtargets, double* dL_dE, void* stream);
 
