@@ -571,7 +571,11 @@ def slab_headline(args):
               "launches_timed": ci["regions"], "ms_per_solve": ci["ms_per_solve"]}
     ranked = sorted((roof_gj, roof_s, roof_c), key=lambda r: -r["ms_per_solve"])
     roofline, roofline_other = ranked[0], ranked[1:]
-    mvb = bsr_bytes(info)
+    # the product kernel also reads the basis vectors V_0..V_j for the first
+    # Gram-Schmidt dots ((J + 1) / 2 on average over a cycle of J iterations)
+    # and writes the flexible basis copy of its input
+    its_f = legs["fp64"]["warm"]["krylov_iters_mean"]
+    mvb = bsr_bytes(info) + ((its_f + 1) / 2 + 1) * 3 * info["n_verts"] * 8
     mv = prof["bsr"]
     tet_bytes = nt * (16 + 14 * 8) + nnzb * 9 * 8
     tet_us = prof["tet"]["avg_us"] + prof["assemble"]["avg_us"]
@@ -618,7 +622,9 @@ def slab_headline(args):
         "roofline": roofline,
         "roofline_other": roofline_other,
         "matvec": {"kernel": "Acal^T product fused with the first Gram-Schmidt dots (k_bsr_dots)",
-                   "bytes_per_launch": mvb, "avg_launch_us": mv["avg_us"],
+                   "bytes_per_launch": mvb, "bytes_note": "blocks, indices, x, w, the flexible-basis copy of x "
+                                                         "and the mean (J + 1) / 2 basis vectors read for the dots",
+                   "avg_launch_us": mv["avg_us"],
                    "GB/s": mvb / (mv["avg_us"] * 1e-6) / 1e9 if mv["regions"] else None,
                    "frac": mvb / (mv["avg_us"] * 1e-6) / 1e9 / HBM_PEAK_GBPS if mv["regions"] else None},
         "svd_jacobian": {"kernel": "per-tet SVD / Neo-Hookean projection Jacobian blocks (k_tet_blocks) + gather "

@@ -231,13 +231,17 @@ template <int K>
 __device__ __forceinline__ void gj_rows_step(double (&x)[kNB], bool& used, int& step_of_row, bool& bad,
                                              double* __restrict__ prow) {
   const int lane = threadIdx.x & 63, r = lane & 31;
-  // pivot column value of this lane's row (the A part lives in lanes < 32)
-  const double ak = __shfl(x[K], r, 64);
+  // pivot column value of this lane's row (the A part lives in lanes < 32;
+  // the identity lanes need it only for the update, so the shuffle runs
+  // beside the search instead of before it)
+  const double own = x[K];
+  const double ak = __shfl(own, r, 64);
   // pivot choice on a 32-bit key: |a_rk| rounded to float with its low 5
   // bits replaced by 31 - r (ties within ~2^-18 relative go to the lower
-  // row), used rows 0, unused rows at least 32; one DPP max per level.
-  const unsigned mag = __float_as_uint((float)fabs(ak)) & ~31u;
-  unsigned key = used ? 0u : (max(mag, 32u) | (unsigned)(31 - r));
+  // row), used rows 0, unused rows at least 32; one DPP max per level.  Only
+  // the A lanes' keys are read.
+  const unsigned mag = __float_as_uint((float)fabs(own)) & ~31u;
+  unsigned key = (used || lane >= 32) ? 0u : (max(mag, 32u) | (unsigned)(31 - r));
   key = max_dpp<kDppXor1>(key);
   key = max_dpp<kDppXor2>(key);
   key = max_dpp<kDppHalfMirror>(key);
