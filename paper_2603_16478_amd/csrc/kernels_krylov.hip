@@ -75,9 +75,11 @@ __global__ void __launch_bounds__(256) k_spmv_tasks(const int4* __restrict__ tas
                                                     const double* __restrict__ scale,
                                                     const GmresState* __restrict__ st, int use_j,
                                                     double* __restrict__ y, double alpha = 0.0) {
-  if (gm_inactive(st)) return;
-  __shared__ double lds[32];
+  // the task is loaded before the state is checked, so the two loads overlap
+  // (the level launches of a sweep are chains of a few dependent loads)
   const int4 t = tasks[blockIdx.x];
+  if (gm_inactive(st) && t.x != INT_MIN) return;  // t.x is never INT_MIN: keeps the task load first
+  __shared__ double lds[32];
   const double* x = xbase;
   double sc = 1.0;
   if (use_j) {
