@@ -289,6 +289,8 @@ struct adj_scene {
   // the contact vertices, CSR by elimination row; columns are vertex ids):
   // one S and one S^T product per apply plus two products with Y.  Tasks of
   // the Y rows with entries, and of the contact-vertex rows of S^T.
+  char* h_ystage = nullptr;  // pinned staging of the Y row lists
+  size_t cap_ystage = 0;
   long long *d_Yp = nullptr, *d_Ysrc = nullptr;
   int *d_Ycol = nullptr, *d_Ytasks = nullptr, *d_CTtasks = nullptr;
   double* d_Yval = nullptr;
@@ -402,6 +404,7 @@ static void free_scene(adj_scene* s) {
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (s->h_state) (void)hipHostFree(s->h_state);
+  if (s->h_ystage) (void)hipHostFree(s->h_ystage);
   for (hipEvent_t e : s->prof_ev) (void)hipEventDestroy(e);
   for (hipGraphExec_t& g : s->chunk_exec)
     if (g) (void)hipGraphExecDestroy(g);
@@ -747,22 +750,67 @@ static adj_status int_upload(int** p, size_t* cap, const std::vector<int32_t>& v
 static adj_status build_y_rows(adj_scene* s, hipStream_t st, const std::vector<int>& cv) {
   const HostScene& h = s->hs;
   const int nv = s->nv, ncv = (int)cv.size();
-  std::vector<int64_t> yp(nv + 1, 0);
-  for (int k = 0; k < ncv; ++k)
-    for (int64_t p = h.STp[cv[k]]; p < h.STp[cv[k] + 1]; ++p) yp[h.STj[p] + 1]++;
-  for (int r = 0; r < nv; ++r) yp[r + 1] += yp[r];
-  const long long nnz = yp[nv];
-  std::vector<int32_t> ycol(nnz);
-  std::vector<int64_t> ysrc(nnz);
+  // host threads over contiguous ranges of contact vertices (balanced by
+  // path length): per-thread row counts, then each thread fills its rows'
+  // entries from its own cursors, so every row lists its contact vertices
+  // in increasing k exactly as one thread would
+  const int nth = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  std::vector<int> kb(nth + 1, ncv);
   {
-    std::vector<int64_t> pos(yp.begin(), yp.end() - 1);
-    for (int k = 0; k < ncv; ++k)
+    long long total = 0;
+    for (int k = 0; k < ncv; ++k) total += h.STp[cv[k] + 1] - h.STp[cv[k]];
+    long long acc = 0;
+    int t = 1;
+    kb[0] = 0;
+    for (int k = 0; k < ncv && t < nth; ++k) {
+      acc += h.STp[cv[k] + 1] - h.STp[cv[k]];
+      while (t < nth && acc * nth >= total * t) kb[t++] = k + 1;
+    }
+  }
+  std::vector<std::vector<int64_t>> cur(nth, std::vector<int64_t>(nv + 1, 0));
+  auto run = [&](auto&& body) {
+    std::vector<std::thread> pool;
+    for (int t = 1; t < nth; ++t) pool.emplace_back(body, t);
+    body(0);
+    for (auto& th : pool) th.join();
+  };
+  run([&](int t) {
+    std::vector<int64_t>& c = cur[t];
+    for (int k = kb[t]; k < kb[t + 1]; ++k)
+      for (int64_t p = h.STp[cv[k]]; p < h.STp[cv[k] + 1]; ++p) c[h.STj[p]]++;
+  });
+  std::vector<int64_t> yp(nv + 1, 0);
+  for (int r = 0; r < nv; ++r) {
+    int64_t o = yp[r];
+    for (int t = 0; t < nth; ++t) {
+      const int64_t n = cur[t][r];
+      cur[t][r] = o;  // thread t's cursor in row r
+      o += n;
+    }
+    yp[r + 1] = o;
+  }
+  const long long nnz = yp[nv];
+  // pinned staging of the column and source lists (kept by the scene)
+  const size_t need = (size_t)std::max<long long>(nnz, 1) * (sizeof(int32_t) + sizeof(int64_t));
+  if (need > s->cap_ystage) {
+    if (s->h_ystage) (void)hipHostFree(s->h_ystage);
+    s->h_ystage = nullptr;
+    s->cap_ystage = 0;
+    if (hipHostMalloc((void**)&s->h_ystage, need, hipHostMallocDefault) != hipSuccess)
+      return fail(ADJ_E_OOM, "pinned staging of the Y rows");
+    s->cap_ystage = need;
+  }
+  int64_t* ysrc = reinterpret_cast<int64_t*>(s->h_ystage);
+  int32_t* ycol = reinterpret_cast<int32_t*>(s->h_ystage + (size_t)std::max<long long>(nnz, 1) * sizeof(int64_t));
+  run([&](int t) {
+    std::vector<int64_t>& c = cur[t];
+    for (int k = kb[t]; k < kb[t + 1]; ++k)
       for (int64_t p = h.STp[cv[k]]; p < h.STp[cv[k] + 1]; ++p) {
-        const int64_t o = pos[h.STj[p]]++;
+        const int64_t o = c[h.STj[p]]++;
         ycol[o] = cv[k];
         ysrc[o] = p;
       }
-  }
+  });
   const std::vector<int32_t> ytasks = make_row_tasks(yp, 1024, nullptr, true);
   std::vector<int32_t> rows(cv.begin(), cv.end());
   const std::vector<int32_t> cttasks = make_row_tasks(h.STp, 1024, &rows);
@@ -785,14 +833,14 @@ static adj_status build_y_rows(adj_scene* s, hipStream_t st, const std::vector<i
     return fail(ADJ_E_OOM, "Y row pointer");
   HIPCHK(hipMemcpyAsync(s->d_Yp, yp.data(), (nv + 1) * sizeof(long long), hipMemcpyHostToDevice, st));
   if (nnz) {
-    HIPCHK(hipMemcpyAsync(s->d_Ycol, ycol.data(), nnz * sizeof(int), hipMemcpyHostToDevice, st));
-    HIPCHK(hipMemcpyAsync(s->d_Ysrc, ysrc.data(), nnz * sizeof(long long), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(s->d_Ycol, ycol, nnz * sizeof(int), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(s->d_Ysrc, ysrc, nnz * sizeof(long long), hipMemcpyHostToDevice, st));
   }
   adj_status a;
   if ((a = int_upload(&s->d_Ytasks, &s->cap_ytasks, ytasks, st)) != ADJ_OK) return a;
   if ((a = int_upload(&s->d_CTtasks, &s->cap_cttasks, cttasks, st)) != ADJ_OK) return a;
   launch_gather_values(st, nnz, s->d_Ysrc, s->d_STx, s->d_Yval);
-  HIPCHK(hipStreamSynchronize(st));  // the host vectors go out of scope
+  HIPCHK(hipStreamSynchronize(st));  // the host vectors go out of scope, the staging is reused
   s->nY_tasks = (int)(ytasks.size() / 4);
   s->nCT_tasks = (int)(cttasks.size() / 4);
   s->y_nnz = nnz;
