@@ -254,7 +254,8 @@ def boxes_leg(n_boxes, nsolve):
                          [max(1, int(off[k + 1] - off[k])) for k in range(len(specs))])
     t_build = time.perf_counter() - t0
     info = batch.union_scene().info()
-    print(f"{len(specs)} boxes: batch built in {t_build:.1f} s (nnz(S) {info['nnz_S']})", file=sys.stderr, flush=True)
+    print(f"{len(specs)} boxes: batch built in {t_build:.1f} s (nnz(S) {info['nnz_S']}, nnz(L) {info['nnz_L']})",
+          file=sys.stderr, flush=True)
     rng = np.random.default_rng(300)
     q = torch.tensor(np.concatenate(qs), device=dev)
     gq = torch.tensor(rng.standard_normal(q.shape), device=dev)
@@ -300,23 +301,32 @@ def boxes_leg(n_boxes, nsolve):
         torch.cuda.synchronize()
         return len(specs) * nsolve / (time.perf_counter() - t2)
 
+    default = native.batch_get_tuning(batch)
+    native.batch_set_tuning(batch, chunk=8, graph=0, a_inv=1)
+    products_rate = timed_fp64()
+    native.batch_set_tuning(batch, chunk=8, graph=0, a_inv=2)
+    sweeps_rate = timed_fp64()
     native.batch_set_tuning(batch, chunk=8, graph=1)
     graph_rate = timed_fp64()
     native.batch_set_tuning(batch, chunk=8, graph=0)
     native.batch_setup(batch, states, q, o)
     best = native.batch_autotune(batch, gq, gv, z, o, reps=2)
     tuned_rate = timed_fp64()
-    legs["launch_shapes"] = {"fp64_default": {"chunk": 8, "graph": 0, "value": legs["fp64"]["value"]},
-                             "fp64_graph": {"chunk": 8, "graph": 1, "value": graph_rate},
+    legs["launch_shapes"] = {"fp64_default": default | {"value": legs["fp64"]["value"],
+                                                        "note": "a_inv 0: sweeps when S holds more than 32 M and "
+                                                                "4 nnz(L) entries"},
+                             "fp64_products": {"chunk": 8, "graph": 0, "a_inv": 1, "value": products_rate},
+                             "fp64_sweeps": {"chunk": 8, "graph": 0, "a_inv": 2, "value": sweeps_rate},
+                             "fp64_graph": {"chunk": 8, "graph": 1, "a_inv": 0, "value": graph_rate},
                              "fp64_autotuned": best | {"value": tuned_rate}, "unit": "adjoint solves/s"}
-    print(f"{len(specs)} boxes fp64: graph replay {graph_rate:.1f} solves/s, autotuned {best} {tuned_rate:.1f}",
-          file=sys.stderr, flush=True)
+    print(f"{len(specs)} boxes fp64: S products {products_rate:.1f}, sweeps {sweeps_rate:.1f}, graph replay "
+          f"{graph_rate:.1f} solves/s, autotuned {best} {tuned_rate:.1f}", file=sys.stderr, flush=True)
     batch.close()
     return {"workload": f"batched boxes: the first {len(specs)} of 256 seeded boxes (log-uniform 2k-100k tets), "
                         f"{sum(sp.n_tets for sp in specs)} tets, {sum(sp.n_verts for sp in specs)} vertices, "
                         f"{int(off[len(specs)])} ground contacts; seeded deformed states and sticking values; "
                         "GMRES(64) + Woodbury to 1e-8",
-            "batch_build_s": t_build, "nnz_S": info["nnz_S"], "adjoint": legs}
+            "batch_build_s": t_build, "nnz_S": info["nnz_S"], "nnz_L": info["nnz_L"], "adjoint": legs}
 
 
 def quadruped_leg(steps, checkpoint):

@@ -482,17 +482,23 @@ adj_status adj_batch_scene(adj_batch* batch, adj_scene** out);
  * runs as many as the last solve of the same kind needed); graph: 1 replays
  * each chunk from a HIP graph captured once per adj_batch_setup on the
  * batch's private stream (the same kernels, so results are bitwise those of
- * direct launches).  Defaults: chunk 8, graph 0.  ADJ_E_ARG outside these. */
+ * direct launches); a_inv: A^{-1} of the union in the preconditioner, 1 = the
+ * sparse-inverse products S^T S, 2 = level-scheduled sweeps with the union's
+ * Cholesky factor (every level one launch over all scenes), 0 = automatic
+ * (sweeps when S holds more than 32 million and more than 4 nnz(L) entries).
+ * Defaults: chunk 8, graph 0, a_inv 0.  ADJ_E_ARG outside these. */
 typedef struct {
   int32_t chunk;
   int32_t graph;
+  int32_t a_inv;
 } adj_batch_tuning;
 adj_status adj_batch_set_tuning(adj_batch* batch, const adj_batch_tuning* t);
 adj_status adj_batch_get_tuning(const adj_batch* batch, adj_batch_tuning* t);
 
 /* Batched autotuner (a9): after adj_batch_setup, times adj_batch_solve with
- * the right-hand side (dL_dq, dL_dv) for chunk in {2, 4, 8, 16, 32} with
- * direct launches, then graph replay at the best chunk (each candidate the
+ * the right-hand side (dL_dq, dL_dv) for a_inv in {1, 2} (when the union has
+ * the sweep structure), then chunk in {2, 4, 8, 16, 32} with direct
+ * launches, then graph replay at the best chunk (each candidate the
  * best of `reps` timed solves, HIP events on `stream`, chunk graphs
  * re-captured for every solve as after a fresh setup), keeps the fastest on
  * the batch and writes it to *best.  z: device scratch [3 * total vertices]

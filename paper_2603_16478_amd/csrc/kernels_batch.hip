@@ -27,8 +27,9 @@ constexpr int kBLd = 130;  // partials per block (basis index i)
 // Sparse-inverse products over the union: y = S x with x the scene's current
 // basis vector Vt_{j_s} * scale_s[j_s] (use_j) or x = xbase; rows of stopped
 // scenes are skipped.  rscene: scene of each row (the rows of S are in
-// elimination order, those of S^T in vertex order).
-template <class MT>
+// elimination order, those of S^T in vertex order).  ACC: y[row] += alpha
+// (row . x) instead (the first phase of a sweep level).
+template <class MT, bool ACC = false>
 __global__ void __launch_bounds__(256) kb_spmv_tasks(const int4* __restrict__ tasks,
                                                      const long long* __restrict__ rp,
                                                      const int* __restrict__ cj, const MT* __restrict__ cx,
@@ -36,7 +37,7 @@ __global__ void __launch_bounds__(256) kb_spmv_tasks(const int4* __restrict__ ta
                                                      const double* __restrict__ scale, int lds_scale,
                                                      const GmresState* __restrict__ st,
                                                      const int* __restrict__ rscene, int use_j,
-                                                     double* __restrict__ y) {
+                                                     double* __restrict__ y, double alpha = 0.0) {
   __shared__ double lds[32];
   const int4 t = tasks[blockIdx.x];
   constexpr int kBig = 0x40000000;
@@ -52,9 +53,15 @@ __global__ void __launch_bounds__(256) kb_spmv_tasks(const int4* __restrict__ ta
     a1 = block_sum(a1, lds);
     a2 = block_sum(a2, lds);
     if (threadIdx.x == 0) {
-      y[3 * row] = sc * a0;
-      y[3 * row + 1] = sc * a1;
-      y[3 * row + 2] = sc * a2;
+      if constexpr (ACC) {
+        y[3 * row] += alpha * a0;
+        y[3 * row + 1] += alpha * a1;
+        y[3 * row + 2] += alpha * a2;
+      } else {
+        y[3 * row] = sc * a0;
+        y[3 * row + 1] = sc * a1;
+        y[3 * row + 2] = sc * a2;
+      }
     }
     return;
   }
@@ -71,10 +78,43 @@ __global__ void __launch_bounds__(256) kb_spmv_tasks(const int4* __restrict__ ta
   a1 = wave_sum(a1);
   a2 = wave_sum(a2);
   if (lane == 0) {
-    y[3 * row] = sc * a0;
-    y[3 * row + 1] = sc * a1;
-    y[3 * row + 2] = sc * a2;
+    if constexpr (ACC) {
+      y[3 * row] += alpha * a0;
+      y[3 * row + 1] += alpha * a1;
+      y[3 * row + 2] += alpha * a2;
+    } else {
+      y[3 * row] = sc * a0;
+      y[3 * row + 1] = sc * a1;
+      y[3 * row + 2] = sc * a2;
+    }
   }
+}
+
+// Permutations of the sweeps over the union (elimination position i of the
+// scene pscene[i] holds vertex perm[i]); entries of stopped scenes are left
+// as they are.  Gather: t = scale_s x (x the scene's current basis vector
+// with use_j, else xbase); scatter: out = z back in vertex order.
+__global__ void kb_perm_gather(int n, const int* __restrict__ perm, const int* __restrict__ pscene,
+                               const double* __restrict__ xbase, long long stride, const double* __restrict__ scale,
+                               int lds_scale, const GmresState* __restrict__ st, int use_j, double* __restrict__ t) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= 3 * n) return;
+  const int i = e / 3, c = e - 3 * i;
+  const int s = pscene[i];
+  if (st[s].active == 0) return;
+  const double* x = xbase + (use_j ? (long long)st[s].j * stride : 0);
+  const double sc = use_j ? scale[(size_t)s * lds_scale + st[s].j] : 1.0;
+  t[e] = sc * x[3 * perm[i] + c];
+}
+
+__global__ void kb_perm_scatter(int n, const int* __restrict__ perm, const int* __restrict__ pscene,
+                                const double* __restrict__ z, const GmresState* __restrict__ st,
+                                double* __restrict__ out) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= 3 * n) return;
+  const int i = e / 3, c = e - 3 * i;
+  if (st[pscene[i]].active == 0) return;
+  out[3 * perm[i] + c] = z[e];
 }
 
 // ---------------------------------------------------------------------------
@@ -668,6 +708,27 @@ void launchb_spmv(hipStream_t s, int ntasks, const int4* tasks, const long long*
                   const float* cx, const double* xbase, long long stride, const double* scale, int lds,
                   const GmresState* st, const int* vscene, int use_j, double* y) {
   kb_spmv_tasks<float><<<ntasks, 256, 0, s>>>(tasks, rp, cj, cx, xbase, stride, scale, lds, st, vscene, use_j, y);
+}
+void launchb_spmv_acc(hipStream_t s, int ntasks, const int4* tasks, const long long* rp, const int* cj,
+                      const double* cx, const double* x, double alpha, const GmresState* st, const int* rscene,
+                      double* y) {
+  if (ntasks <= 0) return;
+  kb_spmv_tasks<double, true><<<ntasks, 256, 0, s>>>(tasks, rp, cj, cx, x, 0, nullptr, 0, st, rscene, 0, y, alpha);
+}
+void launchb_spmv_acc(hipStream_t s, int ntasks, const int4* tasks, const long long* rp, const int* cj,
+                      const float* cx, const double* x, double alpha, const GmresState* st, const int* rscene,
+                      double* y) {
+  if (ntasks <= 0) return;
+  kb_spmv_tasks<float, true><<<ntasks, 256, 0, s>>>(tasks, rp, cj, cx, x, 0, nullptr, 0, st, rscene, 0, y, alpha);
+}
+void launchb_perm_gather(hipStream_t s, int n, const int* perm, const int* pscene, const double* xbase,
+                         long long stride, const double* scale, int lds_scale, const GmresState* st, int use_j,
+                         double* t) {
+  kb_perm_gather<<<(3 * n + 255) / 256, 256, 0, s>>>(n, perm, pscene, xbase, stride, scale, lds_scale, st, use_j, t);
+}
+void launchb_perm_scatter(hipStream_t s, int n, const int* perm, const int* pscene, const double* z,
+                          const GmresState* st, double* out) {
+  kb_perm_scatter<<<(3 * n + 255) / 256, 256, 0, s>>>(n, perm, pscene, z, st, out);
 }
 void launchb_wb_gather(hipStream_t s, int nblk, int max_m, const int4* tab, const int* moff, const long long* xpos,
                        const int* mps, const int* row_c, const int* row_i, const int* vid, const double* Q,

@@ -75,10 +75,10 @@ class SolveInfo(C.Structure):
 
 
 class BatchTuning(C.Structure):
-    _fields_ = [("chunk", C.c_int32), ("graph", C.c_int32)]
+    _fields_ = [("chunk", C.c_int32), ("graph", C.c_int32), ("a_inv", C.c_int32)]
 
     def as_dict(self):
-        return {"chunk": self.chunk, "graph": self.graph}
+        return {"chunk": self.chunk, "graph": self.graph, "a_inv": self.a_inv}
 
 
 class Tuning(C.Structure):
@@ -527,8 +527,8 @@ def batch_reverse(b0: Batch, b1: Batch, contacts, q, gq, gv, dfext, grad, opts: 
     return [list(infos[t * ns:(t + 1) * ns]) for t in range(T)]
 
 
-def batch_set_tuning(batch: Batch, chunk=8, graph=0):
-    t = BatchTuning(int(chunk), int(graph))
+def batch_set_tuning(batch: Batch, chunk=8, graph=0, a_inv=0):
+    t = BatchTuning(int(chunk), int(graph), int(a_inv))
     check(load().adj_batch_set_tuning(batch.handle, C.byref(t)))
 
 
@@ -539,7 +539,7 @@ def batch_get_tuning(batch: Batch) -> dict:
 
 
 def batch_autotune(batch: Batch, dL_dq, dL_dv, z, opts: SolveOpts, reps=2, stream=None) -> dict:
-    """Time candidate chunk sizes and graph replay on the set-up batch and keep the fastest."""
+    """Time A^-1 by products or sweeps, chunk sizes and graph replay on the set-up batch; keep the fastest."""
     t = BatchTuning()
     check(load().adj_batch_autotune(batch.handle, _ptr(dL_dq), _ptr(dL_dv), _ptr(z), C.byref(opts), int(reps),
                                     C.byref(t), _stream(stream)))

@@ -42,21 +42,23 @@ def test_batched_chunks_and_graphs_agree_with_oracle():
     batch, keep, states, q, gq, gv = _batch()
     opts = native.solve_opts(rtol=1e-12, maxit=3000, restart=64)
     zs = {}
-    for chunk, graph in ((8, 0), (8, 1), (2, 0), (4, 1), (16, 1)):
-        native.batch_set_tuning(batch, chunk=chunk, graph=graph)
-        assert native.batch_get_tuning(batch) == {"chunk": chunk, "graph": graph}
+    for chunk, graph, a_inv in ((8, 0, 0), (8, 1, 0), (2, 0, 0), (4, 1, 0), (16, 1, 0), (8, 0, 2), (8, 1, 2),
+                                (4, 0, 1)):
+        native.batch_set_tuning(batch, chunk=chunk, graph=graph, a_inv=a_inv)
+        assert native.batch_get_tuning(batch) == {"chunk": chunk, "graph": graph, "a_inv": a_inv}
         native.batch_setup(batch, states, q, opts)
         for rep in range(2):  # graph mode: capture on the first solve, replay after
             z = torch.zeros_like(q)
             infos = native.batch_solve(batch, gq, gv, z, opts, raise_noconv=False)
             zn = z.cpu().numpy()
             errs = [rel(zn[batch.voff[k]:batch.voff[k + 1]], refs[k]) for k in range(len(cases))]
-            print(f"chunk {chunk} graph {graph} rep {rep}: iters {[i.iters for i in infos]}, "
+            print(f"chunk {chunk} graph {graph} a_inv {a_inv} rep {rep}: iters {[i.iters for i in infos]}, "
                   f"z err {max(errs):.2e}", flush=True)
             assert max(errs) <= 1e-9
-            zs.setdefault((chunk, graph), zn)
-            assert np.array_equal(zs[(chunk, graph)], zn)  # replay is deterministic
-    assert np.array_equal(zs[(8, 0)], zs[(8, 1)])  # graph replay = direct launches of the same chunks
+            zs.setdefault((chunk, graph, a_inv), zn)
+            assert np.array_equal(zs[(chunk, graph, a_inv)], zn)  # replay is deterministic
+    assert np.array_equal(zs[(8, 0, 0)], zs[(8, 1, 0)])  # graph replay = direct launches of the same chunks
+    assert np.array_equal(zs[(8, 0, 2)], zs[(8, 1, 2)])
     batch.close()
 
 
@@ -69,10 +71,12 @@ def test_batched_autotune_returns_supported_shape():
     z = torch.zeros_like(q)
     best = native.batch_autotune(batch, gq, gv, z, opts, reps=2)
     print("batched autotune", best, flush=True)
-    assert best["chunk"] in (2, 4, 8, 16, 32) and best["graph"] in (0, 1)
+    assert best["chunk"] in (2, 4, 8, 16, 32) and best["graph"] in (0, 1) and best["a_inv"] in (0, 1, 2)
     assert native.batch_get_tuning(batch) == best
     with pytest.raises(native.AdjError):
         native.batch_set_tuning(batch, chunk=0)
     with pytest.raises(native.AdjError):
         native.batch_set_tuning(batch, chunk=8, graph=2)
+    with pytest.raises(native.AdjError):
+        native.batch_set_tuning(batch, chunk=8, graph=0, a_inv=3)
     batch.close()
