@@ -50,7 +50,7 @@ def _cases():
     return cases
 
 
-def _run_batch(prec, rtol, precond=0):
+def _run_batch(prec, rtol, precond=0, a_inv=0):
     torch = torch_cuda()
     from paper_2603_16478_amd import native
     cases = _cases()
@@ -71,6 +71,8 @@ def _run_batch(prec, rtol, precond=0):
     gv = torch.tensor(np.concatenate([c[5] for c in cases]), device=dev)
     z = torch.zeros_like(q)
     opts = native.solve_opts(rtol=rtol, maxit=3000, restart=64, prec=prec, precond=precond)
+    if a_inv:
+        native.batch_set_tuning(batch, chunk=8, graph=0, a_inv=a_inv)
     native.batch_setup(batch, states, q, opts)
     native.batch_check_status(batch)
     infos = native.batch_solve(batch, gq, gv, z, opts, raise_noconv=False)
@@ -176,12 +178,16 @@ def test_batch_mixed_matches_oracle():
     _check_against_oracle(out, 1e-4)
 
 
+@pytest.mark.parametrize("a_inv", [1, 2])
 @pytest.mark.parametrize("prec", [0, 1])
-def test_batch_without_z_matches_oracle(prec):
-    """The batched Woodbury correction through S^T S of the union (no cached
-    Z; the form large batches use), FP64 and mixed, against the oracle."""
+def test_batch_without_z_matches_oracle(prec, a_inv):
+    """The batched Woodbury correction without a cached Z (the form large
+    batches use), FP64 and mixed, against the oracle: a_inv 1 applies A^{-1}
+    by products with S and the correction through S^T S; a_inv 2 applies it
+    by the level-scheduled sweeps and the correction through the row lists
+    Y = A^{-1} H^T."""
     from paper_2603_16478_amd import native
     if prec == native.ADJ_FP64:
-        _check_against_oracle(_run_batch(native.ADJ_FP64, 1e-12, native.PRECOND_WOODBURY_NO_Z), 1e-9)
+        _check_against_oracle(_run_batch(native.ADJ_FP64, 1e-12, native.PRECOND_WOODBURY_NO_Z, a_inv), 1e-9)
     else:
-        _check_against_oracle(_run_batch(native.ADJ_MIXED, 1e-8, native.PRECOND_WOODBURY_NO_Z), 1e-4)
+        _check_against_oracle(_run_batch(native.ADJ_MIXED, 1e-8, native.PRECOND_WOODBURY_NO_Z, a_inv), 1e-4)
