@@ -138,7 +138,7 @@ def _function_text(src, name):
 GJ_FUNCTIONS = ("readlane_d", "rcp_newton", "max_dpp", "gj_rows_step", "invert32_rows", "gj_tile", "gj_next_pivot",
                 "kb_gj_step_mfma")
 LU_MIN = 4608  # padded capacitance size from which the library factors by block LU (default tuning)
-LUT_FUNCTIONS = ("lu_tile", "k_lu_tiles_rest")
+LUT_FUNCTIONS = ("lu_tile_rest", "k_lu_tiles_rest")
 GJW_FUNCTIONS = ("readlane_d", "rcp_newton", "max_dpp", "gj_rows_step", "invert32_rows", "k_gjw_pivot", "k_gjw_panel",
                  "k_gjw_tiles")
 
@@ -536,7 +536,8 @@ def slab_headline(args):
         lt_ach = lt_fl / (lt["avg_us"] * 1e-6) / 1e12
         roof_gj = {"kernel": "trailing update of the block-LU capacitance factorisation (k_lu_tiles_rest: A_ij -= "
                              "L_iK A_Kj on the 128 x 128 tiles below the pivot block and right of the next panel, "
-                             "rank 128 on FP64 matrix cores, two blocks per CU), one launch per 128-column step",
+                             "rank 128 on FP64 matrix cores, two blocks per CU, the tile's old values read in batches "
+                             "beside the products), one launch per 128-column step",
                    "bound": "mfma", "achieved": lt_ach, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                    "frac": lt_ach / FP64_PEAK_TFLOPS, "traffic": measured_traffic("lu_tiles"),
                    "algorithmic_flops_per_launch": lt_fl, "avg_launch_us": lt["avg_us"],

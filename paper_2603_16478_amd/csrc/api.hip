@@ -967,25 +967,36 @@ static adj_status build_capacitance(adj_scene* s, hipStream_t st, double mu, int
     for (hipEvent_t& e : s->lu_ev)
       if (!e && hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
         return fail(ADJ_E_DEVICE, "hipEventCreateWithFlags failed");
-    hipStream_t sb = s->lu_stream;
     hipEvent_t e_cp = s->lu_ev[0], e_rest = s->lu_ev[1];
+    const hipStream_t sq[2] = {st, s->lu_stream};
+    const int nbk = mp / 128;
     launch_lu_pivot0(st, mp, s->d_C, s->d_lu_P, s->d_err);
-    // per step: the column panel on st; the bulk of the trailing update on
-    // sb once the panel is there; the next panel's column (and the next
-    // pivot inverse) on st once the previous step's bulk has updated it
-    for (int k = 0; k + 1 < mp / 128; ++k) {
-      launch_lu_colpanel(st, mp, k, s->d_C, s->d_lu_P);
-      HIPCHK(hipEventRecord(e_cp, st));
-      if (k > 0) HIPCHK(hipStreamWaitEvent(st, e_rest, 0));  // the rest of step k - 1
-      launch_lu_tiles_next(st, mp, k, s->d_C, s->d_lu_P, s->d_err);
-      HIPCHK(hipStreamWaitEvent(sb, e_cp, 0));
+    if (nbk > 1) launch_lu_colpanel(st, mp, 0, s->d_C, s->d_lu_P);
+    HIPCHK(hipEventRecord(e_cp, st));
+    // Per step k the two streams swap roles.  The bulk of the trailing update
+    // runs on sq[k % 2], behind the column panel of step k (same stream) and
+    // the bulk of step k - 1 (event).  The next panel's column with the next
+    // pivot inverse, then the next column panel, run on sq[(k + 1) % 2]
+    // directly behind the bulk of step k - 1 in that stream, so that they are
+    // released before the bulk of step k (which waits on an event) and their
+    // blocks, which need a whole CU each, are placed first.
+    for (int k = 0; k + 1 < nbk; ++k) {
+      const hipStream_t sa = sq[k & 1], sn = sq[(k + 1) & 1];
+      HIPCHK(hipStreamWaitEvent(sn, e_cp, 0));  // the column panel of step k
+      launch_lu_tiles_next(sn, mp, k, s->d_C, s->d_lu_P, s->d_err);
+      if (k + 2 < nbk) launch_lu_colpanel(sn, mp, k + 1, s->d_C, s->d_lu_P);
+      HIPCHK(hipEventRecord(e_cp, sn));
+      if (k > 0) HIPCHK(hipStreamWaitEvent(sa, e_rest, 0));  // the bulk of step k - 1
       {
-        ProfScope pk(s, 12, sb);
-        launch_lu_tiles_rest(sb, mp, k, s->d_C);
+        ProfScope pk(s, 12, sa);
+        launch_lu_tiles_rest(sa, mp, k, s->d_C);
       }
-      HIPCHK(hipEventRecord(e_rest, sb));
+      HIPCHK(hipEventRecord(e_rest, sa));
     }
-    if (mp / 128 > 1) HIPCHK(hipStreamWaitEvent(st, e_rest, 0));
+    if (nbk > 1) {
+      HIPCHK(hipStreamWaitEvent(st, e_cp, 0));
+      HIPCHK(hipStreamWaitEvent(st, e_rest, 0));
+    }
     launch_lu_rowpanels(st, mp, s->d_C, s->d_lu_P);
     launch_lu_groups(st, mp, s->d_C);
     s->d_X = s->d_C;

@@ -1092,9 +1092,9 @@ __device__ __forceinline__ void lu_tile(int mp, int k0, int I0, int J0, double* 
 //                    next pivot block (blocks start in index order) and
 //                    also inverts it (P_{k+1});
 //   k_lu_tiles_rest  every other trailing tile, two blocks per CU (34 KB of
-//                    LDS, 16-wide chunks), no inversion,
-// so that the pivot chain runs beside the bulk of the update and the bulk
-// runs at two blocks per CU.  Both read the column panel left of the
+//                    LDS, 16-wide chunks, the tile's old values read beside
+//                    the products), no inversion,
+// so that the pivot chain runs beside the bulk of the update.  Both read the column panel left of the
 // trailing matrix and the row panel above it, which neither writes.
 __global__ void __launch_bounds__(256, 1) k_lu_tiles_next(int mp, int k0, double* __restrict__ A,
                                                           double* __restrict__ Pnext, int* __restrict__ err) {
@@ -1118,7 +1118,84 @@ __global__ void __launch_bounds__(256, 1) k_lu_tiles_next(int mp, int k0, double
   for (int e = tid; e < kWB * kWB; e += 256) Pnext[e] = M[(e / kWB) * kWL + e % kWB];
 }
 
+// One 128 x 128 tile of the bulk trailing update with the tile's own old
+// values read beside the products instead of before them: the accumulators
+// start at zero, and in each of the eight 16-wide panel chunks one batch of
+// eight old values per lane is requested with the next chunk's panels and
+// added once the chunk's products are done (a batch has one chunk of
+// products to arrive, and only eight registers are held for it).  Two blocks
+// per CU, so that one block's barriers and waits are covered by the other's
+// products.
 constexpr int kRestKC = 16;
+__device__ __forceinline__ void lu_tile_rest(int mp, int k0, int I0, int J0, double* __restrict__ A,
+                                             double (*__restrict__ Ws)[kRestKC + 1],
+                                             double (*__restrict__ Rs)[kWB + 1]) {
+  constexpr int KC = kRestKC, NP = kWB * KC / 256, NCH = kWB / KC;
+  static_assert(NCH == 8, "one batch of eight old values per chunk");
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, li = lane & 15, lk = lane >> 4;
+  const int wr = 64 * (w >> 1), wc = 64 * (w & 1);
+  double wpre[NP], rpre[NP], ob[8];
+  auto load_chunk = [&](int kc) {
+#pragma unroll
+    for (int u = 0; u < NP; ++u) {
+      const int e = tid + 256 * u;
+      wpre[u] = A[(size_t)(I0 + e / KC) * mp + k0 + kc + e % KC];
+      rpre[u] = A[(size_t)(k0 + kc + e / kWB) * mp + J0 + e % kWB];
+    }
+  };
+  auto store_chunk = [&]() {
+#pragma unroll
+    for (int u = 0; u < NP; ++u) {
+      const int e = tid + 256 * u;
+      Ws[e / KC][e % KC] = wpre[u];
+      Rs[e / kWB][e % kWB] = rpre[u];
+    }
+  };
+  d4 acc[4][4];
+#pragma unroll
+  for (int p = 0; p < 4; ++p)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[p][q] = d4{0, 0, 0, 0};
+  load_chunk(0);
+  store_chunk();
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < NCH; ++c) {
+    if (c + 1 < NCH) load_chunk((c + 1) * KC);
+    // batch c: row block p = c / 2, column blocks 2 (c % 2) and 2 (c % 2) + 1
+    const int pb = c >> 1, q0 = 2 * (c & 1);
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      ob[u] = A[(size_t)(I0 + wr + 16 * pb + lk + 4 * (u & 3)) * mp + J0 + wc + 16 * (q0 + (u >> 2)) + li];
+#pragma unroll
+    for (int k4 = 0; k4 < KC; k4 += 4) {
+      double av[4], bv[4];
+#pragma unroll
+      for (int p = 0; p < 4; ++p) av[p] = -Ws[wr + 16 * p + li][k4 + lk];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) bv[q] = Rs[k4 + lk][wc + 16 * q + li];
+#pragma unroll
+      for (int p = 0; p < 4; ++p)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[p][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[p], bv[q], acc[p][q], 0, 0, 0);
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc[pb][q0 + (u >> 2)][u & 3] += ob[u];
+    if (c + 1 < NCH) {
+      __syncthreads();  // every wave is done with the chunk in LDS
+      store_chunk();
+      __syncthreads();
+    }
+  }
+#pragma unroll
+  for (int p = 0; p < 4; ++p)
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        A[(size_t)(I0 + wr + 16 * p + lk + 4 * e) * mp + J0 + wc + 16 * q + li] = acc[p][q][e];
+}
+
 __global__ void __launch_bounds__(256, 2) k_lu_tiles_rest(int mp, int k0, double* __restrict__ A) {
   __shared__ double Ws[kWB][kRestKC + 1];
   __shared__ double Rs[kRestKC][kWB + 1];
@@ -1132,8 +1209,7 @@ __global__ void __launch_bounds__(256, 2) k_lu_tiles_rest(int mp, int k0, double
   const int L = (int)(x * q + min(x, r) + blockIdx.x / 8);
   const int per = 8 * nc, g0 = (L / per) * 8, gh = min(8, nt - g0), w = L % per;
   const int I0 = base + (g0 + w % gh) * kWB, J0 = base + kWB + (w / gh) * kWB;
-  d4 acc[4][4];
-  lu_tile<kRestKC>(mp, k0, I0, J0, A, Ws, Rs, acc);
+  lu_tile_rest(mp, k0, I0, J0, A, Ws, Rs);
 }
 
 // Pall: mp/128 blocks of 128 x 128 (the inverted pivot blocks P_k).  The
