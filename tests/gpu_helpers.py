@@ -75,3 +75,13 @@ def rel(a, b):
     a = np.asarray(a, float)
     b = np.asarray(b, float)
     return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def rel_entries(a, b, floor=1e-3):
+    """Largest per-entry relative error |a_i - b_i| / |b_i|, each entry's
+    scale floored at `floor` times the largest |b|: small entries are held to
+    their own size down to that floor, not to the largest entry's."""
+    a = np.asarray(a, float)
+    b = np.asarray(b, float)
+    scale = np.maximum(np.abs(b), floor * max(np.max(np.abs(b)), 1e-300))
+    return float(np.max(np.abs(a - b) / scale))

@@ -6,7 +6,7 @@ import functools
 import numpy as np
 import pytest
 
-from gpu_helpers import make_scene, rel, run_adjoint, torch_cuda
+from gpu_helpers import make_scene, rel, rel_entries, run_adjoint, torch_cuda
 from oracle import adjoint as adj
 from oracle.rollout import run_forward
 from synth import tiny_scene
@@ -14,6 +14,10 @@ from synth import tiny_scene
 pytestmark = pytest.mark.gpu
 
 TOL_FP64 = 1e-9  # gradients of the FP64 path against the oracle
+# per-tet gradients, each entry against its own size floored at 1e-3 of the
+# largest (beside the max-normalised TOL_FP64 check): with z accurate to about
+# 1e-11 of its largest entry, an entry at the floor can carry ~1e-8 of its size
+TOL_TET_ENTRY = 1e-7
 
 
 @functools.lru_cache(maxsize=None)
@@ -42,6 +46,9 @@ def test_tiny_adjoint_matches_oracle(step):
     assert rel(out["dfext"], ref.dfext) <= TOL_FP64
     assert rel(out["dE_tet"], ref.dE_tet) <= TOL_FP64
     assert rel(out["dnu_tet"], ref.dnu_tet) <= TOL_FP64
+    ent = {k: rel_entries(out[k], getattr(ref, k)) for k in ("dE_tet", "dnu_tet")}
+    print("per-entry", ent, flush=True)
+    assert max(ent.values()) <= TOL_TET_ENTRY
     g = out["grad3"]
     assert abs(g[0] - ref.dE) <= TOL_FP64 * max(abs(ref.dE), np.abs(ref.dE_tet).sum())
     assert abs(g[1] - ref.dnu) <= TOL_FP64 * max(abs(ref.dnu), np.abs(ref.dnu_tet).sum())
@@ -107,6 +114,9 @@ def test_beam_adjoint_matches_oracle(mu, t):
     for k in ("z", "dqbar", "dvbar", "dfext", "dE_tet", "dnu_tet"):
         ref_k = getattr(ref, k if k != "z" else "z")
         assert rel(out[k], ref_k) <= TOL_FP64, (k, rel(out[k], ref_k))
+    ent = {k: rel_entries(out[k], getattr(ref, k)) for k in ("dE_tet", "dnu_tet")}
+    print("per-entry", ent, flush=True)
+    assert max(ent.values()) <= TOL_TET_ENTRY
     g = out["grad3"]
     assert abs(g[0] - ref.dE) <= TOL_FP64 * np.abs(ref.dE_tet).sum()
     assert abs(g[1] - ref.dnu) <= TOL_FP64 * np.abs(ref.dnu_tet).sum()
@@ -143,6 +153,9 @@ def test_beam_slip_onset_matches_oracle(mu, k):
     assert out["info"].relres <= 1e-9
     for key in ("z", "dqbar", "dvbar", "dfext", "dE_tet", "dnu_tet"):
         assert rel(out[key], getattr(ref, key)) <= TOL_FP64, (key, rel(out[key], getattr(ref, key)))
+    ent = {k: rel_entries(out[k], getattr(ref, k)) for k in ("dE_tet", "dnu_tet")}
+    print("per-entry", ent, flush=True)
+    assert max(ent.values()) <= TOL_TET_ENTRY
     g = out["grad3"]
     assert abs(g[0] - ref.dE) <= TOL_FP64 * np.abs(ref.dE_tet).sum()
     assert abs(g[1] - ref.dnu) <= TOL_FP64 * np.abs(ref.dnu_tet).sum()
