@@ -89,7 +89,7 @@ void launch_sweep_parts(hipStream_t, int, int, int, const int*, const int*, cons
 void launch_sweep_parts(hipStream_t, int, int, int, const int*, const int*, const long long*, const int*,
                         const float*, const long long*, const int*, const float*, const GmresState*, double*,
                         double*);
-void launch_lu_groups(hipStream_t, int, double*);
+void launch_lu_groups(hipStream_t, int, double*, int, int);
 int lu_group_blocks();
 void launch_wb_correct(hipStream_t, int, int, const int*, const int*, const int*, const double*,
                        const double*, const double*, double, const double*, const GmresState*, double*);
@@ -108,7 +108,7 @@ void launch_lu_pivot0(hipStream_t, int, double*, double*, int*);
 void launch_lu_colpanel(hipStream_t, int, int, double*, const double*);
 void launch_lu_tiles_next(hipStream_t, int, int, double*, double*, int*);
 void launch_lu_tiles_rest(hipStream_t, int, int, double*);
-void launch_lu_rowpanels(hipStream_t, int, double*, const double*);
+void launch_lu_rowpanels(hipStream_t, int, double*, const double*, int, int);
 size_t gj_wide_lds_bytes();
 void launch_spmv_tasks_acc(hipStream_t, int, const int4*, const long long*, const int*, const double*,
                            const double*, double, const GmresState*, double*);
@@ -333,8 +333,8 @@ struct adj_scene {
   // second stream of the block-LU factorisation (the bulk of each trailing
   // update runs there beside the next panel and its pivot inversion) and its
   // two ordering events; default priority
-  hipStream_t lu_stream = nullptr;
-  hipEvent_t lu_ev[2] = {nullptr, nullptr};
+  hipStream_t lu_stream = nullptr, lu_post_stream = nullptr;
+  hipEvent_t lu_ev[3] = {nullptr, nullptr, nullptr};
   hipGraphExec_t chunk_exec[8] = {};  // [pcg][FP32 preconditioner][FP32 product]
   // preconditioner of the Krylov solves (adj_precond), set per solve;
   // woodbury_ready: the last setup built the capacitance inverse
@@ -412,6 +412,7 @@ static void free_scene(adj_scene* s) {
   for (hipEvent_t e : s->lu_ev)
     if (e) (void)hipEventDestroy(e);
   if (s->lu_stream) (void)hipStreamDestroy(s->lu_stream);
+  if (s->lu_post_stream) (void)hipStreamDestroy(s->lu_post_stream);
   delete s;
 }
 
@@ -964,12 +965,24 @@ static adj_status build_capacitance(adj_scene* s, hipStream_t st, double mu, int
     launch_gj_pad(st, m, mp, s->d_C);
     if (!s->lu_stream && hipStreamCreateWithFlags(&s->lu_stream, hipStreamNonBlocking) != hipSuccess)
       return fail(ADJ_E_DEVICE, "hipStreamCreateWithFlags failed");
+    if (!s->lu_post_stream && hipStreamCreateWithFlags(&s->lu_post_stream, hipStreamNonBlocking) != hipSuccess)
+      return fail(ADJ_E_DEVICE, "hipStreamCreateWithFlags failed");
     for (hipEvent_t& e : s->lu_ev)
       if (!e && hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
         return fail(ADJ_E_DEVICE, "hipEventCreateWithFlags failed");
-    hipEvent_t e_cp = s->lu_ev[0], e_rest = s->lu_ev[1];
-    const hipStream_t sq[2] = {st, s->lu_stream};
-    const int nbk = mp / 128;
+    hipEvent_t e_cp = s->lu_ev[0], e_rest = s->lu_ev[1], e_post = s->lu_ev[2];
+    const hipStream_t sq[2] = {st, s->lu_stream}, sx = s->lu_post_stream;
+    const int nbk = mp / 128, gb = lu_group_blocks();
+    // Row panels V_Kj = P_k A_Kj and the group rewrites of the factors for the
+    // substitutions: a step's row panel is final once its next column and
+    // bulk have run, a group's blocks once its last step has, and neither is
+    // read by a later step.  From the step where the trailing matrix is down
+    // to 24 blocks (the bulk no longer fills the chip and the steps wait on
+    // the pivot chain) those of the finished steps run on a third stream beside
+    // the chain; the rest after the last step.
+    const int k_post = std::max(1, nbk - 25);
+    int k_rp = 0, g_done = 0;
+    bool posted = false;
     launch_lu_pivot0(st, mp, s->d_C, s->d_lu_P, s->d_err);
     if (nbk > 1) launch_lu_colpanel(st, mp, 0, s->d_C, s->d_lu_P);
     HIPCHK(hipEventRecord(e_cp, st));
@@ -982,6 +995,18 @@ static adj_status build_capacitance(adj_scene* s, hipStream_t st, double mu, int
     // blocks, which need a whole CU each, are placed first.
     for (int k = 0; k + 1 < nbk; ++k) {
       const hipStream_t sa = sq[k & 1], sn = sq[(k + 1) & 1];
+      if (k >= k_post && (k > k_rp || k / gb > g_done)) {
+        // steps < k are finished once the bulk of step k - 1 and the next
+        // column of step k - 1 (with the column panel of step k) are
+        HIPCHK(hipStreamWaitEvent(sx, e_rest, 0));
+        HIPCHK(hipStreamWaitEvent(sx, e_cp, 0));
+        launch_lu_rowpanels(sx, mp, s->d_C, s->d_lu_P, k_rp, k);
+        launch_lu_groups(sx, mp, s->d_C, g_done, k / gb);
+        HIPCHK(hipEventRecord(e_post, sx));
+        k_rp = k;
+        g_done = k / gb;
+        posted = true;
+      }
       HIPCHK(hipStreamWaitEvent(sn, e_cp, 0));  // the column panel of step k
       launch_lu_tiles_next(sn, mp, k, s->d_C, s->d_lu_P, s->d_err);
       if (k + 2 < nbk) launch_lu_colpanel(sn, mp, k + 1, s->d_C, s->d_lu_P);
@@ -997,8 +1022,9 @@ static adj_status build_capacitance(adj_scene* s, hipStream_t st, double mu, int
       HIPCHK(hipStreamWaitEvent(st, e_cp, 0));
       HIPCHK(hipStreamWaitEvent(st, e_rest, 0));
     }
-    launch_lu_rowpanels(st, mp, s->d_C, s->d_lu_P);
-    launch_lu_groups(st, mp, s->d_C);
+    if (posted) HIPCHK(hipStreamWaitEvent(st, e_post, 0));
+    launch_lu_rowpanels(st, mp, s->d_C, s->d_lu_P, k_rp, nbk);
+    launch_lu_groups(st, mp, s->d_C, g_done, nbk);
     s->d_X = s->d_C;
     // the substitutions run over all mp rows: the padding rows of t stay zero
     launch_fill_zero(st, (size_t)(mp - m), s->d_tvec + m);

@@ -888,9 +888,9 @@ size_t gj_wide_lds_bytes() { return sizeof(GjwShared); }
 //   k_lu_tiles_next, k_lu_tiles_rest  A_ij -= L_iK A_Kj for the 128 x 128
 //                  tiles below and right of K, in place; the first tile is
 //                  the next pivot block and is also inverted (P_{k+1});
-// and after the last step k_lu_rowpanels: V_Kj = P_k A_Kj for every K and
-// the columns right of it, in place (row panels are not read again once
-// their step's trailing update has run).
+// and, for each step once its next-column and trailing updates have run,
+// k_lu_rowpanels: V_Kj = P_k A_Kj for the columns right of K, in place (row
+// panels are not read again after that).
 // P_0 comes from k_gjw_pivot.
 __global__ void __launch_bounds__(256) k_lu_colpanel(int mp, int k0, double* __restrict__ A,
                                                      const double* __restrict__ P) {
@@ -945,15 +945,16 @@ __global__ void __launch_bounds__(256) k_lu_colpanel(int mp, int k0, double* __r
     for (int e = 0; e < 4; ++e) A[(size_t)(r0 + 16 * w + lk + 4 * e) * mp + k0 + 16 * q + li] = acc[q][e];
 }
 
-// V_Kj = P_k A_Kj for every step k at once (after the last trailing
-// update: no step reads a row panel again once its own trailing update has
-// run), one block per 128 x 64 column slab right of each diagonal block;
-// block b is slab b - S(k) of step k, S(k) = sum_{i<k} 2 (nb - 1 - i).
-__global__ void __launch_bounds__(256) k_lu_rowpanels(int mp, double* __restrict__ A, const double* __restrict__ Pall) {
+// V_Kj = P_k A_Kj for the steps k_lo <= k < k_hi at once (no step reads a
+// row panel again once its own next-column and trailing updates have run),
+// one block per 128 x 64 column slab right of each diagonal block; block b
+// is slab b - S(k) of step k, S(k) = sum_{k_lo <= i < k} 2 (nb - 1 - i).
+__global__ void __launch_bounds__(256) k_lu_rowpanels(int mp, int k_lo, double* __restrict__ A,
+                                                      const double* __restrict__ Pall) {
   __shared__ double Ps[kWB][kWKC + 1];
   __shared__ double Bs[kWKC][64 + 1];
   const int nb = mp / kWB;
-  int k = 0, b = blockIdx.x;
+  int k = k_lo, b = blockIdx.x;
   while (b >= 2 * (nb - 1 - k)) {
     b -= 2 * (nb - 1 - k);
     ++k;
@@ -1216,7 +1217,8 @@ __global__ void __launch_bounds__(256, 2) k_lu_tiles_rest(int mp, int k0, double
 // factorisation is launch_lu_pivot0, then per step k = 0 .. mp/128 - 2
 // launch_lu_colpanel, then launch_lu_tiles_next and launch_lu_tiles_rest
 // (concurrently; the next step's launch_lu_tiles_next also waits for this
-// step's rest); then launch_lu_rowpanels once.
+// step's rest); launch_lu_rowpanels and launch_lu_groups over ranges of
+// finished steps and groups, beside later steps or after the last.
 void launch_lu_pivot0(hipStream_t st, int mp, double* A, double* Pall, int* err) {
   k_gjw_pivot<<<1, 256, 0, st>>>(mp, 0, A, Pall, err);
 }
@@ -1234,9 +1236,12 @@ void launch_lu_tiles_rest(hipStream_t st, int mp, int k, double* A) {
   const int k0 = k * kWB, nt = (mp - k0 - kWB) / kWB;
   if (nt > 1) k_lu_tiles_rest<<<nt * (nt - 1), 256, 0, st>>>(mp, k0, A);
 }
-void launch_lu_rowpanels(hipStream_t st, int mp, double* A, const double* Pall) {
+void launch_lu_rowpanels(hipStream_t st, int mp, double* A, const double* Pall, int k_lo, int k_hi) {
   const int nb = mp / kWB;
-  if (nb > 1) k_lu_rowpanels<<<nb * (nb - 1), 256, 0, st>>>(mp, A, Pall);
+  if (k_hi > nb - 1) k_hi = nb - 1;
+  int blocks = 0;
+  for (int k = k_lo; k < k_hi; ++k) blocks += 2 * (nb - 1 - k);
+  if (blocks > 0) k_lu_rowpanels<<<blocks, 256, 0, st>>>(mp, k_lo, A, Pall);
 }
 
 
@@ -1330,9 +1335,9 @@ __device__ __forceinline__ void publish_block() {
 //             rows a ascending, so L_ac is still the factor),
 //   Vinv_ab = -(V_ab + sum_{a<c<b} V_ac Vinv_cb)  (a < b; columns b
 //             descending, rows a descending).
-__global__ void __launch_bounds__(256) k_lu_group_inv(int mp, double* __restrict__ A) {
+__global__ void __launch_bounds__(256) k_lu_group_inv(int mp, int g_lo, double* __restrict__ A) {
   __shared__ LuGemmShared sh;
-  const int nb = mp / kWB, b0 = blockIdx.x * kLuGroup, g = min(kLuGroup, nb - b0);
+  const int nb = mp / kWB, b0 = (g_lo + (int)blockIdx.x) * kLuGroup, g = min(kLuGroup, nb - b0);
   auto blk = [&](int a, int b) { return A + (size_t)(b0 + a) * kWB * mp + (size_t)(b0 + b) * kWB; };
   d4 acc[4][4];
   for (int b = 0; b + 1 < g; ++b)
@@ -1355,9 +1360,9 @@ __global__ void __launch_bounds__(256) k_lu_group_inv(int mp, double* __restrict
 // below the group (lower) L_rb <- L_rb + sum_{c>b} L_rc Linv_cb, columns b
 // ascending; above it (upper) V_rb <- V_rb + sum_{c<b} V_rc Vinv_cb, columns
 // b descending.  Each output is written once and not read again here.
-__global__ void __launch_bounds__(256) k_lu_group_apply(int mp, double* __restrict__ A) {
+__global__ void __launch_bounds__(256) k_lu_group_apply(int mp, int g_lo, double* __restrict__ A) {
   __shared__ LuGemmShared sh;
-  const int nb = mp / kWB, r = blockIdx.x, b0 = blockIdx.y * kLuGroup, g = min(kLuGroup, nb - b0);
+  const int nb = mp / kWB, r = blockIdx.x, b0 = (g_lo + (int)blockIdx.y) * kLuGroup, g = min(kLuGroup, nb - b0);
   auto blk = [&](int i, int j) { return A + (size_t)i * kWB * mp + (size_t)j * kWB; };
   d4 acc[4][4];
   if (r >= b0 + g) {
@@ -1375,11 +1380,15 @@ __global__ void __launch_bounds__(256) k_lu_group_apply(int mp, double* __restri
   }
 }
 
-void launch_lu_groups(hipStream_t st, int mp, double* A) {
+// Groups g_lo <= G < g_hi (a group's blocks are final once its last step's
+// updates have run, and no later step reads them; groups touch disjoint
+// block columns).
+void launch_lu_groups(hipStream_t st, int mp, double* A, int g_lo, int g_hi) {
   const int nb = mp / kWB, ng = (nb + kLuGroup - 1) / kLuGroup;
-  if (nb < 2) return;
-  k_lu_group_inv<<<ng, 256, 0, st>>>(mp, A);
-  k_lu_group_apply<<<dim3(nb, ng), 256, 0, st>>>(mp, A);
+  if (g_hi > ng) g_hi = ng;
+  if (nb < 2 || g_hi <= g_lo) return;
+  k_lu_group_inv<<<g_hi - g_lo, 256, 0, st>>>(mp, g_lo, A);
+  k_lu_group_apply<<<dim3(nb, g_hi - g_lo), 256, 0, st>>>(mp, g_lo, A);
 }
 
 int lu_group_blocks() { return kLuGroup; }
