@@ -1330,30 +1330,37 @@ __device__ __forceinline__ void publish_block() {
   __threadfence();
 }
 
-// L_GG^{-1} and V_GG^{-1} of every group in place, one block per group:
+// L_GG^{-1} and V_GG^{-1} of the groups in place, two blocks per group
+// (blockIdx.y 0: the lower triangle, 1: the upper one; they touch disjoint
+// blocks):
 //   Linv_ab = -(L_ab + sum_{b<c<a} L_ac Linv_cb)  (a > b; columns b ascending,
 //             rows a ascending, so L_ac is still the factor),
 //   Vinv_ab = -(V_ab + sum_{a<c<b} V_ac Vinv_cb)  (a < b; columns b
 //             descending, rows a descending).
+// Within a triangle the columns stay in that order: a column reads factor
+// blocks of the later columns, which those columns overwrite.
 __global__ void __launch_bounds__(256) k_lu_group_inv(int mp, int g_lo, double* __restrict__ A) {
   __shared__ LuGemmShared sh;
   const int nb = mp / kWB, b0 = (g_lo + (int)blockIdx.x) * kLuGroup, g = min(kLuGroup, nb - b0);
   auto blk = [&](int a, int b) { return A + (size_t)(b0 + a) * kWB * mp + (size_t)(b0 + b) * kWB; };
   d4 acc[4][4];
-  for (int b = 0; b + 1 < g; ++b)
-    for (int a = b + 1; a < g; ++a) {
-      acc_io(acc, blk(a, b), mp, false, 1.0);
-      for (int c = b + 1; c < a; ++c) mma128(acc, blk(a, c), blk(c, b), mp, sh);
-      acc_io(acc, blk(a, b), mp, true, -1.0);
-      publish_block();
-    }
-  for (int b = g - 1; b >= 1; --b)
-    for (int a = b - 1; a >= 0; --a) {
-      acc_io(acc, blk(a, b), mp, false, 1.0);
-      for (int c = a + 1; c < b; ++c) mma128(acc, blk(a, c), blk(c, b), mp, sh);
-      acc_io(acc, blk(a, b), mp, true, -1.0);
-      publish_block();
-    }
+  if (blockIdx.y == 0) {
+    for (int b = 0; b + 1 < g; ++b)
+      for (int a = b + 1; a < g; ++a) {
+        acc_io(acc, blk(a, b), mp, false, 1.0);
+        for (int c = b + 1; c < a; ++c) mma128(acc, blk(a, c), blk(c, b), mp, sh);
+        acc_io(acc, blk(a, b), mp, true, -1.0);
+        publish_block();
+      }
+  } else {
+    for (int b = g - 1; b >= 1; --b)
+      for (int a = b - 1; a >= 0; --a) {
+        acc_io(acc, blk(a, b), mp, false, 1.0);
+        for (int c = a + 1; c < b; ++c) mma128(acc, blk(a, c), blk(c, b), mp, sh);
+        acc_io(acc, blk(a, b), mp, true, -1.0);
+        publish_block();
+      }
+  }
 }
 
 // The blocks outside the groups, one block per (128-row block r, group):
@@ -1387,7 +1394,7 @@ void launch_lu_groups(hipStream_t st, int mp, double* A, int g_lo, int g_hi) {
   const int nb = mp / kWB, ng = (nb + kLuGroup - 1) / kLuGroup;
   if (g_hi > ng) g_hi = ng;
   if (nb < 2 || g_hi <= g_lo) return;
-  k_lu_group_inv<<<g_hi - g_lo, 256, 0, st>>>(mp, g_lo, A);
+  k_lu_group_inv<<<dim3(g_hi - g_lo, 2), 256, 0, st>>>(mp, g_lo, A);
   k_lu_group_apply<<<dim3(nb, g_hi - g_lo), 256, 0, st>>>(mp, g_lo, A);
 }
 
